@@ -1,0 +1,315 @@
+"""Textbook word-level BFV and the Fermat equality mask, in exact integers.
+
+Test infrastructure only (see the package docstring).
+
+Every ciphertext here is a tuple of polynomials with integer coefficients in
+[0, Q); every operation is written from its integer definition, with
+rounding done on exact Python integers.  The paper fixes the scheme (BFV,
+Sec. 1 and 2.1.5), the parameters (n = 32768, log Q = 881, p = t = 65537,
+Sec. 5.1) and the mask (Eq. eq:equality, evaluated by exponentiation by
+squaring, Sec. 4.3); it leaves the RNS split, distributions, relinearization
+method and rounding conventions to the library (SEAL).  The readings taken
+here are:
+
+* Q*P spans at most 881 bits, P a single special prime for key switching;
+* secret key uniform ternary, errors rounded Gaussian (sigma 3.2), drawn by
+  the caller and passed in;
+* secret-key encryption ct = ([Delta*m + e - a*s]_Q, a), Delta = floor(Q/t);
+* multiply: centred lifts to (-Q/2, Q/2), exact products in Z[X]/(X^N+1),
+  then c_k = [round(t * d_k / Q)]_Q (no ties: Q odd, gcd(t, Q) = 1);
+* relinearize after every multiply with one digit per data prime:
+  D_j = [c_2]_{q_j} in [0, q_j), key evk_j = ([-a_j s + e_j + P g_j s^2]_{PQ},
+  a_j) with g_j = (Q/q_j) * [(Q/q_j)^-1]_{q_j}, and
+  c_b' = [c_b + round(sum_j D_j evk_j[b] / P)]_Q (no ties: P odd);
+* the constant 1 of "1 - z^(p-1)" is the trivial encryption (Delta, 0).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import nt
+from . import ring
+from . import encoding
+
+
+# ------------------------------------------------------------ parameters ---
+
+@dataclass(frozen=True)
+class Params:
+    n: int                      # ring degree = number of slots
+    t: int                      # plaintext modulus p (prime, = 1 mod 2n)
+    q: tuple                    # data primes q_0 .. q_{L-1}
+    P: int                      # special prime for relinearization
+
+    @property
+    def L(self) -> int:
+        return len(self.q)
+
+    @property
+    def Q(self) -> int:
+        out = 1
+        for x in self.q:
+            out *= x
+        return out
+
+    @property
+    def PQ(self) -> int:
+        return self.Q * self.P
+
+    @property
+    def delta(self) -> int:
+        return self.Q // self.t
+
+    @property
+    def moduli_pq(self) -> tuple:
+        """Limb order of a relinearization-key polynomial: q_0..q_{L-1}, P."""
+        return tuple(self.q) + (self.P,)
+
+    def gadget(self, j: int) -> int:
+        """g_j = (Q/q_j) [(Q/q_j)^-1]_{q_j}: g_j = 1 mod q_j, 0 mod q_i (i != j)."""
+        qh = self.Q // self.q[j]
+        return qh * pow(qh, -1, self.q[j])
+
+    def squarings(self) -> int:
+        """Multiplicative depth of EQ: ceil(log2(t - 1)) (Table
+        table:noise_levels, equality row)."""
+        return (self.t - 2).bit_length()
+
+
+def paper_params(n: int = 32768, t: int = 65537) -> Params:
+    q, P = nt.default_modulus_chain()
+    return Params(n, t, tuple(q), P)
+
+
+# --------------------------------------------------------- integer helpers ---
+
+def reduce(a, M: int) -> np.ndarray:
+    return ring.as_object(a) % M
+
+
+def centred(a, M: int) -> np.ndarray:
+    """Representatives in (-M/2, M/2] (for odd M: |x| <= (M-1)/2)."""
+    a = ring.as_object(a) % M
+    return np.where(a > M // 2, a - M, a)
+
+
+def round_div(x, d: int) -> np.ndarray:
+    """Nearest integer to x / d for integer x and d > 0 (halves round up;
+    no call below can meet a half)."""
+    return (2 * ring.as_object(x) + d) // (2 * d)
+
+
+def to_limbs(poly, moduli) -> np.ndarray:
+    """Exchange format: [len(moduli), N] int64 residues in [0, m_i)."""
+    a = ring.as_object(poly)
+    return np.stack([(a % m).astype(np.int64) for m in moduli])
+
+
+def from_limbs(limbs, moduli) -> np.ndarray:
+    """Integers in [0, prod(moduli)) from residues (Chinese remainder)."""
+    limbs = np.asarray(limbs)
+    M = 1
+    for m in moduli:
+        M *= m
+    acc = np.zeros(limbs.shape[-1], dtype=object)
+    for i, m in enumerate(moduli):
+        Mi = M // m
+        acc = acc + limbs[i].astype(object) * (Mi * pow(Mi, -1, m))
+    return acc % M
+
+
+def poly_mul(a, b) -> np.ndarray:
+    return ring.negacyclic_product(a, b)
+
+
+# ------------------------------------------------------------------- keys ---
+
+@dataclass
+class SecretKey:
+    s: np.ndarray                     # ternary coefficients (object ints)
+
+
+@dataclass
+class RelinKey:
+    b: list                           # L polys mod PQ
+    a: list                           # L polys mod PQ
+    _own_cache: dict = field(default_factory=dict, repr=False)
+
+    def limbs(self, params: Params) -> np.ndarray:
+        """Exchange format [L][2][L+1][N] int64, limbs in moduli_pq order,
+        coefficient domain."""
+        m = params.moduli_pq
+        return np.stack([np.stack([to_limbs(self.b[j], m), to_limbs(self.a[j], m)])
+                         for j in range(params.L)])
+
+
+def keygen(params: Params, rnd) -> tuple[SecretKey, RelinKey]:
+    """Secret key and relinearization key from caller-drawn randomness
+    (`synth.key_randomness`)."""
+    s = ring.as_object(rnd.s)
+    s2 = poly_mul(s, s)
+    PQ = params.PQ
+    bs, as_ = [], []
+    for j in range(params.L):
+        a = from_limbs(rnd.a[j], params.moduli_pq)
+        e = ring.as_object(rnd.e[j])
+        b = (-poly_mul(a, s) + e + params.P * params.gadget(j) * s2) % PQ
+        bs.append(b)
+        as_.append(a)
+    return SecretKey(s), RelinKey(bs, as_)
+
+
+# ------------------------------------------------------ encrypt / decrypt ---
+
+def encrypt(params: Params, sk: SecretKey, m_poly, rnd) -> tuple:
+    """Secret-key BFV encryption of plaintext polynomial m (coefficients in
+    [0, t)) with caller-drawn randomness (`synth.enc_randomness`)."""
+    Q = params.Q
+    a = from_limbs(rnd.a, params.q)
+    e = ring.as_object(rnd.e)
+    c0 = (params.delta * ring.as_object(m_poly) + e - poly_mul(a, sk.s)) % Q
+    return (c0, a)
+
+
+def phase(params: Params, sk: SecretKey, ct) -> np.ndarray:
+    """[c_0 + c_1 s + c_2 s^2 + ...]_Q in [0, Q)."""
+    Q = params.Q
+    acc = ring.as_object(ct[0]) % Q
+    spow = None
+    for k in range(1, len(ct)):
+        spow = sk.s if spow is None else poly_mul(spow, sk.s)
+        acc = (acc + poly_mul(ct[k], spow)) % Q
+    return acc
+
+
+def decrypt(params: Params, sk: SecretKey, ct) -> np.ndarray:
+    """Plaintext polynomial [round(t * phase / Q)]_t."""
+    return round_div(params.t * phase(params, sk, ct), params.Q) % params.t
+
+
+def noise_bits(params: Params, sk: SecretKey, ct, m_true) -> float:
+    """Remaining budget log2(Q / (2 |w|_inf)) with w = t*phase - Q*m_true
+    reduced to (-tQ/2, tQ/2]; decryption returns m_true iff the result is
+    positive.  `m_true` is the true plaintext polynomial."""
+    Q, t = params.Q, params.t
+    w = centred(t * phase(params, sk, ct) - Q * ring.as_object(m_true), t * Q)
+    wmax = max(abs(int(x)) for x in w)
+    if wmax == 0:
+        return math.log2(Q)
+    return math.log2(Q) - math.log2(2 * wmax)
+
+
+# --------------------------------------------------------------- evaluate ---
+
+def sub(params: Params, x, y) -> tuple:
+    """Component-wise [x - y]_Q (BFV subtraction, Sec. 2.1.5)."""
+    Q = params.Q
+    return tuple((ring.as_object(a) - ring.as_object(b)) % Q for a, b in zip(x, y))
+
+
+def _scale_round(params: Params, d) -> np.ndarray:
+    return round_div(params.t * d, params.Q) % params.Q
+
+
+def multiply(params: Params, x, y) -> tuple:
+    """Textbook BFV product (before relinearization), three components."""
+    Q = params.Q
+    a0, a1 = centred(x[0], Q), centred(x[1], Q)
+    b0, b1 = centred(y[0], Q), centred(y[1], Q)
+    n = params.n
+    B = ring.OwnBasis(n * (Q // 2) ** 2 * 2, n)
+    fa0, fa1 = B.forward(B.residues(a0)), B.forward(B.residues(a1))
+    fb0, fb1 = B.forward(B.residues(b0)), B.forward(B.residues(b1))
+    d0 = B.to_int(B.inverse(B.mul(fa0, fb0)))
+    d1 = B.to_int(B.inverse(B.add(B.mul(fa0, fb1), B.mul(fa1, fb0))))
+    d2 = B.to_int(B.inverse(B.mul(fa1, fb1)))
+    return tuple(_scale_round(params, d) for d in (d0, d1, d2))
+
+
+def square(params: Params, x) -> tuple:
+    """multiply(x, x), computing the shared transforms once."""
+    Q = params.Q
+    a0, a1 = centred(x[0], Q), centred(x[1], Q)
+    n = params.n
+    B = ring.OwnBasis(n * (Q // 2) ** 2 * 2, n)
+    fa0, fa1 = B.forward(B.residues(a0)), B.forward(B.residues(a1))
+    d0 = B.to_int(B.inverse(B.mul(fa0, fa0)))
+    f01 = B.mul(fa0, fa1)
+    d1 = B.to_int(B.inverse(B.add(f01, f01)))
+    d2 = B.to_int(B.inverse(B.mul(fa1, fa1)))
+    return tuple(_scale_round(params, d) for d in (d0, d1, d2))
+
+
+def _evk_transformed(params: Params, rk: RelinKey, B: ring.OwnBasis):
+    key = B.primes
+    if key not in rk._own_cache:
+        rk._own_cache.clear()
+        rk._own_cache[key] = [(B.forward(B.residues(rk.b[j])), B.forward(B.residues(rk.a[j])))
+                              for j in range(params.L)]
+    return rk._own_cache[key]
+
+
+def relinearize(params: Params, rk: RelinKey, ct3) -> tuple:
+    """Key switching of the s^2 component with one digit per data prime."""
+    Q, P, n = params.Q, params.P, params.n
+    c0, c1, c2 = (ring.as_object(c) for c in ct3)
+    digits = [(c2 % qj).astype(np.int64) for qj in params.q]
+    bound = params.L * max(params.q) * params.PQ * n
+    B = ring.OwnBasis(bound, n)
+    evk = _evk_transformed(params, rk, B)
+    acc0 = np.zeros((len(B.primes), n), dtype=np.int64)
+    acc1 = np.zeros_like(acc0)
+    for j, dj in enumerate(digits):
+        fd = B.forward(B.residues(dj))
+        acc0 = B.add(acc0, B.mul(fd, evk[j][0]))
+        acc1 = B.add(acc1, B.mul(fd, evk[j][1]))
+    u0 = B.to_int(B.inverse(acc0))
+    u1 = B.to_int(B.inverse(acc1))
+    return ((c0 + round_div(u0, P)) % Q, (c1 + round_div(u1, P)) % Q)
+
+
+def square_relin(params: Params, rk: RelinKey, x) -> tuple:
+    return relinearize(params, rk, square(params, x))
+
+
+def mul_relin(params: Params, rk: RelinKey, x, y) -> tuple:
+    return relinearize(params, rk, multiply(params, x, y))
+
+
+def finish(params: Params, z) -> tuple:
+    """(Delta, 0) - z: the encryption of 1 - z (slot-wise)."""
+    Q = params.Q
+    c0 = (-ring.as_object(z[0])) % Q
+    c0[0] = (c0[0] + params.delta) % Q
+    return (c0, (-ring.as_object(z[1])) % Q)
+
+
+def eq_chain(params: Params, rk: RelinKey, x, y) -> tuple[list, tuple]:
+    """EQ(x, y) = 1 - (x - y)^(t-1) by left-to-right square-and-multiply on
+    the exponent t - 1, relinearizing after every product.  Returns the list
+    of intermediate ciphertexts (index 0 = x - y, then one per squaring) and
+    the output.  For a Fermat prime t (t - 1 = 2^k) the list holds exactly k
+    squarings."""
+    z = sub(params, x, y)
+    levels = [z]
+    e = params.t - 1
+    acc = z
+    for bit in bin(e)[3:]:
+        acc = square_relin(params, rk, acc)
+        if bit == "1":
+            acc = mul_relin(params, rk, acc, z)
+        levels.append(acc)
+    return levels, finish(params, acc)
+
+
+# ----------------------------------------------------------- slot helpers ---
+
+def encrypt_slots(params: Params, sk: SecretKey, slots, rnd) -> tuple:
+    return encrypt(params, sk, encoding.encode(slots, params.t), rnd)
+
+
+def decrypt_slots(params: Params, sk: SecretKey, ct) -> np.ndarray:
+    return encoding.decode(decrypt(params, sk, ct), params.t)
