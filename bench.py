@@ -1,0 +1,273 @@
+#!/usr/bin/env python3
+"""Throughput of the NSHEDB equality mask on one MI355X.
+
+One step = EQ(x, y) = 1 - (x - y)^(p-1) (Eq. eq:equality) over one column
+of 2^20 rows held as 32 BFV ciphertexts of 32,768 slots (n = 32768,
+log2(Q*P) <= 881, p = 65537: Sec. 5.1), i.e. the subtraction, 16 squarings
+each with relinearization, and the negate-and-add - every step of the hot
+path - with inputs already resident in HBM.  value = records (slots) per
+second.  The line also carries:
+
+  roofline      the dominant kernel's algorithmic FP64 VALU work per launch
+                over its mean launch time (HIP events on the launch stream,
+                recorded around every launch inside the timed region), against
+                the chip's FP64 VALU issue peak;
+  kernels       per-kernel-kind time and launch counts from the same events;
+  batched       512 instances of uneven size (rows log-uniform in
+                [2^14, 2^20]) in HIP-graph waves vs a per-instance launch loop;
+  cpu_baseline  the exact-integer oracle on a bounded sample, host cores.
+
+Inputs are seeded uniform residues: a fresh RLWE ciphertext is uniform to
+anyone without the key, and every kernel is data-oblivious.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# FP64 VALU issue rate of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# (= 78.6 TFLOP/s counting an FMA as two flops).
+PEAK_FP64_OPS = 256 * 64 * 2.4e9
+# FP64 VALU operations of one exact modular butterfly in this library:
+# twiddle product 6 (mul, fma, mul, rndne, fma, add), operand reduction 3
+# (mul, rndne, fma), sum and difference 2.
+OPS_PER_BUTTERFLY = 11
+PAPER_RECORDS_PER_S = 1.0 / 0.09e-3   # 0.09 ms per record, 1 CPU thread (SEAL)
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("ntt.hip", "rns.hip", "api.hip", "modarith.h", "kernels.h"):
+        with open(os.path.join(ROOT, "paper_2602_24271_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def roofline(prof: dict) -> tuple[dict, str]:
+    ntt = {k: v for k, v in prof.items() if k.startswith("ntt")}
+    dom = max(prof, key=lambda k: prof[k]["ms"])
+    if dom not in ntt:
+        # report the heaviest transform kind; the dominant kind is named too
+        dom_ntt = max(ntt, key=lambda k: ntt[k]["ms"])
+    else:
+        dom_ntt = dom
+    st = prof[dom_ntt]
+    per_launch_ops = st["work"] / st["launches"] * OPS_PER_BUTTERFLY
+    avg_s = st["ms"] / st["launches"] / 1e3
+    achieved = per_launch_ops / avg_s
+    traffic = None
+    tf = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tf):
+        with open(tf) as fh:
+            t = json.load(fh)
+        if t.get("kernel_hash") == kernel_hash() and dom_ntt in t.get("bytes_per_launch", {}):
+            traffic = t["bytes_per_launch"][dom_ntt]
+    return {
+        "bound": "alu",
+        "kernel": dom_ntt,
+        "dominant_kind": dom,
+        "achieved": achieved / 1e12,
+        "peak": PEAK_FP64_OPS / 1e12,
+        "unit": "TOP/s (FP64 VALU ops)",
+        "frac": achieved / PEAK_FP64_OPS,
+        "traffic": traffic,
+        "butterflies_per_launch": st["work"] / st["launches"],
+        "mean_launch_ms": st["ms"] / st["launches"],
+    }, dom_ntt
+
+
+def cpu_baseline() -> dict:
+    """The oracle, untuned, on one 32,768-slot ciphertext: one squaring with
+    relinearization (1/16 of that ciphertext's EQ), extrapolated x16."""
+    import numpy as np  # noqa: F401
+    import synth
+    from oracle import bfv
+    n = 32768
+    pr = bfv.paper_params(n)
+    t0 = time.perf_counter()
+    sk, rk = bfv.keygen(pr, synth.key_randomness(0, n, pr.moduli_pq, pr.L))
+    x, y = synth.column_pair_half_match(0, n)
+    cx = bfv.encrypt_slots(pr, sk, x, synth.enc_randomness(1, n, pr.q))
+    cy = bfv.encrypt_slots(pr, sk, y, synth.enc_randomness(2, n, pr.q))
+    z = bfv.sub(pr, cx, cy)
+    # key transform into the oracle's own basis is setup, not timed
+    from oracle import ring
+    bfv._evk_transformed(pr, rk, ring.OwnBasis(pr.L * max(pr.q) * pr.PQ * n, n))
+    log(f"oracle setup {time.perf_counter() - t0:.1f} s")
+    t1 = time.perf_counter()
+    bfv.square_relin(pr, rk, z)
+    dt = time.perf_counter() - t1
+    cpu = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"value": n / (16 * dt), "unit": "records/s", "cores": 1, "kind": "oracle",
+            "sample": f"one squaring+relinearization of one {n}-slot ciphertext "
+                      f"({dt:.2f} s), x16 for one ciphertext's EQ",
+            "host_cpu": cpu, "host_cores_available": os.cpu_count()}
+
+
+def batched(ctx, n_inst: int, reps: int) -> dict:
+    import torch
+    import synth
+    rows = synth.log_uniform_sizes(2, n_inst, 1 << 14, 1 << 20)
+    cts = [int(math.ceil(r / ctx.n)) for r in rows]
+    total = sum(cts)
+    dev = ctx.device
+    items = []
+    for i, m in enumerate(cts):
+        x = synth.uniform_device_residues((m, 2), ctx.q, ctx.n, 1000 + i, dev)
+        y = synth.uniform_device_residues((1, 2), ctx.q, ctx.n, 5000 + i, dev)
+        items.append((x, y))
+    outs = [torch.empty_like(x) for x, _ in items]
+    wave = 64
+    log(f"batched: {n_inst} instances, {total} ciphertexts, wave {wave}")
+    # graph path
+    ctx.eq_mask_batched(items, wave_ct=wave, use_graph=True, outs=outs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.eq_mask_batched(items, wave_ct=wave, use_graph=True, outs=outs)
+    torch.cuda.synchronize()
+    t_graph = (time.perf_counter() - t0) / reps
+    log(f"batched graph {t_graph * 1e3:.1f} ms")
+    # per-instance loop
+    for (x, y), o in zip(items[:4], outs[:4]):
+        ctx.eq_mask(x, y, o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for (x, y), o in zip(items, outs):
+            ctx.eq_mask(x, y, o)
+    torch.cuda.synchronize()
+    t_loop = (time.perf_counter() - t0) / reps
+    log(f"per-instance loop {t_loop * 1e3:.1f} ms")
+    recs = total * ctx.n
+    return {"instances": n_inst, "ciphertexts": total, "wave_ct": wave,
+            "records_per_s_graph": recs / t_graph, "records_per_s_loop": recs / t_loop,
+            "ms_graph": t_graph * 1e3, "ms_loop": t_loop * 1e3, "speedup": t_loop / t_graph}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n-ct", type=int, default=32, help="ciphertexts per column (2^20 rows)")
+    ap.add_argument("--batched-instances", type=int, default=512)
+    ap.add_argument("--batched-reps", type=int, default=1)
+    ap.add_argument("--skip-batched", action="store_true")
+    ap.add_argument("--skip-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(ciphertexts shard with no communication; see the design notes)", file=sys.stderr)
+        return 2
+
+    import torch
+    import synth
+    from paper_2602_24271_amd import Context
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        return 2
+    dev = torch.device("cuda", 0)
+    ctx = Context.paper(15)
+    n_ct = args.n_ct
+    log(f"context N={ctx.n} L={ctx.L} ext={ctx.L_ext} squarings={ctx.squarings}")
+    x = synth.uniform_device_residues((n_ct, 2), ctx.q, ctx.n, 0, dev)
+    y = synth.uniform_device_residues((n_ct, 2), ctx.q, ctx.n, 1, dev)
+    evk = synth.uniform_device_residues((ctx.L, 2), ctx.q + [ctx.P], ctx.n, 2, dev)
+    ctx.set_relin_key(evk)
+    del evk
+    out = torch.empty_like(x)
+    ctx.workspace(n_ct)
+    ctx.reset_margin_events()
+    for _ in range(args.warmup):
+        ctx.eq_mask(x, y, out)
+    torch.cuda.synchronize()
+    log("warmup done")
+
+    ctx.profile(True)
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(args.steps):
+        ctx.eq_mask(x, y, out)
+    end.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / args.steps
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    margin = ctx.margin_events()
+    records = n_ct * ctx.n
+    value = records / (ms / 1e3)
+    log(f"{ms:.2f} ms/step, {value:.4g} records/s")
+    roof, _ = roofline(prof)
+    kernels = {k: {"launches": v["launches"] // args.steps, "ms_per_step": v["ms"] / args.steps}
+               for k, v in prof.items()}
+
+    bat = None
+    if not args.skip_batched:
+        bat = batched(ctx, args.batched_instances, args.batched_reps)
+    cpu = None
+    if not args.skip_cpu:
+        cpu = cpu_baseline()
+        log(f"cpu baseline {cpu['value']:.1f} records/s")
+
+    line = {
+        "metric": "hot-kernel elements/s + % roofline at 1 GPU; batched and adjoint vs plain",
+        "value": value,
+        "unit": "records/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"EQ mask (16 squarings + relinearization) over a column of "
+                               f"{records} rows = {n_ct} BFV ciphertexts, N=32768, "
+                               f"log2(QP)<=881 (17+1 primes), p=65537",
+                   "rows": records, "ciphertexts": n_ct, "ring_degree": ctx.n,
+                   "data_primes": ctx.L, "plaintext_modulus": ctx.t},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "kernels": kernels,
+        "batched": bat,
+        "adjoint": None,
+        "adjoint_note": "no adjoint: the mask is discrete (Z_t plaintexts, R_Q ciphertexts)",
+        "margin_events": margin,
+        "paper_context": {"records_per_s": PAPER_RECORDS_PER_S,
+                          "hardware": "1 thread of a 16-core Intel Raptor Lake, Microsoft SEAL",
+                          "source": "Table tab:primitive-times, Equality row (0.09 ms per record)"},
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

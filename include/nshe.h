@@ -1,0 +1,222 @@
+/*
+ * nshe.h - C ABI of the MI355X (gfx950) library for the NSHEDB equality-mask
+ * hot path: word-level BFV ciphertext arithmetic on batch-encoded columns.
+ *
+ * What the calls compute (NSHEDB, arXiv 2602.24271):
+ *   - BFV subtraction of two ciphertexts (Sec. 2.1.5, BFV operations);
+ *   - one ciphertext multiplication followed by relinearization (Sec. 2.1.5;
+ *     Sec. 2.1.3 notes relinearization after each multiplication, and that a
+ *     product's depth is max(depth(A), depth(B)) + 1);
+ *   - the equality mask EQ(x, y) = 1 - (x - y)^(p-1) (Eq. eq:equality),
+ *     evaluated by exponentiation by squaring with ceil(log2(p-1))
+ *     multiplications (Sec. 4.3, equality checks; Table table:noise_levels).
+ *     For the paper's p = t = 65537 (Sec. 5.1) this is 16 squarings.
+ *
+ * Every result is an exact integer function of the inputs (the textbook
+ * BFV evaluation):
+ *   multiply     lift both operands' coefficients to (-Q/2, Q/2), form
+ *                d0 = a0 b0, d1 = a0 b1 + a1 b0, d2 = a1 b1 exactly in
+ *                Z[X]/(X^N + 1), output c_k = [round(t d_k / Q)]_Q;
+ *   relinearize  digits D_j = [c2]_{q_j} in [0, q_j), u_b = sum_j D_j evk_j[b],
+ *                output [c_b + round(u_b / P)]_Q;
+ *   EQ           z = [x - y]_Q, z <- relin(z * z) (t - 1 = 2^k times k),
+ *                out = ([-z0 + Delta e_0]_Q, [-z1]_Q) with Delta = floor(Q/t)
+ *                (the trivial encryption of the constant 1, minus z).
+ * The device never holds the secret key (the trusted-client split of
+ * Sec. 3, system overview): keys are generated and data encrypted and
+ * decrypted by the caller.
+ *
+ * Data layout (the exchange format):
+ *   ciphertext  int64 [n_ct][2][L][N]  residues in [0, q_i), coefficient
+ *               domain, natural coefficient order, limb i belongs to q_i;
+ *   relin key   int64 [L][2][L+1][N]   digit j, component b (b = 0 is
+ *               [-a_j s + e_j + P g_j s^2]_{PQ}, b = 1 is a_j), limbs in the
+ *               order q_0 .. q_{L-1}, P; coefficient domain.
+ * Pointers named *_dev are device memory of the context's HIP device;
+ * pointers named *_host are host memory.  The caller owns every buffer
+ * passed in; the library borrows it for the duration of the work enqueued
+ * on the given stream and keeps no reference afterwards (except the relin
+ * key, which is copied).  The library owns only its context (tables and the
+ * transformed relinearization key).
+ *
+ * Workspace: calls that take (ws_dev, ws_bytes) need a caller-allocated
+ * device scratch area of at least nshe_workspace_bytes(ctx, n_ct) bytes,
+ * 256-byte aligned; the library allocates nothing on these paths.
+ *
+ * Streams: `stream` is a hipStream_t (NULL = the null stream).  All work is
+ * enqueued asynchronously; results are valid after the stream synchronises.
+ *
+ * Errors: every int-returning call returns NSHE_OK (0) or a negative code;
+ * nshe_last_error() gives a message for the calling thread.  Arguments are
+ * validated on the host before any work is enqueued (null pointers, sizes,
+ * alignment, parameter ranges); a rejected call enqueues nothing.  Residues
+ * are NOT range-checked on the device (residues outside [0, q_i) give
+ * undefined - but memory-safe - results).  Asynchronous device faults are
+ * reported by the next synchronising HIP call.  No C++ exception crosses
+ * the ABI.  Calls on one context from several host threads must not
+ * overlap.
+ */
+#ifndef NSHE_H
+#define NSHE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NSHE_OK 0
+#define NSHE_EINVAL -1   /* bad argument (null pointer, bad size, bad prime) */
+#define NSHE_ESHAPE -2   /* sizes inconsistent with the context */
+#define NSHE_ENOMEM -3   /* workspace too small, or context allocation failed */
+#define NSHE_EDEVICE -4  /* a HIP runtime call failed */
+#define NSHE_EDEPTH -5   /* t - 1 is not a power of two (EQ chain needs it) */
+#define NSHE_ENOKEY -6   /* relinearization key not set */
+
+#define NSHE_MAX_L 24        /* data primes */
+#define NSHE_MAX_LOG2N 15    /* ring degree up to 32768 */
+#define NSHE_MIN_LOG2N 3
+
+typedef struct nshe_ctx nshe_ctx;
+
+/* BFV parameters (Sec. 5.1: n = 32768, log Q = 881, t = 65537).
+ *   log2_n  ring degree N = 2^log2_n, NSHE_MIN_LOG2N..NSHE_MAX_LOG2N;
+ *   t       plaintext modulus, odd, 2 < t < 2^24, coprime to every prime;
+ *   L       number of data primes, 1..NSHE_MAX_L;
+ *   q_host  L distinct primes, each in [2^48, 2^49) and = 1 (mod 2N);
+ *   P       the special prime, same constraints, distinct from the q_i.
+ * Q = prod q_i.  The library picks its own extension basis (primes of the
+ * same form below min(q, P)) large enough for exact products. */
+typedef struct {
+  uint32_t log2_n;
+  uint64_t t;
+  int32_t L;
+  const uint64_t* q_host;
+  uint64_t P;
+} nshe_params;
+
+/* Read-only description of a context (sizes for the caller's buffers). */
+typedef struct {
+  uint32_t n;            /* ring degree N */
+  int32_t L;             /* data primes */
+  int32_t L_ext;         /* extension primes chosen by the library */
+  int32_t squarings;     /* k with t - 1 = 2^k, or -1 */
+  uint64_t ext_primes[32];
+  size_t ct_words;       /* int64 words of one ciphertext: 2 * L * N */
+  size_t relin_key_words;/* int64 words of the relin key: L * 2 * (L+1) * N */
+} nshe_info;
+
+/* Create a context on HIP device `hip_device`: validates the parameters,
+ * selects the extension basis and uploads its tables (this call allocates
+ * device memory; none of the evaluation calls below do). */
+int nshe_ctx_create(const nshe_params* params, int hip_device, nshe_ctx** out);
+int nshe_ctx_destroy(nshe_ctx* ctx);
+int nshe_ctx_info(const nshe_ctx* ctx, nshe_info* out);
+
+/* Install the relinearization key (Sec. 2.1.3).  Copies and transforms
+ * `evk_dev` (layout above) into context-owned memory on `stream`; the
+ * caller may free `evk_dev` once the stream has synchronised.  Allocates the
+ * context-owned key store on first use. */
+int nshe_set_relin_key(nshe_ctx* ctx, const int64_t* evk_dev, void* stream);
+
+/* Device scratch needed by the evaluation calls for n_ct ciphertexts. */
+size_t nshe_workspace_bytes(const nshe_ctx* ctx, int n_ct);
+
+/* out = [x - y]_Q, component-wise, for n_ct ciphertext pairs (Sec. 2.1.5).
+ * out may alias x or y. */
+int nshe_sub(nshe_ctx* ctx, const int64_t* x_dev, const int64_t* y_dev,
+             int64_t* out_dev, int n_ct, void* stream);
+
+/* out = relin(in * in): one squaring level of the EQ chain (Sec. 4.3).
+ * out may alias in. */
+int nshe_square_relin(nshe_ctx* ctx, const int64_t* in_dev, int64_t* out_dev,
+                      int n_ct, void* ws_dev, size_t ws_bytes, void* stream);
+
+/* out = relin(a * b) (Sec. 2.1.5 multiplication; SELECT and AND, Eq.
+ * eq:select and Table tab:operator-support, are this call). */
+int nshe_mul_relin(nshe_ctx* ctx, const int64_t* a_dev, const int64_t* b_dev,
+                   int64_t* out_dev, int n_ct, void* ws_dev, size_t ws_bytes,
+                   void* stream);
+
+/* The three-component product before relinearization: out3 is int64
+ * [n_ct][3][L][N] = ([round(t d_k / Q)]_Q)_{k=0,1,2}. */
+int nshe_multiply(nshe_ctx* ctx, const int64_t* a_dev, const int64_t* b_dev,
+                  int64_t* out3_dev, int n_ct, void* ws_dev, size_t ws_bytes,
+                  void* stream);
+
+/* Relinearization alone: in3 int64 [n_ct][3][L][N] -> out [n_ct][2][L][N]. */
+int nshe_relinearize(nshe_ctx* ctx, const int64_t* in3_dev, int64_t* out_dev,
+                     int n_ct, void* ws_dev, size_t ws_bytes, void* stream);
+
+/* EQ(x, y) = 1 - (x - y)^(t-1) (Eq. eq:equality) for n_ct ciphertexts:
+ * x is [n_ct][2][L][N]; y is the same shape, or one ciphertext broadcast to
+ * every x when y_broadcast != 0 (an encrypted predicate constant).  Requires
+ * t - 1 = 2^k (k squarings).  out may alias x (not y when broadcast). */
+int nshe_eq_mask(nshe_ctx* ctx, const int64_t* x_dev, const int64_t* y_dev,
+                 int64_t* out_dev, int n_ct, int y_broadcast, void* ws_dev,
+                 size_t ws_bytes, void* stream);
+
+/* Batched EQ over instances of uneven size: item i has n_ct ciphertexts.
+ * The items' ciphertexts are processed together, in waves of at most
+ * `wave_ct` ciphertexts (0 = as many as the workspace holds), with one
+ * shared pass over the relinearization key per squaring and wave.  When
+ * use_graph != 0 the whole chain of a wave is captured once into a HIP graph
+ * and replayed (capture happens on `stream`; it must not already be
+ * capturing).  ws_bytes must cover nshe_workspace_bytes(ctx, wave size). */
+typedef struct {
+  const int64_t* x_dev;
+  const int64_t* y_dev;
+  int64_t* out_dev;
+  int32_t n_ct;
+  int32_t y_broadcast;
+} nshe_item;
+
+int nshe_eq_mask_batched(nshe_ctx* ctx, const nshe_item* items_host,
+                         int n_items, int wave_ct, int use_graph, void* ws_dev,
+                         size_t ws_bytes, void* stream);
+
+/* Negacyclic NTT (debug/parity entry): for each of n_poly polynomials of L
+ * data-prime limbs (int64 [n_poly][L][N], residues in [0, q_i)), out holds
+ * the evaluations at psi_i^(2j+1), j = 0..N-1, in natural j order, where
+ * psi_i = g^((q_i - 1) / 2N) for the smallest primitive root g of q_i.
+ * inverse != 0 applies the inverse transform (evaluations -> coefficients). */
+int nshe_ntt(nshe_ctx* ctx, const int64_t* in_dev, int64_t* out_dev,
+             int n_poly, int inverse, void* ws_dev, size_t ws_bytes,
+             void* stream);
+
+/* Exactness monitor.  The centred lift between residue bases decides an
+ * overflow count from a floating-point estimate; when the estimate falls
+ * within its proven error bound of a decision boundary the library takes
+ * an exact mixed-radix comparison instead and counts the event here.
+ * Results are exact either way.  (Synchronises `stream` to read.) */
+int nshe_margin_events(nshe_ctx* ctx, uint64_t* count_host, void* stream);
+int nshe_reset_margin_events(nshe_ctx* ctx, void* stream);
+
+/* Kernel timing.  nshe_profile(ctx, 1) starts recording a pair of HIP
+ * events on the call's stream around every kernel launch of subsequent
+ * non-graph calls (clearing earlier records); nshe_profile(ctx, 0) stops.
+ * nshe_profile_read waits for the recorded events and returns, per kernel
+ * kind, the launch count, the summed event time and the summed algorithmic
+ * work: butterflies for the transform kinds (ntt_fwd, ntt_inv, ntt_digit;
+ * N/2 log2 N per limb), coefficient-limbs or coefficients for the others.
+ * Reading clears the records. */
+typedef struct {
+  char name[24];
+  uint64_t launches;
+  double total_ms;
+  double work;
+} nshe_kernel_stat;
+
+int nshe_profile(nshe_ctx* ctx, int enable);
+int nshe_profile_read(nshe_ctx* ctx, nshe_kernel_stat* stats_host, int max_stats,
+                      int* n_stats_host);
+
+/* Message for the last error on the calling thread ("" if none). */
+const char* nshe_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NSHE_H */

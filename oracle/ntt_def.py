@@ -25,3 +25,14 @@ def evaluations(a, q: int) -> list[int]:
             acc = (acc * z + int(c)) % q
         out.append(acc)
     return out
+
+
+def evaluation_at(a, q: int, j: int) -> int:
+    """a(psi^(2j+1)) mod q for one index j (Horner, O(N))."""
+    n = len(a)
+    psi = nt.root_of_unity(q, 2 * n)
+    z = pow(psi, 2 * j + 1, q)
+    acc = 0
+    for c in reversed(list(a)):
+        acc = (acc * z + int(c)) % q
+    return acc

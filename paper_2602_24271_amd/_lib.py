@@ -1,0 +1,92 @@
+"""ctypes binding of libnshe.so (argument marshalling only).
+
+The library is the only compute path: there is no fallback.  Loading fails
+loudly when libnshe.so has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnshe.so")
+
+NSHE_MAX_L = 24
+
+
+class NsheParams(ctypes.Structure):
+    _fields_ = [("log2_n", ctypes.c_uint32), ("t", ctypes.c_uint64), ("L", ctypes.c_int32),
+                ("q_host", ctypes.POINTER(ctypes.c_uint64)), ("P", ctypes.c_uint64)]
+
+
+class NsheInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint32), ("L", ctypes.c_int32), ("L_ext", ctypes.c_int32),
+                ("squarings", ctypes.c_int32), ("ext_primes", ctypes.c_uint64 * 32),
+                ("ct_words", ctypes.c_size_t), ("relin_key_words", ctypes.c_size_t)]
+
+
+class NsheItem(ctypes.Structure):
+    _fields_ = [("x_dev", ctypes.c_void_p), ("y_dev", ctypes.c_void_p),
+                ("out_dev", ctypes.c_void_p), ("n_ct", ctypes.c_int32),
+                ("y_broadcast", ctypes.c_int32)]
+
+
+class NsheKernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_uint64),
+                ("total_ms", ctypes.c_double), ("work", ctypes.c_double)]
+
+
+# name -> (restype, argtypes)
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_SZ = ctypes.c_size_t
+SIGNATURES = {
+    "nshe_ctx_create": (_I, [ctypes.POINTER(NsheParams), _I, ctypes.POINTER(_P)]),
+    "nshe_ctx_destroy": (_I, [_P]),
+    "nshe_ctx_info": (_I, [_P, ctypes.POINTER(NsheInfo)]),
+    "nshe_set_relin_key": (_I, [_P, _P, _P]),
+    "nshe_workspace_bytes": (_SZ, [_P, _I]),
+    "nshe_sub": (_I, [_P, _P, _P, _P, _I, _P]),
+    "nshe_square_relin": (_I, [_P, _P, _P, _I, _P, _SZ, _P]),
+    "nshe_mul_relin": (_I, [_P, _P, _P, _P, _I, _P, _SZ, _P]),
+    "nshe_multiply": (_I, [_P, _P, _P, _P, _I, _P, _SZ, _P]),
+    "nshe_relinearize": (_I, [_P, _P, _P, _I, _P, _SZ, _P]),
+    "nshe_eq_mask": (_I, [_P, _P, _P, _P, _I, _I, _P, _SZ, _P]),
+    "nshe_eq_mask_batched": (_I, [_P, ctypes.POINTER(NsheItem), _I, _I, _I, _P, _SZ, _P]),
+    "nshe_ntt": (_I, [_P, _P, _P, _I, _I, _P, _SZ, _P]),
+    "nshe_margin_events": (_I, [_P, ctypes.POINTER(ctypes.c_uint64), _P]),
+    "nshe_reset_margin_events": (_I, [_P, _P]),
+    "nshe_profile": (_I, [_P, _I]),
+    "nshe_profile_read": (_I, [_P, ctypes.POINTER(NsheKernelStat), _I, ctypes.POINTER(_I)]),
+    "nshe_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2602_24271_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class NsheError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"nshe error {code}: {msg}")
+        self.code = code
+
+
+def check(rc: int) -> None:
+    if rc != 0:
+        raise NsheError(rc, load().nshe_last_error().decode())

@@ -1,0 +1,207 @@
+"""Python face of the library: torch tensors in, torch tensors out.
+
+Every call marshals pointers, sizes and the current HIP stream into the C
+ABI (libnshe.so); all arithmetic runs in the library's kernels.  Device
+memory (ciphertexts, keys, workspace) comes from PyTorch's allocator.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+
+
+def _ptr(t: torch.Tensor) -> int:
+    return t.data_ptr()
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+class Context:
+    """BFV context on one HIP device (NSHEDB Sec. 5.1 parameters by default)."""
+
+    def __init__(self, log2_n: int, t: int, q, P: int, device: int = 0):
+        lib = _lib.load()
+        self.device = torch.device("cuda", device)
+        qa = (ctypes.c_uint64 * len(q))(*q)
+        pr = _lib.NsheParams(log2_n, t, len(q), ctypes.cast(qa, ctypes.POINTER(ctypes.c_uint64)), P)
+        h = ctypes.c_void_p()
+        _lib.check(lib.nshe_ctx_create(ctypes.byref(pr), device, ctypes.byref(h)))
+        self._h = h
+        self._lib = lib
+        info = _lib.NsheInfo()
+        _lib.check(lib.nshe_ctx_info(h, ctypes.byref(info)))
+        self.n = info.n
+        self.L = info.L
+        self.L_ext = info.L_ext
+        self.squarings = info.squarings
+        self.ext_primes = [info.ext_primes[i] for i in range(info.L_ext)]
+        self.q = list(q)
+        self.P = P
+        self.t = t
+        self._ws = None
+        self._key = None
+
+    @classmethod
+    def paper(cls, log2_n: int = 15, device: int = 0) -> "Context":
+        from .params import paper_params
+        p = paper_params(log2_n)
+        return cls(p["log2_n"], p["t"], p["q"], p["P"], device)
+
+    def close(self):
+        if self._h:
+            self._lib.nshe_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ helpers
+    def ct_shape(self, n_ct: int):
+        return (n_ct, 2, self.L, self.n)
+
+    def workspace_bytes(self, n_ct: int) -> int:
+        return int(self._lib.nshe_workspace_bytes(self._h, n_ct))
+
+    def workspace(self, n_ct: int) -> torch.Tensor:
+        need = self.workspace_bytes(n_ct)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = None
+            self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def _check_ct(self, x: torch.Tensor, comps: int = 2) -> int:
+        if x.dtype != torch.int64 or x.device != self.device or not x.is_contiguous():
+            raise ValueError("ciphertexts must be contiguous int64 tensors on the context device")
+        if x.dim() != 4 or x.shape[1] != comps or x.shape[2] != self.L or x.shape[3] != self.n:
+            raise ValueError(f"expected shape [n_ct, {comps}, {self.L}, {self.n}], got {tuple(x.shape)}")
+        return x.shape[0]
+
+    # ---------------------------------------------------------------- API
+    def set_relin_key(self, evk: torch.Tensor) -> None:
+        want = (self.L, 2, self.L + 1, self.n)
+        if evk.dtype != torch.int64 or tuple(evk.shape) != want or evk.device != self.device:
+            raise ValueError(f"relin key must be int64 {want} on the context device")
+        evk = evk.contiguous()
+        _lib.check(self._lib.nshe_set_relin_key(self._h, _ptr(evk), _stream()))
+        self._key = evk  # keep alive until the stream has consumed it
+        torch.cuda.current_stream().synchronize()
+        self._key = None
+
+    def sub(self, x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
+        n = self._check_ct(x)
+        if self._check_ct(y) != n:
+            raise ValueError("x and y must hold the same number of ciphertexts")
+        out = torch.empty_like(x)
+        _lib.check(self._lib.nshe_sub(self._h, _ptr(x), _ptr(y), _ptr(out), n, _stream()))
+        return out
+
+    def square_relin(self, x: torch.Tensor) -> torch.Tensor:
+        n = self._check_ct(x)
+        out = torch.empty_like(x)
+        ws = self.workspace(n)
+        _lib.check(self._lib.nshe_square_relin(self._h, _ptr(x), _ptr(out), n, _ptr(ws),
+                                               ws.numel(), _stream()))
+        return out
+
+    def mul_relin(self, a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
+        n = self._check_ct(a)
+        if self._check_ct(b) != n:
+            raise ValueError("a and b must hold the same number of ciphertexts")
+        out = torch.empty_like(a)
+        ws = self.workspace(n)
+        _lib.check(self._lib.nshe_mul_relin(self._h, _ptr(a), _ptr(b), _ptr(out), n, _ptr(ws),
+                                            ws.numel(), _stream()))
+        return out
+
+    def multiply(self, a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
+        n = self._check_ct(a)
+        if self._check_ct(b) != n:
+            raise ValueError("a and b must hold the same number of ciphertexts")
+        out = torch.empty((n, 3, self.L, self.n), dtype=torch.int64, device=self.device)
+        ws = self.workspace(n)
+        _lib.check(self._lib.nshe_multiply(self._h, _ptr(a), _ptr(b), _ptr(out), n, _ptr(ws),
+                                           ws.numel(), _stream()))
+        return out
+
+    def relinearize(self, c3: torch.Tensor) -> torch.Tensor:
+        n = self._check_ct(c3, comps=3)
+        out = torch.empty((n, 2, self.L, self.n), dtype=torch.int64, device=self.device)
+        ws = self.workspace(n)
+        _lib.check(self._lib.nshe_relinearize(self._h, _ptr(c3), _ptr(out), n, _ptr(ws),
+                                              ws.numel(), _stream()))
+        return out
+
+    def eq_mask(self, x: torch.Tensor, y: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """EQ(x, y) = 1 - (x - y)^(t-1) (Eq. eq:equality).  y holds as many
+        ciphertexts as x, or one ciphertext broadcast to all of them."""
+        n = self._check_ct(x)
+        ny = self._check_ct(y)
+        if ny not in (n, 1):
+            raise ValueError("y must hold n_ct ciphertexts or one")
+        bcast = 1 if (ny == 1 and n != 1) else 0
+        if out is None:
+            out = torch.empty_like(x)
+        ws = self.workspace(n)
+        _lib.check(self._lib.nshe_eq_mask(self._h, _ptr(x), _ptr(y), _ptr(out), n, bcast, _ptr(ws),
+                                          ws.numel(), _stream()))
+        return out
+
+    def eq_mask_batched(self, items, wave_ct: int = 0, use_graph: bool = True, outs=None):
+        """items: list of (x, y) with y one ciphertext (broadcast) or as many
+        as x.  Returns the list of outputs."""
+        arr = (_lib.NsheItem * len(items))()
+        res = []
+        for i, (x, y) in enumerate(items):
+            n = self._check_ct(x)
+            ny = self._check_ct(y)
+            if ny not in (n, 1):
+                raise ValueError("y must hold n_ct ciphertexts or one")
+            out = outs[i] if outs is not None else torch.empty_like(x)
+            res.append(out)
+            arr[i] = _lib.NsheItem(_ptr(x), _ptr(y), _ptr(out), n, 1 if (ny == 1 and n != 1) else 0)
+        total = sum(int(x.shape[0]) for x, _ in items)
+        wave = wave_ct if wave_ct > 0 else total
+        ws = self.workspace(min(wave, total))
+        _lib.check(self._lib.nshe_eq_mask_batched(self._h, arr, len(items), wave_ct,
+                                                  1 if use_graph else 0, _ptr(ws), ws.numel(),
+                                                  _stream()))
+        return res
+
+    def ntt(self, polys: torch.Tensor) -> torch.Tensor:
+        """Forward negacyclic NTT of [n_poly, L, N] int64 limbs: evaluations
+        at psi_i^(2j+1) in natural j order."""
+        if polys.dim() != 3 or polys.shape[1] != self.L or polys.shape[2] != self.n:
+            raise ValueError("polys must be [n_poly, L, N]")
+        polys = polys.contiguous()
+        n = polys.shape[0]
+        out = torch.empty_like(polys)
+        ws = torch.empty(n * self.L * self.n * 8, dtype=torch.uint8, device=self.device)
+        _lib.check(self._lib.nshe_ntt(self._h, _ptr(polys), _ptr(out), n, 0, _ptr(ws), ws.numel(),
+                                      _stream()))
+        return out
+
+    def profile(self, enable: bool) -> None:
+        _lib.check(self._lib.nshe_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        arr = (_lib.NsheKernelStat * 16)()
+        n = ctypes.c_int()
+        _lib.check(self._lib.nshe_profile_read(self._h, arr, 16, ctypes.byref(n)))
+        return {arr[i].name.decode(): {"launches": arr[i].launches, "ms": arr[i].total_ms,
+                                        "work": arr[i].work} for i in range(n.value)}
+
+    def margin_events(self) -> int:
+        v = ctypes.c_uint64()
+        _lib.check(self._lib.nshe_margin_events(self._h, ctypes.byref(v), _stream()))
+        return v.value
+
+    def reset_margin_events(self) -> None:
+        _lib.check(self._lib.nshe_reset_margin_events(self._h, _stream()))

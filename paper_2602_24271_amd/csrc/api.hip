@@ -1,0 +1,965 @@
+// C ABI: context (parameter validation, extension basis, constant tables,
+// twiddles, relinearization key) and the evaluation entry points.
+#include "../../include/nshe.h"
+
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+namespace nshe {
+
+using u64 = uint64_t;
+using u128 = unsigned __int128;
+
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+// ------------------------------------------------------- host number theory
+
+static u64 mulmod(u64 a, u64 b, u64 m) { return (u64)((u128)a * b % m); }
+
+static u64 powmod(u64 a, u64 e, u64 m) {
+  u64 r = 1 % m;
+  a %= m;
+  while (e) {
+    if (e & 1) r = mulmod(r, a, m);
+    a = mulmod(a, a, m);
+    e >>= 1;
+  }
+  return r;
+}
+
+// Deterministic Miller-Rabin for 64-bit n (the first twelve primes as bases).
+static bool is_prime(u64 n) {
+  static const u64 bases[] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
+  if (n < 2) return false;
+  for (u64 p : bases)
+    if (n % p == 0) return n == p;
+  u64 d = n - 1;
+  int s = 0;
+  while ((d & 1) == 0) {
+    d >>= 1;
+    ++s;
+  }
+  for (u64 a : bases) {
+    u64 x = powmod(a, d, n);
+    if (x == 1 || x == n - 1) continue;
+    bool composite = true;
+    for (int r = 1; r < s; ++r) {
+      x = mulmod(x, x, n);
+      if (x == n - 1) {
+        composite = false;
+        break;
+      }
+    }
+    if (composite) return false;
+  }
+  return true;
+}
+
+static u64 invmod(u64 a, u64 m) { return powmod(a % m, m - 2, m); }  // m prime
+
+static u64 primitive_root(u64 q) {
+  std::vector<u64> fs;
+  u64 n = q - 1;
+  for (u64 d = 2; d * d <= n; d += (d == 2 ? 1 : 2)) {
+    if (n % d == 0) {
+      fs.push_back(d);
+      while (n % d == 0) n /= d;
+    }
+  }
+  if (n > 1) fs.push_back(n);
+  for (u64 g = 2;; ++g) {
+    bool ok = true;
+    for (u64 f : fs)
+      if (powmod(g, (q - 1) / f, q) == 1) {
+        ok = false;
+        break;
+      }
+    if (ok) return g;
+  }
+}
+
+static double bal(u64 x, u64 m) {
+  x %= m;
+  return x > m / 2 ? (double)x - (double)m : (double)x;
+}
+
+static u64 prod_mod(const std::vector<u64>& v, int skip, u64 m) {
+  u64 r = 1 % m;
+  for (int i = 0; i < (int)v.size(); ++i)
+    if (i != skip) r = mulmod(r, v[i] % m, m);
+  return r;
+}
+
+static int brv(int x, int bits) {
+  int r = 0;
+  for (int i = 0; i < bits; ++i)
+    if (x & (1 << i)) r |= 1 << (bits - 1 - i);
+  return r;
+}
+
+}  // namespace nshe
+
+using namespace nshe;
+
+struct nshe_ctx {
+  int device = 0;
+  int log2n = 0, n = 0, L = 0, LB = 0, K = 0;
+  u64 t = 0;
+  int squarings = -1;
+  std::vector<u64> primes;  // q_0..q_{L-1}, b_0..b_L, P
+  int loge = 0, r0 = 0, rounds = 0, tw_len = 0;
+  void* dev_tables = nullptr;
+  int* lp_ext = nullptr;  // identity over 2L+1 limbs
+  int* lp_ks = nullptr;   // 0..L-1, 2L+1
+  Tables tb{};
+  double* evk = nullptr;  // [L][2][L+1][N] NTT domain
+  bool has_key = false;
+  struct GraphEntry {
+    hipGraphExec_t exec;
+  };
+  std::map<std::vector<uintptr_t>, GraphEntry> graphs;
+  // kernel timing (HIP events around every launch of a non-graph call)
+  bool prof = false;
+  struct Rec {
+    int kind;
+    hipEvent_t a, b;
+    double work;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  hipStream_t cap_stream = nullptr;  // capture-only stream (the null stream cannot capture)
+};
+
+namespace nshe {
+
+#define HIPCHK(expr)                                                            \
+  do {                                                                          \
+    hipError_t e_ = (expr);                                                     \
+    if (e_ != hipSuccess)                                                       \
+      return fail(NSHE_EDEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+static int W_of(const nshe_ctx* c) { return 2 * c->L + 1; }
+
+// ------------------------------------------------------------ profiling
+
+enum Kind { K_SUB, K_LIFT, K_NTT_FWD, K_TENSOR, K_NTT_INV, K_SCALE, K_NTT_DIGIT, K_KS_MAC,
+            K_MODDOWN, K_CONVERT, K_COUNT };
+static const char* kKindName[K_COUNT] = {"sub",   "lift",      "ntt_fwd", "tensor",  "ntt_inv",
+                                         "scale", "ntt_digit", "ks_mac",  "moddown", "convert"};
+
+static hipEvent_t take_event(nshe_ctx* c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets one launch with events on its stream when profiling is on.
+struct Prof {
+  nshe_ctx* c;
+  int kind;
+  hipStream_t st;
+  double work;
+  hipEvent_t a = nullptr;
+  Prof(nshe_ctx* c_, int kind_, hipStream_t st_, double work_)
+      : c(c_), kind(kind_), st(st_), work(work_) {
+    if (c->prof && (a = take_event(c))) (void)hipEventRecord(a, st);
+  }
+  ~Prof() {
+    if (!a) return;
+    hipEvent_t b = take_event(c);
+    if (!b) return;
+    (void)hipEventRecord(b, st);
+    c->recs.push_back(nshe_ctx::Rec{kind, a, b, work});
+  }
+};
+
+static double ntt_work(const nshe_ctx* c, int polys_times_limbs) {
+  return (double)polys_times_limbs * (c->n / 2) * c->log2n;
+}
+
+// ------------------------------------------------------------- workspace
+
+struct Ws {
+  double* ext;   // [n_ct][2][W][N]
+  double* dt;    // [n_ct][3][W][N]
+  double* dig;   // [n_ct][L][K][N]  (also the second operand's extension)
+  double* acc;   // [n_ct][2][K][N]
+};
+
+static size_t ws_doubles(const nshe_ctx* c, int n_ct) {
+  const size_t W = W_of(c), K = c->L + 1, L = c->L, N = c->n;
+  const size_t dig = std::max(L * K, 2 * W);
+  return (size_t)n_ct * N * (2 * W + 3 * W + dig + 2 * K);
+}
+
+static Ws carve(const nshe_ctx* c, void* ws, int n_ct) {
+  const size_t W = W_of(c), K = c->L + 1, L = c->L, N = c->n;
+  const size_t dig = std::max(L * K, 2 * W);
+  double* p = static_cast<double*>(ws);
+  Ws w;
+  w.ext = p;
+  p += (size_t)n_ct * 2 * W * N;
+  w.dt = p;
+  p += (size_t)n_ct * 3 * W * N;
+  w.dig = p;
+  p += (size_t)n_ct * dig * N;
+  w.acc = p;
+  return w;
+}
+
+static int check_ws(const nshe_ctx* c, void* ws, size_t bytes, int n_ct) {
+  if (!ws) return fail(NSHE_EINVAL, "workspace pointer is null");
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(NSHE_EINVAL, "workspace not 256-byte aligned");
+  if (bytes < ws_doubles(c, n_ct) * sizeof(double))
+    return fail(NSHE_ENOMEM, "workspace smaller than nshe_workspace_bytes(ctx, n_ct)");
+  return NSHE_OK;
+}
+
+// ---------------------------------------------------------- level pieces
+
+static int ntt_job_ext(nshe_ctx* c, double* base, int npoly, int dir, hipStream_t st) {
+  NttJob j{};
+  j.base = base;
+  j.poly_stride = (size_t)W_of(c) * c->n;
+  j.npoly = npoly;
+  j.nlimb = W_of(c);
+  j.limb_prime = c->lp_ext;
+  j.count = npoly * j.nlimb;
+  Prof pf(c, dir ? K_NTT_INV : K_NTT_FWD, st, ntt_work(c, j.count));
+  HIPCHK(run_ntt(c->log2n, j, c->tb, dir, st));
+  return NSHE_OK;
+}
+
+static int ntt_job_ks(nshe_ctx* c, double* base, int npoly, int dir, hipStream_t st) {
+  NttJob j{};
+  j.base = base;
+  j.poly_stride = (size_t)(c->L + 1) * c->n;
+  j.npoly = npoly;
+  j.nlimb = c->L + 1;
+  j.limb_prime = c->lp_ks;
+  j.count = npoly * j.nlimb;
+  Prof pf(c, dir ? K_NTT_INV : K_NTT_FWD, st, ntt_work(c, j.count));
+  HIPCHK(run_ntt(c->log2n, j, c->tb, dir, st));
+  return NSHE_OK;
+}
+
+// Lift + forward NTT of the ciphertexts held in ext (limbs 0..L-1).
+static int prepare_operand(nshe_ctx* c, double* ext, int n_ct, hipStream_t st) {
+  Dims d{c->n, c->L, c->LB, n_ct};
+  {
+    Prof pf(c, K_LIFT, st, 2.0 * n_ct * c->n);
+    HIPCHK(run_lift(d, ext, c->tb, st));
+  }
+  return ntt_job_ext(c, ext, n_ct * 2, 0, st);
+}
+
+// ext (NTT domain, operands) -> dt limbs 0..L-1 of the 3 components:
+// [round(t d_k / Q)]_Q, coefficient domain.
+static int tensor_scale(nshe_ctx* c, const Ws& w, const double* ext_b, int n_ct, hipStream_t st) {
+  Dims d{c->n, c->L, c->LB, n_ct};
+  {
+    Prof pf(c, K_TENSOR, st, (double)n_ct * W_of(c) * c->n);
+    HIPCHK(run_tensor(d, w.ext, ext_b, w.dt, c->tb, st));
+  }
+  int rc = ntt_job_ext(c, w.dt, n_ct * 3, 1, st);
+  if (rc) return rc;
+  {
+    Prof pf(c, K_SCALE, st, 3.0 * n_ct * c->n);
+    HIPCHK(run_scale(d, w.dt, c->tb, st));
+  }
+  return NSHE_OK;
+}
+
+// Relinearize the components in dt (limbs 0..L-1) into ext limbs 0..L-1.
+static int relin(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st) {
+  Dims d{c->n, c->L, c->LB, n_ct};
+  NttJob j{};
+  j.base = w.dig;
+  j.poly_stride = (size_t)(c->L + 1) * c->n;
+  j.npoly = n_ct * c->L;
+  j.nlimb = c->L + 1;
+  j.limb_prime = c->lp_ks;
+  j.count = j.npoly * j.nlimb;
+  j.src = w.dt + (size_t)2 * W_of(c) * c->n;
+  j.src_ct_stride = (size_t)3 * W_of(c) * c->n;
+  j.digits = c->L;
+  {
+    Prof pf(c, K_NTT_DIGIT, st, ntt_work(c, j.count));
+    HIPCHK(run_ntt(c->log2n, j, c->tb, 2, st));
+  }
+  {
+    Prof pf(c, K_KS_MAC, st, (double)n_ct * c->L * 2 * (c->L + 1) * c->n);
+    HIPCHK(run_ks_mac(d, w.dig, c->evk, w.acc, c->tb, st));
+  }
+  int rc = ntt_job_ks(c, w.acc, n_ct * 2, 1, st);
+  if (rc) return rc;
+  {
+    Prof pf(c, K_MODDOWN, st, 2.0 * n_ct * c->n);
+    HIPCHK(run_moddown(d, w.acc, w.dt, w.ext, c->tb, st));
+  }
+  return NSHE_OK;
+}
+
+// One squaring level on the ciphertexts in ext.
+static int square_level(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st) {
+  int rc = prepare_operand(c, w.ext, n_ct, st);
+  if (rc) return rc;
+  rc = tensor_scale(c, w, nullptr, n_ct, st);
+  if (rc) return rc;
+  return relin(c, w, n_ct, st);
+}
+
+static int check_ctx(const nshe_ctx* c) {
+  if (!c) return fail(NSHE_EINVAL, "context is null");
+  return NSHE_OK;
+}
+
+static int check_key(const nshe_ctx* c) {
+  if (!c->has_key) return fail(NSHE_ENOKEY, "relinearization key not set");
+  return NSHE_OK;
+}
+
+static int set_device(const nshe_ctx* c) {
+  HIPCHK(hipSetDevice(c->device));
+  return NSHE_OK;
+}
+
+}  // namespace nshe
+
+// =================================================================== ABI
+
+extern "C" {
+
+const char* nshe_last_error(void) { return g_err.c_str(); }
+
+int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
+  g_err.clear();
+  if (!pr || !out) return fail(NSHE_EINVAL, "null argument");
+  *out = nullptr;
+  if (pr->log2_n < NSHE_MIN_LOG2N || pr->log2_n > NSHE_MAX_LOG2N)
+    return fail(NSHE_EINVAL, "log2_n out of range");
+  if (pr->L < 1 || pr->L > NSHE_MAX_L) return fail(NSHE_EINVAL, "L out of range");
+  if (!pr->q_host) return fail(NSHE_EINVAL, "q_host is null");
+  if (pr->t < 3 || (pr->t & 1) == 0 || pr->t >= (1u << 24))
+    return fail(NSHE_EINVAL, "t must be odd, 3 <= t < 2^24");
+  const int n = 1 << pr->log2_n;
+  const u64 lo = 1ull << 48, hi = 1ull << 49;
+  std::vector<u64> q(pr->q_host, pr->q_host + pr->L);
+  std::vector<u64> qp = q;
+  qp.push_back(pr->P);
+  for (size_t i = 0; i < qp.size(); ++i) {
+    const u64 x = qp[i];
+    if (x < lo || x >= hi) return fail(NSHE_EINVAL, "every prime must lie in [2^48, 2^49)");
+    if ((x - 1) % (2ull * n)) return fail(NSHE_EINVAL, "every prime must be 1 mod 2N");
+    if (!is_prime(x)) return fail(NSHE_EINVAL, "modulus is not prime");
+    if (x % pr->t == 0) return fail(NSHE_EINVAL, "t shares a factor with a prime");
+    for (size_t k = 0; k < i; ++k)
+      if (qp[k] == x) return fail(NSHE_EINVAL, "primes must be distinct");
+  }
+  // --- extension basis: L + 1 largest primes = 1 mod 2^16 below min(q, P)
+  const int L = pr->L, LB = L + 1;
+  u64 mn = *std::min_element(qp.begin(), qp.end());
+  std::vector<u64> b;
+  for (u64 k = (mn - 2) >> 16; (int)b.size() < LB && k > 0; --k) {
+    u64 c = (k << 16) + 1;
+    if (c >= mn || c < lo) continue;
+    if (is_prime(c)) b.push_back(c);
+  }
+  if ((int)b.size() < LB) return fail(NSHE_EINVAL, "no room for the extension basis");
+  double bits_q = 0, bits_b = 0;
+  for (u64 x : q) bits_q += std::log2((double)x);
+  for (u64 x : b) bits_b += std::log2((double)x);
+  if (bits_b < bits_q + std::log2((double)pr->t) + pr->log2_n + 6)
+    return fail(NSHE_EINVAL, "extension basis too small for exact products");
+
+  nshe_ctx* c = new (std::nothrow) nshe_ctx();
+  if (!c) return fail(NSHE_ENOMEM, "host allocation failed");
+  c->device = hip_device;
+  c->log2n = pr->log2_n;
+  c->n = n;
+  c->L = L;
+  c->LB = LB;
+  c->K = 2 * L + 2;
+  c->t = pr->t;
+  {
+    u64 e = pr->t - 1;
+    int k = 0;
+    while ((e & 1) == 0) {
+      e >>= 1;
+      ++k;
+    }
+    c->squarings = e == 1 ? k : -1;
+  }
+  c->primes = q;
+  c->primes.insert(c->primes.end(), b.begin(), b.end());
+  c->primes.push_back(pr->P);
+  c->rounds = ntt_rounds(c->log2n, &c->loge, &c->r0);
+  {
+    const int E = 1 << c->loge;
+    int len = 0;
+    for (int r = 0; r < c->rounds; ++r) {
+      const int ss = r == 0 ? 0 : c->r0 + (r - 1) * c->loge;
+      len += (1 << ss) * E;
+    }
+    c->tw_len = len;
+  }
+  const int K = c->K;
+  const std::vector<u64>& P_ = c->primes;
+  auto prime = [&](int i) { return P_[i]; };
+
+  // --- host tables
+  std::vector<double> h_p(K), h_pinv(K), h_ninv(K);
+  for (int i = 0; i < K; ++i) {
+    h_p[i] = (double)prime(i);
+    h_pinv[i] = 1.0 / (double)prime(i);
+    h_ninv[i] = bal(invmod((u64)n, prime(i)), prime(i));
+  }
+  std::vector<double> tw_f((size_t)K * c->tw_len, 0.0), tw_i((size_t)K * c->tw_len, 0.0);
+  {
+    const int E = 1 << c->loge;
+    std::vector<u64> pbr(n), pibr(n);
+    for (int k = 0; k < K; ++k) {
+      const u64 p = prime(k);
+      const u64 psi = powmod(primitive_root(p), (p - 1) / (2ull * n), p);
+      const u64 psi_inv = invmod(psi, p);
+      std::vector<u64> pw(n), pwi(n);
+      pw[0] = pwi[0] = 1;
+      for (int i = 1; i < n; ++i) {
+        pw[i] = mulmod(pw[i - 1], psi, p);
+        pwi[i] = mulmod(pwi[i - 1], psi_inv, p);
+      }
+      for (int i = 0; i < n; ++i) {
+        pbr[i] = pw[brv(i, c->log2n)];
+        pibr[i] = pwi[brv(i, c->log2n)];
+      }
+      int off = 0;
+      for (int r = 0; r < c->rounds; ++r) {
+        const int ss = r == 0 ? 0 : c->r0 + (r - 1) * c->loge;
+        const int R = r == 0 ? c->r0 : c->loge;
+        for (int u = 0; u < (1 << ss); ++u)
+          for (int kk = 0; kk < R; ++kk)
+            for (int j = 0; j < (1 << kk); ++j) {
+              const int idx = (1 << (ss + kk)) + (u << kk) + j;
+              const size_t o = (size_t)k * c->tw_len + off + (size_t)u * E + (1 << kk) + j;
+              tw_f[o] = bal(pbr[idx], p);
+              tw_i[o] = bal(pibr[idx], p);
+            }
+        off += (1 << ss) * E;
+      }
+    }
+  }
+  std::vector<u64> qv(q), bv(b);
+  std::vector<double> q_hat_inv(L), q_hat_b((size_t)LB * L), Q_b(LB), t_qhinv(L), t_q(L),
+      c1(LB), c2((size_t)LB * L), b_hat_inv(LB), b_hat_q((size_t)L * LB), B_q(L), P_inv_q(L),
+      delta_q(L), mrc_inv((size_t)L * L, 0.0), mrc_half(L);
+  u64 Qmodt = 1;
+  for (u64 x : qv) Qmodt = mulmod(Qmodt, x % c->t, c->t);
+  for (int i = 0; i < L; ++i) {
+    const u64 qi = qv[i];
+    const u64 qhi = invmod(prod_mod(qv, i, qi), qi);
+    q_hat_inv[i] = bal(qhi, qi);
+    t_qhinv[i] = bal(mulmod(c->t % qi, qhi, qi), qi);
+    t_q[i] = bal(c->t % qi, qi);
+    B_q[i] = bal(prod_mod(bv, -1, qi), qi);
+    P_inv_q[i] = bal(invmod(pr->P % qi, qi), qi);
+    // Delta = (Q - (Q mod t)) / t = -(Q mod t) * t^-1 (mod q_i)
+    delta_q[i] = bal((qi - mulmod(Qmodt, invmod(c->t % qi, qi), qi)) % qi, qi);
+    for (int k = 0; k < LB; ++k) b_hat_q[(size_t)i * LB + k] = bal(prod_mod(bv, k, qi), qi);
+    for (int j = 0; j < i; ++j) mrc_inv[(size_t)j * L + i] = bal(invmod(qv[j] % qi, qi), qi);
+  }
+  for (int k = 0; k < LB; ++k) {
+    const u64 bk = bv[k];
+    const u64 Qb = prod_mod(qv, -1, bk);
+    Q_b[k] = bal(Qb, bk);
+    const u64 bhi = invmod(prod_mod(bv, k, bk), bk);
+    b_hat_inv[k] = bal(bhi, bk);
+    c1[k] = bal(mulmod(mulmod(c->t % bk, invmod(Qb, bk), bk), bhi, bk), bk);
+    for (int i = 0; i < L; ++i) {
+      q_hat_b[(size_t)k * L + i] = bal(prod_mod(qv, i, bk), bk);
+      c2[(size_t)k * L + i] = bal(mulmod(invmod(qv[i] % bk, bk), bhi, bk), bk);
+    }
+  }
+  // mixed-radix digits of (Q-1)/2, whose residue mod q_i is (q_i - 1)/2
+  {
+    std::vector<u64> a(L);
+    for (int i = 0; i < L; ++i) {
+      const u64 qi = qv[i];
+      u64 tv = (qi - 1) / 2;
+      for (int j = 0; j < i; ++j) {
+        const u64 diff = (tv + qi - a[j] % qi) % qi;
+        tv = mulmod(diff, invmod(qv[j] % qi, qi), qi);
+      }
+      a[i] = tv;
+      mrc_half[i] = (double)tv;
+    }
+  }
+  // --- upload
+  std::vector<std::pair<const std::vector<double>*, const double**>> parts = {
+      {&h_p, &c->tb.p},           {&h_pinv, &c->tb.pinv},     {&h_pinv, &c->tb.recip},
+      {&h_ninv, &c->tb.ninv},     {&tw_f, &c->tb.tw_fwd},     {&tw_i, &c->tb.tw_inv},
+      {&q_hat_inv, &c->tb.q_hat_inv}, {&q_hat_b, &c->tb.q_hat_b}, {&Q_b, &c->tb.Q_b},
+      {&t_qhinv, &c->tb.t_qhinv}, {&t_q, &c->tb.t_q},         {&c1, &c->tb.c1},
+      {&c2, &c->tb.c2},           {&b_hat_inv, &c->tb.b_hat_inv}, {&b_hat_q, &c->tb.b_hat_q},
+      {&B_q, &c->tb.B_q},         {&P_inv_q, &c->tb.P_inv_q}, {&delta_q, &c->tb.delta_q},
+      {&mrc_inv, &c->tb.mrc_inv}, {&mrc_half, &c->tb.mrc_half}};
+  size_t total = 0;
+  std::vector<size_t> offs;
+  for (auto& pp : parts) {
+    offs.push_back(total);
+    total += (pp.first->size() * sizeof(double) + 255) & ~size_t(255);
+  }
+  const size_t off_counters = total;
+  total += 256;
+  const size_t off_lp = total;
+  total += ((size_t)(W_of(c) + L + 1) * sizeof(int) + 255) & ~size_t(255);
+  int rc = NSHE_OK;
+  hipError_t e = hipSetDevice(hip_device);
+  if (e == hipSuccess) e = hipMalloc(&c->dev_tables, total);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(NSHE_EDEVICE, std::string("table allocation: ") + hipGetErrorString(e));
+  }
+  char* base = static_cast<char*>(c->dev_tables);
+  for (size_t i = 0; i < parts.size() && e == hipSuccess; ++i) {
+    *parts[i].second = reinterpret_cast<const double*>(base + offs[i]);
+    e = hipMemcpy(base + offs[i], parts[i].first->data(), parts[i].first->size() * sizeof(double),
+                  hipMemcpyHostToDevice);
+  }
+  c->tb.tw_len = c->tw_len;
+  c->tb.margin = reinterpret_cast<unsigned long long*>(base + off_counters);
+  c->tb.fault = c->tb.margin + 1;
+  if (e == hipSuccess) e = hipMemset(base + off_counters, 0, 256);
+  std::vector<int> lp;
+  for (int i = 0; i < W_of(c); ++i) lp.push_back(i);
+  for (int i = 0; i < L; ++i) lp.push_back(i);
+  lp.push_back(2 * L + 1);
+  c->lp_ext = reinterpret_cast<int*>(base + off_lp);
+  c->lp_ks = c->lp_ext + W_of(c);
+  if (e == hipSuccess)
+    e = hipMemcpy(c->lp_ext, lp.data(), lp.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(c->dev_tables);
+    delete c;
+    return fail(NSHE_EDEVICE, std::string("table upload: ") + hipGetErrorString(e));
+  }
+  *out = c;
+  return rc;
+}
+
+int nshe_ctx_destroy(nshe_ctx* c) {
+  if (!c) return NSHE_OK;
+  (void)hipSetDevice(c->device);
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second.exec);
+  for (auto& r : c->recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto& e : c->pool) (void)hipEventDestroy(e);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  if (c->evk) (void)hipFree(c->evk);
+  if (c->dev_tables) (void)hipFree(c->dev_tables);
+  delete c;
+  return NSHE_OK;
+}
+
+int nshe_ctx_info(const nshe_ctx* c, nshe_info* out) {
+  if (check_ctx(c) || !out) return fail(NSHE_EINVAL, "null argument");
+  std::memset(out, 0, sizeof(*out));
+  out->n = (uint32_t)c->n;
+  out->L = c->L;
+  out->L_ext = c->LB;
+  out->squarings = c->squarings;
+  for (int k = 0; k < c->LB && k < 32; ++k) out->ext_primes[k] = c->primes[c->L + k];
+  out->ct_words = (size_t)2 * c->L * c->n;
+  out->relin_key_words = (size_t)c->L * 2 * (c->L + 1) * c->n;
+  return NSHE_OK;
+}
+
+size_t nshe_workspace_bytes(const nshe_ctx* c, int n_ct) {
+  if (!c || n_ct <= 0) return 0;
+  return ws_doubles(c, n_ct) * sizeof(double);
+}
+
+int nshe_set_relin_key(nshe_ctx* c, const int64_t* evk_dev, void* stream) {
+  g_err.clear();
+  if (check_ctx(c)) return NSHE_EINVAL;
+  if (!evk_dev) return fail(NSHE_EINVAL, "evk is null");
+  if (set_device(c)) return NSHE_EDEVICE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t rows = (size_t)c->L * 2 * (c->L + 1);
+  if (!c->evk) HIPCHK(hipMalloc(&c->evk, rows * c->n * sizeof(double)));
+  HIPCHK(run_i64_to_dbl_limbs(rows, c->n, evk_dev, c->evk, c->lp_ks, c->L + 1, c->tb, st));
+  int rc = ntt_job_ks(c, c->evk, c->L * 2, 0, st);
+  if (rc) return rc;
+  c->has_key = true;
+  return NSHE_OK;
+}
+
+int nshe_sub(nshe_ctx* c, const int64_t* x, const int64_t* y, int64_t* out, int n_ct,
+             void* stream) {
+  g_err.clear();
+  if (check_ctx(c)) return NSHE_EINVAL;
+  if (n_ct < 0) return fail(NSHE_ESHAPE, "n_ct < 0");
+  if (n_ct == 0) return NSHE_OK;
+  if (!x || !y || !out) return fail(NSHE_EINVAL, "null buffer");
+  if (set_device(c)) return NSHE_EDEVICE;
+  Dims d{c->n, c->L, c->LB, n_ct};
+  HIPCHK(run_sub_i64(d, x, y, out, c->tb, static_cast<hipStream_t>(stream)));
+  return NSHE_OK;
+}
+
+static int common_checks(nshe_ctx* c, int n_ct, void* ws, size_t ws_bytes, bool need_key) {
+  g_err.clear();
+  if (check_ctx(c)) return NSHE_EINVAL;
+  if (n_ct < 0) return fail(NSHE_ESHAPE, "n_ct < 0");
+  if (n_ct > 0) {
+    int rc = check_ws(c, ws, ws_bytes, n_ct);
+    if (rc) return rc;
+  }
+  if (need_key && check_key(c)) return NSHE_ENOKEY;
+  if (set_device(c)) return NSHE_EDEVICE;
+  return NSHE_OK;
+}
+
+int nshe_square_relin(nshe_ctx* c, const int64_t* in, int64_t* out, int n_ct, void* ws,
+                      size_t ws_bytes, void* stream) {
+  int rc = common_checks(c, n_ct, ws, ws_bytes, true);
+  if (rc) return rc;
+  if (n_ct == 0) return NSHE_OK;
+  if (!in || !out) return fail(NSHE_EINVAL, "null buffer");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Ws w = carve(c, ws, n_ct);
+  Dims d{c->n, c->L, c->LB, n_ct};
+  const size_t W = W_of(c), N = c->n;
+  HIPCHK(run_i64_to_polys(d, in, 2, w.ext, 2 * W * N, W * N, c->tb, st));
+  rc = square_level(c, w, n_ct, st);
+  if (rc) return rc;
+  HIPCHK(run_polys_to_i64(d, w.ext, 2, 2 * W * N, W * N, out, 0, c->tb, st));
+  return NSHE_OK;
+}
+
+static int load_two(nshe_ctx* c, const Ws& w, const int64_t* a, const int64_t* b, int n_ct,
+                    hipStream_t st) {
+  Dims d{c->n, c->L, c->LB, n_ct};
+  const size_t W = W_of(c), N = c->n;
+  HIPCHK(run_i64_to_polys(d, a, 2, w.ext, 2 * W * N, W * N, c->tb, st));
+  HIPCHK(run_i64_to_polys(d, b, 2, w.dig, 2 * W * N, W * N, c->tb, st));
+  int rc = prepare_operand(c, w.ext, n_ct, st);
+  if (rc) return rc;
+  return prepare_operand(c, w.dig, n_ct, st);
+}
+
+int nshe_mul_relin(nshe_ctx* c, const int64_t* a, const int64_t* b, int64_t* out, int n_ct,
+                   void* ws, size_t ws_bytes, void* stream) {
+  int rc = common_checks(c, n_ct, ws, ws_bytes, true);
+  if (rc) return rc;
+  if (n_ct == 0) return NSHE_OK;
+  if (!a || !b || !out) return fail(NSHE_EINVAL, "null buffer");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Ws w = carve(c, ws, n_ct);
+  Dims d{c->n, c->L, c->LB, n_ct};
+  const size_t W = W_of(c), N = c->n;
+  rc = load_two(c, w, a, b, n_ct, st);
+  if (rc) return rc;
+  rc = tensor_scale(c, w, w.dig, n_ct, st);
+  if (rc) return rc;
+  rc = relin(c, w, n_ct, st);
+  if (rc) return rc;
+  HIPCHK(run_polys_to_i64(d, w.ext, 2, 2 * W * N, W * N, out, 0, c->tb, st));
+  return NSHE_OK;
+}
+
+int nshe_multiply(nshe_ctx* c, const int64_t* a, const int64_t* b, int64_t* out3, int n_ct,
+                  void* ws, size_t ws_bytes, void* stream) {
+  int rc = common_checks(c, n_ct, ws, ws_bytes, false);
+  if (rc) return rc;
+  if (n_ct == 0) return NSHE_OK;
+  if (!a || !b || !out3) return fail(NSHE_EINVAL, "null buffer");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Ws w = carve(c, ws, n_ct);
+  Dims d{c->n, c->L, c->LB, n_ct};
+  const size_t W = W_of(c), N = c->n;
+  rc = load_two(c, w, a, b, n_ct, st);
+  if (rc) return rc;
+  rc = tensor_scale(c, w, w.dig, n_ct, st);
+  if (rc) return rc;
+  HIPCHK(run_polys_to_i64(d, w.dt, 3, 3 * W * N, W * N, out3, 0, c->tb, st));
+  return NSHE_OK;
+}
+
+int nshe_relinearize(nshe_ctx* c, const int64_t* in3, int64_t* out, int n_ct, void* ws,
+                     size_t ws_bytes, void* stream) {
+  int rc = common_checks(c, n_ct, ws, ws_bytes, true);
+  if (rc) return rc;
+  if (n_ct == 0) return NSHE_OK;
+  if (!in3 || !out) return fail(NSHE_EINVAL, "null buffer");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Ws w = carve(c, ws, n_ct);
+  Dims d{c->n, c->L, c->LB, n_ct};
+  const size_t W = W_of(c), N = c->n;
+  HIPCHK(run_i64_to_polys(d, in3, 3, w.dt, 3 * W * N, W * N, c->tb, st));
+  rc = relin(c, w, n_ct, st);
+  if (rc) return rc;
+  HIPCHK(run_polys_to_i64(d, w.ext, 2, 2 * W * N, W * N, out, 0, c->tb, st));
+  return NSHE_OK;
+}
+
+// The EQ chain on ciphertexts already differenced into w.ext.
+static int eq_levels(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st) {
+  for (int k = 0; k < c->squarings; ++k) {
+    int rc = square_level(c, w, n_ct, st);
+    if (rc) return rc;
+  }
+  return NSHE_OK;
+}
+
+int nshe_eq_mask(nshe_ctx* c, const int64_t* x, const int64_t* y, int64_t* out, int n_ct,
+                 int y_broadcast, void* ws, size_t ws_bytes, void* stream) {
+  int rc = common_checks(c, n_ct, ws, ws_bytes, true);
+  if (rc) return rc;
+  if (c->squarings < 0) return fail(NSHE_EDEPTH, "t - 1 is not a power of two");
+  if (n_ct == 0) return NSHE_OK;
+  if (!x || !y || !out) return fail(NSHE_EINVAL, "null buffer");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Ws w = carve(c, ws, n_ct);
+  Dims d{c->n, c->L, c->LB, n_ct};
+  const size_t W = W_of(c), N = c->n;
+  {
+    Prof pf(c, K_SUB, st, 2.0 * n_ct * c->L * c->n);
+    HIPCHK(run_sub_to_ext(d, x, y, y_broadcast ? 1 : 0, w.ext, c->tb, st));
+  }
+  rc = eq_levels(c, w, n_ct, st);
+  if (rc) return rc;
+  {
+    Prof pf(c, K_CONVERT, st, 2.0 * n_ct * c->L * c->n);
+    HIPCHK(run_polys_to_i64(d, w.ext, 2, 2 * W * N, W * N, out, 1, c->tb, st));
+  }
+  return NSHE_OK;
+}
+
+// Enqueue one wave of the batched chain: segments (item, first ct, count).
+struct Seg {
+  const nshe_item* it;
+  int first, count;
+};
+
+static int enqueue_wave(nshe_ctx* c, const std::vector<Seg>& segs, int wave_ct, const Ws& w,
+                        hipStream_t st) {
+  const size_t W = W_of(c), N = c->n, ctw = (size_t)2 * c->L * N;
+  int pos = 0;
+  for (const Seg& s : segs) {
+    Dims d{c->n, c->L, c->LB, s.count};
+    const int64_t* y = s.it->y_broadcast ? s.it->y_dev : s.it->y_dev + (size_t)s.first * ctw;
+    HIPCHK(run_sub_to_ext(d, s.it->x_dev + (size_t)s.first * ctw, y, s.it->y_broadcast ? 1 : 0,
+                          w.ext + (size_t)pos * 2 * W * N, c->tb, st));
+    pos += s.count;
+  }
+  int rc = eq_levels(c, w, wave_ct, st);
+  if (rc) return rc;
+  pos = 0;
+  for (const Seg& s : segs) {
+    Dims d{c->n, c->L, c->LB, s.count};
+    HIPCHK(run_polys_to_i64(d, w.ext + (size_t)pos * 2 * W * N, 2, 2 * W * N, W * N,
+                            s.it->out_dev + (size_t)s.first * ctw, 1, c->tb, st));
+    pos += s.count;
+  }
+  return NSHE_OK;
+}
+
+int nshe_eq_mask_batched(nshe_ctx* c, const nshe_item* items, int n_items, int wave_ct,
+                         int use_graph, void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  if (check_ctx(c)) return NSHE_EINVAL;
+  if (n_items < 0 || (n_items > 0 && !items)) return fail(NSHE_EINVAL, "bad item list");
+  if (c->squarings < 0) return fail(NSHE_EDEPTH, "t - 1 is not a power of two");
+  if (check_key(c)) return NSHE_ENOKEY;
+  long long total = 0;
+  for (int i = 0; i < n_items; ++i) {
+    if (items[i].n_ct < 0) return fail(NSHE_ESHAPE, "item with n_ct < 0");
+    if (items[i].n_ct > 0 && (!items[i].x_dev || !items[i].y_dev || !items[i].out_dev))
+      return fail(NSHE_EINVAL, "item with a null buffer");
+    total += items[i].n_ct;
+  }
+  if (total == 0) return NSHE_OK;
+  if (!ws) return fail(NSHE_EINVAL, "workspace pointer is null");
+  const size_t per_ct = ws_doubles(c, 1) * sizeof(double);
+  const int fit = (int)std::min<size_t>(ws_bytes / per_ct, 1 << 20);
+  if (wave_ct <= 0) wave_ct = fit;
+  if (wave_ct <= 0 || wave_ct > fit) return fail(NSHE_ENOMEM, "workspace smaller than one wave");
+  if (wave_ct > total) wave_ct = (int)total;
+  if (check_ws(c, ws, ws_bytes, wave_ct)) return NSHE_ENOMEM;
+  if (set_device(c)) return NSHE_EDEVICE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // split items into waves of wave_ct ciphertexts
+  std::vector<std::vector<Seg>> waves(1);
+  int fill = 0;
+  for (int i = 0; i < n_items; ++i) {
+    int done = 0;
+    while (done < items[i].n_ct) {
+      if (fill == wave_ct) {
+        waves.emplace_back();
+        fill = 0;
+      }
+      const int take = std::min(items[i].n_ct - done, wave_ct - fill);
+      waves.back().push_back(Seg{&items[i], done, take});
+      done += take;
+      fill += take;
+    }
+  }
+  for (const auto& wv : waves) {
+    int cnt = 0;
+    for (const Seg& s : wv) cnt += s.count;
+    Ws w = carve(c, ws, cnt);
+    if (!use_graph) {
+      int rc = enqueue_wave(c, wv, cnt, w, st);
+      if (rc) return rc;
+      continue;
+    }
+    std::vector<uintptr_t> key = {reinterpret_cast<uintptr_t>(ws), (uintptr_t)cnt};
+    for (const Seg& s : wv) {
+      key.push_back(reinterpret_cast<uintptr_t>(s.it->x_dev));
+      key.push_back(reinterpret_cast<uintptr_t>(s.it->y_dev));
+      key.push_back(reinterpret_cast<uintptr_t>(s.it->out_dev));
+      key.push_back(((uintptr_t)s.first << 33) | ((uintptr_t)s.count << 1) | (s.it->y_broadcast ? 1 : 0));
+    }
+    const bool prof_saved = c->prof;
+    c->prof = false;  // no event records inside a captured graph
+    struct Restore {
+      nshe_ctx* c;
+      bool v;
+      ~Restore() { c->prof = v; }
+    } restore{c, prof_saved};
+    auto found = c->graphs.find(key);
+    if (found == c->graphs.end()) {
+      // Capture on a context-owned stream (nothing executes during capture);
+      // the instantiated graph is then launched on the caller's stream.
+      if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+      hipGraph_t g = nullptr;
+      HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+      int rc = enqueue_wave(c, wv, cnt, w, c->cap_stream);
+      hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+      if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+      }
+      if (e != hipSuccess) return fail(NSHE_EDEVICE, std::string("capture: ") + hipGetErrorString(e));
+      hipGraphExec_t ex = nullptr;
+      e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) return fail(NSHE_EDEVICE, std::string("instantiate: ") + hipGetErrorString(e));
+      if (c->graphs.size() > 64) {
+        for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second.exec);
+        c->graphs.clear();
+      }
+      found = c->graphs.emplace(key, nshe_ctx::GraphEntry{ex}).first;
+    }
+    HIPCHK(hipGraphLaunch(found->second.exec, st));
+  }
+  return NSHE_OK;
+}
+
+int nshe_ntt(nshe_ctx* c, const int64_t* in, int64_t* out, int n_poly, int inverse, void* ws,
+             size_t ws_bytes, void* stream) {
+  g_err.clear();
+  if (check_ctx(c)) return NSHE_EINVAL;
+  if (!in || !out || !ws) return fail(NSHE_EINVAL, "null buffer");
+  if (n_poly < 0) return fail(NSHE_ESHAPE, "n_poly < 0");
+  if (n_poly == 0) return NSHE_OK;
+  const size_t need = (size_t)n_poly * c->L * c->n * sizeof(double);
+  if (ws_bytes < need) return fail(NSHE_ENOMEM, "workspace too small");
+  if (inverse) return fail(NSHE_EINVAL, "inverse debug transform not provided");
+  if (set_device(c)) return NSHE_EDEVICE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  double* buf = static_cast<double*>(ws);
+  HIPCHK(run_i64_to_dbl_limbs((size_t)n_poly * c->L, c->n, in, buf, c->lp_ext, c->L, c->tb, st));
+  NttJob j{};
+  j.base = buf;
+  j.poly_stride = (size_t)c->L * c->n;
+  j.npoly = n_poly;
+  j.nlimb = c->L;
+  j.limb_prime = c->lp_ext;
+  j.count = n_poly * c->L;
+  HIPCHK(run_ntt(c->log2n, j, c->tb, 0, st));
+  HIPCHK(run_ntt_order(c->log2n, (size_t)n_poly * c->L, buf, out, c->lp_ext, c->L, 1, c->tb, st));
+  return NSHE_OK;
+}
+
+int nshe_profile(nshe_ctx* c, int enable) {
+  g_err.clear();
+  if (check_ctx(c)) return NSHE_EINVAL;
+  for (auto& r : c->recs) {
+    c->pool.push_back(r.a);
+    c->pool.push_back(r.b);
+  }
+  c->recs.clear();
+  c->prof = enable != 0;
+  return NSHE_OK;
+}
+
+int nshe_profile_read(nshe_ctx* c, nshe_kernel_stat* out, int max_stats, int* n_stats) {
+  g_err.clear();
+  if (check_ctx(c) || !out || !n_stats) return fail(NSHE_EINVAL, "null argument");
+  if (set_device(c)) return NSHE_EDEVICE;
+  nshe_kernel_stat acc[K_COUNT];
+  std::memset(acc, 0, sizeof(acc));
+  for (auto& r : c->recs) {
+    HIPCHK(hipEventSynchronize(r.b));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
+    acc[r.kind].launches += 1;
+    acc[r.kind].total_ms += ms;
+    acc[r.kind].work += r.work;
+    c->pool.push_back(r.a);
+    c->pool.push_back(r.b);
+  }
+  c->recs.clear();
+  int k = 0;
+  for (int i = 0; i < K_COUNT && k < max_stats; ++i) {
+    if (!acc[i].launches) continue;
+    out[k] = acc[i];
+    std::strncpy(out[k].name, kKindName[i], sizeof(out[k].name) - 1);
+    ++k;
+  }
+  *n_stats = k;
+  return NSHE_OK;
+}
+
+int nshe_margin_events(nshe_ctx* c, uint64_t* count, void* stream) {
+  g_err.clear();
+  if (check_ctx(c) || !count) return fail(NSHE_EINVAL, "null argument");
+  if (set_device(c)) return NSHE_EDEVICE;
+  unsigned long long h[2] = {0, 0};
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIPCHK(hipMemcpyAsync(h, c->tb.margin, sizeof(h), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (h[1]) return fail(NSHE_EDEVICE, "extension-basis lift left its proven range");
+  *count = h[0];
+  return NSHE_OK;
+}
+
+int nshe_reset_margin_events(nshe_ctx* c, void* stream) {
+  g_err.clear();
+  if (check_ctx(c)) return NSHE_EINVAL;
+  if (set_device(c)) return NSHE_EDEVICE;
+  HIPCHK(hipMemsetAsync(c->tb.margin, 0, 2 * sizeof(unsigned long long),
+                        static_cast<hipStream_t>(stream)));
+  return NSHE_OK;
+}
+
+}  // extern "C"

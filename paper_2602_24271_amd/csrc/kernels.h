@@ -1,0 +1,100 @@
+// Shared declarations of the device kernels and their launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+#include "modarith.h"
+
+namespace nshe {
+
+constexpr int MAX_L = 24;            // data primes
+constexpr int MAX_PRIMES = 2 * MAX_L + 2;
+
+// Device constant tables of a context (all pointers are device memory).
+// Prime index convention: data primes q_0..q_{L-1} are 0..L-1, extension
+// primes b_0..b_{L} are L..2L, the special prime P is 2L+1.
+struct Tables {
+  const double* p;           // [K]
+  const double* pinv;        // [K] fl(1/p)
+  const double* recip;       // [K] fl(1/p) (kept separate: the CRT estimate)
+  const double* ninv;        // [K] balanced N^-1
+  const double* tw_fwd;      // [K][tw_len]
+  const double* tw_inv;      // [K][tw_len]
+  int tw_len;
+  // centred lift Q -> B
+  const double* q_hat_inv;   // [L]      [(Q/q_i)^-1]_{q_i}
+  const double* q_hat_b;     // [LB][L]  [Q/q_i]_{b_k}
+  const double* Q_b;         // [LB]     [Q]_{b_k}
+  // scale and round, then B -> Q
+  const double* t_qhinv;     // [L]      [t (Q/q_i)^-1]_{q_i}
+  const double* t_q;         // [L]      [t]_{q_i}
+  const double* c1;          // [LB]     [t Q^-1 (B/b_k)^-1]_{b_k}
+  const double* c2;          // [LB][L]  [q_i^-1 (B/b_k)^-1]_{b_k}
+  const double* b_hat_inv;   // [LB]     [(B/b_k)^-1]_{b_k}
+  const double* b_hat_q;     // [L][LB]  [B/b_k]_{q_i}
+  const double* B_q;         // [L]      [B]_{q_i}
+  // key switching
+  const double* P_inv_q;     // [L]      [P^-1]_{q_i}
+  const double* delta_q;     // [L]      [floor(Q/t)]_{q_i}
+  // exact fallback of the Q lift: mixed-radix digits
+  const double* mrc_inv;     // [L][L]   [q_j^-1]_{q_i}, canonical, row j
+  const double* mrc_half;    // [L]      mixed-radix digits of (Q-1)/2
+  unsigned long long* margin;  // event counter (fallbacks taken)
+  unsigned long long* fault;   // B->Q lift outside its proven range (never)
+};
+
+enum { NTT_INPLACE = 0, NTT_DIGIT = 1 };
+
+struct NttJob {
+  double* base;              // first limb of poly 0
+  size_t poly_stride;        // doubles between consecutive polys
+  int npoly;                 // polys in the launch
+  int nlimb;                 // limbs per poly transformed
+  const int* limb_prime;     // [nlimb] prime index of each limb
+  int count;                 // npoly * nlimb
+  // NTT_DIGIT source
+  const double* src;         // digit source (third component, data limbs)
+  size_t src_ct_stride;      // doubles between ciphertexts in src
+  int digits;                // L (digits per ciphertext)
+};
+
+hipError_t run_ntt(int log2n, const NttJob& job, const Tables& tb, int dir, hipStream_t st);
+int ntt_rounds(int log2n, int* loge, int* r0);
+
+// Per-coefficient and elementwise kernels (rns.hip).
+struct Dims {
+  int n;        // N
+  int L;        // data primes
+  int LB;       // extension primes (= L + 1)
+  int n_ct;     // ciphertexts in the call
+};
+
+hipError_t run_lift(const Dims& d, double* ext, const Tables& tb, hipStream_t st);
+hipError_t run_lift_b(const Dims& d, double* ext_b, const Tables& tb, hipStream_t st);
+hipError_t run_tensor(const Dims& d, const double* ext_a, const double* ext_b, double* dt,
+                      const Tables& tb, hipStream_t st);
+hipError_t run_scale(const Dims& d, double* dt, const Tables& tb, hipStream_t st);
+hipError_t run_ks_mac(const Dims& d, const double* dig, const double* evk, double* acc,
+                      const Tables& tb, hipStream_t st);
+hipError_t run_moddown(const Dims& d, const double* acc, const double* dt, double* ext,
+                       const Tables& tb, hipStream_t st);
+// conversions at the boundary
+hipError_t run_sub_to_ext(const Dims& d, const int64_t* x, const int64_t* y, int y_bcast,
+                          double* ext, const Tables& tb, hipStream_t st);
+hipError_t run_sub_i64(const Dims& d, const int64_t* x, const int64_t* y, int64_t* out,
+                       const Tables& tb, hipStream_t st);
+hipError_t run_i64_to_polys(const Dims& d, const int64_t* in, int npoly_in, double* out,
+                            size_t out_ct_stride, size_t out_poly_stride, const Tables& tb,
+                            hipStream_t st);
+hipError_t run_polys_to_i64(const Dims& d, const double* in, int npoly, size_t in_ct_stride,
+                            size_t in_poly_stride, int64_t* out, int negate_delta,
+                            const Tables& tb, hipStream_t st);
+hipError_t run_i64_to_dbl_limbs(size_t rows, int n, const int64_t* in, double* out,
+                                const int* row_prime, int nprime_rows, const Tables& tb,
+                                hipStream_t st);
+hipError_t run_ntt_order(int log2n, size_t rows, const double* in, int64_t* out,
+                         const int* row_prime, int nprime_rows, int to_natural,
+                         const Tables& tb, hipStream_t st);
+
+}  // namespace nshe

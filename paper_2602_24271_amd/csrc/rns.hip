@@ -1,0 +1,474 @@
+// Per-coefficient residue-number-system kernels: exact centred lifts between
+// the data basis Q = {q_i} and the extension basis B = {b_k}, the BFV
+// scale-and-round, key-switch accumulation and mod-down, and the
+// conversions at the library boundary.
+//
+// Exact centred lift (used by the product's operand lift and by the
+// scale-and-round): for residues x_i of X in [0, Q), let
+// y_i = [x_i (Q/q_i)^-1]_{q_i} (balanced) and S = sum_i y_i / q_i.  Then
+// sum_i y_i (Q/q_i) = X + kQ with k = S - X/Q an integer, so the centred
+// representative of X is sum_i y_i (Q/q_i) - rint(S) Q.  S is evaluated in
+// double precision with absolute error below 2^-45 (L <= 24 terms of
+// magnitude < 1/2); when S lies within 2^-40 of a half-integer the rounding
+// decision is taken exactly instead: floor(S) = k, and X > (Q-1)/2 is
+// decided by comparing mixed-radix digits of X with those of (Q-1)/2
+// (Garner's algorithm).  Each such event is counted.
+//
+// Scale and round (BFV multiply): for d in Q u B (|d| < QB/2), the exact
+// r = [t d]_Q (centred) gives y = (t d - r) / Q = round(t d / Q) exactly.
+// In base B: [y]_{b_k} = [t Q^-1 d_k - sum_i y_i q_i^-1 + v]_{b_k} where
+// y_i, v are the lift quantities of r; then y is lifted from B to Q (|y| <
+// t N Q / 2 < B / 32, so that lift's estimate is never near a half-integer;
+// a violation would be counted in `fault`).
+#include "kernels.h"
+
+namespace nshe {
+
+constexpr double LIFT_EPS = 0x1p-40;
+
+// Garner mixed-radix digits of X (canonical residues r, basis q_0..q_{L-1})
+// compared with those of (Q-1)/2: returns X > (Q-1)/2.
+template <int L>
+__device__ __noinline__ bool mrc_greater_than_half(const double* r, const Tables& tb) {
+  double a[L];
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    const double p = tb.p[i], pinv = tb.pinv[i];
+    double t = r[i];
+    for (int j = 0; j < i; ++j) {
+      t = mul_bal(t - a[j], tb.mrc_inv[j * L + i], p, pinv);
+      t = to_canonical(t, p);
+    }
+    a[i] = t;
+  }
+  for (int i = L - 1; i >= 0; --i) {
+    const double h = tb.mrc_half[i];
+    if (a[i] != h) return a[i] > h;
+  }
+  return false;
+}
+
+// ------------------------------------------------------------------ lift ---
+
+// ext: [n_poly][L+LB][N]; limbs 0..L-1 (balanced, coefficient domain) are
+// lifted to limbs L..L+LB-1 (the extension basis) in place.
+template <int L>
+__global__ void __launch_bounds__(256) k_lift(int n, size_t n_poly, double* ext, Tables tb) {
+  constexpr int LB = L + 1;
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= n_poly * (size_t)n) return;
+  const size_t pc = gid / n;
+  const int c = (int)(gid - pc * n);
+  double* base = ext + pc * (size_t)(L + LB) * n + c;
+  double y[L];
+  double S = 0.0;
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    y[i] = mul_bal(base[(size_t)i * n], tb.q_hat_inv[i], tb.p[i], tb.pinv[i]);
+    S += y[i] * tb.recip[i];
+  }
+  double v = __builtin_rint(S);
+  if (__builtin_fabs(S - v) > 0.5 - LIFT_EPS) {
+    double r[L];
+#pragma unroll
+    for (int i = 0; i < L; ++i) r[i] = to_canonical(base[(size_t)i * n], tb.p[i]);
+    v = __builtin_floor(S) + (mrc_greater_than_half<L>(r, tb) ? 1.0 : 0.0);
+    atomicAdd(tb.margin, 1ull);
+  }
+#pragma unroll
+  for (int k = 0; k < LB; ++k) {
+    const double b = tb.p[L + k], binv = tb.pinv[L + k];
+    double acc = -v * tb.Q_b[k];
+#pragma unroll
+    for (int i = 0; i < L; ++i) acc += mul_lazy(y[i], tb.q_hat_b[k * L + i], b, binv);
+    base[(size_t)(L + k) * n] = reduce_bal(acc, b, binv);
+  }
+}
+
+// ----------------------------------------------------------------- scale ---
+
+// dt: [n_poly][L+LB][N] coefficient domain (balanced).  Writes
+// [round(t d / Q)]_Q into limbs 0..L-1 of the same poly.
+template <int L>
+__global__ void __launch_bounds__(256) k_scale(int n, size_t n_poly, double* dt, Tables tb) {
+  constexpr int LB = L + 1;
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= n_poly * (size_t)n) return;
+  const size_t pc = gid / n;
+  const int c = (int)(gid - pc * n);
+  double* base = dt + pc * (size_t)(L + LB) * n + c;
+  double y[L];
+  double S = 0.0;
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    y[i] = mul_bal(base[(size_t)i * n], tb.t_qhinv[i], tb.p[i], tb.pinv[i]);
+    S += y[i] * tb.recip[i];
+  }
+  double v = __builtin_rint(S);
+  if (__builtin_fabs(S - v) > 0.5 - LIFT_EPS) {
+    double r[L];
+#pragma unroll
+    for (int i = 0; i < L; ++i)
+      r[i] = to_canonical(mul_bal(base[(size_t)i * n], tb.t_q[i], tb.p[i], tb.pinv[i]), tb.p[i]);
+    v = __builtin_floor(S) + (mrc_greater_than_half<L>(r, tb) ? 1.0 : 0.0);
+    atomicAdd(tb.margin, 1ull);
+  }
+  double w[LB];
+  double S2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < LB; ++k) {
+    const double b = tb.p[L + k], binv = tb.pinv[L + k];
+    double acc = mul_lazy(base[(size_t)(L + k) * n], tb.c1[k], b, binv) + v * tb.b_hat_inv[k];
+#pragma unroll
+    for (int i = 0; i < L; ++i) acc -= mul_lazy(y[i], tb.c2[k * L + i], b, binv);
+    w[k] = reduce_bal(acc, b, binv);
+    S2 += w[k] * tb.recip[L + k];
+  }
+  const double v2 = __builtin_rint(S2);
+  if (__builtin_fabs(S2 - v2) > 0.25) atomicAdd(tb.fault, 1ull);
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    const double q = tb.p[i], qinv = tb.pinv[i];
+    double acc = -v2 * tb.B_q[i];
+#pragma unroll
+    for (int k = 0; k < LB; ++k) acc += mul_lazy(w[k], tb.b_hat_q[i * LB + k], q, qinv);
+    base[(size_t)i * n] = reduce_bal(acc, q, qinv);
+  }
+}
+
+// ---------------------------------------------------------------- tensor ---
+
+// NTT domain, all L+LB limbs: d0 = a0 b0, d1 = a0 b1 + a1 b0, d2 = a1 b1.
+// ext_b == ext_a (or nullptr) squares.  Prime index of limb l is l.
+template <int L>
+__global__ void __launch_bounds__(256) k_tensor(int n, int n_ct, const double* ext_a,
+                                                const double* ext_b, double* dt, Tables tb) {
+  constexpr int W = 2 * L + 1;
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (size_t)n_ct * W * n) return;
+  const size_t row = gid / n;               // ct * W + limb
+  const int c = (int)(gid - row * n);
+  const int ct = (int)(row / W);
+  const int limb = (int)(row - (size_t)ct * W);
+  const double p = tb.p[limb], pinv = tb.pinv[limb];
+  const size_t ia0 = ((size_t)(ct * 2 + 0) * W + limb) * n + c;
+  const size_t ia1 = ((size_t)(ct * 2 + 1) * W + limb) * n + c;
+  const double a0 = ext_a[ia0], a1 = ext_a[ia1];
+  double d0, d1, d2;
+  if (ext_b == nullptr) {
+    d0 = mul_bal(a0, a0, p, pinv);
+    d1 = mul_bal(a0 + a0, a1, p, pinv);
+    d2 = mul_bal(a1, a1, p, pinv);
+  } else {
+    const double b0 = ext_b[ia0], b1 = ext_b[ia1];
+    d0 = mul_bal(a0, b0, p, pinv);
+    d1 = reduce_bal(mul_lazy(a0, b1, p, pinv) + mul_lazy(a1, b0, p, pinv), p, pinv);
+    d2 = mul_bal(a1, b1, p, pinv);
+  }
+  const size_t o = ((size_t)(ct * 3) * W + limb) * n + c;
+  const size_t ps = (size_t)W * n;
+  dt[o] = d0;
+  dt[o + ps] = d1;
+  dt[o + 2 * ps] = d2;
+}
+
+// ---------------------------------------------------------- key switching ---
+
+// acc[ct][b][i] = sum_j dig[ct][j][i] * evk[j][b][i] (NTT domain), limbs
+// i = 0..L (the last one mod P).  The key is read once per chunk of CH
+// ciphertexts.
+template <int L, int CH>
+__global__ void __launch_bounds__(256) k_ks_mac(int n, int n_ct, const double* dig,
+                                                const double* evk, double* acc, Tables tb) {
+  constexpr int K = L + 1;
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (size_t)K * n) return;
+  const int i = (int)(gid / n);
+  const int c = (int)(gid - (size_t)i * n);
+  const int prime = i < L ? i : 2 * L + 1;
+  const double p = tb.p[prime], pinv = tb.pinv[prime];
+  for (int c0 = 0; c0 < n_ct; c0 += CH) {
+    double a0[CH], a1[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) a0[u] = a1[u] = 0.0;
+    for (int j = 0; j < L; ++j) {
+      const double e0 = evk[((size_t)(j * 2 + 0) * K + i) * n + c];
+      const double e1 = evk[((size_t)(j * 2 + 1) * K + i) * n + c];
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        if (c0 + u < n_ct) {
+          const double dv = dig[((size_t)((c0 + u) * L + j) * K + i) * n + c];
+          a0[u] += mul_lazy(dv, e0, p, pinv);
+          a1[u] += mul_lazy(dv, e1, p, pinv);
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      if (c0 + u < n_ct) {
+        acc[((size_t)((c0 + u) * 2 + 0) * K + i) * n + c] = reduce_bal(a0[u], p, pinv);
+        acc[((size_t)((c0 + u) * 2 + 1) * K + i) * n + c] = reduce_bal(a1[u], p, pinv);
+      }
+    }
+  }
+}
+
+// new ct (into ext limbs 0..L-1) = e_b + (acc_b - [acc_b]_P) * P^-1, where
+// [acc_b]_P is the balanced (= centred) residue of the P limb.
+template <int L>
+__global__ void __launch_bounds__(256) k_moddown(int n, int n_ct, const double* acc,
+                                                 const double* dt, double* ext, Tables tb) {
+  constexpr int K = L + 1;
+  constexpr int W = 2 * L + 1;
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (size_t)n_ct * 2 * n) return;
+  const size_t cb = gid / n;               // ct * 2 + b
+  const int c = (int)(gid - cb * n);
+  const size_t ct = cb >> 1;
+  const int b = (int)(cb & 1);
+  const double* a = acc + cb * (size_t)K * n + c;
+  const double aP = a[(size_t)L * n];
+  const double* e = dt + ((ct * 3 + b) * (size_t)W) * n + c;
+  double* o = ext + cb * (size_t)W * n + c;
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    const double q = tb.p[i], qinv = tb.pinv[i];
+    const double r = mul_lazy(a[(size_t)i * n] - aP, tb.P_inv_q[i], q, qinv);
+    o[(size_t)i * n] = reduce_bal(e[(size_t)i * n] + r, q, qinv);
+  }
+}
+
+// ------------------------------------------------------------ boundary ---
+
+// ext[ct][b][i] (i < L) = balanced(x - y); y broadcast over ct if y_bcast.
+__global__ void __launch_bounds__(256) k_sub_to_ext(int n, int L, int n_ct, const int64_t* x,
+                                                    const int64_t* y, int y_bcast, double* ext,
+                                                    Tables tb) {
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t per_ct = (size_t)2 * L * n;
+  if (gid >= (size_t)n_ct * per_ct) return;
+  const size_t ct = gid / per_ct;
+  const size_t r = gid - ct * per_ct;       // (b * L + i) * n + c
+  const int i = (int)((r / n) % L);
+  const double p = tb.p[i], pinv = tb.pinv[i];
+  const double xv = (double)x[gid];
+  const double yv = (double)y[y_bcast ? r : gid];
+  const size_t bi = r / n;                  // b * L + i
+  const int b = (int)(bi / L);
+  const int c = (int)(r - bi * n);
+  ext[((ct * 2 + b) * (size_t)(2 * L + 1) + i) * n + c] = reduce_bal(xv - yv, p, pinv);
+}
+
+__global__ void __launch_bounds__(256) k_sub_i64(int n, int L, size_t total, const int64_t* x,
+                                                 const int64_t* y, int64_t* out, Tables tb) {
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= total) return;
+  const int i = (int)((gid / n) % L);
+  const double p = tb.p[i];
+  double z = (double)x[gid] - (double)y[gid];
+  out[gid] = (int64_t)(z < 0.0 ? z + p : z);
+}
+
+// int64 [n_ct][npoly][L][N] canonical -> balanced doubles at
+// out + ct * ct_stride + poly * poly_stride + i * N.
+__global__ void __launch_bounds__(256) k_i64_to_polys(int n, int L, int npoly, size_t total,
+                                                      const int64_t* in, double* out,
+                                                      size_t ct_stride, size_t poly_stride,
+                                                      Tables tb) {
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= total) return;
+  const size_t row = gid / n;               // (ct * npoly + poly) * L + i
+  const int c = (int)(gid - row * n);
+  const int i = (int)(row % L);
+  const size_t cp = row / L;
+  const size_t ct = cp / npoly;
+  const int poly = (int)(cp - ct * npoly);
+  out[ct * ct_stride + poly * poly_stride + (size_t)i * n + c] = from_u64(in[gid], tb.p[i]);
+}
+
+// balanced doubles -> canonical int64 [n_ct][npoly][L][N].  With
+// negate_delta, outputs [-x]_q plus [Delta]_q at coefficient 0 of poly 0.
+__global__ void __launch_bounds__(256) k_polys_to_i64(int n, int L, int npoly, size_t total,
+                                                      const double* in, size_t ct_stride,
+                                                      size_t poly_stride, int64_t* out,
+                                                      int negate_delta, Tables tb) {
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= total) return;
+  const size_t row = gid / n;
+  const int c = (int)(gid - row * n);
+  const int i = (int)(row % L);
+  const size_t cp = row / L;
+  const size_t ct = cp / npoly;
+  const int poly = (int)(cp - ct * npoly);
+  const double p = tb.p[i], pinv = tb.pinv[i];
+  double v = in[ct * ct_stride + poly * poly_stride + (size_t)i * n + c];
+  if (negate_delta) {
+    v = -v;
+    if (poly == 0 && c == 0) v = reduce_bal(v + tb.delta_q[i], p, pinv);
+  }
+  out[gid] = to_i64(v, p);
+}
+
+// rows of int64 residues -> balanced doubles; row r uses prime
+// row_prime[r % nprime_rows].
+__global__ void __launch_bounds__(256) k_i64_rows(size_t total, int n, const int64_t* in,
+                                                  double* out, const int* row_prime,
+                                                  int nprime_rows, Tables tb) {
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= total) return;
+  const size_t row = gid / n;
+  const int prime = row_prime[row % nprime_rows];
+  out[gid] = from_u64(in[gid], tb.p[prime]);
+}
+
+__device__ __forceinline__ int brv(int x, int bits) {
+  return (int)(__builtin_bitreverse32((unsigned)x) >> (32 - bits));
+}
+
+// NTT-domain rows between the internal order and natural evaluation order:
+// natural j holds a(psi^(2j+1)), i.e. standard position brv(j), stored at
+// internal position (i mod E) * T + i / E.
+__global__ void __launch_bounds__(256) k_ntt_order(size_t total, int log2n, int loge,
+                                                   const double* in, int64_t* out,
+                                                   const int* row_prime, int nprime_rows,
+                                                   Tables tb) {
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= total) return;
+  const int n = 1 << log2n;
+  const size_t row = gid / n;
+  const int j = (int)(gid - row * n);
+  const int prime = row_prime[row % nprime_rows];
+  const int i = brv(j, log2n);
+  const int E = 1 << loge;
+  const int T = n >> loge;
+  const int pos = (i & (E - 1)) * T + (i >> loge);
+  out[gid] = to_i64(in[row * (size_t)n + pos], tb.p[prime]);
+}
+
+// ---------------------------------------------------------------- host ---
+
+static inline dim3 grid_for(size_t total) { return dim3((unsigned)((total + 255) / 256)); }
+
+#define NSHE_L_CASES(X) X(2) X(3) X(4) X(8) X(12) X(16) X(17) X(20) X(24)
+
+hipError_t run_lift(const Dims& d, double* ext, const Tables& tb, hipStream_t st) {
+  const size_t np = (size_t)d.n_ct * 2;
+  switch (d.L) {
+#define C_(L_) \
+  case L_: hipLaunchKernelGGL(k_lift<L_>, grid_for(np * d.n), dim3(256), 0, st, d.n, np, ext, tb); break;
+    NSHE_L_CASES(C_)
+#undef C_
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t run_lift_b(const Dims& d, double* ext_b, const Tables& tb, hipStream_t st) {
+  return run_lift(d, ext_b, tb, st);
+}
+
+hipError_t run_scale(const Dims& d, double* dt, const Tables& tb, hipStream_t st) {
+  const size_t np = (size_t)d.n_ct * 3;
+  switch (d.L) {
+#define C_(L_) \
+  case L_: hipLaunchKernelGGL(k_scale<L_>, grid_for(np * d.n), dim3(256), 0, st, d.n, np, dt, tb); break;
+    NSHE_L_CASES(C_)
+#undef C_
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t run_tensor(const Dims& d, const double* ext_a, const double* ext_b, double* dt,
+                      const Tables& tb, hipStream_t st) {
+  const size_t total = (size_t)d.n_ct * (2 * d.L + 1) * d.n;
+  switch (d.L) {
+#define C_(L_) \
+  case L_: hipLaunchKernelGGL(k_tensor<L_>, grid_for(total), dim3(256), 0, st, d.n, d.n_ct, ext_a, ext_b, dt, tb); break;
+    NSHE_L_CASES(C_)
+#undef C_
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t run_ks_mac(const Dims& d, const double* dig, const double* evk, double* acc,
+                      const Tables& tb, hipStream_t st) {
+  const size_t total = (size_t)(d.L + 1) * d.n;
+  switch (d.L) {
+#define C_(L_) \
+  case L_: hipLaunchKernelGGL((k_ks_mac<L_, 8>), grid_for(total), dim3(256), 0, st, d.n, d.n_ct, dig, evk, acc, tb); break;
+    NSHE_L_CASES(C_)
+#undef C_
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t run_moddown(const Dims& d, const double* acc, const double* dt, double* ext,
+                       const Tables& tb, hipStream_t st) {
+  const size_t total = (size_t)d.n_ct * 2 * d.n;
+  switch (d.L) {
+#define C_(L_) \
+  case L_: hipLaunchKernelGGL(k_moddown<L_>, grid_for(total), dim3(256), 0, st, d.n, d.n_ct, acc, dt, ext, tb); break;
+    NSHE_L_CASES(C_)
+#undef C_
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t run_sub_to_ext(const Dims& d, const int64_t* x, const int64_t* y, int y_bcast,
+                          double* ext, const Tables& tb, hipStream_t st) {
+  const size_t total = (size_t)d.n_ct * 2 * d.L * d.n;
+  hipLaunchKernelGGL(k_sub_to_ext, grid_for(total), dim3(256), 0, st, d.n, d.L, d.n_ct, x, y,
+                     y_bcast, ext, tb);
+  return hipGetLastError();
+}
+
+hipError_t run_sub_i64(const Dims& d, const int64_t* x, const int64_t* y, int64_t* out,
+                       const Tables& tb, hipStream_t st) {
+  const size_t total = (size_t)d.n_ct * 2 * d.L * d.n;
+  hipLaunchKernelGGL(k_sub_i64, grid_for(total), dim3(256), 0, st, d.n, d.L, total, x, y, out, tb);
+  return hipGetLastError();
+}
+
+hipError_t run_i64_to_polys(const Dims& d, const int64_t* in, int npoly_in, double* out,
+                            size_t out_ct_stride, size_t out_poly_stride, const Tables& tb,
+                            hipStream_t st) {
+  const size_t total = (size_t)d.n_ct * npoly_in * d.L * d.n;
+  hipLaunchKernelGGL(k_i64_to_polys, grid_for(total), dim3(256), 0, st, d.n, d.L, npoly_in, total,
+                     in, out, out_ct_stride, out_poly_stride, tb);
+  return hipGetLastError();
+}
+
+hipError_t run_polys_to_i64(const Dims& d, const double* in, int npoly, size_t in_ct_stride,
+                            size_t in_poly_stride, int64_t* out, int negate_delta,
+                            const Tables& tb, hipStream_t st) {
+  const size_t total = (size_t)d.n_ct * npoly * d.L * d.n;
+  hipLaunchKernelGGL(k_polys_to_i64, grid_for(total), dim3(256), 0, st, d.n, d.L, npoly, total,
+                     in, in_ct_stride, in_poly_stride, out, negate_delta, tb);
+  return hipGetLastError();
+}
+
+hipError_t run_i64_to_dbl_limbs(size_t rows, int n, const int64_t* in, double* out,
+                                const int* row_prime, int nprime_rows, const Tables& tb,
+                                hipStream_t st) {
+  const size_t total = rows * n;
+  hipLaunchKernelGGL(k_i64_rows, grid_for(total), dim3(256), 0, st, total, n, in, out, row_prime,
+                     nprime_rows, tb);
+  return hipGetLastError();
+}
+
+hipError_t run_ntt_order(int log2n, size_t rows, const double* in, int64_t* out,
+                         const int* row_prime, int nprime_rows, int to_natural,
+                         const Tables& tb, hipStream_t st) {
+  int loge = 0, r0 = 0;
+  if (ntt_rounds(log2n, &loge, &r0) < 0 || !to_natural) return hipErrorInvalidValue;
+  const size_t total = rows << log2n;
+  hipLaunchKernelGGL(k_ntt_order, grid_for(total), dim3(256), 0, st, total, log2n, loge, in, out,
+                     row_prime, nprime_rows, tb);
+  return hipGetLastError();
+}
+
+}  // namespace nshe

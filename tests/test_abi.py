@@ -1,0 +1,84 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point include/nshe.h declares, rejects bad parameters before it
+touches a device, and the package's default parameters equal the oracle's
+independently derived ones."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2602_24271_amd import _lib, params
+from oracle import nt
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nshe.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(nshe_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_expected_calls():
+    names = _declared()
+    for must in ("nshe_ctx_create", "nshe_set_relin_key", "nshe_sub", "nshe_square_relin",
+                 "nshe_mul_relin", "nshe_eq_mask", "nshe_eq_mask_batched", "nshe_margin_events",
+                 "nshe_last_error", "nshe_workspace_bytes"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+    # and the binding describes every one of them
+    assert set(_declared()) == set(_lib.SIGNATURES)
+
+
+def _create(log2_n=10, t=65537, q=None, P=None):
+    lib = _lib.load()
+    if q is None:
+        q, P = params.modulus_chain()
+    qa = (ctypes.c_uint64 * len(q))(*q)
+    pr = _lib.NsheParams(log2_n, t, len(q), ctypes.cast(qa, ctypes.POINTER(ctypes.c_uint64)), P)
+    h = ctypes.c_void_p()
+    rc = lib.nshe_ctx_create(ctypes.byref(pr), 0, ctypes.byref(h))
+    return rc, lib.nshe_last_error().decode(), h
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(log2_n=2), "log2_n"),
+    (dict(log2_n=16), "log2_n"),
+    (dict(t=65536), "t must be odd"),
+    (dict(t=1), "t must be odd"),
+    (dict(q=[97], P=193), "[2^48, 2^49)"),
+])
+def test_create_rejects_bad_parameters_before_device_use(kw, msg):
+    rc, err, h = _create(**kw)
+    assert rc == -1 and msg in err and not h.value
+
+
+def test_create_rejects_composite_and_duplicate_primes():
+    q, P = params.modulus_chain()
+    rc, err, _ = _create(q=[q[0] + 65536 * 3] + q[1:], P=P)  # 1 mod 2^16, composite or not prime
+    if nt.is_prime(q[0] + 65536 * 3):
+        pytest.skip("perturbed value happens to be prime")
+    assert rc == -1 and "not prime" in err
+    rc, err, _ = _create(q=[q[0], q[0]] + q[2:], P=P)
+    assert rc == -1 and "distinct" in err
+
+
+def test_null_arguments_are_rejected():
+    lib = _lib.load()
+    assert lib.nshe_ctx_create(None, 0, None) == -1
+    assert lib.nshe_sub(None, None, None, None, 1, None) == -1
+    assert lib.nshe_workspace_bytes(None, 4) == 0
+    assert lib.nshe_eq_mask(None, None, None, None, 1, 0, None, 0, None) == -1
+
+
+def test_default_parameters_match_the_oracle():
+    q, P = params.modulus_chain()
+    oq, oP = nt.default_modulus_chain()
+    assert (q, P) == (oq, oP)

@@ -1,0 +1,45 @@
+"""Full paper size (N = 32768, 17 + 1 primes of ~49 bits, p = 65537):
+sampled NTT outputs, one squaring bit-exact against the oracle, and the
+whole 16-squaring mask decrypting to [x == y] with budget to spare."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import bfv, encoding, ntt_def
+from tests.gpu_common import Setup
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def s32k():
+    return Setup(15)
+
+
+def test_full_size_ntt_sampled(s32k):
+    S = s32k
+    rng = np.random.default_rng(3)
+    polys = np.stack([rng.integers(0, q, S.pr.n) for q in S.pr.q])[None]
+    got = S.ctx.ntt(torch.from_numpy(polys).to(S.ctx.device)).cpu().numpy()
+    for i in (0, S.pr.L - 1):
+        for j in (0, 32767, int(rng.integers(0, 32768))):
+            assert got[0, i, j] == ntt_def.evaluation_at(list(polys[0, i]), S.pr.q[i], j)
+
+
+def test_full_size_square_and_mask(s32k):
+    S = s32k
+    x, y = synth.column_pair_half_match(0, S.pr.n)
+    x, y = synth.edge_differences(x, y, S.pr.t)
+    cx, cy = S.enc(x, 1), S.enc(y, 2)
+    z0 = bfv.sub(S.pr, cx, cy)
+    want1 = bfv.square_relin(S.pr, S.rk, z0)
+    dz = S.ctx.sub(S.to_dev([cx]), S.to_dev([cy]))
+    got1 = S.ctx.square_relin(dz)
+    np.testing.assert_array_equal(got1[0].cpu().numpy(), S.limbs(want1))
+    out = S.ctx.eq_mask(S.to_dev([cx]), S.to_dev([cy]))
+    got = S.from_dev(out)[0]
+    mask = bfv.decrypt_slots(S.pr, S.sk, got)
+    assert list(mask) == list((x == y).astype(int))
+    m_true = encoding.encode((x == y).astype(int), S.pr.t)
+    assert bfv.noise_bits(S.pr, S.sk, got, m_true) > 100
