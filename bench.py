@@ -39,10 +39,11 @@ sys.path.insert(0, ROOT)
 # FP64 VALU issue rate of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 # (= 78.6 TFLOP/s counting an FMA as two flops).
 PEAK_FP64_OPS = 256 * 64 * 2.4e9
-# FP64 VALU operations of one exact modular butterfly in this library:
-# twiddle product 6 (mul, fma, mul, rndne, fma, add), operand reduction 3
-# (mul, rndne, fma), sum and difference 2.
-OPS_PER_BUTTERFLY = 11
+# Algorithmic FP64 VALU operations of one exact modular butterfly: the
+# modular product (mul, fma, mul, rndne, fma, add = 6, the error-free FMA
+# formulation) and the sum and difference (2).  Range reductions the
+# kernel adds (lazy, once per round) are overhead, not counted.
+OPS_PER_BUTTERFLY = 8
 PAPER_RECORDS_PER_S = 1.0 / 0.09e-3   # 0.09 ms per record, 1 CPU thread (SEAL)
 
 
@@ -168,7 +169,70 @@ def batched(ctx, n_inst: int, reps: int) -> dict:
             "ms_graph": t_graph * 1e3, "ms_loop": t_loop * 1e3, "speedup": t_loop / t_graph}
 
 
+def summarize_profiles(prof_dir: str, out_dir: str) -> None:
+    """Turn rocprofv3 output (kernel trace stats; FETCH_SIZE and WRITE_SIZE
+    counter passes that include a device copy of known size) into the short
+    summaries kept under profiles/.  Counter readings are scaled by the
+    ratio of the copy's known bytes to what the same counter reads for it."""
+    import csv
+    import collections
+    os.makedirs(out_dir, exist_ok=True)
+    stats = list(csv.DictReader(open(os.path.join(prof_dir, "trace", "eq_kernel_stats.csv"))))
+    lines = ["| kernel | calls | mean us | total ms | % |", "|---|---|---|---|---|"]
+    for r in stats:
+        lines.append(f"| {r['Name'][:90]} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.1f} |")
+    mib = 256
+    traffic = {}
+    factors = {}
+    per_kind = {}
+    for counter, sub in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
+        rows = list(csv.DictReader(open(os.path.join(prof_dir, sub, "eq_counter_collection.csv"))))
+        copy = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]
+                and int(r["Grid_Size"]) >= 131072]
+        factor = (mib * 1024) / max(copy) if copy else 1.0
+        factors[counter] = factor
+        agg = collections.defaultdict(list)
+        for r in rows:
+            agg[(r["Kernel_Name"], int(r["Grid_Size"]))].append(float(r["Counter_Value"]))
+        for (name, grid), v in agg.items():
+            per_kind.setdefault((name, grid), {})[counter] = sum(v) / len(v) * 1024 * factor
+    tl = ["| kernel | grid | fetch MB/launch | write MB/launch |", "|---|---|---|---|"]
+    for (name, grid), d in sorted(per_kind.items(), key=lambda kv: -sum(kv[1].values())):
+        if sum(d.values()) < 1e8:
+            continue
+        tl.append(f"| {name[:70]} | {grid} | {d.get('FETCH_SIZE', 0) / 1e6:.1f} | "
+                  f"{d.get('WRITE_SIZE', 0) / 1e6:.1f} |")
+    # the digit transform is the NTT launch over n_ct * L * (L + 1) limbs
+    for (name, grid), d in per_kind.items():
+        if "ntt_fwd" in name and "1>" in name or ("ntt_fwd" in name and grid == 32 * 17 * 18 * 1024):
+            traffic["ntt_digit"] = d.get("FETCH_SIZE", 0) + d.get("WRITE_SIZE", 0)
+    with open(os.path.join(out_dir, "traffic.json"), "w") as fh:
+        json.dump({"kernel_hash": kernel_hash(), "bytes_per_launch": traffic,
+                   "calibration": {"copy_mib": mib, "factors": factors}}, fh, indent=1)
+    cmd_trace = ("rocprofv3 --kernel-trace --stats -d gpurun_out/prof/trace -o eq --output-format csv "
+                 "-- python3 bench.py --steps 3 --warmup 1 --skip-batched --skip-cpu")
+    cmd_pmc = ("rocprofv3 --pmc {C} -d gpurun_out/prof/{d} -o eq --output-format csv -- python3 "
+               "bench.py --steps 1 --warmup 0 --skip-batched --skip-cpu --calibrate-copy-mib 256")
+    with open(os.path.join(out_dir, "eq_mask_2p20_rows_kernels.md"), "w") as fh:
+        fh.write("# EQ mask, 2^20 rows (32 ciphertexts, N=32768), per-kernel time\n\n")
+        fh.write(f"Kernel sources hash: {kernel_hash()}\n\nCommand (from the repo root, "
+                 f"TMPDIR=/tmp):\n\n    {cmd_trace}\n\n")
+        fh.write("\n".join(lines) + "\n")
+    with open(os.path.join(out_dir, "eq_mask_2p20_rows_hbm_traffic.md"), "w") as fh:
+        fh.write("# EQ mask, 2^20 rows: HBM bytes per launch (FETCH_SIZE, WRITE_SIZE)\n\n")
+        fh.write(f"Kernel sources hash: {kernel_hash()}\n\nCommands, one counter per pass:\n\n")
+        fh.write("    " + cmd_pmc.format(C="FETCH_SIZE", d="fetch") + "\n")
+        fh.write("    " + cmd_pmc.format(C="WRITE_SIZE", d="write") + "\n\n")
+        fh.write(f"Calibration: a {mib} MiB device copy reads {mib} MiB and writes {mib} MiB; "
+                 f"scale factors applied: {json.dumps(factors)}.\n\n")
+        fh.write("\n".join(tl) + "\n")
+
+
 def main() -> int:
+    if len(sys.argv) >= 2 and sys.argv[1] == "--summarize-profiles":
+        summarize_profiles(sys.argv[2], os.path.join(ROOT, "profiles"))
+        return 0
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
@@ -178,6 +242,8 @@ def main() -> int:
     ap.add_argument("--batched-reps", type=int, default=1)
     ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="run one device copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -192,6 +258,12 @@ def main() -> int:
         print("bench.py needs a HIP device", file=sys.stderr)
         return 2
     dev = torch.device("cuda", 0)
+    if args.calibrate_copy_mib:
+        a = torch.empty(args.calibrate_copy_mib << 17, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     ctx = Context.paper(15)
     n_ct = args.n_ct
     log(f"context N={ctx.n} L={ctx.L} ext={ctx.L_ext} squarings={ctx.squarings}")

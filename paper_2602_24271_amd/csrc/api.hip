@@ -153,10 +153,11 @@ static int W_of(const nshe_ctx* c) { return 2 * c->L + 1; }
 
 // ------------------------------------------------------------ profiling
 
-enum Kind { K_SUB, K_LIFT, K_NTT_FWD, K_TENSOR, K_NTT_INV, K_SCALE, K_NTT_DIGIT, K_KS_MAC,
-            K_MODDOWN, K_CONVERT, K_COUNT };
-static const char* kKindName[K_COUNT] = {"sub",   "lift",      "ntt_fwd", "tensor",  "ntt_inv",
-                                         "scale", "ntt_digit", "ks_mac",  "moddown", "convert"};
+enum Kind { K_SUB, K_LIFT, K_NTT_FWD, K_NTT_INV_TENSOR, K_NTT_INV, K_SCALE, K_NTT_DIGIT,
+            K_KS_MAC, K_MODDOWN, K_CONVERT, K_COUNT };
+static const char* kKindName[K_COUNT] = {"sub",   "lift",      "ntt_fwd", "ntt_inv_tensor",
+                                         "ntt_inv", "scale", "ntt_digit", "ks_mac",
+                                         "moddown", "convert"};
 
 static hipEvent_t take_event(nshe_ctx* c) {
   if (!c->pool.empty()) {
@@ -274,11 +275,20 @@ static int prepare_operand(nshe_ctx* c, double* ext, int n_ct, hipStream_t st) {
 static int tensor_scale(nshe_ctx* c, const Ws& w, const double* ext_b, int n_ct, hipStream_t st) {
   Dims d{c->n, c->L, c->LB, n_ct};
   {
-    Prof pf(c, K_TENSOR, st, (double)n_ct * W_of(c) * c->n);
-    HIPCHK(run_tensor(d, w.ext, ext_b, w.dt, c->tb, st));
+    // the tensor product is formed while the inverse transform loads
+    NttJob j{};
+    j.base = w.dt;
+    j.poly_stride = (size_t)W_of(c) * c->n;
+    j.npoly = n_ct * 3;
+    j.nlimb = W_of(c);
+    j.limb_prime = c->lp_ext;
+    j.count = j.npoly * j.nlimb;
+    j.src = w.ext;
+    j.src_b = ext_b;
+    j.src_ct_stride = (size_t)2 * W_of(c) * c->n;
+    Prof pf(c, K_NTT_INV_TENSOR, st, ntt_work(c, j.count));
+    HIPCHK(run_ntt(c->log2n, j, c->tb, 3, st));
   }
-  int rc = ntt_job_ext(c, w.dt, n_ct * 3, 1, st);
-  if (rc) return rc;
   {
     Prof pf(c, K_SCALE, st, 3.0 * n_ct * c->n);
     HIPCHK(run_scale(d, w.dt, c->tb, st));
@@ -466,7 +476,7 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
   }
   std::vector<u64> qv(q), bv(b);
   std::vector<double> q_hat_inv(L), q_hat_b((size_t)LB * L), Q_b(LB), t_qhinv(L), t_q(L),
-      c1(LB), c2((size_t)LB * L), b_hat_inv(LB), b_hat_q((size_t)L * LB), B_q(L), P_inv_q(L),
+      c1(LB), c2((size_t)LB * L), b_hat_inv(LB), b_hat_q((size_t)L * LB), B_q(L), P_inv_q(L), NP_inv_q(L),
       delta_q(L), mrc_inv((size_t)L * L, 0.0), mrc_half(L);
   u64 Qmodt = 1;
   for (u64 x : qv) Qmodt = mulmod(Qmodt, x % c->t, c->t);
@@ -474,10 +484,13 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
     const u64 qi = qv[i];
     const u64 qhi = invmod(prod_mod(qv, i, qi), qi);
     q_hat_inv[i] = bal(qhi, qi);
-    t_qhinv[i] = bal(mulmod(c->t % qi, qhi, qi), qi);
-    t_q[i] = bal(c->t % qi, qi);
+    // inverse transforms return N times the coefficients: fold N^-1 here
+    const u64 ninv_q = invmod((u64)n % qi, qi);
+    t_qhinv[i] = bal(mulmod(mulmod(c->t % qi, qhi, qi), ninv_q, qi), qi);
+    t_q[i] = bal(mulmod(c->t % qi, ninv_q, qi), qi);
     B_q[i] = bal(prod_mod(bv, -1, qi), qi);
     P_inv_q[i] = bal(invmod(pr->P % qi, qi), qi);
+    NP_inv_q[i] = bal(mulmod(invmod(pr->P % qi, qi), ninv_q, qi), qi);
     // Delta = (Q - (Q mod t)) / t = -(Q mod t) * t^-1 (mod q_i)
     delta_q[i] = bal((qi - mulmod(Qmodt, invmod(c->t % qi, qi), qi)) % qi, qi);
     for (int k = 0; k < LB; ++k) b_hat_q[(size_t)i * LB + k] = bal(prod_mod(bv, k, qi), qi);
@@ -489,7 +502,8 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
     Q_b[k] = bal(Qb, bk);
     const u64 bhi = invmod(prod_mod(bv, k, bk), bk);
     b_hat_inv[k] = bal(bhi, bk);
-    c1[k] = bal(mulmod(mulmod(c->t % bk, invmod(Qb, bk), bk), bhi, bk), bk);
+    c1[k] = bal(mulmod(mulmod(mulmod(c->t % bk, invmod(Qb, bk), bk), bhi, bk),
+                       invmod((u64)n % bk, bk), bk), bk);
     for (int i = 0; i < L; ++i) {
       q_hat_b[(size_t)k * L + i] = bal(prod_mod(qv, i, bk), bk);
       c2[(size_t)k * L + i] = bal(mulmod(invmod(qv[i] % bk, bk), bhi, bk), bk);
@@ -516,7 +530,8 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
       {&q_hat_inv, &c->tb.q_hat_inv}, {&q_hat_b, &c->tb.q_hat_b}, {&Q_b, &c->tb.Q_b},
       {&t_qhinv, &c->tb.t_qhinv}, {&t_q, &c->tb.t_q},         {&c1, &c->tb.c1},
       {&c2, &c->tb.c2},           {&b_hat_inv, &c->tb.b_hat_inv}, {&b_hat_q, &c->tb.b_hat_q},
-      {&B_q, &c->tb.B_q},         {&P_inv_q, &c->tb.P_inv_q}, {&delta_q, &c->tb.delta_q},
+      {&B_q, &c->tb.B_q},         {&P_inv_q, &c->tb.P_inv_q}, {&NP_inv_q, &c->tb.NP_inv_q},
+      {&delta_q, &c->tb.delta_q},
       {&mrc_inv, &c->tb.mrc_inv}, {&mrc_half, &c->tb.mrc_half}};
   size_t total = 0;
   std::vector<size_t> offs;

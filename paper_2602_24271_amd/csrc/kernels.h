@@ -27,15 +27,18 @@ struct Tables {
   const double* q_hat_b;     // [LB][L]  [Q/q_i]_{b_k}
   const double* Q_b;         // [LB]     [Q]_{b_k}
   // scale and round, then B -> Q
-  const double* t_qhinv;     // [L]      [t (Q/q_i)^-1]_{q_i}
-  const double* t_q;         // [L]      [t]_{q_i}
-  const double* c1;          // [LB]     [t Q^-1 (B/b_k)^-1]_{b_k}
+  // (the scale-and-round reads inverse-transform output, which carries a
+  // factor N: its constants include N^-1)
+  const double* t_qhinv;     // [L]      [t (Q/q_i)^-1 N^-1]_{q_i}
+  const double* t_q;         // [L]      [t N^-1]_{q_i}
+  const double* c1;          // [LB]     [t Q^-1 (B/b_k)^-1 N^-1]_{b_k}
   const double* c2;          // [LB][L]  [q_i^-1 (B/b_k)^-1]_{b_k}
   const double* b_hat_inv;   // [LB]     [(B/b_k)^-1]_{b_k}
   const double* b_hat_q;     // [L][LB]  [B/b_k]_{q_i}
   const double* B_q;         // [L]      [B]_{q_i}
   // key switching
   const double* P_inv_q;     // [L]      [P^-1]_{q_i}
+  const double* NP_inv_q;    // [L]      [N^-1 P^-1]_{q_i}
   const double* delta_q;     // [L]      [floor(Q/t)]_{q_i}
   // exact fallback of the Q lift: mixed-radix digits
   const double* mrc_inv;     // [L][L]   [q_j^-1]_{q_i}, canonical, row j
@@ -44,7 +47,7 @@ struct Tables {
   unsigned long long* fault;   // B->Q lift outside its proven range (never)
 };
 
-enum { NTT_INPLACE = 0, NTT_DIGIT = 1 };
+enum { NTT_INPLACE = 0, NTT_DIGIT = 1, INV_TENSOR = 2 };
 
 struct NttJob {
   double* base;              // first limb of poly 0
@@ -53,11 +56,16 @@ struct NttJob {
   int nlimb;                 // limbs per poly transformed
   const int* limb_prime;     // [nlimb] prime index of each limb
   int count;                 // npoly * nlimb
-  // NTT_DIGIT source
-  const double* src;         // digit source (third component, data limbs)
+  // NTT_DIGIT source: third component's data limbs; INV_TENSOR: the
+  // operands' transforms ([ct][2][W][N], src_b null when squaring)
+  const double* src;
+  const double* src_b;
   size_t src_ct_stride;      // doubles between ciphertexts in src
   int digits;                // L (digits per ciphertext)
 };
+
+// run_ntt directions: 0 forward in place, 1 inverse in place, 2 forward of
+// relinearization digits, 3 inverse of the tensor product formed on load.
 
 hipError_t run_ntt(int log2n, const NttJob& job, const Tables& tb, int dir, hipStream_t st);
 int ntt_rounds(int log2n, int* loge, int* r0);
@@ -72,8 +80,6 @@ struct Dims {
 
 hipError_t run_lift(const Dims& d, double* ext, const Tables& tb, hipStream_t st);
 hipError_t run_lift_b(const Dims& d, double* ext_b, const Tables& tb, hipStream_t st);
-hipError_t run_tensor(const Dims& d, const double* ext_a, const double* ext_b, double* dt,
-                      const Tables& tb, hipStream_t st);
 hipError_t run_scale(const Dims& d, double* dt, const Tables& tb, hipStream_t st);
 hipError_t run_ks_mac(const Dims& d, const double* dig, const double* evk, double* acc,
                       const Tables& tb, hipStream_t st);

@@ -81,4 +81,13 @@ __device__ __forceinline__ void buf_store(double v, __amdgpu_buffer_rsrc_t r, un
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, v), r, voff, soff, 0);
 }
 
+// Read-only table load through the constant address space: uniform
+// indices then use scalar loads (SGPRs) instead of one vector load per lane.
+// Valid because the tables are never written while a kernel runs.
+typedef const __attribute__((address_space(4))) double* const_dptr;
+typedef const __attribute__((address_space(4))) int* const_iptr;
+
+__device__ __forceinline__ double cld(const double* p, int i) { return ((const_dptr)p)[i]; }
+__device__ __forceinline__ int cldi(const int* p, int i) { return ((const_iptr)p)[i]; }
+
 }  // namespace nshe

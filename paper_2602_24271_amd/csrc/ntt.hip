@@ -6,7 +6,8 @@
 // psi^(brv(2^s + m)) (m = index >> (b+1)), psi a primitive 2N-th root of
 // unity mod p; the output at standard position i is a(psi^(2 brv(i) + 1)).
 // The inverse runs the Gentleman-Sande butterflies with inverse twiddles in
-// reverse stage order and scales by N^-1.
+// reverse stage order and returns N times the coefficients: the N^-1 factor
+// is folded into the constants of every consumer of an inverse transform.
 //
 // Work decomposition (one workgroup = one N-point limb, T = N / E threads,
 // E = 2^LOGE values per thread held in VGPRs): stages are grouped in
@@ -64,6 +65,12 @@ struct NttShape {
 
 __device__ __forceinline__ int pad32(int i) { return i + (i >> 5); }
 
+__host__ __device__ constexpr int brv_c(int x, int bits) {
+  int r = 0;
+  for (int i = 0; i < bits; ++i) r |= ((x >> i) & 1) << (bits - 1 - i);
+  return r;
+}
+
 template <int LOGN>
 __device__ __forceinline__ int round_index(int r, int tid, int e) {
   using S = NttShape<LOGN>;
@@ -83,106 +90,187 @@ __device__ __forceinline__ constexpr int slot_off(int r, int e) {
   return (e << NttShape<LOGN>::lo(r)) + ((e << NttShape<LOGN>::lo(r)) >> 5);
 }
 
+// LDS word address of element e in round r: a per-thread base plus a
+// constant.  Offsets beyond the 16-bit immediate of ds_read/ds_write are
+// split off into a per-chunk base (CH elements per chunk).
+template <int LOGN, int BYTES>
+__device__ __forceinline__ constexpr int lds_chunk() {
+  int ch = NttShape<LOGN>::E;
+  for (int r = 0; r < NttShape<LOGN>::ROUNDS; ++r)
+    while (ch > 1 && slot_off<LOGN>(r, ch - 1) * BYTES >= 65536) ch >>= 1;
+  return ch;
+}
+
 // Move the E values of every thread from round r0's index map to r1's.
+// The base addresses are made opaque per pass (inline asm), so that no
+// per-element address registers stay live across the barriers.
 template <int LOGN>
 __device__ __forceinline__ void exchange(double (&x)[NttShape<LOGN>::E], int r0, int r1,
                                          uint32_t* lds) {
   using S = NttShape<LOGN>;
   const int tid = threadIdx.x;
-  const int b0 = slot_base<LOGN>(r0, tid);
-  const int b1 = slot_base<LOGN>(r1, tid);
   if constexpr (S::SPLIT) {
+    constexpr int C0 = lds_chunk<LOGN, 4>();
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
+      int b0 = slot_base<LOGN>(r0, tid);
+      asm volatile("" : "+v"(b0));
 #pragma unroll
-      for (int e = 0; e < S::E; ++e) {
-        unsigned long long v = __double_as_longlong(x[e]);
-        lds[b0 + slot_off<LOGN>(r0, e)] = half ? (uint32_t)(v >> 32) : (uint32_t)v;
+      for (int c = 0; c < S::E; c += C0) {
+        uint32_t* base = lds + b0 + slot_off<LOGN>(r0, c);
+#pragma unroll
+        for (int e = c; e < c + C0; ++e) {
+          unsigned long long v = __double_as_longlong(x[e]);
+          base[slot_off<LOGN>(r0, e) - slot_off<LOGN>(r0, c)] =
+              half ? (uint32_t)(v >> 32) : (uint32_t)v;
+        }
       }
       __syncthreads();
+      int b1 = slot_base<LOGN>(r1, tid);
+      asm volatile("" : "+v"(b1));
 #pragma unroll
-      for (int e = 0; e < S::E; ++e) {
-        uint32_t w = lds[b1 + slot_off<LOGN>(r1, e)];
-        unsigned long long v = __double_as_longlong(x[e]);
-        v = half ? ((v & 0xffffffffull) | ((unsigned long long)w << 32))
-                 : ((v & 0xffffffff00000000ull) | w);
-        x[e] = __longlong_as_double(v);
+      for (int c = 0; c < S::E; c += C0) {
+        const uint32_t* base = lds + b1 + slot_off<LOGN>(r1, c);
+#pragma unroll
+        for (int e = c; e < c + C0; ++e) {
+          const uint32_t w = base[slot_off<LOGN>(r1, e) - slot_off<LOGN>(r1, c)];
+          unsigned long long v = __double_as_longlong(x[e]);
+          v = half ? ((v & 0xffffffffull) | ((unsigned long long)w << 32))
+                   : ((v & 0xffffffff00000000ull) | w);
+          x[e] = __longlong_as_double(v);
+        }
       }
       __syncthreads();
     }
   } else {
     double* d = reinterpret_cast<double*>(lds);
+    constexpr int C0 = lds_chunk<LOGN, 8>();
+    int b0 = slot_base<LOGN>(r0, tid);
+    asm volatile("" : "+v"(b0));
 #pragma unroll
-    for (int e = 0; e < S::E; ++e) d[b0 + slot_off<LOGN>(r0, e)] = x[e];
+    for (int c = 0; c < S::E; c += C0) {
+      double* base = d + b0 + slot_off<LOGN>(r0, c);
+#pragma unroll
+      for (int e = c; e < c + C0; ++e)
+        base[slot_off<LOGN>(r0, e) - slot_off<LOGN>(r0, c)] = x[e];
+    }
     __syncthreads();
+    int b1 = slot_base<LOGN>(r1, tid);
+    asm volatile("" : "+v"(b1));
 #pragma unroll
-    for (int e = 0; e < S::E; ++e) x[e] = d[b1 + slot_off<LOGN>(r1, e)];
+    for (int c = 0; c < S::E; c += C0) {
+      const double* base = d + b1 + slot_off<LOGN>(r1, c);
+#pragma unroll
+      for (int e = c; e < c + C0; ++e) x[e] = base[slot_off<LOGN>(r1, e) - slot_off<LOGN>(r1, c)];
+    }
     __syncthreads();
   }
 }
 
+// Cooley-Tukey butterfly without reducing X: with balanced input (|x| <
+// p/2) and balanced twiddles (|W| < p/2), |T| <= (1/2 + d) p where the
+// quotient error d <= |Y W / p| 3 2^-53 <= 0.094 |Y|/p, so five stages grow
+// |x| at most to 1.0, 1.59, 2.24, 2.95, 3.73 p < 4p: every product stays in
+// mul_lazy's range (|Y W| < 2 p^2) and every value below 2^53.  A round
+// (<= 5 stages) therefore reduces only once, at its end.
 __device__ __forceinline__ void ct_bfly(double& X, double& Y, double W, double p, double pinv) {
-  double xr = reduce_bal(X, p, pinv);
   double t = mul_lazy(Y, W, p, pinv);
-  X = xr + t;
-  Y = xr - t;
+  double x = X;
+  X = x + t;
+  Y = x - t;
 }
 
+// Gentleman-Sande butterfly; the sum is reduced on alternate stages only
+// (REDUCE_SUM), the difference feeds the modular product directly.  With
+// inputs below 0.76 p after a product and 0.5 p after a reduction, the
+// unreduced sum stays below 1.52 p + 0.76 p and every difference below
+// 2.3 p, inside mul_lazy's range.
+template <bool REDUCE_SUM>
 __device__ __forceinline__ void gs_bfly(double& X, double& Y, double W, double p, double pinv) {
   double s = X + Y;
   double d = X - Y;
-  X = reduce_bal(s, p, pinv);
+  X = REDUCE_SUM ? reduce_bal(s, p, pinv) : s;
   Y = mul_lazy(d, W, p, pinv);
 }
+
+// Twiddle w of stage k, slot j (1 <= 2^k + j < E) in round r.  Round 0's
+// twiddles are the same for every thread and come through the scalar
+// cache; later rounds' depend on the thread and use a buffer load whose
+// offset is made to depend (inline asm) on the previous stage's results,
+// so that no stage's loads are hoisted above it (which spills registers at
+// 1024 threads per workgroup).
+template <int LOGN>
+struct Twiddles {
+  using S = NttShape<LOGN>;
+  const double* __restrict__ t0;
+  __amdgpu_buffer_rsrc_t tr;
+  unsigned tvo;
+  __device__ __forceinline__ Twiddles(const double* __restrict__ tw, int r) {
+    t0 = tw;
+    tr = make_rsrc(tw, S::tw_len() * 8);
+    const int u = r == 0 ? 0 : (int)(threadIdx.x >> S::lo(r));
+    tvo = (S::tw_off(r) + u * S::E) * 8;
+  }
+  __device__ __forceinline__ unsigned stage_offset(const double& fence) const {
+    unsigned o = tvo;
+    asm volatile("" : "+v"(o) : "v"(fence));
+    return o;
+  }
+};
 
 // Round r of the forward transform on this thread's registers.
 template <int LOGN>
 __device__ __forceinline__ void fwd_round(double (&x)[NttShape<LOGN>::E], int r,
                                           const double* __restrict__ tw, double p, double pinv) {
   using S = NttShape<LOGN>;
-  const int tid = threadIdx.x;
-  const int u = r == 0 ? 0 : (tid >> S::lo(r));
-  const auto tr = make_rsrc(tw, S::tw_len() * 8);
-  const unsigned tvo = (S::tw_off(r) + u * S::E) * 8;
+  const Twiddles<LOGN> T(tw, r);
   const int R = S::stages(r);
 #pragma unroll
   for (int k = 0; k < S::LOGE; ++k) {
     if (k >= R) break;
     const int eb = S::LOGE - 1 - k;
-    double w[1 << (S::LOGE - 1)];
+    const unsigned o = r == 0 ? 0u : T.stage_offset(x[0]);
 #pragma unroll
-    for (int j = 0; j < (1 << k); ++j) w[j] = buf_load(tr, tvo, ((1 << k) + j) * 8);
+    for (int j = 0; j < (1 << k); ++j) {
+      const double w = r == 0 ? cld(T.t0, S::tw_off(0) + (1 << k) + j) : buf_load(T.tr, o, ((1 << k) + j) * 8);
 #pragma unroll
-    for (int e = 0; e < S::E; ++e) {
-      if (e & (1 << eb)) continue;
-      ct_bfly(x[e], x[e | (1 << eb)], w[e >> (eb + 1)], p, pinv);
+      for (int b = 0; b < (1 << eb); ++b) {
+        const int e = (j << (eb + 1)) | b;
+        ct_bfly(x[e], x[e | (1 << eb)], w, p, pinv);
+      }
     }
   }
+#pragma unroll
+  for (int e = 0; e < S::E; ++e) x[e] = reduce_bal(x[e], p, pinv);
 }
 
 template <int LOGN>
 __device__ __forceinline__ void inv_round(double (&x)[NttShape<LOGN>::E], int r,
                                           const double* __restrict__ tw, double p, double pinv) {
   using S = NttShape<LOGN>;
-  const int tid = threadIdx.x;
-  const int u = r == 0 ? 0 : (tid >> S::lo(r));
-  const auto tr = make_rsrc(tw, S::tw_len() * 8);
-  const unsigned tvo = (S::tw_off(r) + u * S::E) * 8;
+  const Twiddles<LOGN> T(tw, r);
   const int R = S::stages(r);
 #pragma unroll
   for (int kk = 0; kk < S::LOGE; ++kk) {
     const int k = S::LOGE - 1 - kk;
     if (k >= R) continue;
     const int eb = S::LOGE - 1 - k;
-    double w[1 << (S::LOGE - 1)];
+    const unsigned o = r == 0 ? 0u : T.stage_offset(x[0]);
 #pragma unroll
-    for (int j = 0; j < (1 << k); ++j) w[j] = buf_load(tr, tvo, ((1 << k) + j) * 8);
+    for (int j = 0; j < (1 << k); ++j) {
+      const double w = r == 0 ? cld(T.t0, S::tw_off(0) + (1 << k) + j) : buf_load(T.tr, o, ((1 << k) + j) * 8);
 #pragma unroll
-    for (int e = 0; e < S::E; ++e) {
-      if (e & (1 << eb)) continue;
-      gs_bfly(x[e], x[e | (1 << eb)], w[e >> (eb + 1)], p, pinv);
+      for (int b = 0; b < (1 << eb); ++b) {
+        const int e = (j << (eb + 1)) | b;
+        if (kk & 1)
+          gs_bfly<true>(x[e], x[e | (1 << eb)], w, p, pinv);
+        else
+          gs_bfly<false>(x[e], x[e | (1 << eb)], w, p, pinv);
+      }
     }
   }
+#pragma unroll
+  for (int e = 0; e < S::E; ++e) x[e] = reduce_bal(x[e], p, pinv);
 }
 
 // Work item of an NTT launch: item = limb * npoly + poly (limb-major, so
@@ -200,12 +288,31 @@ __global__ void __launch_bounds__(NttShape<LOGN>::T)
 k_ntt_fwd(NttJob job, Tables tb) {
   using S = NttShape<LOGN>;
   __shared__ uint32_t lds[S::LDS_WORDS];
-  const int item = xcd_item(job.count);
-  if (item >= job.count) return;
-  const int limb = item / job.npoly;
-  const int poly = item - limb * job.npoly;
-  const int prime = job.limb_prime[limb];
-  const double p = tb.p[prime], pinv = tb.pinv[prime];
+  int limb, poly;
+  if (MODE == NTT_DIGIT) {
+    // The digit transforms read one source limb per (ciphertext, digit) for
+    // all L + 1 target primes.  Split the (source x prime) grid into 8
+    // blocks, one per XCD: two halves of the primes x four quarters of the
+    // sources.  Each XCD then keeps about half the primes' twiddle tables
+    // in its L2, reads each of its sources once (the half's transforms of
+    // a source are numbered consecutively) and every source is read twice.
+    const int x = blockIdx.x & 7, l = blockIdx.x >> 3;
+    const int ph = (job.nlimb + 1) >> 1;                 // primes in half 0
+    const int g = x & 1;
+    const int np = g ? job.nlimb - ph : ph;
+    const int sq = (job.npoly + 3) >> 2;                  // sources per quarter
+    const int src = (x >> 1) * sq + l / np;
+    if (l / np >= sq || src >= job.npoly) return;
+    poly = src;
+    limb = g * ph + l % np;
+  } else {
+    const int item = xcd_item(job.count);
+    if (item >= job.count) return;
+    limb = item / job.npoly;
+    poly = item - limb * job.npoly;
+  }
+  const int prime = cldi(job.limb_prime, limb);
+  const double p = cld(tb.p, prime), pinv = cld(tb.pinv, prime);
   const double* __restrict__ tw = tb.tw_fwd + (size_t)prime * tb.tw_len;
   double* dst = job.base + ((size_t)poly * job.poly_stride + (size_t)limb * S::N);
   const auto rd = make_rsrc(dst, S::N * 8);
@@ -217,17 +324,23 @@ k_ntt_fwd(NttJob job, Tables tb) {
     // third component, balanced mod q_j; D_j = canonical value in [0, q_j).
     const int ct = poly / job.digits;
     const int j = poly - ct * job.digits;
-    const double qj = tb.p[j];
+    const double qj = cld(tb.p, j);
     const auto rs = make_rsrc(job.src + (size_t)ct * job.src_ct_stride + (size_t)j * S::N, S::N * 8);
 #pragma unroll
-    for (int e = 0; e < S::E; ++e) {
+    for (int i = 0; i < S::E; ++i) {
+      const int e = brv_c(i, S::LOGE);
       double v = buf_load(rs, vo, e * S::T * 8);
       v = v < 0.0 ? v + qj : v;
       x[e] = reduce_bal(v, p, pinv);
     }
   } else {
+    // loads in bit-reversed element order: the first stage pairs e with
+    // e + E/2, so it can start as soon as the first two loads land
 #pragma unroll
-    for (int e = 0; e < S::E; ++e) x[e] = buf_load(rd, vo, e * S::T * 8);
+    for (int i = 0; i < S::E; ++i) {
+      const int e = brv_c(i, S::LOGE);
+      x[e] = buf_load(rd, vo, e * S::T * 8);
+    }
   }
 #pragma unroll
   for (int r = 0; r < S::ROUNDS; ++r) {
@@ -235,10 +348,10 @@ k_ntt_fwd(NttJob job, Tables tb) {
     fwd_round<LOGN>(x, r, tw, p, pinv);
   }
 #pragma unroll
-  for (int e = 0; e < S::E; ++e) buf_store(reduce_bal(x[e], p, pinv), rd, vo, e * S::T * 8);
+  for (int e = 0; e < S::E; ++e) buf_store(x[e], rd, vo, e * S::T * 8);
 }
 
-template <int LOGN>
+template <int LOGN, int MODE>
 __global__ void __launch_bounds__(NttShape<LOGN>::T)
 k_ntt_inv(NttJob job, Tables tb) {
   using S = NttShape<LOGN>;
@@ -247,40 +360,85 @@ k_ntt_inv(NttJob job, Tables tb) {
   if (item >= job.count) return;
   const int limb = item / job.npoly;
   const int poly = item - limb * job.npoly;
-  const int prime = job.limb_prime[limb];
-  const double p = tb.p[prime], pinv = tb.pinv[prime];
+  const int prime = cldi(job.limb_prime, limb);
+  const double p = cld(tb.p, prime), pinv = cld(tb.pinv, prime);
   const double* __restrict__ tw = tb.tw_inv + (size_t)prime * tb.tw_len;
   double* dst = job.base + ((size_t)poly * job.poly_stride + (size_t)limb * S::N);
   const auto rd = make_rsrc(dst, S::N * 8);
   const int tid = threadIdx.x;
   const unsigned vo = tid * 8;
   double x[S::E];
+  if constexpr (MODE == INV_TENSOR) {
+    // poly = ct * 3 + k: form the k-th tensor component from the operands'
+    // transforms (a in src, b in src_b, or b = a when src_b is null):
+    // d0 = a0 b0, d1 = a0 b1 + a1 b0, d2 = a1 b1.  Loads go in groups of 8
+    // elements, each group fenced on the previous one's results.
+    const int ct = poly / 3;
+    const int k = poly - ct * 3;
+    const size_t o0 = (size_t)ct * job.src_ct_stride + (size_t)limb * S::N;
+    const size_t o1 = o0 + job.src_ct_stride / 2;
+    const auto ra0 = make_rsrc(job.src + o0, S::N * 8);
+    const auto ra1 = make_rsrc(job.src + o1, S::N * 8);
+    const double* sb = job.src_b ? job.src_b : job.src;
+    const auto rb0 = make_rsrc(sb + o0, S::N * 8);
+    const auto rb1 = make_rsrc(sb + o1, S::N * 8);
+    unsigned v = vo;
 #pragma unroll
-  for (int e = 0; e < S::E; ++e) x[e] = buf_load(rd, vo, e * S::T * 8);
+    for (int g = 0; g < S::E; g += 8) {
+      if (g) asm volatile("" : "+v"(v) : "v"(x[g - 1]));
+#pragma unroll
+      for (int e = g; e < g + 8 && e < S::E; ++e) {
+        const unsigned so = e * S::T * 8;
+        if (k == 0) {
+          x[e] = mul_bal(buf_load(ra0, v, so), buf_load(rb0, v, so), p, pinv);
+        } else if (k == 2) {
+          x[e] = mul_bal(buf_load(ra1, v, so), buf_load(rb1, v, so), p, pinv);
+        } else {
+          const double a0 = buf_load(ra0, v, so), a1 = buf_load(ra1, v, so);
+          const double b0 = buf_load(rb0, v, so), b1 = buf_load(rb1, v, so);
+          x[e] = reduce_bal(mul_lazy(a0, b1, p, pinv) + mul_lazy(a1, b0, p, pinv), p, pinv);
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < S::E; ++e) x[e] = buf_load(rd, vo, e * S::T * 8);
+  }
 #pragma unroll
   for (int rr = 0; rr < S::ROUNDS; ++rr) {
     const int r = S::ROUNDS - 1 - rr;
     if (rr > 0) exchange<LOGN>(x, r + 1, r, lds);
     inv_round<LOGN>(x, r, tw, p, pinv);
   }
-  const double ninv = tb.ninv[prime];
 #pragma unroll
-  for (int e = 0; e < S::E; ++e) buf_store(mul_bal(x[e], ninv, p, pinv), rd, vo, e * S::T * 8);
+  for (int e = 0; e < S::E; ++e) buf_store(x[e], rd, vo, e * S::T * 8);
 }
 
 // ---------------------------------------------------------------- host ---
 
+// Workgroups per XCD for a launch (grid = 8 x this).
+static int per_xcd(const NttJob& job, int dir) {
+  if (dir == 2) {
+    const int ph = (job.nlimb + 1) >> 1;
+    const int sq = (job.npoly + 3) >> 2;
+    return sq * ph;
+  }
+  return (job.count + 7) >> 3;
+}
+
 template <int LOGN>
 static hipError_t launch_ntt(const NttJob& job, const Tables& tb, int dir, hipStream_t st) {
   using S = NttShape<LOGN>;
-  const int per = (job.count + 7) >> 3;
+  const int per = per_xcd(job, dir);
   dim3 grid(per * 8), block(S::T);
   if (dir == 0)
     hipLaunchKernelGGL((k_ntt_fwd<LOGN, NTT_INPLACE>), grid, block, 0, st, job, tb);
   else if (dir == 1)
-    hipLaunchKernelGGL((k_ntt_inv<LOGN>), grid, block, 0, st, job, tb);
-  else
+    hipLaunchKernelGGL((k_ntt_inv<LOGN, NTT_INPLACE>), grid, block, 0, st, job, tb);
+  else if (dir == 2)
     hipLaunchKernelGGL((k_ntt_fwd<LOGN, NTT_DIGIT>), grid, block, 0, st, job, tb);
+  else
+    hipLaunchKernelGGL((k_ntt_inv<LOGN, INV_TENSOR>), grid, block, 0, st, job, tb);
   return hipGetLastError();
 }
 

@@ -28,21 +28,26 @@ constexpr double LIFT_EPS = 0x1p-40;
 
 // Garner mixed-radix digits of X (canonical residues r, basis q_0..q_{L-1})
 // compared with those of (Q-1)/2: returns X > (Q-1)/2.
+// (Arguments by value: taking the address of the kernel's Tables argument
+// would copy it to scratch memory in every thread.)
 template <int L>
-__device__ __noinline__ bool mrc_greater_than_half(const double* r, const Tables& tb) {
+__device__ __noinline__ bool mrc_greater_than_half(const double* r, const double* __restrict__ P,
+                                                   const double* __restrict__ Pinv,
+                                                   const double* __restrict__ inv,
+                                                   const double* __restrict__ half) {
   double a[L];
 #pragma unroll
   for (int i = 0; i < L; ++i) {
-    const double p = tb.p[i], pinv = tb.pinv[i];
+    const double p = P[i], pinv = Pinv[i];
     double t = r[i];
     for (int j = 0; j < i; ++j) {
-      t = mul_bal(t - a[j], tb.mrc_inv[j * L + i], p, pinv);
+      t = mul_bal(t - a[j], inv[j * L + i], p, pinv);
       t = to_canonical(t, p);
     }
     a[i] = t;
   }
   for (int i = L - 1; i >= 0; --i) {
-    const double h = tb.mrc_half[i];
+    const double h = half[i];
     if (a[i] != h) return a[i] > h;
   }
   return false;
@@ -64,23 +69,23 @@ __global__ void __launch_bounds__(256) k_lift(int n, size_t n_poly, double* ext,
   double S = 0.0;
 #pragma unroll
   for (int i = 0; i < L; ++i) {
-    y[i] = mul_bal(base[(size_t)i * n], tb.q_hat_inv[i], tb.p[i], tb.pinv[i]);
-    S += y[i] * tb.recip[i];
+    y[i] = mul_bal(base[(size_t)i * n], cld(tb.q_hat_inv, i), cld(tb.p, i), cld(tb.pinv, i));
+    S += y[i] * cld(tb.recip, i);
   }
   double v = __builtin_rint(S);
   if (__builtin_fabs(S - v) > 0.5 - LIFT_EPS) {
     double r[L];
 #pragma unroll
-    for (int i = 0; i < L; ++i) r[i] = to_canonical(base[(size_t)i * n], tb.p[i]);
-    v = __builtin_floor(S) + (mrc_greater_than_half<L>(r, tb) ? 1.0 : 0.0);
+    for (int i = 0; i < L; ++i) r[i] = to_canonical(base[(size_t)i * n], cld(tb.p, i));
+    v = __builtin_floor(S) + (mrc_greater_than_half<L>(r, tb.p, tb.pinv, tb.mrc_inv, tb.mrc_half) ? 1.0 : 0.0);
     atomicAdd(tb.margin, 1ull);
   }
 #pragma unroll
   for (int k = 0; k < LB; ++k) {
-    const double b = tb.p[L + k], binv = tb.pinv[L + k];
-    double acc = -v * tb.Q_b[k];
+    const double b = cld(tb.p, L + k), binv = cld(tb.pinv, L + k);
+    double acc = -v * cld(tb.Q_b, k);
 #pragma unroll
-    for (int i = 0; i < L; ++i) acc += mul_lazy(y[i], tb.q_hat_b[k * L + i], b, binv);
+    for (int i = 0; i < L; ++i) acc += mul_lazy(y[i], cld(tb.q_hat_b, k * L + i), b, binv);
     base[(size_t)(L + k) * n] = reduce_bal(acc, b, binv);
   }
 }
@@ -101,75 +106,39 @@ __global__ void __launch_bounds__(256) k_scale(int n, size_t n_poly, double* dt,
   double S = 0.0;
 #pragma unroll
   for (int i = 0; i < L; ++i) {
-    y[i] = mul_bal(base[(size_t)i * n], tb.t_qhinv[i], tb.p[i], tb.pinv[i]);
-    S += y[i] * tb.recip[i];
+    y[i] = mul_bal(base[(size_t)i * n], cld(tb.t_qhinv, i), cld(tb.p, i), cld(tb.pinv, i));
+    S += y[i] * cld(tb.recip, i);
   }
   double v = __builtin_rint(S);
   if (__builtin_fabs(S - v) > 0.5 - LIFT_EPS) {
     double r[L];
 #pragma unroll
     for (int i = 0; i < L; ++i)
-      r[i] = to_canonical(mul_bal(base[(size_t)i * n], tb.t_q[i], tb.p[i], tb.pinv[i]), tb.p[i]);
-    v = __builtin_floor(S) + (mrc_greater_than_half<L>(r, tb) ? 1.0 : 0.0);
+      r[i] = to_canonical(mul_bal(base[(size_t)i * n], cld(tb.t_q, i), cld(tb.p, i), cld(tb.pinv, i)), cld(tb.p, i));
+    v = __builtin_floor(S) + (mrc_greater_than_half<L>(r, tb.p, tb.pinv, tb.mrc_inv, tb.mrc_half) ? 1.0 : 0.0);
     atomicAdd(tb.margin, 1ull);
   }
   double w[LB];
   double S2 = 0.0;
 #pragma unroll
   for (int k = 0; k < LB; ++k) {
-    const double b = tb.p[L + k], binv = tb.pinv[L + k];
-    double acc = mul_lazy(base[(size_t)(L + k) * n], tb.c1[k], b, binv) + v * tb.b_hat_inv[k];
+    const double b = cld(tb.p, L + k), binv = cld(tb.pinv, L + k);
+    double acc = mul_lazy(base[(size_t)(L + k) * n], cld(tb.c1, k), b, binv) + v * cld(tb.b_hat_inv, k);
 #pragma unroll
-    for (int i = 0; i < L; ++i) acc -= mul_lazy(y[i], tb.c2[k * L + i], b, binv);
+    for (int i = 0; i < L; ++i) acc -= mul_lazy(y[i], cld(tb.c2, k * L + i), b, binv);
     w[k] = reduce_bal(acc, b, binv);
-    S2 += w[k] * tb.recip[L + k];
+    S2 += w[k] * cld(tb.recip, L + k);
   }
   const double v2 = __builtin_rint(S2);
   if (__builtin_fabs(S2 - v2) > 0.25) atomicAdd(tb.fault, 1ull);
 #pragma unroll
   for (int i = 0; i < L; ++i) {
-    const double q = tb.p[i], qinv = tb.pinv[i];
-    double acc = -v2 * tb.B_q[i];
+    const double q = cld(tb.p, i), qinv = cld(tb.pinv, i);
+    double acc = -v2 * cld(tb.B_q, i);
 #pragma unroll
-    for (int k = 0; k < LB; ++k) acc += mul_lazy(w[k], tb.b_hat_q[i * LB + k], q, qinv);
+    for (int k = 0; k < LB; ++k) acc += mul_lazy(w[k], cld(tb.b_hat_q, i * LB + k), q, qinv);
     base[(size_t)i * n] = reduce_bal(acc, q, qinv);
   }
-}
-
-// ---------------------------------------------------------------- tensor ---
-
-// NTT domain, all L+LB limbs: d0 = a0 b0, d1 = a0 b1 + a1 b0, d2 = a1 b1.
-// ext_b == ext_a (or nullptr) squares.  Prime index of limb l is l.
-template <int L>
-__global__ void __launch_bounds__(256) k_tensor(int n, int n_ct, const double* ext_a,
-                                                const double* ext_b, double* dt, Tables tb) {
-  constexpr int W = 2 * L + 1;
-  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= (size_t)n_ct * W * n) return;
-  const size_t row = gid / n;               // ct * W + limb
-  const int c = (int)(gid - row * n);
-  const int ct = (int)(row / W);
-  const int limb = (int)(row - (size_t)ct * W);
-  const double p = tb.p[limb], pinv = tb.pinv[limb];
-  const size_t ia0 = ((size_t)(ct * 2 + 0) * W + limb) * n + c;
-  const size_t ia1 = ((size_t)(ct * 2 + 1) * W + limb) * n + c;
-  const double a0 = ext_a[ia0], a1 = ext_a[ia1];
-  double d0, d1, d2;
-  if (ext_b == nullptr) {
-    d0 = mul_bal(a0, a0, p, pinv);
-    d1 = mul_bal(a0 + a0, a1, p, pinv);
-    d2 = mul_bal(a1, a1, p, pinv);
-  } else {
-    const double b0 = ext_b[ia0], b1 = ext_b[ia1];
-    d0 = mul_bal(a0, b0, p, pinv);
-    d1 = reduce_bal(mul_lazy(a0, b1, p, pinv) + mul_lazy(a1, b0, p, pinv), p, pinv);
-    d2 = mul_bal(a1, b1, p, pinv);
-  }
-  const size_t o = ((size_t)(ct * 3) * W + limb) * n + c;
-  const size_t ps = (size_t)W * n;
-  dt[o] = d0;
-  dt[o + ps] = d1;
-  dt[o + 2 * ps] = d2;
 }
 
 // ---------------------------------------------------------- key switching ---
@@ -186,7 +155,7 @@ __global__ void __launch_bounds__(256) k_ks_mac(int n, int n_ct, const double* d
   const int i = (int)(gid / n);
   const int c = (int)(gid - (size_t)i * n);
   const int prime = i < L ? i : 2 * L + 1;
-  const double p = tb.p[prime], pinv = tb.pinv[prime];
+  const double p = cld(tb.p, prime), pinv = cld(tb.pinv, prime);
   for (int c0 = 0; c0 < n_ct; c0 += CH) {
     double a0[CH], a1[CH];
 #pragma unroll
@@ -214,7 +183,8 @@ __global__ void __launch_bounds__(256) k_ks_mac(int n, int n_ct, const double* d
 }
 
 // new ct (into ext limbs 0..L-1) = e_b + (acc_b - [acc_b]_P) * P^-1, where
-// [acc_b]_P is the balanced (= centred) residue of the P limb.
+// [acc_b]_P is the balanced (= centred) residue of the P limb.  Since
+// mul_lazy(aP, .) needs |aP| < 2p only, P may exceed q_i (both < 2^49).
 template <int L>
 __global__ void __launch_bounds__(256) k_moddown(int n, int n_ct, const double* acc,
                                                  const double* dt, double* ext, Tables tb) {
@@ -227,13 +197,17 @@ __global__ void __launch_bounds__(256) k_moddown(int n, int n_ct, const double* 
   const size_t ct = cb >> 1;
   const int b = (int)(cb & 1);
   const double* a = acc + cb * (size_t)K * n + c;
-  const double aP = a[(size_t)L * n];
+  // acc is inverse-transform output (N times the sum): the centred residue
+  // mod P is [N^-1 acc_P]_P
+  const int ip = 2 * L + 1;
+  const double aP = mul_bal(a[(size_t)L * n], cld(tb.ninv, ip), cld(tb.p, ip), cld(tb.pinv, ip));
   const double* e = dt + ((ct * 3 + b) * (size_t)W) * n + c;
   double* o = ext + cb * (size_t)W * n + c;
 #pragma unroll
   for (int i = 0; i < L; ++i) {
-    const double q = tb.p[i], qinv = tb.pinv[i];
-    const double r = mul_lazy(a[(size_t)i * n] - aP, tb.P_inv_q[i], q, qinv);
+    const double q = cld(tb.p, i), qinv = cld(tb.pinv, i);
+    const double r = mul_lazy(a[(size_t)i * n], cld(tb.NP_inv_q, i), q, qinv) -
+                     mul_lazy(aP, cld(tb.P_inv_q, i), q, qinv);
     o[(size_t)i * n] = reduce_bal(e[(size_t)i * n] + r, q, qinv);
   }
 }
@@ -250,7 +224,7 @@ __global__ void __launch_bounds__(256) k_sub_to_ext(int n, int L, int n_ct, cons
   const size_t ct = gid / per_ct;
   const size_t r = gid - ct * per_ct;       // (b * L + i) * n + c
   const int i = (int)((r / n) % L);
-  const double p = tb.p[i], pinv = tb.pinv[i];
+  const double p = cld(tb.p, i), pinv = cld(tb.pinv, i);
   const double xv = (double)x[gid];
   const double yv = (double)y[y_bcast ? r : gid];
   const size_t bi = r / n;                  // b * L + i
@@ -264,7 +238,7 @@ __global__ void __launch_bounds__(256) k_sub_i64(int n, int L, size_t total, con
   const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= total) return;
   const int i = (int)((gid / n) % L);
-  const double p = tb.p[i];
+  const double p = cld(tb.p, i);
   double z = (double)x[gid] - (double)y[gid];
   out[gid] = (int64_t)(z < 0.0 ? z + p : z);
 }
@@ -283,7 +257,7 @@ __global__ void __launch_bounds__(256) k_i64_to_polys(int n, int L, int npoly, s
   const size_t cp = row / L;
   const size_t ct = cp / npoly;
   const int poly = (int)(cp - ct * npoly);
-  out[ct * ct_stride + poly * poly_stride + (size_t)i * n + c] = from_u64(in[gid], tb.p[i]);
+  out[ct * ct_stride + poly * poly_stride + (size_t)i * n + c] = from_u64(in[gid], cld(tb.p, i));
 }
 
 // balanced doubles -> canonical int64 [n_ct][npoly][L][N].  With
@@ -300,11 +274,11 @@ __global__ void __launch_bounds__(256) k_polys_to_i64(int n, int L, int npoly, s
   const size_t cp = row / L;
   const size_t ct = cp / npoly;
   const int poly = (int)(cp - ct * npoly);
-  const double p = tb.p[i], pinv = tb.pinv[i];
+  const double p = cld(tb.p, i), pinv = cld(tb.pinv, i);
   double v = in[ct * ct_stride + poly * poly_stride + (size_t)i * n + c];
   if (negate_delta) {
     v = -v;
-    if (poly == 0 && c == 0) v = reduce_bal(v + tb.delta_q[i], p, pinv);
+    if (poly == 0 && c == 0) v = reduce_bal(v + cld(tb.delta_q, i), p, pinv);
   }
   out[gid] = to_i64(v, p);
 }
@@ -318,7 +292,7 @@ __global__ void __launch_bounds__(256) k_i64_rows(size_t total, int n, const int
   if (gid >= total) return;
   const size_t row = gid / n;
   const int prime = row_prime[row % nprime_rows];
-  out[gid] = from_u64(in[gid], tb.p[prime]);
+  out[gid] = from_u64(in[gid], cld(tb.p, prime));
 }
 
 __device__ __forceinline__ int brv(int x, int bits) {
@@ -342,7 +316,7 @@ __global__ void __launch_bounds__(256) k_ntt_order(size_t total, int log2n, int 
   const int E = 1 << loge;
   const int T = n >> loge;
   const int pos = (i & (E - 1)) * T + (i >> loge);
-  out[gid] = to_i64(in[row * (size_t)n + pos], tb.p[prime]);
+  out[gid] = to_i64(in[row * (size_t)n + pos], cld(tb.p, prime));
 }
 
 // ---------------------------------------------------------------- host ---
@@ -379,25 +353,12 @@ hipError_t run_scale(const Dims& d, double* dt, const Tables& tb, hipStream_t st
   return hipGetLastError();
 }
 
-hipError_t run_tensor(const Dims& d, const double* ext_a, const double* ext_b, double* dt,
-                      const Tables& tb, hipStream_t st) {
-  const size_t total = (size_t)d.n_ct * (2 * d.L + 1) * d.n;
-  switch (d.L) {
-#define C_(L_) \
-  case L_: hipLaunchKernelGGL(k_tensor<L_>, grid_for(total), dim3(256), 0, st, d.n, d.n_ct, ext_a, ext_b, dt, tb); break;
-    NSHE_L_CASES(C_)
-#undef C_
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
 hipError_t run_ks_mac(const Dims& d, const double* dig, const double* evk, double* acc,
                       const Tables& tb, hipStream_t st) {
   const size_t total = (size_t)(d.L + 1) * d.n;
   switch (d.L) {
 #define C_(L_) \
-  case L_: hipLaunchKernelGGL((k_ks_mac<L_, 8>), grid_for(total), dim3(256), 0, st, d.n, d.n_ct, dig, evk, acc, tb); break;
+  case L_: hipLaunchKernelGGL((k_ks_mac<L_, 16>), grid_for(total), dim3(256), 0, st, d.n, d.n_ct, dig, evk, acc, tb); break;
     NSHE_L_CASES(C_)
 #undef C_
     default: return hipErrorInvalidValue;
