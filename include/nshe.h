@@ -115,9 +115,10 @@ int nshe_ctx_destroy(nshe_ctx* ctx);
 int nshe_ctx_info(const nshe_ctx* ctx, nshe_info* out);
 
 /* Install the relinearization key (Sec. 2.1.3).  Copies and transforms
- * `evk_dev` (layout above) into context-owned memory on `stream`; the
- * caller may free `evk_dev` once the stream has synchronised.  Allocates the
- * context-owned key store on first use. */
+ * `evk_dev` (layout above) into context-owned memory on `stream` and waits
+ * for it; `evk_dev` may be freed on return.  Allocates the context-owned
+ * key store on first use and a temporary of the same size during the call
+ * (set-up, not the evaluation path). */
 int nshe_set_relin_key(nshe_ctx* ctx, const int64_t* evk_dev, void* stream);
 
 /* Device scratch needed by the evaluation calls for n_ct ciphertexts. */
@@ -180,7 +181,8 @@ int nshe_eq_mask_batched(nshe_ctx* ctx, const nshe_item* items_host,
  * data-prime limbs (int64 [n_poly][L][N], residues in [0, q_i)), out holds
  * the evaluations at psi_i^(2j+1), j = 0..N-1, in natural j order, where
  * psi_i = g^((q_i - 1) / 2N) for the smallest primitive root g of q_i.
- * inverse != 0 applies the inverse transform (evaluations -> coefficients). */
+ * The workspace must hold 2 * n_poly * L * N doubles.  Only the forward
+ * transform is exposed: inverse != 0 returns NSHE_EINVAL. */
 int nshe_ntt(nshe_ctx* ctx, const int64_t* in_dev, int64_t* out_dev,
              int n_poly, int inverse, void* ws_dev, size_t ws_bytes,
              void* stream);

@@ -183,7 +183,7 @@ class Context:
         polys = polys.contiguous()
         n = polys.shape[0]
         out = torch.empty_like(polys)
-        ws = torch.empty(n * self.L * self.n * 8, dtype=torch.uint8, device=self.device)
+        ws = torch.empty(2 * n * self.L * self.n * 8, dtype=torch.uint8, device=self.device)
         _lib.check(self._lib.nshe_ntt(self._h, _ptr(polys), _ptr(out), n, 0, _ptr(ws), ws.numel(),
                                       _stream()))
         return out

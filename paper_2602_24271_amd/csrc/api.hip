@@ -197,24 +197,31 @@ static double ntt_work(const nshe_ctx* c, int polys_times_limbs) {
 // ------------------------------------------------------------- workspace
 
 struct Ws {
-  double* ext;   // [n_ct][2][W][N]
+  double* ext;   // [n_ct][2][W][N]  current ciphertext (limbs 0..L-1) and its lift
+  double* fx;    // [n_ct][2][W][N]  the operand's transform
   double* dt;    // [n_ct][3][W][N]
-  double* dig;   // [n_ct][L][K][N]  (also the second operand's extension)
+  double* dig;   // [n_ct][L][K][N]  (a second operand's lift and transform first)
   double* acc;   // [n_ct][2][K][N]
 };
 
+static size_t dig_limbs(const nshe_ctx* c) {
+  const size_t W = W_of(c), K = c->L + 1, L = c->L;
+  return std::max(L * K, 4 * W);
+}
+
 static size_t ws_doubles(const nshe_ctx* c, int n_ct) {
-  const size_t W = W_of(c), K = c->L + 1, L = c->L, N = c->n;
-  const size_t dig = std::max(L * K, 2 * W);
-  return (size_t)n_ct * N * (2 * W + 3 * W + dig + 2 * K);
+  const size_t W = W_of(c), K = c->L + 1, N = c->n;
+  return (size_t)n_ct * N * (2 * W + 2 * W + 3 * W + dig_limbs(c) + 2 * K);
 }
 
 static Ws carve(const nshe_ctx* c, void* ws, int n_ct) {
-  const size_t W = W_of(c), K = c->L + 1, L = c->L, N = c->n;
-  const size_t dig = std::max(L * K, 2 * W);
+  const size_t W = W_of(c), N = c->n;
+  const size_t dig = dig_limbs(c);
   double* p = static_cast<double*>(ws);
   Ws w;
   w.ext = p;
+  p += (size_t)n_ct * 2 * W * N;
+  w.fx = p;
   p += (size_t)n_ct * 2 * W * N;
   w.dt = p;
   p += (size_t)n_ct * 3 * W * N;
@@ -234,9 +241,11 @@ static int check_ws(const nshe_ctx* c, void* ws, size_t bytes, int n_ct) {
 
 // ---------------------------------------------------------- level pieces
 
-static int ntt_job_ext(nshe_ctx* c, double* base, int npoly, int dir, hipStream_t st) {
+static int ntt_job_ext(nshe_ctx* c, double* base, double* out, int npoly, int dir,
+                       hipStream_t st) {
   NttJob j{};
   j.base = base;
+  j.out = out;
   j.poly_stride = (size_t)W_of(c) * c->n;
   j.npoly = npoly;
   j.nlimb = W_of(c);
@@ -247,9 +256,11 @@ static int ntt_job_ext(nshe_ctx* c, double* base, int npoly, int dir, hipStream_
   return NSHE_OK;
 }
 
-static int ntt_job_ks(nshe_ctx* c, double* base, int npoly, int dir, hipStream_t st) {
+static int ntt_job_ks(nshe_ctx* c, double* base, double* out, int npoly, int dir,
+                      hipStream_t st) {
   NttJob j{};
   j.base = base;
+  j.out = out;
   j.poly_stride = (size_t)(c->L + 1) * c->n;
   j.npoly = npoly;
   j.nlimb = c->L + 1;
@@ -260,19 +271,20 @@ static int ntt_job_ks(nshe_ctx* c, double* base, int npoly, int dir, hipStream_t
   return NSHE_OK;
 }
 
-// Lift + forward NTT of the ciphertexts held in ext (limbs 0..L-1).
-static int prepare_operand(nshe_ctx* c, double* ext, int n_ct, hipStream_t st) {
+// Lift the ciphertexts held in ext (limbs 0..L-1) and transform all limbs
+// into fx.
+static int prepare_operand(nshe_ctx* c, double* ext, double* fx, int n_ct, hipStream_t st) {
   Dims d{c->n, c->L, c->LB, n_ct};
   {
     Prof pf(c, K_LIFT, st, 2.0 * n_ct * c->n);
     HIPCHK(run_lift(d, ext, c->tb, st));
   }
-  return ntt_job_ext(c, ext, n_ct * 2, 0, st);
+  return ntt_job_ext(c, ext, fx, n_ct * 2, 0, st);
 }
 
-// ext (NTT domain, operands) -> dt limbs 0..L-1 of the 3 components:
-// [round(t d_k / Q)]_Q, coefficient domain.
-static int tensor_scale(nshe_ctx* c, const Ws& w, const double* ext_b, int n_ct, hipStream_t st) {
+// fx (NTT domain, operands; the second in fx_b, or squaring) -> dt limbs
+// 0..L-1 of the 3 components: [round(t d_k / Q)]_Q, coefficient domain.
+static int tensor_scale(nshe_ctx* c, const Ws& w, const double* fx_b, int n_ct, hipStream_t st) {
   Dims d{c->n, c->L, c->LB, n_ct};
   {
     // the tensor product is formed while the inverse transform loads
@@ -283,8 +295,8 @@ static int tensor_scale(nshe_ctx* c, const Ws& w, const double* ext_b, int n_ct,
     j.nlimb = W_of(c);
     j.limb_prime = c->lp_ext;
     j.count = j.npoly * j.nlimb;
-    j.src = w.ext;
-    j.src_b = ext_b;
+    j.src = w.fx;
+    j.src_b = fx_b;
     j.src_ct_stride = (size_t)2 * W_of(c) * c->n;
     Prof pf(c, K_NTT_INV_TENSOR, st, ntt_work(c, j.count));
     HIPCHK(run_ntt(c->log2n, j, c->tb, 3, st));
@@ -301,6 +313,7 @@ static int relin(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st) {
   Dims d{c->n, c->L, c->LB, n_ct};
   NttJob j{};
   j.base = w.dig;
+  j.out = w.dig;
   j.poly_stride = (size_t)(c->L + 1) * c->n;
   j.npoly = n_ct * c->L;
   j.nlimb = c->L + 1;
@@ -317,7 +330,7 @@ static int relin(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st) {
     Prof pf(c, K_KS_MAC, st, (double)n_ct * c->L * 2 * (c->L + 1) * c->n);
     HIPCHK(run_ks_mac(d, w.dig, c->evk, w.acc, c->tb, st));
   }
-  int rc = ntt_job_ks(c, w.acc, n_ct * 2, 1, st);
+  int rc = ntt_job_ks(c, w.acc, nullptr, n_ct * 2, 1, st);
   if (rc) return rc;
   {
     Prof pf(c, K_MODDOWN, st, 2.0 * n_ct * c->n);
@@ -328,7 +341,7 @@ static int relin(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st) {
 
 // One squaring level on the ciphertexts in ext.
 static int square_level(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st) {
-  int rc = prepare_operand(c, w.ext, n_ct, st);
+  int rc = prepare_operand(c, w.ext, w.fx, n_ct, st);
   if (rc) return rc;
   rc = tensor_scale(c, w, nullptr, n_ct, st);
   if (rc) return rc;
@@ -441,6 +454,17 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
     h_ninv[i] = bal(invmod((u64)n, prime(i)), prime(i));
   }
   std::vector<double> tw_f((size_t)K * c->tw_len, 0.0), tw_i((size_t)K * c->tw_len, 0.0);
+  // N = 2^15: twiddles of the two half-limb forward sub-transforms (2^14
+  // points each; the shape of the 2^14 transform)
+  int h_loge = 0, h_r0 = 0, h_rounds = 0, h_len = 0;
+  if (c->log2n == 15) {
+    h_rounds = ntt_rounds(14, &h_loge, &h_r0);
+    for (int r = 0; r < h_rounds; ++r) {
+      const int ss = r == 0 ? 0 : h_r0 + (r - 1) * h_loge;
+      h_len += (1 << ss) << h_loge;
+    }
+  }
+  std::vector<double> tw_h((size_t)K * 2 * h_len, 0.0), tw_h0(K, 0.0);
   {
     const int E = 1 << c->loge;
     std::vector<u64> pbr(n), pibr(n);
@@ -457,6 +481,26 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
       for (int i = 0; i < n; ++i) {
         pbr[i] = pw[brv(i, c->log2n)];
         pibr[i] = pwi[brv(i, c->log2n)];
+      }
+      if (h_len) {
+        tw_h0[k] = bal(pbr[1], p);
+        const int E = 1 << h_loge;
+        for (int hh = 0; hh < 2; ++hh) {
+          int off = 0;
+          for (int r = 0; r < h_rounds; ++r) {
+            const int ss = r == 0 ? 0 : h_r0 + (r - 1) * h_loge;
+            const int R = r == 0 ? h_r0 : h_loge;
+            for (int u = 0; u < (1 << ss); ++u)
+              for (int kk = 0; kk < R; ++kk)
+                for (int j = 0; j < (1 << kk); ++j) {
+                  const int idx = (1 << (ss + kk)) * (2 + hh) + (u << kk) + j;
+                  const size_t o = ((size_t)k * 2 + hh) * h_len + off + (size_t)u * E +
+                                   (1 << kk) + j;
+                  tw_h[o] = bal(pbr[idx], p);
+                }
+            off += (1 << ss) * E;
+          }
+        }
       }
       int off = 0;
       for (int r = 0; r < c->rounds; ++r) {
@@ -532,7 +576,8 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
       {&c2, &c->tb.c2},           {&b_hat_inv, &c->tb.b_hat_inv}, {&b_hat_q, &c->tb.b_hat_q},
       {&B_q, &c->tb.B_q},         {&P_inv_q, &c->tb.P_inv_q}, {&NP_inv_q, &c->tb.NP_inv_q},
       {&delta_q, &c->tb.delta_q},
-      {&mrc_inv, &c->tb.mrc_inv}, {&mrc_half, &c->tb.mrc_half}};
+      {&mrc_inv, &c->tb.mrc_inv}, {&mrc_half, &c->tb.mrc_half}, {&tw_h, &c->tb.tw_half},
+      {&tw_h0, &c->tb.tw_half0}};
   size_t total = 0;
   std::vector<size_t> offs;
   for (auto& pp : parts) {
@@ -557,6 +602,11 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
                   hipMemcpyHostToDevice);
   }
   c->tb.tw_len = c->tw_len;
+  c->tb.tw_half_len = h_len;
+  if (!h_len) {
+    c->tb.tw_half = nullptr;
+    c->tb.tw_half0 = nullptr;
+  }
   c->tb.margin = reinterpret_cast<unsigned long long*>(base + off_counters);
   c->tb.fault = c->tb.margin + 1;
   if (e == hipSuccess) e = hipMemset(base + off_counters, 0, 256);
@@ -619,8 +669,17 @@ int nshe_set_relin_key(nshe_ctx* c, const int64_t* evk_dev, void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
   const size_t rows = (size_t)c->L * 2 * (c->L + 1);
   if (!c->evk) HIPCHK(hipMalloc(&c->evk, rows * c->n * sizeof(double)));
-  HIPCHK(run_i64_to_dbl_limbs(rows, c->n, evk_dev, c->evk, c->lp_ks, c->L + 1, c->tb, st));
-  int rc = ntt_job_ks(c, c->evk, c->L * 2, 0, st);
+  double* tmp = nullptr;
+  HIPCHK(hipMalloc(&tmp, rows * c->n * sizeof(double)));
+  int rc = NSHE_OK;
+  hipError_t e = run_i64_to_dbl_limbs(rows, c->n, evk_dev, tmp, c->lp_ks, c->L + 1, c->tb, st);
+  if (e != hipSuccess) rc = fail(NSHE_EDEVICE, std::string("key conversion: ") + hipGetErrorString(e));
+  if (!rc) rc = ntt_job_ks(c, tmp, c->evk, c->L * 2, 0, st);
+  if (!rc) {
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) rc = fail(NSHE_EDEVICE, std::string("key transform: ") + hipGetErrorString(e));
+  }
+  (void)hipFree(tmp);
   if (rc) return rc;
   c->has_key = true;
   return NSHE_OK;
@@ -669,15 +728,20 @@ int nshe_square_relin(nshe_ctx* c, const int64_t* in, int64_t* out, int n_ct, vo
   return NSHE_OK;
 }
 
+// The second operand's transform sits in the digit region after its lift.
+static double* fx_second(const nshe_ctx* c, const Ws& w, int n_ct) {
+  return w.dig + (size_t)n_ct * 2 * W_of(c) * c->n;
+}
+
 static int load_two(nshe_ctx* c, const Ws& w, const int64_t* a, const int64_t* b, int n_ct,
                     hipStream_t st) {
   Dims d{c->n, c->L, c->LB, n_ct};
   const size_t W = W_of(c), N = c->n;
   HIPCHK(run_i64_to_polys(d, a, 2, w.ext, 2 * W * N, W * N, c->tb, st));
   HIPCHK(run_i64_to_polys(d, b, 2, w.dig, 2 * W * N, W * N, c->tb, st));
-  int rc = prepare_operand(c, w.ext, n_ct, st);
+  int rc = prepare_operand(c, w.ext, w.fx, n_ct, st);
   if (rc) return rc;
-  return prepare_operand(c, w.dig, n_ct, st);
+  return prepare_operand(c, w.dig, fx_second(c, w, n_ct), n_ct, st);
 }
 
 int nshe_mul_relin(nshe_ctx* c, const int64_t* a, const int64_t* b, int64_t* out, int n_ct,
@@ -692,7 +756,7 @@ int nshe_mul_relin(nshe_ctx* c, const int64_t* a, const int64_t* b, int64_t* out
   const size_t W = W_of(c), N = c->n;
   rc = load_two(c, w, a, b, n_ct, st);
   if (rc) return rc;
-  rc = tensor_scale(c, w, w.dig, n_ct, st);
+  rc = tensor_scale(c, w, fx_second(c, w, n_ct), n_ct, st);
   if (rc) return rc;
   rc = relin(c, w, n_ct, st);
   if (rc) return rc;
@@ -712,7 +776,7 @@ int nshe_multiply(nshe_ctx* c, const int64_t* a, const int64_t* b, int64_t* out3
   const size_t W = W_of(c), N = c->n;
   rc = load_two(c, w, a, b, n_ct, st);
   if (rc) return rc;
-  rc = tensor_scale(c, w, w.dig, n_ct, st);
+  rc = tensor_scale(c, w, fx_second(c, w, n_ct), n_ct, st);
   if (rc) return rc;
   HIPCHK(run_polys_to_i64(d, w.dt, 3, 3 * W * N, W * N, out3, 0, c->tb, st));
   return NSHE_OK;
@@ -896,22 +960,24 @@ int nshe_ntt(nshe_ctx* c, const int64_t* in, int64_t* out, int n_poly, int inver
   if (!in || !out || !ws) return fail(NSHE_EINVAL, "null buffer");
   if (n_poly < 0) return fail(NSHE_ESHAPE, "n_poly < 0");
   if (n_poly == 0) return NSHE_OK;
-  const size_t need = (size_t)n_poly * c->L * c->n * sizeof(double);
-  if (ws_bytes < need) return fail(NSHE_ENOMEM, "workspace too small");
+  const size_t need = 2 * (size_t)n_poly * c->L * c->n * sizeof(double);
+  if (ws_bytes < need) return fail(NSHE_ENOMEM, "workspace too small (2 n_poly L N doubles)");
   if (inverse) return fail(NSHE_EINVAL, "inverse debug transform not provided");
   if (set_device(c)) return NSHE_EDEVICE;
   hipStream_t st = static_cast<hipStream_t>(stream);
   double* buf = static_cast<double*>(ws);
   HIPCHK(run_i64_to_dbl_limbs((size_t)n_poly * c->L, c->n, in, buf, c->lp_ext, c->L, c->tb, st));
+  double* res = buf + (size_t)n_poly * c->L * c->n;
   NttJob j{};
   j.base = buf;
+  j.out = res;
   j.poly_stride = (size_t)c->L * c->n;
   j.npoly = n_poly;
   j.nlimb = c->L;
   j.limb_prime = c->lp_ext;
   j.count = n_poly * c->L;
   HIPCHK(run_ntt(c->log2n, j, c->tb, 0, st));
-  HIPCHK(run_ntt_order(c->log2n, (size_t)n_poly * c->L, buf, out, c->lp_ext, c->L, 1, c->tb, st));
+  HIPCHK(run_ntt_order(c->log2n, (size_t)n_poly * c->L, res, out, c->lp_ext, c->L, 1, c->tb, st));
   return NSHE_OK;
 }
 

@@ -22,6 +22,10 @@ struct Tables {
   const double* tw_fwd;      // [K][tw_len]
   const double* tw_inv;      // [K][tw_len]
   int tw_len;
+  // N = 2^15 only: forward transform split over two half-limb workgroups
+  const double* tw_half;     // [K][2][tw_half_len] sub-transform twiddles per half
+  const double* tw_half0;    // [K] psi^(2^14), the stage-0 twiddle
+  int tw_half_len;
   // centred lift Q -> B
   const double* q_hat_inv;   // [L]      [(Q/q_i)^-1]_{q_i}
   const double* q_hat_b;     // [LB][L]  [Q/q_i]_{b_k}
@@ -47,10 +51,11 @@ struct Tables {
   unsigned long long* fault;   // B->Q lift outside its proven range (never)
 };
 
-enum { NTT_INPLACE = 0, NTT_DIGIT = 1, INV_TENSOR = 2 };
+enum { NTT_INPLACE = 0, NTT_DIGIT = 1, INV_TENSOR = 2, INV_TENSOR2 = 3 };
 
 struct NttJob {
-  double* base;              // first limb of poly 0
+  double* base;              // first limb of poly 0 (input of in-place kinds)
+  double* out;               // output base, same strides (null: in place)
   size_t poly_stride;        // doubles between consecutive polys
   int npoly;                 // polys in the launch
   int nlimb;                 // limbs per poly transformed

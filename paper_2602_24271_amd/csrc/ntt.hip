@@ -218,26 +218,40 @@ struct Twiddles {
   }
 };
 
-// Round r of the forward transform on this thread's registers.
+// Round r of the forward transform on this thread's registers.  Later
+// rounds fetch one stage ahead: stage k+1's twiddles are issued at the start
+// of stage k (fenced on stage k-1's results, so no further), hiding the
+// load latency behind one stage of butterflies.
 template <int LOGN>
 __device__ __forceinline__ void fwd_round(double (&x)[NttShape<LOGN>::E], int r,
                                           const double* __restrict__ tw, double p, double pinv) {
   using S = NttShape<LOGN>;
+  constexpr int HALF = S::E / 2;
   const Twiddles<LOGN> T(tw, r);
   const int R = S::stages(r);
+  double cur[HALF], nxt[HALF];
+  if (r > 0) cur[0] = buf_load(T.tr, T.tvo, 8);
 #pragma unroll
   for (int k = 0; k < S::LOGE; ++k) {
     if (k >= R) break;
     const int eb = S::LOGE - 1 - k;
-    const unsigned o = r == 0 ? 0u : T.stage_offset(x[0]);
+    if (r > 0 && k + 1 < R) {
+      const unsigned o = T.stage_offset(x[0]);
+#pragma unroll
+      for (int j = 0; j < (2 << k); ++j) nxt[j] = buf_load(T.tr, o, ((2 << k) + j) * 8);
+    }
 #pragma unroll
     for (int j = 0; j < (1 << k); ++j) {
-      const double w = r == 0 ? cld(T.t0, S::tw_off(0) + (1 << k) + j) : buf_load(T.tr, o, ((1 << k) + j) * 8);
+      const double w = r == 0 ? cld(T.t0, S::tw_off(0) + (1 << k) + j) : cur[j];
 #pragma unroll
       for (int b = 0; b < (1 << eb); ++b) {
         const int e = (j << (eb + 1)) | b;
         ct_bfly(x[e], x[e | (1 << eb)], w, p, pinv);
       }
+    }
+    if (r > 0 && k + 1 < R) {
+#pragma unroll
+      for (int j = 0; j < (2 << k); ++j) cur[j] = nxt[j];
     }
   }
 #pragma unroll
@@ -248,17 +262,27 @@ template <int LOGN>
 __device__ __forceinline__ void inv_round(double (&x)[NttShape<LOGN>::E], int r,
                                           const double* __restrict__ tw, double p, double pinv) {
   using S = NttShape<LOGN>;
+  constexpr int HALF = S::E / 2;
   const Twiddles<LOGN> T(tw, r);
   const int R = S::stages(r);
+  double cur[HALF], nxt[HALF];
+  if (r > 0) {
+#pragma unroll
+    for (int j = 0; j < (1 << (R - 1)); ++j) cur[j] = buf_load(T.tr, T.tvo, ((1 << (R - 1)) + j) * 8);
+  }
 #pragma unroll
   for (int kk = 0; kk < S::LOGE; ++kk) {
     const int k = S::LOGE - 1 - kk;
     if (k >= R) continue;
     const int eb = S::LOGE - 1 - k;
-    const unsigned o = r == 0 ? 0u : T.stage_offset(x[0]);
+    if (r > 0 && k > 0) {
+      const unsigned o = T.stage_offset(x[0]);
+#pragma unroll
+      for (int j = 0; j < (1 << (k - 1)); ++j) nxt[j] = buf_load(T.tr, o, ((1 << (k - 1)) + j) * 8);
+    }
 #pragma unroll
     for (int j = 0; j < (1 << k); ++j) {
-      const double w = r == 0 ? cld(T.t0, S::tw_off(0) + (1 << k) + j) : buf_load(T.tr, o, ((1 << k) + j) * 8);
+      const double w = r == 0 ? cld(T.t0, S::tw_off(0) + (1 << k) + j) : cur[j];
 #pragma unroll
       for (int b = 0; b < (1 << eb); ++b) {
         const int e = (j << (eb + 1)) | b;
@@ -267,6 +291,10 @@ __device__ __forceinline__ void inv_round(double (&x)[NttShape<LOGN>::E], int r,
         else
           gs_bfly<false>(x[e], x[e | (1 << eb)], w, p, pinv);
       }
+    }
+    if (r > 0 && k > 0) {
+#pragma unroll
+      for (int j = 0; j < (1 << (k - 1)); ++j) cur[j] = nxt[j];
     }
   }
 #pragma unroll
@@ -314,8 +342,10 @@ k_ntt_fwd(NttJob job, Tables tb) {
   const int prime = cldi(job.limb_prime, limb);
   const double p = cld(tb.p, prime), pinv = cld(tb.pinv, prime);
   const double* __restrict__ tw = tb.tw_fwd + (size_t)prime * tb.tw_len;
-  double* dst = job.base + ((size_t)poly * job.poly_stride + (size_t)limb * S::N);
+  const size_t off = (size_t)poly * job.poly_stride + (size_t)limb * S::N;
+  double* dst = job.base + off;
   const auto rd = make_rsrc(dst, S::N * 8);
+  const auto ro = make_rsrc((job.out ? job.out : job.base) + off, S::N * 8);
   const int tid = threadIdx.x;
   const unsigned vo = tid * 8;
   double x[S::E];
@@ -348,7 +378,7 @@ k_ntt_fwd(NttJob job, Tables tb) {
     fwd_round<LOGN>(x, r, tw, p, pinv);
   }
 #pragma unroll
-  for (int e = 0; e < S::E; ++e) buf_store(x[e], rd, vo, e * S::T * 8);
+  for (int e = 0; e < S::E; ++e) buf_store(x[e], ro, vo, e * S::T * 8);
 }
 
 template <int LOGN, int MODE>
@@ -363,12 +393,14 @@ k_ntt_inv(NttJob job, Tables tb) {
   const int prime = cldi(job.limb_prime, limb);
   const double p = cld(tb.p, prime), pinv = cld(tb.pinv, prime);
   const double* __restrict__ tw = tb.tw_inv + (size_t)prime * tb.tw_len;
-  double* dst = job.base + ((size_t)poly * job.poly_stride + (size_t)limb * S::N);
+  const size_t off = (size_t)poly * job.poly_stride + (size_t)limb * S::N;
+  double* dst = job.base + off;
   const auto rd = make_rsrc(dst, S::N * 8);
+  const auto ro = make_rsrc((job.out ? job.out : job.base) + off, S::N * 8);
   const int tid = threadIdx.x;
   const unsigned vo = tid * 8;
   double x[S::E];
-  if constexpr (MODE == INV_TENSOR) {
+  if constexpr (MODE == INV_TENSOR || MODE == INV_TENSOR2) {
     // poly = ct * 3 + k: form the k-th tensor component from the operands'
     // transforms (a in src, b in src_b, or b = a when src_b is null):
     // d0 = a0 b0, d1 = a0 b1 + a1 b0, d2 = a1 b1.  Loads go in groups of 8
@@ -379,7 +411,37 @@ k_ntt_inv(NttJob job, Tables tb) {
     const size_t o1 = o0 + job.src_ct_stride / 2;
     const auto ra0 = make_rsrc(job.src + o0, S::N * 8);
     const auto ra1 = make_rsrc(job.src + o1, S::N * 8);
-    const double* sb = job.src_b ? job.src_b : job.src;
+    if constexpr (MODE == INV_TENSOR) {
+      // squaring: d0 = a0^2, d1 = 2 a0 a1, d2 = a1^2; loads pipelined one
+      // group of G elements ahead (as in the forward half transform)
+      constexpr int G = 4;
+      double ba[2][G], bb[2][G];
+      const auto& r1 = k == 2 ? ra1 : ra0;   // first operand
+#pragma unroll
+      for (int i = 0; i < G; ++i) {
+        ba[0][i] = buf_load(r1, vo, i * S::T * 8);
+        if (k == 1) bb[0][i] = buf_load(ra1, vo, i * S::T * 8);
+      }
+#pragma unroll
+      for (int g = 0; g < S::E; g += G) {
+        const int slot = (g / G) & 1;
+        if (g + G < S::E) {
+          unsigned v = vo;
+          if (g) asm volatile("" : "+v"(v) : "v"(x[g - 1]));
+#pragma unroll
+          for (int i = 0; i < G; ++i) {
+            ba[slot ^ 1][i] = buf_load(r1, v, (g + G + i) * S::T * 8);
+            if (k == 1) bb[slot ^ 1][i] = buf_load(ra1, v, (g + G + i) * S::T * 8);
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+          const double a = ba[slot][i];
+          x[g + i] = k == 1 ? mul_bal(a + a, bb[slot][i], p, pinv) : mul_bal(a, a, p, pinv);
+        }
+      }
+    } else {
+    const double* sb = job.src_b;
     const auto rb0 = make_rsrc(sb + o0, S::N * 8);
     const auto rb1 = make_rsrc(sb + o1, S::N * 8);
     unsigned v = vo;
@@ -400,6 +462,7 @@ k_ntt_inv(NttJob job, Tables tb) {
         }
       }
     }
+    }
   } else {
 #pragma unroll
     for (int e = 0; e < S::E; ++e) x[e] = buf_load(rd, vo, e * S::T * 8);
@@ -411,25 +474,140 @@ k_ntt_inv(NttJob job, Tables tb) {
     inv_round<LOGN>(x, r, tw, p, pinv);
   }
 #pragma unroll
-  for (int e = 0; e < S::E; ++e) buf_store(x[e], rd, vo, e * S::T * 8);
+  for (int e = 0; e < S::E; ++e) buf_store(x[e], ro, vo, e * S::T * 8);
 }
 
 // ---------------------------------------------------------------- host ---
 
-// Workgroups per XCD for a launch (grid = 8 x this).
-static int per_xcd(const NttJob& job, int dir) {
+// Forward transform of a 2^15-point limb by two workgroups of 512 threads,
+// one per half.  Stage 0 pairs index i with i + 2^14 and nothing later
+// mixes the halves, so each workgroup loads the whole limb, keeps its half
+// of stage 0 (X + W Y or X - W Y, W = psi^(2^14)) and runs stages 1..14 as
+// a 2^14-point transform whose twiddles are the full transform's for that
+// half: psi_br[2^s' (2 + h) + m'] at sub-stage s', block m'.  Half a limb
+// needs 68 KB of LDS and 128 VGPRs per thread, so two workgroups share a CU
+// and one loads or stores while the other computes.  Outputs land at the
+// full transform's positions: standard index h 2^14 + i' at
+// (i' mod 32) 1024 + h 512 + i' / 32.
+template <int MODE>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
+k_ntt_fwd_half(NttJob job, Tables tb) {
+  using S = NttShape<14>;
+  constexpr int NF = 1 << 15;
+  __shared__ uint32_t lds[S::LDS_WORDS];
+  int limb, poly, h;
+  if (MODE == NTT_DIGIT) {
+    const int x = blockIdx.x & 7, l2 = blockIdx.x >> 3;
+    h = l2 & 1;
+    const int l = l2 >> 1;
+    const int ph = (job.nlimb + 1) >> 1;
+    const int g = x & 1;
+    const int np = g ? job.nlimb - ph : ph;
+    const int sq = (job.npoly + 3) >> 2;
+    const int src = (x >> 1) * sq + l / np;
+    if (l / np >= sq || src >= job.npoly) return;
+    poly = src;
+    limb = g * ph + l % np;
+  } else {
+    const int item2 = xcd_item(job.count * 2);
+    if (item2 >= job.count * 2) return;
+    h = item2 & 1;
+    const int item = item2 >> 1;
+    limb = item / job.npoly;
+    poly = item - limb * job.npoly;
+  }
+  const int prime = cldi(job.limb_prime, limb);
+  const double p = cld(tb.p, prime), pinv = cld(tb.pinv, prime);
+  const double w0 = cld(tb.tw_half0, prime);
+  const double* __restrict__ tw = tb.tw_half + ((size_t)prime * 2 + h) * tb.tw_half_len;
+  // Both halves read the whole input limb, so the output must be another
+  // buffer (the host never launches this kernel in place).
+  const size_t off = (size_t)poly * job.poly_stride + (size_t)limb * NF;
+  const auto rd = make_rsrc(job.out + off, NF * 8);
+  const int tid = threadIdx.x;
+  const unsigned vo = tid * 8;
+  double x[S::E];
+  {
+    const double* src = job.base + off;
+    double qj = 0.0;
+    if constexpr (MODE == NTT_DIGIT) {
+      const int ct = poly / job.digits;
+      const int j = poly - ct * job.digits;
+      qj = cld(tb.p, j);
+      src = job.src + (size_t)ct * job.src_ct_stride + (size_t)j * NF;
+    }
+    const auto rs = make_rsrc(src, NF * 8);
+    // Loads in groups of G elements, software-pipelined one group ahead:
+    // group g + 1 is issued (fenced on group g - 1's results) before group g
+    // is processed, so at most two groups of loads are in flight.
+    constexpr int G = 8;
+    double bx[2][G], by[2][G];
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+      bx[0][i] = buf_load(rs, vo, i * S::T * 8);
+      by[0][i] = buf_load(rs, vo, (i * S::T + (NF >> 1)) * 8);
+    }
+#pragma unroll
+    for (int g = 0; g < S::E; g += G) {
+      const int slot = (g / G) & 1;
+      if (g + G < S::E) {
+        unsigned v = vo;
+        if (g) asm volatile("" : "+v"(v) : "v"(x[g - 1]));
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+          bx[slot ^ 1][i] = buf_load(rs, v, (g + G + i) * S::T * 8);
+          by[slot ^ 1][i] = buf_load(rs, v, ((g + G + i) * S::T + (NF >> 1)) * 8);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < G; ++i) {
+        double X = bx[slot][i], Y = by[slot][i];
+        if constexpr (MODE == NTT_DIGIT) {
+          // digits are the canonical values in [0, q_j), below 2 p_i:
+          // within the product's range without a reduction mod p_i
+          X = X < 0.0 ? X + qj : X;
+          Y = Y < 0.0 ? Y + qj : Y;
+        }
+        const double T = mul_lazy(Y, w0, p, pinv);
+        x[g + i] = reduce_bal(h ? X - T : X + T, p, pinv);
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < S::ROUNDS; ++r) {
+    if (r > 0) exchange<14>(x, r - 1, r, lds);
+    fwd_round<14>(x, r, tw, p, pinv);
+  }
+  const unsigned so = (h * S::T + tid) * 8;
+#pragma unroll
+  for (int e = 0; e < S::E; ++e) buf_store(x[e], rd, so, e * 1024 * 8);
+}
+
+// Workgroups per XCD for a launch (grid = 8 x this); `halves` = 2 when each
+// limb is split over two workgroups.
+static int per_xcd(const NttJob& job, int dir, int halves) {
   if (dir == 2) {
     const int ph = (job.nlimb + 1) >> 1;
     const int sq = (job.npoly + 3) >> 2;
-    return sq * ph;
+    return sq * ph * halves;
   }
-  return (job.count + 7) >> 3;
+  return (job.count * halves + 7) >> 3;
 }
 
 template <int LOGN>
 static hipError_t launch_ntt(const NttJob& job, const Tables& tb, int dir, hipStream_t st) {
   using S = NttShape<LOGN>;
-  const int per = per_xcd(job, dir);
+  if constexpr (LOGN == 15) {
+    if (((dir == 0 && job.out && job.out != job.base) || dir == 2) && tb.tw_half) {
+      dim3 grid(per_xcd(job, dir, 2) * 8), block(512);
+      if (dir == 0)
+        hipLaunchKernelGGL((k_ntt_fwd_half<NTT_INPLACE>), grid, block, 0, st, job, tb);
+      else
+        hipLaunchKernelGGL((k_ntt_fwd_half<NTT_DIGIT>), grid, block, 0, st, job, tb);
+      return hipGetLastError();
+    }
+  }
+  const int per = per_xcd(job, dir, 1);
   dim3 grid(per * 8), block(S::T);
   if (dir == 0)
     hipLaunchKernelGGL((k_ntt_fwd<LOGN, NTT_INPLACE>), grid, block, 0, st, job, tb);
@@ -437,8 +615,10 @@ static hipError_t launch_ntt(const NttJob& job, const Tables& tb, int dir, hipSt
     hipLaunchKernelGGL((k_ntt_inv<LOGN, NTT_INPLACE>), grid, block, 0, st, job, tb);
   else if (dir == 2)
     hipLaunchKernelGGL((k_ntt_fwd<LOGN, NTT_DIGIT>), grid, block, 0, st, job, tb);
-  else
+  else if (job.src_b == nullptr)
     hipLaunchKernelGGL((k_ntt_inv<LOGN, INV_TENSOR>), grid, block, 0, st, job, tb);
+  else
+    hipLaunchKernelGGL((k_ntt_inv<LOGN, INV_TENSOR2>), grid, block, 0, st, job, tb);
   return hipGetLastError();
 }
 
