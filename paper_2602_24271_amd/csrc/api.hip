@@ -721,7 +721,7 @@ int nshe_square_relin(nshe_ctx* c, const int64_t* in, int64_t* out, int n_ct, vo
   Ws w = carve(c, ws, n_ct);
   Dims d{c->n, c->L, c->LB, n_ct};
   const size_t W = W_of(c), N = c->n;
-  HIPCHK(run_i64_to_polys(d, in, 2, w.ext, 2 * W * N, W * N, c->tb, st));
+  HIPCHK(run_i64_to_polys(d, in, 2, w.ext, 2 * W * N, W * N, 2, c->tb, st));
   rc = square_level(c, w, n_ct, st);
   if (rc) return rc;
   HIPCHK(run_polys_to_i64(d, w.ext, 2, 2 * W * N, W * N, out, 0, c->tb, st));
@@ -737,8 +737,8 @@ static int load_two(nshe_ctx* c, const Ws& w, const int64_t* a, const int64_t* b
                     hipStream_t st) {
   Dims d{c->n, c->L, c->LB, n_ct};
   const size_t W = W_of(c), N = c->n;
-  HIPCHK(run_i64_to_polys(d, a, 2, w.ext, 2 * W * N, W * N, c->tb, st));
-  HIPCHK(run_i64_to_polys(d, b, 2, w.dig, 2 * W * N, W * N, c->tb, st));
+  HIPCHK(run_i64_to_polys(d, a, 2, w.ext, 2 * W * N, W * N, 2, c->tb, st));
+  HIPCHK(run_i64_to_polys(d, b, 2, w.dig, 2 * W * N, W * N, 2, c->tb, st));
   int rc = prepare_operand(c, w.ext, w.fx, n_ct, st);
   if (rc) return rc;
   return prepare_operand(c, w.dig, fx_second(c, w, n_ct), n_ct, st);
@@ -792,7 +792,7 @@ int nshe_relinearize(nshe_ctx* c, const int64_t* in3, int64_t* out, int n_ct, vo
   Ws w = carve(c, ws, n_ct);
   Dims d{c->n, c->L, c->LB, n_ct};
   const size_t W = W_of(c), N = c->n;
-  HIPCHK(run_i64_to_polys(d, in3, 3, w.dt, 3 * W * N, W * N, c->tb, st));
+  HIPCHK(run_i64_to_polys(d, in3, 3, w.dt, 3 * W * N, W * N, 2, c->tb, st));
   rc = relin(c, w, n_ct, st);
   if (rc) return rc;
   HIPCHK(run_polys_to_i64(d, w.ext, 2, 2 * W * N, W * N, out, 0, c->tb, st));

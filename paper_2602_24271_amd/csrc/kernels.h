@@ -61,7 +61,8 @@ struct NttJob {
   int nlimb;                 // limbs per poly transformed
   const int* limb_prime;     // [nlimb] prime index of each limb
   int count;                 // npoly * nlimb
-  // NTT_DIGIT source: third component's data limbs; INV_TENSOR: the
+  // NTT_DIGIT source: third component's data limbs, canonical residues in
+  // [0, q_j) (the digits themselves); INV_TENSOR: the
   // operands' transforms ([ct][2][W][N], src_b null when squaring)
   const double* src;
   const double* src_b;
@@ -95,9 +96,11 @@ hipError_t run_sub_to_ext(const Dims& d, const int64_t* x, const int64_t* y, int
                           double* ext, const Tables& tb, hipStream_t st);
 hipError_t run_sub_i64(const Dims& d, const int64_t* x, const int64_t* y, int64_t* out,
                        const Tables& tb, hipStream_t st);
+// int64 [0, q) -> balanced doubles; polys with index >= canon_from keep the
+// canonical value (the relinearization digit source)
 hipError_t run_i64_to_polys(const Dims& d, const int64_t* in, int npoly_in, double* out,
-                            size_t out_ct_stride, size_t out_poly_stride, const Tables& tb,
-                            hipStream_t st);
+                            size_t out_ct_stride, size_t out_poly_stride, int canon_from,
+                            const Tables& tb, hipStream_t st);
 hipError_t run_polys_to_i64(const Dims& d, const double* in, int npoly, size_t in_ct_stride,
                             size_t in_poly_stride, int64_t* out, int negate_delta,
                             const Tables& tb, hipStream_t st);

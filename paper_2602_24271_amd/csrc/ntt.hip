@@ -167,12 +167,15 @@ __device__ __forceinline__ void exchange(double (&x)[NttShape<LOGN>::E], int r0,
   }
 }
 
-// Cooley-Tukey butterfly without reducing X: with balanced input (|x| <
-// p/2) and balanced twiddles (|W| < p/2), |T| <= (1/2 + d) p where the
-// quotient error d <= |Y W / p| 3 2^-53 <= 0.094 |Y|/p, so five stages grow
-// |x| at most to 1.0, 1.59, 2.24, 2.95, 3.73 p < 4p: every product stays in
-// mul_lazy's range (|Y W| < 2 p^2) and every value below 2^53.  A round
-// (<= 5 stages) therefore reduces only once, at its end.
+// Cooley-Tukey butterfly without reducing X.  With |W| < p/2 and p < 2^49
+// the product T = [Y W] has |T| <= (1/2 + d) p, where the quotient error
+// d <= |Y W / p| 3 2^-53 <= 0.094 |Y| / p, so a stage maps a bound b p on
+// the inputs to (1.094 b + 0.5) p.  From inputs below 2p (a canonical
+// digit of another prime of the chain) ten stages stay below 12.6 p, so
+// every intermediate is an integer below 2^53 and every product is exact
+// (its quotient below 2^53, h - q p and the final sum exactly
+// representable).  A reduction every ten stages therefore suffices; see
+// fwd_reduces_after.
 __device__ __forceinline__ void ct_bfly(double& X, double& Y, double W, double p, double pinv) {
   double t = mul_lazy(Y, W, p, pinv);
   double x = X;
@@ -181,16 +184,50 @@ __device__ __forceinline__ void ct_bfly(double& X, double& Y, double W, double p
 }
 
 // Gentleman-Sande butterfly; the sum is reduced on alternate stages only
-// (REDUCE_SUM), the difference feeds the modular product directly.  With
-// inputs below 0.76 p after a product and 0.5 p after a reduction, the
-// unreduced sum stays below 1.52 p + 0.76 p and every difference below
-// 2.3 p, inside mul_lazy's range.
+// (REDUCE_SUM), the difference feeds the modular product directly.  From
+// balanced inputs the bound before a non-reducing stage settles below
+// 0.8 p (a reduced sum is 0.5 p, a product of a difference below 2 b p is
+// (0.5 + 0.188 b) p), so sums stay below 1.6 p and differences below 3.2 p,
+// well inside mul_lazy's range, whatever the round boundaries; the
+// alternation runs over the global stage count and only the last round
+// reduces every value.
 template <bool REDUCE_SUM>
 __device__ __forceinline__ void gs_bfly(double& X, double& Y, double W, double p, double pinv) {
   double s = X + Y;
   double d = X - Y;
   X = REDUCE_SUM ? reduce_bal(s, p, pinv) : s;
   Y = mul_lazy(d, W, p, pinv);
+}
+
+// Largest number of forward stages between two reductions (see ct_bfly).
+constexpr int FWD_STAGES_PER_REDUCTION = 10;
+
+// Whether the forward transform reduces at the end of round r, given
+// `pre` stages done (unreduced) before round 0: at the last round, and
+// whenever the next round would take the count past the limit.
+template <int LOGN>
+__host__ __device__ constexpr bool fwd_reduces_after(int r, int pre) {
+  using S = NttShape<LOGN>;
+  int since = pre;
+  for (int i = 0; i < S::ROUNDS; ++i) {
+    since += S::stages(i);
+    const bool red = i == S::ROUNDS - 1 || since + S::stages(i + 1) > FWD_STAGES_PER_REDUCTION;
+    if (i == r) return red;
+    if (red) since = 0;
+  }
+  return true;
+}
+
+template <int LOGN>
+constexpr bool fwd_schedule_ok(int pre) {
+  using S = NttShape<LOGN>;
+  int since = pre;
+  for (int i = 0; i < S::ROUNDS; ++i) {
+    since += S::stages(i);
+    if (since > FWD_STAGES_PER_REDUCTION) return false;
+    if (fwd_reduces_after<LOGN>(i, pre)) since = 0;
+  }
+  return true;
 }
 
 // Twiddle w of stage k, slot j (1 <= 2^k + j < E) in round r.  Round 0's
@@ -223,7 +260,7 @@ struct Twiddles {
 // of stage k (fenced on stage k-1's results, so no further), hiding the
 // load latency behind one stage of butterflies.
 template <int LOGN>
-__device__ __forceinline__ void fwd_round(double (&x)[NttShape<LOGN>::E], int r,
+__device__ __forceinline__ void fwd_round(double (&x)[NttShape<LOGN>::E], int r, bool reduce,
                                           const double* __restrict__ tw, double p, double pinv) {
   using S = NttShape<LOGN>;
   constexpr int HALF = S::E / 2;
@@ -254,12 +291,14 @@ __device__ __forceinline__ void fwd_round(double (&x)[NttShape<LOGN>::E], int r,
       for (int j = 0; j < (2 << k); ++j) cur[j] = nxt[j];
     }
   }
+if (reduce) {
 #pragma unroll
-  for (int e = 0; e < S::E; ++e) x[e] = reduce_bal(x[e], p, pinv);
+    for (int e = 0; e < S::E; ++e) x[e] = reduce_bal(x[e], p, pinv);
+  }
 }
 
 template <int LOGN>
-__device__ __forceinline__ void inv_round(double (&x)[NttShape<LOGN>::E], int r,
+__device__ __forceinline__ void inv_round(double (&x)[NttShape<LOGN>::E], int r, int g0,
                                           const double* __restrict__ tw, double p, double pinv) {
   using S = NttShape<LOGN>;
   constexpr int HALF = S::E / 2;
@@ -286,7 +325,7 @@ __device__ __forceinline__ void inv_round(double (&x)[NttShape<LOGN>::E], int r,
 #pragma unroll
       for (int b = 0; b < (1 << eb); ++b) {
         const int e = (j << (eb + 1)) | b;
-        if (kk & 1)
+        if ((g0 + kk - (S::LOGE - R)) & 1)
           gs_bfly<true>(x[e], x[e | (1 << eb)], w, p, pinv);
         else
           gs_bfly<false>(x[e], x[e | (1 << eb)], w, p, pinv);
@@ -297,8 +336,10 @@ __device__ __forceinline__ void inv_round(double (&x)[NttShape<LOGN>::E], int r,
       for (int j = 0; j < (1 << (k - 1)); ++j) cur[j] = nxt[j];
     }
   }
+if (r == 0) {
 #pragma unroll
-  for (int e = 0; e < S::E; ++e) x[e] = reduce_bal(x[e], p, pinv);
+    for (int e = 0; e < S::E; ++e) x[e] = reduce_bal(x[e], p, pinv);
+  }
 }
 
 // Work item of an NTT launch: item = limb * npoly + poly (limb-major, so
@@ -349,19 +390,18 @@ k_ntt_fwd(NttJob job, Tables tb) {
   const int tid = threadIdx.x;
   const unsigned vo = tid * 8;
   double x[S::E];
+  static_assert(fwd_schedule_ok<LOGN>(0), "forward reduction schedule");
   if constexpr (MODE == NTT_DIGIT) {
-    // poly = ct * L + j; limb = target prime i.  Source: digit j of the
-    // third component, balanced mod q_j; D_j = canonical value in [0, q_j).
+    // poly = ct * L + j; limb = target prime i.  Source: limb j of the
+    // third component, stored as the canonical digit D_j in [0, q_j),
+    // below 2 p_i: transformed as it is (see ct_bfly for the bound).
     const int ct = poly / job.digits;
     const int j = poly - ct * job.digits;
-    const double qj = cld(tb.p, j);
     const auto rs = make_rsrc(job.src + (size_t)ct * job.src_ct_stride + (size_t)j * S::N, S::N * 8);
 #pragma unroll
     for (int i = 0; i < S::E; ++i) {
       const int e = brv_c(i, S::LOGE);
-      double v = buf_load(rs, vo, e * S::T * 8);
-      v = v < 0.0 ? v + qj : v;
-      x[e] = reduce_bal(v, p, pinv);
+      x[e] = buf_load(rs, vo, e * S::T * 8);
     }
   } else {
     // loads in bit-reversed element order: the first stage pairs e with
@@ -375,7 +415,7 @@ k_ntt_fwd(NttJob job, Tables tb) {
 #pragma unroll
   for (int r = 0; r < S::ROUNDS; ++r) {
     if (r > 0) exchange<LOGN>(x, r - 1, r, lds);
-    fwd_round<LOGN>(x, r, tw, p, pinv);
+    fwd_round<LOGN>(x, r, fwd_reduces_after<LOGN>(r, 0), tw, p, pinv);
   }
 #pragma unroll
   for (int e = 0; e < S::E; ++e) buf_store(x[e], ro, vo, e * S::T * 8);
@@ -467,11 +507,13 @@ k_ntt_inv(NttJob job, Tables tb) {
 #pragma unroll
     for (int e = 0; e < S::E; ++e) x[e] = buf_load(rd, vo, e * S::T * 8);
   }
+  int g0 = 0;  // stages done before the current round
 #pragma unroll
   for (int rr = 0; rr < S::ROUNDS; ++rr) {
     const int r = S::ROUNDS - 1 - rr;
     if (rr > 0) exchange<LOGN>(x, r + 1, r, lds);
-    inv_round<LOGN>(x, r, tw, p, pinv);
+    inv_round<LOGN>(x, r, g0, tw, p, pinv);
+    g0 += S::stages(r);
   }
 #pragma unroll
   for (int e = 0; e < S::E; ++e) buf_store(x[e], ro, vo, e * S::T * 8);
@@ -527,13 +569,13 @@ k_ntt_fwd_half(NttJob job, Tables tb) {
   const int tid = threadIdx.x;
   const unsigned vo = tid * 8;
   double x[S::E];
+  static_assert(fwd_schedule_ok<14>(1), "forward reduction schedule");
   {
+    // digit sources hold canonical digits in [0, q_j), below 2 p_i
     const double* src = job.base + off;
-    double qj = 0.0;
     if constexpr (MODE == NTT_DIGIT) {
       const int ct = poly / job.digits;
       const int j = poly - ct * job.digits;
-      qj = cld(tb.p, j);
       src = job.src + (size_t)ct * job.src_ct_stride + (size_t)j * NF;
     }
     const auto rs = make_rsrc(src, NF * 8);
@@ -561,22 +603,16 @@ k_ntt_fwd_half(NttJob job, Tables tb) {
       }
 #pragma unroll
       for (int i = 0; i < G; ++i) {
-        double X = bx[slot][i], Y = by[slot][i];
-        if constexpr (MODE == NTT_DIGIT) {
-          // digits are the canonical values in [0, q_j), below 2 p_i:
-          // within the product's range without a reduction mod p_i
-          X = X < 0.0 ? X + qj : X;
-          Y = Y < 0.0 ? Y + qj : Y;
-        }
+        const double X = bx[slot][i], Y = by[slot][i];
         const double T = mul_lazy(Y, w0, p, pinv);
-        x[g + i] = reduce_bal(h ? X - T : X + T, p, pinv);
+        x[g + i] = h ? X - T : X + T;
       }
     }
   }
 #pragma unroll
   for (int r = 0; r < S::ROUNDS; ++r) {
     if (r > 0) exchange<14>(x, r - 1, r, lds);
-    fwd_round<14>(x, r, tw, p, pinv);
+    fwd_round<14>(x, r, fwd_reduces_after<14>(r, 1), tw, p, pinv);
   }
   const unsigned so = (h * S::T + tid) * 8;
 #pragma unroll

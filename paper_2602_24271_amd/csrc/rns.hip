@@ -102,6 +102,7 @@ __global__ void __launch_bounds__(256) k_scale(int n, size_t n_poly, double* dt,
   const size_t pc = gid / n;
   const int c = (int)(gid - pc * n);
   double* base = dt + pc * (size_t)(L + LB) * n + c;
+  const bool third = pc % 3 == 2;
   double y[L];
   double S = 0.0;
 #pragma unroll
@@ -137,7 +138,10 @@ __global__ void __launch_bounds__(256) k_scale(int n, size_t n_poly, double* dt,
     double acc = -v2 * cld(tb.B_q, i);
 #pragma unroll
     for (int k = 0; k < LB; ++k) acc += mul_lazy(w[k], cld(tb.b_hat_q, i * LB + k), q, qinv);
-    base[(size_t)i * n] = reduce_bal(acc, q, qinv);
+    const double r = reduce_bal(acc, q, qinv);
+    // the third component is only read as relinearization digits, which
+    // are its canonical residues
+    base[(size_t)i * n] = third ? to_canonical(r, q) : r;
   }
 }
 
@@ -248,7 +252,7 @@ __global__ void __launch_bounds__(256) k_sub_i64(int n, int L, size_t total, con
 __global__ void __launch_bounds__(256) k_i64_to_polys(int n, int L, int npoly, size_t total,
                                                       const int64_t* in, double* out,
                                                       size_t ct_stride, size_t poly_stride,
-                                                      Tables tb) {
+                                                      int canon_from, Tables tb) {
   const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= total) return;
   const size_t row = gid / n;               // (ct * npoly + poly) * L + i
@@ -257,7 +261,9 @@ __global__ void __launch_bounds__(256) k_i64_to_polys(int n, int L, int npoly, s
   const size_t cp = row / L;
   const size_t ct = cp / npoly;
   const int poly = (int)(cp - ct * npoly);
-  out[ct * ct_stride + poly * poly_stride + (size_t)i * n + c] = from_u64(in[gid], cld(tb.p, i));
+  // polys from canon_from on keep the canonical residue (digit sources)
+  out[ct * ct_stride + poly * poly_stride + (size_t)i * n + c] =
+      poly >= canon_from ? (double)in[gid] : from_u64(in[gid], cld(tb.p, i));
 }
 
 // balanced doubles -> canonical int64 [n_ct][npoly][L][N].  With
@@ -395,11 +401,11 @@ hipError_t run_sub_i64(const Dims& d, const int64_t* x, const int64_t* y, int64_
 }
 
 hipError_t run_i64_to_polys(const Dims& d, const int64_t* in, int npoly_in, double* out,
-                            size_t out_ct_stride, size_t out_poly_stride, const Tables& tb,
-                            hipStream_t st) {
+                            size_t out_ct_stride, size_t out_poly_stride, int canon_from,
+                            const Tables& tb, hipStream_t st) {
   const size_t total = (size_t)d.n_ct * npoly_in * d.L * d.n;
   hipLaunchKernelGGL(k_i64_to_polys, grid_for(total), dim3(256), 0, st, d.n, d.L, npoly_in, total,
-                     in, out, out_ct_stride, out_poly_stride, tb);
+                     in, out, out_ct_stride, out_poly_stride, canon_from, tb);
   return hipGetLastError();
 }
 
