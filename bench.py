@@ -128,7 +128,7 @@ def cpu_baseline() -> dict:
             "host_cpu": cpu, "host_cores_available": os.cpu_count()}
 
 
-def batched(ctx, n_inst: int, reps: int) -> dict:
+def batched(ctx, n_inst: int, reps: int, max_wave: int = 128) -> dict:
     import torch
     import synth
     rows = synth.log_uniform_sizes(2, n_inst, 1 << 14, 1 << 20)
@@ -141,7 +141,13 @@ def batched(ctx, n_inst: int, reps: int) -> dict:
         y = synth.uniform_device_residues((1, 2), ctx.q, ctx.n, 5000 + i, dev)
         items.append((x, y))
     outs = [torch.empty_like(x) for x, _ in items]
-    wave = 64
+    # autotune launch shapes and the wave size on the largest instance
+    sample = max(items, key=lambda it: it[0].shape[0])[0]
+    t0 = time.perf_counter()
+    tuned = ctx.autotune(sample, max_wave_ct=max_wave)
+    t_tune = time.perf_counter() - t0
+    wave = tuned["wave_ct"]
+    log(f"autotuned in {t_tune:.1f} s: {tuned}")
     log(f"batched: {n_inst} instances, {total} ciphertexts, wave {wave}")
     # graph path
     ctx.eq_mask_batched(items, wave_ct=wave, use_graph=True, outs=outs)
@@ -165,6 +171,7 @@ def batched(ctx, n_inst: int, reps: int) -> dict:
     log(f"per-instance loop {t_loop * 1e3:.1f} ms")
     recs = total * ctx.n
     return {"instances": n_inst, "ciphertexts": total, "wave_ct": wave,
+            "autotuned": tuned, "autotune_s": t_tune,
             "records_per_s_graph": recs / t_graph, "records_per_s_loop": recs / t_loop,
             "ms_graph": t_graph * 1e3, "ms_loop": t_loop * 1e3, "speedup": t_loop / t_graph}
 

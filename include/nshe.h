@@ -160,11 +160,16 @@ int nshe_eq_mask(nshe_ctx* ctx, const int64_t* x_dev, const int64_t* y_dev,
 
 /* Batched EQ over instances of uneven size: item i has n_ct ciphertexts.
  * The items' ciphertexts are processed together, in waves of at most
- * `wave_ct` ciphertexts (0 = as many as the workspace holds), with one
+ * `wave_ct` ciphertexts, with one
  * shared pass over the relinearization key per squaring and wave.  When
  * use_graph != 0 the whole chain of a wave is captured once into a HIP graph
- * and replayed (capture happens on `stream`; it must not already be
- * capturing).  ws_bytes must cover nshe_workspace_bytes(ctx, wave size). */
+ * and replayed; the graph reads its wave's ciphertext pointers from a table
+ * in the workspace (filled by small kernels at the start of the call), so
+ * one graph per wave size serves every wave and every later call with the
+ * same workspace and wave size.  Capture runs on a context-owned stream and
+ * the graph is launched on `stream`.  ws_bytes must cover
+ * nshe_batched_workspace_bytes(ctx, wave size, total ciphertexts); with
+ * wave_ct = 0 the wave is the tuned one, capped by what ws_bytes holds. */
 typedef struct {
   const int64_t* x_dev;
   const int64_t* y_dev;
@@ -173,9 +178,55 @@ typedef struct {
   int32_t y_broadcast;
 } nshe_item;
 
+/* Workspace bytes for nshe_eq_mask_batched with waves of wave_ct
+ * ciphertexts over total_ct ciphertexts in all: one wave's ciphertext
+ * workspace, a wave counter and a table of 24-byte per-ciphertext pointers
+ * (total_ct + wave_ct entries).  0 on a bad argument. */
+size_t nshe_batched_workspace_bytes(const nshe_ctx* ctx, int wave_ct, long long total_ct);
+
 int nshe_eq_mask_batched(nshe_ctx* ctx, const nshe_item* items_host,
                          int n_items, int wave_ct, int use_graph, void* ws_dev,
                          size_t ws_bytes, void* stream);
+
+/* Launch shapes and the autotuner.  Results never depend on the tuning
+ * (every kernel computes the same exact integers); only the speed does.
+ *   ks_chunk       ciphertexts accumulated per pass over the relinearization
+ *                  key in the key-switch inner product: 4, 8, 16 or 32;
+ *   split_forward  1: each 2^15-point forward transform runs as two
+ *                  workgroups (one per output half), 0: one workgroup per
+ *                  limb (ignored for smaller N);
+ *   ew_block       threads per workgroup of the per-coefficient kernels
+ *                  (base lift, scale-and-round, mod-down): 64, 128 or 256;
+ *   wave_ct        ciphertexts per wave of nshe_eq_mask_batched when its
+ *                  wave_ct argument is 0 (0: as many as the workspace holds).
+ * A new context starts at {16, 1, 256, 0}.  nshe_set_tuning validates the
+ * values (NSHE_EINVAL otherwise) and drops the batched call's cached graphs.
+ *
+ * nshe_autotune measures, on the caller's sample ciphertexts (int64
+ * [n_sample][2][L][N], repeated cyclically to fill larger trials), squaring
+ * levels of the EQ chain with HIP events: first ks_chunk, split_forward and
+ * ew_block one at a time (each judged by the event time of the kernels it
+ * shapes, on min(32, wave limit) ciphertexts), then the per-ciphertext
+ * time of a level at 1, 2, 4, ... ciphertexts up to the wave limit
+ * (max_wave_ct if > 0, and what ws_bytes holds), keeping the smallest wave
+ * within 3% of the best rate.  The result becomes the context's tuning and
+ * is copied to *out_host (if not NULL); *ms_per_ct_host (if not NULL)
+ * receives the best per-ciphertext level time in ms.  Needs the relin key.
+ * The workspace contents are overwritten; the sample is only read.  The
+ * call synchronises `stream` several times; profiling records and the
+ * profiling flag of the caller are kept aside and restored. */
+typedef struct {
+  int32_t ks_chunk;
+  int32_t split_forward;
+  int32_t ew_block;
+  int32_t wave_ct;
+} nshe_tuning;
+
+int nshe_get_tuning(nshe_ctx* ctx, nshe_tuning* out_host);
+int nshe_set_tuning(nshe_ctx* ctx, const nshe_tuning* in_host);
+int nshe_autotune(nshe_ctx* ctx, const int64_t* sample_dev, int n_sample,
+                  int max_wave_ct, void* ws_dev, size_t ws_bytes, void* stream,
+                  nshe_tuning* out_host, double* ms_per_ct_host);
 
 /* Negacyclic NTT (debug/parity entry): for each of n_poly polynomials of L
  * data-prime limbs (int64 [n_poly][L][N], residues in [0, q_i)), out holds

@@ -36,6 +36,11 @@ class NsheKernelStat(ctypes.Structure):
                 ("total_ms", ctypes.c_double), ("work", ctypes.c_double)]
 
 
+class NsheTuning(ctypes.Structure):
+    _fields_ = [("ks_chunk", ctypes.c_int32), ("split_forward", ctypes.c_int32),
+                ("ew_block", ctypes.c_int32), ("wave_ct", ctypes.c_int32)]
+
+
 # name -> (restype, argtypes)
 _P = ctypes.c_void_p
 _I = ctypes.c_int
@@ -52,7 +57,12 @@ SIGNATURES = {
     "nshe_multiply": (_I, [_P, _P, _P, _P, _I, _P, _SZ, _P]),
     "nshe_relinearize": (_I, [_P, _P, _P, _I, _P, _SZ, _P]),
     "nshe_eq_mask": (_I, [_P, _P, _P, _P, _I, _I, _P, _SZ, _P]),
+    "nshe_batched_workspace_bytes": (_SZ, [_P, _I, ctypes.c_longlong]),
     "nshe_eq_mask_batched": (_I, [_P, ctypes.POINTER(NsheItem), _I, _I, _I, _P, _SZ, _P]),
+    "nshe_get_tuning": (_I, [_P, ctypes.POINTER(NsheTuning)]),
+    "nshe_set_tuning": (_I, [_P, ctypes.POINTER(NsheTuning)]),
+    "nshe_autotune": (_I, [_P, _P, _I, _I, _P, _SZ, _P, ctypes.POINTER(NsheTuning),
+                           ctypes.POINTER(ctypes.c_double)]),
     "nshe_ntt": (_I, [_P, _P, _P, _I, _I, _P, _SZ, _P]),
     "nshe_margin_events": (_I, [_P, ctypes.POINTER(ctypes.c_uint64), _P]),
     "nshe_reset_margin_events": (_I, [_P, _P]),

@@ -71,7 +71,9 @@ class Context:
         return int(self._lib.nshe_workspace_bytes(self._h, n_ct))
 
     def workspace(self, n_ct: int) -> torch.Tensor:
-        need = self.workspace_bytes(n_ct)
+        return self._workspace_bytes(self.workspace_bytes(n_ct))
+
+    def _workspace_bytes(self, need: int) -> torch.Tensor:
         if self._ws is None or self._ws.numel() < need:
             self._ws = None
             self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
@@ -168,12 +170,49 @@ class Context:
             res.append(out)
             arr[i] = _lib.NsheItem(_ptr(x), _ptr(y), _ptr(out), n, 1 if (ny == 1 and n != 1) else 0)
         total = sum(int(x.shape[0]) for x, _ in items)
-        wave = wave_ct if wave_ct > 0 else total
-        ws = self.workspace(min(wave, total))
-        _lib.check(self._lib.nshe_eq_mask_batched(self._h, arr, len(items), wave_ct,
+        wave = wave_ct if wave_ct > 0 else (self.tuning()["wave_ct"] or self.DEFAULT_WAVE)
+        wave = min(wave, total)
+        need = int(self._lib.nshe_batched_workspace_bytes(self._h, wave, total))
+        ws = self._workspace_bytes(need)
+        _lib.check(self._lib.nshe_eq_mask_batched(self._h, arr, len(items), wave,
                                                   1 if use_graph else 0, _ptr(ws), ws.numel(),
                                                   _stream()))
         return res
+
+    TUNING_FIELDS = ("ks_chunk", "split_forward", "ew_block", "wave_ct")
+    DEFAULT_WAVE = 32  # batched wave when neither the call nor the tuning sets one
+
+    def tuning(self) -> dict:
+        t = _lib.NsheTuning()
+        _lib.check(self._lib.nshe_get_tuning(self._h, ctypes.byref(t)))
+        return {f: int(getattr(t, f)) for f in self.TUNING_FIELDS}
+
+    def set_tuning(self, **kw) -> None:
+        cur = self.tuning()
+        unknown = set(kw) - set(cur)
+        if unknown:
+            raise ValueError(f"unknown tuning fields {sorted(unknown)}")
+        cur.update(kw)
+        t = _lib.NsheTuning(**cur)
+        _lib.check(self._lib.nshe_set_tuning(self._h, ctypes.byref(t)))
+
+    def autotune(self, sample: torch.Tensor, max_wave_ct: int) -> dict:
+        """Measure and set the launch shapes and batched wave size (see
+        nshe_autotune) on `sample` ciphertexts, with a workspace for
+        max_wave_ct ciphertexts.  Returns the tuning plus the best
+        per-ciphertext level time ("ms_per_ct")."""
+        n = self._check_ct(sample)
+        if max_wave_ct < 1:
+            raise ValueError("max_wave_ct must be >= 1")
+        ws = self.workspace(max_wave_ct)
+        t = _lib.NsheTuning()
+        ms = ctypes.c_double(0.0)
+        _lib.check(self._lib.nshe_autotune(self._h, _ptr(sample), n, max_wave_ct, _ptr(ws),
+                                           ws.numel(), _stream(), ctypes.byref(t),
+                                           ctypes.byref(ms)))
+        out = {f: int(getattr(t, f)) for f in self.TUNING_FIELDS}
+        out["ms_per_ct"] = ms.value
+        return out
 
     def ntt(self, polys: torch.Tensor) -> torch.Tensor:
         """Forward negacyclic NTT of [n_poly, L, N] int64 limbs: evaluations

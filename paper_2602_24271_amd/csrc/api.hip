@@ -138,6 +138,7 @@ struct nshe_ctx {
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
   hipStream_t cap_stream = nullptr;  // capture-only stream (the null stream cannot capture)
+  nshe_tuning tune{16, 1, 256, 0};
 };
 
 namespace nshe {
@@ -150,6 +151,13 @@ namespace nshe {
   } while (0)
 
 static int W_of(const nshe_ctx* c) { return 2 * c->L + 1; }
+
+static Dims dims(const nshe_ctx* c, int n_ct) {
+  Dims d{c->n, c->L, c->LB, n_ct};
+  d.block = c->tune.ew_block;
+  d.ks_chunk = c->tune.ks_chunk;
+  return d;
+}
 
 // ------------------------------------------------------------ profiling
 
@@ -244,6 +252,7 @@ static int check_ws(const nshe_ctx* c, void* ws, size_t bytes, int n_ct) {
 static int ntt_job_ext(nshe_ctx* c, double* base, double* out, int npoly, int dir,
                        hipStream_t st) {
   NttJob j{};
+  j.split = c->tune.split_forward;
   j.base = base;
   j.out = out;
   j.poly_stride = (size_t)W_of(c) * c->n;
@@ -259,6 +268,7 @@ static int ntt_job_ext(nshe_ctx* c, double* base, double* out, int npoly, int di
 static int ntt_job_ks(nshe_ctx* c, double* base, double* out, int npoly, int dir,
                       hipStream_t st) {
   NttJob j{};
+  j.split = c->tune.split_forward;
   j.base = base;
   j.out = out;
   j.poly_stride = (size_t)(c->L + 1) * c->n;
@@ -274,7 +284,7 @@ static int ntt_job_ks(nshe_ctx* c, double* base, double* out, int npoly, int dir
 // Lift the ciphertexts held in ext (limbs 0..L-1) and transform all limbs
 // into fx.
 static int prepare_operand(nshe_ctx* c, double* ext, double* fx, int n_ct, hipStream_t st) {
-  Dims d{c->n, c->L, c->LB, n_ct};
+  Dims d = dims(c, n_ct);
   {
     Prof pf(c, K_LIFT, st, 2.0 * n_ct * c->n);
     HIPCHK(run_lift(d, ext, c->tb, st));
@@ -285,7 +295,7 @@ static int prepare_operand(nshe_ctx* c, double* ext, double* fx, int n_ct, hipSt
 // fx (NTT domain, operands; the second in fx_b, or squaring) -> dt limbs
 // 0..L-1 of the 3 components: [round(t d_k / Q)]_Q, coefficient domain.
 static int tensor_scale(nshe_ctx* c, const Ws& w, const double* fx_b, int n_ct, hipStream_t st) {
-  Dims d{c->n, c->L, c->LB, n_ct};
+  Dims d = dims(c, n_ct);
   {
     // the tensor product is formed while the inverse transform loads
     NttJob j{};
@@ -310,8 +320,9 @@ static int tensor_scale(nshe_ctx* c, const Ws& w, const double* fx_b, int n_ct, 
 
 // Relinearize the components in dt (limbs 0..L-1) into ext limbs 0..L-1.
 static int relin(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st) {
-  Dims d{c->n, c->L, c->LB, n_ct};
+  Dims d = dims(c, n_ct);
   NttJob j{};
+  j.split = c->tune.split_forward;
   j.base = w.dig;
   j.out = w.dig;
   j.poly_stride = (size_t)(c->L + 1) * c->n;
@@ -693,7 +704,7 @@ int nshe_sub(nshe_ctx* c, const int64_t* x, const int64_t* y, int64_t* out, int 
   if (n_ct == 0) return NSHE_OK;
   if (!x || !y || !out) return fail(NSHE_EINVAL, "null buffer");
   if (set_device(c)) return NSHE_EDEVICE;
-  Dims d{c->n, c->L, c->LB, n_ct};
+  Dims d = dims(c, n_ct);
   HIPCHK(run_sub_i64(d, x, y, out, c->tb, static_cast<hipStream_t>(stream)));
   return NSHE_OK;
 }
@@ -719,7 +730,7 @@ int nshe_square_relin(nshe_ctx* c, const int64_t* in, int64_t* out, int n_ct, vo
   if (!in || !out) return fail(NSHE_EINVAL, "null buffer");
   hipStream_t st = static_cast<hipStream_t>(stream);
   Ws w = carve(c, ws, n_ct);
-  Dims d{c->n, c->L, c->LB, n_ct};
+  Dims d = dims(c, n_ct);
   const size_t W = W_of(c), N = c->n;
   HIPCHK(run_i64_to_polys(d, in, 2, w.ext, 2 * W * N, W * N, 2, c->tb, st));
   rc = square_level(c, w, n_ct, st);
@@ -735,7 +746,7 @@ static double* fx_second(const nshe_ctx* c, const Ws& w, int n_ct) {
 
 static int load_two(nshe_ctx* c, const Ws& w, const int64_t* a, const int64_t* b, int n_ct,
                     hipStream_t st) {
-  Dims d{c->n, c->L, c->LB, n_ct};
+  Dims d = dims(c, n_ct);
   const size_t W = W_of(c), N = c->n;
   HIPCHK(run_i64_to_polys(d, a, 2, w.ext, 2 * W * N, W * N, 2, c->tb, st));
   HIPCHK(run_i64_to_polys(d, b, 2, w.dig, 2 * W * N, W * N, 2, c->tb, st));
@@ -752,7 +763,7 @@ int nshe_mul_relin(nshe_ctx* c, const int64_t* a, const int64_t* b, int64_t* out
   if (!a || !b || !out) return fail(NSHE_EINVAL, "null buffer");
   hipStream_t st = static_cast<hipStream_t>(stream);
   Ws w = carve(c, ws, n_ct);
-  Dims d{c->n, c->L, c->LB, n_ct};
+  Dims d = dims(c, n_ct);
   const size_t W = W_of(c), N = c->n;
   rc = load_two(c, w, a, b, n_ct, st);
   if (rc) return rc;
@@ -772,7 +783,7 @@ int nshe_multiply(nshe_ctx* c, const int64_t* a, const int64_t* b, int64_t* out3
   if (!a || !b || !out3) return fail(NSHE_EINVAL, "null buffer");
   hipStream_t st = static_cast<hipStream_t>(stream);
   Ws w = carve(c, ws, n_ct);
-  Dims d{c->n, c->L, c->LB, n_ct};
+  Dims d = dims(c, n_ct);
   const size_t W = W_of(c), N = c->n;
   rc = load_two(c, w, a, b, n_ct, st);
   if (rc) return rc;
@@ -790,7 +801,7 @@ int nshe_relinearize(nshe_ctx* c, const int64_t* in3, int64_t* out, int n_ct, vo
   if (!in3 || !out) return fail(NSHE_EINVAL, "null buffer");
   hipStream_t st = static_cast<hipStream_t>(stream);
   Ws w = carve(c, ws, n_ct);
-  Dims d{c->n, c->L, c->LB, n_ct};
+  Dims d = dims(c, n_ct);
   const size_t W = W_of(c), N = c->n;
   HIPCHK(run_i64_to_polys(d, in3, 3, w.dt, 3 * W * N, W * N, 2, c->tb, st));
   rc = relin(c, w, n_ct, st);
@@ -817,7 +828,7 @@ int nshe_eq_mask(nshe_ctx* c, const int64_t* x, const int64_t* y, int64_t* out, 
   if (!x || !y || !out) return fail(NSHE_EINVAL, "null buffer");
   hipStream_t st = static_cast<hipStream_t>(stream);
   Ws w = carve(c, ws, n_ct);
-  Dims d{c->n, c->L, c->LB, n_ct};
+  Dims d = dims(c, n_ct);
   const size_t W = W_of(c), N = c->n;
   {
     Prof pf(c, K_SUB, st, 2.0 * n_ct * c->L * c->n);
@@ -832,33 +843,54 @@ int nshe_eq_mask(nshe_ctx* c, const int64_t* x, const int64_t* y, int64_t* out, 
   return NSHE_OK;
 }
 
-// Enqueue one wave of the batched chain: segments (item, first ct, count).
-struct Seg {
-  const nshe_item* it;
-  int first, count;
+static void drop_graphs(nshe_ctx* c);
+
+// Batched waves.  The caller's workspace holds, after the ciphertext area
+// of one wave, a wave counter (256 bytes) and a table of per-ciphertext
+// pointers ([wave][wave_ct] entries); the kernels that read inputs and write outputs look
+// up their wave there, so one captured graph serves every wave of a size.
+static size_t table_entries(int wave_ct, long long total) { return (size_t)(total + wave_ct); }
+
+static size_t batched_ws_bytes(const nshe_ctx* c, int wave_ct, long long total) {
+  const size_t cts = (ws_doubles(c, wave_ct) * sizeof(double) + 255) & ~(size_t)255;
+  const size_t tab = (table_entries(wave_ct, total) * sizeof(CtPtrs) + 255) & ~(size_t)255;
+  return cts + tab + 256;
+}
+
+struct BatchArea {
+  CtPtrs* table;
+  int* counter;
 };
 
-static int enqueue_wave(nshe_ctx* c, const std::vector<Seg>& segs, int wave_ct, const Ws& w,
+static BatchArea batch_area(const nshe_ctx* c, void* ws, int wave_ct, long long total) {
+  char* p = static_cast<char*>(ws);
+  const size_t cts = (ws_doubles(c, wave_ct) * sizeof(double) + 255) & ~(size_t)255;
+  (void)total;
+  return BatchArea{reinterpret_cast<CtPtrs*>(p + cts + 256), reinterpret_cast<int*>(p + cts)};
+}
+
+// One wave of cnt ciphertexts: gather x - y, the 16 levels, scatter the
+// mask, advance the wave counter.
+static int enqueue_wave(nshe_ctx* c, int cnt, int stride, const BatchArea& a, const Ws& w,
                         hipStream_t st) {
-  const size_t W = W_of(c), N = c->n, ctw = (size_t)2 * c->L * N;
-  int pos = 0;
-  for (const Seg& s : segs) {
-    Dims d{c->n, c->L, c->LB, s.count};
-    const int64_t* y = s.it->y_broadcast ? s.it->y_dev : s.it->y_dev + (size_t)s.first * ctw;
-    HIPCHK(run_sub_to_ext(d, s.it->x_dev + (size_t)s.first * ctw, y, s.it->y_broadcast ? 1 : 0,
-                          w.ext + (size_t)pos * 2 * W * N, c->tb, st));
-    pos += s.count;
+  Dims d = dims(c, cnt);
+  {
+    Prof pf(c, K_SUB, st, 2.0 * cnt * c->L * c->n);
+    HIPCHK(run_gather_sub(d, stride, a.table, a.counter, w.ext, c->tb, st));
   }
-  int rc = eq_levels(c, w, wave_ct, st);
+  int rc = eq_levels(c, w, cnt, st);
   if (rc) return rc;
-  pos = 0;
-  for (const Seg& s : segs) {
-    Dims d{c->n, c->L, c->LB, s.count};
-    HIPCHK(run_polys_to_i64(d, w.ext + (size_t)pos * 2 * W * N, 2, 2 * W * N, W * N,
-                            s.it->out_dev + (size_t)s.first * ctw, 1, c->tb, st));
-    pos += s.count;
+  {
+    Prof pf(c, K_CONVERT, st, 2.0 * cnt * c->L * c->n);
+    HIPCHK(run_scatter_mask(d, stride, a.table, a.counter, w.ext, c->tb, st));
   }
+  HIPCHK(run_bump_counter(a.counter, st));
   return NSHE_OK;
+}
+
+size_t nshe_batched_workspace_bytes(const nshe_ctx* c, int wave_ct, long long total_ct) {
+  if (check_ctx(c) || wave_ct < 1 || total_ct < 0) return 0;
+  return batched_ws_bytes(c, wave_ct, total_ct);
 }
 
 int nshe_eq_mask_batched(nshe_ctx* c, const nshe_item* items, int n_items, int wave_ct,
@@ -868,6 +900,7 @@ int nshe_eq_mask_batched(nshe_ctx* c, const nshe_item* items, int n_items, int w
   if (n_items < 0 || (n_items > 0 && !items)) return fail(NSHE_EINVAL, "bad item list");
   if (c->squarings < 0) return fail(NSHE_EDEPTH, "t - 1 is not a power of two");
   if (check_key(c)) return NSHE_ENOKEY;
+  if (wave_ct < 0) return fail(NSHE_EINVAL, "wave_ct < 0");
   long long total = 0;
   for (int i = 0; i < n_items; ++i) {
     if (items[i].n_ct < 0) return fail(NSHE_ESHAPE, "item with n_ct < 0");
@@ -877,46 +910,68 @@ int nshe_eq_mask_batched(nshe_ctx* c, const nshe_item* items, int n_items, int w
   }
   if (total == 0) return NSHE_OK;
   if (!ws) return fail(NSHE_EINVAL, "workspace pointer is null");
-  const size_t per_ct = ws_doubles(c, 1) * sizeof(double);
-  const int fit = (int)std::min<size_t>(ws_bytes / per_ct, 1 << 20);
-  if (wave_ct <= 0) wave_ct = fit;
-  if (wave_ct <= 0 || wave_ct > fit) return fail(NSHE_ENOMEM, "workspace smaller than one wave");
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(NSHE_EINVAL, "workspace not 256-byte aligned");
+  if (wave_ct == 0) {
+    // the tuned wave if it fits, else the largest that does
+    const size_t per_ct = ws_doubles(c, 1) * sizeof(double) + sizeof(CtPtrs);
+    const size_t fixed = (size_t)total * sizeof(CtPtrs) + 1024;
+    const long long fit = ws_bytes > fixed ? (long long)((ws_bytes - fixed) / per_ct) : 0;
+    wave_ct = (int)std::min<long long>(fit, 1 << 20);
+    if (c->tune.wave_ct > 0) wave_ct = std::min(wave_ct, c->tune.wave_ct);
+    while (wave_ct > 1 &&
+           batched_ws_bytes(c, (int)std::min<long long>(wave_ct, total), total) > ws_bytes)
+      --wave_ct;
+    if (wave_ct < 1) return fail(NSHE_ENOMEM, "workspace smaller than one wave");
+  }
   if (wave_ct > total) wave_ct = (int)total;
-  if (check_ws(c, ws, ws_bytes, wave_ct)) return NSHE_ENOMEM;
+  if (ws_bytes < batched_ws_bytes(c, wave_ct, total))
+    return fail(NSHE_ENOMEM, "workspace smaller than nshe_batched_workspace_bytes(ctx, wave_ct, total)");
   if (set_device(c)) return NSHE_EDEVICE;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  // split items into waves of wave_ct ciphertexts
-  std::vector<std::vector<Seg>> waves(1);
-  int fill = 0;
+  const BatchArea area = batch_area(c, ws, wave_ct, total);
+  const size_t ctw = (size_t)2 * c->L * c->n;
+
+  // per-ciphertext pointers, wave by wave (wave k at entries k * wave_ct)
+  HIPCHK(run_set_counter(area.counter, 0, st));
+  TableChunk ch{};
+  ch.first = 0;
+  ch.n = 0;
+  long long k = 0;  // running ciphertext index = wave * wave_ct + position
+  auto flush = [&]() -> int {
+    if (ch.n == 0) return NSHE_OK;
+    HIPCHK(run_fill_table(ch, area.table, st));
+    ch.first += ch.n;
+    ch.n = 0;
+    return NSHE_OK;
+  };
   for (int i = 0; i < n_items; ++i) {
-    int done = 0;
-    while (done < items[i].n_ct) {
-      if (fill == wave_ct) {
-        waves.emplace_back();
-        fill = 0;
+    const nshe_item& it = items[i];
+    for (int j = 0; j < it.n_ct; ++j, ++k) {
+      CtPtrs e;
+      e.x = it.x_dev + (size_t)j * ctw;
+      e.y = it.y_broadcast ? it.y_dev : it.y_dev + (size_t)j * ctw;
+      e.out = it.out_dev + (size_t)j * ctw;
+      ch.e[ch.n++] = e;
+      if (ch.n == TableChunk::CAP) {
+        int rc = flush();
+        if (rc) return rc;
       }
-      const int take = std::min(items[i].n_ct - done, wave_ct - fill);
-      waves.back().push_back(Seg{&items[i], done, take});
-      done += take;
-      fill += take;
     }
   }
-  for (const auto& wv : waves) {
-    int cnt = 0;
-    for (const Seg& s : wv) cnt += s.count;
+  int rc = flush();
+  if (rc) return rc;
+
+  const long long n_waves = (total + wave_ct - 1) / wave_ct;
+  for (long long wv = 0; wv < n_waves; ++wv) {
+    const int cnt = (int)std::min<long long>(wave_ct, total - wv * wave_ct);
     Ws w = carve(c, ws, cnt);
     if (!use_graph) {
-      int rc = enqueue_wave(c, wv, cnt, w, st);
+      rc = enqueue_wave(c, cnt, wave_ct, area, w, st);
       if (rc) return rc;
       continue;
     }
-    std::vector<uintptr_t> key = {reinterpret_cast<uintptr_t>(ws), (uintptr_t)cnt};
-    for (const Seg& s : wv) {
-      key.push_back(reinterpret_cast<uintptr_t>(s.it->x_dev));
-      key.push_back(reinterpret_cast<uintptr_t>(s.it->y_dev));
-      key.push_back(reinterpret_cast<uintptr_t>(s.it->out_dev));
-      key.push_back(((uintptr_t)s.first << 33) | ((uintptr_t)s.count << 1) | (s.it->y_broadcast ? 1 : 0));
-    }
+    const std::vector<uintptr_t> key = {reinterpret_cast<uintptr_t>(ws), (uintptr_t)cnt,
+                                        (uintptr_t)wave_ct};
     const bool prof_saved = c->prof;
     c->prof = false;  // no event records inside a captured graph
     struct Restore {
@@ -931,7 +986,7 @@ int nshe_eq_mask_batched(nshe_ctx* c, const nshe_item* items, int n_items, int w
       if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
       hipGraph_t g = nullptr;
       HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-      int rc = enqueue_wave(c, wv, cnt, w, c->cap_stream);
+      rc = enqueue_wave(c, cnt, wave_ct, area, w, c->cap_stream);
       hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
       if (rc) {
         if (g) (void)hipGraphDestroy(g);
@@ -942,14 +997,212 @@ int nshe_eq_mask_batched(nshe_ctx* c, const nshe_item* items, int n_items, int w
       e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
       (void)hipGraphDestroy(g);
       if (e != hipSuccess) return fail(NSHE_EDEVICE, std::string("instantiate: ") + hipGetErrorString(e));
-      if (c->graphs.size() > 64) {
-        for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second.exec);
-        c->graphs.clear();
-      }
+      if (c->graphs.size() >= 16) drop_graphs(c);
       found = c->graphs.emplace(key, nshe_ctx::GraphEntry{ex}).first;
     }
     HIPCHK(hipGraphLaunch(found->second.exec, st));
   }
+  return NSHE_OK;
+}
+
+// ---------------------------------------------------------------- tuning
+
+static bool tuning_valid(const nshe_tuning& t) {
+  const bool ks = t.ks_chunk == 4 || t.ks_chunk == 8 || t.ks_chunk == 16 || t.ks_chunk == 32;
+  const bool blk = t.ew_block == 64 || t.ew_block == 128 || t.ew_block == 256;
+  return ks && blk && (t.split_forward == 0 || t.split_forward == 1) && t.wave_ct >= 0;
+}
+
+static void drop_graphs(nshe_ctx* c) {
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second.exec);
+  c->graphs.clear();
+}
+
+int nshe_get_tuning(nshe_ctx* c, nshe_tuning* out) {
+  g_err.clear();
+  if (check_ctx(c) || !out) return fail(NSHE_EINVAL, "null argument");
+  *out = c->tune;
+  return NSHE_OK;
+}
+
+int nshe_set_tuning(nshe_ctx* c, const nshe_tuning* in) {
+  g_err.clear();
+  if (check_ctx(c) || !in) return fail(NSHE_EINVAL, "null argument");
+  if (!tuning_valid(*in)) return fail(NSHE_EINVAL, "tuning value out of range");
+  if (set_device(c)) return NSHE_EDEVICE;
+  drop_graphs(c);
+  c->tune = *in;
+  return NSHE_OK;
+}
+
+namespace {
+
+// Per-kind event time of the records taken since the last call (waits).
+static int drain_records(nshe_ctx* c, double ms[K_COUNT]) {
+  for (int i = 0; i < K_COUNT; ++i) ms[i] = 0.0;
+  for (auto& r : c->recs) {
+    HIPCHK(hipEventSynchronize(r.b));
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, r.a, r.b));
+    ms[r.kind] += t;
+    c->pool.push_back(r.a);
+    c->pool.push_back(r.b);
+  }
+  c->recs.clear();
+  return NSHE_OK;
+}
+
+// Fill the first n_ct ciphertext slots of ext from the sample, cyclically.
+static int load_sample(nshe_ctx* c, const Ws& w, const int64_t* sample, int n_sample, int n_ct,
+                       hipStream_t st) {
+  const size_t W = W_of(c), N = c->n, ctw = (size_t)2 * c->L * N;
+  for (int k = 0; k < n_ct; k += n_sample) {
+    const int m = std::min(n_sample, n_ct - k);
+    HIPCHK(run_i64_to_polys(dims(c, m), sample, 2, w.ext + (size_t)k * 2 * W * N, 2 * W * N,
+                            W * N, 2, c->tb, st));
+  }
+  (void)ctw;
+  return NSHE_OK;
+}
+
+// Per-kind times of `reps` squaring levels on n_ct ciphertexts (after one
+// untimed level) under tuning t.
+static int time_kinds(nshe_ctx* c, const nshe_tuning& t, const Ws& w, int n_ct, int reps,
+                      hipStream_t st, double ms[K_COUNT]) {
+  c->tune = t;
+  c->prof = false;
+  int rc = square_level(c, w, n_ct, st);
+  if (rc) return rc;
+  c->prof = true;
+  for (int i = 0; i < reps; ++i) {
+    rc = square_level(c, w, n_ct, st);
+    if (rc) return rc;
+  }
+  c->prof = false;
+  return drain_records(c, ms);
+}
+
+// Wall time of one squaring level on n_ct ciphertexts (after one untimed).
+static int time_level(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st, double* ms) {
+  int rc = square_level(c, w, n_ct, st);
+  if (rc) return rc;
+  hipEvent_t a = take_event(c), b = take_event(c);
+  if (!a || !b) return fail(NSHE_EDEVICE, "event creation failed");
+  HIPCHK(hipEventRecord(a, st));
+  rc = square_level(c, w, n_ct, st);
+  if (rc) return rc;
+  HIPCHK(hipEventRecord(b, st));
+  HIPCHK(hipEventSynchronize(b));
+  float t = 0.f;
+  HIPCHK(hipEventElapsedTime(&t, a, b));
+  c->pool.push_back(a);
+  c->pool.push_back(b);
+  *ms = t;
+  return NSHE_OK;
+}
+
+}  // namespace
+
+int nshe_autotune(nshe_ctx* c, const int64_t* sample, int n_sample, int max_wave_ct, void* ws,
+                  size_t ws_bytes, void* stream, nshe_tuning* out, double* ms_per_ct) {
+  g_err.clear();
+  if (check_ctx(c)) return NSHE_EINVAL;
+  if (!sample || n_sample < 1) return fail(NSHE_EINVAL, "empty sample");
+  if (max_wave_ct < 0) return fail(NSHE_EINVAL, "max_wave_ct < 0");
+  if (check_key(c)) return NSHE_ENOKEY;
+  if (!ws) return fail(NSHE_EINVAL, "workspace pointer is null");
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(NSHE_EINVAL, "workspace not 256-byte aligned");
+  const size_t per_ct = ws_doubles(c, 1) * sizeof(double);
+  int fit = (int)std::min<size_t>(ws_bytes / per_ct, 1 << 20);
+  if (max_wave_ct > 0) fit = std::min(fit, max_wave_ct);
+  if (fit < 1) return fail(NSHE_ENOMEM, "workspace smaller than one ciphertext's");
+  if (set_device(c)) return NSHE_EDEVICE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+
+  // the caller's profiling records and flag are set aside meanwhile
+  std::vector<nshe_ctx::Rec> saved_recs;
+  saved_recs.swap(c->recs);
+  const bool saved_prof = c->prof;
+  const nshe_tuning start = c->tune;
+  struct Restore {
+    nshe_ctx* c;
+    std::vector<nshe_ctx::Rec>& recs;
+    bool prof;
+    ~Restore() {
+      for (auto& r : c->recs) {
+        c->pool.push_back(r.a);
+        c->pool.push_back(r.b);
+      }
+      c->recs.swap(recs);
+      c->prof = prof;
+    }
+  } restore{c, saved_recs, saved_prof};
+
+  // 1. launch shapes, one parameter at a time (each moves only its own
+  // kernels' times), on up to 32 ciphertexts
+  const int n_t = std::min(fit, 32);
+  Ws w = carve(c, ws, n_t);
+  int rc = load_sample(c, w, sample, n_sample, n_t, st);
+  if (rc) { c->tune = start; return rc; }
+  nshe_tuning best = start;
+  double ms[K_COUNT];
+  {
+    const int cand[] = {4, 8, 16, 32};
+    double tbest = 1e300;
+    for (int v : cand) {
+      nshe_tuning t = best;
+      t.ks_chunk = v;
+      rc = time_kinds(c, t, w, n_t, 2, st, ms);
+      if (rc) { c->tune = start; return rc; }
+      if (ms[K_KS_MAC] < tbest) { tbest = ms[K_KS_MAC]; best.ks_chunk = v; }
+    }
+  }
+  if (c->log2n == 15) {
+    double tbest = 1e300;
+    for (int v = 0; v < 2; ++v) {
+      nshe_tuning t = best;
+      t.split_forward = v;
+      rc = time_kinds(c, t, w, n_t, 2, st, ms);
+      if (rc) { c->tune = start; return rc; }
+      const double tt = ms[K_NTT_FWD] + ms[K_NTT_DIGIT];
+      if (tt < tbest) { tbest = tt; best.split_forward = v; }
+    }
+  }
+  {
+    const int cand[] = {64, 128, 256};
+    double tbest = 1e300;
+    for (int v : cand) {
+      nshe_tuning t = best;
+      t.ew_block = v;
+      rc = time_kinds(c, t, w, n_t, 2, st, ms);
+      if (rc) { c->tune = start; return rc; }
+      const double tt = ms[K_LIFT] + ms[K_SCALE] + ms[K_MODDOWN];
+      if (tt < tbest) { tbest = tt; best.ew_block = v; }
+    }
+  }
+  c->tune = best;
+
+  // 2. wave size: per-ciphertext time of a level for 1, 2, 4, ... up to
+  // `fit` ciphertexts; the smallest wave within 3% of the best rate
+  std::vector<std::pair<int, double>> rates;
+  for (int n = 1;; n = std::min(2 * n, fit)) {
+    Ws wn = carve(c, ws, n);
+    rc = load_sample(c, wn, sample, n_sample, n, st);
+    if (rc) { c->tune = start; return rc; }
+    double t = 0.0;
+    rc = time_level(c, wn, n, st, &t);
+    if (rc) { c->tune = start; return rc; }
+    rates.emplace_back(n, t / n);
+    if (n == fit) break;
+  }
+  double rbest = 1e300;
+  for (auto& r : rates) rbest = std::min(rbest, r.second);
+  for (auto& r : rates)
+    if (r.second <= 1.03 * rbest) { best.wave_ct = r.first; break; }
+  drop_graphs(c);
+  c->tune = best;
+  if (out) *out = best;
+  if (ms_per_ct) *ms_per_ct = rbest;
   return NSHE_OK;
 }
 
@@ -969,6 +1222,7 @@ int nshe_ntt(nshe_ctx* c, const int64_t* in, int64_t* out, int n_poly, int inver
   HIPCHK(run_i64_to_dbl_limbs((size_t)n_poly * c->L, c->n, in, buf, c->lp_ext, c->L, c->tb, st));
   double* res = buf + (size_t)n_poly * c->L * c->n;
   NttJob j{};
+  j.split = c->tune.split_forward;
   j.base = buf;
   j.out = res;
   j.poly_stride = (size_t)c->L * c->n;

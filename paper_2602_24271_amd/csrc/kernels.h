@@ -68,6 +68,7 @@ struct NttJob {
   const double* src_b;
   size_t src_ct_stride;      // doubles between ciphertexts in src
   int digits;                // L (digits per ciphertext)
+  int split = 1;             // 2^15-point forward: two workgroups per limb
 };
 
 // run_ntt directions: 0 forward in place, 1 inverse in place, 2 forward of
@@ -82,6 +83,9 @@ struct Dims {
   int L;        // data primes
   int LB;       // extension primes (= L + 1)
   int n_ct;     // ciphertexts in the call
+  // launch shape (tunable; results do not depend on it)
+  int block = 256;     // threads per workgroup of lift, scale and mod-down
+  int ks_chunk = 16;   // ciphertexts per pass over the key in k_ks_mac
 };
 
 hipError_t run_lift(const Dims& d, double* ext, const Tables& tb, hipStream_t st);
@@ -94,6 +98,27 @@ hipError_t run_moddown(const Dims& d, const double* acc, const double* dt, doubl
 // conversions at the boundary
 hipError_t run_sub_to_ext(const Dims& d, const int64_t* x, const int64_t* y, int y_bcast,
                           double* ext, const Tables& tb, hipStream_t st);
+// batched waves (see k_gather_sub): per-ciphertext pointers of a wave
+struct CtPtrs {
+  const int64_t* x;
+  const int64_t* y;
+  int64_t* out;
+};
+hipError_t run_gather_sub(const Dims& d, int stride, const CtPtrs* table, const int* wave,
+                          double* ext, const Tables& tb, hipStream_t st);
+hipError_t run_scatter_mask(const Dims& d, int stride, const CtPtrs* table, const int* wave,
+                            const double* ext, const Tables& tb, hipStream_t st);
+// table entries [first, first + n) passed by value (kernel arguments are
+// copied at launch, so the host array may be reused at once)
+struct TableChunk {
+  static constexpr int CAP = 128;
+  CtPtrs e[CAP];
+  int first;
+  int n;
+};
+hipError_t run_fill_table(const TableChunk& ch, CtPtrs* table, hipStream_t st);
+hipError_t run_set_counter(int* counter, int v, hipStream_t st);
+hipError_t run_bump_counter(int* counter, hipStream_t st);
 hipError_t run_sub_i64(const Dims& d, const int64_t* x, const int64_t* y, int64_t* out,
                        const Tables& tb, hipStream_t st);
 // int64 [0, q) -> balanced doubles; polys with index >= canon_from keep the

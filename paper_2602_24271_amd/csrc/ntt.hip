@@ -634,7 +634,7 @@ template <int LOGN>
 static hipError_t launch_ntt(const NttJob& job, const Tables& tb, int dir, hipStream_t st) {
   using S = NttShape<LOGN>;
   if constexpr (LOGN == 15) {
-    if (((dir == 0 && job.out && job.out != job.base) || dir == 2) && tb.tw_half) {
+    if (((dir == 0 && job.out && job.out != job.base) || dir == 2) && tb.tw_half && job.split) {
       dim3 grid(per_xcd(job, dir, 2) * 8), block(512);
       if (dir == 0)
         hipLaunchKernelGGL((k_ntt_fwd_half<NTT_INPLACE>), grid, block, 0, st, job, tb);

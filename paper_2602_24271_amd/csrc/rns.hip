@@ -237,6 +237,61 @@ __global__ void __launch_bounds__(256) k_sub_to_ext(int n, int L, int n_ct, cons
   ext[((ct * 2 + b) * (size_t)(2 * L + 1) + i) * n + c] = reduce_bal(xv - yv, p, pinv);
 }
 
+// Batched waves: the ciphertexts of a wave are named by a device table of
+// per-ciphertext pointers, [wave][stride] entries, and the wave by a device
+// counter, so one captured graph serves every wave of the same size.
+__global__ void __launch_bounds__(256) k_gather_sub(int n, int L, int cnt, int stride,
+                                                    const CtPtrs* table, const int* wave,
+                                                    double* ext, Tables tb) {
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t per_ct = (size_t)2 * L * n;
+  if (gid >= (size_t)cnt * per_ct) return;
+  const size_t ct = gid / per_ct;
+  const size_t r = gid - ct * per_ct;       // (b * L + i) * n + c
+  const CtPtrs e = table[(size_t)(*wave) * stride + ct];
+  const int i = (int)((r / n) % L);
+  const double p = cld(tb.p, i), pinv = cld(tb.pinv, i);
+  const double xv = (double)e.x[r];
+  const double yv = (double)e.y[r];
+  const size_t bi = r / n;
+  const int b = (int)(bi / L);
+  const int c = (int)(r - bi * n);
+  ext[((ct * 2 + b) * (size_t)(2 * L + 1) + i) * n + c] = reduce_bal(xv - yv, p, pinv);
+}
+
+// out = ([-z0 + Delta e_0]_q, [-z1]_q) of the wave's ciphertexts in ext.
+__global__ void __launch_bounds__(256) k_scatter_mask(int n, int L, int cnt, int stride,
+                                                      const CtPtrs* table, const int* wave,
+                                                      const double* ext, Tables tb) {
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t per_ct = (size_t)2 * L * n;
+  if (gid >= (size_t)cnt * per_ct) return;
+  const size_t ct = gid / per_ct;
+  const size_t r = gid - ct * per_ct;
+  const CtPtrs e = table[(size_t)(*wave) * stride + ct];
+  const size_t bi = r / n;
+  const int b = (int)(bi / L);
+  const int i = (int)(bi - (size_t)b * L);
+  const int c = (int)(r - bi * n);
+  const double p = cld(tb.p, i), pinv = cld(tb.pinv, i);
+  double v = -ext[((ct * 2 + b) * (size_t)(2 * L + 1) + i) * n + c];
+  if (b == 0 && c == 0) v = reduce_bal(v + cld(tb.delta_q, i), p, pinv);
+  e.out[r] = to_i64(v, p);
+}
+
+__global__ void k_fill_table(TableChunk ch, CtPtrs* table) {
+  const int i = threadIdx.x;
+  if (i < ch.n) table[ch.first + i] = ch.e[i];
+}
+
+__global__ void k_set_counter(int* counter, int v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) counter[0] = v;
+}
+
+__global__ void k_bump_counter(int* counter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) counter[0] += 1;
+}
+
 __global__ void __launch_bounds__(256) k_sub_i64(int n, int L, size_t total, const int64_t* x,
                                                  const int64_t* y, int64_t* out, Tables tb) {
   const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -327,7 +382,9 @@ __global__ void __launch_bounds__(256) k_ntt_order(size_t total, int log2n, int 
 
 // ---------------------------------------------------------------- host ---
 
-static inline dim3 grid_for(size_t total) { return dim3((unsigned)((total + 255) / 256)); }
+static inline dim3 grid_for(size_t total, int block = 256) {
+  return dim3((unsigned)((total + block - 1) / block));
+}
 
 #define NSHE_L_CASES(X) X(2) X(3) X(4) X(8) X(12) X(16) X(17) X(20) X(24)
 
@@ -335,7 +392,7 @@ hipError_t run_lift(const Dims& d, double* ext, const Tables& tb, hipStream_t st
   const size_t np = (size_t)d.n_ct * 2;
   switch (d.L) {
 #define C_(L_) \
-  case L_: hipLaunchKernelGGL(k_lift<L_>, grid_for(np * d.n), dim3(256), 0, st, d.n, np, ext, tb); break;
+  case L_: hipLaunchKernelGGL(k_lift<L_>, grid_for(np * d.n, d.block), dim3(d.block), 0, st, d.n, np, ext, tb); break;
     NSHE_L_CASES(C_)
 #undef C_
     default: return hipErrorInvalidValue;
@@ -351,7 +408,7 @@ hipError_t run_scale(const Dims& d, double* dt, const Tables& tb, hipStream_t st
   const size_t np = (size_t)d.n_ct * 3;
   switch (d.L) {
 #define C_(L_) \
-  case L_: hipLaunchKernelGGL(k_scale<L_>, grid_for(np * d.n), dim3(256), 0, st, d.n, np, dt, tb); break;
+  case L_: hipLaunchKernelGGL(k_scale<L_>, grid_for(np * d.n, d.block), dim3(d.block), 0, st, d.n, np, dt, tb); break;
     NSHE_L_CASES(C_)
 #undef C_
     default: return hipErrorInvalidValue;
@@ -364,7 +421,16 @@ hipError_t run_ks_mac(const Dims& d, const double* dig, const double* evk, doubl
   const size_t total = (size_t)(d.L + 1) * d.n;
   switch (d.L) {
 #define C_(L_) \
-  case L_: hipLaunchKernelGGL((k_ks_mac<L_, 16>), grid_for(total), dim3(256), 0, st, d.n, d.n_ct, dig, evk, acc, tb); break;
+  case L_:                                                                                     \
+    if (d.ks_chunk == 4)                                                                       \
+      hipLaunchKernelGGL((k_ks_mac<L_, 4>), grid_for(total), dim3(256), 0, st, d.n, d.n_ct, dig, evk, acc, tb); \
+    else if (d.ks_chunk == 8)                                                                  \
+      hipLaunchKernelGGL((k_ks_mac<L_, 8>), grid_for(total), dim3(256), 0, st, d.n, d.n_ct, dig, evk, acc, tb); \
+    else if (d.ks_chunk == 32)                                                                 \
+      hipLaunchKernelGGL((k_ks_mac<L_, 32>), grid_for(total), dim3(256), 0, st, d.n, d.n_ct, dig, evk, acc, tb); \
+    else                                                                                       \
+      hipLaunchKernelGGL((k_ks_mac<L_, 16>), grid_for(total), dim3(256), 0, st, d.n, d.n_ct, dig, evk, acc, tb); \
+    break;
     NSHE_L_CASES(C_)
 #undef C_
     default: return hipErrorInvalidValue;
@@ -377,7 +443,7 @@ hipError_t run_moddown(const Dims& d, const double* acc, const double* dt, doubl
   const size_t total = (size_t)d.n_ct * 2 * d.n;
   switch (d.L) {
 #define C_(L_) \
-  case L_: hipLaunchKernelGGL(k_moddown<L_>, grid_for(total), dim3(256), 0, st, d.n, d.n_ct, acc, dt, ext, tb); break;
+  case L_: hipLaunchKernelGGL(k_moddown<L_>, grid_for(total, d.block), dim3(d.block), 0, st, d.n, d.n_ct, acc, dt, ext, tb); break;
     NSHE_L_CASES(C_)
 #undef C_
     default: return hipErrorInvalidValue;
@@ -390,6 +456,37 @@ hipError_t run_sub_to_ext(const Dims& d, const int64_t* x, const int64_t* y, int
   const size_t total = (size_t)d.n_ct * 2 * d.L * d.n;
   hipLaunchKernelGGL(k_sub_to_ext, grid_for(total), dim3(256), 0, st, d.n, d.L, d.n_ct, x, y,
                      y_bcast, ext, tb);
+  return hipGetLastError();
+}
+
+hipError_t run_gather_sub(const Dims& d, int stride, const CtPtrs* table, const int* wave,
+                          double* ext, const Tables& tb, hipStream_t st) {
+  const size_t total = (size_t)d.n_ct * 2 * d.L * d.n;
+  hipLaunchKernelGGL(k_gather_sub, grid_for(total), dim3(256), 0, st, d.n, d.L, d.n_ct, stride,
+                     table, wave, ext, tb);
+  return hipGetLastError();
+}
+
+hipError_t run_scatter_mask(const Dims& d, int stride, const CtPtrs* table, const int* wave,
+                            const double* ext, const Tables& tb, hipStream_t st) {
+  const size_t total = (size_t)d.n_ct * 2 * d.L * d.n;
+  hipLaunchKernelGGL(k_scatter_mask, grid_for(total), dim3(256), 0, st, d.n, d.L, d.n_ct, stride,
+                     table, wave, ext, tb);
+  return hipGetLastError();
+}
+
+hipError_t run_fill_table(const TableChunk& ch, CtPtrs* table, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_table, dim3(1), dim3(TableChunk::CAP), 0, st, ch, table);
+  return hipGetLastError();
+}
+
+hipError_t run_set_counter(int* counter, int v, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_counter, dim3(1), dim3(64), 0, st, counter, v);
+  return hipGetLastError();
+}
+
+hipError_t run_bump_counter(int* counter, hipStream_t st) {
+  hipLaunchKernelGGL(k_bump_counter, dim3(1), dim3(64), 0, st, counter);
   return hipGetLastError();
 }
 

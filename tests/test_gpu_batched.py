@@ -38,3 +38,49 @@ def test_batched_matches_oracle(s256, wave_ct, use_graph):
         for o, w in zip(outs, want):
             for i, ct in enumerate(w):
                 np.testing.assert_array_equal(o[i].cpu().numpy(), S.limbs(ct))
+
+
+def test_tunings_do_not_change_results(s256):
+    """Every launch shape gives the same integers (and the oracle's)."""
+    S = s256
+    items, want = _instances(S, [2, 1], 70)
+    start = S.ctx.tuning()
+    try:
+        for ks, blk in [(4, 64), (8, 128), (32, 256)]:
+            S.ctx.set_tuning(ks_chunk=ks, ew_block=blk)
+            outs = S.ctx.eq_mask_batched(items, wave_ct=3, use_graph=True)
+            torch.cuda.synchronize()
+            for o, w in zip(outs, want):
+                for i, ct in enumerate(w):
+                    np.testing.assert_array_equal(o[i].cpu().numpy(), S.limbs(ct))
+    finally:
+        S.ctx.set_tuning(**start)
+
+
+def test_set_tuning_rejects_bad_values(s256):
+    from paper_2602_24271_amd._lib import NsheError
+    for bad in [dict(ks_chunk=5), dict(ew_block=32), dict(split_forward=2), dict(wave_ct=-1)]:
+        with pytest.raises(NsheError):
+            s256.ctx.set_tuning(**bad)
+
+
+def test_autotune_then_batched(s256):
+    """The autotuner picks valid shapes and a wave; the batched call that
+    uses them (wave_ct = 0) still matches the oracle."""
+    S = s256
+    items, want = _instances(S, [3, 2, 1], 90)
+    start = S.ctx.tuning()
+    try:
+        tuned = S.ctx.autotune(items[0][0], max_wave_ct=4)
+        assert tuned["ks_chunk"] in (4, 8, 16, 32)
+        assert tuned["ew_block"] in (64, 128, 256)
+        assert 1 <= tuned["wave_ct"] <= 4
+        assert tuned["ms_per_ct"] > 0
+        assert {k: tuned[k] for k in start} == S.ctx.tuning()
+        outs = S.ctx.eq_mask_batched(items, wave_ct=0, use_graph=True)
+        torch.cuda.synchronize()
+        for o, w in zip(outs, want):
+            for i, ct in enumerate(w):
+                np.testing.assert_array_equal(o[i].cpu().numpy(), S.limbs(ct))
+    finally:
+        S.ctx.set_tuning(**start)

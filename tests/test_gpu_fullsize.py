@@ -37,6 +37,15 @@ def test_full_size_square_and_mask(s32k):
     dz = S.ctx.sub(S.to_dev([cx]), S.to_dev([cy]))
     got1 = S.ctx.square_relin(dz)
     np.testing.assert_array_equal(got1[0].cpu().numpy(), S.limbs(want1))
+    # the other launch shapes (one workgroup per forward limb, other key
+    # chunks and block sizes) give the same integers
+    start = S.ctx.tuning()
+    try:
+        S.ctx.set_tuning(split_forward=0, ks_chunk=4, ew_block=64)
+        got2 = S.ctx.square_relin(dz)
+        np.testing.assert_array_equal(got2[0].cpu().numpy(), S.limbs(want1))
+    finally:
+        S.ctx.set_tuning(**start)
     out = S.ctx.eq_mask(S.to_dev([cx]), S.to_dev([cy]))
     got = S.from_dev(out)[0]
     mask = bfv.decrypt_slots(S.pr, S.sk, got)
