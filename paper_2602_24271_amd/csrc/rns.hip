@@ -170,7 +170,7 @@ __global__ void __launch_bounds__(256) k_ks_mac(int n, int n_ct, const double* d
 #pragma unroll
       for (int u = 0; u < CH; ++u) {
         if (c0 + u < n_ct) {
-          const double dv = dig[((size_t)((c0 + u) * L + j) * K + i) * n + c];
+          const double dv = __builtin_nontemporal_load(&dig[((size_t)((c0 + u) * L + j) * K + i) * n + c]);
           a0[u] += mul_lazy(dv, e0, p, pinv);
           a1[u] += mul_lazy(dv, e1, p, pinv);
         }
