@@ -24,6 +24,8 @@ Modules
   encoding  batch encoding of slot vectors (client side)
   bfv       parameters, keys, encryption, textbook multiply/relinearize, EQ,
             decryption and noise
+  query     operators built on EQ: IN (Eq. eq:in), GROUP BY masks, SELECT
+            (Eq. eq:select), BFV addition
   ntt_def   the negacyclic number-theoretic transform written from its
             definition (O(N^2)), for checking a device transform's output
 
