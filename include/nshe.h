@@ -188,6 +188,34 @@ int nshe_eq_mask_batched(nshe_ctx* ctx, const nshe_item* items_host,
                          int n_items, int wave_ct, int use_graph, void* ws_dev,
                          size_t ws_bytes, void* stream);
 
+/* BFV addition (Sec. 2.1.5): out = [a + b]_Q per residue, int64
+ * [n_ct][2][L][N] canonical residues.  No workspace. */
+int nshe_add(nshe_ctx* ctx, const int64_t* a_dev, const int64_t* b_dev,
+             int64_t* out_dev, int n_ct, void* stream);
+
+/* Sum of k ciphertext arrays: in_dev is int64 [k][n_ct][2][L][N], out_dev
+ * [n_ct][2][L][N] = [sum_j in[j]]_Q.  k = 0 writes the encryption (0, 0).
+ * BFV addition is exact per residue, so the order of the sum does not
+ * change the result. */
+int nshe_sum(nshe_ctx* ctx, const int64_t* in_dev, int k, int64_t* out_dev,
+             int n_ct, void* stream);
+
+/* Set membership, IN(x, S) = sum over y in S of EQ(x, y) (Eq. eq:in,
+ * Sec. 4.3 range and set queries): x_dev is one column of n_ct
+ * ciphertexts, set_dev holds the k members as k single ciphertexts
+ * (int64 [k][2][L][N], each broadcast over the column).  With distinct
+ * members out_dev decrypts to the indicator [x in S]; a member given twice
+ * counts twice.  The k equality masks run as one batched call (waves of
+ * wave_ct ciphertexts, 0 = the tuned wave else 32; use_graph as for
+ * nshe_eq_mask_batched) into the workspace, then are summed.  GROUP BY
+ * (one mask per group value, Sec. 4.3) is nshe_eq_mask_batched with items
+ * (x, value_j, out_j, n_ct, y_broadcast = 1).  ws_bytes must cover
+ * nshe_in_workspace_bytes(ctx, n_ct, k, wave_ct). */
+size_t nshe_in_workspace_bytes(const nshe_ctx* ctx, int n_ct, int k, int wave_ct);
+int nshe_in_mask(nshe_ctx* ctx, const int64_t* x_dev, const int64_t* set_dev, int k,
+                 int64_t* out_dev, int n_ct, int wave_ct, int use_graph,
+                 void* ws_dev, size_t ws_bytes, void* stream);
+
 /* Launch shapes and the autotuner.  Results never depend on the tuning
  * (every kernel computes the same exact integers); only the speed does.
  *   ks_chunk       ciphertexts accumulated per pass over the relinearization

@@ -59,6 +59,10 @@ SIGNATURES = {
     "nshe_eq_mask": (_I, [_P, _P, _P, _P, _I, _I, _P, _SZ, _P]),
     "nshe_batched_workspace_bytes": (_SZ, [_P, _I, ctypes.c_longlong]),
     "nshe_eq_mask_batched": (_I, [_P, ctypes.POINTER(NsheItem), _I, _I, _I, _P, _SZ, _P]),
+    "nshe_add": (_I, [_P, _P, _P, _P, _I, _P]),
+    "nshe_sum": (_I, [_P, _P, _I, _P, _I, _P]),
+    "nshe_in_workspace_bytes": (_SZ, [_P, _I, _I, _I]),
+    "nshe_in_mask": (_I, [_P, _P, _P, _I, _P, _I, _I, _I, _P, _SZ, _P]),
     "nshe_get_tuning": (_I, [_P, ctypes.POINTER(NsheTuning)]),
     "nshe_set_tuning": (_I, [_P, ctypes.POINTER(NsheTuning)]),
     "nshe_autotune": (_I, [_P, _P, _I, _I, _P, _SZ, _P, ctypes.POINTER(NsheTuning),

@@ -105,6 +105,49 @@ class Context:
         _lib.check(self._lib.nshe_sub(self._h, _ptr(x), _ptr(y), _ptr(out), n, _stream()))
         return out
 
+    def add(self, a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
+        n = self._check_ct(a)
+        if self._check_ct(b) != n:
+            raise ValueError("a and b must hold the same number of ciphertexts")
+        out = torch.empty_like(a)
+        _lib.check(self._lib.nshe_add(self._h, _ptr(a), _ptr(b), _ptr(out), n, _stream()))
+        return out
+
+    def sum(self, cts: torch.Tensor) -> torch.Tensor:
+        """cts: int64 [k][n_ct][2][L][N] -> their sum [n_ct][2][L][N]."""
+        if cts.dim() != 5 or not cts.is_contiguous() or cts.dtype != torch.int64:
+            raise ValueError("expected a contiguous int64 [k][n_ct][2][L][N] tensor")
+        k = int(cts.shape[0])
+        n = int(cts.shape[1])
+        out = torch.empty(self.ct_shape(n), dtype=torch.int64, device=cts.device)
+        _lib.check(self._lib.nshe_sum(self._h, _ptr(cts), k, _ptr(out), n, _stream()))
+        return out
+
+    def in_mask(self, x: torch.Tensor, members: torch.Tensor, wave_ct: int = 0,
+                use_graph: bool = True) -> torch.Tensor:
+        """IN(x, S) (Eq. eq:in); members: k single ciphertexts [k][2][L][N]."""
+        n = self._check_ct(x)
+        k = self._check_ct(members)
+        out = torch.empty_like(x)
+        need = int(self._lib.nshe_in_workspace_bytes(self._h, n, k, wave_ct))
+        ws = self._workspace_bytes(need)
+        _lib.check(self._lib.nshe_in_mask(self._h, _ptr(x), _ptr(members), k, _ptr(out), n,
+                                          wave_ct, 1 if use_graph else 0, _ptr(ws), ws.numel(),
+                                          _stream()))
+        return out
+
+    def group_masks(self, x: torch.Tensor, values: torch.Tensor, wave_ct: int = 0,
+                    use_graph: bool = True) -> list:
+        """GROUP BY: EQ(x, v) for each of the k encrypted group values
+        (values: [k][2][L][N]), as one batched call."""
+        self._check_ct(values)
+        items = [(x, values[j:j + 1]) for j in range(values.shape[0])]
+        return self.eq_mask_batched(items, wave_ct=wave_ct, use_graph=use_graph)
+
+    def select(self, column: torch.Tensor, mask: torch.Tensor) -> torch.Tensor:
+        """SELECT column WHERE mask (Eq. eq:select): column * mask, relinearized."""
+        return self.mul_relin(column, mask)
+
     def square_relin(self, x: torch.Tensor) -> torch.Tensor:
         n = self._check_ct(x)
         out = torch.empty_like(x)

@@ -709,6 +709,35 @@ int nshe_sub(nshe_ctx* c, const int64_t* x, const int64_t* y, int64_t* out, int 
   return NSHE_OK;
 }
 
+int nshe_add(nshe_ctx* c, const int64_t* a, const int64_t* b, int64_t* out, int n_ct,
+             void* stream) {
+  g_err.clear();
+  if (check_ctx(c)) return NSHE_EINVAL;
+  if (n_ct < 0) return fail(NSHE_ESHAPE, "n_ct < 0");
+  if (n_ct == 0) return NSHE_OK;
+  if (!a || !b || !out) return fail(NSHE_EINVAL, "null buffer");
+  if (set_device(c)) return NSHE_EDEVICE;
+  HIPCHK(run_sum_i64(dims(c, n_ct), a, b, 0, 1, out, c->tb, static_cast<hipStream_t>(stream)));
+  return NSHE_OK;
+}
+
+int nshe_sum(nshe_ctx* c, const int64_t* in, int k, int64_t* out, int n_ct, void* stream) {
+  g_err.clear();
+  if (check_ctx(c)) return NSHE_EINVAL;
+  if (n_ct < 0 || k < 0) return fail(NSHE_ESHAPE, "n_ct < 0 or k < 0");
+  if (n_ct == 0) return NSHE_OK;
+  if (!out || (k > 0 && !in)) return fail(NSHE_EINVAL, "null buffer");
+  if (set_device(c)) return NSHE_EDEVICE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t words = (size_t)n_ct * 2 * c->L * c->n;
+  if (k == 0) {
+    HIPCHK(hipMemsetAsync(out, 0, words * sizeof(int64_t), st));  // the encryption (0, 0)
+    return NSHE_OK;
+  }
+  HIPCHK(run_sum_i64(dims(c, n_ct), in, in + words, words, k - 1, out, c->tb, st));
+  return NSHE_OK;
+}
+
 static int common_checks(nshe_ctx* c, int n_ct, void* ws, size_t ws_bytes, bool need_key) {
   g_err.clear();
   if (check_ctx(c)) return NSHE_EINVAL;
@@ -1003,6 +1032,50 @@ int nshe_eq_mask_batched(nshe_ctx* c, const nshe_item* items, int n_items, int w
     HIPCHK(hipGraphLaunch(found->second.exec, st));
   }
   return NSHE_OK;
+}
+
+// ------------------------------------------------------------ IN / GROUP BY
+
+static int in_wave(const nshe_ctx* c, int wave_ct, long long total) {
+  if (wave_ct <= 0) wave_ct = c->tune.wave_ct > 0 ? c->tune.wave_ct : 32;
+  return (int)std::min<long long>(wave_ct, total);
+}
+
+static size_t in_masks_bytes(const nshe_ctx* c, int n_ct, int k) {
+  return ((size_t)k * n_ct * 2 * c->L * c->n * sizeof(int64_t) + 255) & ~(size_t)255;
+}
+
+size_t nshe_in_workspace_bytes(const nshe_ctx* c, int n_ct, int k, int wave_ct) {
+  if (check_ctx(c) || n_ct < 0 || k < 0 || wave_ct < 0) return 0;
+  const long long total = (long long)k * n_ct;
+  if (total == 0) return 256;
+  return in_masks_bytes(c, n_ct, k) + batched_ws_bytes(c, in_wave(c, wave_ct, total), total);
+}
+
+int nshe_in_mask(nshe_ctx* c, const int64_t* x, const int64_t* set, int k, int64_t* out, int n_ct,
+                 int wave_ct, int use_graph, void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  if (check_ctx(c)) return NSHE_EINVAL;
+  if (n_ct < 0 || k < 0 || wave_ct < 0) return fail(NSHE_ESHAPE, "n_ct, k or wave_ct < 0");
+  if (n_ct == 0) return NSHE_OK;
+  if (!x || !out || (k > 0 && !set)) return fail(NSHE_EINVAL, "null buffer");
+  if (k == 0) return nshe_sum(c, nullptr, 0, out, n_ct, stream);
+  if (!ws) return fail(NSHE_EINVAL, "workspace pointer is null");
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(NSHE_EINVAL, "workspace not 256-byte aligned");
+  const long long total = (long long)k * n_ct;
+  const int wave = in_wave(c, wave_ct, total);
+  const size_t mb = in_masks_bytes(c, n_ct, k);
+  if (ws_bytes < mb + batched_ws_bytes(c, wave, total))
+    return fail(NSHE_ENOMEM, "workspace smaller than nshe_in_workspace_bytes(ctx, n_ct, k, wave_ct)");
+  const size_t ctw = (size_t)2 * c->L * c->n;
+  int64_t* masks = static_cast<int64_t*>(ws);
+  std::vector<nshe_item> items((size_t)k);
+  for (int j = 0; j < k; ++j)
+    items[j] = nshe_item{x, set + (size_t)j * ctw, masks + (size_t)j * n_ct * ctw, n_ct, 1};
+  int rc = nshe_eq_mask_batched(c, items.data(), k, wave, use_graph, static_cast<char*>(ws) + mb,
+                                ws_bytes - mb, stream);
+  if (rc) return rc;
+  return nshe_sum(c, masks, k, out, n_ct, stream);
 }
 
 // ---------------------------------------------------------------- tuning

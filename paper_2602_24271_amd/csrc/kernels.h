@@ -98,6 +98,9 @@ hipError_t run_moddown(const Dims& d, const double* acc, const double* dt, doubl
 // conversions at the boundary
 hipError_t run_sub_to_ext(const Dims& d, const int64_t* x, const int64_t* y, int y_bcast,
                           double* ext, const Tables& tb, hipStream_t st);
+// out = a + sum_{j < k} b[j * stride] (canonical int64 ciphertexts)
+hipError_t run_sum_i64(const Dims& d, const int64_t* a, const int64_t* b, size_t stride, int k,
+                       int64_t* out, const Tables& tb, hipStream_t st);
 // batched waves (see k_gather_sub): per-ciphertext pointers of a wave
 struct CtPtrs {
   const int64_t* x;

@@ -237,6 +237,24 @@ __global__ void __launch_bounds__(256) k_sub_to_ext(int n, int L, int n_ct, cons
   ext[((ct * 2 + b) * (size_t)(2 * L + 1) + i) * n + c] = reduce_bal(xv - yv, p, pinv);
 }
 
+// out = [a + sum_{j < k} b[j * stride]]_q per residue (BFV addition of
+// canonical residues; each partial sum is kept in [0, q) by one
+// conditional subtraction, so any k is exact).
+__global__ void __launch_bounds__(256) k_sum_i64(int n, int L, size_t total, const int64_t* a,
+                                                 const int64_t* b, size_t stride, int k,
+                                                 int64_t* out, Tables tb) {
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= total) return;
+  const int i = (int)((gid / n) % L);
+  const int64_t q = (int64_t)cld(tb.p, i);
+  int64_t s = a[gid];
+  for (int j = 0; j < k; ++j) {
+    s += b[(size_t)j * stride + gid];
+    s = s >= q ? s - q : s;
+  }
+  out[gid] = s;
+}
+
 // Batched waves: the ciphertexts of a wave are named by a device table of
 // per-ciphertext pointers, [wave][stride] entries, and the wave by a device
 // counter, so one captured graph serves every wave of the same size.
@@ -456,6 +474,14 @@ hipError_t run_sub_to_ext(const Dims& d, const int64_t* x, const int64_t* y, int
   const size_t total = (size_t)d.n_ct * 2 * d.L * d.n;
   hipLaunchKernelGGL(k_sub_to_ext, grid_for(total), dim3(256), 0, st, d.n, d.L, d.n_ct, x, y,
                      y_bcast, ext, tb);
+  return hipGetLastError();
+}
+
+hipError_t run_sum_i64(const Dims& d, const int64_t* a, const int64_t* b, size_t stride, int k,
+                       int64_t* out, const Tables& tb, hipStream_t st) {
+  const size_t total = (size_t)d.n_ct * 2 * d.L * d.n;
+  hipLaunchKernelGGL(k_sum_i64, grid_for(total), dim3(256), 0, st, d.n, d.L, total, a, b, stride,
+                     k, out, tb);
   return hipGetLastError();
 }
 
