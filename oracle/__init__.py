@@ -26,6 +26,8 @@ Modules
             decryption and noise
   query     operators built on EQ: IN (Eq. eq:in), GROUP BY masks, SELECT
             (Eq. eq:select), BFV addition
+  galois    slot rotations (automorphisms + key switching) and the
+            rotate-and-add aggregation of COUNT / SUM
   ntt_def   the negacyclic number-theoretic transform written from its
             definition (O(N^2)), for checking a device transform's output
 

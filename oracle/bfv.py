@@ -146,20 +146,28 @@ class RelinKey:
                          for j in range(params.L)])
 
 
-def keygen(params: Params, rnd) -> tuple[SecretKey, RelinKey]:
-    """Secret key and relinearization key from caller-drawn randomness
-    (`synth.key_randomness`)."""
-    s = ring.as_object(rnd.s)
-    s2 = poly_mul(s, s)
+def switching_key(params: Params, s, s_from, a_limbs, errors) -> RelinKey:
+    """Key switching key from s_from to s: per digit j,
+    (b_j, a_j) = ([-a_j s + e_j + P g_j s_from]_{PQ}, a_j)."""
     PQ = params.PQ
+    s = ring.as_object(s)
+    s_from = ring.as_object(s_from)
     bs, as_ = [], []
     for j in range(params.L):
-        a = from_limbs(rnd.a[j], params.moduli_pq)
-        e = ring.as_object(rnd.e[j])
-        b = (-poly_mul(a, s) + e + params.P * params.gadget(j) * s2) % PQ
+        a = from_limbs(a_limbs[j], params.moduli_pq)
+        e = ring.as_object(errors[j])
+        b = (-poly_mul(a, s) + e + params.P * params.gadget(j) * s_from) % PQ
         bs.append(b)
         as_.append(a)
-    return SecretKey(s), RelinKey(bs, as_)
+    return RelinKey(bs, as_)
+
+
+def keygen(params: Params, rnd) -> tuple[SecretKey, RelinKey]:
+    """Secret key and relinearization key (switching from s^2 to s) from
+    caller-drawn randomness (`synth.key_randomness`)."""
+    s = ring.as_object(rnd.s)
+    s2 = poly_mul(s, s)
+    return SecretKey(s), switching_key(params, s, s2, rnd.a, rnd.e)
 
 
 # ------------------------------------------------------ encrypt / decrypt ---
@@ -252,14 +260,18 @@ def _evk_transformed(params: Params, rk: RelinKey, B: ring.OwnBasis):
     return rk._own_cache[key]
 
 
-def relinearize(params: Params, rk: RelinKey, ct3) -> tuple:
-    """Key switching of the s^2 component with one digit per data prime."""
+def key_switch(params: Params, key: RelinKey, c) -> tuple:
+    """Key switching of one polynomial c (coefficients mod Q) with a
+    switching key for some s' (b_j + a_j s = e_j + P g_j s' mod PQ): one
+    digit per data prime, D_j = [c]_{q_j} in [0, q_j), and
+    (round(sum_j D_j b_j / P), round(sum_j D_j a_j / P)) mod Q, whose phase
+    is c * s' plus a small error."""
     Q, P, n = params.Q, params.P, params.n
-    c0, c1, c2 = (ring.as_object(c) for c in ct3)
-    digits = [(c2 % qj).astype(np.int64) for qj in params.q]
+    c = ring.as_object(c)
+    digits = [(c % qj).astype(np.int64) for qj in params.q]
     bound = params.L * max(params.q) * params.PQ * n
     B = ring.OwnBasis(bound, n)
-    evk = _evk_transformed(params, rk, B)
+    evk = _evk_transformed(params, key, B)
     acc0 = np.zeros((len(B.primes), n), dtype=np.int64)
     acc1 = np.zeros_like(acc0)
     for j, dj in enumerate(digits):
@@ -268,7 +280,15 @@ def relinearize(params: Params, rk: RelinKey, ct3) -> tuple:
         acc1 = B.add(acc1, B.mul(fd, evk[j][1]))
     u0 = B.to_int(B.inverse(acc0))
     u1 = B.to_int(B.inverse(acc1))
-    return ((c0 + round_div(u0, P)) % Q, (c1 + round_div(u1, P)) % Q)
+    return (round_div(u0, P) % Q, round_div(u1, P) % Q)
+
+
+def relinearize(params: Params, rk: RelinKey, ct3) -> tuple:
+    """Key switching of the s^2 component with one digit per data prime."""
+    Q = params.Q
+    c0, c1, c2 = (ring.as_object(c) for c in ct3)
+    k0, k1 = key_switch(params, rk, c2)
+    return ((c0 + k0) % Q, (c1 + k1) % Q)
 
 
 def square_relin(params: Params, rk: RelinKey, x) -> tuple:

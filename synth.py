@@ -55,6 +55,20 @@ def key_randomness(seed: int, n: int, moduli_pq, n_digits: int) -> KeyRandomness
 
 
 @dataclass
+class SwitchRandomness:
+    a: list                    # L arrays [len(moduli_pq), N] uniform residues
+    e: list                    # L arrays [N] errors
+
+
+def switch_randomness(seed: int, n: int, moduli_pq, n_digits: int) -> SwitchRandomness:
+    """Randomness of one key switching key (e.g. a Galois key)."""
+    g = _gens(seed, 2 * n_digits)
+    a = [uniform_residues(g[2 * j], moduli_pq, n) for j in range(n_digits)]
+    e = [gaussian(g[2 * j + 1], n) for j in range(n_digits)]
+    return SwitchRandomness(a, e)
+
+
+@dataclass
 class EncRandomness:
     a: np.ndarray              # [L, N] uniform residues mod the data primes
     e: np.ndarray              # [N] errors
