@@ -216,6 +216,32 @@ int nshe_in_mask(nshe_ctx* ctx, const int64_t* x_dev, const int64_t* set_dev, in
                  int64_t* out_dev, int n_ct, int wave_ct, int use_graph,
                  void* ws_dev, size_t ws_bytes, void* stream);
 
+/* Slot rotations and the rotate-and-add aggregation (COUNT and SUM,
+ * Sec. 4.3 aggregation).  Slots follow the 2 x N/2 layout: slot s < N/2 is
+ * the plaintext's value at psi^(3^s), slot N/2 + s at psi^(-3^s) (psi a
+ * primitive 2N-th root of unity mod t), so the automorphism X -> X^g with
+ * g = 3^r mod 2N rotates each half left by r and g = 2N - 1 swaps the
+ * halves.  A rotation applies X -> X^g to both components and switches the
+ * second from sigma_g(s) back to s with the Galois key of g:
+ *   key_g  int64 [L][2][L+1][N], digit j = ([-a_j s + e_j + P g_j
+ *          sigma_g(s)]_{PQ}, a_j) (the relin key's format with sigma_g(s)
+ *          in place of s^2); copied and transformed into context memory
+ *          (waits for `stream`; allocates on the first key for g);
+ *   out    = ([sigma_g(c0) + round(sum_j D_j b_j / P)]_Q,
+ *             [round(sum_j D_j a_j / P)]_Q), D_j = [sigma_g(c1)]_{q_j}.
+ * nshe_sum_slots replaces each ciphertext by ct + rot(ct) for the Galois
+ * elements nshe_galois_elements lists (rotations by N/4, ..., 1, then the
+ * swap): every slot of the result holds the sum of all slots.  COUNT is
+ * nshe_sum_slots of a 0/1 mask, SUM nshe_sum_slots of a column times the
+ * mask (nshe_mul_relin).  Workspace: nshe_workspace_bytes(ctx, n_ct).
+ * NSHE_ENOKEY names a missing Galois key. */
+int nshe_set_galois_key(nshe_ctx* ctx, uint32_t g, const int64_t* key_dev, void* stream);
+int nshe_galois_elements(const nshe_ctx* ctx, uint32_t* out_host, int max_out, int* n_out_host);
+int nshe_rotate(nshe_ctx* ctx, const int64_t* in_dev, uint32_t g, int64_t* out_dev,
+                int n_ct, void* ws_dev, size_t ws_bytes, void* stream);
+int nshe_sum_slots(nshe_ctx* ctx, const int64_t* in_dev, int64_t* out_dev, int n_ct,
+                   void* ws_dev, size_t ws_bytes, void* stream);
+
 /* Launch shapes and the autotuner.  Results never depend on the tuning
  * (every kernel computes the same exact integers); only the speed does.
  *   ks_chunk       ciphertexts accumulated per pass over the relinearization

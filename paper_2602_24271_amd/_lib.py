@@ -63,6 +63,10 @@ SIGNATURES = {
     "nshe_sum": (_I, [_P, _P, _I, _P, _I, _P]),
     "nshe_in_workspace_bytes": (_SZ, [_P, _I, _I, _I]),
     "nshe_in_mask": (_I, [_P, _P, _P, _I, _P, _I, _I, _I, _P, _SZ, _P]),
+    "nshe_set_galois_key": (_I, [_P, ctypes.c_uint32, _P, _P]),
+    "nshe_galois_elements": (_I, [_P, ctypes.POINTER(ctypes.c_uint32), _I, ctypes.POINTER(_I)]),
+    "nshe_rotate": (_I, [_P, _P, ctypes.c_uint32, _P, _I, _P, _SZ, _P]),
+    "nshe_sum_slots": (_I, [_P, _P, _P, _I, _P, _SZ, _P]),
     "nshe_get_tuning": (_I, [_P, ctypes.POINTER(NsheTuning)]),
     "nshe_set_tuning": (_I, [_P, ctypes.POINTER(NsheTuning)]),
     "nshe_autotune": (_I, [_P, _P, _I, _I, _P, _SZ, _P, ctypes.POINTER(NsheTuning),

@@ -148,6 +148,38 @@ class Context:
         """SELECT column WHERE mask (Eq. eq:select): column * mask, relinearized."""
         return self.mul_relin(column, mask)
 
+    def galois_elements(self) -> list:
+        """Galois elements whose keys nshe_sum_slots needs, in order of use."""
+        n = ctypes.c_int(0)
+        buf = (ctypes.c_uint32 * 64)()
+        _lib.check(self._lib.nshe_galois_elements(self._h, buf, 64, ctypes.byref(n)))
+        return [int(buf[i]) for i in range(n.value)]
+
+    def set_galois_key(self, g: int, key: torch.Tensor) -> None:
+        if key.dtype != torch.int64 or not key.is_contiguous() or key.device != self.device:
+            raise ValueError("key must be a contiguous int64 tensor on the context device")
+        if tuple(key.shape) != (self.L, 2, self.L + 1, self.n):
+            raise ValueError("key must have shape [L, 2, L+1, N]")
+        _lib.check(self._lib.nshe_set_galois_key(self._h, g, _ptr(key), _stream()))
+
+    def rotate(self, x: torch.Tensor, g: int) -> torch.Tensor:
+        n = self._check_ct(x)
+        out = torch.empty_like(x)
+        ws = self.workspace(n)
+        _lib.check(self._lib.nshe_rotate(self._h, _ptr(x), g, _ptr(out), n, _ptr(ws), ws.numel(),
+                                         _stream()))
+        return out
+
+    def sum_slots(self, x: torch.Tensor) -> torch.Tensor:
+        """COUNT / SUM aggregation: every slot of the result holds the sum of
+        all slots of its ciphertext."""
+        n = self._check_ct(x)
+        out = torch.empty_like(x)
+        ws = self.workspace(n)
+        _lib.check(self._lib.nshe_sum_slots(self._h, _ptr(x), _ptr(out), n, _ptr(ws), ws.numel(),
+                                            _stream()))
+        return out
+
     def square_relin(self, x: torch.Tensor) -> torch.Tensor:
         n = self._check_ct(x)
         out = torch.empty_like(x)

@@ -139,6 +139,7 @@ struct nshe_ctx {
   std::vector<hipEvent_t> pool;
   hipStream_t cap_stream = nullptr;  // capture-only stream (the null stream cannot capture)
   nshe_tuning tune{16, 1, 256, 0};
+  std::map<uint32_t, double*> galois;  // Galois element -> switching key (NTT domain)
 };
 
 namespace nshe {
@@ -162,10 +163,10 @@ static Dims dims(const nshe_ctx* c, int n_ct) {
 // ------------------------------------------------------------ profiling
 
 enum Kind { K_SUB, K_LIFT, K_NTT_FWD, K_NTT_INV_TENSOR, K_NTT_INV, K_SCALE, K_NTT_DIGIT,
-            K_KS_MAC, K_MODDOWN, K_CONVERT, K_COUNT };
+            K_KS_MAC, K_MODDOWN, K_CONVERT, K_AUTOMORPH, K_ADD, K_COUNT };
 static const char* kKindName[K_COUNT] = {"sub",   "lift",      "ntt_fwd", "ntt_inv_tensor",
                                          "ntt_inv", "scale", "ntt_digit", "ks_mac",
-                                         "moddown", "convert"};
+                                         "moddown", "convert", "automorph", "add"};
 
 static hipEvent_t take_event(nshe_ctx* c) {
   if (!c->pool.empty()) {
@@ -318,8 +319,13 @@ static int tensor_scale(nshe_ctx* c, const Ws& w, const double* fx_b, int n_ct, 
   return NSHE_OK;
 }
 
-// Relinearize the components in dt (limbs 0..L-1) into ext limbs 0..L-1.
-static int relin(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st) {
+// Key-switch the third component in dt (limbs 0..L-1, canonical) with
+// `key` (the relinearization key unless given) and add the result to the
+// first two: (c0 + k0, c1 + k1) into `out` (ext unless given), limbs 0..L-1.
+static int relin(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st,
+                 const double* key = nullptr, double* out = nullptr) {
+  if (!key) key = c->evk;
+  if (!out) out = w.ext;
   Dims d = dims(c, n_ct);
   NttJob j{};
   j.split = c->tune.split_forward;
@@ -339,13 +345,13 @@ static int relin(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st) {
   }
   {
     Prof pf(c, K_KS_MAC, st, (double)n_ct * c->L * 2 * (c->L + 1) * c->n);
-    HIPCHK(run_ks_mac(d, w.dig, c->evk, w.acc, c->tb, st));
+    HIPCHK(run_ks_mac(d, w.dig, key, w.acc, c->tb, st));
   }
   int rc = ntt_job_ks(c, w.acc, nullptr, n_ct * 2, 1, st);
   if (rc) return rc;
   {
     Prof pf(c, K_MODDOWN, st, 2.0 * n_ct * c->n);
-    HIPCHK(run_moddown(d, w.acc, w.dt, w.ext, c->tb, st));
+    HIPCHK(run_moddown(d, w.acc, w.dt, out, c->tb, st));
   }
   return NSHE_OK;
 }
@@ -649,6 +655,7 @@ int nshe_ctx_destroy(nshe_ctx* c) {
   for (auto& e : c->pool) (void)hipEventDestroy(e);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->evk) (void)hipFree(c->evk);
+  for (auto& kv : c->galois) (void)hipFree(kv.second);
   if (c->dev_tables) (void)hipFree(c->dev_tables);
   delete c;
   return NSHE_OK;
@@ -672,28 +679,49 @@ size_t nshe_workspace_bytes(const nshe_ctx* c, int n_ct) {
   return ws_doubles(c, n_ct) * sizeof(double);
 }
 
-int nshe_set_relin_key(nshe_ctx* c, const int64_t* evk_dev, void* stream) {
-  g_err.clear();
-  if (check_ctx(c)) return NSHE_EINVAL;
-  if (!evk_dev) return fail(NSHE_EINVAL, "evk is null");
-  if (set_device(c)) return NSHE_EDEVICE;
-  hipStream_t st = static_cast<hipStream_t>(stream);
+// Convert a switching key (int64 [L][2][L+1][N], coefficient domain) into
+// *dst (NTT domain, allocated on first use); waits for the stream.
+static int load_switch_key(nshe_ctx* c, const int64_t* key_dev, double** dst, hipStream_t st) {
   const size_t rows = (size_t)c->L * 2 * (c->L + 1);
-  if (!c->evk) HIPCHK(hipMalloc(&c->evk, rows * c->n * sizeof(double)));
+  if (!*dst) HIPCHK(hipMalloc(dst, rows * c->n * sizeof(double)));
   double* tmp = nullptr;
   HIPCHK(hipMalloc(&tmp, rows * c->n * sizeof(double)));
   int rc = NSHE_OK;
-  hipError_t e = run_i64_to_dbl_limbs(rows, c->n, evk_dev, tmp, c->lp_ks, c->L + 1, c->tb, st);
+  hipError_t e = run_i64_to_dbl_limbs(rows, c->n, key_dev, tmp, c->lp_ks, c->L + 1, c->tb, st);
   if (e != hipSuccess) rc = fail(NSHE_EDEVICE, std::string("key conversion: ") + hipGetErrorString(e));
-  if (!rc) rc = ntt_job_ks(c, tmp, c->evk, c->L * 2, 0, st);
+  if (!rc) rc = ntt_job_ks(c, tmp, *dst, c->L * 2, 0, st);
   if (!rc) {
     e = hipStreamSynchronize(st);
     if (e != hipSuccess) rc = fail(NSHE_EDEVICE, std::string("key transform: ") + hipGetErrorString(e));
   }
   (void)hipFree(tmp);
+  return rc;
+}
+
+int nshe_set_relin_key(nshe_ctx* c, const int64_t* evk_dev, void* stream) {
+  g_err.clear();
+  if (check_ctx(c)) return NSHE_EINVAL;
+  if (!evk_dev) return fail(NSHE_EINVAL, "evk is null");
+  if (set_device(c)) return NSHE_EDEVICE;
+  int rc = load_switch_key(c, evk_dev, &c->evk, static_cast<hipStream_t>(stream));
   if (rc) return rc;
   c->has_key = true;
   return NSHE_OK;
+}
+
+int nshe_set_galois_key(nshe_ctx* c, uint32_t g, const int64_t* key_dev, void* stream) {
+  g_err.clear();
+  if (check_ctx(c)) return NSHE_EINVAL;
+  if (!key_dev) return fail(NSHE_EINVAL, "key is null");
+  if (g % 2 == 0 || g >= 2u * (uint32_t)c->n) return fail(NSHE_EINVAL, "g must be odd and below 2N");
+  if (set_device(c)) return NSHE_EDEVICE;
+  double*& slot = c->galois[g];
+  int rc = load_switch_key(c, key_dev, &slot, static_cast<hipStream_t>(stream));
+  if (rc) {
+    if (slot) (void)hipFree(slot);
+    c->galois.erase(g);
+  }
+  return rc;
 }
 
 int nshe_sub(nshe_ctx* c, const int64_t* x, const int64_t* y, int64_t* out, int n_ct,
@@ -1031,6 +1059,105 @@ int nshe_eq_mask_batched(nshe_ctx* c, const nshe_item* items, int n_items, int w
     }
     HIPCHK(hipGraphLaunch(found->second.exec, st));
   }
+  return NSHE_OK;
+}
+
+// ------------------------------------------------------------- rotations
+
+// Galois elements of the rotate-and-add sum, in order: 3^(N/4), ..., 3^1
+// (rotations of each half of the slots by N/4, ..., 1), then 2N - 1 (swap).
+static std::vector<uint32_t> sum_elements(const nshe_ctx* c) {
+  std::vector<uint32_t> out;
+  const uint64_t two_n = 2ull * c->n;
+  for (int r = c->n / 4; r >= 1; r /= 2) {
+    uint64_t g = 1;
+    for (int k = 0; k < r; ++k) g = g * 3 % two_n;
+    out.push_back((uint32_t)g);
+  }
+  out.push_back((uint32_t)(two_n - 1));
+  return out;
+}
+
+static unsigned inv_mod_2n(const nshe_ctx* c, uint32_t g) {
+  const uint64_t two_n = 2ull * c->n;
+  uint64_t x = 1;
+  for (uint64_t k = 1; k < two_n; ++k) {
+    x = x * g % two_n;
+    if (x == 1) {
+      // g^k = 1, so g^(k-1) = g^-1
+      uint64_t r = 1;
+      for (uint64_t m = 0; m + 1 < k; ++m) r = r * g % two_n;
+      return (unsigned)r;
+    }
+  }
+  return 1;
+}
+
+// One rotation of the ciphertexts in w.ext by Galois element g into `out`
+// ([ct][2][W][N] limbs 0..L-1).
+static int rotate_ext(nshe_ctx* c, const Ws& w, int n_ct, uint32_t g, const double* key,
+                      double* out, hipStream_t st) {
+  Dims d = dims(c, n_ct);
+  {
+    Prof pf(c, K_AUTOMORPH, st, 2.0 * n_ct * c->L * c->n);
+    HIPCHK(run_automorph(d, inv_mod_2n(c, g), w.ext, w.dt, c->tb, st));
+  }
+  return relin(c, w, n_ct, st, key, out);
+}
+
+int nshe_galois_elements(const nshe_ctx* c, uint32_t* out, int max_out, int* n_out) {
+  g_err.clear();
+  if (check_ctx(c) || !n_out || (max_out > 0 && !out)) return fail(NSHE_EINVAL, "null argument");
+  const std::vector<uint32_t> e = sum_elements(c);
+  *n_out = (int)e.size();
+  for (int i = 0; i < (int)e.size() && i < max_out; ++i) out[i] = e[i];
+  return NSHE_OK;
+}
+
+int nshe_rotate(nshe_ctx* c, const int64_t* in, uint32_t g, int64_t* out, int n_ct, void* ws,
+                size_t ws_bytes, void* stream) {
+  int rc = common_checks(c, n_ct, ws, ws_bytes, false);
+  if (rc) return rc;
+  if (n_ct == 0) return NSHE_OK;
+  if (!in || !out) return fail(NSHE_EINVAL, "null buffer");
+  auto key = c->galois.find(g);
+  if (key == c->galois.end()) return fail(NSHE_ENOKEY, "no Galois key for g = " + std::to_string(g));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Ws w = carve(c, ws, n_ct);
+  Dims d = dims(c, n_ct);
+  const size_t W = W_of(c), N = c->n;
+  HIPCHK(run_i64_to_polys(d, in, 2, w.ext, 2 * W * N, W * N, 2, c->tb, st));
+  rc = rotate_ext(c, w, n_ct, g, key->second, w.fx, st);
+  if (rc) return rc;
+  HIPCHK(run_polys_to_i64(d, w.fx, 2, 2 * W * N, W * N, out, 0, c->tb, st));
+  return NSHE_OK;
+}
+
+int nshe_sum_slots(nshe_ctx* c, const int64_t* in, int64_t* out, int n_ct, void* ws,
+                   size_t ws_bytes, void* stream) {
+  int rc = common_checks(c, n_ct, ws, ws_bytes, false);
+  if (rc) return rc;
+  if (n_ct == 0) return NSHE_OK;
+  if (!in || !out) return fail(NSHE_EINVAL, "null buffer");
+  const std::vector<uint32_t> els = sum_elements(c);
+  std::vector<const double*> keys;
+  for (uint32_t g : els) {
+    auto k = c->galois.find(g);
+    if (k == c->galois.end()) return fail(NSHE_ENOKEY, "no Galois key for g = " + std::to_string(g));
+    keys.push_back(k->second);
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Ws w = carve(c, ws, n_ct);
+  Dims d = dims(c, n_ct);
+  const size_t W = W_of(c), N = c->n;
+  HIPCHK(run_i64_to_polys(d, in, 2, w.ext, 2 * W * N, W * N, 2, c->tb, st));
+  for (size_t k = 0; k < els.size(); ++k) {
+    rc = rotate_ext(c, w, n_ct, els[k], keys[k], w.fx, st);
+    if (rc) return rc;
+    Prof pf(c, K_ADD, st, 2.0 * n_ct * c->L * c->n);
+    HIPCHK(run_add_bal(d, w.ext, w.fx, c->tb, st));
+  }
+  HIPCHK(run_polys_to_i64(d, w.ext, 2, 2 * W * N, W * N, out, 0, c->tb, st));
   return NSHE_OK;
 }
 

@@ -98,6 +98,12 @@ hipError_t run_moddown(const Dims& d, const double* acc, const double* dt, doubl
 // conversions at the boundary
 hipError_t run_sub_to_ext(const Dims& d, const int64_t* x, const int64_t* y, int y_bcast,
                           double* ext, const Tables& tb, hipStream_t st);
+// rotations: automorphism of ext into dt's key-switching layout, and
+// a += b over the data limbs of [ct][2][W][N] ciphertexts
+hipError_t run_automorph(const Dims& d, unsigned ginv, const double* ext, double* dt,
+                         const Tables& tb, hipStream_t st);
+hipError_t run_add_bal(const Dims& d, double* a, const double* b, const Tables& tb,
+                       hipStream_t st);
 // out = a + sum_{j < k} b[j * stride] (canonical int64 ciphertexts)
 hipError_t run_sum_i64(const Dims& d, const int64_t* a, const int64_t* b, size_t stride, int k,
                        int64_t* out, const Tables& tb, hipStream_t st);

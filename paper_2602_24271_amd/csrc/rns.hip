@@ -216,6 +216,50 @@ __global__ void __launch_bounds__(256) k_moddown(int n, int n_ct, const double* 
   }
 }
 
+// ------------------------------------------------------------- rotations ---
+
+// Ring automorphism a(X) -> a(X^g) of the ciphertexts in ext (limbs
+// 0..L-1, balanced) into the key-switching input layout of dt: component 0
+// gets sigma(c0), component 1 zero, component 2 (the digit source) the
+// canonical residues of sigma(c1).  Output coefficient j of sigma(a) is
+// a_i for i = j g^-1 mod 2N when i < N, else -a_{i-N} (since X^N = -1).
+__global__ void __launch_bounds__(256) k_automorph(int n, int L, int n_ct, unsigned ginv,
+                                                   const double* ext, double* dt, Tables tb) {
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (size_t)n_ct * 2 * L * n) return;
+  const size_t row = gid / n;               // (ct * 2 + b) * L + i
+  const int j = (int)(gid - row * n);
+  const int i = (int)(row % L);
+  const size_t cb = row / L;
+  const size_t ct = cb >> 1;
+  const int b = (int)(cb & 1);
+  const size_t W = (size_t)2 * L + 1;
+  const unsigned src = (unsigned)(((unsigned long long)j * ginv) % (2ull * n));
+  const double* a = ext + (cb * W + i) * n;
+  double v = src < (unsigned)n ? a[src] : -a[src - n];
+  double* d = dt + (ct * 3 * W + i) * n + j;
+  if (b == 0) {
+    d[0] = v;
+    d[W * n] = 0.0;
+  } else {
+    d[2 * W * n] = to_canonical(v, cld(tb.p, i));
+  }
+}
+
+// a = [a + b] per residue (balanced), ciphertext layout [ct][2][W][N],
+// limbs 0..L-1.
+__global__ void __launch_bounds__(256) k_add_bal(int n, int L, int n_ct, double* a,
+                                                 const double* b, Tables tb) {
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (size_t)n_ct * 2 * L * n) return;
+  const size_t row = gid / n;
+  const int c = (int)(gid - row * n);
+  const int i = (int)(row % L);
+  const size_t cb = row / L;
+  const size_t off = (cb * (2 * L + 1) + i) * n + c;
+  a[off] = reduce_bal(a[off] + b[off], cld(tb.p, i), cld(tb.pinv, i));
+}
+
 // ------------------------------------------------------------ boundary ---
 
 // ext[ct][b][i] (i < L) = balanced(x - y); y broadcast over ct if y_bcast.
@@ -474,6 +518,21 @@ hipError_t run_sub_to_ext(const Dims& d, const int64_t* x, const int64_t* y, int
   const size_t total = (size_t)d.n_ct * 2 * d.L * d.n;
   hipLaunchKernelGGL(k_sub_to_ext, grid_for(total), dim3(256), 0, st, d.n, d.L, d.n_ct, x, y,
                      y_bcast, ext, tb);
+  return hipGetLastError();
+}
+
+hipError_t run_automorph(const Dims& d, unsigned ginv, const double* ext, double* dt,
+                         const Tables& tb, hipStream_t st) {
+  const size_t total = (size_t)d.n_ct * 2 * d.L * d.n;
+  hipLaunchKernelGGL(k_automorph, grid_for(total), dim3(256), 0, st, d.n, d.L, d.n_ct, ginv, ext,
+                     dt, tb);
+  return hipGetLastError();
+}
+
+hipError_t run_add_bal(const Dims& d, double* a, const double* b, const Tables& tb,
+                       hipStream_t st) {
+  const size_t total = (size_t)d.n_ct * 2 * d.L * d.n;
+  hipLaunchKernelGGL(k_add_bal, grid_for(total), dim3(256), 0, st, d.n, d.L, d.n_ct, a, b, tb);
   return hipGetLastError();
 }
 

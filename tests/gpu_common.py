@@ -43,3 +43,15 @@ class Setup:
         a = t.cpu().numpy()
         return [tuple(bfv.from_limbs(a[i, k], self.pr.q) for k in range(a.shape[1]))
                 for i in range(a.shape[0])]
+
+
+def galois_keys(S: Setup, seed: int = 500):
+    """Oracle Galois keys for every element of the rotate-and-add sum, also
+    loaded into the device context."""
+    from oracle import galois
+    keys = {}
+    for i, g in enumerate(galois.sum_elements(S.pr.n)):
+        rnd = synth.switch_randomness(seed + i, S.pr.n, S.pr.moduli_pq, S.pr.L)
+        keys[g] = galois.galois_key(S.pr, S.sk, g, rnd)
+        S.ctx.set_galois_key(g, torch.from_numpy(keys[g].limbs(S.pr)).to(S.ctx.device))
+    return keys
