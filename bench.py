@@ -14,7 +14,10 @@ second.  The line also carries:
                 the chip's FP64 VALU issue peak;
   kernels       per-kernel-kind time and launch counts from the same events;
   batched       512 instances of uneven size (rows log-uniform in
-                [2^14, 2^20]) in HIP-graph waves vs a per-instance launch loop;
+                [2^14, 2^20]) in HIP-graph waves (autotuned launch shapes and
+                wave size) vs a per-instance launch loop;
+  next_rows     IN against 4 members, SELECT, and the rotate-and-add
+                SUM/COUNT over the same column;
   cpu_baseline  the exact-integer oracle on a bounded sample, host cores.
 
 Inputs are seeded uniform residues: a fresh RLWE ciphertext is uniform to
@@ -176,6 +179,61 @@ def batched(ctx, n_inst: int, reps: int, max_wave: int = 128) -> dict:
             "ms_graph": t_graph * 1e3, "ms_loop": t_loop * 1e3, "speedup": t_loop / t_graph}
 
 
+def timed(fn, reps: int) -> float:
+    """Mean wall time (s) of fn() over reps calls after one untimed call,
+    the device synchronised around the timed region."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def next_rows(ctx, x, mask, reps: int) -> dict:
+    """The operators built on EQ over the same column (n_ct ciphertexts):
+    IN against 4 encrypted members (Eq. eq:in), SELECT (Eq. eq:select), and
+    the rotate-and-add SUM/COUNT (Sec. 4.3) with 15 Galois keys.  Keys and
+    members are seeded uniform residues (timing is data-oblivious)."""
+    import synth
+    dev = ctx.device
+    n_ct = x.shape[0]
+    rows = n_ct * ctx.n
+    out = {}
+    k = 4
+    members = synth.uniform_device_residues((k, 2), ctx.q, ctx.n, 30, dev)
+    t = timed(lambda: ctx.in_mask(x, members), reps)
+    out["in"] = {"members": k, "rows": rows, "ms": t * 1e3, "records_per_s": rows / t,
+                 "eq_records_per_s": k * rows / t,
+                 "paper_ms_per_record": 0.09, "paper_source": "Table tab:primitive-times, IN row"}
+    log(f"IN (k={k}) {t * 1e3:.1f} ms")
+    t = timed(lambda: ctx.select(x, mask), reps)
+    out["select"] = {"rows": rows, "ms": t * 1e3, "records_per_s": rows / t}
+    log(f"SELECT {t * 1e3:.2f} ms")
+    key = synth.uniform_device_residues((ctx.L, 2), ctx.q + [ctx.P], ctx.n, 31, dev)
+    els = ctx.galois_elements()
+    for g in els:
+        ctx.set_galois_key(g, key)
+    del key
+    sel = ctx.select(x, mask)
+    t = timed(lambda: ctx.sum_slots(sel), reps)
+    ctx.profile(True)                 # one more call, every launch timed
+    ctx.sum_slots(sel)
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    roof, _ = roofline(prof)
+    out["sum_slots"] = {"rotations": len(els), "rows": rows, "ms": t * 1e3,
+                        "records_per_s": rows / t, "roofline": roof,
+                        "kernels": {kk: {"launches": v["launches"], "ms": v["ms"]}
+                                    for kk, v in prof.items()},
+                        "paper_ms_per_record": 0.04,
+                        "paper_source": "Table tab:primitive-times, SUM and COUNT rows"}
+    log(f"SUM/COUNT ({len(els)} rotations) {t * 1e3:.1f} ms")
+    return out
+
+
 def summarize_profiles(prof_dir: str, out_dir: str) -> None:
     """Turn rocprofv3 output (kernel trace stats; FETCH_SIZE and WRITE_SIZE
     counter passes that include a device copy of known size) into the short
@@ -249,6 +307,9 @@ def main() -> int:
     ap.add_argument("--batched-reps", type=int, default=1)
     ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--skip-next", action="store_true",
+                    help="skip IN / SELECT / SUM over the same column")
+    ap.add_argument("--next-reps", type=int, default=2)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
@@ -307,6 +368,9 @@ def main() -> int:
     kernels = {k: {"launches": v["launches"] // args.steps, "ms_per_step": v["ms"] / args.steps}
                for k, v in prof.items()}
 
+    nxt = None
+    if not args.skip_next:
+        nxt = next_rows(ctx, x, out, args.next_reps)
     bat = None
     if not args.skip_batched:
         bat = batched(ctx, args.batched_instances, args.batched_reps)
@@ -337,6 +401,7 @@ def main() -> int:
         "cpu_baseline": cpu,
         "kernels": kernels,
         "batched": bat,
+        "next_rows": nxt,
         "adjoint": None,
         "adjoint_note": "no adjoint: the mask is discrete (Z_t plaintexts, R_Q ciphertexts)",
         "margin_events": margin,
