@@ -28,6 +28,8 @@ Modules
             (Eq. eq:select), BFV addition
   galois    slot rotations (automorphisms + key switching) and the
             rotate-and-add aggregation of COUNT / SUM
+  compare   LT / LE / BETWEEN: the comparison polynomial of the Fermat sum
+            and its baby-step giant-step evaluation
   ntt_def   the negacyclic number-theoretic transform written from its
             definition (O(N^2)), for checking a device transform's output
 
