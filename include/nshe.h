@@ -216,6 +216,39 @@ int nshe_in_mask(nshe_ctx* ctx, const int64_t* x_dev, const int64_t* set_dev, in
                  int64_t* out_dev, int n_ct, int wave_ct, int use_graph,
                  void* ws_dev, size_t ws_bytes, void* stream);
 
+/* Range comparisons (Eq. eq:inequality; BETWEEN, Sec. 4.3).  LT(x, y) is
+ * the sum over a in A = {-(p-1)/2, ..., -1} of 1 - (x - y - a)^(p-1), i.e.
+ * the encrypted indicator of x - y in the negative half of Z_p: [x < y] when
+ * |x - y| <= (p-1)/2 (larger differences wrap around).  It is evaluated as
+ * one polynomial f(z) = c_(p-1) z^(p-1) + z g(z^2), z = x - y, whose
+ * coefficients the context derives from t (a prime 2^K + 1, else
+ * NSHE_EDEPTH), by a fixed program every result follows exactly:
+ *   levels[a] = z^(2^a) by K squarings (a = 0..K);
+ *   w = levels[1]; k = 2^floor(K/2) babies B_i = w^i (B_0 = (Delta, 0),
+ *   powers of two from the levels, others B_h * B_(i-h) with h the largest
+ *   power of two below i); m = 2^(K-1)/k giants W_j = w^(k j) (powers of
+ *   two from the levels, others W_h * W_(j-h));
+ *   G_j = sum_i c_(2(jk+i)+1) B_i with centred coefficients (scalar
+ *   products, exact mod Q); g = G_0 + sum_{j>=1} G_j * W_j;
+ *   LT = c_(p-1) levels[K] + z * g,
+ * every product a multiplication followed by relinearization (as
+ * nshe_mul_relin / nshe_square_relin).  op 0 gives LT(x, y); op 1 gives
+ * LE(x, y) = (Delta, 0) - LT(y, x).  nshe_between gives
+ * LE(lo, x) * LE(x, hi) (one more multiplication).  y (or lo and hi) may be
+ * one ciphertext broadcast over the column.  Workspace:
+ * nshe_compare_workspace_bytes(ctx, n_ct) (about K + k + m + 27 ciphertext
+ * arrays plus the multiply workspace; 0 if the context has no comparison
+ * polynomial). */
+#define NSHE_CMP_LT 0
+#define NSHE_CMP_LE 1
+size_t nshe_compare_workspace_bytes(const nshe_ctx* ctx, int n_ct);
+int nshe_compare(nshe_ctx* ctx, const int64_t* x_dev, const int64_t* y_dev, int y_broadcast,
+                 int op, int64_t* out_dev, int n_ct, void* ws_dev, size_t ws_bytes,
+                 void* stream);
+int nshe_between(nshe_ctx* ctx, const int64_t* x_dev, const int64_t* lo_dev,
+                 const int64_t* hi_dev, int bounds_broadcast, int64_t* out_dev, int n_ct,
+                 void* ws_dev, size_t ws_bytes, void* stream);
+
 /* Slot rotations and the rotate-and-add aggregation (COUNT and SUM,
  * Sec. 4.3 aggregation).  Slots follow the 2 x N/2 layout: slot s < N/2 is
  * the plaintext's value at psi^(3^s), slot N/2 + s at psi^(-3^s) (psi a

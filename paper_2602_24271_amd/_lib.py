@@ -63,6 +63,9 @@ SIGNATURES = {
     "nshe_sum": (_I, [_P, _P, _I, _P, _I, _P]),
     "nshe_in_workspace_bytes": (_SZ, [_P, _I, _I, _I]),
     "nshe_in_mask": (_I, [_P, _P, _P, _I, _P, _I, _I, _I, _P, _SZ, _P]),
+    "nshe_compare_workspace_bytes": (_SZ, [_P, _I]),
+    "nshe_compare": (_I, [_P, _P, _P, _I, _I, _P, _I, _P, _SZ, _P]),
+    "nshe_between": (_I, [_P, _P, _P, _P, _I, _P, _I, _P, _SZ, _P]),
     "nshe_set_galois_key": (_I, [_P, ctypes.c_uint32, _P, _P]),
     "nshe_galois_elements": (_I, [_P, ctypes.POINTER(ctypes.c_uint32), _I, ctypes.POINTER(_I)]),
     "nshe_rotate": (_I, [_P, _P, ctypes.c_uint32, _P, _I, _P, _SZ, _P]),

@@ -148,6 +148,40 @@ class Context:
         """SELECT column WHERE mask (Eq. eq:select): column * mask, relinearized."""
         return self.mul_relin(column, mask)
 
+    def _cmp_ws(self, n: int) -> torch.Tensor:
+        need = int(self._lib.nshe_compare_workspace_bytes(self._h, n))
+        if need == 0:
+            raise ValueError("comparisons need t = 2^K + 1 prime")
+        return self._workspace_bytes(need)
+
+    def compare(self, x: torch.Tensor, y: torch.Tensor, op: str = "lt") -> torch.Tensor:
+        """[x < y] (op "lt") or [x <= y] (op "le") for |x - y| <= (t-1)/2
+        (Eq. eq:inequality); y: as many ciphertexts as x, or one (broadcast)."""
+        n = self._check_ct(x)
+        ny = self._check_ct(y)
+        if ny not in (n, 1):
+            raise ValueError("y must hold n_ct ciphertexts or one")
+        code = {"lt": 0, "le": 1}[op]
+        out = torch.empty_like(x)
+        ws = self._cmp_ws(n)
+        _lib.check(self._lib.nshe_compare(self._h, _ptr(x), _ptr(y), int(ny == 1 and n != 1),
+                                          code, _ptr(out), n, _ptr(ws), ws.numel(), _stream()))
+        return out
+
+    def between(self, x: torch.Tensor, lo: torch.Tensor, hi: torch.Tensor) -> torch.Tensor:
+        """[lo <= x <= hi] = LE(lo, x) * LE(x, hi); lo, hi: as many ciphertexts
+        as x, or one each (broadcast)."""
+        n = self._check_ct(x)
+        nl, nh = self._check_ct(lo), self._check_ct(hi)
+        if nl != nh or nl not in (n, 1):
+            raise ValueError("lo and hi must both hold n_ct ciphertexts or one")
+        out = torch.empty_like(x)
+        ws = self._cmp_ws(n)
+        _lib.check(self._lib.nshe_between(self._h, _ptr(x), _ptr(lo), _ptr(hi),
+                                          int(nl == 1 and n != 1), _ptr(out), n, _ptr(ws),
+                                          ws.numel(), _stream()))
+        return out
+
     def galois_elements(self) -> list:
         """Galois elements whose keys nshe_sum_slots needs, in order of use."""
         n = ctypes.c_int(0)

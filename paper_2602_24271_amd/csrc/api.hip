@@ -107,6 +107,55 @@ static int brv(int x, int bits) {
   return r;
 }
 
+// Cyclic transform y_k = sum_e x_e w^(e k) mod p, length a power of two
+// (iterative radix 2; p < 2^31).
+static std::vector<u64> cyclic_transform(std::vector<u64> x, u64 w, u64 p) {
+  const size_t n = x.size();
+  int bits = 0;
+  while ((size_t(1) << bits) < n) ++bits;
+  for (size_t i = 0; i < n; ++i) {
+    const size_t r = (size_t)brv((int)i, bits);
+    if (r > i) std::swap(x[i], x[r]);
+  }
+  for (size_t len = 2; len <= n; len <<= 1) {
+    const u64 wl = powmod(w, n / len, p);
+    for (size_t s = 0; s < n; s += len) {
+      u64 tw = 1;
+      for (size_t j = 0; j < len / 2; ++j) {
+        const u64 a = x[s + j], b = x[s + j + len / 2] * tw % p;
+        x[s + j] = (a + b) % p;
+        x[s + j + len / 2] = (a + p - b) % p;
+        tw = tw * wl % p;
+      }
+    }
+  }
+  return x;
+}
+
+// Coefficients c_0..c_(p-1) of the polynomial f with f(z) = [z in A],
+// A = {-(p-1)/2, ..., -1} mod p (the sum of Fermat equalities over the
+// negative half): c_0 = f(0) = 0, c_k = -sum_{z != 0} f(z) z^-k for
+// 1 <= k <= p-2 (a cyclic transform over the multiplicative group, with z =
+// gamma^e for a primitive root gamma), c_(p-1) = -|A|.  p = 2^K + 1 prime.
+static std::vector<u64> comparison_poly(u64 p) {
+  const u64 n = p - 1, h = n / 2;
+  u64 g = 2;
+  while (powmod(g, n / 2, p) == 1) ++g;  // 2 is the only prime factor of p - 1
+  std::vector<u64> f(n, 0);
+  u64 z = 1;
+  for (u64 e = 0; e < n; ++e) {
+    f[e] = z > h ? 1 : 0;
+    z = z * g % p;
+  }
+  const std::vector<u64> y = cyclic_transform(f, powmod(g, p - 2, p), p);
+  std::vector<u64> c(p, 0);
+  for (u64 k = 1; k + 1 < p; ++k) c[k] = (p - y[k]) % p;
+  c[p - 1] = (p - h) % p;
+  return c;
+}
+
+static int centred_small(u64 v, u64 p) { return v > p / 2 ? (int)v - (int)p : (int)v; }
+
 }  // namespace nshe
 
 using namespace nshe;
@@ -140,6 +189,10 @@ struct nshe_ctx {
   hipStream_t cap_stream = nullptr;  // capture-only stream (the null stream cannot capture)
   nshe_tuning tune{16, 1, 256, 0};
   std::map<uint32_t, double*> galois;  // Galois element -> switching key (NTT domain)
+  // comparison polynomial (t = 2^K + 1 prime; lt_K = 0 otherwise): k babies,
+  // m giants, coefficient matrix [m][k] (centred ints) on the device
+  int lt_K = 0, lt_k = 0, lt_m = 0, lt_top = 0;
+  const int* lt_coef = nullptr;
 };
 
 namespace nshe {
@@ -163,10 +216,10 @@ static Dims dims(const nshe_ctx* c, int n_ct) {
 // ------------------------------------------------------------ profiling
 
 enum Kind { K_SUB, K_LIFT, K_NTT_FWD, K_NTT_INV_TENSOR, K_NTT_INV, K_SCALE, K_NTT_DIGIT,
-            K_KS_MAC, K_MODDOWN, K_CONVERT, K_AUTOMORPH, K_ADD, K_COUNT };
+            K_KS_MAC, K_MODDOWN, K_CONVERT, K_AUTOMORPH, K_ADD, K_LINCOMB, K_COUNT };
 static const char* kKindName[K_COUNT] = {"sub",   "lift",      "ntt_fwd", "ntt_inv_tensor",
                                          "ntt_inv", "scale", "ntt_digit", "ks_mac",
-                                         "moddown", "convert", "automorph", "add"};
+                                         "moddown", "convert", "automorph", "add", "lincomb"};
 
 static hipEvent_t take_event(nshe_ctx* c) {
   if (!c->pool.empty()) {
@@ -605,6 +658,23 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
   total += 256;
   const size_t off_lp = total;
   total += ((size_t)(W_of(c) + L + 1) * sizeof(int) + 255) & ~size_t(255);
+  // comparison polynomial for a Fermat prime t
+  std::vector<int> lt_coef;
+  if (c->squarings >= 2 && is_prime(c->t)) {
+    const int K = c->squarings, kb = K / 2;
+    c->lt_K = K;
+    c->lt_k = 1 << kb;
+    c->lt_m = 1 << (K - 1 - kb);
+    const std::vector<u64> cp = comparison_poly(c->t);
+    lt_coef.resize((size_t)c->lt_m * c->lt_k);
+    for (int j = 0; j < c->lt_m; ++j)
+      for (int i = 0; i < c->lt_k; ++i)
+        lt_coef[(size_t)j * c->lt_k + i] = centred_small(cp[2 * ((size_t)j * c->lt_k + i) + 1], c->t);
+    c->lt_top = centred_small(cp[c->t - 1], c->t);
+    lt_coef.push_back(c->lt_top);  // the z^(p-1) coefficient, after the matrix
+  }
+  const size_t off_lt = total;
+  total += (lt_coef.size() * sizeof(int) + 255) & ~size_t(255);
   int rc = NSHE_OK;
   hipError_t e = hipSetDevice(hip_device);
   if (e == hipSuccess) e = hipMalloc(&c->dev_tables, total);
@@ -635,6 +705,12 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
   c->lp_ks = c->lp_ext + W_of(c);
   if (e == hipSuccess)
     e = hipMemcpy(c->lp_ext, lp.data(), lp.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (!lt_coef.empty()) {
+    c->lt_coef = reinterpret_cast<const int*>(base + off_lt);
+    if (e == hipSuccess)
+      e = hipMemcpy(base + off_lt, lt_coef.data(), lt_coef.size() * sizeof(int),
+                    hipMemcpyHostToDevice);
+  }
   if (e != hipSuccess) {
     (void)hipFree(c->dev_tables);
     delete c;
@@ -1159,6 +1235,189 @@ int nshe_sum_slots(nshe_ctx* c, const int64_t* in, int64_t* out, int n_ct, void*
   }
   HIPCHK(run_polys_to_i64(d, w.ext, 2, 2 * W * N, W * N, out, 0, c->tb, st));
   return NSHE_OK;
+}
+
+// ------------------------------------------------------------ comparisons
+
+static int ilog2(int x) {
+  int r = 0;
+  while ((1 << (r + 1)) <= x) ++r;
+  return r;
+}
+
+static size_t ct_bytes(const nshe_ctx* c, int n_ct) {
+  return ((size_t)n_ct * 2 * c->L * c->n * sizeof(int64_t) + 255) & ~(size_t)255;
+}
+
+// Ciphertext-array slots of the comparison workspace (then the multiply
+// workspace): chain levels 1..K (slot 0 unused), babies, giants, 16
+// linear combinations, the core's g, T, S, and the callers' z, LT, and two
+// comparison results (the last four).
+static int cmp_slots(const nshe_ctx* c) { return c->lt_K + 1 + c->lt_k + c->lt_m + 16 + 3 + 4; }
+
+size_t nshe_compare_workspace_bytes(const nshe_ctx* c, int n_ct) {
+  if (check_ctx(c) || n_ct < 0 || c->lt_K == 0) return 0;
+  return (size_t)cmp_slots(c) * ct_bytes(c, n_ct) + ws_doubles(c, n_ct) * sizeof(double);
+}
+
+struct CmpArea {
+  int64_t* slot0;
+  size_t U;       // int64 words per slot
+  void* mws;      // multiply workspace
+  size_t mws_bytes;
+  int64_t* slot(int i) const { return slot0 + (size_t)i * U; }
+};
+
+// LT of the differences z (int64, n_ct ciphertexts, not in the area) into
+// out: the baby-step giant-step program of the comparison polynomial
+// (its odd part in w = z^2, powers of two of w from the squaring chain).
+// On return slot `one` holds the trivial encryption of 1.
+static int lt_core(nshe_ctx* c, const int64_t* z, int64_t* out, int n_ct, const CmpArea& a,
+                   int* one_slot, hipStream_t st) {
+  const int K = c->lt_K, k = c->lt_k, m = c->lt_m;
+  void* stv = st;
+  const int s_lev = 0, s_bab = K + 1, s_gi = s_bab + k, s_G = s_gi + m, s_g = s_G + 16,
+            s_T = s_g + 1, s_S = s_g + 2;
+  Dims d = dims(c, n_ct);
+  std::vector<const int64_t*> lev(K + 1);
+  lev[0] = z;
+  for (int i = 1; i <= K; ++i) {
+    int rc = nshe_square_relin(c, lev[i - 1], a.slot(s_lev + i), n_ct, a.mws, a.mws_bytes, stv);
+    if (rc) return rc;
+    lev[i] = a.slot(s_lev + i);
+  }
+  BabyPtrs bp{};
+  HIPCHK(run_fill_one(d, a.slot(s_bab), c->tb, st));
+  bp.p[0] = a.slot(s_bab);
+  bp.p[1] = lev[1];
+  for (int i = 2; i < k; ++i) {
+    const int h = 1 << ilog2(i), r = i - h;
+    if (r == 0) {
+      bp.p[i] = lev[ilog2(i) + 1];
+    } else {
+      int rc = nshe_mul_relin(c, bp.p[h], bp.p[r], a.slot(s_bab + i), n_ct, a.mws, a.mws_bytes, stv);
+      if (rc) return rc;
+      bp.p[i] = a.slot(s_bab + i);
+    }
+  }
+  std::vector<const int64_t*> gi(m, nullptr);
+  if (m > 1) gi[1] = lev[ilog2(k) + 1];
+  for (int j = 2; j < m; ++j) {
+    const int h = 1 << ilog2(j), r = j - h;
+    if (r == 0) {
+      gi[j] = lev[ilog2(k) + ilog2(j) + 1];
+    } else {
+      int rc = nshe_mul_relin(c, gi[h], gi[r], a.slot(s_gi + j), n_ct, a.mws, a.mws_bytes, stv);
+      if (rc) return rc;
+      gi[j] = a.slot(s_gi + j);
+    }
+  }
+  // g = G_0 + sum_j G_j W_j, G_j = sum_i c_(2(jk+i)+1) B_i in chunks of 16
+  int64_t* g = a.slot(s_g);
+  for (int j0 = 0; j0 < m; j0 += 16) {
+    const int J = std::min(16, m - j0);
+    {
+      Prof pf(c, K_LINCOMB, st, (double)J * k * n_ct * 2 * c->L * c->n);
+      HIPCHK(run_lincomb(d, k, bp, c->lt_coef + (size_t)j0 * k, J, a.slot(s_G), a.U, c->tb, st));
+    }
+    for (int jj = 0; jj < J; ++jj) {
+      const int j = j0 + jj;
+      const int64_t* Gj = a.slot(s_G + jj);
+      if (j == 0) {
+        HIPCHK(run_sum_i64(d, Gj, nullptr, 0, 0, g, c->tb, st));
+        continue;
+      }
+      int rc = nshe_mul_relin(c, Gj, gi[j], a.slot(s_T), n_ct, a.mws, a.mws_bytes, stv);
+      if (rc) return rc;
+      HIPCHK(run_sum_i64(d, g, a.slot(s_T), 0, 1, g, c->tb, st));
+    }
+  }
+  // out = c_(p-1) z^(p-1) + z g
+  int rc = nshe_mul_relin(c, lev[0], g, a.slot(s_T), n_ct, a.mws, a.mws_bytes, stv);
+  if (rc) return rc;
+  BabyPtrs top{};
+  top.p[0] = lev[K];
+  {
+    Prof pf(c, K_LINCOMB, st, (double)n_ct * 2 * c->L * c->n);
+    HIPCHK(run_lincomb(d, 1, top, c->lt_coef + (size_t)m * k, 1, a.slot(s_S), a.U, c->tb, st));
+  }
+  HIPCHK(run_sum_i64(d, a.slot(s_S), a.slot(s_T), 0, 1, out, c->tb, st));
+  *one_slot = s_bab;
+  return NSHE_OK;
+}
+
+static int cmp_checks(nshe_ctx* c, int n_ct, void* ws, size_t ws_bytes, CmpArea* a) {
+  g_err.clear();
+  if (check_ctx(c)) return NSHE_EINVAL;
+  if (c->lt_K == 0) return fail(NSHE_EDEPTH, "comparisons need t = 2^K + 1 prime");
+  if (n_ct < 0) return fail(NSHE_ESHAPE, "n_ct < 0");
+  if (check_key(c)) return NSHE_ENOKEY;
+  if (n_ct == 0) return NSHE_OK;
+  if (!ws) return fail(NSHE_EINVAL, "workspace pointer is null");
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(NSHE_EINVAL, "workspace not 256-byte aligned");
+  if (ws_bytes < nshe_compare_workspace_bytes(c, n_ct))
+    return fail(NSHE_ENOMEM, "workspace smaller than nshe_compare_workspace_bytes(ctx, n_ct)");
+  if (set_device(c)) return NSHE_EDEVICE;
+  const size_t cb = ct_bytes(c, n_ct);
+  a->slot0 = static_cast<int64_t*>(ws);
+  a->U = cb / sizeof(int64_t);
+  a->mws = static_cast<char*>(ws) + (size_t)cmp_slots(c) * cb;
+  a->mws_bytes = ws_bytes - (size_t)cmp_slots(c) * cb;
+  return NSHE_OK;
+}
+
+// z = sign (x - y) into the area's last slot, then LT (op 0) or 1 - LT (op 1)
+static int compare_into(nshe_ctx* c, const int64_t* x, const int64_t* y, int y_bcast, int op,
+                        int64_t* out, int n_ct, const CmpArea& a, hipStream_t st) {
+  Dims d = dims(c, n_ct);
+  int64_t* z = a.slot(cmp_slots(c) - 1);
+  // LT(x, y) takes z = x - y; LE(x, y) = 1 - LT(y, x) takes z = y - x
+  HIPCHK(run_diff_i64(d, x, y, y_bcast, op == 1 ? 1 : 0, z, c->tb, st));
+  int one = 0;
+  if (op == 0) return lt_core(c, z, out, n_ct, a, &one, st);
+  int64_t* lt = a.slot(cmp_slots(c) - 2);
+  int rc = lt_core(c, z, lt, n_ct, a, &one, st);
+  if (rc) return rc;
+  HIPCHK(run_diff_i64(d, a.slot(one), lt, 0, 0, out, c->tb, st));
+  return NSHE_OK;
+}
+
+int nshe_compare(nshe_ctx* c, const int64_t* x, const int64_t* y, int y_broadcast, int op,
+                 int64_t* out, int n_ct, void* ws, size_t ws_bytes, void* stream) {
+  CmpArea a{};
+  int rc = cmp_checks(c, n_ct, ws, ws_bytes, &a);
+  if (rc || n_ct == 0) return rc;
+  if (op != 0 && op != 1) return fail(NSHE_EINVAL, "op must be 0 (LT) or 1 (LE)");
+  if (!x || !y || !out) return fail(NSHE_EINVAL, "null buffer");
+  return compare_into(c, x, y, y_broadcast ? 1 : 0, op, out, n_ct, a,
+                      static_cast<hipStream_t>(stream));
+}
+
+int nshe_between(nshe_ctx* c, const int64_t* x, const int64_t* lo, const int64_t* hi,
+                 int bounds_broadcast, int64_t* out, int n_ct, void* ws, size_t ws_bytes,
+                 void* stream) {
+  CmpArea a{};
+  int rc = cmp_checks(c, n_ct, ws, ws_bytes, &a);
+  if (rc || n_ct == 0) return rc;
+  if (!x || !lo || !hi || !out) return fail(NSHE_EINVAL, "null buffer");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Dims d = dims(c, n_ct);
+  const int bc = bounds_broadcast ? 1 : 0;
+  int64_t* ge = a.slot(cmp_slots(c) - 3);   // [lo <= x] = 1 - LT(x, lo)
+  int64_t* z = a.slot(cmp_slots(c) - 1);
+  HIPCHK(run_diff_i64(d, x, lo, bc, 0, z, c->tb, st));
+  int one = 0;
+  int64_t* lt = a.slot(cmp_slots(c) - 2);
+  rc = lt_core(c, z, lt, n_ct, a, &one, st);
+  if (rc) return rc;
+  HIPCHK(run_diff_i64(d, a.slot(one), lt, 0, 0, ge, c->tb, st));
+  // [x <= hi] = 1 - LT(hi, x), z = hi - x
+  HIPCHK(run_diff_i64(d, x, hi, bc, 1, z, c->tb, st));
+  rc = lt_core(c, z, lt, n_ct, a, &one, st);
+  if (rc) return rc;
+  int64_t* le = a.slot(cmp_slots(c) - 4);
+  HIPCHK(run_diff_i64(d, a.slot(one), lt, 0, 0, le, c->tb, st));
+  return nshe_mul_relin(c, ge, le, out, n_ct, a.mws, a.mws_bytes, stream);
 }
 
 // ------------------------------------------------------------ IN / GROUP BY

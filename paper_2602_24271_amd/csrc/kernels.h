@@ -98,6 +98,18 @@ hipError_t run_moddown(const Dims& d, const double* acc, const double* dt, doubl
 // conversions at the boundary
 hipError_t run_sub_to_ext(const Dims& d, const int64_t* x, const int64_t* y, int y_bcast,
                           double* ext, const Tables& tb, hipStream_t st);
+// comparisons: scalar linear combinations of up to 256 ciphertext arrays
+// (J <= 16 outputs, coefficient rows [J][k]), the trivial encryption of 1,
+// and differences with optional broadcast and sign
+struct BabyPtrs {
+  static constexpr int CAP = 256;
+  const int64_t* p[CAP];
+};
+hipError_t run_lincomb(const Dims& d, int k, const BabyPtrs& b, const int* coef, int J,
+                       int64_t* out, size_t out_stride, const Tables& tb, hipStream_t st);
+hipError_t run_fill_one(const Dims& d, int64_t* out, const Tables& tb, hipStream_t st);
+hipError_t run_diff_i64(const Dims& d, const int64_t* x, const int64_t* y, int y_bcast,
+                        int negate, int64_t* out, const Tables& tb, hipStream_t st);
 // rotations: automorphism of ext into dt's key-switching layout, and
 // a += b over the data limbs of [ct][2][W][N] ciphertexts
 hipError_t run_automorph(const Dims& d, unsigned ginv, const double* ext, double* dt,

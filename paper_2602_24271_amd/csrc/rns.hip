@@ -216,6 +216,65 @@ __global__ void __launch_bounds__(256) k_moddown(int n, int n_ct, const double* 
   }
 }
 
+// ----------------------------------------------------------- comparisons ---
+
+// out[jj * out_stride + r] = [sum_t coef[jj * k + t] * b.p[t][r]]_q per
+// residue r < per, jj < J <= 16 (int64 canonical in and out).
+// Coefficients are small centred integers (|c| < 2^15 < p/2), so each
+// product is a lazy modular product below 0.55 p; sums are reduced every
+// 16 terms (below 9.3 p).  Coefficients are uniform across the grid
+// (scalar loads).
+__global__ void __launch_bounds__(256) k_lincomb(int n, int L, size_t per, int k, BabyPtrs b,
+                                                 const int* coef, int J, int64_t* out,
+                                                 size_t out_stride, Tables tb) {
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= per) return;
+  const int i = (int)((gid / n) % L);
+  const double p = cld(tb.p, i), pinv = cld(tb.pinv, i);
+  double acc[16];
+#pragma unroll
+  for (int jj = 0; jj < 16; ++jj) acc[jj] = 0.0;
+  for (int t = 0; t < k; ++t) {
+    const double v = from_u64(b.p[t][gid], p);
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj)
+      if (jj < J) acc[jj] += mul_lazy(v, (double)cldi(coef, jj * k + t), p, pinv);
+    if ((t & 15) == 15) {
+#pragma unroll
+      for (int jj = 0; jj < 16; ++jj) acc[jj] = reduce_bal(acc[jj], p, pinv);
+    }
+  }
+#pragma unroll
+  for (int jj = 0; jj < 16; ++jj)
+    if (jj < J) out[(size_t)jj * out_stride + gid] = to_i64(reduce_bal(acc[jj], p, pinv), p);
+}
+
+// The trivial encryption (Delta, 0) of 1 in each of n_ct ciphertexts.
+__global__ void __launch_bounds__(256) k_fill_one(int n, int L, size_t total, int64_t* out,
+                                                  Tables tb) {
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= total) return;
+  const size_t row = gid / n;                 // (ct * 2 + b) * L + i
+  const int c = (int)(gid - row * n);
+  const int i = (int)(row % L);
+  const int b = (int)((row / L) & 1);
+  out[gid] = (b == 0 && c == 0) ? to_i64(cld(tb.delta_q, i), cld(tb.p, i)) : 0;
+}
+
+// out = [x - y]_Q or [y - x]_Q (negate), y broadcast over ct if y_bcast.
+__global__ void __launch_bounds__(256) k_diff_i64(int n, int L, size_t total, const int64_t* x,
+                                                  const int64_t* y, int y_bcast, int negate,
+                                                  int64_t* out, Tables tb) {
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= total) return;
+  const size_t per_ct = (size_t)2 * L * n;
+  const int i = (int)((gid / n) % L);
+  const int64_t q = (int64_t)cld(tb.p, i);
+  const int64_t a = x[gid], b = y[y_bcast ? gid % per_ct : gid];
+  int64_t d = negate ? b - a : a - b;
+  out[gid] = d < 0 ? d + q : d;
+}
+
 // ------------------------------------------------------------- rotations ---
 
 // Ring automorphism a(X) -> a(X^g) of the ciphertexts in ext (limbs
@@ -518,6 +577,30 @@ hipError_t run_sub_to_ext(const Dims& d, const int64_t* x, const int64_t* y, int
   const size_t total = (size_t)d.n_ct * 2 * d.L * d.n;
   hipLaunchKernelGGL(k_sub_to_ext, grid_for(total), dim3(256), 0, st, d.n, d.L, d.n_ct, x, y,
                      y_bcast, ext, tb);
+  return hipGetLastError();
+}
+
+hipError_t run_lincomb(const Dims& d, int k, const BabyPtrs& b, const int* coef, int J,
+                       int64_t* out, size_t out_stride, const Tables& tb, hipStream_t st) {
+  const size_t per = (size_t)d.n_ct * 2 * d.L * d.n;
+  if (k < 1 || k > BabyPtrs::CAP || J < 1 || J > 16 || (J > 1 && out_stride < per))
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_lincomb, grid_for(per), dim3(256), 0, st, d.n, d.L, per, k, b, coef, J,
+                     out, out_stride, tb);
+  return hipGetLastError();
+}
+
+hipError_t run_fill_one(const Dims& d, int64_t* out, const Tables& tb, hipStream_t st) {
+  const size_t total = (size_t)d.n_ct * 2 * d.L * d.n;
+  hipLaunchKernelGGL(k_fill_one, grid_for(total), dim3(256), 0, st, d.n, d.L, total, out, tb);
+  return hipGetLastError();
+}
+
+hipError_t run_diff_i64(const Dims& d, const int64_t* x, const int64_t* y, int y_bcast,
+                        int negate, int64_t* out, const Tables& tb, hipStream_t st) {
+  const size_t total = (size_t)d.n_ct * 2 * d.L * d.n;
+  hipLaunchKernelGGL(k_diff_i64, grid_for(total), dim3(256), 0, st, d.n, d.L, total, x, y,
+                     y_bcast, negate, out, tb);
   return hipGetLastError();
 }
 

@@ -52,3 +52,21 @@ def test_full_size_square_and_mask(s32k):
     assert list(mask) == list((x == y).astype(int))
     m_true = encoding.encode((x == y).astype(int), S.pr.t)
     assert bfv.noise_bits(S.pr, S.sk, got, m_true) > 100
+
+
+def test_full_size_lt_decrypts(s32k):
+    """LT at the paper's parameters (p = 65537: 16 squarings, 256 babies,
+    128 giants) on one ciphertext of 15-bit values against a broadcast
+    constant: decrypts to [x < y] with budget left."""
+    S = s32k
+    rng = np.random.default_rng(11)
+    x = rng.integers(0, 1 << 15, S.pr.n)
+    x[:5] = [20000, 19999, 20001, 0, 32767]
+    cx, cy = S.enc(x, 21), S.enc(np.full(S.pr.n, 20000), 22)
+    out = S.ctx.compare(S.to_dev([cx]), S.to_dev([cy]), "lt")
+    got = S.from_dev(out)[0]
+    want = (x < 20000).astype(int)
+    assert list(bfv.decrypt_slots(S.pr, S.sk, got)) == list(want)
+    budget = bfv.noise_bits(S.pr, S.sk, got, encoding.encode(want, S.pr.t))
+    print(f"LT budget left at N=32768: {budget:.1f} bits")
+    assert budget > 0
