@@ -16,8 +16,8 @@ second.  The line also carries:
   batched       512 instances of uneven size (rows log-uniform in
                 [2^14, 2^20]) in HIP-graph waves (autotuned launch shapes and
                 wave size) vs a per-instance launch loop;
-  next_rows     IN against 4 members, SELECT, and the rotate-and-add
-                SUM/COUNT over the same column;
+  next_rows     IN against 4 members, SELECT, the rotate-and-add SUM/COUNT
+                and LT against a constant over the same column;
   cpu_baseline  the exact-integer oracle on a bounded sample, host cores.
 
 Inputs are seeded uniform residues: a fresh RLWE ciphertext is uniform to
@@ -194,9 +194,10 @@ def timed(fn, reps: int) -> float:
 
 def next_rows(ctx, x, mask, reps: int) -> dict:
     """The operators built on EQ over the same column (n_ct ciphertexts):
-    IN against 4 encrypted members (Eq. eq:in), SELECT (Eq. eq:select), and
-    the rotate-and-add SUM/COUNT (Sec. 4.3) with 15 Galois keys.  Keys and
-    members are seeded uniform residues (timing is data-oblivious)."""
+    IN against 4 encrypted members (Eq. eq:in), SELECT (Eq. eq:select), the
+    rotate-and-add SUM/COUNT (Sec. 4.3) with 15 Galois keys, and LT against
+    one constant (Eq. eq:inequality).  Keys, members and the constant are
+    seeded uniform residues (timing is data-oblivious)."""
     import synth
     dev = ctx.device
     n_ct = x.shape[0]
@@ -231,6 +232,29 @@ def next_rows(ctx, x, mask, reps: int) -> dict:
                         "paper_ms_per_record": 0.04,
                         "paper_source": "Table tab:primitive-times, SUM and COUNT rows"}
     log(f"SUM/COUNT ({len(els)} rotations) {t * 1e3:.1f} ms")
+    # LT against a broadcast constant, in chunks of 8 ciphertexts (the
+    # comparison workspace holds about 420 ciphertext arrays per chunk)
+    const = synth.uniform_device_residues((1, 2), ctx.q, ctx.n, 32, dev)
+    chunk = min(8, n_ct)
+
+    def lt_column():
+        for c0 in range(0, n_ct, chunk):
+            ctx.compare(x[c0:c0 + chunk], const, "lt")
+
+    ctx.compare(x[:chunk], const, "lt")
+    t = timed(lt_column, 1)
+    ctx.profile(True)                 # one chunk, every launch timed
+    ctx.compare(x[:chunk], const, "lt")
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    roof, _ = roofline(prof)
+    out["lt"] = {"rows": rows, "chunk_ct": chunk, "ms": t * 1e3, "records_per_s": rows / t,
+                 "roofline": roof,
+                 "kernels": {kk: {"launches": v["launches"], "ms": v["ms"]}
+                             for kk, v in prof.items()},
+                 "paper_ms_per_record": 3.66,
+                 "paper_source": "Table tab:primitive-times, Comparison rows"}
+    log(f"LT {t * 1e3:.1f} ms")
     return out
 
 
