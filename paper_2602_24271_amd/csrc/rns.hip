@@ -167,13 +167,19 @@ __global__ void __launch_bounds__(256) k_ks_mac(int n, int n_ct, const double* d
     for (int j = 0; j < L; ++j) {
       const double e0 = evk[((size_t)(j * 2 + 0) * K + i) * n + c];
       const double e1 = evk[((size_t)(j * 2 + 1) * K + i) * n + c];
+      // every load of the chunk is issued before the products: past the
+      // last ciphertext the index is clamped (a valid address) and the
+      // result is never stored
+      double dv[CH];
 #pragma unroll
       for (int u = 0; u < CH; ++u) {
-        if (c0 + u < n_ct) {
-          const double dv = __builtin_nontemporal_load(&dig[((size_t)((c0 + u) * L + j) * K + i) * n + c]);
-          a0[u] += mul_lazy(dv, e0, p, pinv);
-          a1[u] += mul_lazy(dv, e1, p, pinv);
-        }
+        const int cu = c0 + u < n_ct ? c0 + u : n_ct - 1;
+        dv[u] = __builtin_nontemporal_load(&dig[((size_t)(cu * L + j) * K + i) * n + c]);
+      }
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        a0[u] += mul_lazy(dv[u], e0, p, pinv);
+        a1[u] += mul_lazy(dv[u], e1, p, pinv);
       }
     }
 #pragma unroll
@@ -190,8 +196,9 @@ __global__ void __launch_bounds__(256) k_ks_mac(int n, int n_ct, const double* d
 // [acc_b]_P is the balanced (= centred) residue of the P limb.  Since
 // mul_lazy(aP, .) needs |aP| < 2p only, P may exceed q_i (both < 2^49).
 template <int L>
-__global__ void __launch_bounds__(256) k_moddown(int n, int n_ct, const double* acc,
-                                                 const double* dt, double* ext, Tables tb) {
+__global__ void __launch_bounds__(256) k_moddown(int n, int n_ct, const double* __restrict__ acc,
+                                                 const double* __restrict__ dt,
+                                                 double* __restrict__ ext, Tables tb) {
   constexpr int K = L + 1;
   constexpr int W = 2 * L + 1;
   const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
