@@ -30,6 +30,8 @@ Modules
             rotate-and-add aggregation of COUNT / SUM
   compare   LT / LE / BETWEEN: the comparison polynomial of the Fermat sum
             and its baby-step giant-step evaluation
+  join      plaintext products, Extract, Broadcast and the fused equi-join
+            aggregation
   ntt_def   the negacyclic number-theoretic transform written from its
             definition (O(N^2)), for checking a device transform's output
 
