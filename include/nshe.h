@@ -249,6 +249,35 @@ int nshe_between(nshe_ctx* ctx, const int64_t* x_dev, const int64_t* lo_dev,
                  const int64_t* hi_dev, int bounds_broadcast, int64_t* out_dev, int n_ct,
                  void* ws_dev, size_t ws_bytes, void* stream);
 
+/* Plaintext products, Extract and Broadcast (the derived operations of
+ * Sec. 2.1.5) and the fused equi-join aggregation (Sec. 4.3, JOIN).
+ *   nshe_mul_plain  out = ([c0 m]_Q, [c1 m]_Q) for the plaintext polynomial
+ *                   m (int64 [N], coefficients in [0, t), taken as centred
+ *                   representatives), exact in Z[X]/(X^N + 1);
+ *   nshe_extract    the product with the basis plaintext of `slot` (slot
+ *                   order as for rotations: its polynomial is
+ *                   N^-1 zeta^-i mod t, zeta the slot's root psi^(+-3^s));
+ *                   with broadcast != 0 followed by nshe_sum_slots, which
+ *                   puts that slot's value in every slot (needs the Galois
+ *                   keys);
+ *   nshe_join_sum   for the fact-table key column a_key (n_ct ciphertexts)
+ *                   and one reference ciphertext each of keys and of an
+ *                   attribute: sum over the given reference rows j of
+ *                   EQ(a_key, bcast(b_key, j)) * bcast(b_attr, j); with
+ *                   unique reference keys each fact row decrypts to the
+ *                   attribute of its matching row among them, else 0.
+ * All need t = 1 (mod 2N) (the batched slots).  Workspace:
+ * nshe_workspace_bytes(ctx, n_ct) for the first two,
+ * nshe_join_workspace_bytes(ctx, n_ct) for the join. */
+int nshe_mul_plain(nshe_ctx* ctx, const int64_t* in_dev, const int64_t* pt_dev,
+                   int64_t* out_dev, int n_ct, void* ws_dev, size_t ws_bytes, void* stream);
+int nshe_extract(nshe_ctx* ctx, const int64_t* in_dev, int slot, int broadcast,
+                 int64_t* out_dev, int n_ct, void* ws_dev, size_t ws_bytes, void* stream);
+size_t nshe_join_workspace_bytes(const nshe_ctx* ctx, int n_ct);
+int nshe_join_sum(nshe_ctx* ctx, const int64_t* a_key_dev, const int64_t* b_key_dev,
+                  const int64_t* b_attr_dev, const int32_t* rows_host, int n_rows,
+                  int64_t* out_dev, int n_ct, void* ws_dev, size_t ws_bytes, void* stream);
+
 /* Slot rotations and the rotate-and-add aggregation (COUNT and SUM,
  * Sec. 4.3 aggregation).  Slots follow the 2 x N/2 layout: slot s < N/2 is
  * the plaintext's value at psi^(3^s), slot N/2 + s at psi^(-3^s) (psi a

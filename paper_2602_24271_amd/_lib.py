@@ -66,6 +66,11 @@ SIGNATURES = {
     "nshe_compare_workspace_bytes": (_SZ, [_P, _I]),
     "nshe_compare": (_I, [_P, _P, _P, _I, _I, _P, _I, _P, _SZ, _P]),
     "nshe_between": (_I, [_P, _P, _P, _P, _I, _P, _I, _P, _SZ, _P]),
+    "nshe_mul_plain": (_I, [_P, _P, _P, _P, _I, _P, _SZ, _P]),
+    "nshe_extract": (_I, [_P, _P, _I, _I, _P, _I, _P, _SZ, _P]),
+    "nshe_join_workspace_bytes": (_SZ, [_P, _I]),
+    "nshe_join_sum": (_I, [_P, _P, _P, _P, ctypes.POINTER(ctypes.c_int32), _I, _P, _I, _P, _SZ,
+                           _P]),
     "nshe_set_galois_key": (_I, [_P, ctypes.c_uint32, _P, _P]),
     "nshe_galois_elements": (_I, [_P, ctypes.POINTER(ctypes.c_uint32), _I, ctypes.POINTER(_I)]),
     "nshe_rotate": (_I, [_P, _P, ctypes.c_uint32, _P, _I, _P, _SZ, _P]),

@@ -182,6 +182,41 @@ class Context:
                                           ws.numel(), _stream()))
         return out
 
+    def mul_plain(self, x: torch.Tensor, pt: torch.Tensor) -> torch.Tensor:
+        """x times the plaintext polynomial pt (int64 [N], values in [0, t))."""
+        n = self._check_ct(x)
+        if pt.dtype != torch.int64 or pt.device != self.device or tuple(pt.shape) != (self.n,):
+            raise ValueError("pt must be an int64 [N] tensor on the context device")
+        out = torch.empty_like(x)
+        ws = self.workspace(n)
+        _lib.check(self._lib.nshe_mul_plain(self._h, _ptr(x), _ptr(pt.contiguous()), _ptr(out), n,
+                                            _ptr(ws), ws.numel(), _stream()))
+        return out
+
+    def extract(self, x: torch.Tensor, slot: int, broadcast: bool = False) -> torch.Tensor:
+        """Extract one slot (others zero), or Broadcast it to every slot."""
+        n = self._check_ct(x)
+        out = torch.empty_like(x)
+        ws = self.workspace(n)
+        _lib.check(self._lib.nshe_extract(self._h, _ptr(x), slot, int(bool(broadcast)), _ptr(out),
+                                          n, _ptr(ws), ws.numel(), _stream()))
+        return out
+
+    def join_sum(self, a_key: torch.Tensor, b_key: torch.Tensor, b_attr: torch.Tensor,
+                 rows) -> torch.Tensor:
+        """Fused equi-join aggregation over the reference rows `rows`."""
+        n = self._check_ct(a_key)
+        if self._check_ct(b_key) != 1 or self._check_ct(b_attr) != 1:
+            raise ValueError("b_key and b_attr must be one ciphertext each")
+        rows = list(rows)
+        arr = (ctypes.c_int32 * max(1, len(rows)))(*rows)
+        out = torch.empty_like(a_key)
+        ws = self._workspace_bytes(int(self._lib.nshe_join_workspace_bytes(self._h, n)))
+        _lib.check(self._lib.nshe_join_sum(self._h, _ptr(a_key), _ptr(b_key), _ptr(b_attr), arr,
+                                           len(rows), _ptr(out), n, _ptr(ws), ws.numel(),
+                                           _stream()))
+        return out
+
     def galois_elements(self) -> list:
         """Galois elements whose keys nshe_sum_slots needs, in order of use."""
         n = ctypes.c_int(0)

@@ -1138,6 +1138,11 @@ int nshe_eq_mask_batched(nshe_ctx* c, const nshe_item* items, int n_items, int w
   return NSHE_OK;
 }
 
+// bytes of an int64 ciphertext array, rounded up to 256
+static size_t ct_bytes(const nshe_ctx* c, int n_ct) {
+  return ((size_t)n_ct * 2 * c->L * c->n * sizeof(int64_t) + 255) & ~(size_t)255;
+}
+
 // ------------------------------------------------------------- rotations
 
 // Galois elements of the rotate-and-add sum, in order: 3^(N/4), ..., 3^1
@@ -1181,6 +1186,31 @@ static int rotate_ext(nshe_ctx* c, const Ws& w, int n_ct, uint32_t g, const doub
   return relin(c, w, n_ct, st, key, out);
 }
 
+// ct <- ct + rot_g(ct) over the sum elements, on the ciphertexts in w.ext
+static int sum_slots_ext(nshe_ctx* c, const Ws& w, int n_ct, const std::vector<uint32_t>& els,
+                         const std::vector<const double*>& keys, hipStream_t st) {
+  Dims d = dims(c, n_ct);
+  for (size_t k = 0; k < els.size(); ++k) {
+    int rc = rotate_ext(c, w, n_ct, els[k], keys[k], w.fx, st);
+    if (rc) return rc;
+    Prof pf(c, K_ADD, st, 2.0 * n_ct * c->L * c->n);
+    HIPCHK(run_add_bal(d, w.ext, w.fx, c->tb, st));
+  }
+  return NSHE_OK;
+}
+
+// The Galois keys of the sum elements (NSHE_ENOKEY naming a missing one).
+static int sum_keys(nshe_ctx* c, std::vector<uint32_t>* els, std::vector<const double*>* keys) {
+  *els = sum_elements(c);
+  keys->clear();
+  for (uint32_t g : *els) {
+    auto k = c->galois.find(g);
+    if (k == c->galois.end()) return fail(NSHE_ENOKEY, "no Galois key for g = " + std::to_string(g));
+    keys->push_back(k->second);
+  }
+  return NSHE_OK;
+}
+
 int nshe_galois_elements(const nshe_ctx* c, uint32_t* out, int max_out, int* n_out) {
   g_err.clear();
   if (check_ctx(c) || !n_out || (max_out > 0 && !out)) return fail(NSHE_EINVAL, "null argument");
@@ -1215,25 +1245,192 @@ int nshe_sum_slots(nshe_ctx* c, const int64_t* in, int64_t* out, int n_ct, void*
   if (rc) return rc;
   if (n_ct == 0) return NSHE_OK;
   if (!in || !out) return fail(NSHE_EINVAL, "null buffer");
-  const std::vector<uint32_t> els = sum_elements(c);
+  std::vector<uint32_t> els;
   std::vector<const double*> keys;
-  for (uint32_t g : els) {
-    auto k = c->galois.find(g);
-    if (k == c->galois.end()) return fail(NSHE_ENOKEY, "no Galois key for g = " + std::to_string(g));
-    keys.push_back(k->second);
+  rc = sum_keys(c, &els, &keys);
+  if (rc) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Ws w = carve(c, ws, n_ct);
+  Dims d = dims(c, n_ct);
+  const size_t W = W_of(c), N = c->n;
+  HIPCHK(run_i64_to_polys(d, in, 2, w.ext, 2 * W * N, W * N, 2, c->tb, st));
+  rc = sum_slots_ext(c, w, n_ct, els, keys, st);
+  if (rc) return rc;
+  HIPCHK(run_polys_to_i64(d, w.ext, 2, 2 * W * N, W * N, out, 0, c->tb, st));
+  return NSHE_OK;
+}
+
+// ------------------------------------------------------ plaintext products
+
+// ct (in w.ext, data limbs) times the plaintext pt (int64 [N] in [0, t)) into
+// w.fx's data limbs: forward transforms of ct and of the plaintext's limbs
+// (times N^-1, in w.dt), pointwise products, inverse transform.
+static int mul_plain_ext(nshe_ctx* c, const Ws& w, const int64_t* pt, int n_ct, hipStream_t st) {
+  Dims d = dims(c, n_ct);
+  const size_t W = W_of(c), N = c->n;
+  HIPCHK(run_plain_limbs(d, (int64_t)c->t, pt, w.dt, c->tb, st));
+  NttJob j{};
+  j.split = c->tune.split_forward;
+  j.base = w.dt;
+  j.out = w.dt + W * N;
+  j.poly_stride = W * N;
+  j.npoly = 1;
+  j.nlimb = c->L;
+  j.limb_prime = c->lp_ext;
+  j.count = c->L;
+  {
+    Prof pf(c, K_NTT_FWD, st, ntt_work(c, j.count));
+    HIPCHK(run_ntt(c->log2n, j, c->tb, 0, st));
+  }
+  j.base = w.ext;
+  j.out = w.fx;
+  j.npoly = 2 * n_ct;
+  j.count = j.npoly * c->L;
+  {
+    Prof pf(c, K_NTT_FWD, st, ntt_work(c, j.count));
+    HIPCHK(run_ntt(c->log2n, j, c->tb, 0, st));
+  }
+  HIPCHK(run_pointwise_plain(d, w.fx, w.dt + W * N, c->tb, st));
+  j.base = w.fx;
+  j.out = nullptr;
+  {
+    Prof pf(c, K_NTT_INV, st, ntt_work(c, j.count));
+    HIPCHK(run_ntt(c->log2n, j, c->tb, 1, st));
+  }
+  return NSHE_OK;
+}
+
+// The basis plaintext of `slot` (slot order of the 2 x N/2 layout) into out.
+static int basis_plain(nshe_ctx* c, int slot, int64_t* out, hipStream_t st) {
+  const u64 t = c->t, two_n = 2ull * c->n;
+  const u64 psi = powmod(primitive_root(t), (t - 1) / two_n, t);
+  const int half = c->n / 2;
+  u64 e = 1;
+  for (int s = 0; s < slot % half; ++s) e = e * 3 % two_n;
+  if (slot >= half) e = two_n - e;
+  const u64 zinv = powmod(psi, two_n - e, t);   // psi^-e
+  HIPCHK(run_basis_plain(c->n, t, zinv, invmod((u64)c->n % t, t), out, st));
+  return NSHE_OK;
+}
+
+int nshe_mul_plain(nshe_ctx* c, const int64_t* in, const int64_t* pt, int64_t* out, int n_ct,
+                   void* ws, size_t ws_bytes, void* stream) {
+  int rc = common_checks(c, n_ct, ws, ws_bytes, false);
+  if (rc) return rc;
+  if (n_ct == 0) return NSHE_OK;
+  if (!in || !pt || !out) return fail(NSHE_EINVAL, "null buffer");
+  if ((c->t - 1) % (2ull * c->n)) return fail(NSHE_EINVAL, "plaintext slots need t = 1 mod 2N");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Ws w = carve(c, ws, n_ct);
+  Dims d = dims(c, n_ct);
+  const size_t W = W_of(c), N = c->n;
+  HIPCHK(run_i64_to_polys(d, in, 2, w.ext, 2 * W * N, W * N, 2, c->tb, st));
+  rc = mul_plain_ext(c, w, pt, n_ct, st);
+  if (rc) return rc;
+  HIPCHK(run_polys_to_i64(d, w.fx, 2, 2 * W * N, W * N, out, 0, c->tb, st));
+  return NSHE_OK;
+}
+
+// Extract (broadcast = 0) or Broadcast (1) of one slot, ciphertexts in w.ext
+// -> w.ext.
+static int extract_ext(nshe_ctx* c, const Ws& w, int slot, int n_ct, int bcast, hipStream_t st) {
+  int64_t* pt = reinterpret_cast<int64_t*>(w.acc);
+  int rc = basis_plain(c, slot, pt, st);
+  if (rc) return rc;
+  rc = mul_plain_ext(c, w, pt, n_ct, st);
+  if (rc) return rc;
+  const size_t W = W_of(c), N = c->n;
+  HIPCHK(hipMemcpyAsync(w.ext, w.fx, (size_t)n_ct * 2 * W * N * sizeof(double),
+                        hipMemcpyDeviceToDevice, st));
+  if (!bcast) return NSHE_OK;
+  std::vector<uint32_t> els;
+  std::vector<const double*> keys;
+  rc = sum_keys(c, &els, &keys);
+  if (rc) return rc;
+  return sum_slots_ext(c, w, n_ct, els, keys, st);
+}
+
+int nshe_extract(nshe_ctx* c, const int64_t* in, int slot, int broadcast, int64_t* out,
+                 int n_ct, void* ws, size_t ws_bytes, void* stream) {
+  int rc = common_checks(c, n_ct, ws, ws_bytes, false);
+  if (rc) return rc;
+  if (n_ct == 0) return NSHE_OK;
+  if (!in || !out) return fail(NSHE_EINVAL, "null buffer");
+  if (slot < 0 || slot >= c->n) return fail(NSHE_EINVAL, "slot out of range");
+  if ((c->t - 1) % (2ull * c->n)) return fail(NSHE_EINVAL, "plaintext slots need t = 1 mod 2N");
+  if (broadcast) {
+    std::vector<uint32_t> els;
+    std::vector<const double*> keys;
+    rc = sum_keys(c, &els, &keys);
+    if (rc) return rc;
   }
   hipStream_t st = static_cast<hipStream_t>(stream);
   Ws w = carve(c, ws, n_ct);
   Dims d = dims(c, n_ct);
   const size_t W = W_of(c), N = c->n;
   HIPCHK(run_i64_to_polys(d, in, 2, w.ext, 2 * W * N, W * N, 2, c->tb, st));
-  for (size_t k = 0; k < els.size(); ++k) {
-    rc = rotate_ext(c, w, n_ct, els[k], keys[k], w.fx, st);
-    if (rc) return rc;
-    Prof pf(c, K_ADD, st, 2.0 * n_ct * c->L * c->n);
-    HIPCHK(run_add_bal(d, w.ext, w.fx, c->tb, st));
-  }
+  rc = extract_ext(c, w, slot, n_ct, broadcast ? 1 : 0, st);
+  if (rc) return rc;
   HIPCHK(run_polys_to_i64(d, w.ext, 2, 2 * W * N, W * N, out, 0, c->tb, st));
+  return NSHE_OK;
+}
+
+// ------------------------------------------------------------------ JOIN
+
+size_t nshe_join_workspace_bytes(const nshe_ctx* c, int n_ct) {
+  if (check_ctx(c) || n_ct < 0) return 0;
+  return 3 * ct_bytes(c, n_ct) + 2 * ct_bytes(c, 1) + ws_doubles(c, std::max(n_ct, 1)) * sizeof(double);
+}
+
+int nshe_join_sum(nshe_ctx* c, const int64_t* a_key, const int64_t* b_key, const int64_t* b_attr,
+                  const int32_t* rows, int n_rows, int64_t* out, int n_ct, void* ws,
+                  size_t ws_bytes, void* stream) {
+  g_err.clear();
+  if (check_ctx(c)) return NSHE_EINVAL;
+  if (n_ct < 0 || n_rows < 0) return fail(NSHE_ESHAPE, "n_ct or n_rows < 0");
+  if (n_ct == 0) return NSHE_OK;
+  if (!a_key || !b_key || !b_attr || !out || (n_rows > 0 && !rows))
+    return fail(NSHE_EINVAL, "null buffer");
+  if (c->squarings < 0) return fail(NSHE_EDEPTH, "t - 1 is not a power of two");
+  if ((c->t - 1) % (2ull * c->n)) return fail(NSHE_EINVAL, "plaintext slots need t = 1 mod 2N");
+  for (int r = 0; r < n_rows; ++r)
+    if (rows[r] < 0 || rows[r] >= c->n) return fail(NSHE_EINVAL, "row index out of range");
+  if (check_key(c)) return NSHE_ENOKEY;
+  {
+    std::vector<uint32_t> els;
+    std::vector<const double*> keys;
+    int rc = sum_keys(c, &els, &keys);
+    if (rc) return rc;
+  }
+  if (!ws) return fail(NSHE_EINVAL, "workspace pointer is null");
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(NSHE_EINVAL, "workspace not 256-byte aligned");
+  if (ws_bytes < nshe_join_workspace_bytes(c, n_ct))
+    return fail(NSHE_ENOMEM, "workspace smaller than nshe_join_workspace_bytes(ctx, n_ct)");
+  if (set_device(c)) return NSHE_EDEVICE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (n_rows == 0) return nshe_sum(c, nullptr, 0, out, n_ct, stream);
+  const size_t cb = ct_bytes(c, n_ct), cb1 = ct_bytes(c, 1);
+  char* p = static_cast<char*>(ws);
+  int64_t* mask = reinterpret_cast<int64_t*>(p);
+  int64_t* term = reinterpret_cast<int64_t*>(p + cb);
+  int64_t* rep = reinterpret_cast<int64_t*>(p + 2 * cb);
+  int64_t* bk = reinterpret_cast<int64_t*>(p + 3 * cb);
+  int64_t* ba = reinterpret_cast<int64_t*>(p + 3 * cb + cb1);
+  void* mws = p + 3 * cb + 2 * cb1;
+  const size_t mws_bytes = ws_bytes - (3 * cb + 2 * cb1);
+  const size_t ctw = (size_t)2 * c->L * c->n;
+  Dims d = dims(c, n_ct);
+  for (int r = 0; r < n_rows; ++r) {
+    int rc = nshe_extract(c, b_key, rows[r], 1, bk, 1, mws, mws_bytes, stream);
+    if (!rc) rc = nshe_extract(c, b_attr, rows[r], 1, ba, 1, mws, mws_bytes, stream);
+    if (!rc) rc = nshe_eq_mask(c, a_key, bk, mask, n_ct, 1, mws, mws_bytes, stream);
+    if (rc) return rc;
+    for (int k = 0; k < n_ct; ++k)
+      HIPCHK(hipMemcpyAsync(rep + k * ctw, ba, ctw * sizeof(int64_t), hipMemcpyDeviceToDevice, st));
+    rc = nshe_mul_relin(c, mask, rep, r == 0 ? out : term, n_ct, mws, mws_bytes, stream);
+    if (rc) return rc;
+    if (r > 0) HIPCHK(run_sum_i64(d, out, term, 0, 1, out, c->tb, st));
+  }
   return NSHE_OK;
 }
 
@@ -1243,10 +1440,6 @@ static int ilog2(int x) {
   int r = 0;
   while ((1 << (r + 1)) <= x) ++r;
   return r;
-}
-
-static size_t ct_bytes(const nshe_ctx* c, int n_ct) {
-  return ((size_t)n_ct * 2 * c->L * c->n * sizeof(int64_t) + 255) & ~(size_t)255;
 }
 
 // Ciphertext-array slots of the comparison workspace (then the multiply

@@ -98,6 +98,14 @@ hipError_t run_moddown(const Dims& d, const double* acc, const double* dt, doubl
 // conversions at the boundary
 hipError_t run_sub_to_ext(const Dims& d, const int64_t* x, const int64_t* y, int y_bcast,
                           double* ext, const Tables& tb, hipStream_t st);
+// plaintext products: a slot's basis plaintext, a plaintext's limbs (times
+// N^-1), and the pointwise product with the data limbs of transforms
+hipError_t run_basis_plain(int n, uint64_t t, uint64_t zinv, uint64_t ninv_t, int64_t* out,
+                           hipStream_t st);
+hipError_t run_plain_limbs(const Dims& d, int64_t t, const int64_t* pt, double* out,
+                           const Tables& tb, hipStream_t st);
+hipError_t run_pointwise_plain(const Dims& d, double* fx, const double* pt, const Tables& tb,
+                               hipStream_t st);
 // comparisons: scalar linear combinations of up to 256 ciphertext arrays
 // (J <= 16 outputs, coefficient rows [J][k]), the trivial encryption of 1,
 // and differences with optional broadcast and sign

@@ -223,6 +223,49 @@ __global__ void __launch_bounds__(256) k_moddown(int n, int n_ct, const double* 
   }
 }
 
+// ------------------------------------------------------ plaintext products ---
+
+// The basis plaintext of one slot: m_i = N^-1 zeta^-i mod t, zinv = zeta^-1
+// for the slot's root zeta (t < 2^24, so products fit 64 bits).
+__global__ void __launch_bounds__(256) k_basis_plain(int n, uint64_t t, uint64_t zinv,
+                                                     uint64_t ninv_t, int64_t* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t r = 1, b = zinv;
+  for (unsigned e = (unsigned)i; e; e >>= 1) {
+    if (e & 1) r = r * b % t;
+    b = b * b % t;
+  }
+  out[i] = (int64_t)(r * ninv_t % t);
+}
+
+// Plaintext polynomial (int64 [N] in [0, t)) -> its centred value times
+// N^-1 in each data prime (limbs 0..L-1 at stride N): the operand of a
+// pointwise product whose inverse transform returns N times the result.
+__global__ void __launch_bounds__(256) k_plain_limbs(int n, int L, int64_t t, const int64_t* pt,
+                                                     double* out, Tables tb) {
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (size_t)L * n) return;
+  const int i = (int)(gid / n);
+  const int c = (int)(gid - (size_t)i * n);
+  const int64_t v = pt[c];
+  const double x = (double)(v > t / 2 ? v - t : v);
+  out[gid] = mul_bal(x, cld(tb.ninv, i), cld(tb.p, i), cld(tb.pinv, i));
+}
+
+// fx[ct][b][i] *= pt[i] (NTT domain, data limbs of [ct][2][W][N]).
+__global__ void __launch_bounds__(256) k_pointwise_plain(int n, int L, int n_ct, double* fx,
+                                                         const double* pt, Tables tb) {
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (size_t)n_ct * 2 * L * n) return;
+  const size_t row = gid / n;
+  const int c = (int)(gid - row * n);
+  const int i = (int)(row % L);
+  const size_t cb = row / L;
+  const size_t off = (cb * (2 * L + 1) + i) * n + c;
+  fx[off] = mul_bal(fx[off], pt[(size_t)i * n + c], cld(tb.p, i), cld(tb.pinv, i));
+}
+
 // ----------------------------------------------------------- comparisons ---
 
 // out[jj * out_stride + r] = [sum_t coef[jj * k + t] * b.p[t][r]]_q per
@@ -584,6 +627,27 @@ hipError_t run_sub_to_ext(const Dims& d, const int64_t* x, const int64_t* y, int
   const size_t total = (size_t)d.n_ct * 2 * d.L * d.n;
   hipLaunchKernelGGL(k_sub_to_ext, grid_for(total), dim3(256), 0, st, d.n, d.L, d.n_ct, x, y,
                      y_bcast, ext, tb);
+  return hipGetLastError();
+}
+
+hipError_t run_basis_plain(int n, uint64_t t, uint64_t zinv, uint64_t ninv_t, int64_t* out,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_basis_plain, grid_for(n), dim3(256), 0, st, n, t, zinv, ninv_t, out);
+  return hipGetLastError();
+}
+
+hipError_t run_plain_limbs(const Dims& d, int64_t t, const int64_t* pt, double* out,
+                           const Tables& tb, hipStream_t st) {
+  hipLaunchKernelGGL(k_plain_limbs, grid_for((size_t)d.L * d.n), dim3(256), 0, st, d.n, d.L, t, pt,
+                     out, tb);
+  return hipGetLastError();
+}
+
+hipError_t run_pointwise_plain(const Dims& d, double* fx, const double* pt, const Tables& tb,
+                               hipStream_t st) {
+  const size_t total = (size_t)d.n_ct * 2 * d.L * d.n;
+  hipLaunchKernelGGL(k_pointwise_plain, grid_for(total), dim3(256), 0, st, d.n, d.L, d.n_ct, fx, pt,
+                     tb);
   return hipGetLastError();
 }
 
