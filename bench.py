@@ -16,8 +16,8 @@ second.  The line also carries:
   batched       512 instances of uneven size (rows log-uniform in
                 [2^14, 2^20]) in HIP-graph waves (autotuned launch shapes and
                 wave size) vs a per-instance launch loop;
-  next_rows     IN against 4 members, SELECT, the rotate-and-add SUM/COUNT
-                and LT against a constant over the same column;
+  next_rows     IN against 4 members, SELECT, the rotate-and-add SUM/COUNT,
+                LT against a constant and a 4-row JOIN over the same column;
   cpu_baseline  the exact-integer oracle on a bounded sample, host cores.
 
 Inputs are seeded uniform residues: a fresh RLWE ciphertext is uniform to
@@ -255,6 +255,16 @@ def next_rows(ctx, x, mask, reps: int) -> dict:
                  "paper_ms_per_record": 3.66,
                  "paper_source": "Table tab:primitive-times, Comparison rows"}
     log(f"LT {t * 1e3:.1f} ms")
+    # JOIN: the column as fact-table keys against 4 rows of one reference
+    # ciphertext (keys and an attribute), Galois keys as loaded above
+    b_key = synth.uniform_device_residues((1, 2), ctx.q, ctx.n, 33, dev)
+    b_attr = synth.uniform_device_residues((1, 2), ctx.q, ctx.n, 34, dev)
+    rows_j = [0, 1, 2, 3]
+    t = timed(lambda: ctx.join_sum(x, b_key, b_attr, rows_j), 1)
+    out["join"] = {"rows": rows, "reference_rows": len(rows_j), "ms": t * 1e3,
+                   "ms_per_reference_row": t * 1e3 / len(rows_j),
+                   "fact_records_per_s_per_reference_row": rows * len(rows_j) / t}
+    log(f"JOIN ({len(rows_j)} reference rows) {t * 1e3:.1f} ms")
     return out
 
 
