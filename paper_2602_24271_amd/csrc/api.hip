@@ -535,6 +535,16 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
     }
   }
   std::vector<double> tw_h((size_t)K * 2 * h_len, 0.0), tw_h0(K, 0.0);
+  // compact last-round tables (first twiddle of each stage per row) and the
+  // per-(stage, slot) constants omega_k^(+-brv_k(j)), omega_k = psi^(N/2^k)
+  const int last_ss = c->rounds >= 2 ? c->r0 + (c->rounds - 2) * c->loge : 0;
+  const int last_len = c->rounds >= 2 ? (1 << last_ss) * 8 : 0;
+  const int last_h_ss = h_rounds >= 2 ? h_r0 + (h_rounds - 2) * h_loge : 0;
+  const int last_h_len = h_rounds >= 2 ? (1 << last_h_ss) * 8 : 0;
+  std::vector<double> tw_lf((size_t)K * std::max(last_len, 1), 0.0),
+      tw_li((size_t)K * std::max(last_len, 1), 0.0),
+      tw_lh((size_t)K * 2 * std::max(last_h_len, 1), 0.0), tw_cf((size_t)K * 32, 0.0),
+      tw_ci((size_t)K * 32, 0.0);
   {
     const int E = 1 << c->loge;
     std::vector<u64> pbr(n), pibr(n);
@@ -552,6 +562,27 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
         pbr[i] = pw[brv(i, c->log2n)];
         pibr[i] = pwi[brv(i, c->log2n)];
       }
+      for (int kk = 1; kk < c->loge && kk < 5; ++kk) {
+        const u64 om = powmod(psi, (u64)n >> kk, p), omi = invmod(om, p);
+        for (int j = 1; j < (1 << kk); ++j) {
+          tw_cf[(size_t)k * 32 + (1 << kk) + j] = bal(powmod(om, (u64)brv(j, kk), p), p);
+          tw_ci[(size_t)k * 32 + (1 << kk) + j] = bal(powmod(omi, (u64)brv(j, kk), p), p);
+        }
+      }
+      if (last_len)
+        for (int u = 0; u < (1 << last_ss); ++u)
+          for (int kk = 0; kk < c->loge; ++kk) {
+            const int idx = (1 << (last_ss + kk)) + (u << kk);
+            tw_lf[(size_t)k * last_len + (size_t)u * 8 + kk] = bal(pbr[idx], p);
+            tw_li[(size_t)k * last_len + (size_t)u * 8 + kk] = bal(pibr[idx], p);
+          }
+      if (last_h_len)
+        for (int hh = 0; hh < 2; ++hh)
+          for (int u = 0; u < (1 << last_h_ss); ++u)
+            for (int kk = 0; kk < h_loge; ++kk) {
+              const int idx = (1 << (last_h_ss + kk)) * (2 + hh) + (u << kk);
+              tw_lh[((size_t)k * 2 + hh) * last_h_len + (size_t)u * 8 + kk] = bal(pbr[idx], p);
+            }
       if (h_len) {
         tw_h0[k] = bal(pbr[1], p);
         const int E = 1 << h_loge;
@@ -647,7 +678,8 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
       {&B_q, &c->tb.B_q},         {&P_inv_q, &c->tb.P_inv_q}, {&NP_inv_q, &c->tb.NP_inv_q},
       {&delta_q, &c->tb.delta_q},
       {&mrc_inv, &c->tb.mrc_inv}, {&mrc_half, &c->tb.mrc_half}, {&tw_h, &c->tb.tw_half},
-      {&tw_h0, &c->tb.tw_half0}};
+      {&tw_h0, &c->tb.tw_half0},  {&tw_lf, &c->tb.tw_last_f}, {&tw_li, &c->tb.tw_last_i},
+      {&tw_lh, &c->tb.tw_last_h}, {&tw_cf, &c->tb.tw_cst_f},  {&tw_ci, &c->tb.tw_cst_i}};
   size_t total = 0;
   std::vector<size_t> offs;
   for (auto& pp : parts) {
@@ -690,6 +722,8 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
   }
   c->tb.tw_len = c->tw_len;
   c->tb.tw_half_len = h_len;
+  c->tb.tw_last_len = last_len;
+  c->tb.tw_last_h_len = last_h_len;
   if (!h_len) {
     c->tb.tw_half = nullptr;
     c->tb.tw_half0 = nullptr;

@@ -259,11 +259,65 @@ struct Twiddles {
 // rounds fetch one stage ahead: stage k+1's twiddles are issued at the start
 // of stage k (fenced on stage k-1's results, so no further), hiding the
 // load latency behind one stage of butterflies.
+// Twiddle sources of a transform: the per-round tables, and for the last
+// round the compact table (first twiddle of each stage per index row) with
+// the per-(stage, slot) constants: W(k, j) = W(k, 0) omega_k^(+-brv_k(j)),
+// since the bits of j, of the row and of the stage are disjoint in the
+// bit-reversed exponent.
+struct TwSrc {
+  const double* tw;
+  const double* last;
+  const double* cst;
+};
+
+// The last round (r > 0, LOGE stages) with compact twiddles: 5 loads per
+// thread instead of 31, the other twiddles one product each.
+template <int LOGN, bool FWD>
+__device__ __forceinline__ void last_round(double (&x)[NttShape<LOGN>::E], int r, const TwSrc& t,
+                                           double p, double pinv) {
+  using S = NttShape<LOGN>;
+  const auto rl = make_rsrc(t.last, (1 << S::s_start(r)) * 64);
+  const unsigned lo = (threadIdx.x >> S::lo(r)) * 64;
+  double wb[S::LOGE];
+#pragma unroll
+  for (int k = 0; k < S::LOGE; ++k) wb[k] = buf_load(rl, lo, k * 8);
+#pragma unroll
+  for (int kk = 0; kk < S::LOGE; ++kk) {
+    const int k = FWD ? kk : S::LOGE - 1 - kk;
+    const int eb = S::LOGE - 1 - k;
+#pragma unroll
+    for (int j = 0; j < (1 << k); ++j) {
+      const double w = j == 0 ? wb[k] : mul_bal(wb[k], cld(t.cst, (1 << k) + j), p, pinv);
+#pragma unroll
+      for (int b = 0; b < (1 << eb); ++b) {
+        const int e = (j << (eb + 1)) | b;
+        if constexpr (FWD) {
+          ct_bfly(x[e], x[e | (1 << eb)], w, p, pinv);
+        } else {
+          if (kk & 1)
+            gs_bfly<true>(x[e], x[e | (1 << eb)], w, p, pinv);
+          else
+            gs_bfly<false>(x[e], x[e | (1 << eb)], w, p, pinv);
+        }
+      }
+    }
+  }
+}
+
 template <int LOGN>
 __device__ __forceinline__ void fwd_round(double (&x)[NttShape<LOGN>::E], int r, bool reduce,
-                                          const double* __restrict__ tw, double p, double pinv) {
+                                          const TwSrc& ts, double p, double pinv) {
   using S = NttShape<LOGN>;
   constexpr int HALF = S::E / 2;
+  if (r > 0 && r == S::ROUNDS - 1) {
+    last_round<LOGN, true>(x, r, ts, p, pinv);
+    if (reduce) {
+#pragma unroll
+      for (int e = 0; e < S::E; ++e) x[e] = reduce_bal(x[e], p, pinv);
+    }
+    return;
+  }
+  const double* __restrict__ tw = ts.tw;
   const Twiddles<LOGN> T(tw, r);
   const int R = S::stages(r);
   double cur[HALF], nxt[HALF];
@@ -299,9 +353,16 @@ if (reduce) {
 
 template <int LOGN>
 __device__ __forceinline__ void inv_round(double (&x)[NttShape<LOGN>::E], int r, int g0,
-                                          const double* __restrict__ tw, double p, double pinv) {
+                                          const TwSrc& ts, double p, double pinv) {
   using S = NttShape<LOGN>;
   constexpr int HALF = S::E / 2;
+  if (r > 0 && r == S::ROUNDS - 1) {
+    // processed first: g0 = 0, so the sums of odd local stages are reduced,
+    // as in the general path
+    last_round<LOGN, false>(x, r, ts, p, pinv);
+    return;
+  }
+  const double* __restrict__ tw = ts.tw;
   const Twiddles<LOGN> T(tw, r);
   const int R = S::stages(r);
   double cur[HALF], nxt[HALF];
@@ -382,7 +443,8 @@ k_ntt_fwd(NttJob job, Tables tb) {
   }
   const int prime = cldi(job.limb_prime, limb);
   const double p = cld(tb.p, prime), pinv = cld(tb.pinv, prime);
-  const double* __restrict__ tw = tb.tw_fwd + (size_t)prime * tb.tw_len;
+  const TwSrc tw{tb.tw_fwd + (size_t)prime * tb.tw_len,
+                 tb.tw_last_f + (size_t)prime * tb.tw_last_len, tb.tw_cst_f + (size_t)prime * 32};
   const size_t off = (size_t)poly * job.poly_stride + (size_t)limb * S::N;
   double* dst = job.base + off;
   const auto rd = make_rsrc(dst, S::N * 8);
@@ -432,7 +494,8 @@ k_ntt_inv(NttJob job, Tables tb) {
   const int poly = item - limb * job.npoly;
   const int prime = cldi(job.limb_prime, limb);
   const double p = cld(tb.p, prime), pinv = cld(tb.pinv, prime);
-  const double* __restrict__ tw = tb.tw_inv + (size_t)prime * tb.tw_len;
+  const TwSrc tw{tb.tw_inv + (size_t)prime * tb.tw_len,
+                 tb.tw_last_i + (size_t)prime * tb.tw_last_len, tb.tw_cst_i + (size_t)prime * 32};
   const size_t off = (size_t)poly * job.poly_stride + (size_t)limb * S::N;
   double* dst = job.base + off;
   const auto rd = make_rsrc(dst, S::N * 8);
@@ -561,7 +624,9 @@ k_ntt_fwd_half(NttJob job, Tables tb) {
   const int prime = cldi(job.limb_prime, limb);
   const double p = cld(tb.p, prime), pinv = cld(tb.pinv, prime);
   const double w0 = cld(tb.tw_half0, prime);
-  const double* __restrict__ tw = tb.tw_half + ((size_t)prime * 2 + h) * tb.tw_half_len;
+  const TwSrc tw{tb.tw_half + ((size_t)prime * 2 + h) * tb.tw_half_len,
+                 tb.tw_last_h + ((size_t)prime * 2 + h) * tb.tw_last_h_len,
+                 tb.tw_cst_f + (size_t)prime * 32};
   // Both halves read the whole input limb, so the output must be another
   // buffer (the host never launches this kernel in place).
   const size_t off = (size_t)poly * job.poly_stride + (size_t)limb * NF;
