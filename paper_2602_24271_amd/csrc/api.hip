@@ -503,15 +503,7 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
   c->primes.insert(c->primes.end(), b.begin(), b.end());
   c->primes.push_back(pr->P);
   c->rounds = ntt_rounds(c->log2n, &c->loge, &c->r0);
-  {
-    const int E = 1 << c->loge;
-    int len = 0;
-    for (int r = 0; r < c->rounds; ++r) {
-      const int ss = r == 0 ? 0 : c->r0 + (r - 1) * c->loge;
-      len += (1 << ss) * E;
-    }
-    c->tw_len = len;
-  }
+  c->tw_len = 1 << c->loge;   // round 0's row
   const int K = c->K;
   const std::vector<u64>& P_ = c->primes;
   auto prime = [&](int i) { return P_[i]; };
@@ -524,29 +516,27 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
     h_ninv[i] = bal(invmod((u64)n, prime(i)), prime(i));
   }
   std::vector<double> tw_f((size_t)K * c->tw_len, 0.0), tw_i((size_t)K * c->tw_len, 0.0);
-  // N = 2^15: twiddles of the two half-limb forward sub-transforms (2^14
-  // points each; the shape of the 2^14 transform)
-  int h_loge = 0, h_r0 = 0, h_rounds = 0, h_len = 0;
-  if (c->log2n == 15) {
-    h_rounds = ntt_rounds(14, &h_loge, &h_r0);
-    for (int r = 0; r < h_rounds; ++r) {
-      const int ss = r == 0 ? 0 : h_r0 + (r - 1) * h_loge;
-      h_len += (1 << ss) << h_loge;
-    }
-  }
-  std::vector<double> tw_h((size_t)K * 2 * h_len, 0.0), tw_h0(K, 0.0);
-  // compact last-round tables (first twiddle of each stage per row) and the
-  // per-(stage, slot) constants omega_k^(+-brv_k(j)), omega_k = psi^(N/2^k)
-  const int last_ss = c->rounds >= 2 ? c->r0 + (c->rounds - 2) * c->loge : 0;
-  const int last_len = c->rounds >= 2 ? (1 << last_ss) * 8 : 0;
-  const int last_h_ss = h_rounds >= 2 ? h_r0 + (h_rounds - 2) * h_loge : 0;
-  const int last_h_len = h_rounds >= 2 ? (1 << last_h_ss) * 8 : 0;
-  std::vector<double> tw_lf((size_t)K * std::max(last_len, 1), 0.0),
-      tw_li((size_t)K * std::max(last_len, 1), 0.0),
-      tw_lh((size_t)K * 2 * std::max(last_h_len, 1), 0.0), tw_cf((size_t)K * 32, 0.0),
-      tw_ci((size_t)K * 32, 0.0);
+  // Compact rows of rounds r >= 1: row u of round r holds, at slot k, the
+  // first twiddle of the round's stage k, psi^brv(2^(s_r + k) + (u << k));
+  // rows of consecutive rounds follow each other (the device's layout).
+  auto cmp_len_of = [](int rounds, int r0, int loge) {
+    int len = 0;
+    for (int r = 1; r < rounds; ++r) len += (1 << (r0 + (r - 1) * loge)) * 8;
+    return len;
+  };
+  const int cmp_len = cmp_len_of(c->rounds, c->r0, c->loge);
+  // N = 2^15: the two half-limb forward sub-transforms (2^14 points each,
+  // the shape of the 2^14 transform, the full transform's twiddles)
+  int h_loge = 0, h_r0 = 0, h_rounds = 0;
+  if (c->log2n == 15) h_rounds = ntt_rounds(14, &h_loge, &h_r0);
+  const int h_len = h_rounds ? 1 << h_loge : 0;
+  const int cmp_h_len = h_rounds ? cmp_len_of(h_rounds, h_r0, h_loge) : 0;
+  std::vector<double> tw_h((size_t)K * 2 * std::max(h_len, 1), 0.0), tw_h0(K, 0.0);
+  std::vector<double> tw_cf((size_t)K * std::max(cmp_len, 1), 0.0),
+      tw_ci((size_t)K * std::max(cmp_len, 1), 0.0),
+      tw_ch((size_t)K * 2 * std::max(cmp_h_len, 1), 0.0), tw_kf((size_t)K * 32, 0.0),
+      tw_ki((size_t)K * 32, 0.0);
   {
-    const int E = 1 << c->loge;
     std::vector<u64> pbr(n), pibr(n);
     for (int k = 0; k < K; ++k) {
       const u64 p = prime(k);
@@ -562,60 +552,49 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
         pbr[i] = pw[brv(i, c->log2n)];
         pibr[i] = pwi[brv(i, c->log2n)];
       }
+      // per-(stage, slot) constants omega_k^(+-brv_k(j)), omega_k = psi^(N/2^k)
       for (int kk = 1; kk < c->loge && kk < 5; ++kk) {
         const u64 om = powmod(psi, (u64)n >> kk, p), omi = invmod(om, p);
         for (int j = 1; j < (1 << kk); ++j) {
-          tw_cf[(size_t)k * 32 + (1 << kk) + j] = bal(powmod(om, (u64)brv(j, kk), p), p);
-          tw_ci[(size_t)k * 32 + (1 << kk) + j] = bal(powmod(omi, (u64)brv(j, kk), p), p);
+          tw_kf[(size_t)k * 32 + (1 << kk) + j] = bal(powmod(om, (u64)brv(j, kk), p), p);
+          tw_ki[(size_t)k * 32 + (1 << kk) + j] = bal(powmod(omi, (u64)brv(j, kk), p), p);
         }
       }
-      if (last_len)
-        for (int u = 0; u < (1 << last_ss); ++u)
-          for (int kk = 0; kk < c->loge; ++kk) {
-            const int idx = (1 << (last_ss + kk)) + (u << kk);
-            tw_lf[(size_t)k * last_len + (size_t)u * 8 + kk] = bal(pbr[idx], p);
-            tw_li[(size_t)k * last_len + (size_t)u * 8 + kk] = bal(pibr[idx], p);
-          }
-      if (last_h_len)
-        for (int hh = 0; hh < 2; ++hh)
-          for (int u = 0; u < (1 << last_h_ss); ++u)
-            for (int kk = 0; kk < h_loge; ++kk) {
-              const int idx = (1 << (last_h_ss + kk)) * (2 + hh) + (u << kk);
-              tw_lh[((size_t)k * 2 + hh) * last_h_len + (size_t)u * 8 + kk] = bal(pbr[idx], p);
+      // round 0 (uniform) and the compact rows of the full transform
+      for (int kk = 0; kk < c->r0; ++kk)
+        for (int j = 0; j < (1 << kk); ++j) {
+          tw_f[(size_t)k * c->tw_len + (1 << kk) + j] = bal(pbr[(1 << kk) + j], p);
+          tw_i[(size_t)k * c->tw_len + (1 << kk) + j] = bal(pibr[(1 << kk) + j], p);
+        }
+      {
+        size_t off = (size_t)k * cmp_len;
+        for (int r = 1; r < c->rounds; ++r) {
+          const int ss = c->r0 + (r - 1) * c->loge;
+          for (int u = 0; u < (1 << ss); ++u, off += 8)
+            for (int kk = 0; kk < c->loge; ++kk) {
+              const int idx = (1 << (ss + kk)) + (u << kk);
+              tw_cf[off + kk] = bal(pbr[idx], p);
+              tw_ci[off + kk] = bal(pibr[idx], p);
             }
-      if (h_len) {
+        }
+      }
+      // half-limb sub-transforms: sub-stage s' of half h is the full
+      // transform's stage s' + 1 over the indices with top bit h
+      if (h_rounds) {
         tw_h0[k] = bal(pbr[1], p);
-        const int E = 1 << h_loge;
         for (int hh = 0; hh < 2; ++hh) {
-          int off = 0;
-          for (int r = 0; r < h_rounds; ++r) {
-            const int ss = r == 0 ? 0 : h_r0 + (r - 1) * h_loge;
-            const int R = r == 0 ? h_r0 : h_loge;
-            for (int u = 0; u < (1 << ss); ++u)
-              for (int kk = 0; kk < R; ++kk)
-                for (int j = 0; j < (1 << kk); ++j) {
-                  const int idx = (1 << (ss + kk)) * (2 + hh) + (u << kk) + j;
-                  const size_t o = ((size_t)k * 2 + hh) * h_len + off + (size_t)u * E +
-                                   (1 << kk) + j;
-                  tw_h[o] = bal(pbr[idx], p);
-                }
-            off += (1 << ss) * E;
+          for (int kk = 0; kk < h_r0; ++kk)
+            for (int j = 0; j < (1 << kk); ++j)
+              tw_h[((size_t)k * 2 + hh) * h_len + (1 << kk) + j] =
+                  bal(pbr[(1 << kk) * (2 + hh) + j], p);
+          size_t off = ((size_t)k * 2 + hh) * cmp_h_len;
+          for (int r = 1; r < h_rounds; ++r) {
+            const int ss = h_r0 + (r - 1) * h_loge;
+            for (int u = 0; u < (1 << ss); ++u, off += 8)
+              for (int kk = 0; kk < h_loge; ++kk)
+                tw_ch[off + kk] = bal(pbr[(1 << (ss + kk)) * (2 + hh) + (u << kk)], p);
           }
         }
-      }
-      int off = 0;
-      for (int r = 0; r < c->rounds; ++r) {
-        const int ss = r == 0 ? 0 : c->r0 + (r - 1) * c->loge;
-        const int R = r == 0 ? c->r0 : c->loge;
-        for (int u = 0; u < (1 << ss); ++u)
-          for (int kk = 0; kk < R; ++kk)
-            for (int j = 0; j < (1 << kk); ++j) {
-              const int idx = (1 << (ss + kk)) + (u << kk) + j;
-              const size_t o = (size_t)k * c->tw_len + off + (size_t)u * E + (1 << kk) + j;
-              tw_f[o] = bal(pbr[idx], p);
-              tw_i[o] = bal(pibr[idx], p);
-            }
-        off += (1 << ss) * E;
       }
     }
   }
@@ -678,8 +657,8 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
       {&B_q, &c->tb.B_q},         {&P_inv_q, &c->tb.P_inv_q}, {&NP_inv_q, &c->tb.NP_inv_q},
       {&delta_q, &c->tb.delta_q},
       {&mrc_inv, &c->tb.mrc_inv}, {&mrc_half, &c->tb.mrc_half}, {&tw_h, &c->tb.tw_half},
-      {&tw_h0, &c->tb.tw_half0},  {&tw_lf, &c->tb.tw_last_f}, {&tw_li, &c->tb.tw_last_i},
-      {&tw_lh, &c->tb.tw_last_h}, {&tw_cf, &c->tb.tw_cst_f},  {&tw_ci, &c->tb.tw_cst_i}};
+      {&tw_h0, &c->tb.tw_half0},  {&tw_cf, &c->tb.tw_cmp_f},  {&tw_ci, &c->tb.tw_cmp_i},
+      {&tw_ch, &c->tb.tw_cmp_h},  {&tw_kf, &c->tb.tw_cst_f},  {&tw_ki, &c->tb.tw_cst_i}};
   size_t total = 0;
   std::vector<size_t> offs;
   for (auto& pp : parts) {
@@ -722,8 +701,8 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
   }
   c->tb.tw_len = c->tw_len;
   c->tb.tw_half_len = h_len;
-  c->tb.tw_last_len = last_len;
-  c->tb.tw_last_h_len = last_h_len;
+  c->tb.tw_cmp_len = cmp_len;
+  c->tb.tw_cmp_h_len = cmp_h_len;
   if (!h_len) {
     c->tb.tw_half = nullptr;
     c->tb.tw_half0 = nullptr;

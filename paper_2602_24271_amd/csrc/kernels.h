@@ -19,21 +19,20 @@ struct Tables {
   const double* pinv;        // [K] fl(1/p)
   const double* recip;       // [K] fl(1/p) (kept separate: the CRT estimate)
   const double* ninv;        // [K] balanced N^-1
-  const double* tw_fwd;      // [K][tw_len]
+  const double* tw_fwd;      // [K][tw_len] round-0 twiddles (slot 2^k + j)
   const double* tw_inv;      // [K][tw_len]
   int tw_len;
-  // N = 2^15 only: forward transform split over two half-limb workgroups
-  // last round of every transform: per index row u only the first twiddle
-  // of each stage (8 slots, stage k at slot k); the others are that one
-  // times a constant per (stage, slot) shared by all rows
-  const double* tw_last_f;   // [K][tw_last_len]
-  const double* tw_last_i;   // [K][tw_last_len]
-  int tw_last_len;
-  const double* tw_last_h;   // [K][2][tw_last_h_len] (half-limb forward)
-  int tw_last_h_len;
+  // rounds >= 1: per index row u the first twiddle of each stage (8 slots,
+  // stage k at slot k), rounds one after the other; the others are that
+  // one times a constant per (stage, slot) shared by all rows
+  const double* tw_cmp_f;    // [K][tw_cmp_len]
+  const double* tw_cmp_i;    // [K][tw_cmp_len]
+  int tw_cmp_len;
+  const double* tw_cmp_h;    // [K][2][tw_cmp_h_len] (half-limb forward)
+  int tw_cmp_h_len;
   const double* tw_cst_f;    // [K][32] slot 2^k + j: omega_k^brv_k(j)
   const double* tw_cst_i;    // [K][32] slot 2^k + j: omega_k^-brv_k(j)
-  const double* tw_half;     // [K][2][tw_half_len] sub-transform twiddles per half
+  const double* tw_half;     // [K][2][tw_half_len] round-0 twiddles of each half's sub-transform
   const double* tw_half0;    // [K] psi^(2^14), the stage-0 twiddle
   int tw_half_len;
   // centred lift Q -> B

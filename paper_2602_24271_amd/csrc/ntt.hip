@@ -26,9 +26,10 @@
 // round) are unit-stride across threads.  Only pointwise kernels and the
 // inverse transform read the NTT domain, and they do not care about order.
 //
-// Twiddles: per round a table [2^s_start][E] holding, for each value u of
-// the index bits above the round, the E-1 twiddles the round needs in the
-// order (stage k, j < 2^k) -> slot 2^k + j.  Values are balanced residues.
+// Twiddles: round 0 (the top index bits) uses the same E - 1 twiddles in
+// every thread, slot 2^k + j for stage k, j < 2^k; later rounds keep per
+// index row only each stage's first twiddle and derive the others (see
+// TwSrc).  Values are balanced residues.
 #include "kernels.h"
 
 namespace nshe {
@@ -61,6 +62,14 @@ struct NttShape {
     return off;
   }
   __host__ __device__ static constexpr int tw_len() { return tw_off(ROUNDS); }
+  // offset (doubles) of round r's rows in the compact table (rounds >= 1,
+  // 8 slots per row)
+  __host__ __device__ static constexpr int cmp_off(int r) {
+    int off = 0;
+    for (int i = 1; i < r; ++i) off += (1 << s_start(i)) * 8;
+    return off;
+  }
+  __host__ __device__ static constexpr int cmp_len() { return cmp_off(ROUNDS); }
 };
 
 __device__ __forceinline__ int pad32(int i) { return i + (i >> 5); }
@@ -230,177 +239,122 @@ constexpr bool fwd_schedule_ok(int pre) {
   return true;
 }
 
-// Twiddle w of stage k, slot j (1 <= 2^k + j < E) in round r.  Round 0's
-// twiddles are the same for every thread and come through the scalar
-// cache; later rounds' depend on the thread and use a buffer load whose
-// offset is made to depend (inline asm) on the previous stage's results,
-// so that no stage's loads are hoisted above it (which spills registers at
-// 1024 threads per workgroup).
-template <int LOGN>
-struct Twiddles {
-  using S = NttShape<LOGN>;
-  const double* __restrict__ t0;
-  __amdgpu_buffer_rsrc_t tr;
-  unsigned tvo;
-  __device__ __forceinline__ Twiddles(const double* __restrict__ tw, int r) {
-    t0 = tw;
-    tr = make_rsrc(tw, S::tw_len() * 8);
-    const int u = r == 0 ? 0 : (int)(threadIdx.x >> S::lo(r));
-    tvo = (S::tw_off(r) + u * S::E) * 8;
-  }
-  __device__ __forceinline__ unsigned stage_offset(const double& fence) const {
-    unsigned o = tvo;
-    asm volatile("" : "+v"(o) : "v"(fence));
-    return o;
-  }
-};
-
-// Round r of the forward transform on this thread's registers.  Later
-// rounds fetch one stage ahead: stage k+1's twiddles are issued at the start
-// of stage k (fenced on stage k-1's results, so no further), hiding the
-// load latency behind one stage of butterflies.
-// Twiddle sources of a transform: the per-round tables, and for the last
-// round the compact table (first twiddle of each stage per index row) with
-// the per-(stage, slot) constants: W(k, j) = W(k, 0) omega_k^(+-brv_k(j)),
-// since the bits of j, of the row and of the stage are disjoint in the
-// bit-reversed exponent.
+// Twiddle sources of a transform.  Round 0's twiddles are the same for
+// every thread (slot 2^k + j of a [E] row, through the scalar cache).  In a
+// later round the twiddle of stage k, slot j for index row u is
+// W(k, j) = W(k, 0) omega_k^(+-brv_k(j)) (the bits of j, of u and of the
+// stage are disjoint in the bit-reversed exponent): the compact table keeps
+// W(k, 0) per row (8 slots, stage k at slot k; rounds r >= 1 one after the
+// other) and cst the per-(stage, slot) constants shared by all rows, so a
+// thread loads 5 twiddles per round instead of 31 and derives the rest
+// with one modular product each.
 struct TwSrc {
-  const double* tw;
-  const double* last;
-  const double* cst;
+  const double* tw0;   // round 0 row
+  const double* cmp;   // compact rows of rounds >= 1
+  const double* cst;   // [32] slot 2^k + j: omega_k^(+-brv_k(j))
 };
 
-// The last round (r > 0, LOGE stages) with compact twiddles: 5 loads per
-// thread instead of 31, the other twiddles one product each.
+// Rounds r >= 1 (LOGE stages each) with compact twiddles.  A stage's base
+// twiddle is loaded one stage ahead, fenced on the previous stage's inputs
+// so that the loads are not all hoisted to the top (register pressure).
+// Forward (FWD): Cooley-Tukey stages k = 0..LOGE-1.  Inverse: Gentleman-
+// Sande stages k = LOGE-1..0, the sum reduced on odd global stages (g0 =
+// stages done before this round).
 template <int LOGN, bool FWD>
-__device__ __forceinline__ void last_round(double (&x)[NttShape<LOGN>::E], int r, const TwSrc& t,
-                                           double p, double pinv) {
+__device__ __forceinline__ void compact_round(double (&x)[NttShape<LOGN>::E], int r, int g0,
+                                              const TwSrc& t, double p, double pinv) {
   using S = NttShape<LOGN>;
-  const auto rl = make_rsrc(t.last, (1 << S::s_start(r)) * 64);
+  const auto rl = make_rsrc(t.cmp + S::cmp_off(r), (1 << S::s_start(r)) * 64);
   const unsigned lo = (threadIdx.x >> S::lo(r)) * 64;
-  double wb[S::LOGE];
-#pragma unroll
-  for (int k = 0; k < S::LOGE; ++k) wb[k] = buf_load(rl, lo, k * 8);
+  double wcur = buf_load(rl, lo, (FWD ? 0 : S::LOGE - 1) * 8), wnxt = 0.0;
 #pragma unroll
   for (int kk = 0; kk < S::LOGE; ++kk) {
     const int k = FWD ? kk : S::LOGE - 1 - kk;
     const int eb = S::LOGE - 1 - k;
+    if (kk + 1 < S::LOGE) {
+      unsigned o = lo;
+      asm volatile("" : "+v"(o) : "v"(x[0]));
+      wnxt = buf_load(rl, o, (FWD ? k + 1 : k - 1) * 8);
+    }
+    const double wk = wcur;
 #pragma unroll
     for (int j = 0; j < (1 << k); ++j) {
-      const double w = j == 0 ? wb[k] : mul_bal(wb[k], cld(t.cst, (1 << k) + j), p, pinv);
+      const double w = j == 0 ? wk : mul_bal(wk, cld(t.cst, (1 << k) + j), p, pinv);
 #pragma unroll
       for (int b = 0; b < (1 << eb); ++b) {
         const int e = (j << (eb + 1)) | b;
         if constexpr (FWD) {
           ct_bfly(x[e], x[e | (1 << eb)], w, p, pinv);
         } else {
-          if (kk & 1)
+          if ((g0 + kk) & 1)
             gs_bfly<true>(x[e], x[e | (1 << eb)], w, p, pinv);
           else
             gs_bfly<false>(x[e], x[e | (1 << eb)], w, p, pinv);
         }
       }
     }
+    wcur = wnxt;
   }
 }
 
+// Round r of the forward transform on this thread's registers.
 template <int LOGN>
 __device__ __forceinline__ void fwd_round(double (&x)[NttShape<LOGN>::E], int r, bool reduce,
                                           const TwSrc& ts, double p, double pinv) {
   using S = NttShape<LOGN>;
-  constexpr int HALF = S::E / 2;
-  if (r > 0 && r == S::ROUNDS - 1) {
-    last_round<LOGN, true>(x, r, ts, p, pinv);
-    if (reduce) {
+  if (r > 0) {
+    compact_round<LOGN, true>(x, r, 0, ts, p, pinv);
+  } else {
 #pragma unroll
-      for (int e = 0; e < S::E; ++e) x[e] = reduce_bal(x[e], p, pinv);
-    }
-    return;
-  }
-  const double* __restrict__ tw = ts.tw;
-  const Twiddles<LOGN> T(tw, r);
-  const int R = S::stages(r);
-  double cur[HALF], nxt[HALF];
-  if (r > 0) cur[0] = buf_load(T.tr, T.tvo, 8);
+    for (int k = 0; k < S::R0; ++k) {
+      const int eb = S::LOGE - 1 - k;
 #pragma unroll
-  for (int k = 0; k < S::LOGE; ++k) {
-    if (k >= R) break;
-    const int eb = S::LOGE - 1 - k;
-    if (r > 0 && k + 1 < R) {
-      const unsigned o = T.stage_offset(x[0]);
+      for (int j = 0; j < (1 << k); ++j) {
+        const double w = cld(ts.tw0, (1 << k) + j);
 #pragma unroll
-      for (int j = 0; j < (2 << k); ++j) nxt[j] = buf_load(T.tr, o, ((2 << k) + j) * 8);
-    }
-#pragma unroll
-    for (int j = 0; j < (1 << k); ++j) {
-      const double w = r == 0 ? cld(T.t0, S::tw_off(0) + (1 << k) + j) : cur[j];
-#pragma unroll
-      for (int b = 0; b < (1 << eb); ++b) {
-        const int e = (j << (eb + 1)) | b;
-        ct_bfly(x[e], x[e | (1 << eb)], w, p, pinv);
+        for (int b = 0; b < (1 << eb); ++b) {
+          const int e = (j << (eb + 1)) | b;
+          ct_bfly(x[e], x[e | (1 << eb)], w, p, pinv);
+        }
       }
     }
-    if (r > 0 && k + 1 < R) {
-#pragma unroll
-      for (int j = 0; j < (2 << k); ++j) cur[j] = nxt[j];
-    }
   }
-if (reduce) {
+  if (reduce) {
 #pragma unroll
     for (int e = 0; e < S::E; ++e) x[e] = reduce_bal(x[e], p, pinv);
   }
 }
 
+// Round r of the inverse; g0 = stages done before it (the reduction
+// alternation runs over the global stage count).  Round 0 is the last one
+// processed and reduces every value at its end.
 template <int LOGN>
 __device__ __forceinline__ void inv_round(double (&x)[NttShape<LOGN>::E], int r, int g0,
                                           const TwSrc& ts, double p, double pinv) {
   using S = NttShape<LOGN>;
-  constexpr int HALF = S::E / 2;
-  if (r > 0 && r == S::ROUNDS - 1) {
-    // processed first: g0 = 0, so the sums of odd local stages are reduced,
-    // as in the general path
-    last_round<LOGN, false>(x, r, ts, p, pinv);
+  if (r > 0) {
+    compact_round<LOGN, false>(x, r, g0, ts, p, pinv);
     return;
   }
-  const double* __restrict__ tw = ts.tw;
-  const Twiddles<LOGN> T(tw, r);
-  const int R = S::stages(r);
-  double cur[HALF], nxt[HALF];
-  if (r > 0) {
 #pragma unroll
-    for (int j = 0; j < (1 << (R - 1)); ++j) cur[j] = buf_load(T.tr, T.tvo, ((1 << (R - 1)) + j) * 8);
-  }
-#pragma unroll
-  for (int kk = 0; kk < S::LOGE; ++kk) {
+  for (int kk = S::LOGE - S::R0; kk < S::LOGE; ++kk) {
     const int k = S::LOGE - 1 - kk;
-    if (k >= R) continue;
     const int eb = S::LOGE - 1 - k;
-    if (r > 0 && k > 0) {
-      const unsigned o = T.stage_offset(x[0]);
-#pragma unroll
-      for (int j = 0; j < (1 << (k - 1)); ++j) nxt[j] = buf_load(T.tr, o, ((1 << (k - 1)) + j) * 8);
-    }
 #pragma unroll
     for (int j = 0; j < (1 << k); ++j) {
-      const double w = r == 0 ? cld(T.t0, S::tw_off(0) + (1 << k) + j) : cur[j];
+      const double w = cld(ts.tw0, (1 << k) + j);
 #pragma unroll
       for (int b = 0; b < (1 << eb); ++b) {
         const int e = (j << (eb + 1)) | b;
-        if ((g0 + kk - (S::LOGE - R)) & 1)
+        if ((g0 + kk - (S::LOGE - S::R0)) & 1)
           gs_bfly<true>(x[e], x[e | (1 << eb)], w, p, pinv);
         else
           gs_bfly<false>(x[e], x[e | (1 << eb)], w, p, pinv);
       }
     }
-    if (r > 0 && k > 0) {
-#pragma unroll
-      for (int j = 0; j < (1 << (k - 1)); ++j) cur[j] = nxt[j];
-    }
   }
-if (r == 0) {
 #pragma unroll
-    for (int e = 0; e < S::E; ++e) x[e] = reduce_bal(x[e], p, pinv);
-  }
+  for (int e = 0; e < S::E; ++e) x[e] = reduce_bal(x[e], p, pinv);
 }
 
 // Work item of an NTT launch: item = limb * npoly + poly (limb-major, so
@@ -444,7 +398,7 @@ k_ntt_fwd(NttJob job, Tables tb) {
   const int prime = cldi(job.limb_prime, limb);
   const double p = cld(tb.p, prime), pinv = cld(tb.pinv, prime);
   const TwSrc tw{tb.tw_fwd + (size_t)prime * tb.tw_len,
-                 tb.tw_last_f + (size_t)prime * tb.tw_last_len, tb.tw_cst_f + (size_t)prime * 32};
+                 tb.tw_cmp_f + (size_t)prime * tb.tw_cmp_len, tb.tw_cst_f + (size_t)prime * 32};
   const size_t off = (size_t)poly * job.poly_stride + (size_t)limb * S::N;
   double* dst = job.base + off;
   const auto rd = make_rsrc(dst, S::N * 8);
@@ -495,7 +449,7 @@ k_ntt_inv(NttJob job, Tables tb) {
   const int prime = cldi(job.limb_prime, limb);
   const double p = cld(tb.p, prime), pinv = cld(tb.pinv, prime);
   const TwSrc tw{tb.tw_inv + (size_t)prime * tb.tw_len,
-                 tb.tw_last_i + (size_t)prime * tb.tw_last_len, tb.tw_cst_i + (size_t)prime * 32};
+                 tb.tw_cmp_i + (size_t)prime * tb.tw_cmp_len, tb.tw_cst_i + (size_t)prime * 32};
   const size_t off = (size_t)poly * job.poly_stride + (size_t)limb * S::N;
   double* dst = job.base + off;
   const auto rd = make_rsrc(dst, S::N * 8);
@@ -625,7 +579,7 @@ k_ntt_fwd_half(NttJob job, Tables tb) {
   const double p = cld(tb.p, prime), pinv = cld(tb.pinv, prime);
   const double w0 = cld(tb.tw_half0, prime);
   const TwSrc tw{tb.tw_half + ((size_t)prime * 2 + h) * tb.tw_half_len,
-                 tb.tw_last_h + ((size_t)prime * 2 + h) * tb.tw_last_h_len,
+                 tb.tw_cmp_h + ((size_t)prime * 2 + h) * tb.tw_cmp_h_len,
                  tb.tw_cst_f + (size_t)prime * 32};
   // Both halves read the whole input limb, so the output must be another
   // buffer (the host never launches this kernel in place).
