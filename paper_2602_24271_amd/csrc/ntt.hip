@@ -176,15 +176,16 @@ __device__ __forceinline__ void exchange(double (&x)[NttShape<LOGN>::E], int r0,
   }
 }
 
-// Cooley-Tukey butterfly without reducing X.  With |W| < p/2 and p < 2^49
+// Cooley-Tukey butterfly without reducing X.  With |W| <= 0.55 p (a
+// balanced table twiddle, or one derived by a lazy product) and p < 2^49
 // the product T = [Y W] has |T| <= (1/2 + d) p, where the quotient error
-// d <= |Y W / p| 3 2^-53 <= 0.094 |Y| / p, so a stage maps a bound b p on
-// the inputs to (1.094 b + 0.5) p.  From inputs below 2p (a canonical
-// digit of another prime of the chain) ten stages stay below 12.6 p, so
+// d <= |Y W / p| 3 2^-53 <= 0.103 |Y| / p, so a stage maps a bound b p on
+// the inputs to (1.103 b + 0.5) p.  From inputs below 2p (a canonical
+// digit of another prime of the chain) ten stages stay below 13.5 p, so
 // every intermediate is an integer below 2^53 and every product is exact
 // (its quotient below 2^53, h - q p and the final sum exactly
 // representable).  A reduction every ten stages therefore suffices; see
-// fwd_reduces_after.
+// fwd_reduces_after.  Five stages from a reduced input end below 3.9 p.
 __device__ __forceinline__ void ct_bfly(double& X, double& Y, double W, double p, double pinv) {
   double t = mul_lazy(Y, W, p, pinv);
   double x = X;
@@ -195,11 +196,11 @@ __device__ __forceinline__ void ct_bfly(double& X, double& Y, double W, double p
 // Gentleman-Sande butterfly; the sum is reduced on alternate stages only
 // (REDUCE_SUM), the difference feeds the modular product directly.  From
 // balanced inputs the bound before a non-reducing stage settles below
-// 0.8 p (a reduced sum is 0.5 p, a product of a difference below 2 b p is
-// (0.5 + 0.188 b) p), so sums stay below 1.6 p and differences below 3.2 p,
-// well inside mul_lazy's range, whatever the round boundaries; the
-// alternation runs over the global stage count and only the last round
-// reduces every value.
+// 0.85 p (a reduced sum is 0.5 p, a product of a difference below 2 b p
+// with |W| <= 0.55 p is (0.5 + 0.206 b) p), so sums stay below 1.7 p and
+// differences below 3.4 p, well inside mul_lazy's range, whatever the
+// round boundaries; the alternation runs over the global stage count and
+// only the last round reduces every value.
 template <bool REDUCE_SUM>
 __device__ __forceinline__ void gs_bfly(double& X, double& Y, double W, double p, double pinv) {
   double s = X + Y;
@@ -279,7 +280,8 @@ __device__ __forceinline__ void compact_round(double (&x)[NttShape<LOGN>::E], in
     const double wk = wcur;
 #pragma unroll
     for (int j = 0; j < (1 << k); ++j) {
-      const double w = j == 0 ? wk : mul_bal(wk, cld(t.cst, (1 << k) + j), p, pinv);
+      // a lazy product: |w| <= 0.55 p (see ct_bfly)
+      const double w = j == 0 ? wk : mul_lazy(wk, cld(t.cst, (1 << k) + j), p, pinv);
 #pragma unroll
       for (int b = 0; b < (1 << eb); ++b) {
         const int e = (j << (eb + 1)) | b;
@@ -431,7 +433,9 @@ k_ntt_fwd(NttJob job, Tables tb) {
 #pragma unroll
   for (int r = 0; r < S::ROUNDS; ++r) {
     if (r > 0) exchange<LOGN>(x, r - 1, r, lds);
-    fwd_round<LOGN>(x, r, fwd_reduces_after<LOGN>(r, 0), tw, p, pinv);
+    fwd_round<LOGN>(x, r,
+                    fwd_reduces_after<LOGN>(r, 0) && !(MODE == NTT_DIGIT && r == S::ROUNDS - 1),
+                    tw, p, pinv);
   }
 #pragma unroll
   for (int e = 0; e < S::E; ++e) buf_store(x[e], ro, vo, e * S::T * 8);
@@ -631,7 +635,10 @@ k_ntt_fwd_half(NttJob job, Tables tb) {
 #pragma unroll
   for (int r = 0; r < S::ROUNDS; ++r) {
     if (r > 0) exchange<14>(x, r - 1, r, lds);
-    fwd_round<14>(x, r, fwd_reduces_after<14>(r, 1), tw, p, pinv);
+    // digit transforms skip the final reduction (outputs below 3.9 p):
+    // their only reader, the key-switch product, reduces its sums itself
+    fwd_round<14>(x, r, fwd_reduces_after<14>(r, 1) && !(MODE == NTT_DIGIT && r == S::ROUNDS - 1),
+                  tw, p, pinv);
   }
   const unsigned so = (h * S::T + tid) * 8;
 #pragma unroll
