@@ -581,7 +581,8 @@ k_ntt_fwd_half(NttJob job, Tables tb) {
   }
   const int prime = cldi(job.limb_prime, limb);
   const double p = cld(tb.p, prime), pinv = cld(tb.pinv, prime);
-  const double w0 = cld(tb.tw_half0, prime);
+  // half 1 takes X - W Y = X + (-W) Y: one uniform sign flip of the twiddle
+  const double w0 = h ? -cld(tb.tw_half0, prime) : cld(tb.tw_half0, prime);
   const TwSrc tw{tb.tw_half + ((size_t)prime * 2 + h) * tb.tw_half_len,
                  tb.tw_cmp_h + ((size_t)prime * 2 + h) * tb.tw_cmp_h_len,
                  tb.tw_cst_f + (size_t)prime * 32};
@@ -627,8 +628,7 @@ k_ntt_fwd_half(NttJob job, Tables tb) {
 #pragma unroll
       for (int i = 0; i < G; ++i) {
         const double X = bx[slot][i], Y = by[slot][i];
-        const double T = mul_lazy(Y, w0, p, pinv);
-        x[g + i] = h ? X - T : X + T;
+        x[g + i] = X + mul_lazy(Y, w0, p, pinv);
       }
     }
   }
