@@ -88,6 +88,17 @@ typedef const __attribute__((address_space(4))) double* const_dptr;
 typedef const __attribute__((address_space(4))) int* const_iptr;
 
 __device__ __forceinline__ double cld(const double* p, int i) { return ((const_dptr)p)[i]; }
+
+// A row of a uniform table whose address the compiler cannot see through
+// (inline asm on the scalar register), so that its scalar loads are not
+// hoisted into earlier loop iterations: a base-conversion loop over 18
+// rows of 17 constants would otherwise keep hundreds of constants live in
+// SGPRs and spill them into VGPR lanes.
+__device__ __forceinline__ const double* opaque_row(const double* p, int off) {
+  const double* r = p + off;
+  asm volatile("" : "+s"(r));
+  return r;
+}
 __device__ __forceinline__ int cldi(const int* p, int i) { return ((const_iptr)p)[i]; }
 
 }  // namespace nshe

@@ -29,28 +29,49 @@ constexpr double LIFT_EPS = 0x1p-40;
 // Garner mixed-radix digits of X (canonical residues r, basis q_0..q_{L-1})
 // compared with those of (Q-1)/2: returns X > (Q-1)/2.
 // (Arguments by value: taking the address of the kernel's Tables argument
-// would copy it to scratch memory in every thread.)
+// would copy it to scratch memory in every thread.  A rare fallback: its
+// loops stay rolled and its digits in private memory, so that it does not
+// raise the register count - and lower the occupancy - of its callers.)
 template <int L>
 __device__ __noinline__ bool mrc_greater_than_half(const double* r, const double* __restrict__ P,
                                                    const double* __restrict__ Pinv,
                                                    const double* __restrict__ inv,
                                                    const double* __restrict__ half) {
   double a[L];
-#pragma unroll
+#pragma unroll 1
   for (int i = 0; i < L; ++i) {
     const double p = P[i], pinv = Pinv[i];
     double t = r[i];
+#pragma unroll 1
     for (int j = 0; j < i; ++j) {
       t = mul_bal(t - a[j], inv[j * L + i], p, pinv);
       t = to_canonical(t, p);
     }
     a[i] = t;
   }
+#pragma unroll 1
   for (int i = L - 1; i >= 0; --i) {
     const double h = half[i];
     if (a[i] != h) return a[i] > h;
   }
   return false;
+}
+
+// Per-poly block mapping of the per-coefficient kernels: block b covers
+// coefficients [(b mod bpp) blockDim, ...) of poly b / bpp, so the poly and
+// its base address are uniform (scalar registers): limb accesses are buffer
+// loads with one per-lane offset and a scalar limb offset.
+struct PolyBlock {
+  size_t pc;
+  int c;
+  bool ok;
+};
+
+__device__ __forceinline__ PolyBlock poly_block(int n, size_t n_poly) {
+  const int bpp = (n + (int)blockDim.x - 1) / (int)blockDim.x;
+  const size_t pc = blockIdx.x / (unsigned)bpp;
+  const int c = (int)(blockIdx.x - pc * bpp) * (int)blockDim.x + (int)threadIdx.x;
+  return PolyBlock{pc, c, pc < n_poly && c < n};
 }
 
 // ------------------------------------------------------------------ lift ---
@@ -60,33 +81,34 @@ __device__ __noinline__ bool mrc_greater_than_half(const double* r, const double
 template <int L>
 __global__ void __launch_bounds__(256) k_lift(int n, size_t n_poly, double* ext, Tables tb) {
   constexpr int LB = L + 1;
-  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= n_poly * (size_t)n) return;
-  const size_t pc = gid / n;
-  const int c = (int)(gid - pc * n);
-  double* base = ext + pc * (size_t)(L + LB) * n + c;
+  const PolyBlock pb = poly_block(n, n_poly);
+  if (!pb.ok) return;
+  const auto rs = make_rsrc(ext + pb.pc * (size_t)(L + LB) * n, (unsigned)((L + LB) * n * 8));
+  const unsigned vo = (unsigned)pb.c * 8;
+  const unsigned ls = (unsigned)n * 8;   // bytes per limb
   double y[L];
   double S = 0.0;
 #pragma unroll
   for (int i = 0; i < L; ++i) {
-    y[i] = mul_bal(base[(size_t)i * n], cld(tb.q_hat_inv, i), cld(tb.p, i), cld(tb.pinv, i));
+    y[i] = mul_bal(buf_load(rs, vo, i * ls), cld(tb.q_hat_inv, i), cld(tb.p, i), cld(tb.pinv, i));
     S += y[i] * cld(tb.recip, i);
   }
   double v = __builtin_rint(S);
   if (__builtin_fabs(S - v) > 0.5 - LIFT_EPS) {
     double r[L];
 #pragma unroll
-    for (int i = 0; i < L; ++i) r[i] = to_canonical(base[(size_t)i * n], cld(tb.p, i));
+    for (int i = 0; i < L; ++i) r[i] = to_canonical(buf_load(rs, vo, i * ls), cld(tb.p, i));
     v = __builtin_floor(S) + (mrc_greater_than_half<L>(r, tb.p, tb.pinv, tb.mrc_inv, tb.mrc_half) ? 1.0 : 0.0);
     atomicAdd(tb.margin, 1ull);
   }
 #pragma unroll
   for (int k = 0; k < LB; ++k) {
     const double b = cld(tb.p, L + k), binv = cld(tb.pinv, L + k);
+    const double* qb = opaque_row(tb.q_hat_b, k * L);
     double acc = -v * cld(tb.Q_b, k);
 #pragma unroll
-    for (int i = 0; i < L; ++i) acc += mul_lazy(y[i], cld(tb.q_hat_b, k * L + i), b, binv);
-    base[(size_t)(L + k) * n] = reduce_bal(acc, b, binv);
+    for (int i = 0; i < L; ++i) acc += mul_lazy(y[i], cld(qb, i), b, binv);
+    buf_store(reduce_bal(acc, b, binv), rs, vo, (L + k) * ls);
   }
 }
 
@@ -97,17 +119,17 @@ __global__ void __launch_bounds__(256) k_lift(int n, size_t n_poly, double* ext,
 template <int L>
 __global__ void __launch_bounds__(256) k_scale(int n, size_t n_poly, double* dt, Tables tb) {
   constexpr int LB = L + 1;
-  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= n_poly * (size_t)n) return;
-  const size_t pc = gid / n;
-  const int c = (int)(gid - pc * n);
-  double* base = dt + pc * (size_t)(L + LB) * n + c;
-  const bool third = pc % 3 == 2;
+  const PolyBlock pb = poly_block(n, n_poly);
+  if (!pb.ok) return;
+  const auto rs = make_rsrc(dt + pb.pc * (size_t)(L + LB) * n, (unsigned)((L + LB) * n * 8));
+  const unsigned vo = (unsigned)pb.c * 8;
+  const unsigned ls = (unsigned)n * 8;   // bytes per limb
+  const bool third = pb.pc % 3 == 2;
   double y[L];
   double S = 0.0;
 #pragma unroll
   for (int i = 0; i < L; ++i) {
-    y[i] = mul_bal(base[(size_t)i * n], cld(tb.t_qhinv, i), cld(tb.p, i), cld(tb.pinv, i));
+    y[i] = mul_bal(buf_load(rs, vo, i * ls), cld(tb.t_qhinv, i), cld(tb.p, i), cld(tb.pinv, i));
     S += y[i] * cld(tb.recip, i);
   }
   double v = __builtin_rint(S);
@@ -115,7 +137,7 @@ __global__ void __launch_bounds__(256) k_scale(int n, size_t n_poly, double* dt,
     double r[L];
 #pragma unroll
     for (int i = 0; i < L; ++i)
-      r[i] = to_canonical(mul_bal(base[(size_t)i * n], cld(tb.t_q, i), cld(tb.p, i), cld(tb.pinv, i)), cld(tb.p, i));
+      r[i] = to_canonical(mul_bal(buf_load(rs, vo, i * ls), cld(tb.t_q, i), cld(tb.p, i), cld(tb.pinv, i)), cld(tb.p, i));
     v = __builtin_floor(S) + (mrc_greater_than_half<L>(r, tb.p, tb.pinv, tb.mrc_inv, tb.mrc_half) ? 1.0 : 0.0);
     atomicAdd(tb.margin, 1ull);
   }
@@ -124,9 +146,10 @@ __global__ void __launch_bounds__(256) k_scale(int n, size_t n_poly, double* dt,
 #pragma unroll
   for (int k = 0; k < LB; ++k) {
     const double b = cld(tb.p, L + k), binv = cld(tb.pinv, L + k);
-    double acc = mul_lazy(base[(size_t)(L + k) * n], cld(tb.c1, k), b, binv) + v * cld(tb.b_hat_inv, k);
+    const double* c2k = opaque_row(tb.c2, k * L);
+    double acc = mul_lazy(buf_load(rs, vo, (L + k) * ls), cld(tb.c1, k), b, binv) + v * cld(tb.b_hat_inv, k);
 #pragma unroll
-    for (int i = 0; i < L; ++i) acc -= mul_lazy(y[i], cld(tb.c2, k * L + i), b, binv);
+    for (int i = 0; i < L; ++i) acc -= mul_lazy(y[i], cld(c2k, i), b, binv);
     w[k] = reduce_bal(acc, b, binv);
     S2 += w[k] * cld(tb.recip, L + k);
   }
@@ -135,13 +158,14 @@ __global__ void __launch_bounds__(256) k_scale(int n, size_t n_poly, double* dt,
 #pragma unroll
   for (int i = 0; i < L; ++i) {
     const double q = cld(tb.p, i), qinv = cld(tb.pinv, i);
+    const double* bq = opaque_row(tb.b_hat_q, i * LB);
     double acc = -v2 * cld(tb.B_q, i);
 #pragma unroll
-    for (int k = 0; k < LB; ++k) acc += mul_lazy(w[k], cld(tb.b_hat_q, i * LB + k), q, qinv);
+    for (int k = 0; k < LB; ++k) acc += mul_lazy(w[k], cld(bq, k), q, qinv);
     const double r = reduce_bal(acc, q, qinv);
     // the third component is only read as relinearization digits, which
     // are its canonical residues
-    base[(size_t)i * n] = third ? to_canonical(r, q) : r;
+    buf_store(third ? to_canonical(r, q) : r, rs, vo, i * ls);
   }
 }
 
@@ -564,6 +588,11 @@ __global__ void __launch_bounds__(256) k_ntt_order(size_t total, int log2n, int 
 
 // ---------------------------------------------------------------- host ---
 
+// grid of the per-poly block mapping (see poly_block)
+static inline dim3 poly_grid(size_t n_poly, int n, int block) {
+  return dim3((unsigned)(n_poly * (size_t)((n + block - 1) / block)));
+}
+
 static inline dim3 grid_for(size_t total, int block = 256) {
   return dim3((unsigned)((total + block - 1) / block));
 }
@@ -574,7 +603,7 @@ hipError_t run_lift(const Dims& d, double* ext, const Tables& tb, hipStream_t st
   const size_t np = (size_t)d.n_ct * 2;
   switch (d.L) {
 #define C_(L_) \
-  case L_: hipLaunchKernelGGL(k_lift<L_>, grid_for(np * d.n, d.block), dim3(d.block), 0, st, d.n, np, ext, tb); break;
+  case L_: hipLaunchKernelGGL(k_lift<L_>, poly_grid(np, d.n, d.block), dim3(d.block), 0, st, d.n, np, ext, tb); break;
     NSHE_L_CASES(C_)
 #undef C_
     default: return hipErrorInvalidValue;
@@ -590,7 +619,7 @@ hipError_t run_scale(const Dims& d, double* dt, const Tables& tb, hipStream_t st
   const size_t np = (size_t)d.n_ct * 3;
   switch (d.L) {
 #define C_(L_) \
-  case L_: hipLaunchKernelGGL(k_scale<L_>, grid_for(np * d.n, d.block), dim3(d.block), 0, st, d.n, np, dt, tb); break;
+  case L_: hipLaunchKernelGGL(k_scale<L_>, poly_grid(np, d.n, d.block), dim3(d.block), 0, st, d.n, np, dt, tb); break;
     NSHE_L_CASES(C_)
 #undef C_
     default: return hipErrorInvalidValue;
