@@ -55,13 +55,6 @@ struct NttShape {
     return r == 0 ? LOGN - LOGE : LOGN - s_start(r) - LOGE;
   }
   __host__ __device__ static constexpr int stages(int r) { return r == 0 ? R0 : LOGE; }
-  // offset of round r's twiddle table (in doubles)
-  __host__ __device__ static constexpr int tw_off(int r) {
-    int off = 0;
-    for (int i = 0; i < r; ++i) off += (1 << s_start(i)) * E;
-    return off;
-  }
-  __host__ __device__ static constexpr int tw_len() { return tw_off(ROUNDS); }
   // offset (doubles) of round r's rows in the compact table (rounds >= 1,
   // 8 slots per row)
   __host__ __device__ static constexpr int cmp_off(int r) {
@@ -548,8 +541,8 @@ k_ntt_inv(NttJob job, Tables tb) {
 // of stage 0 (X + W Y or X - W Y, W = psi^(2^14)) and runs stages 1..14 as
 // a 2^14-point transform whose twiddles are the full transform's for that
 // half: psi_br[2^s' (2 + h) + m'] at sub-stage s', block m'.  Half a limb
-// needs 68 KB of LDS and 128 VGPRs per thread, so two workgroups share a CU
-// and one loads or stores while the other computes.  Outputs land at the
+// needs 68 KB of LDS and at most 128 VGPRs per thread, so two workgroups
+// share a CU and one loads or stores while the other computes.  Outputs land at the
 // full transform's positions: standard index h 2^14 + i' at
 // (i' mod 32) 1024 + h 512 + i' / 32.
 template <int MODE>
