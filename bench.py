@@ -310,9 +310,10 @@ def summarize_profiles(prof_dir: str, out_dir: str) -> None:
         json.dump({"kernel_hash": kernel_hash(), "bytes_per_launch": traffic,
                    "calibration": {"copy_mib": mib, "factors": factors}}, fh, indent=1)
     cmd_trace = ("rocprofv3 --kernel-trace --stats -d gpurun_out/prof/trace -o eq --output-format csv "
-                 "-- python3 bench.py --steps 3 --warmup 1 --skip-batched --skip-cpu")
+                 "-- python3 bench.py --steps 3 --warmup 1 --skip-batched --skip-cpu --skip-next")
     cmd_pmc = ("rocprofv3 --pmc {C} -d gpurun_out/prof/{d} -o eq --output-format csv -- python3 "
-               "bench.py --steps 1 --warmup 0 --skip-batched --skip-cpu --calibrate-copy-mib 256")
+               "bench.py --steps 1 --warmup 0 --skip-batched --skip-cpu --skip-next "
+               "--calibrate-copy-mib 256")
     with open(os.path.join(out_dir, "eq_mask_2p20_rows_kernels.md"), "w") as fh:
         fh.write("# EQ mask, 2^20 rows (32 ciphertexts, N=32768), per-kernel time\n\n")
         fh.write(f"Kernel sources hash: {kernel_hash()}\n\nCommand (from the repo root, "

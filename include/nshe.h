@@ -315,7 +315,7 @@ int nshe_sum_slots(nshe_ctx* ctx, const int64_t* in_dev, int64_t* out_dev, int n
  *                  (base lift, scale-and-round, mod-down): 64, 128 or 256;
  *   wave_ct        ciphertexts per wave of nshe_eq_mask_batched when its
  *                  wave_ct argument is 0 (0: as many as the workspace holds).
- * A new context starts at {16, 1, 256, 0}.  nshe_set_tuning validates the
+ * A new context starts at {32, 1, 128, 0}.  nshe_set_tuning validates the
  * values (NSHE_EINVAL otherwise) and drops the batched call's cached graphs.
  *
  * nshe_autotune measures, on the caller's sample ciphertexts (int64

@@ -187,7 +187,7 @@ struct nshe_ctx {
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
   hipStream_t cap_stream = nullptr;  // capture-only stream (the null stream cannot capture)
-  nshe_tuning tune{16, 1, 256, 0};
+  nshe_tuning tune{32, 1, 128, 0};   // the autotuner's choice at 32 ciphertexts, N = 2^15
   std::map<uint32_t, double*> galois;  // Galois element -> switching key (NTT domain)
   // comparison polynomial (t = 2^K + 1 prime; lt_K = 0 otherwise): k babies,
   // m giants, coefficient matrix [m][k] (centred ints) on the device
