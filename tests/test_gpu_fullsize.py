@@ -1,12 +1,14 @@
 """Full paper size (N = 32768, 17 + 1 primes of ~49 bits, p = 65537):
-sampled NTT outputs, one squaring bit-exact against the oracle, and the
-whole 16-squaring mask decrypting to [x == y] with budget to spare."""
+sampled NTT outputs, one squaring bit-exact against the oracle (also under
+a second launch shape), the whole 16-squaring mask decrypting to [x == y]
+with budget to spare, the benchmark's 32-ciphertext configuration, and LT
+decrypting to [x < y]."""
 import numpy as np
 import pytest
 import torch
 
 import synth
-from oracle import bfv, encoding, ntt_def
+from oracle import bfv, encoding, ntt_def, ring
 from tests.gpu_common import Setup
 
 pytestmark = pytest.mark.gpu
@@ -70,3 +72,35 @@ def test_full_size_lt_decrypts(s32k):
     budget = bfv.noise_bits(S.pr, S.sk, got, encoding.encode(want, S.pr.t))
     print(f"LT budget left at N=32768: {budget:.1f} bits")
     assert budget > 0
+
+
+def test_full_size_bench_configuration(s32k):
+    """The benchmark's launch configuration: 32 ciphertexts (2^20 rows) in
+    one call.  Distinct ciphertexts x_k = Enc(x) + (Delta m_k, 0) with known
+    plaintexts; one squaring level bit-exact for the first and last, and the
+    whole mask decrypting to [x_k == y] on a spread of them."""
+    S = s32k
+    n_ct = 32
+    rng = np.random.default_rng(12)
+    x, y = synth.column_pair_half_match(3, S.pr.n)
+    cx, cy = S.enc(x, 31), S.enc(y, 32)
+    shifts = [np.where(rng.random(S.pr.n) < 0.25, rng.integers(1, S.pr.t, S.pr.n), 0)
+              for _ in range(n_ct)]
+    shifts[0][:] = 0
+    cts = []
+    for d in shifts:
+        m = encoding.encode(d, S.pr.t)
+        c0 = (ring.as_object(cx[0]) + S.pr.delta * ring.as_object(m)) % S.pr.Q
+        cts.append((c0, cx[1]))
+    dx = S.to_dev(cts)
+    dy = S.to_dev([cy])
+    dz = S.ctx.sub(dx, S.to_dev([cy] * n_ct))
+    sq = S.ctx.square_relin(dz)
+    for k in (0, n_ct - 1):
+        want = bfv.square_relin(S.pr, S.rk, bfv.sub(S.pr, cts[k], cy))
+        np.testing.assert_array_equal(sq[k].cpu().numpy(), S.limbs(want))
+    out = S.ctx.eq_mask(dx, dy)
+    got = S.from_dev(out)
+    for k in (0, 1, 7, 13, 20, 26, n_ct - 1):
+        xk = (x + shifts[k]) % S.pr.t
+        assert list(bfv.decrypt_slots(S.pr, S.sk, got[k])) == list((xk == y % S.pr.t).astype(int))
