@@ -309,9 +309,9 @@ def summarize_profiles(prof_dir: str, out_dir: str) -> None:
     with open(os.path.join(out_dir, "traffic.json"), "w") as fh:
         json.dump({"kernel_hash": kernel_hash(), "bytes_per_launch": traffic,
                    "calibration": {"copy_mib": mib, "factors": factors}}, fh, indent=1)
-    cmd_trace = ("rocprofv3 --kernel-trace --stats -d gpurun_out/prof/trace -o eq --output-format csv "
+    cmd_trace = (f"rocprofv3 --kernel-trace --stats -d {prof_dir}/trace -o eq --output-format csv "
                  "-- python3 bench.py --steps 3 --warmup 1 --skip-batched --skip-cpu --skip-next")
-    cmd_pmc = ("rocprofv3 --pmc {C} -d gpurun_out/prof/{d} -o eq --output-format csv -- python3 "
+    cmd_pmc = (f"rocprofv3 --pmc {{C}} -d {prof_dir}/{{d}} -o eq --output-format csv -- python3 "
                "bench.py --steps 1 --warmup 0 --skip-batched --skip-cpu --skip-next "
                "--calibrate-copy-mib 256")
     with open(os.path.join(out_dir, "eq_mask_2p20_rows_kernels.md"), "w") as fh:

@@ -104,3 +104,33 @@ def test_full_size_bench_configuration(s32k):
     for k in (0, 1, 7, 13, 20, 26, n_ct - 1):
         xk = (x + shifts[k]) % S.pr.t
         assert list(bfv.decrypt_slots(S.pr, S.sk, got[k])) == list((xk == y % S.pr.t).astype(int))
+
+
+def test_full_size_batched_waves(s32k):
+    """Batched EQ at full size: three instances of 3, 1 and 2 ciphertexts,
+    each against its own broadcast constant, in graph waves of 2 (replayed
+    twice): every mask equals the single-instance call's and decrypts."""
+    S = s32k
+    rng = np.random.default_rng(13)
+    x = rng.integers(0, 1 << 16, S.pr.n)
+    cx = S.enc(x, 41)
+    items, plain = [], []
+    for k, m in enumerate((3, 1, 2)):
+        c = int(x[k])
+        cts, xs = [], []
+        for i in range(m):
+            d = np.where(rng.random(S.pr.n) < 0.5, 0, rng.integers(1, S.pr.t, S.pr.n))
+            mm = encoding.encode(d, S.pr.t)
+            cts.append(((ring.as_object(cx[0]) + S.pr.delta * ring.as_object(mm)) % S.pr.Q, cx[1]))
+            xs.append((x + d) % S.pr.t)
+        items.append((S.to_dev(cts), S.to_dev([S.enc(np.full(S.pr.n, c), 50 + k)])))
+        plain.append((xs, c))
+    for rep in range(2):
+        outs = S.ctx.eq_mask_batched(items, wave_ct=2, use_graph=True)
+        torch.cuda.synchronize()
+    for (dx, dy), o, (xs, c) in zip(items, outs, plain):
+        ref = S.ctx.eq_mask(dx, dy)
+        np.testing.assert_array_equal(o.cpu().numpy(), ref.cpu().numpy())
+        got = S.from_dev(o)
+        for i in range(len(xs)):
+            assert list(bfv.decrypt_slots(S.pr, S.sk, got[i])) == list((xs[i] == c).astype(int))
