@@ -83,7 +83,9 @@ typedef struct nshe_ctx nshe_ctx;
 /* BFV parameters (Sec. 5.1: n = 32768, log Q = 881, t = 65537).
  *   log2_n  ring degree N = 2^log2_n, NSHE_MIN_LOG2N..NSHE_MAX_LOG2N;
  *   t       plaintext modulus, odd, 2 < t < 2^24, coprime to every prime;
- *   L       number of data primes, 1..NSHE_MAX_L;
+ *   L       number of data primes: 2, 3, 4, 8, 12, 16, 17, 20 or 24 (the
+ *           counts the base-conversion kernels are built for; the paper's
+ *           parameters use 17);
  *   q_host  L distinct primes, each in [2^48, 2^49) and = 1 (mod 2N);
  *   P       the special prime, same constraints, distinct from the q_i.
  * Q = prod q_i.  The library picks its own extension basis (primes of the

@@ -448,6 +448,13 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
   if (pr->log2_n < NSHE_MIN_LOG2N || pr->log2_n > NSHE_MAX_LOG2N)
     return fail(NSHE_EINVAL, "log2_n out of range");
   if (pr->L < 1 || pr->L > NSHE_MAX_L) return fail(NSHE_EINVAL, "L out of range");
+  {
+    // the base-conversion kernels are instantiated for these prime counts
+    static const int kSupportedL[] = {2, 3, 4, 8, 12, 16, 17, 20, 24};
+    bool ok = false;
+    for (int v : kSupportedL) ok = ok || v == pr->L;
+    if (!ok) return fail(NSHE_EINVAL, "L must be one of 2, 3, 4, 8, 12, 16, 17, 20, 24");
+  }
   if (!pr->q_host) return fail(NSHE_EINVAL, "q_host is null");
   if (pr->t < 3 || (pr->t & 1) == 0 || pr->t >= (1u << 24))
     return fail(NSHE_EINVAL, "t must be odd, 3 <= t < 2^24");

@@ -53,11 +53,19 @@ def _create(log2_n=10, t=65537, q=None, P=None):
     (dict(log2_n=16), "log2_n"),
     (dict(t=65536), "t must be odd"),
     (dict(t=1), "t must be odd"),
-    (dict(q=[97], P=193), "[2^48, 2^49)"),
+    (dict(q=[97, 193], P=257), "[2^48, 2^49)"),
 ])
 def test_create_rejects_bad_parameters_before_device_use(kw, msg):
     rc, err, h = _create(**kw)
     assert rc == -1 and msg in err and not h.value
+
+
+def test_create_rejects_unsupported_prime_counts():
+    q, P = params.modulus_chain()
+    for L in (1, 5, 18):
+        rc, err, h = _create(q=q[:L] if L <= len(q) else q + q[:1], P=P)
+        assert rc == -1 and not h.value
+        assert "L must be one of" in err
 
 
 def test_create_rejects_composite_and_duplicate_primes():
