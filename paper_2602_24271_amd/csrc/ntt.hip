@@ -434,6 +434,75 @@ k_ntt_fwd(NttJob job, Tables tb) {
   for (int e = 0; e < S::E; ++e) buf_store(x[e], ro, vo, e * S::T * 8);
 }
 
+// Tensor component of a squaring from one limb of the operand's
+// transforms: a^2 (CROSS false, a = ra) or 2 a0 a1 (CROSS true, a0 = ra,
+// a1 = rb).  Loads run one group of G elements ahead of the products, each
+// group's addresses fenced on the previous group's results.
+template <int LOGN, bool CROSS>
+__device__ __forceinline__ void tensor_square(double (&x)[NttShape<LOGN>::E],
+                                              __amdgpu_buffer_rsrc_t ra,
+                                              __amdgpu_buffer_rsrc_t rb, unsigned vo,
+                                              double p, double pinv) {
+  using S = NttShape<LOGN>;
+  constexpr int G = 4;
+  double ba[2][G], bb[2][G];
+#pragma unroll
+  for (int i = 0; i < G; ++i) {
+    ba[0][i] = buf_load(ra, vo, i * S::T * 8);
+    if constexpr (CROSS) bb[0][i] = buf_load(rb, vo, i * S::T * 8);
+  }
+#pragma unroll
+  for (int g = 0; g < S::E; g += G) {
+    const int slot = (g / G) & 1;
+    if (g + G < S::E) {
+      unsigned v = vo;
+      if (g) asm volatile("" : "+v"(v) : "v"(x[g - 1]));
+#pragma unroll
+      for (int i = 0; i < G; ++i) {
+        ba[slot ^ 1][i] = buf_load(ra, v, (g + G + i) * S::T * 8);
+        if constexpr (CROSS) bb[slot ^ 1][i] = buf_load(rb, v, (g + G + i) * S::T * 8);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+      const double a = ba[slot][i];
+      if constexpr (CROSS)
+        x[g + i] = mul_bal(a + a, bb[slot][i], p, pinv);
+      else
+        x[g + i] = mul_bal(a, a, p, pinv);
+    }
+  }
+}
+
+// Tensor component of a product: a b (CROSS false) or a b + c d (CROSS
+// true), loads in groups of 8 elements, each group fenced on the previous
+// one's results.
+template <int LOGN, bool CROSS>
+__device__ __forceinline__ void tensor_product(double (&x)[NttShape<LOGN>::E],
+                                               __amdgpu_buffer_rsrc_t ra,
+                                               __amdgpu_buffer_rsrc_t rb,
+                                               __amdgpu_buffer_rsrc_t rc,
+                                               __amdgpu_buffer_rsrc_t rd, unsigned vo,
+                                               double p, double pinv) {
+  using S = NttShape<LOGN>;
+  unsigned v = vo;
+#pragma unroll
+  for (int g = 0; g < S::E; g += 8) {
+    if (g) asm volatile("" : "+v"(v) : "v"(x[g - 1]));
+#pragma unroll
+    for (int e = g; e < g + 8 && e < S::E; ++e) {
+      const unsigned so = e * S::T * 8;
+      if constexpr (CROSS) {
+        const double a = buf_load(ra, v, so), b = buf_load(rb, v, so);
+        const double c = buf_load(rc, v, so), d = buf_load(rd, v, so);
+        x[e] = reduce_bal(mul_lazy(a, b, p, pinv) + mul_lazy(c, d, p, pinv), p, pinv);
+      } else {
+        x[e] = mul_bal(buf_load(ra, v, so), buf_load(rb, v, so), p, pinv);
+      }
+    }
+  }
+}
+
 template <int LOGN, int MODE>
 __global__ void __launch_bounds__(NttShape<LOGN>::T)
 k_ntt_inv(NttJob job, Tables tb) {
@@ -456,9 +525,10 @@ k_ntt_inv(NttJob job, Tables tb) {
   double x[S::E];
   if constexpr (MODE == INV_TENSOR || MODE == INV_TENSOR2) {
     // poly = ct * 3 + k: form the k-th tensor component from the operands'
-    // transforms (a in src, b in src_b, or b = a when src_b is null):
-    // d0 = a0 b0, d1 = a0 b1 + a1 b0, d2 = a1 b1.  Loads go in groups of 8
-    // elements, each group fenced on the previous one's results.
+    // transforms (a in src, b in src_b, or b = a for a squaring):
+    // d0 = a0 b0, d1 = a0 b1 + a1 b0, d2 = a1 b1.  k is uniform over the
+    // block, so it selects a whole load loop once: branches inside the loop
+    // would make every load wait for the one before it.
     const int ct = poly / 3;
     const int k = poly - ct * 3;
     const size_t o0 = (size_t)ct * job.src_ct_stride + (size_t)limb * S::N;
@@ -466,56 +536,19 @@ k_ntt_inv(NttJob job, Tables tb) {
     const auto ra0 = make_rsrc(job.src + o0, S::N * 8);
     const auto ra1 = make_rsrc(job.src + o1, S::N * 8);
     if constexpr (MODE == INV_TENSOR) {
-      // squaring: d0 = a0^2, d1 = 2 a0 a1, d2 = a1^2; loads pipelined one
-      // group of G elements ahead (as in the forward half transform)
-      constexpr int G = 4;
-      double ba[2][G], bb[2][G];
-      const auto& r1 = k == 2 ? ra1 : ra0;   // first operand
-#pragma unroll
-      for (int i = 0; i < G; ++i) {
-        ba[0][i] = buf_load(r1, vo, i * S::T * 8);
-        if (k == 1) bb[0][i] = buf_load(ra1, vo, i * S::T * 8);
-      }
-#pragma unroll
-      for (int g = 0; g < S::E; g += G) {
-        const int slot = (g / G) & 1;
-        if (g + G < S::E) {
-          unsigned v = vo;
-          if (g) asm volatile("" : "+v"(v) : "v"(x[g - 1]));
-#pragma unroll
-          for (int i = 0; i < G; ++i) {
-            ba[slot ^ 1][i] = buf_load(r1, v, (g + G + i) * S::T * 8);
-            if (k == 1) bb[slot ^ 1][i] = buf_load(ra1, v, (g + G + i) * S::T * 8);
-          }
-        }
-#pragma unroll
-        for (int i = 0; i < G; ++i) {
-          const double a = ba[slot][i];
-          x[g + i] = k == 1 ? mul_bal(a + a, bb[slot][i], p, pinv) : mul_bal(a, a, p, pinv);
-        }
-      }
+      if (k == 1)
+        tensor_square<LOGN, true>(x, ra0, ra1, vo, p, pinv);
+      else
+        tensor_square<LOGN, false>(x, k == 2 ? ra1 : ra0, ra1, vo, p, pinv);
     } else {
-    const double* sb = job.src_b;
-    const auto rb0 = make_rsrc(sb + o0, S::N * 8);
-    const auto rb1 = make_rsrc(sb + o1, S::N * 8);
-    unsigned v = vo;
-#pragma unroll
-    for (int g = 0; g < S::E; g += 8) {
-      if (g) asm volatile("" : "+v"(v) : "v"(x[g - 1]));
-#pragma unroll
-      for (int e = g; e < g + 8 && e < S::E; ++e) {
-        const unsigned so = e * S::T * 8;
-        if (k == 0) {
-          x[e] = mul_bal(buf_load(ra0, v, so), buf_load(rb0, v, so), p, pinv);
-        } else if (k == 2) {
-          x[e] = mul_bal(buf_load(ra1, v, so), buf_load(rb1, v, so), p, pinv);
-        } else {
-          const double a0 = buf_load(ra0, v, so), a1 = buf_load(ra1, v, so);
-          const double b0 = buf_load(rb0, v, so), b1 = buf_load(rb1, v, so);
-          x[e] = reduce_bal(mul_lazy(a0, b1, p, pinv) + mul_lazy(a1, b0, p, pinv), p, pinv);
-        }
-      }
-    }
+      const auto rb0 = make_rsrc(job.src_b + o0, S::N * 8);
+      const auto rb1 = make_rsrc(job.src_b + o1, S::N * 8);
+      if (k == 1)
+        tensor_product<LOGN, true>(x, ra0, rb1, ra1, rb0, vo, p, pinv);
+      else if (k == 0)
+        tensor_product<LOGN, false>(x, ra0, rb0, ra0, rb0, vo, p, pinv);
+      else
+        tensor_product<LOGN, false>(x, ra1, rb1, ra1, rb1, vo, p, pinv);
     }
   } else {
 #pragma unroll
