@@ -13,9 +13,12 @@ second.  The line also carries:
                 recorded around every launch inside the timed region), against
                 the chip's FP64 VALU issue peak;
   kernels       per-kernel-kind time and launch counts from the same events;
+  rates         squarings/s, transformed residues/s, modular products/s;
+  latency_1ct_ms  one ciphertext (32,768 rows) through the whole mask;
   batched       512 instances of uneven size (rows log-uniform in
                 [2^14, 2^20]) in HIP-graph waves (autotuned launch shapes and
                 wave size) vs a per-instance launch loop;
+  batched_128   the same for 128 instances, rows in [2^16, 2^20];
   next_rows     IN against 4 members, SELECT, the rotate-and-add SUM/COUNT,
                 LT against a constant and a 4-row JOIN over the same column;
   cpu_baseline  the exact-integer oracle on a bounded sample, host cores.
@@ -131,17 +134,20 @@ def cpu_baseline() -> dict:
             "host_cpu": cpu, "host_cores_available": os.cpu_count()}
 
 
-def batched(ctx, n_inst: int, reps: int, max_wave: int = 128) -> dict:
+def batched(ctx, n_inst: int, reps: int, max_wave: int = 128, seed: int = 2,
+            lo_rows: int = 1 << 14, hi_rows: int = 1 << 20) -> dict:
+    """n_inst instances with rows log-uniform in [lo_rows, hi_rows] (one
+    encrypted constant each as y), HIP-graph waves vs a per-instance loop."""
     import torch
     import synth
-    rows = synth.log_uniform_sizes(2, n_inst, 1 << 14, 1 << 20)
+    rows = synth.log_uniform_sizes(seed, n_inst, lo_rows, hi_rows)
     cts = [int(math.ceil(r / ctx.n)) for r in rows]
     total = sum(cts)
     dev = ctx.device
     items = []
     for i, m in enumerate(cts):
-        x = synth.uniform_device_residues((m, 2), ctx.q, ctx.n, 1000 + i, dev)
-        y = synth.uniform_device_residues((1, 2), ctx.q, ctx.n, 5000 + i, dev)
+        x = synth.uniform_device_residues((m, 2), ctx.q, ctx.n, 1000 * seed + 10000 + i, dev)
+        y = synth.uniform_device_residues((1, 2), ctx.q, ctx.n, 1000 * seed + 50000 + i, dev)
         items.append((x, y))
     outs = [torch.empty_like(x) for x, _ in items]
     # autotune launch shapes and the wave size on the largest instance
@@ -173,10 +179,34 @@ def batched(ctx, n_inst: int, reps: int, max_wave: int = 128) -> dict:
     t_loop = (time.perf_counter() - t0) / reps
     log(f"per-instance loop {t_loop * 1e3:.1f} ms")
     recs = total * ctx.n
-    return {"instances": n_inst, "ciphertexts": total, "wave_ct": wave,
+    return {"instances": n_inst, "rows_range": [lo_rows, hi_rows], "seed": seed,
+            "ciphertexts": total, "wave_ct": wave,
             "autotuned": tuned, "autotune_s": t_tune,
             "records_per_s_graph": recs / t_graph, "records_per_s_loop": recs / t_loop,
             "ms_graph": t_graph * 1e3, "ms_loop": t_loop * 1e3, "speedup": t_loop / t_graph}
+
+
+def derived_rates(ctx, prof: dict, steps: int, n_ct: int, ms: float) -> dict:
+    """The timed steps in the method's own units per second: squarings (one
+    per ciphertext and level), residues through a number-theoretic transform
+    (forward or inverse; from the transform launches' butterfly counts) and
+    algorithmic modular products.  Products per ciphertext and level, with
+    L data primes, LB = L + 1 extension primes and N coefficients: one per
+    butterfly; the squaring's tensor 3 (L + LB) N; the lift 2 (L + LB L) N;
+    the scale-and-round 3 (L + LB (L + 1) + L LB) N; the key-switch inner
+    product 2 L (L + 1) N; the mod-down 2 (2 L + 1) N."""
+    sec = ms / 1e3
+    n, L = ctx.n, ctx.L
+    LB = L + 1
+    log2n = n.bit_length() - 1
+    bfly = sum(v["work"] for k, v in prof.items() if k.startswith("ntt")) / steps
+    levels = ctx.squarings * n_ct
+    per_level = (3 * (L + LB) + 2 * (L + LB * L) + 3 * (L + LB * (L + 1) + L * LB)
+                 + 2 * L * (L + 1) + 2 * (2 * L + 1)) * n
+    return {"squarings_per_s": levels / sec,
+            "ntt_residues_per_s": bfly * 2 / log2n / sec,
+            "modmul_per_s": (bfly + levels * per_level) / sec,
+            "modmul_per_step": bfly + levels * per_level}
 
 
 def timed(fn, reps: int) -> float:
@@ -400,15 +430,21 @@ def main() -> int:
     value = records / (ms / 1e3)
     log(f"{ms:.2f} ms/step, {value:.4g} records/s")
     roof, _ = roofline(prof)
+    rates = derived_rates(ctx, prof, args.steps, n_ct, ms)
+    # one ciphertext (32,768 rows, the paper's per-query workload): latency
+    lat_ms = timed(lambda: ctx.eq_mask(x[:1], y[:1], out[:1]), 5) * 1e3
+    log(f"one-ciphertext latency {lat_ms:.2f} ms")
     kernels = {k: {"launches": v["launches"] // args.steps, "ms_per_step": v["ms"] / args.steps}
                for k, v in prof.items()}
 
     nxt = None
     if not args.skip_next:
         nxt = next_rows(ctx, x, out, args.next_reps)
-    bat = None
+    bat = bat_fwd = None
     if not args.skip_batched:
         bat = batched(ctx, args.batched_instances, args.batched_reps)
+        # 128 instances, rows log-uniform in [2^16, 2^20] (2..32 ciphertexts)
+        bat_fwd = batched(ctx, 128, args.batched_reps, seed=3, lo_rows=1 << 16)
     cpu = None
     if not args.skip_cpu:
         cpu = cpu_baseline()
@@ -434,8 +470,11 @@ def main() -> int:
                    "data_primes": ctx.L, "plaintext_modulus": ctx.t},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "rates": rates,
+        "latency_1ct_ms": lat_ms,
         "kernels": kernels,
         "batched": bat,
+        "batched_128": bat_fwd,
         "next_rows": nxt,
         "adjoint": None,
         "adjoint_note": "no adjoint: the mask is discrete (Z_t plaintexts, R_Q ciphertexts)",

@@ -89,3 +89,22 @@ def test_lt_outside_range_matches_oracle():
     np.testing.assert_array_equal(got[0].cpu().numpy(), S.limbs(want))
     A = set(compare.negative_half(17))
     assert list(bfv.decrypt_slots(S.pr, S.sk, want)) == [int((a - b) % 17 in A) for a, b in zip(x, y)]
+
+
+def test_launch_sequence_is_data_oblivious(s256):
+    """The same kernels, launch counts and work for a structured encrypted
+    column and for uniform residues: nothing in the path depends on values."""
+    S = s256
+    x, y = synth.column_structured(1, S.pr.n)
+    enc = S.to_dev([S.enc(x, 40)]), S.to_dev([S.enc(y, 41)])
+    uni = tuple(synth.uniform_device_residues((1, 2), list(S.pr.q), S.pr.n, 42 + i, S.ctx.device)
+                for i in range(2))
+    seen = []
+    for a, b in (enc, uni):
+        S.ctx.profile(True)
+        S.ctx.eq_mask(a, b)
+        torch.cuda.synchronize()
+        rec = S.ctx.profile_read()
+        S.ctx.profile(False)
+        seen.append({k: (v["launches"], v["work"]) for k, v in rec.items()})
+    assert seen[0] == seen[1] and seen[0]
