@@ -606,8 +606,23 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
     }
   }
   std::vector<u64> qv(q), bv(b);
-  std::vector<double> q_hat_inv(L), q_hat_b((size_t)LB * L), Q_b(LB), t_qhinv(L), t_q(L),
-      c1(LB), c2((size_t)LB * L), b_hat_inv(LB), b_hat_q((size_t)L * LB), B_q(L), P_inv_q(L), NP_inv_q(L),
+  // Base-conversion matrices: each entry M (balanced mod m) split as M =
+  // c1 2^24 + c0 (|c1| <= 2^24, |c0| <= 2^23) for exact FMA accumulation.
+  auto split = [](double* d, u64 M, u64 m) {
+    const double cb = bal(M, m);
+    const double c1v = std::nearbyint(cb * 0x1p-24);
+    d[0] = c1v;
+    d[1] = cb - c1v * 0x1p24;
+  };
+  std::vector<double> q_hat_b_sp((size_t)LB * L * 2), c2_sp((size_t)LB * L * 2),
+      b_hat_q_sp((size_t)L * LB * 2), two24(K), two48(K);
+  for (int i = 0; i < K; ++i) {
+    const u64 m = prime(i), t24 = (1ull << 24) % m;
+    two24[i] = bal(t24, m);
+    two48[i] = bal(mulmod(t24, t24, m), m);
+  }
+  std::vector<double> q_hat_inv(L), Q_b(LB), t_qhinv(L), t_q(L),
+      c1(LB), b_hat_inv(LB), B_q(L), P_inv_q(L), NP_inv_q(L),
       delta_q(L), mrc_inv((size_t)L * L, 0.0), mrc_half(L);
   u64 Qmodt = 1;
   for (u64 x : qv) Qmodt = mulmod(Qmodt, x % c->t, c->t);
@@ -624,7 +639,7 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
     NP_inv_q[i] = bal(mulmod(invmod(pr->P % qi, qi), ninv_q, qi), qi);
     // Delta = (Q - (Q mod t)) / t = -(Q mod t) * t^-1 (mod q_i)
     delta_q[i] = bal((qi - mulmod(Qmodt, invmod(c->t % qi, qi), qi)) % qi, qi);
-    for (int k = 0; k < LB; ++k) b_hat_q[(size_t)i * LB + k] = bal(prod_mod(bv, k, qi), qi);
+    for (int k = 0; k < LB; ++k) split(&b_hat_q_sp[((size_t)i * LB + k) * 2], prod_mod(bv, k, qi), qi);
     for (int j = 0; j < i; ++j) mrc_inv[(size_t)j * L + i] = bal(invmod(qv[j] % qi, qi), qi);
   }
   for (int k = 0; k < LB; ++k) {
@@ -636,8 +651,8 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
     c1[k] = bal(mulmod(mulmod(mulmod(c->t % bk, invmod(Qb, bk), bk), bhi, bk),
                        invmod((u64)n % bk, bk), bk), bk);
     for (int i = 0; i < L; ++i) {
-      q_hat_b[(size_t)k * L + i] = bal(prod_mod(qv, i, bk), bk);
-      c2[(size_t)k * L + i] = bal(mulmod(invmod(qv[i] % bk, bk), bhi, bk), bk);
+      split(&q_hat_b_sp[((size_t)k * L + i) * 2], prod_mod(qv, i, bk), bk);
+      split(&c2_sp[((size_t)k * L + i) * 2], mulmod(invmod(qv[i] % bk, bk), bhi, bk), bk);
     }
   }
   // mixed-radix digits of (Q-1)/2, whose residue mod q_i is (q_i - 1)/2
@@ -658,14 +673,16 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
   std::vector<std::pair<const std::vector<double>*, const double**>> parts = {
       {&h_p, &c->tb.p},           {&h_pinv, &c->tb.pinv},     {&h_pinv, &c->tb.recip},
       {&h_ninv, &c->tb.ninv},     {&tw_f, &c->tb.tw_fwd},     {&tw_i, &c->tb.tw_inv},
-      {&q_hat_inv, &c->tb.q_hat_inv}, {&q_hat_b, &c->tb.q_hat_b}, {&Q_b, &c->tb.Q_b},
+      {&q_hat_inv, &c->tb.q_hat_inv}, {&Q_b, &c->tb.Q_b},
       {&t_qhinv, &c->tb.t_qhinv}, {&t_q, &c->tb.t_q},         {&c1, &c->tb.c1},
-      {&c2, &c->tb.c2},           {&b_hat_inv, &c->tb.b_hat_inv}, {&b_hat_q, &c->tb.b_hat_q},
+      {&b_hat_inv, &c->tb.b_hat_inv},
       {&B_q, &c->tb.B_q},         {&P_inv_q, &c->tb.P_inv_q}, {&NP_inv_q, &c->tb.NP_inv_q},
       {&delta_q, &c->tb.delta_q},
       {&mrc_inv, &c->tb.mrc_inv}, {&mrc_half, &c->tb.mrc_half}, {&tw_h, &c->tb.tw_half},
       {&tw_h0, &c->tb.tw_half0},  {&tw_cf, &c->tb.tw_cmp_f},  {&tw_ci, &c->tb.tw_cmp_i},
-      {&tw_ch, &c->tb.tw_cmp_h},  {&tw_kf, &c->tb.tw_cst_f},  {&tw_ki, &c->tb.tw_cst_i}};
+      {&tw_ch, &c->tb.tw_cmp_h},  {&tw_kf, &c->tb.tw_cst_f},  {&tw_ki, &c->tb.tw_cst_i},
+      {&q_hat_b_sp, &c->tb.q_hat_b_sp}, {&c2_sp, &c->tb.c2_sp}, {&b_hat_q_sp, &c->tb.b_hat_q_sp},
+      {&two24, &c->tb.two24},     {&two48, &c->tb.two48}};
   size_t total = 0;
   std::vector<size_t> offs;
   for (auto& pp : parts) {

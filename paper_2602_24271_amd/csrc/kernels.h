@@ -37,7 +37,6 @@ struct Tables {
   int tw_half_len;
   // centred lift Q -> B
   const double* q_hat_inv;   // [L]      [(Q/q_i)^-1]_{q_i}
-  const double* q_hat_b;     // [LB][L]  [Q/q_i]_{b_k}
   const double* Q_b;         // [LB]     [Q]_{b_k}
   // scale and round, then B -> Q
   // (the scale-and-round reads inverse-transform output, which carries a
@@ -45,10 +44,16 @@ struct Tables {
   const double* t_qhinv;     // [L]      [t (Q/q_i)^-1 N^-1]_{q_i}
   const double* t_q;         // [L]      [t N^-1]_{q_i}
   const double* c1;          // [LB]     [t Q^-1 (B/b_k)^-1 N^-1]_{b_k}
-  const double* c2;          // [LB][L]  [q_i^-1 (B/b_k)^-1]_{b_k}
   const double* b_hat_inv;   // [LB]     [(B/b_k)^-1]_{b_k}
-  const double* b_hat_q;     // [L][LB]  [B/b_k]_{q_i}
   const double* B_q;         // [L]      [B]_{q_i}
+  // the three base-conversion matrices, each balanced entry M split for
+  // exact FMA accumulation as M = c1 2^24 + c0, stored {c1, c0} (see
+  // conv_row), and [2^24]_p, [2^48]_p per prime
+  const double* q_hat_b_sp;  // [LB][L][2]  [Q/q_i]_{b_k}
+  const double* c2_sp;       // [LB][L][2]  [q_i^-1 (B/b_k)^-1]_{b_k}
+  const double* b_hat_q_sp;  // [L][LB][2]  [B/b_k]_{q_i}
+  const double* two24;       // [K]
+  const double* two48;       // [K]
   // key switching
   const double* P_inv_q;     // [L]      [P^-1]_{q_i}
   const double* NP_inv_q;    // [L]      [N^-1 P^-1]_{q_i}

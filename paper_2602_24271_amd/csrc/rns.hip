@@ -20,6 +20,10 @@
 // y_i, v are the lift quantities of r; then y is lifted from B to Q (|y| <
 // t N Q / 2 < B / 32, so that lift's estimate is never near a half-integer;
 // a violation would be counted in `fault`).
+//
+// The sums over the other basis (sum_i y_i [Q/q_i]_{b_k} and the like) are
+// matrix-vector products mod b_k; they run as exact FMA accumulations of
+// split operands (conv_row) with one modular reduction per output.
 #include "kernels.h"
 
 namespace nshe {
@@ -74,6 +78,50 @@ __device__ __forceinline__ PolyBlock poly_block(int n, size_t n_poly) {
   return PolyBlock{pc, c, pc < n_poly && c < n};
 }
 
+// ------------------------------------------------ split base conversion ---
+
+// A base-conversion row sum_j y_j M_j (mod m) over NT <= 25 terms with four
+// FMAs per term instead of a modular product.  Each input (a reduced
+// residue, |y| <= 2^48) is split once as y = yh 2^24 + yl (|yh| <= 2^24,
+// |yl| <= 2^23) and each constant is stored split the same way, M = c1 2^24
+// + c0 (|c1| <= 2^24, |c0| <= 2^23).  Then
+//   y M = yh c1 2^48 + (yh c0 + yl c1) 2^24 + yl c0,
+// so the row is W48 [2^48]_m + W24 [2^24]_m + W0 (mod m) with W48 = sum yh
+// c1, W24 = sum yh c0 + yl c1 and W0 = sum yl c0.  Every product is an
+// integer of at most 2^48, so exact, and so is every partial sum (|W48|,
+// |W24| <= NT 2^48 < 2^53, |W0| <= NT 2^46).  The two lazy products have
+// quotients below 2^53 and remainders below 1.8 m; the result is returned
+// unreduced, |result| <= (NT / 4 + 7.2) 2^48.
+constexpr int CONV_SPLIT_MAX = 25;
+constexpr int CONV_CHUNK = 9;
+
+__device__ __forceinline__ void split24(double y, double& yh, double& yl) {
+  yh = __builtin_rint(y * 0x1p-24);
+  yl = __builtin_fma(-yh, 0x1p24, y);
+}
+
+// sp: the row's constants {c1, c0} per term; t24 = [2^24]_m, t48 = [2^48]_m.
+template <int NT>
+__device__ __forceinline__ double conv_row(const double (&yh)[NT], const double (&yl)[NT],
+                                           const double* sp, double t24, double t48, double m,
+                                           double minv) {
+  static_assert(NT <= CONV_SPLIT_MAX, "partial sums must stay below 2^53");
+  double w48 = 0.0, w24a = 0.0, w24b = 0.0, w0 = 0.0;
+#pragma unroll
+  for (int j = 0; j < NT; ++j) {
+    // constants are fetched CONV_CHUNK terms at a time: the row pointer is
+    // made to depend on the running sums, so later terms' scalar loads are
+    // not all hoisted to the row's start (which spills scalar registers)
+    if (j && j % CONV_CHUNK == 0) asm volatile("" : "+s"(sp) : "v"(w0));
+    const double c1 = cld(sp, 2 * j), c0 = cld(sp, 2 * j + 1);
+    w48 = __builtin_fma(yh[j], c1, w48);
+    w24a = __builtin_fma(yh[j], c0, w24a);
+    w24b = __builtin_fma(yl[j], c1, w24b);
+    w0 = __builtin_fma(yl[j], c0, w0);
+  }
+  return mul_lazy(w48, t48, m, minv) + mul_lazy(w24a + w24b, t24, m, minv) + w0;
+}
+
 // ------------------------------------------------------------------ lift ---
 
 // ext: [n_poly][L+LB][N]; limbs 0..L-1 (balanced, coefficient domain) are
@@ -101,13 +149,17 @@ __global__ void __launch_bounds__(256) k_lift(int n, size_t n_poly, double* ext,
     v = __builtin_floor(S) + (mrc_greater_than_half<L>(r, tb.p, tb.pinv, tb.mrc_inv, tb.mrc_half) ? 1.0 : 0.0);
     atomicAdd(tb.margin, 1ull);
   }
+  // |acc| <= (L / 4 + 7.2 + L/2 + 1) 2^48 < 2^53: reduce_bal is exact there
+  // (its result within p/2 + 4)
+  double yh[L], yl[L];
+#pragma unroll
+  for (int i = 0; i < L; ++i) split24(y[i], yh[i], yl[i]);
 #pragma unroll
   for (int k = 0; k < LB; ++k) {
     const double b = cld(tb.p, L + k), binv = cld(tb.pinv, L + k);
-    const double* qb = opaque_row(tb.q_hat_b, k * L);
-    double acc = -v * cld(tb.Q_b, k);
-#pragma unroll
-    for (int i = 0; i < L; ++i) acc += mul_lazy(y[i], cld(qb, i), b, binv);
+    const double* sp = opaque_row(tb.q_hat_b_sp, k * L * 2);
+    const double acc = conv_row<L>(yh, yl, sp, cld(tb.two24, L + k), cld(tb.two48, L + k), b, binv) -
+                       v * cld(tb.Q_b, k);
     buf_store(reduce_bal(acc, b, binv), rs, vo, (L + k) * ls);
   }
 }
@@ -141,27 +193,43 @@ __global__ void __launch_bounds__(256) k_scale(int n, size_t n_poly, double* dt,
     v = __builtin_floor(S) + (mrc_greater_than_half<L>(r, tb.p, tb.pinv, tb.mrc_inv, tb.mrc_half) ? 1.0 : 0.0);
     atomicAdd(tb.margin, 1ull);
   }
-  double w[LB];
+  // Split conversions (conv_row).  The base-B residues w_k wait in LDS (this
+  // thread's own slots, [LB][blockDim]) between the two conversions, so
+  // that the split inputs of one and of the other are never live together.
+  // Every sum before a reduction stays below 2^53 (at most (L / 4 + 7.2 +
+  // 1.75 + L/2 + 1) 2^48), where reduce_bal is exact with its result within
+  // p/2 + 4, so |w_k| <= 2^48.
+  extern __shared__ double wpark[];
+  double* wp = wpark + threadIdx.x;
+  const int bs = (int)blockDim.x;
   double S2 = 0.0;
+  {
+    double yh[L], yl[L];
 #pragma unroll
-  for (int k = 0; k < LB; ++k) {
-    const double b = cld(tb.p, L + k), binv = cld(tb.pinv, L + k);
-    const double* c2k = opaque_row(tb.c2, k * L);
-    double acc = mul_lazy(buf_load(rs, vo, (L + k) * ls), cld(tb.c1, k), b, binv) + v * cld(tb.b_hat_inv, k);
+    for (int i = 0; i < L; ++i) split24(y[i], yh[i], yl[i]);
 #pragma unroll
-    for (int i = 0; i < L; ++i) acc -= mul_lazy(y[i], cld(c2k, i), b, binv);
-    w[k] = reduce_bal(acc, b, binv);
-    S2 += w[k] * cld(tb.recip, L + k);
+    for (int k = 0; k < LB; ++k) {
+      const double b = cld(tb.p, L + k), binv = cld(tb.pinv, L + k);
+      const double* sp = opaque_row(tb.c2_sp, k * L * 2);
+      const double acc = mul_lazy(buf_load(rs, vo, (L + k) * ls), cld(tb.c1, k), b, binv) +
+                         v * cld(tb.b_hat_inv, k) -
+                         conv_row<L>(yh, yl, sp, cld(tb.two24, L + k), cld(tb.two48, L + k), b, binv);
+      const double w = reduce_bal(acc, b, binv);
+      wp[k * bs] = w;
+      S2 += w * cld(tb.recip, L + k);
+    }
   }
   const double v2 = __builtin_rint(S2);
   if (__builtin_fabs(S2 - v2) > 0.25) atomicAdd(tb.fault, 1ull);
+  double wh[LB], wl[LB];
+#pragma unroll
+  for (int k = 0; k < LB; ++k) split24(wp[k * bs], wh[k], wl[k]);
 #pragma unroll
   for (int i = 0; i < L; ++i) {
     const double q = cld(tb.p, i), qinv = cld(tb.pinv, i);
-    const double* bq = opaque_row(tb.b_hat_q, i * LB);
-    double acc = -v2 * cld(tb.B_q, i);
-#pragma unroll
-    for (int k = 0; k < LB; ++k) acc += mul_lazy(w[k], cld(bq, k), q, qinv);
+    const double* sp = opaque_row(tb.b_hat_q_sp, i * LB * 2);
+    const double acc = conv_row<LB>(wh, wl, sp, cld(tb.two24, i), cld(tb.two48, i), q, qinv) -
+                       v2 * cld(tb.B_q, i);
     const double r = reduce_bal(acc, q, qinv);
     // the third component is only read as relinearization digits, which
     // are its canonical residues
@@ -619,7 +687,8 @@ hipError_t run_scale(const Dims& d, double* dt, const Tables& tb, hipStream_t st
   const size_t np = (size_t)d.n_ct * 3;
   switch (d.L) {
 #define C_(L_) \
-  case L_: hipLaunchKernelGGL(k_scale<L_>, poly_grid(np, d.n, d.block), dim3(d.block), 0, st, d.n, np, dt, tb); break;
+  case L_: hipLaunchKernelGGL(k_scale<L_>, poly_grid(np, d.n, d.block), dim3(d.block), \
+                              (size_t)(L_ + 1) * d.block * 8, st, d.n, np, dt, tb); break;
     NSHE_L_CASES(C_)
 #undef C_
     default: return hipErrorInvalidValue;
