@@ -105,12 +105,17 @@ __device__ __forceinline__ constexpr int lds_chunk() {
 
 // Move the E values of every thread from round r0's index map to r1's.
 // The base addresses are made opaque per pass (inline asm), so that no
-// per-element address registers stay live across the barriers.
+// per-element address registers stay live across the barriers.  Each pass
+// is write, barrier, read; a barrier separates a pass's reads from the next
+// pass's writes.  After the last read there is none: the next exchange
+// starts with it instead (wait_prev), so that a wave starts the round's
+// arithmetic as soon as its own values have arrived.
 template <int LOGN>
 __device__ __forceinline__ void exchange(double (&x)[NttShape<LOGN>::E], int r0, int r1,
-                                         uint32_t* lds) {
+                                         uint32_t* lds, bool wait_prev) {
   using S = NttShape<LOGN>;
   const int tid = threadIdx.x;
+  if (wait_prev) __syncthreads();
   if constexpr (S::SPLIT) {
     constexpr int C0 = lds_chunk<LOGN, 4>();
 #pragma unroll
@@ -142,7 +147,7 @@ __device__ __forceinline__ void exchange(double (&x)[NttShape<LOGN>::E], int r0,
           x[e] = __longlong_as_double(v);
         }
       }
-      __syncthreads();
+      if (half == 0) __syncthreads();
     }
   } else {
     double* d = reinterpret_cast<double*>(lds);
@@ -165,7 +170,6 @@ __device__ __forceinline__ void exchange(double (&x)[NttShape<LOGN>::E], int r0,
 #pragma unroll
       for (int e = c; e < c + C0; ++e) x[e] = base[slot_off<LOGN>(r1, e) - slot_off<LOGN>(r1, c)];
     }
-    __syncthreads();
   }
 }
 
@@ -425,7 +429,7 @@ k_ntt_fwd(NttJob job, Tables tb) {
   }
 #pragma unroll
   for (int r = 0; r < S::ROUNDS; ++r) {
-    if (r > 0) exchange<LOGN>(x, r - 1, r, lds);
+    if (r > 0) exchange<LOGN>(x, r - 1, r, lds, r > 1);
     fwd_round<LOGN>(x, r,
                     fwd_reduces_after<LOGN>(r, 0) && !(MODE == NTT_DIGIT && r == S::ROUNDS - 1),
                     tw, p, pinv);
@@ -558,7 +562,7 @@ k_ntt_inv(NttJob job, Tables tb) {
 #pragma unroll
   for (int rr = 0; rr < S::ROUNDS; ++rr) {
     const int r = S::ROUNDS - 1 - rr;
-    if (rr > 0) exchange<LOGN>(x, r + 1, r, lds);
+    if (rr > 0) exchange<LOGN>(x, r + 1, r, lds, rr > 1);
     inv_round<LOGN>(x, r, g0, tw, p, pinv);
     g0 += S::stages(r);
   }
@@ -660,7 +664,7 @@ k_ntt_fwd_half(NttJob job, Tables tb) {
   }
 #pragma unroll
   for (int r = 0; r < S::ROUNDS; ++r) {
-    if (r > 0) exchange<14>(x, r - 1, r, lds);
+    if (r > 0) exchange<14>(x, r - 1, r, lds, r > 1);
     // digit transforms skip the final reduction (outputs below 3.9 p):
     // their only reader, the key-switch product, reduces its sums itself
     fwd_round<14>(x, r, fwd_reduces_after<14>(r, 1) && !(MODE == NTT_DIGIT && r == S::ROUNDS - 1),
