@@ -340,9 +340,10 @@ def summarize_profiles(prof_dir: str, out_dir: str) -> None:
         json.dump({"kernel_hash": kernel_hash(), "bytes_per_launch": traffic,
                    "calibration": {"copy_mib": mib, "factors": factors}}, fh, indent=1)
     cmd_trace = (f"rocprofv3 --kernel-trace --stats -d {prof_dir}/trace -o eq --output-format csv "
-                 "-- python3 bench.py --steps 3 --warmup 1 --skip-batched --skip-cpu --skip-next")
+                 "-- python3 bench.py --steps 3 --warmup 1 --skip-batched --skip-cpu --skip-next "
+                 "--skip-latency")
     cmd_pmc = (f"rocprofv3 --pmc {{C}} -d {prof_dir}/{{d}} -o eq --output-format csv -- python3 "
-               "bench.py --steps 1 --warmup 0 --skip-batched --skip-cpu --skip-next "
+               "bench.py --steps 1 --warmup 0 --skip-batched --skip-cpu --skip-next --skip-latency "
                "--calibrate-copy-mib 256")
     with open(os.path.join(out_dir, "eq_mask_2p20_rows_kernels.md"), "w") as fh:
         fh.write("# EQ mask, 2^20 rows (32 ciphertexts, N=32768), per-kernel time\n\n")
@@ -372,6 +373,9 @@ def main() -> int:
     ap.add_argument("--batched-reps", type=int, default=1)
     ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--skip-latency", action="store_true",
+                    help="skip the one-ciphertext latency runs (profiling: keeps every "
+                         "launch at the column's size)")
     ap.add_argument("--skip-next", action="store_true",
                     help="skip IN / SELECT / SUM over the same column")
     ap.add_argument("--next-reps", type=int, default=2)
@@ -432,8 +436,10 @@ def main() -> int:
     roof, _ = roofline(prof)
     rates = derived_rates(ctx, prof, args.steps, n_ct, ms)
     # one ciphertext (32,768 rows, the paper's per-query workload): latency
-    lat_ms = timed(lambda: ctx.eq_mask(x[:1], y[:1], out[:1]), 5) * 1e3
-    log(f"one-ciphertext latency {lat_ms:.2f} ms")
+    lat_ms = None
+    if not args.skip_latency:
+        lat_ms = timed(lambda: ctx.eq_mask(x[:1], y[:1], out[:1]), 5) * 1e3
+        log(f"one-ciphertext latency {lat_ms:.2f} ms")
     kernels = {k: {"launches": v["launches"] // args.steps, "ms_per_step": v["ms"] / args.steps}
                for k, v in prof.items()}
 
