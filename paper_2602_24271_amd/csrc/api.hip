@@ -206,10 +206,18 @@ namespace nshe {
 
 static int W_of(const nshe_ctx* c) { return 2 * c->L + 1; }
 
+// 2^15-point limbs: the inverse transforms feeding the scale-and-round and
+// the mod-down run as two half-limb workgroups each, their last stage
+// applied by those consumers (with the split forward, under one tuning flag).
+static bool split_inverse(const nshe_ctx* c) {
+  return c->log2n == 15 && c->tune.split_forward && c->tb.tw_half_inv;
+}
+
 static Dims dims(const nshe_ctx* c, int n_ct) {
   Dims d{c->n, c->L, c->LB, n_ct};
   d.block = c->tune.ew_block;
   d.ks_chunk = c->tune.ks_chunk;
+  d.fused = split_inverse(c) ? 1 : 0;
   return d;
 }
 
@@ -320,9 +328,10 @@ static int ntt_job_ext(nshe_ctx* c, double* base, double* out, int npoly, int di
 }
 
 static int ntt_job_ks(nshe_ctx* c, double* base, double* out, int npoly, int dir,
-                      hipStream_t st) {
+                      hipStream_t st, bool for_moddown = false) {
   NttJob j{};
   j.split = c->tune.split_forward;
+  j.split_inv = for_moddown && split_inverse(c) ? 1 : 0;
   j.base = base;
   j.out = out;
   j.poly_stride = (size_t)(c->L + 1) * c->n;
@@ -362,6 +371,7 @@ static int tensor_scale(nshe_ctx* c, const Ws& w, const double* fx_b, int n_ct, 
     j.src = w.fx;
     j.src_b = fx_b;
     j.src_ct_stride = (size_t)2 * W_of(c) * c->n;
+    j.split_inv = d.fused;
     Prof pf(c, K_NTT_INV_TENSOR, st, ntt_work(c, j.count));
     HIPCHK(run_ntt(c->log2n, j, c->tb, 3, st));
   }
@@ -400,7 +410,7 @@ static int relin(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st,
     Prof pf(c, K_KS_MAC, st, (double)n_ct * c->L * 2 * (c->L + 1) * c->n);
     HIPCHK(run_ks_mac(d, w.dig, key, w.acc, c->tb, st));
   }
-  int rc = ntt_job_ks(c, w.acc, nullptr, n_ct * 2, 1, st);
+  int rc = ntt_job_ks(c, w.acc, nullptr, n_ct * 2, 1, st, true);
   if (rc) return rc;
   {
     Prof pf(c, K_MODDOWN, st, 2.0 * n_ct * c->n);
@@ -538,11 +548,15 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
   if (c->log2n == 15) h_rounds = ntt_rounds(14, &h_loge, &h_r0);
   const int h_len = h_rounds ? 1 << h_loge : 0;
   const int cmp_h_len = h_rounds ? cmp_len_of(h_rounds, h_r0, h_loge) : 0;
-  std::vector<double> tw_h((size_t)K * 2 * std::max(h_len, 1), 0.0), tw_h0(K, 0.0);
+  std::vector<double> tw_h((size_t)K * 2 * std::max(h_len, 1), 0.0), tw_h0(K, 0.0),
+      tw_hi((size_t)K * 2 * std::max(h_len, 1), 0.0);
   std::vector<double> tw_cf((size_t)K * std::max(cmp_len, 1), 0.0),
       tw_ci((size_t)K * std::max(cmp_len, 1), 0.0),
-      tw_ch((size_t)K * 2 * std::max(cmp_h_len, 1), 0.0), tw_kf((size_t)K * 32, 0.0),
+      tw_ch((size_t)K * 2 * std::max(cmp_h_len, 1), 0.0),
+      tw_chi((size_t)K * 2 * std::max(cmp_h_len, 1), 0.0), tw_kf((size_t)K * 32, 0.0),
       tw_ki((size_t)K * 32, 0.0);
+  // the inverse's last-stage twiddle of each prime (slot 1 of its round-0 row)
+  std::vector<u64> w_last(K, 1);
   {
     std::vector<u64> pbr(n), pibr(n);
     for (int k = 0; k < K; ++k) {
@@ -559,6 +573,7 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
         pbr[i] = pw[brv(i, c->log2n)];
         pibr[i] = pwi[brv(i, c->log2n)];
       }
+      w_last[k] = pibr[1];
       // per-(stage, slot) constants omega_k^(+-brv_k(j)), omega_k = psi^(N/2^k)
       for (int kk = 1; kk < c->loge && kk < 5; ++kk) {
         const u64 om = powmod(psi, (u64)n >> kk, p), omi = invmod(om, p);
@@ -591,15 +606,21 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
         tw_h0[k] = bal(pbr[1], p);
         for (int hh = 0; hh < 2; ++hh) {
           for (int kk = 0; kk < h_r0; ++kk)
-            for (int j = 0; j < (1 << kk); ++j)
+            for (int j = 0; j < (1 << kk); ++j) {
               tw_h[((size_t)k * 2 + hh) * h_len + (1 << kk) + j] =
                   bal(pbr[(1 << kk) * (2 + hh) + j], p);
+              tw_hi[((size_t)k * 2 + hh) * h_len + (1 << kk) + j] =
+                  bal(pibr[(1 << kk) * (2 + hh) + j], p);
+            }
           size_t off = ((size_t)k * 2 + hh) * cmp_h_len;
           for (int r = 1; r < h_rounds; ++r) {
             const int ss = h_r0 + (r - 1) * h_loge;
             for (int u = 0; u < (1 << ss); ++u, off += 8)
-              for (int kk = 0; kk < h_loge; ++kk)
-                tw_ch[off + kk] = bal(pbr[(1 << (ss + kk)) * (2 + hh) + (u << kk)], p);
+              for (int kk = 0; kk < h_loge; ++kk) {
+                const int idx = (1 << (ss + kk)) * (2 + hh) + (u << kk);
+                tw_ch[off + kk] = bal(pbr[idx], p);
+                tw_chi[off + kk] = bal(pibr[idx], p);
+              }
           }
         }
       }
@@ -621,8 +642,9 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
     two24[i] = bal(t24, m);
     two48[i] = bal(mulmod(t24, t24, m), m);
   }
-  std::vector<double> q_hat_inv(L), Q_b(LB), t_qhinv(L), t_q(L),
-      c1(LB), b_hat_inv(LB), B_q(L), P_inv_q(L), NP_inv_q(L),
+  // t_qhinv, t_q, c1: a second row times the inverse's last-stage twiddle
+  std::vector<double> q_hat_inv(L), Q_b(LB), t_qhinv(2 * L), t_q(2 * L),
+      c1(2 * LB), b_hat_inv(LB), B_q(L), P_inv_q(L), NP_inv_q(L),
       delta_q(L), mrc_inv((size_t)L * L, 0.0), mrc_half(L);
   u64 Qmodt = 1;
   for (u64 x : qv) Qmodt = mulmod(Qmodt, x % c->t, c->t);
@@ -632,8 +654,11 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
     q_hat_inv[i] = bal(qhi, qi);
     // inverse transforms return N times the coefficients: fold N^-1 here
     const u64 ninv_q = invmod((u64)n % qi, qi);
-    t_qhinv[i] = bal(mulmod(mulmod(c->t % qi, qhi, qi), ninv_q, qi), qi);
-    t_q[i] = bal(mulmod(c->t % qi, ninv_q, qi), qi);
+    const u64 tqh = mulmod(mulmod(c->t % qi, qhi, qi), ninv_q, qi), tq = mulmod(c->t % qi, ninv_q, qi);
+    t_qhinv[i] = bal(tqh, qi);
+    t_q[i] = bal(tq, qi);
+    t_qhinv[L + i] = bal(mulmod(tqh, w_last[i], qi), qi);
+    t_q[L + i] = bal(mulmod(tq, w_last[i], qi), qi);
     B_q[i] = bal(prod_mod(bv, -1, qi), qi);
     P_inv_q[i] = bal(invmod(pr->P % qi, qi), qi);
     NP_inv_q[i] = bal(mulmod(invmod(pr->P % qi, qi), ninv_q, qi), qi);
@@ -648,8 +673,10 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
     Q_b[k] = bal(Qb, bk);
     const u64 bhi = invmod(prod_mod(bv, k, bk), bk);
     b_hat_inv[k] = bal(bhi, bk);
-    c1[k] = bal(mulmod(mulmod(mulmod(c->t % bk, invmod(Qb, bk), bk), bhi, bk),
-                       invmod((u64)n % bk, bk), bk), bk);
+    const u64 c1k = mulmod(mulmod(mulmod(c->t % bk, invmod(Qb, bk), bk), bhi, bk),
+                           invmod((u64)n % bk, bk), bk);
+    c1[k] = bal(c1k, bk);
+    c1[LB + k] = bal(mulmod(c1k, w_last[L + k], bk), bk);
     for (int i = 0; i < L; ++i) {
       split(&q_hat_b_sp[((size_t)k * L + i) * 2], prod_mod(qv, i, bk), bk);
       split(&c2_sp[((size_t)k * L + i) * 2], mulmod(invmod(qv[i] % bk, bk), bhi, bk), bk);
@@ -682,7 +709,8 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
       {&tw_h0, &c->tb.tw_half0},  {&tw_cf, &c->tb.tw_cmp_f},  {&tw_ci, &c->tb.tw_cmp_i},
       {&tw_ch, &c->tb.tw_cmp_h},  {&tw_kf, &c->tb.tw_cst_f},  {&tw_ki, &c->tb.tw_cst_i},
       {&q_hat_b_sp, &c->tb.q_hat_b_sp}, {&c2_sp, &c->tb.c2_sp}, {&b_hat_q_sp, &c->tb.b_hat_q_sp},
-      {&two24, &c->tb.two24},     {&two48, &c->tb.two48}};
+      {&two24, &c->tb.two24},     {&two48, &c->tb.two48},
+      {&tw_hi, &c->tb.tw_half_inv}, {&tw_chi, &c->tb.tw_cmp_hi}};
   size_t total = 0;
   std::vector<size_t> offs;
   for (auto& pp : parts) {
@@ -730,6 +758,7 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
   if (!h_len) {
     c->tb.tw_half = nullptr;
     c->tb.tw_half0 = nullptr;
+    c->tb.tw_half_inv = nullptr;
   }
   c->tb.margin = reinterpret_cast<unsigned long long*>(base + off_counters);
   c->tb.fault = c->tb.margin + 1;

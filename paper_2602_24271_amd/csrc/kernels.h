@@ -35,15 +35,21 @@ struct Tables {
   const double* tw_half;     // [K][2][tw_half_len] round-0 twiddles of each half's sub-transform
   const double* tw_half0;    // [K] psi^(2^14), the stage-0 twiddle
   int tw_half_len;
+  // the same for the half-limb inverse sub-transforms (inverse twiddles)
+  const double* tw_half_inv; // [K][2][tw_half_len]
+  const double* tw_cmp_hi;   // [K][2][tw_cmp_h_len]
   // centred lift Q -> B
   const double* q_hat_inv;   // [L]      [(Q/q_i)^-1]_{q_i}
   const double* Q_b;         // [LB]     [Q]_{b_k}
   // scale and round, then B -> Q
   // (the scale-and-round reads inverse-transform output, which carries a
   // factor N: its constants include N^-1)
-  const double* t_qhinv;     // [L]      [t (Q/q_i)^-1 N^-1]_{q_i}
-  const double* t_q;         // [L]      [t N^-1]_{q_i}
-  const double* c1;          // [LB]     [t Q^-1 (B/b_k)^-1 N^-1]_{b_k}
+  // t_qhinv, t_q and c1 hold a second row: the same constants times w,
+  // the 2^15-point inverse's last-stage twiddle of the prime (for the upper
+  // coefficients after the split inverse)
+  const double* t_qhinv;     // [2][L]   [t (Q/q_i)^-1 N^-1]_{q_i}
+  const double* t_q;         // [2][L]   [t N^-1]_{q_i}
+  const double* c1;          // [2][LB]  [t Q^-1 (B/b_k)^-1 N^-1]_{b_k}
   const double* b_hat_inv;   // [LB]     [(B/b_k)^-1]_{b_k}
   const double* B_q;         // [L]      [B]_{q_i}
   // the three base-conversion matrices, each balanced entry M split for
@@ -83,6 +89,10 @@ struct NttJob {
   size_t src_ct_stride;      // doubles between ciphertexts in src
   int digits;                // L (digits per ciphertext)
   int split = 1;             // 2^15-point forward: two workgroups per limb
+  // 2^15-point inverse (directions 1 and 3): two workgroups per limb that
+  // stop before the last stage, which the consumer (scale-and-round, or
+  // mod-down) applies as it loads; see k_ntt_inv_half for the layouts
+  int split_inv = 0;
 };
 
 // run_ntt directions: 0 forward in place, 1 inverse in place, 2 forward of
@@ -100,6 +110,9 @@ struct Dims {
   // launch shape (tunable; results do not depend on it)
   int block = 256;     // threads per workgroup of lift, scale and mod-down
   int ks_chunk = 16;   // ciphertexts per pass over the key in k_ks_mac
+  // scale-and-round / mod-down inputs come from the split inverse (2^15
+  // points): the last inverse stage is still to be applied on load
+  int fused = 0;
 };
 
 hipError_t run_lift(const Dims& d, double* ext, const Tables& tb, hipStream_t st);

@@ -101,4 +101,13 @@ __device__ __forceinline__ const double* opaque_row(const double* p, int off) {
 }
 __device__ __forceinline__ int cldi(const int* p, int i) { return ((const_iptr)p)[i]; }
 
+// An index the compiler cannot see through (inline asm on a scalar
+// register): the scalar loads of an unrolled loop iteration indexed by it
+// are neither hoisted above that point nor merged with other iterations'
+// into wide loads whose values would be held (and spilled) across the loop.
+__device__ __forceinline__ int opaque_idx(int i) {
+  asm volatile("" : "+s"(i));
+  return i;
+}
+
 }  // namespace nshe

@@ -675,6 +675,91 @@ k_ntt_fwd_half(NttJob job, Tables tb) {
   for (int e = 0; e < S::E; ++e) buf_store(x[e], rd, so, e * 1024 * 8);
 }
 
+// Inverse of a 2^15-point limb by two workgroups of 512 threads that stop
+// before the last Gentleman-Sande stage.  Every stage but the last pairs
+// indices with the same top bit h, so half h (standard indices h 2^14 + i')
+// is an independent 2^14-point inverse with the full transform's inverse
+// twiddles for that half (the mirror of k_ntt_fwd_half): 68 KB of LDS,
+// two workgroups per CU.  The last stage, X + Y and (X - Y) w with
+// w = the full inverse's round-0 twiddle at slot 1, couples the halves and
+// is left to the consumer, which loads X = U[i'] and Y = V[i'] (U, V: the
+// two halves' outputs, reduced to balanced residues).  Input: internal
+// order, element e of thread tid at e 1024 + h 512 + tid.  Output (i' =
+// 512 e + tid):
+//   NTT_INPLACE (the key-switch sum, read by the mod-down): in place, at
+//     the positions read, so U[i'] is at (i' / 512) 1024 + (i' mod 512) and
+//     V[i'] 512 further;
+//   INV_TENSOR, INV_TENSOR2 (read by the scale-and-round): U[i'] at i',
+//     V[i'] at 2^14 + i' (the natural positions of the two coefficients the
+//     last stage produces from them).
+template <int MODE>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
+k_ntt_inv_half(NttJob job, Tables tb) {
+  using S = NttShape<14>;
+  constexpr int NF = 1 << 15;
+  __shared__ uint32_t lds[S::LDS_WORDS];
+  const int item2 = xcd_item(job.count * 2);
+  if (item2 >= job.count * 2) return;
+  const int h = item2 & 1;
+  const int item = item2 >> 1;
+  const int limb = item / job.npoly;
+  const int poly = item - limb * job.npoly;
+  const int prime = cldi(job.limb_prime, limb);
+  const double p = cld(tb.p, prime), pinv = cld(tb.pinv, prime);
+  const TwSrc tw{tb.tw_half_inv + ((size_t)prime * 2 + h) * tb.tw_half_len,
+                 tb.tw_cmp_hi + ((size_t)prime * 2 + h) * tb.tw_cmp_h_len,
+                 tb.tw_cst_i + (size_t)prime * 32};
+  const size_t off = (size_t)poly * job.poly_stride + (size_t)limb * NF;
+  const auto rd = make_rsrc(job.base + off, NF * 8);
+  const auto ro = make_rsrc((job.out ? job.out : job.base) + off, NF * 8);
+  const int tid = threadIdx.x;
+  const unsigned vi = (h * S::T + tid) * 8;
+  double x[S::E];
+  if constexpr (MODE == INV_TENSOR || MODE == INV_TENSOR2) {
+    // as in k_ntt_inv (same element stride, 1024), from this half's slots
+    const int ct = poly / 3;
+    const int k = poly - ct * 3;
+    const size_t o0 = (size_t)ct * job.src_ct_stride + (size_t)limb * NF;
+    const size_t o1 = o0 + job.src_ct_stride / 2;
+    const auto ra0 = make_rsrc(job.src + o0, NF * 8);
+    const auto ra1 = make_rsrc(job.src + o1, NF * 8);
+    if constexpr (MODE == INV_TENSOR) {
+      if (k == 1)
+        tensor_square<15, true>(x, ra0, ra1, vi, p, pinv);
+      else
+        tensor_square<15, false>(x, k == 2 ? ra1 : ra0, ra1, vi, p, pinv);
+    } else {
+      const auto rb0 = make_rsrc(job.src_b + o0, NF * 8);
+      const auto rb1 = make_rsrc(job.src_b + o1, NF * 8);
+      if (k == 1)
+        tensor_product<15, true>(x, ra0, rb1, ra1, rb0, vi, p, pinv);
+      else if (k == 0)
+        tensor_product<15, false>(x, ra0, rb0, ra0, rb0, vi, p, pinv);
+      else
+        tensor_product<15, false>(x, ra1, rb1, ra1, rb1, vi, p, pinv);
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < S::E; ++e) x[e] = buf_load(rd, vi, e * 1024 * 8);
+  }
+  int g0 = 0;  // stages done before the current round
+#pragma unroll
+  for (int rr = 0; rr < S::ROUNDS; ++rr) {
+    const int r = S::ROUNDS - 1 - rr;
+    if (rr > 0) exchange<14>(x, r + 1, r, lds, rr > 1);
+    inv_round<14>(x, r, g0, tw, p, pinv);
+    g0 += S::stages(r);
+  }
+  if constexpr (MODE == NTT_INPLACE) {
+#pragma unroll
+    for (int e = 0; e < S::E; ++e) buf_store(x[e], ro, vi, e * 1024 * 8);
+  } else {
+    const unsigned so = (h * (NF >> 1) + tid) * 8;
+#pragma unroll
+    for (int e = 0; e < S::E; ++e) buf_store(x[e], ro, so, e * S::T * 8);
+  }
+}
+
 // Workgroups per XCD for a launch (grid = 8 x this); `halves` = 2 when each
 // limb is split over two workgroups.
 static int per_xcd(const NttJob& job, int dir, int halves) {
@@ -690,6 +775,16 @@ template <int LOGN>
 static hipError_t launch_ntt(const NttJob& job, const Tables& tb, int dir, hipStream_t st) {
   using S = NttShape<LOGN>;
   if constexpr (LOGN == 15) {
+    if ((dir == 1 || dir == 3) && job.split_inv && tb.tw_half_inv) {
+      dim3 grid(per_xcd(job, dir, 2) * 8), block(512);
+      if (dir == 1)
+        hipLaunchKernelGGL((k_ntt_inv_half<NTT_INPLACE>), grid, block, 0, st, job, tb);
+      else if (job.src_b == nullptr)
+        hipLaunchKernelGGL((k_ntt_inv_half<INV_TENSOR>), grid, block, 0, st, job, tb);
+      else
+        hipLaunchKernelGGL((k_ntt_inv_half<INV_TENSOR2>), grid, block, 0, st, job, tb);
+      return hipGetLastError();
+    }
     if (((dir == 0 && job.out && job.out != job.base) || dir == 2) && tb.tw_half && job.split) {
       dim3 grid(per_xcd(job, dir, 2) * 8), block(512);
       if (dir == 0)

@@ -164,32 +164,122 @@ __global__ void __launch_bounds__(256) k_lift(int n, size_t n_poly, double* ext,
   }
 }
 
+// ------------------------------------------------- inverse-transform output ---
+
+// Where a per-coefficient kernel reads coefficient c of a limb written by an
+// inverse transform.  Plain: at c (byte offset v).  After the split inverse
+// of a 2^15-point limb (FUSED) the coefficient is the inverse's last stage
+// applied to the two half outputs U and V of its pair: U + V for the lower
+// half of the coefficients, (U - V) w for the upper (hi), w = the full
+// inverse's last-stage twiddle of the limb's prime.  Every such value is
+// only ever multiplied by a constant, so w is folded into that constant
+// (the "hi" tables) and the load returns U + V or U - V (|.| <= p + 8, as
+// |U|, |V| <= p/2 + 4).  Lanes l and l + 32 of a wave hold the two
+// coefficients of a pair, each loading its own position (U's or V's) and
+// taking the other value from its partner lane, so every value is read once.
+struct CoefSrc {
+  unsigned v;      // this lane's position (bytes)
+  unsigned vu;     // the pair's U and V positions, for loads in divergent
+  unsigned vv;     // code (coef_load_both)
+  double sg;       // -1 upper, +1 lower
+  bool hi;
+};
+
+// The value of lane l xor 32: v_permlane32_swap exchanges the upper half
+// of one register's lanes with the lower half of another's (a VALU
+// operation, no LDS round trip); swapping a register with itself leaves the
+// partner's value in the first result for the upper lanes and in the second
+// for the lower ones.
+__device__ __forceinline__ double pair_swap(double x, bool upper) {
+  const unsigned long long b = __double_as_longlong(x);
+  const unsigned lo = (unsigned)b, hi = (unsigned)(b >> 32);
+  const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  const unsigned plo = upper ? l[0] : l[1], phi = upper ? h[0] : h[1];
+  return __longlong_as_double(((unsigned long long)phi << 32) | plo);
+}
+
+template <bool FUSED>
+__device__ __forceinline__ double coef_load(__amdgpu_buffer_rsrc_t rs, const CoefSrc& s,
+                                            unsigned soff) {
+  const double x = buf_load(rs, s.v, soff);
+  if constexpr (!FUSED) {
+    return x;
+  } else {
+    return __builtin_fma(s.sg, x, pair_swap(x, s.hi));   // lower y + x, upper y - x
+  }
+}
+
+// The same value without the partner lane (any lane may be inactive).
+template <bool FUSED>
+__device__ __forceinline__ double coef_load_both(__amdgpu_buffer_rsrc_t rs, const CoefSrc& s,
+                                                 unsigned soff) {
+  if constexpr (!FUSED) {
+    return buf_load(rs, s.v, soff);
+  } else {
+    return __builtin_fma(s.sg, buf_load(rs, s.vv, soff), buf_load(rs, s.vu, soff));
+  }
+}
+
+// The constant a coefficient of this lane is multiplied by: entry i of a
+// [2][count] table (lower, then upper = lower times w).  FUSED lanes differ
+// in the half they need, so they read it per lane (a vector load that hits
+// the cache) rather than select between two scalar constants, which would
+// keep both halves' constants in scalar registers.
+template <bool FUSED>
+__device__ __forceinline__ double coef_const(const CoefSrc& s, const double* tab, int i,
+                                             int count) {
+  if constexpr (!FUSED) return cld(tab, i);
+  else return tab[(s.hi ? count : 0) + i];
+}
+
 // ----------------------------------------------------------------- scale ---
 
 // dt: [n_poly][L+LB][N] coefficient domain (balanced).  Writes
 // [round(t d / Q)]_Q into limbs 0..L-1 of the same poly.
-template <int L>
+// FUSED: dt holds the split inverse's half outputs (see coef_load); each
+// wave takes 32 coefficient pairs (c, c + N/2), lanes 0-31 the lower
+// coefficients and 32-63 the upper, and writes its outputs in place at the
+// positions it alone reads.
+template <int L, bool FUSED>
 __global__ void __launch_bounds__(256) k_scale(int n, size_t n_poly, double* dt, Tables tb) {
   constexpr int LB = L + 1;
   const PolyBlock pb = poly_block(n, n_poly);
   if (!pb.ok) return;
   const auto rs = make_rsrc(dt + pb.pc * (size_t)(L + LB) * n, (unsigned)((L + LB) * n * 8));
-  const unsigned vo = (unsigned)pb.c * 8;
+  CoefSrc cs{(unsigned)pb.c * 8, 0u, 0u, 1.0, false};
+  if constexpr (FUSED) {
+    const int t = (int)threadIdx.x, lane = t & 63;
+    const int cp = ((pb.c - t) >> 1) + (t >> 6) * 32 + (lane & 31);
+    cs.hi = lane >= 32;
+    cs.vu = (unsigned)cp * 8;
+    cs.vv = (unsigned)(cp + (n >> 1)) * 8;
+    cs.v = cs.hi ? cs.vv : cs.vu;
+    cs.sg = cs.hi ? -1.0 : 1.0;
+  }
+  const unsigned vo = cs.v;
   const unsigned ls = (unsigned)n * 8;   // bytes per limb
   const bool third = pb.pc % 3 == 2;
   double y[L];
   double S = 0.0;
 #pragma unroll
   for (int i = 0; i < L; ++i) {
-    y[i] = mul_bal(buf_load(rs, vo, i * ls), cld(tb.t_qhinv, i), cld(tb.p, i), cld(tb.pinv, i));
-    S += y[i] * cld(tb.recip, i);
+    const int iq = opaque_idx(i);
+    const double p = cld(tb.p, iq), pinv = cld(tb.pinv, iq);
+    y[i] = mul_bal(coef_load<FUSED>(rs, cs, i * ls),
+                   coef_const<FUSED>(cs, tb.t_qhinv, iq, L), p, pinv);
+    S += y[i] * cld(tb.recip, iq);
   }
   double v = __builtin_rint(S);
   if (__builtin_fabs(S - v) > 0.5 - LIFT_EPS) {
     double r[L];
 #pragma unroll
-    for (int i = 0; i < L; ++i)
-      r[i] = to_canonical(mul_bal(buf_load(rs, vo, i * ls), cld(tb.t_q, i), cld(tb.p, i), cld(tb.pinv, i)), cld(tb.p, i));
+    for (int i = 0; i < L; ++i) {
+      const double p = cld(tb.p, i), pinv = cld(tb.pinv, i);
+      r[i] = to_canonical(mul_bal(coef_load_both<FUSED>(rs, cs, i * ls),
+                                  coef_const<FUSED>(cs, tb.t_q, i, L), p, pinv),
+                          p);
+    }
     v = __builtin_floor(S) + (mrc_greater_than_half<L>(r, tb.p, tb.pinv, tb.mrc_inv, tb.mrc_half) ? 1.0 : 0.0);
     atomicAdd(tb.margin, 1ull);
   }
@@ -209,14 +299,16 @@ __global__ void __launch_bounds__(256) k_scale(int n, size_t n_poly, double* dt,
     for (int i = 0; i < L; ++i) split24(y[i], yh[i], yl[i]);
 #pragma unroll
     for (int k = 0; k < LB; ++k) {
-      const double b = cld(tb.p, L + k), binv = cld(tb.pinv, L + k);
+      const int kq = opaque_idx(k), pk = L + kq;
+      const double b = cld(tb.p, pk), binv = cld(tb.pinv, pk);
       const double* sp = opaque_row(tb.c2_sp, k * L * 2);
-      const double acc = mul_lazy(buf_load(rs, vo, (L + k) * ls), cld(tb.c1, k), b, binv) +
-                         v * cld(tb.b_hat_inv, k) -
-                         conv_row<L>(yh, yl, sp, cld(tb.two24, L + k), cld(tb.two48, L + k), b, binv);
+      const double acc = mul_lazy(coef_load<FUSED>(rs, cs, (L + k) * ls),
+                                  coef_const<FUSED>(cs, tb.c1, kq, LB), b, binv) +
+                         v * cld(tb.b_hat_inv, kq) -
+                         conv_row<L>(yh, yl, sp, cld(tb.two24, pk), cld(tb.two48, pk), b, binv);
       const double w = reduce_bal(acc, b, binv);
       wp[k * bs] = w;
-      S2 += w * cld(tb.recip, L + k);
+      S2 += w * cld(tb.recip, pk);
     }
   }
   const double v2 = __builtin_rint(S2);
@@ -226,10 +318,11 @@ __global__ void __launch_bounds__(256) k_scale(int n, size_t n_poly, double* dt,
   for (int k = 0; k < LB; ++k) split24(wp[k * bs], wh[k], wl[k]);
 #pragma unroll
   for (int i = 0; i < L; ++i) {
-    const double q = cld(tb.p, i), qinv = cld(tb.pinv, i);
+    const int iq = opaque_idx(i);
+    const double q = cld(tb.p, iq), qinv = cld(tb.pinv, iq);
     const double* sp = opaque_row(tb.b_hat_q_sp, i * LB * 2);
-    const double acc = conv_row<LB>(wh, wl, sp, cld(tb.two24, i), cld(tb.two48, i), q, qinv) -
-                       v2 * cld(tb.B_q, i);
+    const double acc = conv_row<LB>(wh, wl, sp, cld(tb.two24, iq), cld(tb.two48, iq), q, qinv) -
+                       v2 * cld(tb.B_q, iq);
     const double r = reduce_bal(acc, q, qinv);
     // the third component is only read as relinearization digits, which
     // are its canonical residues
@@ -298,31 +391,59 @@ __global__ void __launch_bounds__(256) k_ks_mac(int n, int n_ct, const double* d
 // new ct (into ext limbs 0..L-1) = e_b + (acc_b - [acc_b]_P) * P^-1, where
 // [acc_b]_P is the balanced (= centred) residue of the P limb.  Since
 // mul_lazy(aP, .) needs |aP| < 2p only, P may exceed q_i (both < 2^49).
-template <int L>
+// FUSED: acc holds the split inverse's in-place half outputs of a 2^15-point
+// limb (U of pair c at (c / 512) 1024 + c mod 512, V 512 further; see
+// k_ntt_inv_half) and a thread produces both coefficients c and c + N/2.
+template <int L, bool FUSED>
 __global__ void __launch_bounds__(256) k_moddown(int n, int n_ct, const double* __restrict__ acc,
                                                  const double* __restrict__ dt,
                                                  double* __restrict__ ext, Tables tb) {
   constexpr int K = L + 1;
   constexpr int W = 2 * L + 1;
+  const int per = FUSED ? n >> 1 : n;      // threads per (ct, component)
   const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= (size_t)n_ct * 2 * n) return;
-  const size_t cb = gid / n;               // ct * 2 + b
-  const int c = (int)(gid - cb * n);
+  if (gid >= (size_t)n_ct * 2 * per) return;
+  const size_t cb = gid / per;             // ct * 2 + b
+  const int c = (int)(gid - cb * per);
   const size_t ct = cb >> 1;
   const int b = (int)(cb & 1);
-  const double* a = acc + cb * (size_t)K * n + c;
-  // acc is inverse-transform output (N times the sum): the centred residue
-  // mod P is [N^-1 acc_P]_P
   const int ip = 2 * L + 1;
-  const double aP = mul_bal(a[(size_t)L * n], cld(tb.ninv, ip), cld(tb.p, ip), cld(tb.pinv, ip));
+  const double pP = cld(tb.p, ip), pPinv = cld(tb.pinv, ip);
   const double* e = dt + ((ct * 3 + b) * (size_t)W) * n + c;
   double* o = ext + cb * (size_t)W * n + c;
+  if constexpr (!FUSED) {
+    const double* a = acc + cb * (size_t)K * n + c;
+    // acc is inverse-transform output (N times the sum): the centred
+    // residue mod P is [N^-1 acc_P]_P
+    const double aP = mul_bal(a[(size_t)L * n], cld(tb.ninv, ip), pP, pPinv);
 #pragma unroll
-  for (int i = 0; i < L; ++i) {
-    const double q = cld(tb.p, i), qinv = cld(tb.pinv, i);
-    const double r = mul_lazy(a[(size_t)i * n], cld(tb.NP_inv_q, i), q, qinv) -
-                     mul_lazy(aP, cld(tb.P_inv_q, i), q, qinv);
-    o[(size_t)i * n] = reduce_bal(e[(size_t)i * n] + r, q, qinv);
+    for (int i = 0; i < L; ++i) {
+      const double q = cld(tb.p, i), qinv = cld(tb.pinv, i);
+      const double r = mul_lazy(a[(size_t)i * n], cld(tb.NP_inv_q, i), q, qinv) -
+                       mul_lazy(aP, cld(tb.P_inv_q, i), q, qinv);
+      o[(size_t)i * n] = reduce_bal(e[(size_t)i * n] + r, q, qinv);
+    }
+  } else {
+    const int ht = n >> 6;                 // 512: a half transform's threads
+    const double* a = acc + cb * (size_t)K * n + (size_t)(c / ht) * 2 * ht + (c % ht);
+    const size_t hn = (size_t)(n >> 1);
+    const double uP = a[(size_t)L * n], vP = a[(size_t)L * n + ht];
+    const double ninvP = cld(tb.ninv, ip);
+    const double aP_lo = mul_bal(uP + vP, ninvP, pP, pPinv);
+    const double aP_hi =
+        mul_bal(mul_lazy(uP - vP, cld(tb.tw_inv, ip * tb.tw_len + 1), pP, pPinv), ninvP, pP, pPinv);
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+      const double q = cld(tb.p, i), qinv = cld(tb.pinv, i);
+      const double u = a[(size_t)i * n], v = a[(size_t)i * n + ht];
+      const double lo = u + v;
+      const double hi = mul_lazy(u - v, cld(tb.tw_inv, i * tb.tw_len + 1), q, qinv);
+      const double npq = cld(tb.NP_inv_q, i), pq = cld(tb.P_inv_q, i);
+      const double r_lo = mul_lazy(lo, npq, q, qinv) - mul_lazy(aP_lo, pq, q, qinv);
+      const double r_hi = mul_lazy(hi, npq, q, qinv) - mul_lazy(aP_hi, pq, q, qinv);
+      o[(size_t)i * n] = reduce_bal(e[(size_t)i * n] + r_lo, q, qinv);
+      o[(size_t)i * n + hn] = reduce_bal(e[(size_t)i * n + hn] + r_hi, q, qinv);
+    }
   }
 }
 
@@ -687,8 +808,14 @@ hipError_t run_scale(const Dims& d, double* dt, const Tables& tb, hipStream_t st
   const size_t np = (size_t)d.n_ct * 3;
   switch (d.L) {
 #define C_(L_) \
-  case L_: hipLaunchKernelGGL(k_scale<L_>, poly_grid(np, d.n, d.block), dim3(d.block), \
-                              (size_t)(L_ + 1) * d.block * 8, st, d.n, np, dt, tb); break;
+  case L_:                                                                                 \
+    if (d.fused)                                                                           \
+      hipLaunchKernelGGL((k_scale<L_, true>), poly_grid(np, d.n, d.block), dim3(d.block),  \
+                         (size_t)(L_ + 1) * d.block * 8, st, d.n, np, dt, tb);             \
+    else                                                                                   \
+      hipLaunchKernelGGL((k_scale<L_, false>), poly_grid(np, d.n, d.block), dim3(d.block), \
+                         (size_t)(L_ + 1) * d.block * 8, st, d.n, np, dt, tb);             \
+    break;
     NSHE_L_CASES(C_)
 #undef C_
     default: return hipErrorInvalidValue;
@@ -720,10 +847,17 @@ hipError_t run_ks_mac(const Dims& d, const double* dig, const double* evk, doubl
 
 hipError_t run_moddown(const Dims& d, const double* acc, const double* dt, double* ext,
                        const Tables& tb, hipStream_t st) {
-  const size_t total = (size_t)d.n_ct * 2 * d.n;
+  const size_t total = (size_t)d.n_ct * 2 * (d.fused ? d.n / 2 : d.n);
   switch (d.L) {
-#define C_(L_) \
-  case L_: hipLaunchKernelGGL(k_moddown<L_>, grid_for(total, d.block), dim3(d.block), 0, st, d.n, d.n_ct, acc, dt, ext, tb); break;
+#define C_(L_)                                                                              \
+  case L_:                                                                                  \
+    if (d.fused)                                                                            \
+      hipLaunchKernelGGL((k_moddown<L_, true>), grid_for(total, d.block), dim3(d.block), 0, \
+                         st, d.n, d.n_ct, acc, dt, ext, tb);                                \
+    else                                                                                    \
+      hipLaunchKernelGGL((k_moddown<L_, false>), grid_for(total, d.block), dim3(d.block), 0, \
+                         st, d.n, d.n_ct, acc, dt, ext, tb);                                \
+    break;
     NSHE_L_CASES(C_)
 #undef C_
     default: return hipErrorInvalidValue;
