@@ -224,10 +224,12 @@ static Dims dims(const nshe_ctx* c, int n_ct) {
 // ------------------------------------------------------------ profiling
 
 enum Kind { K_SUB, K_LIFT, K_NTT_FWD, K_NTT_INV_TENSOR, K_NTT_INV, K_SCALE, K_NTT_DIGIT,
-            K_KS_MAC, K_MODDOWN, K_CONVERT, K_AUTOMORPH, K_ADD, K_LINCOMB, K_COUNT };
+            K_KS_MAC, K_MODDOWN, K_CONVERT, K_AUTOMORPH, K_ADD, K_LINCOMB, K_MODDOWN_LIFT,
+            K_COUNT };
 static const char* kKindName[K_COUNT] = {"sub",   "lift",      "ntt_fwd", "ntt_inv_tensor",
                                          "ntt_inv", "scale", "ntt_digit", "ks_mac",
-                                         "moddown", "convert", "automorph", "add", "lincomb"};
+                                         "moddown", "convert", "automorph", "add", "lincomb",
+                                         "moddown_lift"};
 
 static hipEvent_t take_event(nshe_ctx* c) {
   if (!c->pool.empty()) {
@@ -346,9 +348,11 @@ static int ntt_job_ks(nshe_ctx* c, double* base, double* out, int npoly, int dir
 
 // Lift the ciphertexts held in ext (limbs 0..L-1) and transform all limbs
 // into fx.
-static int prepare_operand(nshe_ctx* c, double* ext, double* fx, int n_ct, hipStream_t st) {
+// (lifted: the mod-down that wrote ext already lifted it)
+static int prepare_operand(nshe_ctx* c, double* ext, double* fx, int n_ct, hipStream_t st,
+                           bool lifted = false) {
   Dims d = dims(c, n_ct);
-  {
+  if (!lifted) {
     Prof pf(c, K_LIFT, st, 2.0 * n_ct * c->n);
     HIPCHK(run_lift(d, ext, c->tb, st));
   }
@@ -385,8 +389,10 @@ static int tensor_scale(nshe_ctx* c, const Ws& w, const double* fx_b, int n_ct, 
 // Key-switch the third component in dt (limbs 0..L-1, canonical) with
 // `key` (the relinearization key unless given) and add the result to the
 // first two: (c0 + k0, c1 + k1) into `out` (ext unless given), limbs 0..L-1.
+// lift_out: also lift the result (limbs L..2L of out), for a squaring that
+// follows at once (only with the split inverse).
 static int relin(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st,
-                 const double* key = nullptr, double* out = nullptr) {
+                 const double* key = nullptr, double* out = nullptr, bool lift_out = false) {
   if (!key) key = c->evk;
   if (!out) out = w.ext;
   Dims d = dims(c, n_ct);
@@ -412,20 +418,27 @@ static int relin(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st,
   }
   int rc = ntt_job_ks(c, w.acc, nullptr, n_ct * 2, 1, st, true);
   if (rc) return rc;
-  {
+  if (lift_out && d.fused) {
+    Prof pf(c, K_MODDOWN_LIFT, st, 2.0 * n_ct * c->n);
+    HIPCHK(run_moddown_lift(d, w.acc, w.dt, out, c->tb, st));
+  } else {
     Prof pf(c, K_MODDOWN, st, 2.0 * n_ct * c->n);
     HIPCHK(run_moddown(d, w.acc, w.dt, out, c->tb, st));
   }
   return NSHE_OK;
 }
 
-// One squaring level on the ciphertexts in ext.
-static int square_level(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st) {
-  int rc = prepare_operand(c, w.ext, w.fx, n_ct, st);
+// One squaring level on the ciphertexts in ext.  In a chain of squarings
+// (with the split inverse) each level but the last also lifts its result
+// for the next (lift_out), which then skips its own lift (lifted).
+static int square_level(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st,
+                        bool lifted = false, bool lift_out = false) {
+  const bool chain = split_inverse(c);
+  int rc = prepare_operand(c, w.ext, w.fx, n_ct, st, lifted && chain);
   if (rc) return rc;
   rc = tensor_scale(c, w, nullptr, n_ct, st);
   if (rc) return rc;
-  return relin(c, w, n_ct, st);
+  return relin(c, w, n_ct, st, nullptr, nullptr, lift_out && chain);
 }
 
 static int check_ctx(const nshe_ctx* c) {
@@ -644,8 +657,13 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
   }
   // t_qhinv, t_q, c1: a second row times the inverse's last-stage twiddle
   std::vector<double> q_hat_inv(L), Q_b(LB), t_qhinv(2 * L), t_q(2 * L),
-      c1(2 * LB), b_hat_inv(LB), B_q(L), P_inv_q(L), NP_inv_q(L),
+      c1(2 * LB), b_hat_inv(LB), B_q(L), P_inv_q(L), NP_inv_q(2 * L), ninv_P(2),
       delta_q(L), mrc_inv((size_t)L * L, 0.0), mrc_half(L);
+  {
+    const u64 Pp = pr->P, nP = invmod((u64)n % Pp, Pp);
+    ninv_P[0] = bal(nP, Pp);
+    ninv_P[1] = bal(mulmod(nP, w_last[2 * L + 1], Pp), Pp);
+  }
   u64 Qmodt = 1;
   for (u64 x : qv) Qmodt = mulmod(Qmodt, x % c->t, c->t);
   for (int i = 0; i < L; ++i) {
@@ -661,7 +679,9 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
     t_q[L + i] = bal(mulmod(tq, w_last[i], qi), qi);
     B_q[i] = bal(prod_mod(bv, -1, qi), qi);
     P_inv_q[i] = bal(invmod(pr->P % qi, qi), qi);
-    NP_inv_q[i] = bal(mulmod(invmod(pr->P % qi, qi), ninv_q, qi), qi);
+    const u64 npq = mulmod(invmod(pr->P % qi, qi), ninv_q, qi);
+    NP_inv_q[i] = bal(npq, qi);
+    NP_inv_q[L + i] = bal(mulmod(npq, w_last[i], qi), qi);
     // Delta = (Q - (Q mod t)) / t = -(Q mod t) * t^-1 (mod q_i)
     delta_q[i] = bal((qi - mulmod(Qmodt, invmod(c->t % qi, qi), qi)) % qi, qi);
     for (int k = 0; k < LB; ++k) split(&b_hat_q_sp[((size_t)i * LB + k) * 2], prod_mod(bv, k, qi), qi);
@@ -704,6 +724,7 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
       {&t_qhinv, &c->tb.t_qhinv}, {&t_q, &c->tb.t_q},         {&c1, &c->tb.c1},
       {&b_hat_inv, &c->tb.b_hat_inv},
       {&B_q, &c->tb.B_q},         {&P_inv_q, &c->tb.P_inv_q}, {&NP_inv_q, &c->tb.NP_inv_q},
+      {&ninv_P, &c->tb.ninv_P},
       {&delta_q, &c->tb.delta_q},
       {&mrc_inv, &c->tb.mrc_inv}, {&mrc_half, &c->tb.mrc_half}, {&tw_h, &c->tb.tw_half},
       {&tw_h0, &c->tb.tw_half0},  {&tw_cf, &c->tb.tw_cmp_f},  {&tw_ci, &c->tb.tw_cmp_i},
@@ -1012,7 +1033,7 @@ int nshe_relinearize(nshe_ctx* c, const int64_t* in3, int64_t* out, int n_ct, vo
 // The EQ chain on ciphertexts already differenced into w.ext.
 static int eq_levels(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st) {
   for (int k = 0; k < c->squarings; ++k) {
-    int rc = square_level(c, w, n_ct, st);
+    int rc = square_level(c, w, n_ct, st, k > 0, k + 1 < c->squarings);
     if (rc) return rc;
   }
   return NSHE_OK;

@@ -62,7 +62,9 @@ struct Tables {
   const double* two48;       // [K]
   // key switching
   const double* P_inv_q;     // [L]      [P^-1]_{q_i}
-  const double* NP_inv_q;    // [L]      [N^-1 P^-1]_{q_i}
+  const double* NP_inv_q;    // [2][L]   [N^-1 P^-1]_{q_i}; second row times w_i
+  const double* ninv_P;      // [2]      [N^-1]_P, times w_P (w: the 2^15-point
+                             //          inverse's last-stage twiddle of the prime)
   const double* delta_q;     // [L]      [floor(Q/t)]_{q_i}
   // exact fallback of the Q lift: mixed-radix digits
   const double* mrc_inv;     // [L][L]   [q_j^-1]_{q_i}, canonical, row j
@@ -122,6 +124,10 @@ hipError_t run_ks_mac(const Dims& d, const double* dig, const double* evk, doubl
                       const Tables& tb, hipStream_t st);
 hipError_t run_moddown(const Dims& d, const double* acc, const double* dt, double* ext,
                        const Tables& tb, hipStream_t st);
+// mod-down of the split inverse's output followed by the lift of the result
+// (the next squaring's operand), one kernel; needs d.fused
+hipError_t run_moddown_lift(const Dims& d, const double* acc, const double* dt, double* ext,
+                            const Tables& tb, hipStream_t st);
 // conversions at the boundary
 hipError_t run_sub_to_ext(const Dims& d, const int64_t* x, const int64_t* y, int y_bcast,
                           double* ext, const Tables& tb, hipStream_t st);

@@ -447,6 +447,79 @@ __global__ void __launch_bounds__(256) k_moddown(int n, int n_ct, const double* 
   }
 }
 
+// The mod-down of the split inverse's output (k_moddown, FUSED) followed by
+// the lift of its result (k_lift): within the squaring chain the next level
+// lifts exactly what this level's mod-down writes, so one kernel saves
+// re-reading it.  One thread per coefficient of each (ct, b) polynomial
+// (blocks mapped like k_lift); lanes l and l + 32 of a wave hold the two
+// coefficients of a pair (c, c + N/2) and exchange the key-switch sum's half
+// outputs as the scale-and-round does, with the last inverse stage's
+// twiddle folded into the second rows of NP_inv_q and ninv_P.
+template <int L>
+__global__ void __launch_bounds__(256) k_moddown_lift(int n, size_t n_poly,
+                                                      const double* __restrict__ acc,
+                                                      const double* __restrict__ dt,
+                                                      double* __restrict__ ext, Tables tb) {
+  constexpr int K = L + 1;
+  constexpr int W = 2 * L + 1;
+  constexpr int LB = L + 1;
+  const PolyBlock pb = poly_block(n, n_poly);   // poly = ct * 2 + b
+  if (!pb.ok) return;
+  const int t = (int)threadIdx.x, lane = t & 63;
+  const int cp = ((pb.c - t) >> 1) + (t >> 6) * 32 + (lane & 31);
+  const bool hi = lane >= 32;
+  const double sg = hi ? -1.0 : 1.0;
+  const int ht = n >> 6;                         // 512: see k_ntt_inv_half
+  const unsigned pos = (unsigned)((cp / ht) * 2 * ht + cp % ht + (hi ? ht : 0)) * 8;
+  const unsigned vo = (unsigned)(cp + (hi ? n >> 1 : 0)) * 8;
+  const unsigned ls = (unsigned)n * 8;
+  const size_t cb = pb.pc, ct = cb >> 1;
+  const int b = (int)(cb & 1);
+  const auto ra = make_rsrc(acc + cb * (size_t)K * n, (unsigned)(K * n * 8));
+  const auto re = make_rsrc(dt + (ct * 3 + b) * (size_t)W * n, (unsigned)(L * n * 8));
+  const auto rs = make_rsrc(ext + cb * (size_t)W * n, (unsigned)(W * n * 8));
+  const int row = hi ? 1 : 0;
+  // centred [N^-1 acc_P]_P of this coefficient
+  const int ip = 2 * L + 1;
+  const double pP = cld(tb.p, ip), pPinv = cld(tb.pinv, ip);
+  const double xP = buf_load(ra, pos, L * ls);
+  const double aP = mul_bal(__builtin_fma(sg, xP, pair_swap(xP, hi)), tb.ninv_P[row], pP, pPinv);
+  double o[L], y[L];
+  double S = 0.0;
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    const int iq = opaque_idx(i);
+    const double q = cld(tb.p, iq), qinv = cld(tb.pinv, iq);
+    const double x = buf_load(ra, pos, i * ls);
+    const double r = mul_lazy(__builtin_fma(sg, x, pair_swap(x, hi)), tb.NP_inv_q[row * L + iq], q, qinv) -
+                     mul_lazy(aP, cld(tb.P_inv_q, iq), q, qinv);
+    o[i] = reduce_bal(buf_load(re, vo, i * ls) + r, q, qinv);
+    buf_store(o[i], rs, vo, i * ls);
+    y[i] = mul_bal(o[i], cld(tb.q_hat_inv, iq), q, qinv);
+    S += y[i] * cld(tb.recip, iq);
+  }
+  double v = __builtin_rint(S);
+  if (__builtin_fabs(S - v) > 0.5 - LIFT_EPS) {
+    double r[L];
+#pragma unroll
+    for (int i = 0; i < L; ++i) r[i] = to_canonical(o[i], cld(tb.p, i));
+    v = __builtin_floor(S) + (mrc_greater_than_half<L>(r, tb.p, tb.pinv, tb.mrc_inv, tb.mrc_half) ? 1.0 : 0.0);
+    atomicAdd(tb.margin, 1ull);
+  }
+  double yh[L], yl[L];
+#pragma unroll
+  for (int i = 0; i < L; ++i) split24(y[i], yh[i], yl[i]);
+#pragma unroll
+  for (int k = 0; k < LB; ++k) {
+    const int kq = opaque_idx(k), pk = L + kq;
+    const double bb = cld(tb.p, pk), binv = cld(tb.pinv, pk);
+    const double* sp = opaque_row(tb.q_hat_b_sp, k * L * 2);
+    const double a = conv_row<L>(yh, yl, sp, cld(tb.two24, pk), cld(tb.two48, pk), bb, binv) -
+                     v * cld(tb.Q_b, kq);
+    buf_store(reduce_bal(a, bb, binv), rs, vo, (L + k) * ls);
+  }
+}
+
 // ------------------------------------------------------ plaintext products ---
 
 // The basis plaintext of one slot: m_i = N^-1 zeta^-i mod t, zinv = zeta^-1
@@ -793,6 +866,23 @@ hipError_t run_lift(const Dims& d, double* ext, const Tables& tb, hipStream_t st
   switch (d.L) {
 #define C_(L_) \
   case L_: hipLaunchKernelGGL(k_lift<L_>, poly_grid(np, d.n, d.block), dim3(d.block), 0, st, d.n, np, ext, tb); break;
+    NSHE_L_CASES(C_)
+#undef C_
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t run_moddown_lift(const Dims& d, const double* acc, const double* dt, double* ext,
+                            const Tables& tb, hipStream_t st) {
+  if (!d.fused) return hipErrorInvalidValue;
+  const size_t np = (size_t)d.n_ct * 2;
+  switch (d.L) {
+#define C_(L_)                                                                               \
+  case L_:                                                                                   \
+    hipLaunchKernelGGL(k_moddown_lift<L_>, poly_grid(np, d.n, d.block), dim3(d.block), 0, st, \
+                       d.n, np, acc, dt, ext, tb);                                           \
+    break;
     NSHE_L_CASES(C_)
 #undef C_
     default: return hipErrorInvalidValue;
