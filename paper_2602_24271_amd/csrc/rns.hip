@@ -484,6 +484,9 @@ __global__ void __launch_bounds__(256) k_moddown_lift(int n, size_t n_poly,
   const double pP = cld(tb.p, ip), pPinv = cld(tb.pinv, ip);
   const double xP = buf_load(ra, pos, L * ls);
   const double aP = mul_bal(__builtin_fma(sg, xP, pair_swap(xP, hi)), tb.ninv_P[row], pP, pPinv);
+  // the new ciphertext's residues are stored only after every load: buffer
+  // stores between them would make each limb's loads wait for the previous
+  // limb's (the compiler cannot tell the buffers apart)
   double o[L], y[L];
   double S = 0.0;
 #pragma unroll
@@ -494,10 +497,11 @@ __global__ void __launch_bounds__(256) k_moddown_lift(int n, size_t n_poly,
     const double r = mul_lazy(__builtin_fma(sg, x, pair_swap(x, hi)), tb.NP_inv_q[row * L + iq], q, qinv) -
                      mul_lazy(aP, cld(tb.P_inv_q, iq), q, qinv);
     o[i] = reduce_bal(buf_load(re, vo, i * ls) + r, q, qinv);
-    buf_store(o[i], rs, vo, i * ls);
     y[i] = mul_bal(o[i], cld(tb.q_hat_inv, iq), q, qinv);
     S += y[i] * cld(tb.recip, iq);
   }
+#pragma unroll
+  for (int i = 0; i < L; ++i) buf_store(o[i], rs, vo, i * ls);
   double v = __builtin_rint(S);
   if (__builtin_fabs(S - v) > 0.5 - LIFT_EPS) {
     double r[L];
