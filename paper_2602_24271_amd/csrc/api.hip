@@ -548,7 +548,9 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
   std::vector<double> tw_f((size_t)K * c->tw_len, 0.0), tw_i((size_t)K * c->tw_len, 0.0);
   // Compact rows of rounds r >= 1: row u of round r holds, at slot k, the
   // first twiddle of the round's stage k, psi^brv(2^(s_r + k) + (u << k));
-  // rows of consecutive rounds follow each other (the device's layout).
+  // a round's 8 x 2^s_r entries are stored slot-major (slot k of row u at
+  // k 2^s_r + u, so a wave's load of one slot is contiguous), rounds one
+  // after the other (the device's layout).
   auto cmp_len_of = [](int rounds, int r0, int loge) {
     int len = 0;
     for (int r = 1; r < rounds; ++r) len += (1 << (r0 + (r - 1) * loge)) * 8;
@@ -605,12 +607,13 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
         size_t off = (size_t)k * cmp_len;
         for (int r = 1; r < c->rounds; ++r) {
           const int ss = c->r0 + (r - 1) * c->loge;
-          for (int u = 0; u < (1 << ss); ++u, off += 8)
+          for (int u = 0; u < (1 << ss); ++u)
             for (int kk = 0; kk < c->loge; ++kk) {
               const int idx = (1 << (ss + kk)) + (u << kk);
-              tw_cf[off + kk] = bal(pbr[idx], p);
-              tw_ci[off + kk] = bal(pibr[idx], p);
+              tw_cf[off + ((size_t)kk << ss) + u] = bal(pbr[idx], p);
+              tw_ci[off + ((size_t)kk << ss) + u] = bal(pibr[idx], p);
             }
+          off += (size_t)8 << ss;
         }
       }
       // half-limb sub-transforms: sub-stage s' of half h is the full
@@ -628,12 +631,13 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
           size_t off = ((size_t)k * 2 + hh) * cmp_h_len;
           for (int r = 1; r < h_rounds; ++r) {
             const int ss = h_r0 + (r - 1) * h_loge;
-            for (int u = 0; u < (1 << ss); ++u, off += 8)
+            for (int u = 0; u < (1 << ss); ++u)
               for (int kk = 0; kk < h_loge; ++kk) {
                 const int idx = (1 << (ss + kk)) * (2 + hh) + (u << kk);
-                tw_ch[off + kk] = bal(pbr[idx], p);
-                tw_chi[off + kk] = bal(pibr[idx], p);
+                tw_ch[off + ((size_t)kk << ss) + u] = bal(pbr[idx], p);
+                tw_chi[off + ((size_t)kk << ss) + u] = bal(pibr[idx], p);
               }
+            off += (size_t)8 << ss;
           }
         }
       }

@@ -23,8 +23,9 @@ struct Tables {
   const double* tw_inv;      // [K][tw_len]
   int tw_len;
   // rounds >= 1: per index row u the first twiddle of each stage (8 slots,
-  // stage k at slot k), rounds one after the other; the others are that
-  // one times a constant per (stage, slot) shared by all rows
+  // stage k at slot k; a round's rows stored slot-major, slot k of row u at
+  // k rows + u), rounds one after the other; the others are that one times
+  // a constant per (stage, slot) shared by all rows
   const double* tw_cmp_f;    // [K][tw_cmp_len]
   const double* tw_cmp_i;    // [K][tw_cmp_len]
   int tw_cmp_len;

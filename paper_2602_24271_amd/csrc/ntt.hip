@@ -242,8 +242,9 @@ constexpr bool fwd_schedule_ok(int pre) {
 // later round the twiddle of stage k, slot j for index row u is
 // W(k, j) = W(k, 0) omega_k^(+-brv_k(j)) (the bits of j, of u and of the
 // stage are disjoint in the bit-reversed exponent): the compact table keeps
-// W(k, 0) per row (8 slots, stage k at slot k; rounds r >= 1 one after the
-// other) and cst the per-(stage, slot) constants shared by all rows, so a
+// W(k, 0) per row (8 slots, stage k at slot k, stored slot-major within a
+// round; rounds r >= 1 one after the other) and cst the per-(stage, slot)
+// constants shared by all rows, so a
 // thread loads 5 twiddles per round instead of 31 and derives the rest
 // with one modular product each.
 struct TwSrc {
@@ -262,9 +263,12 @@ template <int LOGN, bool FWD>
 __device__ __forceinline__ void compact_round(double (&x)[NttShape<LOGN>::E], int r, int g0,
                                               const TwSrc& t, double p, double pinv) {
   using S = NttShape<LOGN>;
-  const auto rl = make_rsrc(t.cmp + S::cmp_off(r), (1 << S::s_start(r)) * 64);
-  const unsigned lo = (threadIdx.x >> S::lo(r)) * 64;
-  double wcur = buf_load(rl, lo, (FWD ? 0 : S::LOGE - 1) * 8), wnxt = 0.0;
+  // slot k of row u at k rows + u (slot-major: one slot's loads by a wave
+  // are contiguous)
+  const unsigned rows = 1u << S::s_start(r);
+  const auto rl = make_rsrc(t.cmp + S::cmp_off(r), rows * 64);
+  const unsigned lo = (threadIdx.x >> S::lo(r)) * 8;
+  double wcur = buf_load(rl, lo, (FWD ? 0 : S::LOGE - 1) * rows * 8), wnxt = 0.0;
 #pragma unroll
   for (int kk = 0; kk < S::LOGE; ++kk) {
     const int k = FWD ? kk : S::LOGE - 1 - kk;
@@ -272,7 +276,7 @@ __device__ __forceinline__ void compact_round(double (&x)[NttShape<LOGN>::E], in
     if (kk + 1 < S::LOGE) {
       unsigned o = lo;
       asm volatile("" : "+v"(o) : "v"(x[0]));
-      wnxt = buf_load(rl, o, (FWD ? k + 1 : k - 1) * 8);
+      wnxt = buf_load(rl, o, (FWD ? k + 1 : k - 1) * rows * 8);
     }
     const double wk = wcur;
 #pragma unroll

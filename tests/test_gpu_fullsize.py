@@ -134,3 +134,21 @@ def test_full_size_batched_waves(s32k):
         got = S.from_dev(o)
         for i in range(len(xs)):
             assert list(bfv.decrypt_slots(S.pr, S.sk, got[i])) == list((xs[i] == c).astype(int))
+
+
+def test_full_size_chain_matches_levels(s32k):
+    """The EQ chain (each level's mod-down fused with the next level's lift,
+    the split inverse's last stage applied by the consumers) gives the
+    integers of the separate squarings, each bit-exact against the oracle
+    above, followed by the oracle's finish."""
+    S = s32k
+    x, y = synth.column_pair_half_match(3, 2 * S.pr.n)
+    cts = [S.enc(x[k * S.pr.n:(k + 1) * S.pr.n], 7 + k) for k in range(2)]
+    cys = [S.enc(y[k * S.pr.n:(k + 1) * S.pr.n], 9 + k) for k in range(2)]
+    z = S.ctx.sub(S.to_dev(cts), S.to_dev(cys))
+    for _ in range(S.ctx.squarings):
+        z = S.ctx.square_relin(z)
+    levels = S.from_dev(z)
+    got = S.ctx.eq_mask(S.to_dev(cts), S.to_dev(cys))
+    for k in range(2):
+        np.testing.assert_array_equal(got[k].cpu().numpy(), S.limbs(bfv.finish(S.pr, levels[k])))
