@@ -13,6 +13,8 @@ second.  The line also carries:
                 recorded around every launch inside the timed region), against
                 the chip's FP64 VALU issue peak;
   kernels       per-kernel-kind time and launch counts from the same events;
+  roofline_ks_mac  the key-switch product's algorithmic HBM bytes per launch
+                over its mean launch time, against the 8 TB/s HBM peak;
   rates         squarings/s, transformed residues/s, modular products/s;
   latency_1ct_ms  one ciphertext (32,768 rows) through the whole mask;
   batched       512 instances of uneven size (rows log-uniform in
@@ -96,6 +98,26 @@ def roofline(prof: dict) -> tuple[dict, str]:
         "butterflies_per_launch": st["work"] / st["launches"],
         "mean_launch_ms": st["ms"] / st["launches"],
     }, dom_ntt
+
+
+PEAK_HBM_BYTES = 8.0e12   # MI355X HBM3E
+
+
+def roofline_ks(ctx, prof: dict, n_ct: int, ks_chunk: int) -> dict | None:
+    """The key-switch product (HBM-bound), against the HBM peak: per launch it
+    reads the n_ct ciphertexts' digits (L digits x (L+1) limbs x N doubles
+    each), the key (L x 2 x (L+1) x N) once per chunk of ks_chunk
+    ciphertexts, and writes 2 x (L+1) x N sums per ciphertext."""
+    st = prof.get("ks_mac")
+    if not st or not st["launches"]:
+        return None
+    n, L = ctx.n, ctx.L
+    chunks = -(-n_ct // ks_chunk)
+    per_launch = 8 * n * (L + 1) * (n_ct * L + chunks * 2 * L + n_ct * 2)
+    avg_s = st["ms"] / st["launches"] / 1e3
+    return {"bound": "hbm", "kernel": "ks_mac", "achieved": per_launch / avg_s / 1e9,
+            "peak": PEAK_HBM_BYTES / 1e9, "unit": "GB/s", "frac": per_launch / avg_s / PEAK_HBM_BYTES,
+            "bytes_per_launch": per_launch, "mean_launch_ms": st["ms"] / st["launches"]}
 
 
 def cpu_baseline() -> dict:
@@ -435,6 +457,7 @@ def main() -> int:
     log(f"{ms:.2f} ms/step, {value:.4g} records/s")
     roof, _ = roofline(prof)
     rates = derived_rates(ctx, prof, args.steps, n_ct, ms)
+    roof_ks = roofline_ks(ctx, prof, n_ct, ctx.tuning()["ks_chunk"])
     # one ciphertext (32,768 rows, the paper's per-query workload): latency
     lat_ms = None
     if not args.skip_latency:
@@ -475,6 +498,7 @@ def main() -> int:
                    "rows": records, "ciphertexts": n_ct, "ring_degree": ctx.n,
                    "data_primes": ctx.L, "plaintext_modulus": ctx.t},
         "roofline": roof,
+        "roofline_ks_mac": roof_ks,
         "cpu_baseline": cpu,
         "rates": rates,
         "latency_1ct_ms": lat_ms,
