@@ -564,7 +564,8 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
   const int h_len = h_rounds ? 1 << h_loge : 0;
   const int cmp_h_len = h_rounds ? cmp_len_of(h_rounds, h_r0, h_loge) : 0;
   std::vector<double> tw_h((size_t)K * 2 * std::max(h_len, 1), 0.0), tw_h0(K, 0.0),
-      tw_hi((size_t)K * 2 * std::max(h_len, 1), 0.0);
+      tw_hi((size_t)K * 2 * std::max(h_len, 1), 0.0), tw_r1f((size_t)K * 2 * 512, 0.0),
+      tw_r1i((size_t)K * 2 * 512, 0.0);
   std::vector<double> tw_cf((size_t)K * std::max(cmp_len, 1), 0.0),
       tw_ci((size_t)K * std::max(cmp_len, 1), 0.0),
       tw_ch((size_t)K * 2 * std::max(cmp_h_len, 1), 0.0),
@@ -628,6 +629,18 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
               tw_hi[((size_t)k * 2 + hh) * h_len + (1 << kk) + j] =
                   bal(pibr[(1 << kk) * (2 + hh) + j], p);
             }
+          // round 1 in full (16 rows x 32 slots), for the LDS copy
+          {
+            const int ss = h_r0;
+            for (int u = 0; u < (1 << ss) && (1 << ss) * 32 == 512; ++u)
+              for (int kk = 0; kk < h_loge; ++kk)
+                for (int j = 0; j < (1 << kk); ++j) {
+                  const int idx = (1 << (ss + kk)) * (2 + hh) + (u << kk) + j;
+                  const size_t o = ((size_t)k * 2 + hh) * 512 + (size_t)u * 32 + (1 << kk) + j;
+                  tw_r1f[o] = bal(pbr[idx], p);
+                  tw_r1i[o] = bal(pibr[idx], p);
+                }
+          }
           size_t off = ((size_t)k * 2 + hh) * cmp_h_len;
           for (int r = 1; r < h_rounds; ++r) {
             const int ss = h_r0 + (r - 1) * h_loge;
@@ -735,7 +748,8 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
       {&tw_ch, &c->tb.tw_cmp_h},  {&tw_kf, &c->tb.tw_cst_f},  {&tw_ki, &c->tb.tw_cst_i},
       {&q_hat_b_sp, &c->tb.q_hat_b_sp}, {&c2_sp, &c->tb.c2_sp}, {&b_hat_q_sp, &c->tb.b_hat_q_sp},
       {&two24, &c->tb.two24},     {&two48, &c->tb.two48},
-      {&tw_hi, &c->tb.tw_half_inv}, {&tw_chi, &c->tb.tw_cmp_hi}};
+      {&tw_hi, &c->tb.tw_half_inv}, {&tw_chi, &c->tb.tw_cmp_hi},
+      {&tw_r1f, &c->tb.tw_r1_f},  {&tw_r1i, &c->tb.tw_r1_i}};
   size_t total = 0;
   std::vector<size_t> offs;
   for (auto& pp : parts) {

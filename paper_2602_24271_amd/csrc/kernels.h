@@ -39,6 +39,10 @@ struct Tables {
   // the same for the half-limb inverse sub-transforms (inverse twiddles)
   const double* tw_half_inv; // [K][2][tw_half_len]
   const double* tw_cmp_hi;   // [K][2][tw_cmp_h_len]
+  // round 1 of each half's sub-transform in full: [K][2][16 rows][32 slots],
+  // slot 2^k + j of row u the twiddle of the round's stage k, block j
+  const double* tw_r1_f;
+  const double* tw_r1_i;
   // centred lift Q -> B
   const double* q_hat_inv;   // [L]      [(Q/q_i)^-1]_{q_i}
   const double* Q_b;         // [LB]     [Q]_{b_k}

@@ -300,12 +300,56 @@ __device__ __forceinline__ void compact_round(double (&x)[NttShape<LOGN>::E], in
   }
 }
 
-// Round r of the forward transform on this thread's registers.
-template <int LOGN>
-__device__ __forceinline__ void fwd_round(double (&x)[NttShape<LOGN>::E], int r, bool reduce,
-                                          const TwSrc& ts, double p, double pinv) {
+// Round 1 of a half-limb transform with every twiddle read from LDS: the
+// round has only 2^R0 index rows (16 for the 2^14-point halves), so a
+// workgroup copies their full rows (32 slots, stage k slot 2^k + j) into
+// LDS once and reads them there, shared by the 2^lo(1) threads of a row,
+// instead of loading each stage's first twiddle and deriving the others
+// with a modular product.
+constexpr int LDS_ROW = 32;
+
+template <int LOGN, bool FWD>
+__device__ __forceinline__ void lds_round(double (&x)[NttShape<LOGN>::E], int r, int g0,
+                                          const double* ltw, double p, double pinv) {
   using S = NttShape<LOGN>;
-  if (r > 0) {
+  const int row = (threadIdx.x >> S::lo(r)) * LDS_ROW;
+#pragma unroll
+  for (int kk = 0; kk < S::LOGE; ++kk) {
+    const int k = FWD ? kk : S::LOGE - 1 - kk;
+    const int eb = S::LOGE - 1 - k;
+    // a stage's reads wait for the previous stage's results (registers:
+    // otherwise all 31 are hoisted to the round's start)
+    int rk = row;
+    asm volatile("" : "+v"(rk) : "v"(x[0]));
+#pragma unroll
+    for (int j = 0; j < (1 << k); ++j) {
+      const double w = ltw[rk + (1 << k) + j];
+#pragma unroll
+      for (int b = 0; b < (1 << eb); ++b) {
+        const int e = (j << (eb + 1)) | b;
+        if constexpr (FWD) {
+          ct_bfly(x[e], x[e | (1 << eb)], w, p, pinv);
+        } else {
+          if ((g0 + kk) & 1)
+            gs_bfly<true>(x[e], x[e | (1 << eb)], w, p, pinv);
+          else
+            gs_bfly<false>(x[e], x[e | (1 << eb)], w, p, pinv);
+        }
+      }
+    }
+  }
+}
+
+// Round r of the forward transform on this thread's registers (LDS1: round
+// 1's twiddle rows are in LDS at ltw).
+template <int LOGN, bool LDS1 = false>
+__device__ __forceinline__ void fwd_round(double (&x)[NttShape<LOGN>::E], int r, bool reduce,
+                                          const TwSrc& ts, double p, double pinv,
+                                          const double* ltw = nullptr) {
+  using S = NttShape<LOGN>;
+  if (LDS1 && r == 1) {
+    lds_round<LOGN, true>(x, r, 0, ltw, p, pinv);
+  } else if (r > 0) {
     compact_round<LOGN, true>(x, r, 0, ts, p, pinv);
   } else {
 #pragma unroll
@@ -331,10 +375,15 @@ __device__ __forceinline__ void fwd_round(double (&x)[NttShape<LOGN>::E], int r,
 // Round r of the inverse; g0 = stages done before it (the reduction
 // alternation runs over the global stage count).  Round 0 is the last one
 // processed and reduces every value at its end.
-template <int LOGN>
+template <int LOGN, bool LDS1 = false>
 __device__ __forceinline__ void inv_round(double (&x)[NttShape<LOGN>::E], int r, int g0,
-                                          const TwSrc& ts, double p, double pinv) {
+                                          const TwSrc& ts, double p, double pinv,
+                                          const double* ltw = nullptr) {
   using S = NttShape<LOGN>;
+  if (LDS1 && r == 1) {
+    lds_round<LOGN, false>(x, r, g0, ltw, p, pinv);
+    return;
+  }
   if (r > 0) {
     compact_round<LOGN, false>(x, r, g0, ts, p, pinv);
     return;
@@ -591,7 +640,10 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
 k_ntt_fwd_half(NttJob job, Tables tb) {
   using S = NttShape<14>;
   constexpr int NF = 1 << 15;
+  constexpr int R1 = 1 << S::s_start(1);   // round 1's index rows
+  static_assert(R1 * LDS_ROW == 512, "one table entry per thread");
   __shared__ uint32_t lds[S::LDS_WORDS];
+  __shared__ double ltw[R1 * LDS_ROW];
   int limb, poly, h;
   if (MODE == NTT_DIGIT) {
     const int x = blockIdx.x & 7, l2 = blockIdx.x >> 3;
@@ -620,6 +672,8 @@ k_ntt_fwd_half(NttJob job, Tables tb) {
   const TwSrc tw{tb.tw_half + ((size_t)prime * 2 + h) * tb.tw_half_len,
                  tb.tw_cmp_h + ((size_t)prime * 2 + h) * tb.tw_cmp_h_len,
                  tb.tw_cst_f + (size_t)prime * 32};
+  // round 1's rows into LDS (read after the first exchange's barriers)
+  ltw[threadIdx.x] = tb.tw_r1_f[((size_t)prime * 2 + h) * 512 + threadIdx.x];
   // Both halves read the whole input limb, so the output must be another
   // buffer (the host never launches this kernel in place).
   const size_t off = (size_t)poly * job.poly_stride + (size_t)limb * NF;
@@ -671,8 +725,8 @@ k_ntt_fwd_half(NttJob job, Tables tb) {
     if (r > 0) exchange<14>(x, r - 1, r, lds, r > 1);
     // digit transforms skip the final reduction (outputs below 3.9 p):
     // their only reader, the key-switch product, reduces its sums itself
-    fwd_round<14>(x, r, fwd_reduces_after<14>(r, 1) && !(MODE == NTT_DIGIT && r == S::ROUNDS - 1),
-                  tw, p, pinv);
+    fwd_round<14, true>(x, r, fwd_reduces_after<14>(r, 1) && !(MODE == NTT_DIGIT && r == S::ROUNDS - 1),
+                        tw, p, pinv, ltw);
   }
   const unsigned so = (h * S::T + tid) * 8;
 #pragma unroll
@@ -701,7 +755,10 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
 k_ntt_inv_half(NttJob job, Tables tb) {
   using S = NttShape<14>;
   constexpr int NF = 1 << 15;
+  constexpr int R1 = 1 << S::s_start(1);
+  static_assert(R1 * LDS_ROW == 512, "one table entry per thread");
   __shared__ uint32_t lds[S::LDS_WORDS];
+  __shared__ double ltw[R1 * LDS_ROW];
   const int item2 = xcd_item(job.count * 2);
   if (item2 >= job.count * 2) return;
   const int h = item2 & 1;
@@ -713,6 +770,8 @@ k_ntt_inv_half(NttJob job, Tables tb) {
   const TwSrc tw{tb.tw_half_inv + ((size_t)prime * 2 + h) * tb.tw_half_len,
                  tb.tw_cmp_hi + ((size_t)prime * 2 + h) * tb.tw_cmp_h_len,
                  tb.tw_cst_i + (size_t)prime * 32};
+  // round 1's rows into LDS (read after the first exchange's barriers)
+  ltw[threadIdx.x] = tb.tw_r1_i[((size_t)prime * 2 + h) * 512 + threadIdx.x];
   const size_t off = (size_t)poly * job.poly_stride + (size_t)limb * NF;
   const auto rd = make_rsrc(job.base + off, NF * 8);
   const auto ro = make_rsrc((job.out ? job.out : job.base) + off, NF * 8);
@@ -751,7 +810,7 @@ k_ntt_inv_half(NttJob job, Tables tb) {
   for (int rr = 0; rr < S::ROUNDS; ++rr) {
     const int r = S::ROUNDS - 1 - rr;
     if (rr > 0) exchange<14>(x, r + 1, r, lds, rr > 1);
-    inv_round<14>(x, r, g0, tw, p, pinv);
+    inv_round<14, true>(x, r, g0, tw, p, pinv, ltw);
     g0 += S::stages(r);
   }
   if constexpr (MODE == NTT_INPLACE) {
