@@ -259,9 +259,12 @@ struct TwSrc {
 // Forward (FWD): Cooley-Tukey stages k = 0..LOGE-1.  Inverse: Gentleman-
 // Sande stages k = LOGE-1..0, the sum reduced on odd global stages (g0 =
 // stages done before this round).
+// reduce_x0 (forward): reduce the X operand of each first-stage butterfly
+// as it is used.
 template <int LOGN, bool FWD>
 __device__ __forceinline__ void compact_round(double (&x)[NttShape<LOGN>::E], int r, int g0,
-                                              const TwSrc& t, double p, double pinv) {
+                                              const TwSrc& t, double p, double pinv,
+                                              bool reduce_x0 = false) {
   using S = NttShape<LOGN>;
   // slot k of row u at k rows + u (slot-major: one slot's loads by a wave
   // are contiguous)
@@ -287,6 +290,10 @@ __device__ __forceinline__ void compact_round(double (&x)[NttShape<LOGN>::E], in
       for (int b = 0; b < (1 << eb); ++b) {
         const int e = (j << (eb + 1)) | b;
         if constexpr (FWD) {
+          if (kk == 0 && reduce_x0) {
+            x[e] = reduce_bal(x[e], p, pinv);
+            asm volatile("" : "+v"(x[e]));   // keep it next to its butterfly
+          }
           ct_bfly(x[e], x[e | (1 << eb)], w, p, pinv);
         } else {
           if ((g0 + kk) & 1)
@@ -345,12 +352,12 @@ __device__ __forceinline__ void lds_round(double (&x)[NttShape<LOGN>::E], int r,
 template <int LOGN, bool LDS1 = false>
 __device__ __forceinline__ void fwd_round(double (&x)[NttShape<LOGN>::E], int r, bool reduce,
                                           const TwSrc& ts, double p, double pinv,
-                                          const double* ltw = nullptr) {
+                                          const double* ltw = nullptr, bool reduce_x0 = false) {
   using S = NttShape<LOGN>;
   if (LDS1 && r == 1) {
     lds_round<LOGN, true>(x, r, 0, ltw, p, pinv);
   } else if (r > 0) {
-    compact_round<LOGN, true>(x, r, 0, ts, p, pinv);
+    compact_round<LOGN, true>(x, r, 0, ts, p, pinv, reduce_x0);
   } else {
 #pragma unroll
     for (int k = 0; k < S::R0; ++k) {
@@ -682,6 +689,12 @@ k_ntt_fwd_half(NttJob job, Tables tb) {
   const unsigned vo = tid * 8;
   double x[S::E];
   static_assert(fwd_schedule_ok<14>(1), "forward reduction schedule");
+  // the schedule reduces after round 1 (stage 0 and rounds 0, 1: ten
+  // stages) and at the end; the mid reduction is replaced by the half one
+  constexpr int HALF_REDUCE_ROUND = 2;
+  static_assert(S::ROUNDS == 3 && fwd_reduces_after<14>(HALF_REDUCE_ROUND - 1, 1) &&
+                    1 + S::stages(0) + S::stages(1) == FWD_STAGES_PER_REDUCTION,
+                "half reduction placement");
   {
     // digit sources hold canonical digits in [0, q_j), below 2 p_i
     const double* src = job.base + off;
@@ -723,10 +736,18 @@ k_ntt_fwd_half(NttJob job, Tables tb) {
 #pragma unroll
   for (int r = 0; r < S::ROUNDS; ++r) {
     if (r > 0) exchange<14>(x, r - 1, r, lds, r > 1);
-    // digit transforms skip the final reduction (outputs below 3.9 p):
+    // The ten stages to the end of round 1 leave values below 13.5 p.  Only
+    // the X operands of round 2's first stage (elements 0..E/2-1: it pairs
+    // e with e + E/2) are reduced, at that round's start: its products
+    // take |Y| < 13.5 p (results below 1.9 p), so it outputs below 2.4 p
+    // and the last four stages below 5.9 p (ct_bfly's bound), half the
+    // reductions of reducing every value after round 1.
+    // digit transforms skip the final reduction (outputs below 5.9 p):
     // their only reader, the key-switch product, reduces its sums itself
-    fwd_round<14, true>(x, r, fwd_reduces_after<14>(r, 1) && !(MODE == NTT_DIGIT && r == S::ROUNDS - 1),
-                        tw, p, pinv, ltw);
+    fwd_round<14, true>(x, r,
+                        fwd_reduces_after<14>(r, 1) && r != HALF_REDUCE_ROUND - 1 &&
+                            !(MODE == NTT_DIGIT && r == S::ROUNDS - 1),
+                        tw, p, pinv, ltw, r == HALF_REDUCE_ROUND);
   }
   const unsigned so = (h * S::T + tid) * 8;
 #pragma unroll

@@ -367,7 +367,7 @@ __global__ void __launch_bounds__(256) k_ks_mac(int n, int n_ct, const double* d
         a1[u] += mul_lazy(dv[u], e1, p, pinv);
       }
       // digit transforms are not reduced at their end: |dv| < 13.5 p (at
-      // most ten unreduced stages from inputs below 2p; 3.9 p at N = 2^15),
+      // most ten unreduced stages from inputs below 2p; 5.9 p at N = 2^15),
       // so each product is below 1.75 p and eight of them plus a reduced
       // sum stay below 14.5 p < 2^53 / p: reduce the sums every 8 digits
       if ((j & 7) == 7) {
