@@ -190,14 +190,19 @@ __device__ __forceinline__ void ct_bfly(double& X, double& Y, double W, double p
   Y = x - t;
 }
 
-// Gentleman-Sande butterfly; the sum is reduced on alternate stages only
-// (REDUCE_SUM), the difference feeds the modular product directly.  From
-// balanced inputs the bound before a non-reducing stage settles below
-// 0.85 p (a reduced sum is 0.5 p, a product of a difference below 2 b p
-// with |W| <= 0.55 p is (0.5 + 0.206 b) p), so sums stay below 1.7 p and
-// differences below 3.4 p, well inside mul_lazy's range, whatever the
-// round boundaries; the alternation runs over the global stage count and
-// only the last round reduces every value.
+// Gentleman-Sande butterfly; the sum is reduced on every third stage only
+// (REDUCE_SUM, gs_reduces), the difference feeds the modular product
+// directly.  A stage maps a bound B p on its inputs to sums below 2 B p (or
+// p/2 when reduced) and products of differences below (0.5 + 0.206 B) p
+// (|X - Y| <= 2 B p, |W| <= 0.55 p).  From balanced inputs, stage by stage:
+// 1, 2, 0.91, 1.82, 3.64, 1.25, 2.5, 5.0, 1.53, 3.06, 6.12, 1.76, 3.52, 7.04
+// (fourteen stages) and 1.95 after a fifteenth: every difference entering a
+// product stays below 14.1 p, inside mul_lazy's exact range (quotient below
+// 2^53, remainder and correction exactly representable, for |a| < 16 p and
+// p < 2^49), and every sum below 2^52.  The rule runs over the global stage
+// count, whatever the round boundaries; the last round reduces every value.
+__host__ __device__ constexpr bool gs_reduces(int g) { return g % 3 == 2; }
+
 template <bool REDUCE_SUM>
 __device__ __forceinline__ void gs_bfly(double& X, double& Y, double W, double p, double pinv) {
   double s = X + Y;
@@ -257,7 +262,7 @@ struct TwSrc {
 // twiddle is loaded one stage ahead, fenced on the previous stage's inputs
 // so that the loads are not all hoisted to the top (register pressure).
 // Forward (FWD): Cooley-Tukey stages k = 0..LOGE-1.  Inverse: Gentleman-
-// Sande stages k = LOGE-1..0, the sum reduced on odd global stages (g0 =
+// Sande stages k = LOGE-1..0, the sum reduced per gs_reduces (g0 =
 // stages done before this round).
 // reduce_x0 (forward): reduce the X operand of each first-stage butterfly
 // as it is used.
@@ -296,7 +301,7 @@ __device__ __forceinline__ void compact_round(double (&x)[NttShape<LOGN>::E], in
           }
           ct_bfly(x[e], x[e | (1 << eb)], w, p, pinv);
         } else {
-          if ((g0 + kk) & 1)
+          if (gs_reduces(g0 + kk))
             gs_bfly<true>(x[e], x[e | (1 << eb)], w, p, pinv);
           else
             gs_bfly<false>(x[e], x[e | (1 << eb)], w, p, pinv);
@@ -337,7 +342,7 @@ __device__ __forceinline__ void lds_round(double (&x)[NttShape<LOGN>::E], int r,
         if constexpr (FWD) {
           ct_bfly(x[e], x[e | (1 << eb)], w, p, pinv);
         } else {
-          if ((g0 + kk) & 1)
+          if (gs_reduces(g0 + kk))
             gs_bfly<true>(x[e], x[e | (1 << eb)], w, p, pinv);
           else
             gs_bfly<false>(x[e], x[e | (1 << eb)], w, p, pinv);
@@ -379,8 +384,8 @@ __device__ __forceinline__ void fwd_round(double (&x)[NttShape<LOGN>::E], int r,
   }
 }
 
-// Round r of the inverse; g0 = stages done before it (the reduction
-// alternation runs over the global stage count).  Round 0 is the last one
+// Round r of the inverse; g0 = stages done before it (the sum-reduction
+// rule runs over the global stage count).  Round 0 is the last one
 // processed and reduces every value at its end.
 template <int LOGN, bool LDS1 = false>
 __device__ __forceinline__ void inv_round(double (&x)[NttShape<LOGN>::E], int r, int g0,
@@ -405,7 +410,7 @@ __device__ __forceinline__ void inv_round(double (&x)[NttShape<LOGN>::E], int r,
 #pragma unroll
       for (int b = 0; b < (1 << eb); ++b) {
         const int e = (j << (eb + 1)) | b;
-        if ((g0 + kk - (S::LOGE - S::R0)) & 1)
+        if (gs_reduces(g0 + kk - (S::LOGE - S::R0)))
           gs_bfly<true>(x[e], x[e | (1 << eb)], w, p, pinv);
         else
           gs_bfly<false>(x[e], x[e | (1 << eb)], w, p, pinv);
