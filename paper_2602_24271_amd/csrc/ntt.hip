@@ -506,8 +506,11 @@ k_ntt_fwd(NttJob job, Tables tb) {
 // Tensor component of a squaring from one limb of the operand's
 // transforms: a^2 (CROSS false, a = ra) or 2 a0 a1 (CROSS true, a0 = ra,
 // a1 = rb).  Loads run one group of G elements ahead of the products, each
-// group's addresses fenced on the previous group's results.
-template <int LOGN, bool CROSS>
+// group's addresses fenced on the previous group's results.  LAZY leaves
+// the products unreduced (below 0.875 p): the 14 stages of a half-limb
+// inverse then keep sums below 7.7 p and the differences entering a
+// product below 13.9 p (gs_reduces' sequence from 0.875 p).
+template <int LOGN, bool CROSS, bool LAZY = false>
 __device__ __forceinline__ void tensor_square(double (&x)[NttShape<LOGN>::E],
                                               __amdgpu_buffer_rsrc_t ra,
                                               __amdgpu_buffer_rsrc_t rb, unsigned vo,
@@ -535,10 +538,8 @@ __device__ __forceinline__ void tensor_square(double (&x)[NttShape<LOGN>::E],
 #pragma unroll
     for (int i = 0; i < G; ++i) {
       const double a = ba[slot][i];
-      if constexpr (CROSS)
-        x[g + i] = mul_bal(a + a, bb[slot][i], p, pinv);
-      else
-        x[g + i] = mul_bal(a, a, p, pinv);
+      const double pr = CROSS ? mul_lazy(a + a, bb[slot][i], p, pinv) : mul_lazy(a, a, p, pinv);
+      x[g + i] = LAZY ? pr : reduce_bal(pr, p, pinv);
     }
   }
 }
@@ -814,9 +815,9 @@ k_ntt_inv_half(NttJob job, Tables tb) {
     const auto ra1 = make_rsrc(job.src + o1, NF * 8);
     if constexpr (MODE == INV_TENSOR) {
       if (k == 1)
-        tensor_square<15, true>(x, ra0, ra1, vi, p, pinv);
+        tensor_square<15, true, true>(x, ra0, ra1, vi, p, pinv);
       else
-        tensor_square<15, false>(x, k == 2 ? ra1 : ra0, ra1, vi, p, pinv);
+        tensor_square<15, false, true>(x, k == 2 ? ra1 : ra0, ra1, vi, p, pinv);
     } else {
       const auto rb0 = make_rsrc(job.src_b + o0, NF * 8);
       const auto rb1 = make_rsrc(job.src_b + o1, NF * 8);
