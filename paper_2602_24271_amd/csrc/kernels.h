@@ -123,7 +123,6 @@ struct Dims {
 };
 
 hipError_t run_lift(const Dims& d, double* ext, const Tables& tb, hipStream_t st);
-hipError_t run_lift_b(const Dims& d, double* ext_b, const Tables& tb, hipStream_t st);
 hipError_t run_scale(const Dims& d, double* dt, const Tables& tb, hipStream_t st);
 hipError_t run_ks_mac(const Dims& d, const double* dig, const double* evk, double* acc,
                       const Tables& tb, hipStream_t st);

@@ -894,9 +894,6 @@ hipError_t run_moddown_lift(const Dims& d, const double* acc, const double* dt, 
   return hipGetLastError();
 }
 
-hipError_t run_lift_b(const Dims& d, double* ext_b, const Tables& tb, hipStream_t st) {
-  return run_lift(d, ext_b, tb, st);
-}
 
 hipError_t run_scale(const Dims& d, double* dt, const Tables& tb, hipStream_t st) {
   const size_t np = (size_t)d.n_ct * 3;
