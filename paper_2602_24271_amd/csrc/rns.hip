@@ -257,6 +257,16 @@ __global__ void __launch_bounds__(256) k_scale(int n, size_t n_poly, double* dt,
     cs.v = cs.hi ? cs.vv : cs.vu;
     cs.sg = cs.hi ? -1.0 : 1.0;
   }
+  // FUSED: the two rows of t_qhinv and c1 copied into LDS once per block,
+  // so that each lane's constant (lower or upper row) is an LDS read that
+  // half a wave shares, not a vector memory load
+  __shared__ double kl[FUSED ? 2 * (L + LB) : 1];
+  if constexpr (FUSED) {
+    const int t = (int)threadIdx.x;
+    if (t < 2 * L) kl[t] = tb.t_qhinv[t];
+    if (t < 2 * LB) kl[2 * L + t] = tb.c1[t];
+    __syncthreads();
+  }
   const unsigned vo = cs.v;
   const unsigned ls = (unsigned)n * 8;   // bytes per limb
   const bool third = pb.pc % 3 == 2;
@@ -267,7 +277,7 @@ __global__ void __launch_bounds__(256) k_scale(int n, size_t n_poly, double* dt,
     const int iq = opaque_idx(i);
     const double p = cld(tb.p, iq), pinv = cld(tb.pinv, iq);
     y[i] = mul_bal(coef_load<FUSED>(rs, cs, i * ls),
-                   coef_const<FUSED>(cs, tb.t_qhinv, iq, L), p, pinv);
+                   coef_const<FUSED>(cs, FUSED ? kl : tb.t_qhinv, iq, L), p, pinv);
     S += y[i] * cld(tb.recip, iq);
   }
   double v = __builtin_rint(S);
@@ -303,7 +313,7 @@ __global__ void __launch_bounds__(256) k_scale(int n, size_t n_poly, double* dt,
       const double b = cld(tb.p, pk), binv = cld(tb.pinv, pk);
       const double* sp = opaque_row(tb.c2_sp, k * L * 2);
       const double acc = mul_lazy(coef_load<FUSED>(rs, cs, (L + k) * ls),
-                                  coef_const<FUSED>(cs, tb.c1, kq, LB), b, binv) +
+                                  coef_const<FUSED>(cs, FUSED ? kl + 2 * L : tb.c1, kq, LB), b, binv) +
                          v * cld(tb.b_hat_inv, kq) -
                          conv_row<L>(yh, yl, sp, cld(tb.two24, pk), cld(tb.two48, pk), b, binv);
       const double w = reduce_bal(acc, b, binv);
