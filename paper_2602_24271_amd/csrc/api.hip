@@ -1049,9 +1049,10 @@ int nshe_relinearize(nshe_ctx* c, const int64_t* in3, int64_t* out, int n_ct, vo
 }
 
 // The EQ chain on ciphertexts already differenced into w.ext.
-static int eq_levels(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st) {
+static int eq_levels(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st,
+                     bool first_lifted = false) {
   for (int k = 0; k < c->squarings; ++k) {
-    int rc = square_level(c, w, n_ct, st, k > 0, k + 1 < c->squarings);
+    int rc = square_level(c, w, n_ct, st, k > 0 || first_lifted, k + 1 < c->squarings);
     if (rc) return rc;
   }
   return NSHE_OK;
@@ -1068,11 +1069,17 @@ int nshe_eq_mask(nshe_ctx* c, const int64_t* x, const int64_t* y, int64_t* out, 
   Ws w = carve(c, ws, n_ct);
   Dims d = dims(c, n_ct);
   const size_t W = W_of(c), N = c->n;
+  // with the split inverse the subtraction also lifts (the first squaring's
+  // operand), like every later level's mod-down
+  const bool chain = split_inverse(c);
   {
     Prof pf(c, K_SUB, st, 2.0 * n_ct * c->L * c->n);
-    HIPCHK(run_sub_to_ext(d, x, y, y_broadcast ? 1 : 0, w.ext, c->tb, st));
+    if (chain)
+      HIPCHK(run_sub_lift(d, x, y, y_broadcast ? 1 : 0, w.ext, c->tb, st));
+    else
+      HIPCHK(run_sub_to_ext(d, x, y, y_broadcast ? 1 : 0, w.ext, c->tb, st));
   }
-  rc = eq_levels(c, w, n_ct, st);
+  rc = eq_levels(c, w, n_ct, st, chain);
   if (rc) return rc;
   {
     Prof pf(c, K_CONVERT, st, 2.0 * n_ct * c->L * c->n);

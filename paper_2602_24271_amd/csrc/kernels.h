@@ -128,6 +128,9 @@ hipError_t run_ks_mac(const Dims& d, const double* dig, const double* evk, doubl
                       const Tables& tb, hipStream_t st);
 hipError_t run_moddown(const Dims& d, const double* acc, const double* dt, double* ext,
                        const Tables& tb, hipStream_t st);
+// subtraction into ext followed by its lift (the first squaring's operand)
+hipError_t run_sub_lift(const Dims& d, const int64_t* x, const int64_t* y, int y_bcast,
+                        double* ext, const Tables& tb, hipStream_t st);
 // mod-down of the split inverse's output followed by the lift of the result
 // (the next squaring's operand), one kernel; needs d.fused
 hipError_t run_moddown_lift(const Dims& d, const double* acc, const double* dt, double* ext,

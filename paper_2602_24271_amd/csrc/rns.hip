@@ -457,6 +457,37 @@ __global__ void __launch_bounds__(256) k_moddown(int n, int n_ct, const double* 
   }
 }
 
+// The rest of a lift whose L residues o (balanced) and y_i = [o_i
+// (Q/q_i)^-1]_{q_i}, S = sum_i y_i / q_i are already in registers: the
+// overflow count v (exact fallback near a half-integer, as k_lift), then
+// limbs L..2L of rs at vo.
+template <int L>
+__device__ __forceinline__ void lift_tail(const double (&o)[L], const double (&y)[L], double S,
+                                          __amdgpu_buffer_rsrc_t rs, unsigned vo, unsigned ls,
+                                          const Tables& tb) {
+  constexpr int LB = L + 1;
+  double v = __builtin_rint(S);
+  if (__builtin_fabs(S - v) > 0.5 - LIFT_EPS) {
+    double r[L];
+#pragma unroll
+    for (int i = 0; i < L; ++i) r[i] = to_canonical(o[i], cld(tb.p, i));
+    v = __builtin_floor(S) + (mrc_greater_than_half<L>(r, tb.p, tb.pinv, tb.mrc_inv, tb.mrc_half) ? 1.0 : 0.0);
+    atomicAdd(tb.margin, 1ull);
+  }
+  double yh[L], yl[L];
+#pragma unroll
+  for (int i = 0; i < L; ++i) split24(y[i], yh[i], yl[i]);
+#pragma unroll
+  for (int k = 0; k < LB; ++k) {
+    const int kq = opaque_idx(k), pk = L + kq;
+    const double bb = cld(tb.p, pk), binv = cld(tb.pinv, pk);
+    const double* sp = opaque_row(tb.q_hat_b_sp, k * L * 2);
+    const double a = conv_row<L>(yh, yl, sp, cld(tb.two24, pk), cld(tb.two48, pk), bb, binv) -
+                     v * cld(tb.Q_b, kq);
+    buf_store(reduce_bal(a, bb, binv), rs, vo, (L + k) * ls);
+  }
+}
+
 // The mod-down of the split inverse's output (k_moddown, FUSED) followed by
 // the lift of its result (k_lift): within the squaring chain the next level
 // lifts exactly what this level's mod-down writes, so one kernel saves
@@ -512,26 +543,40 @@ __global__ void __launch_bounds__(256) k_moddown_lift(int n, size_t n_poly,
   }
 #pragma unroll
   for (int i = 0; i < L; ++i) buf_store(o[i], rs, vo, i * ls);
-  double v = __builtin_rint(S);
-  if (__builtin_fabs(S - v) > 0.5 - LIFT_EPS) {
-    double r[L];
+  lift_tail<L>(o, y, S, rs, vo, ls, tb);
+}
+
+// Subtraction z = [x - y]_Q of two ciphertexts (int64, canonical; y one
+// ciphertext broadcast when y_bcast) into ext limbs 0..L-1, followed by the
+// lift of z (limbs L..2L): the first level of the chain, one kernel.  One
+// thread per coefficient of each (ct, b) polynomial, blocks as in k_lift.
+template <int L>
+__global__ void __launch_bounds__(256) k_sub_lift(int n, size_t n_poly,
+                                                  const int64_t* __restrict__ xs,
+                                                  const int64_t* __restrict__ ys, int y_bcast,
+                                                  double* __restrict__ ext, Tables tb) {
+  constexpr int W = 2 * L + 1;
+  const PolyBlock pb = poly_block(n, n_poly);   // poly = ct * 2 + b
+  if (!pb.ok) return;
+  const size_t cb = pb.pc;
+  const int b = (int)(cb & 1);
+  const int64_t* xp = xs + cb * (size_t)L * n + pb.c;
+  const int64_t* yp = (y_bcast ? ys + (size_t)b * L * n : ys + cb * (size_t)L * n) + pb.c;
+  const auto rs = make_rsrc(ext + cb * (size_t)W * n, (unsigned)(W * n * 8));
+  const unsigned vo = (unsigned)pb.c * 8, ls = (unsigned)n * 8;
+  double o[L], y[L];
+  double S = 0.0;
 #pragma unroll
-    for (int i = 0; i < L; ++i) r[i] = to_canonical(o[i], cld(tb.p, i));
-    v = __builtin_floor(S) + (mrc_greater_than_half<L>(r, tb.p, tb.pinv, tb.mrc_inv, tb.mrc_half) ? 1.0 : 0.0);
-    atomicAdd(tb.margin, 1ull);
+  for (int i = 0; i < L; ++i) {
+    const int iq = opaque_idx(i);
+    const double q = cld(tb.p, iq), qinv = cld(tb.pinv, iq);
+    o[i] = reduce_bal((double)xp[(size_t)i * n] - (double)yp[(size_t)i * n], q, qinv);
+    y[i] = mul_bal(o[i], cld(tb.q_hat_inv, iq), q, qinv);
+    S += y[i] * cld(tb.recip, iq);
   }
-  double yh[L], yl[L];
 #pragma unroll
-  for (int i = 0; i < L; ++i) split24(y[i], yh[i], yl[i]);
-#pragma unroll
-  for (int k = 0; k < LB; ++k) {
-    const int kq = opaque_idx(k), pk = L + kq;
-    const double bb = cld(tb.p, pk), binv = cld(tb.pinv, pk);
-    const double* sp = opaque_row(tb.q_hat_b_sp, k * L * 2);
-    const double a = conv_row<L>(yh, yl, sp, cld(tb.two24, pk), cld(tb.two48, pk), bb, binv) -
-                     v * cld(tb.Q_b, kq);
-    buf_store(reduce_bal(a, bb, binv), rs, vo, (L + k) * ls);
-  }
+  for (int i = 0; i < L; ++i) buf_store(o[i], rs, vo, i * ls);
+  lift_tail<L>(o, y, S, rs, vo, ls, tb);
 }
 
 // ------------------------------------------------------ plaintext products ---
@@ -880,6 +925,22 @@ hipError_t run_lift(const Dims& d, double* ext, const Tables& tb, hipStream_t st
   switch (d.L) {
 #define C_(L_) \
   case L_: hipLaunchKernelGGL(k_lift<L_>, poly_grid(np, d.n, d.block), dim3(d.block), 0, st, d.n, np, ext, tb); break;
+    NSHE_L_CASES(C_)
+#undef C_
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t run_sub_lift(const Dims& d, const int64_t* x, const int64_t* y, int y_bcast,
+                        double* ext, const Tables& tb, hipStream_t st) {
+  const size_t np = (size_t)d.n_ct * 2;
+  switch (d.L) {
+#define C_(L_)                                                                            \
+  case L_:                                                                                \
+    hipLaunchKernelGGL(k_sub_lift<L_>, poly_grid(np, d.n, d.block), dim3(d.block), 0, st, \
+                       d.n, np, x, y, y_bcast, ext, tb);                                  \
+    break;
     NSHE_L_CASES(C_)
 #undef C_
     default: return hipErrorInvalidValue;
