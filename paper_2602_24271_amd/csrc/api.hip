@@ -391,8 +391,11 @@ static int tensor_scale(nshe_ctx* c, const Ws& w, const double* fx_b, int n_ct, 
 // first two: (c0 + k0, c1 + k1) into `out` (ext unless given), limbs 0..L-1.
 // lift_out: also lift the result (limbs L..2L of out), for a squaring that
 // follows at once (only with the split inverse).
+// finish_out: write the result to this int64 buffer with the mask's finish
+// instead (only with the split inverse).
 static int relin(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st,
-                 const double* key = nullptr, double* out = nullptr, bool lift_out = false) {
+                 const double* key = nullptr, double* out = nullptr, bool lift_out = false,
+                 int64_t* finish_out = nullptr) {
   if (!key) key = c->evk;
   if (!out) out = w.ext;
   Dims d = dims(c, n_ct);
@@ -418,7 +421,10 @@ static int relin(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st,
   }
   int rc = ntt_job_ks(c, w.acc, nullptr, n_ct * 2, 1, st, true);
   if (rc) return rc;
-  if (lift_out && d.fused) {
+  if (finish_out && d.fused) {
+    Prof pf(c, K_MODDOWN, st, 2.0 * n_ct * c->n);
+    HIPCHK(run_moddown_finish(d, w.acc, w.dt, finish_out, c->tb, st));
+  } else if (lift_out && d.fused) {
     Prof pf(c, K_MODDOWN_LIFT, st, 2.0 * n_ct * c->n);
     HIPCHK(run_moddown_lift(d, w.acc, w.dt, out, c->tb, st));
   } else {
@@ -432,13 +438,15 @@ static int relin(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st,
 // (with the split inverse) each level but the last also lifts its result
 // for the next (lift_out), which then skips its own lift (lifted).
 static int square_level(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st,
-                        bool lifted = false, bool lift_out = false) {
+                        bool lifted = false, bool lift_out = false,
+                        int64_t* finish_out = nullptr) {
   const bool chain = split_inverse(c);
   int rc = prepare_operand(c, w.ext, w.fx, n_ct, st, lifted && chain);
   if (rc) return rc;
   rc = tensor_scale(c, w, nullptr, n_ct, st);
   if (rc) return rc;
-  return relin(c, w, n_ct, st, nullptr, nullptr, lift_out && chain);
+  return relin(c, w, n_ct, st, nullptr, nullptr, lift_out && chain,
+               chain ? finish_out : nullptr);
 }
 
 static int check_ctx(const nshe_ctx* c) {
@@ -1049,10 +1057,13 @@ int nshe_relinearize(nshe_ctx* c, const int64_t* in3, int64_t* out, int n_ct, vo
 }
 
 // The EQ chain on ciphertexts already differenced into w.ext.
+// finish_out (with the split inverse): the last level writes the mask to it.
 static int eq_levels(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st,
-                     bool first_lifted = false) {
+                     bool first_lifted = false, int64_t* finish_out = nullptr) {
   for (int k = 0; k < c->squarings; ++k) {
-    int rc = square_level(c, w, n_ct, st, k > 0 || first_lifted, k + 1 < c->squarings);
+    const bool last = k + 1 == c->squarings;
+    int rc = square_level(c, w, n_ct, st, k > 0 || first_lifted, !last,
+                          last ? finish_out : nullptr);
     if (rc) return rc;
   }
   return NSHE_OK;
@@ -1079,9 +1090,9 @@ int nshe_eq_mask(nshe_ctx* c, const int64_t* x, const int64_t* y, int64_t* out, 
     else
       HIPCHK(run_sub_to_ext(d, x, y, y_broadcast ? 1 : 0, w.ext, c->tb, st));
   }
-  rc = eq_levels(c, w, n_ct, st, chain);
+  rc = eq_levels(c, w, n_ct, st, chain, chain ? out : nullptr);
   if (rc) return rc;
-  {
+  if (!chain) {
     Prof pf(c, K_CONVERT, st, 2.0 * n_ct * c->L * c->n);
     HIPCHK(run_polys_to_i64(d, w.ext, 2, 2 * W * N, W * N, out, 1, c->tb, st));
   }

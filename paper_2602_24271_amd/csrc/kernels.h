@@ -128,6 +128,10 @@ hipError_t run_ks_mac(const Dims& d, const double* dig, const double* evk, doubl
                       const Tables& tb, hipStream_t st);
 hipError_t run_moddown(const Dims& d, const double* acc, const double* dt, double* ext,
                        const Tables& tb, hipStream_t st);
+// the last level's mod-down written to int64 with the mask's finish,
+// (Delta, 0) - z; needs d.fused
+hipError_t run_moddown_finish(const Dims& d, const double* acc, const double* dt, int64_t* out,
+                              const Tables& tb, hipStream_t st);
 // subtraction into ext followed by its lift (the first squaring's operand)
 hipError_t run_sub_lift(const Dims& d, const int64_t* x, const int64_t* y, int y_bcast,
                         double* ext, const Tables& tb, hipStream_t st);

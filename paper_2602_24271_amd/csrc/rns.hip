@@ -457,6 +457,54 @@ __global__ void __launch_bounds__(256) k_moddown(int n, int n_ct, const double* 
   }
 }
 
+// The last level's mod-down (split inverse, pairs as in k_moddown FUSED)
+// written straight to the caller's int64 output with the mask's finish: out
+// = (Delta, 0) - z, i.e. every residue negated and [Delta]_{q_i} added to
+// the constant coefficient of c0; canonical residues in [0, q_i).
+template <int L>
+__global__ void __launch_bounds__(256) k_moddown_finish(int n, int n_ct,
+                                                        const double* __restrict__ acc,
+                                                        const double* __restrict__ dt,
+                                                        int64_t* __restrict__ out, Tables tb) {
+  constexpr int K = L + 1;
+  constexpr int W = 2 * L + 1;
+  const int per = n >> 1;
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (size_t)n_ct * 2 * per) return;
+  const size_t cb = gid / per;             // ct * 2 + b
+  const int c = (int)(gid - cb * per);
+  const size_t ct = cb >> 1;
+  const int b = (int)(cb & 1);
+  const int ip = 2 * L + 1;
+  const double pP = cld(tb.p, ip), pPinv = cld(tb.pinv, ip);
+  const double* e = dt + ((ct * 3 + b) * (size_t)W) * n + c;
+  int64_t* o = out + cb * (size_t)L * n + c;
+  const int ht = n >> 6;
+  const double* a = acc + cb * (size_t)K * n + (size_t)(c / ht) * 2 * ht + (c % ht);
+  const size_t hn = (size_t)(n >> 1);
+  const double uP = a[(size_t)L * n], vP = a[(size_t)L * n + ht];
+  const double ninvP = cld(tb.ninv, ip);
+  const double aP_lo = mul_bal(uP + vP, ninvP, pP, pPinv);
+  const double aP_hi =
+      mul_bal(mul_lazy(uP - vP, cld(tb.tw_inv, ip * tb.tw_len + 1), pP, pPinv), ninvP, pP, pPinv);
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    const double q = cld(tb.p, i), qinv = cld(tb.pinv, i);
+    const double u = a[(size_t)i * n], v = a[(size_t)i * n + ht];
+    const double lo = u + v;
+    const double hi = mul_lazy(u - v, cld(tb.tw_inv, i * tb.tw_len + 1), q, qinv);
+    const double npq = cld(tb.NP_inv_q, i), pq = cld(tb.P_inv_q, i);
+    const double r_lo = mul_lazy(lo, npq, q, qinv) - mul_lazy(aP_lo, pq, q, qinv);
+    const double r_hi = mul_lazy(hi, npq, q, qinv) - mul_lazy(aP_hi, pq, q, qinv);
+    // -(e + r), plus Delta at coefficient 0 of c0
+    double z_lo = -(e[(size_t)i * n] + r_lo);
+    if (b == 0 && c == 0) z_lo += cld(tb.delta_q, i);
+    const double z_hi = -(e[(size_t)i * n + hn] + r_hi);
+    o[(size_t)i * n] = to_i64(reduce_bal(z_lo, q, qinv), q);
+    o[(size_t)i * n + hn] = to_i64(reduce_bal(z_hi, q, qinv), q);
+  }
+}
+
 // The rest of a lift whose L residues o (balanced) and y_i = [o_i
 // (Q/q_i)^-1]_{q_i}, S = sum_i y_i / q_i are already in registers: the
 // overflow count v (exact fallback near a half-integer, as k_lift), then
@@ -925,6 +973,23 @@ hipError_t run_lift(const Dims& d, double* ext, const Tables& tb, hipStream_t st
   switch (d.L) {
 #define C_(L_) \
   case L_: hipLaunchKernelGGL(k_lift<L_>, poly_grid(np, d.n, d.block), dim3(d.block), 0, st, d.n, np, ext, tb); break;
+    NSHE_L_CASES(C_)
+#undef C_
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t run_moddown_finish(const Dims& d, const double* acc, const double* dt, int64_t* out,
+                              const Tables& tb, hipStream_t st) {
+  if (!d.fused) return hipErrorInvalidValue;
+  const size_t total = (size_t)d.n_ct * 2 * (d.n / 2);
+  switch (d.L) {
+#define C_(L_)                                                                                 \
+  case L_:                                                                                     \
+    hipLaunchKernelGGL(k_moddown_finish<L_>, grid_for(total, d.block), dim3(d.block), 0, st,   \
+                       d.n, d.n_ct, acc, dt, out, tb);                                         \
+    break;
     NSHE_L_CASES(C_)
 #undef C_
     default: return hipErrorInvalidValue;
