@@ -103,18 +103,76 @@ __device__ __forceinline__ constexpr int lds_chunk() {
   return ch;
 }
 
+// The thread that holds index i in round r (the inverse of round_index).
+template <int LOGN>
+__host__ __device__ constexpr int round_tid(int r, int i) {
+  using S = NttShape<LOGN>;
+  const int lo = S::lo(r);
+  return ((i >> (lo + S::LOGE)) << lo) | (i & ((1 << lo) - 1));
+}
+
+// Between the last two rounds (when neither is round 0) the values move
+// only among threads of one wavefront: round ROUNDS-2 holds index bits
+// [LOGE, 2 LOGE) in registers and the last round bits [0, LOGE), so an
+// index keeps its bits from 2 LOGE up in the thread number under both maps
+// and the E threads that trade values share tid >> LOGE.
+template <int LOGN>
+__host__ __device__ constexpr bool wave_local(int r0, int r1) {
+  using S = NttShape<LOGN>;
+  const int a = r0 < r1 ? r0 : r1, b = r0 < r1 ? r1 : r0;
+  return a >= 1 && b == S::ROUNDS - 1 && b - a == 1 && S::E <= 64;
+}
+
+// Every index's two holders (under the maps of a wave-local pair of
+// rounds) are in the same wavefront of 64 threads.
+template <int LOGN>
+constexpr bool wave_local_sound() {
+  using S = NttShape<LOGN>;
+  for (int a = 0; a + 1 < S::ROUNDS; ++a) {
+    if (!wave_local<LOGN>(a, a + 1)) continue;
+    for (int i = 0; i < S::N; ++i)
+      if ((round_tid<LOGN>(a, i) >> 6) != (round_tid<LOGN>(a + 1, i) >> 6)) return false;
+  }
+  return true;
+}
+static_assert(wave_local_sound<15>(), "wave-local exchanges stay inside a wavefront");
+static_assert(wave_local_sound<14>(), "wave-local exchanges stay inside a wavefront");
+static_assert(wave_local_sound<13>(), "wave-local exchanges stay inside a wavefront");
+static_assert(wave_local_sound<12>(), "wave-local exchanges stay inside a wavefront");
+static_assert(wave_local_sound<11>(), "wave-local exchanges stay inside a wavefront");
+static_assert(wave_local_sound<10>(), "wave-local exchanges stay inside a wavefront");
+static_assert(wave_local_sound<9>(), "wave-local exchanges stay inside a wavefront");
+
+// Order one pass's LDS writes before its reads (and the reads before the
+// next pass's writes): a workgroup barrier, or for a wave-local exchange
+// only a wavefront-scope fence, since one wavefront's LDS operations are
+// carried out in issue order.
+__device__ __forceinline__ void lds_pass_sync(bool wave_only) {
+  if (wave_only) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 // Move the E values of every thread from round r0's index map to r1's.
 // The base addresses are made opaque per pass (inline asm), so that no
 // per-element address registers stay live across the barriers.  Each pass
 // is write, barrier, read; a barrier separates a pass's reads from the next
 // pass's writes.  After the last read there is none: the next exchange
 // starts with it instead (wait_prev), so that a wave starts the round's
-// arithmetic as soon as its own values have arrived.
+// arithmetic as soon as its own values have arrived.  A wave-local
+// exchange (see wave_local) orders its passes within the wavefront only;
+// it still needs wait_prev when the previous exchange was not wave-local,
+// as other wavefronts may be reading its slots.
 template <int LOGN>
 __device__ __forceinline__ void exchange(double (&x)[NttShape<LOGN>::E], int r0, int r1,
                                          uint32_t* lds, bool wait_prev) {
   using S = NttShape<LOGN>;
   const int tid = threadIdx.x;
+  const bool local = wave_local<LOGN>(r0, r1);
   if (wait_prev) __syncthreads();
   if constexpr (S::SPLIT) {
     constexpr int C0 = lds_chunk<LOGN, 4>();
@@ -132,7 +190,7 @@ __device__ __forceinline__ void exchange(double (&x)[NttShape<LOGN>::E], int r0,
               half ? (uint32_t)(v >> 32) : (uint32_t)v;
         }
       }
-      __syncthreads();
+      lds_pass_sync(local);
       int b1 = slot_base<LOGN>(r1, tid);
       asm volatile("" : "+v"(b1));
 #pragma unroll
@@ -147,7 +205,7 @@ __device__ __forceinline__ void exchange(double (&x)[NttShape<LOGN>::E], int r0,
           x[e] = __longlong_as_double(v);
         }
       }
-      if (half == 0) __syncthreads();
+      if (half == 0) lds_pass_sync(local);
     }
   } else {
     double* d = reinterpret_cast<double*>(lds);
@@ -161,7 +219,7 @@ __device__ __forceinline__ void exchange(double (&x)[NttShape<LOGN>::E], int r0,
       for (int e = c; e < c + C0; ++e)
         base[slot_off<LOGN>(r0, e) - slot_off<LOGN>(r0, c)] = x[e];
     }
-    __syncthreads();
+    lds_pass_sync(local);
     int b1 = slot_base<LOGN>(r1, tid);
     asm volatile("" : "+v"(b1));
 #pragma unroll
@@ -797,7 +855,8 @@ k_ntt_inv_half(NttJob job, Tables tb) {
   const TwSrc tw{tb.tw_half_inv + ((size_t)prime * 2 + h) * tb.tw_half_len,
                  tb.tw_cmp_hi + ((size_t)prime * 2 + h) * tb.tw_cmp_h_len,
                  tb.tw_cst_i + (size_t)prime * 32};
-  // round 1's rows into LDS (read after the first exchange's barriers)
+  // round 1's rows into LDS (read after the barrier that opens the first
+  // exchange: that exchange itself is wave-local)
   ltw[threadIdx.x] = tb.tw_r1_i[((size_t)prime * 2 + h) * 512 + threadIdx.x];
   const size_t off = (size_t)poly * job.poly_stride + (size_t)limb * NF;
   const auto rd = make_rsrc(job.base + off, NF * 8);
@@ -836,7 +895,9 @@ k_ntt_inv_half(NttJob job, Tables tb) {
 #pragma unroll
   for (int rr = 0; rr < S::ROUNDS; ++rr) {
     const int r = S::ROUNDS - 1 - rr;
-    if (rr > 0) exchange<14>(x, r + 1, r, lds, rr > 1);
+    static_assert(S::ROUNDS == 3 && wave_local<14>(2, 1) && !wave_local<14>(1, 0),
+                  "exchange barriers of the half inverse");
+    if (rr > 0) exchange<14>(x, r + 1, r, lds, true);
     inv_round<14, true>(x, r, g0, tw, p, pinv, ltw);
     g0 += S::stages(r);
   }
