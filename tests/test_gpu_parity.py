@@ -58,6 +58,28 @@ def test_ntt_small_workload_sampled(s1k):
             assert got[0, i, j] == ntt_def.evaluation_at(list(polys[0, i]), S.pr.q[i], j)
 
 
+@pytest.mark.parametrize("log2_n,split", [(3, 1), (5, 1), (7, 1), (8, 1), (9, 1), (11, 1),
+                                           (12, 1), (13, 1), (14, 1), (15, 1), (15, 0)])
+def test_ntt_every_size_sampled(log2_n, split):
+    """Every transform size (one, two and three register rounds, exchanges
+    within a wavefront and across the workgroup; at 2^15 both the split
+    half-limb and the full-limb forward), sampled against the definition."""
+    require_gpu()
+    from paper_2602_24271_amd import Context
+    pr = bfv.paper_params(1 << log2_n)
+    ctx = Context(log2_n, pr.t, list(pr.q), pr.P)
+    ctx.set_tuning(split_forward=split)
+    rng = np.random.default_rng(100 + log2_n)
+    polys = np.stack([np.stack([rng.integers(0, q, pr.n) for q in pr.q]) for _ in range(2)])
+    got = ctx.ntt(torch.from_numpy(polys).to(ctx.device)).cpu().numpy()
+    js = sorted({0, 1, pr.n // 2 - 1, pr.n // 2, pr.n - 1, int(rng.integers(0, pr.n))})
+    for p in range(2):
+        for i in (0, pr.L // 2, pr.L - 1):
+            for j in js:
+                want = ntt_def.evaluation_at(list(polys[p, i]), pr.q[i], j)
+                assert got[p, i, j] == want, (log2_n, split, p, i, j)
+
+
 # ----------------------------------------------------- ciphertext calls ---
 
 def test_sub_matches_oracle(s1k):
