@@ -60,10 +60,15 @@ def log(msg: str) -> None:
 
 
 def kernel_hash() -> str:
+    """Hash of the built library (its machine code): HBM counters taken on
+    one build are reported only while the library is bit-identical (the
+    build is deterministic, so edits to comments keep it)."""
+    lib = os.path.join(ROOT, "paper_2602_24271_amd", "libnshe.so")
+    if not os.path.exists(lib):
+        return "none"
     h = hashlib.sha256()
-    for f in ("ntt.hip", "rns.hip", "api.hip", "modarith.h", "kernels.h"):
-        with open(os.path.join(ROOT, "paper_2602_24271_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    with open(lib, "rb") as fh:
+        h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -369,12 +374,12 @@ def summarize_profiles(prof_dir: str, out_dir: str) -> None:
                "--calibrate-copy-mib 256")
     with open(os.path.join(out_dir, "eq_mask_2p20_rows_kernels.md"), "w") as fh:
         fh.write("# EQ mask, 2^20 rows (32 ciphertexts, N=32768), per-kernel time\n\n")
-        fh.write(f"Kernel sources hash: {kernel_hash()}\n\nCommand (from the repo root, "
+        fh.write(f"Library hash: {kernel_hash()}\n\nCommand (from the repo root, "
                  f"TMPDIR=/tmp):\n\n    {cmd_trace}\n\n")
         fh.write("\n".join(lines) + "\n")
     with open(os.path.join(out_dir, "eq_mask_2p20_rows_hbm_traffic.md"), "w") as fh:
         fh.write("# EQ mask, 2^20 rows: HBM bytes per launch (FETCH_SIZE, WRITE_SIZE)\n\n")
-        fh.write(f"Kernel sources hash: {kernel_hash()}\n\nCommands, one counter per pass:\n\n")
+        fh.write(f"Library hash: {kernel_hash()}\n\nCommands, one counter per pass:\n\n")
         fh.write("    " + cmd_pmc.format(C="FETCH_SIZE", d="fetch") + "\n")
         fh.write("    " + cmd_pmc.format(C="WRITE_SIZE", d="write") + "\n\n")
         fh.write(f"Calibration: a {mib} MiB device copy reads {mib} MiB and writes {mib} MiB; "

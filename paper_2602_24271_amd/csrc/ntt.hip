@@ -702,9 +702,10 @@ k_ntt_inv(NttJob job, Tables tb) {
 // of stage 0 (X + W Y or X - W Y, W = psi^(2^14)) and runs stages 1..14 as
 // a 2^14-point transform whose twiddles are the full transform's for that
 // half: psi_br[2^s' (2 + h) + m'] at sub-stage s', block m'.  Half a limb
-// needs 68 KB of LDS and at most 128 VGPRs per thread, so two workgroups
-// share a CU and one loads or stores while the other computes.  Outputs land at the
-// full transform's positions: standard index h 2^14 + i' at
+// needs 72 KB of LDS (the exchange buffer and round 1's twiddle rows) and
+// at most 128 VGPRs per thread, so two workgroups share a CU and one loads
+// or stores while the other computes.  Outputs land at the full
+// transform's positions: standard index h 2^14 + i' at
 // (i' mod 32) 1024 + h 512 + i' / 32.
 template <int MODE>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
@@ -822,7 +823,7 @@ k_ntt_fwd_half(NttJob job, Tables tb) {
 // before the last Gentleman-Sande stage.  Every stage but the last pairs
 // indices with the same top bit h, so half h (standard indices h 2^14 + i')
 // is an independent 2^14-point inverse with the full transform's inverse
-// twiddles for that half (the mirror of k_ntt_fwd_half): 68 KB of LDS,
+// twiddles for that half (the mirror of k_ntt_fwd_half): 72 KB of LDS,
 // two workgroups per CU.  The last stage, X + Y and (X - Y) w with
 // w = the full inverse's round-0 twiddle at slot 1, couples the halves and
 // is left to the consumer, which loads X = U[i'] and Y = V[i'] (U, V: the
