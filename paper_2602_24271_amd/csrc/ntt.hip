@@ -157,6 +157,94 @@ __device__ __forceinline__ void lds_pass_sync(bool wave_only) {
   }
 }
 
+// LDS byte address of a pointer into a __shared__ array.
+__device__ __forceinline__ uint32_t lds_addr(const uint32_t* p) {
+  return (uint32_t)(size_t)(const __attribute__((address_space(3))) uint32_t*)p;
+}
+
+// 32 LDS words at a + k STRIDE (bytes), k = 0..31, each into its own
+// register, issued and waited for inside one asm block (no read is in
+// flight past it).  Written out because the compiler pairs such reads
+// (ds_read2) into adjacent registers, which in an exchange are halves of
+// different doubles and then cost a register move each.
+template <int STRIDE>
+__device__ __forceinline__ void lds_read32(uint32_t (&w)[32], uint32_t a) {
+  static_assert(STRIDE > 0 && 31 * STRIDE < 65536, "offsets fit the 16-bit immediate");
+  asm volatile(
+      "ds_read_b32 %0, %32 offset:%c33*0\n\t"
+      "ds_read_b32 %1, %32 offset:%c33*1\n\t"
+      "ds_read_b32 %2, %32 offset:%c33*2\n\t"
+      "ds_read_b32 %3, %32 offset:%c33*3\n\t"
+      "ds_read_b32 %4, %32 offset:%c33*4\n\t"
+      "ds_read_b32 %5, %32 offset:%c33*5\n\t"
+      "ds_read_b32 %6, %32 offset:%c33*6\n\t"
+      "ds_read_b32 %7, %32 offset:%c33*7\n\t"
+      "ds_read_b32 %8, %32 offset:%c33*8\n\t"
+      "ds_read_b32 %9, %32 offset:%c33*9\n\t"
+      "ds_read_b32 %10, %32 offset:%c33*10\n\t"
+      "ds_read_b32 %11, %32 offset:%c33*11\n\t"
+      "ds_read_b32 %12, %32 offset:%c33*12\n\t"
+      "ds_read_b32 %13, %32 offset:%c33*13\n\t"
+      "ds_read_b32 %14, %32 offset:%c33*14\n\t"
+      "ds_read_b32 %15, %32 offset:%c33*15\n\t"
+      "ds_read_b32 %16, %32 offset:%c33*16\n\t"
+      "ds_read_b32 %17, %32 offset:%c33*17\n\t"
+      "ds_read_b32 %18, %32 offset:%c33*18\n\t"
+      "ds_read_b32 %19, %32 offset:%c33*19\n\t"
+      "ds_read_b32 %20, %32 offset:%c33*20\n\t"
+      "ds_read_b32 %21, %32 offset:%c33*21\n\t"
+      "ds_read_b32 %22, %32 offset:%c33*22\n\t"
+      "ds_read_b32 %23, %32 offset:%c33*23\n\t"
+      "ds_read_b32 %24, %32 offset:%c33*24\n\t"
+      "ds_read_b32 %25, %32 offset:%c33*25\n\t"
+      "ds_read_b32 %26, %32 offset:%c33*26\n\t"
+      "ds_read_b32 %27, %32 offset:%c33*27\n\t"
+      "ds_read_b32 %28, %32 offset:%c33*28\n\t"
+      "ds_read_b32 %29, %32 offset:%c33*29\n\t"
+      "ds_read_b32 %30, %32 offset:%c33*30\n\t"
+      "ds_read_b32 %31, %32 offset:%c33*31\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(w[0]), "=&v"(w[1]), "=&v"(w[2]), "=&v"(w[3]), "=&v"(w[4]), "=&v"(w[5]), "=&v"(w[6]), "=&v"(w[7]),
+        "=&v"(w[8]), "=&v"(w[9]), "=&v"(w[10]), "=&v"(w[11]), "=&v"(w[12]), "=&v"(w[13]), "=&v"(w[14]), "=&v"(w[15]),
+        "=&v"(w[16]), "=&v"(w[17]), "=&v"(w[18]), "=&v"(w[19]), "=&v"(w[20]), "=&v"(w[21]), "=&v"(w[22]), "=&v"(w[23]),
+        "=&v"(w[24]), "=&v"(w[25]), "=&v"(w[26]), "=&v"(w[27]), "=&v"(w[28]), "=&v"(w[29]), "=&v"(w[30]), "=&v"(w[31])
+      : "v"(a), "i"(STRIDE)
+      : "memory");
+}
+
+// Round R's slot offsets are e times that of element 1 (true when the
+// round's lowest register bit is 0 or at least 5).
+template <int LOGN, int R>
+constexpr bool linear_slots() {
+  for (int e = 0; e < NttShape<LOGN>::E; ++e)
+    if (slot_off<LOGN>(R, e) != e * slot_off<LOGN>(R, 1)) return false;
+  return true;
+}
+
+// One pass's words of round R's 32 elements into their halves of x.
+template <int LOGN, int R>
+__device__ __forceinline__ void take_words(double (&x)[NttShape<LOGN>::E], uint32_t a, int half) {
+  static_assert(NttShape<LOGN>::E == 32 && linear_slots<LOGN, R>(), "32 evenly spaced slots");
+  uint32_t w[32];
+  lds_read32<slot_off<LOGN>(R, 1) * 4>(w, a);
+#pragma unroll
+  for (int e = 0; e < 32; ++e) {
+    unsigned long long v = __double_as_longlong(x[e]);
+    v = half ? ((v & 0xffffffffull) | ((unsigned long long)w[e] << 32))
+             : ((v & 0xffffffff00000000ull) | w[e]);
+    x[e] = __longlong_as_double(v);
+  }
+}
+
+// Exchanges of this size read their words with lds_read32.
+template <int LOGN>
+constexpr bool word_reads() {
+  using S = NttShape<LOGN>;
+  if constexpr (S::E != 32 || S::ROUNDS != 3 || !S::SPLIT) return false;
+  else return linear_slots<LOGN, 0>() && linear_slots<LOGN, 1>() && linear_slots<LOGN, 2>() &&
+              31 * slot_off<LOGN>(0, 1) * 4 < 65536;
+}
+
 // Move the E values of every thread from round r0's index map to r1's.
 // The base addresses are made opaque per pass (inline asm), so that no
 // per-element address registers stay live across the barriers.  Each pass
@@ -166,8 +254,11 @@ __device__ __forceinline__ void lds_pass_sync(bool wave_only) {
 // arithmetic as soon as its own values have arrived.  A wave-local
 // exchange (see wave_local) orders its passes within the wavefront only;
 // it still needs wait_prev when the previous exchange was not wave-local,
-// as other wavefronts may be reading its slots.
-template <int LOGN>
+// as other wavefronts may be reading its slots.  WORDS: read each pass's
+// words one per register (lds_read32) where the size allows; measured
+// faster only for the tensor inverse (the other transforms keep the
+// compiler's paired reads).
+template <int LOGN, bool WORDS = false>
 __device__ __forceinline__ void exchange(double (&x)[NttShape<LOGN>::E], int r0, int r1,
                                          uint32_t* lds, bool wait_prev) {
   using S = NttShape<LOGN>;
@@ -193,6 +284,17 @@ __device__ __forceinline__ void exchange(double (&x)[NttShape<LOGN>::E], int r0,
       lds_pass_sync(local);
       int b1 = slot_base<LOGN>(r1, tid);
       asm volatile("" : "+v"(b1));
+      if constexpr (WORDS && word_reads<LOGN>()) {
+        const uint32_t a = lds_addr(lds + b1);
+        if (r1 == 0)
+          take_words<LOGN, 0>(x, a, half);
+        else if (r1 == 1)
+          take_words<LOGN, 1>(x, a, half);
+        else
+          take_words<LOGN, 2>(x, a, half);
+        if (half == 0) lds_pass_sync(local);
+        continue;
+      }
 #pragma unroll
       for (int c = 0; c < S::E; c += C0) {
         const uint32_t* base = lds + b1 + slot_off<LOGN>(r1, c);
@@ -898,7 +1000,8 @@ k_ntt_inv_half(NttJob job, Tables tb) {
     const int r = S::ROUNDS - 1 - rr;
     static_assert(S::ROUNDS == 3 && wave_local<14>(2, 1) && !wave_local<14>(1, 0),
                   "exchange barriers of the half inverse");
-    if (rr > 0) exchange<14>(x, r + 1, r, lds, true);
+    if (rr > 0)
+      exchange<14, MODE == INV_TENSOR || MODE == INV_TENSOR2>(x, r + 1, r, lds, true);
     inv_round<14, true>(x, r, g0, tw, p, pinv, ltw);
     g0 += S::stages(r);
   }
