@@ -185,18 +185,20 @@ struct CoefSrc {
   bool hi;
 };
 
-// The value of lane l xor 32: v_permlane32_swap exchanges the upper half
-// of one register's lanes with the lower half of another's (a VALU
-// operation, no LDS round trip); swapping a register with itself leaves the
-// partner's value in the first result for the upper lanes and in the second
-// for the lower ones.
-__device__ __forceinline__ double pair_swap(double x, bool upper) {
+// U + sg V for a pair whose U is in lane l and V in lane l + 32 (sg = +1
+// in the lower lanes, -1 in the upper): a lower lane gets U + V, an upper
+// lane U - V.  v_permlane32_swap exchanges the upper half of one
+// register's lanes with the lower half of another's (a VALU operation, no
+// LDS round trip); swapping a register with itself leaves U in every
+// lane's first result and V in every lane's second, so no lane selects.
+__device__ __forceinline__ double pair_combine(double x, double sg) {
   const unsigned long long b = __double_as_longlong(x);
   const unsigned lo = (unsigned)b, hi = (unsigned)(b >> 32);
   const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
   const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
-  const unsigned plo = upper ? l[0] : l[1], phi = upper ? h[0] : h[1];
-  return __longlong_as_double(((unsigned long long)phi << 32) | plo);
+  const double u = __longlong_as_double(((unsigned long long)h[0] << 32) | l[0]);
+  const double v = __longlong_as_double(((unsigned long long)h[1] << 32) | l[1]);
+  return __builtin_fma(sg, v, u);
 }
 
 template <bool FUSED>
@@ -206,7 +208,7 @@ __device__ __forceinline__ double coef_load(__amdgpu_buffer_rsrc_t rs, const Coe
   if constexpr (!FUSED) {
     return x;
   } else {
-    return __builtin_fma(s.sg, x, pair_swap(x, s.hi));   // lower y + x, upper y - x
+    return pair_combine(x, s.sg);   // lower U + V, upper U - V
   }
 }
 
@@ -572,7 +574,7 @@ __global__ void __launch_bounds__(256) k_moddown_lift(int n, size_t n_poly,
   const int ip = 2 * L + 1;
   const double pP = cld(tb.p, ip), pPinv = cld(tb.pinv, ip);
   const double xP = buf_load(ra, pos, L * ls);
-  const double aP = mul_bal(__builtin_fma(sg, xP, pair_swap(xP, hi)), tb.ninv_P[row], pP, pPinv);
+  const double aP = mul_bal(pair_combine(xP, sg), tb.ninv_P[row], pP, pPinv);
   // the new ciphertext's residues are stored only after every load: buffer
   // stores between them would make each limb's loads wait for the previous
   // limb's (the compiler cannot tell the buffers apart)
@@ -583,7 +585,7 @@ __global__ void __launch_bounds__(256) k_moddown_lift(int n, size_t n_poly,
     const int iq = opaque_idx(i);
     const double q = cld(tb.p, iq), qinv = cld(tb.pinv, iq);
     const double x = buf_load(ra, pos, i * ls);
-    const double r = mul_lazy(__builtin_fma(sg, x, pair_swap(x, hi)), tb.NP_inv_q[row * L + iq], q, qinv) -
+    const double r = mul_lazy(pair_combine(x, sg), tb.NP_inv_q[row * L + iq], q, qinv) -
                      mul_lazy(aP, cld(tb.P_inv_q, iq), q, qinv);
     o[i] = reduce_bal(buf_load(re, vo, i * ls) + r, q, qinv);
     y[i] = mul_bal(o[i], cld(tb.q_hat_inv, iq), q, qinv);
