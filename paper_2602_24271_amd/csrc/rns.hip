@@ -676,10 +676,12 @@ __global__ void __launch_bounds__(256) k_pointwise_plain(int n, int L, int n_ct,
 
 // out[jj * out_stride + r] = [sum_t coef[jj * k + t] * b.p[t][r]]_q per
 // residue r < per, jj < J <= 16 (int64 canonical in and out).
-// Coefficients are small centred integers (|c| < 2^15 < p/2), so each
-// product is a lazy modular product below 0.55 p; sums are reduced every
-// 16 terms (below 9.3 p).  Coefficients are uniform across the grid
-// (scalar loads).
+// Coefficients are small centred integers (|c| <= 2^15: the comparison
+// polynomial's coefficients mod a Fermat prime t <= 65537) and uniform
+// across the grid (scalar loads).  Each input v (balanced, |v| <= 2^48) is
+// split once as v = vh 2^24 + vl (split24), so that every product is an
+// exact FMA (|vh c| <= 2^39): two exact sums per output over k <= 256
+// terms (below 2^47), combined once as Wh [2^24]_q + Wl.
 __global__ void __launch_bounds__(256) k_lincomb(int n, int L, size_t per, int k, BabyPtrs b,
                                                  const int* coef, int J, int64_t* out,
                                                  size_t out_stride, Tables tb) {
@@ -687,22 +689,27 @@ __global__ void __launch_bounds__(256) k_lincomb(int n, int L, size_t per, int k
   if (gid >= per) return;
   const int i = (int)((gid / n) % L);
   const double p = cld(tb.p, i), pinv = cld(tb.pinv, i);
-  double acc[16];
+  double ah[16], al[16];
 #pragma unroll
-  for (int jj = 0; jj < 16; ++jj) acc[jj] = 0.0;
+  for (int jj = 0; jj < 16; ++jj) ah[jj] = al[jj] = 0.0;
   for (int t = 0; t < k; ++t) {
-    const double v = from_u64(b.p[t][gid], p);
+    double vh, vl;
+    split24(from_u64(b.p[t][gid], p), vh, vl);
 #pragma unroll
-    for (int jj = 0; jj < 16; ++jj)
-      if (jj < J) acc[jj] += mul_lazy(v, (double)cldi(coef, jj * k + t), p, pinv);
-    if ((t & 15) == 15) {
-#pragma unroll
-      for (int jj = 0; jj < 16; ++jj) acc[jj] = reduce_bal(acc[jj], p, pinv);
+    for (int jj = 0; jj < 16; ++jj) {
+      if (jj < J) {
+        const double c = (double)cldi(coef, jj * k + t);
+        ah[jj] = __builtin_fma(vh, c, ah[jj]);
+        al[jj] = __builtin_fma(vl, c, al[jj]);
+      }
     }
   }
+  const double t24 = cld(tb.two24, i);
 #pragma unroll
   for (int jj = 0; jj < 16; ++jj)
-    if (jj < J) out[(size_t)jj * out_stride + gid] = to_i64(reduce_bal(acc[jj], p, pinv), p);
+    if (jj < J)
+      out[(size_t)jj * out_stride + gid] =
+          to_i64(reduce_bal(mul_lazy(ah[jj], t24, p, pinv) + al[jj], p, pinv), p);
 }
 
 // The trivial encryption (Delta, 0) of 1 in each of n_ct ciphertexts.
@@ -1055,14 +1062,18 @@ hipError_t run_scale(const Dims& d, double* dt, const Tables& tb, hipStream_t st
 hipError_t run_ks_mac(const Dims& d, const double* dig, const double* evk, double* acc,
                       const Tables& tb, hipStream_t st) {
   const size_t total = (size_t)(d.L + 1) * d.n;
+  // a chunk wider than the ciphertexts present would only repeat its
+  // (clamped) loads and products: halve it down to them
+  int ch = d.ks_chunk;
+  while (ch > 4 && ch / 2 >= d.n_ct) ch /= 2;
   switch (d.L) {
 #define C_(L_) \
   case L_:                                                                                     \
-    if (d.ks_chunk == 4)                                                                       \
+    if (ch == 4)                                                                               \
       hipLaunchKernelGGL((k_ks_mac<L_, 4>), grid_for(total), dim3(256), 0, st, d.n, d.n_ct, dig, evk, acc, tb); \
-    else if (d.ks_chunk == 8)                                                                  \
+    else if (ch == 8)                                                                          \
       hipLaunchKernelGGL((k_ks_mac<L_, 8>), grid_for(total), dim3(256), 0, st, d.n, d.n_ct, dig, evk, acc, tb); \
-    else if (d.ks_chunk == 32)                                                                 \
+    else if (ch == 32)                                                                         \
       hipLaunchKernelGGL((k_ks_mac<L_, 32>), grid_for(total), dim3(256), 0, st, d.n, d.n_ct, dig, evk, acc, tb); \
     else                                                                                       \
       hipLaunchKernelGGL((k_ks_mac<L_, 16>), grid_for(total), dim3(256), 0, st, d.n, d.n_ct, dig, evk, acc, tb); \
