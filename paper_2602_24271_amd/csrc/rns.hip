@@ -681,10 +681,13 @@ __global__ void __launch_bounds__(256) k_pointwise_plain(int n, int L, int n_ct,
 // across the grid (scalar loads).  Each input v (balanced, |v| <= 2^48) is
 // split once as v = vh 2^24 + vl (split24), so that every product is an
 // exact FMA (|vh c| <= 2^39): two exact sums per output over k <= 256
-// terms (below 2^47), combined once as Wh [2^24]_q + Wl.
+// terms (below 2^47), combined once as Wh [2^24]_q + Wl.  JT: J fixed at
+// compile time (16 or 1), or 0 for any J (a branch per output and term).
+template <int JT>
 __global__ void __launch_bounds__(256) k_lincomb(int n, int L, size_t per, int k, BabyPtrs b,
-                                                 const int* coef, int J, int64_t* out,
+                                                 const int* coef, int Jr, int64_t* out,
                                                  size_t out_stride, Tables tb) {
+  const int J = JT ? JT : Jr;
   const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= per) return;
   const int i = (int)((gid / n) % L);
@@ -692,7 +695,27 @@ __global__ void __launch_bounds__(256) k_lincomb(int n, int L, size_t per, int k
   double ah[16], al[16];
 #pragma unroll
   for (int jj = 0; jj < 16; ++jj) ah[jj] = al[jj] = 0.0;
-  for (int t = 0; t < k; ++t) {
+  // babies in groups of G whose loads are all issued before their products
+  // (one load per term would leave the loop waiting on memory latency)
+  constexpr int G = 4;
+  int t = 0;
+  for (; t + G <= k; t += G) {
+    double vh[G], vl[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) split24(from_u64(b.p[t + u][gid], p), vh[u], vl[u]);
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj) {
+      if (jj < J) {
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+          const double c = (double)cldi(coef, jj * k + t + u);
+          ah[jj] = __builtin_fma(vh[u], c, ah[jj]);
+          al[jj] = __builtin_fma(vl[u], c, al[jj]);
+        }
+      }
+    }
+  }
+  for (; t < k; ++t) {
     double vh, vl;
     split24(from_u64(b.p[t][gid], p), vh, vl);
 #pragma unroll
@@ -1139,8 +1162,15 @@ hipError_t run_lincomb(const Dims& d, int k, const BabyPtrs& b, const int* coef,
   const size_t per = (size_t)d.n_ct * 2 * d.L * d.n;
   if (k < 1 || k > BabyPtrs::CAP || J < 1 || J > 16 || (J > 1 && out_stride < per))
     return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_lincomb, grid_for(per), dim3(256), 0, st, d.n, d.L, per, k, b, coef, J,
-                     out, out_stride, tb);
+  if (J == 16)
+    hipLaunchKernelGGL(k_lincomb<16>, grid_for(per), dim3(256), 0, st, d.n, d.L, per, k, b, coef,
+                       J, out, out_stride, tb);
+  else if (J == 1)
+    hipLaunchKernelGGL(k_lincomb<1>, grid_for(per), dim3(256), 0, st, d.n, d.L, per, k, b, coef,
+                       J, out, out_stride, tb);
+  else
+    hipLaunchKernelGGL(k_lincomb<0>, grid_for(per), dim3(256), 0, st, d.n, d.L, per, k, b, coef,
+                       J, out, out_stride, tb);
   return hipGetLastError();
 }
 
