@@ -239,8 +239,8 @@ int nshe_in_mask(nshe_ctx* ctx, const int64_t* x_dev, const int64_t* set_dev, in
  * LE(lo, x) * LE(x, hi) (one more multiplication).  y (or lo and hi) may be
  * one ciphertext broadcast over the column.  Workspace:
  * nshe_compare_workspace_bytes(ctx, n_ct) (about K + k + m + 27 ciphertext
- * arrays plus the multiply workspace; 0 if the context has no comparison
- * polynomial). */
+ * arrays, one operand's transform and the multiply workspace; 0 if the
+ * context has no comparison polynomial). */
 #define NSHE_CMP_LT 0
 #define NSHE_CMP_LE 1
 size_t nshe_compare_workspace_bytes(const nshe_ctx* ctx, int n_ct);

@@ -359,9 +359,11 @@ static int prepare_operand(nshe_ctx* c, double* ext, double* fx, int n_ct, hipSt
   return ntt_job_ext(c, ext, fx, n_ct * 2, 0, st);
 }
 
-// fx (NTT domain, operands; the second in fx_b, or squaring) -> dt limbs
-// 0..L-1 of the 3 components: [round(t d_k / Q)]_Q, coefficient domain.
-static int tensor_scale(nshe_ctx* c, const Ws& w, const double* fx_b, int n_ct, hipStream_t st) {
+// fx (NTT domain, operands; the first in fx_a when given, else w.fx; the
+// second in fx_b, or squaring) -> dt limbs 0..L-1 of the 3 components:
+// [round(t d_k / Q)]_Q, coefficient domain.
+static int tensor_scale(nshe_ctx* c, const Ws& w, const double* fx_b, int n_ct, hipStream_t st,
+                        const double* fx_a = nullptr) {
   Dims d = dims(c, n_ct);
   {
     // the tensor product is formed while the inverse transform loads
@@ -372,7 +374,7 @@ static int tensor_scale(nshe_ctx* c, const Ws& w, const double* fx_b, int n_ct, 
     j.nlimb = W_of(c);
     j.limb_prime = c->lp_ext;
     j.count = j.npoly * j.nlimb;
-    j.src = w.fx;
+    j.src = fx_a ? fx_a : w.fx;
     j.src_b = fx_b;
     j.src_ct_stride = (size_t)2 * W_of(c) * c->n;
     j.split_inv = d.fused;
@@ -1571,18 +1573,52 @@ static int ilog2(int x) {
 // comparison results (the last four).
 static int cmp_slots(const nshe_ctx* c) { return c->lt_K + 1 + c->lt_k + c->lt_m + 16 + 3 + 4; }
 
+// one operand's transform, [n_ct][2][W][N] doubles
+static size_t fx_bytes(const nshe_ctx* c, int n_ct) {
+  return ((size_t)n_ct * 2 * W_of(c) * c->n * sizeof(double) + 255) & ~(size_t)255;
+}
+
 size_t nshe_compare_workspace_bytes(const nshe_ctx* c, int n_ct) {
   if (check_ctx(c) || n_ct < 0 || c->lt_K == 0) return 0;
-  return (size_t)cmp_slots(c) * ct_bytes(c, n_ct) + ws_doubles(c, n_ct) * sizeof(double);
+  return (size_t)cmp_slots(c) * ct_bytes(c, n_ct) + fx_bytes(c, n_ct) +
+         ws_doubles(c, n_ct) * sizeof(double);
 }
 
 struct CmpArea {
   int64_t* slot0;
   size_t U;       // int64 words per slot
+  double* fx;     // a shared operand's transform (mul_shared)
   void* mws;      // multiply workspace
   size_t mws_bytes;
   int64_t* slot(int i) const { return slot0 + (size_t)i * U; }
 };
+
+// A product a * b relinearized (as nshe_mul_relin) whose first operand's
+// lift and transform are kept in the area's fx and reused while the next
+// product has the same first operand (`held`): the babies' and giants'
+// products share their power-of-two factor.  Same arithmetic, so the same
+// result as nshe_mul_relin.
+static int mul_shared(nshe_ctx* c, const CmpArea& a, const int64_t** held, const int64_t* x,
+                      const int64_t* y, int64_t* out, int n_ct, hipStream_t st) {
+  Ws w = carve(c, a.mws, n_ct);
+  Dims d = dims(c, n_ct);
+  const size_t W = W_of(c), N = c->n;
+  if (*held != x) {
+    HIPCHK(run_i64_to_polys(d, x, 2, w.ext, 2 * W * N, W * N, 2, c->tb, st));
+    int rc = prepare_operand(c, w.ext, a.fx, n_ct, st);
+    if (rc) return rc;
+    *held = x;
+  }
+  HIPCHK(run_i64_to_polys(d, y, 2, w.dig, 2 * W * N, W * N, 2, c->tb, st));
+  int rc = prepare_operand(c, w.dig, fx_second(c, w, n_ct), n_ct, st);
+  if (rc) return rc;
+  rc = tensor_scale(c, w, fx_second(c, w, n_ct), n_ct, st, a.fx);
+  if (rc) return rc;
+  rc = relin(c, w, n_ct, st);
+  if (rc) return rc;
+  HIPCHK(run_polys_to_i64(d, w.ext, 2, 2 * W * N, W * N, out, 0, c->tb, st));
+  return NSHE_OK;
+}
 
 // LT of the differences z (int64, n_ct ciphertexts, not in the area) into
 // out: the baby-step giant-step program of the comparison polynomial
@@ -1606,12 +1642,13 @@ static int lt_core(nshe_ctx* c, const int64_t* z, int64_t* out, int n_ct, const 
   HIPCHK(run_fill_one(d, a.slot(s_bab), c->tb, st));
   bp.p[0] = a.slot(s_bab);
   bp.p[1] = lev[1];
+  const int64_t* held = nullptr;   // the operand whose transform a.fx holds
   for (int i = 2; i < k; ++i) {
     const int h = 1 << ilog2(i), r = i - h;
     if (r == 0) {
       bp.p[i] = lev[ilog2(i) + 1];
     } else {
-      int rc = nshe_mul_relin(c, bp.p[h], bp.p[r], a.slot(s_bab + i), n_ct, a.mws, a.mws_bytes, stv);
+      int rc = mul_shared(c, a, &held, bp.p[h], bp.p[r], a.slot(s_bab + i), n_ct, st);
       if (rc) return rc;
       bp.p[i] = a.slot(s_bab + i);
     }
@@ -1623,7 +1660,7 @@ static int lt_core(nshe_ctx* c, const int64_t* z, int64_t* out, int n_ct, const 
     if (r == 0) {
       gi[j] = lev[ilog2(k) + ilog2(j) + 1];
     } else {
-      int rc = nshe_mul_relin(c, gi[h], gi[r], a.slot(s_gi + j), n_ct, a.mws, a.mws_bytes, stv);
+      int rc = mul_shared(c, a, &held, gi[h], gi[r], a.slot(s_gi + j), n_ct, st);
       if (rc) return rc;
       gi[j] = a.slot(s_gi + j);
     }
@@ -1677,8 +1714,10 @@ static int cmp_checks(nshe_ctx* c, int n_ct, void* ws, size_t ws_bytes, CmpArea*
   const size_t cb = ct_bytes(c, n_ct);
   a->slot0 = static_cast<int64_t*>(ws);
   a->U = cb / sizeof(int64_t);
-  a->mws = static_cast<char*>(ws) + (size_t)cmp_slots(c) * cb;
-  a->mws_bytes = ws_bytes - (size_t)cmp_slots(c) * cb;
+  a->fx = reinterpret_cast<double*>(static_cast<char*>(ws) + (size_t)cmp_slots(c) * cb);
+  const size_t used = (size_t)cmp_slots(c) * cb + fx_bytes(c, n_ct);
+  a->mws = static_cast<char*>(ws) + used;
+  a->mws_bytes = ws_bytes - used;
   return NSHE_OK;
 }
 
