@@ -327,7 +327,7 @@ int nshe_sum_slots(nshe_ctx* ctx, const int64_t* in_dev, int64_t* out_dev, int n
  * shapes, on min(32, wave limit) ciphertexts), then the per-ciphertext
  * time of a level at 1, 2, 4, ... ciphertexts up to the wave limit
  * (max_wave_ct if > 0, and what ws_bytes holds), keeping the smallest wave
- * within 3% of the best rate.  The result becomes the context's tuning and
+ * within 1% of the best rate.  The result becomes the context's tuning and
  * is copied to *out_host (if not NULL); *ms_per_ct_host (if not NULL)
  * receives the best per-ciphertext level time in ms.  Needs the relin key.
  * The workspace contents are overwritten; the sample is only read.  The

@@ -1997,7 +1997,8 @@ int nshe_autotune(nshe_ctx* c, const int64_t* sample, int n_sample, int max_wave
   c->tune = best;
 
   // 2. wave size: per-ciphertext time of a level for 1, 2, 4, ... up to
-  // `fit` ciphertexts; the smallest wave within 3% of the best rate
+  // `fit` ciphertexts; the smallest wave within 1% of the best rate (a
+  // wave half as large costs about 2% of the rate, measured)
   std::vector<std::pair<int, double>> rates;
   for (int n = 1;; n = std::min(2 * n, fit)) {
     Ws wn = carve(c, ws, n);
@@ -2012,7 +2013,7 @@ int nshe_autotune(nshe_ctx* c, const int64_t* sample, int n_sample, int max_wave
   double rbest = 1e300;
   for (auto& r : rates) rbest = std::min(rbest, r.second);
   for (auto& r : rates)
-    if (r.second <= 1.03 * rbest) { best.wave_ct = r.first; break; }
+    if (r.second <= 1.01 * rbest) { best.wave_ct = r.first; break; }
   drop_graphs(c);
   c->tune = best;
   if (out) *out = best;
