@@ -553,7 +553,6 @@ __global__ void __launch_bounds__(256) k_moddown_lift(int n, size_t n_poly,
                                                       double* __restrict__ ext, Tables tb) {
   constexpr int K = L + 1;
   constexpr int W = 2 * L + 1;
-  constexpr int LB = L + 1;
   const PolyBlock pb = poly_block(n, n_poly);   // poly = ct * 2 + b
   if (!pb.ok) return;
   const int t = (int)threadIdx.x, lane = t & 63;
