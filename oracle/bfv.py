@@ -222,8 +222,9 @@ def _scale_round(params: Params, d) -> np.ndarray:
     return round_div(params.t * d, params.Q) % params.Q
 
 
-def multiply(params: Params, x, y) -> tuple:
-    """Textbook BFV product (before relinearization), three components."""
+def tensor(params: Params, x, y) -> tuple:
+    """The exact tensor components d0 = a0 b0, d1 = a0 b1 + a1 b0, d2 = a1 b1
+    of two ciphertexts' centred lifts, as integer polynomials."""
     Q = params.Q
     a0, a1 = centred(x[0], Q), centred(x[1], Q)
     b0, b1 = centred(y[0], Q), centred(y[1], Q)
@@ -234,7 +235,12 @@ def multiply(params: Params, x, y) -> tuple:
     d0 = B.to_int(B.inverse(B.mul(fa0, fb0)))
     d1 = B.to_int(B.inverse(B.add(B.mul(fa0, fb1), B.mul(fa1, fb0))))
     d2 = B.to_int(B.inverse(B.mul(fa1, fb1)))
-    return tuple(_scale_round(params, d) for d in (d0, d1, d2))
+    return (d0, d1, d2)
+
+
+def multiply(params: Params, x, y) -> tuple:
+    """Textbook BFV product (before relinearization), three components."""
+    return tuple(_scale_round(params, d) for d in tensor(params, x, y))
 
 
 def square(params: Params, x) -> tuple:
@@ -297,6 +303,17 @@ def square_relin(params: Params, rk: RelinKey, x) -> tuple:
 
 def mul_relin(params: Params, rk: RelinKey, x, y) -> tuple:
     return relinearize(params, rk, multiply(params, x, y))
+
+
+def mul_sum_relin(params: Params, rk: RelinKey, pairs) -> tuple:
+    """A sum of products with one scale-and-round and one relinearization:
+    the pairs' exact tensors are added as integers, then [round(t D / Q)]_Q
+    and relinearized (it decrypts to the sum of the products)."""
+    D = None
+    for x, y in pairs:
+        d = tensor(params, x, y)
+        D = d if D is None else tuple(u + v for u, v in zip(D, d))
+    return relinearize(params, rk, tuple(_scale_round(params, d) for d in D))
 
 
 def finish(params: Params, z) -> tuple:

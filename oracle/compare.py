@@ -23,7 +23,9 @@ chain's squarings:
   of two below i); giants W_j = w^(k j), j < m (powers of two from the
   chain, others W_h * W_(j-h)); k = 2^ceil((K-1)/2), m = 2^(K-1) / k;
   G_j = sum_i c_(2(jk+i)+1) B_i (scalar products, centred coefficients);
-  g = G_0 + sum_{j>=1} G_j * W_j;  LT = c_(p-1) levels[K] + z * g.
+  g = G_0 + sum_{j>=1} G_j * W_j, the m - 1 products' exact tensors added
+  before one scale-and-round and one relinearization (bfv.mul_sum_relin);
+  LT = c_(p-1) levels[K] + z * g.
 
 LE(x, y) = 1 - LT(y, x); BETWEEN(x, lo, hi) = LE(lo, x) * LE(x, hi), the
 product of two comparisons (Sec. 4.3, BETWEEN).
@@ -191,11 +193,14 @@ def lt(params: bfv.Params, rk: bfv.RelinKey, x, y) -> tuple:
         h, r = _split(j)
         giants.append(levels[k.bit_length() + h.bit_length() - 1] if r == 0
                       else bfv.mul_relin(params, rk, giants[h], giants[r]))
-    g = None
-    for j in range(m):
-        Gj = lincomb(params, babies, [centred(c[2 * (j * k + i) + 1], p) for i in range(k)])
-        term = Gj if j == 0 else bfv.mul_relin(params, rk, Gj, giants[j])
-        g = term if g is None else query.add(params, g, term)
+    # g = G_0 + sum_{j >= 1} G_j W_j, the products' tensors summed before one
+    # scale-and-round and one relinearization (bfv.mul_sum_relin)
+    G = [lincomb(params, babies, [centred(c[2 * (j * k + i) + 1], p) for i in range(k)])
+         for j in range(m)]
+    g = G[0]
+    if m > 1:
+        g = query.add(params, g, bfv.mul_sum_relin(params, rk,
+                                                   [(G[j], giants[j]) for j in range(1, m)]))
     return query.add(params, scalar_mul(params, levels[K], centred(c[p - 1], p)),
                      bfv.mul_relin(params, rk, z, g))
 

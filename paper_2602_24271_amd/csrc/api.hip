@@ -225,11 +225,11 @@ static Dims dims(const nshe_ctx* c, int n_ct) {
 
 enum Kind { K_SUB, K_LIFT, K_NTT_FWD, K_NTT_INV_TENSOR, K_NTT_INV, K_SCALE, K_NTT_DIGIT,
             K_KS_MAC, K_MODDOWN, K_CONVERT, K_AUTOMORPH, K_ADD, K_LINCOMB, K_MODDOWN_LIFT,
-            K_COUNT };
+            K_TENSOR_MAC, K_COUNT };
 static const char* kKindName[K_COUNT] = {"sub",   "lift",      "ntt_fwd", "ntt_inv_tensor",
                                          "ntt_inv", "scale", "ntt_digit", "ks_mac",
                                          "moddown", "convert", "automorph", "add", "lincomb",
-                                         "moddown_lift"};
+                                         "moddown_lift", "tensor_mac"};
 
 static hipEvent_t take_event(nshe_ctx* c) {
   if (!c->pool.empty()) {
@@ -1578,9 +1578,14 @@ static size_t fx_bytes(const nshe_ctx* c, int n_ct) {
   return ((size_t)n_ct * 2 * W_of(c) * c->n * sizeof(double) + 255) & ~(size_t)255;
 }
 
+// the summed tensor, [n_ct][3][W][N] doubles
+static size_t dacc_bytes(const nshe_ctx* c, int n_ct) {
+  return ((size_t)n_ct * 3 * W_of(c) * c->n * sizeof(double) + 255) & ~(size_t)255;
+}
+
 size_t nshe_compare_workspace_bytes(const nshe_ctx* c, int n_ct) {
   if (check_ctx(c) || n_ct < 0 || c->lt_K == 0) return 0;
-  return (size_t)cmp_slots(c) * ct_bytes(c, n_ct) + fx_bytes(c, n_ct) +
+  return (size_t)cmp_slots(c) * ct_bytes(c, n_ct) + fx_bytes(c, n_ct) + dacc_bytes(c, n_ct) +
          ws_doubles(c, n_ct) * sizeof(double);
 }
 
@@ -1588,6 +1593,7 @@ struct CmpArea {
   int64_t* slot0;
   size_t U;       // int64 words per slot
   double* fx;     // a shared operand's transform (mul_shared)
+  double* dacc;   // the giants' products' summed tensor
   void* mws;      // multiply workspace
   size_t mws_bytes;
   int64_t* slot(int i) const { return slot0 + (size_t)i * U; }
@@ -1665,8 +1671,11 @@ static int lt_core(nshe_ctx* c, const int64_t* z, int64_t* out, int n_ct, const 
       gi[j] = a.slot(s_gi + j);
     }
   }
-  // g = G_0 + sum_j G_j W_j, G_j = sum_i c_(2(jk+i)+1) B_i in chunks of 16
+  // g = G_0 + sum_{j>=1} G_j W_j, G_j = sum_i c_(2(jk+i)+1) B_i in chunks of
+  // 16.  The products' tensors are summed in the extended basis (exact: Q B
+  // exceeds m N Q^2), then scaled, rounded and relinearized once.
   int64_t* g = a.slot(s_g);
+  Ws w = carve(c, a.mws, n_ct);
   for (int j0 = 0; j0 < m; j0 += 16) {
     const int J = std::min(16, m - j0);
     {
@@ -1680,10 +1689,35 @@ static int lt_core(nshe_ctx* c, const int64_t* z, int64_t* out, int n_ct, const 
         HIPCHK(run_sum_i64(d, Gj, nullptr, 0, 0, g, c->tb, st));
         continue;
       }
-      int rc = nshe_mul_relin(c, Gj, gi[j], a.slot(s_T), n_ct, a.mws, a.mws_bytes, stv);
+      int rc = load_two(c, w, Gj, gi[j], n_ct, st);
       if (rc) return rc;
-      HIPCHK(run_sum_i64(d, g, a.slot(s_T), 0, 1, g, c->tb, st));
+      Prof pf(c, K_TENSOR_MAC, st, 3.0 * n_ct * W_of(c) * c->n);
+      HIPCHK(run_tensor_mac(d, w.fx, fx_second(c, w, n_ct), a.dacc, j == 1 ? 1 : 0, c->tb, st));
     }
+  }
+  if (m > 1) {
+    NttJob j{};
+    j.base = a.dacc;
+    j.out = w.dt;
+    j.poly_stride = (size_t)W_of(c) * c->n;
+    j.npoly = n_ct * 3;
+    j.nlimb = W_of(c);
+    j.limb_prime = c->lp_ext;
+    j.count = j.npoly * j.nlimb;
+    j.split_inv = d.fused;
+    {
+      Prof pf(c, K_NTT_INV, st, ntt_work(c, j.count));
+      HIPCHK(run_ntt(c->log2n, j, c->tb, 4, st));
+    }
+    {
+      Prof pf(c, K_SCALE, st, 3.0 * n_ct * c->n);
+      HIPCHK(run_scale(d, w.dt, c->tb, st));
+    }
+    int rc = relin(c, w, n_ct, st);
+    if (rc) return rc;
+    const size_t W = W_of(c), N = c->n;
+    HIPCHK(run_polys_to_i64(d, w.ext, 2, 2 * W * N, W * N, a.slot(s_T), 0, c->tb, st));
+    HIPCHK(run_sum_i64(d, g, a.slot(s_T), 0, 1, g, c->tb, st));
   }
   // out = c_(p-1) z^(p-1) + z g
   int rc = nshe_mul_relin(c, lev[0], g, a.slot(s_T), n_ct, a.mws, a.mws_bytes, stv);
@@ -1715,7 +1749,8 @@ static int cmp_checks(nshe_ctx* c, int n_ct, void* ws, size_t ws_bytes, CmpArea*
   a->slot0 = static_cast<int64_t*>(ws);
   a->U = cb / sizeof(int64_t);
   a->fx = reinterpret_cast<double*>(static_cast<char*>(ws) + (size_t)cmp_slots(c) * cb);
-  const size_t used = (size_t)cmp_slots(c) * cb + fx_bytes(c, n_ct);
+  a->dacc = reinterpret_cast<double*>(reinterpret_cast<char*>(a->fx) + fx_bytes(c, n_ct));
+  const size_t used = (size_t)cmp_slots(c) * cb + fx_bytes(c, n_ct) + dacc_bytes(c, n_ct);
   a->mws = static_cast<char*>(ws) + used;
   a->mws_bytes = ws_bytes - used;
   return NSHE_OK;

@@ -78,7 +78,7 @@ struct Tables {
   unsigned long long* fault;   // B->Q lift outside its proven range (never)
 };
 
-enum { NTT_INPLACE = 0, NTT_DIGIT = 1, INV_TENSOR = 2, INV_TENSOR2 = 3 };
+enum { NTT_INPLACE = 0, NTT_DIGIT = 1, INV_TENSOR = 2, INV_TENSOR2 = 3, INV_PLAIN = 4 };
 
 struct NttJob {
   double* base;              // first limb of poly 0 (input of in-place kinds)
@@ -103,7 +103,9 @@ struct NttJob {
 };
 
 // run_ntt directions: 0 forward in place, 1 inverse in place, 2 forward of
-// relinearization digits, 3 inverse of the tensor product formed on load.
+// relinearization digits, 3 inverse of the tensor product formed on load,
+// 4 inverse of tensor components already formed (base) into out, in the
+// layout direction 3 writes.
 
 hipError_t run_ntt(int log2n, const NttJob& job, const Tables& tb, int dir, hipStream_t st);
 int ntt_rounds(int log2n, int* loge, int* r0);
@@ -157,6 +159,8 @@ struct BabyPtrs {
   static constexpr int CAP = 256;
   const int64_t* p[CAP];
 };
+hipError_t run_tensor_mac(const Dims& d, const double* fa, const double* fb, double* acc,
+                          int first, const Tables& tb, hipStream_t st);
 hipError_t run_lincomb(const Dims& d, int k, const BabyPtrs& b, const int* coef, int J,
                        int64_t* out, size_t out_stride, const Tables& tb, hipStream_t st);
 hipError_t run_fill_one(const Dims& d, int64_t* out, const Tables& tb, hipStream_t st);

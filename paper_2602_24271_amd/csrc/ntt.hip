@@ -1030,10 +1030,12 @@ template <int LOGN>
 static hipError_t launch_ntt(const NttJob& job, const Tables& tb, int dir, hipStream_t st) {
   using S = NttShape<LOGN>;
   if constexpr (LOGN == 15) {
-    if ((dir == 1 || dir == 3) && job.split_inv && tb.tw_half_inv) {
+    if ((dir == 1 || dir == 3 || dir == 4) && job.split_inv && tb.tw_half_inv) {
       dim3 grid(per_xcd(job, dir, 2) * 8), block(512);
       if (dir == 1)
         hipLaunchKernelGGL((k_ntt_inv_half<NTT_INPLACE>), grid, block, 0, st, job, tb);
+      else if (dir == 4)
+        hipLaunchKernelGGL((k_ntt_inv_half<INV_PLAIN>), grid, block, 0, st, job, tb);
       else if (job.src_b == nullptr)
         hipLaunchKernelGGL((k_ntt_inv_half<INV_TENSOR>), grid, block, 0, st, job, tb);
       else
@@ -1048,6 +1050,11 @@ static hipError_t launch_ntt(const NttJob& job, const Tables& tb, int dir, hipSt
         hipLaunchKernelGGL((k_ntt_fwd_half<NTT_DIGIT>), grid, block, 0, st, job, tb);
       return hipGetLastError();
     }
+  }
+  // direction 4 without the split inverse: a plain inverse into out
+  if (dir == 4) {
+    if (!job.out || job.out == job.base) return hipErrorInvalidValue;
+    dir = 1;
   }
   const int per = per_xcd(job, dir, 1);
   dim3 grid(per * 8), block(S::T);

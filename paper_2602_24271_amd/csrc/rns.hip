@@ -673,6 +673,40 @@ __global__ void __launch_bounds__(256) k_pointwise_plain(int n, int L, int n_ct,
 
 // ----------------------------------------------------------- comparisons ---
 
+// acc += the tensor of two transformed operands (acc = it when first):
+// per limb of the extended basis, pointwise in the NTT domain, d0 = a0 b0,
+// d1 = a0 b1 + a1 b0, d2 = a1 b1, each running sum kept as a balanced
+// residue.  fa, fb: [n_ct][2][W][N] (balanced transform outputs); acc:
+// [n_ct][3][W][N].  Summing products' tensors before one scale-and-round
+// is exact while the sum stays inside the extended basis' range.
+__global__ void __launch_bounds__(256) k_tensor_mac(int n, int W, size_t total,
+                                                    const double* __restrict__ fa,
+                                                    const double* __restrict__ fb,
+                                                    double* __restrict__ acc, int first,
+                                                    Tables tb) {
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= total) return;
+  const size_t per = (size_t)W * n;
+  const size_t ct = gid / per, r = gid - ct * per;
+  const int l = (int)(r / n);                 // extended-basis limb = prime index
+  const double p = cld(tb.p, l), pinv = cld(tb.pinv, l);
+  const double* a = fa + ct * 2 * per + r;
+  const double* b = fb + ct * 2 * per + r;
+  double* o = acc + ct * 3 * per + r;
+  const double a0 = a[0], a1 = a[per], b0 = b[0], b1 = b[per];
+  double d0 = mul_lazy(a0, b0, p, pinv);
+  double d1 = mul_lazy(a0, b1, p, pinv) + mul_lazy(a1, b0, p, pinv);
+  double d2 = mul_lazy(a1, b1, p, pinv);
+  if (!first) {
+    d0 += o[0];
+    d1 += o[per];
+    d2 += o[2 * per];
+  }
+  o[0] = reduce_bal(d0, p, pinv);
+  o[per] = reduce_bal(d1, p, pinv);
+  o[2 * per] = reduce_bal(d2, p, pinv);
+}
+
 // out[jj * out_stride + r] = [sum_t coef[jj * k + t] * b.p[t][r]]_q per
 // residue r < per, jj < J <= 16 (int64 canonical in and out).
 // Coefficients are small centred integers (|c| <= 2^15: the comparison
@@ -1153,6 +1187,15 @@ hipError_t run_pointwise_plain(const Dims& d, double* fx, const double* pt, cons
   const size_t total = (size_t)d.n_ct * 2 * d.L * d.n;
   hipLaunchKernelGGL(k_pointwise_plain, grid_for(total), dim3(256), 0, st, d.n, d.L, d.n_ct, fx, pt,
                      tb);
+  return hipGetLastError();
+}
+
+hipError_t run_tensor_mac(const Dims& d, const double* fa, const double* fb, double* acc,
+                          int first, const Tables& tb, hipStream_t st) {
+  const int W = 2 * d.L + 1;
+  const size_t total = (size_t)d.n_ct * W * d.n;
+  hipLaunchKernelGGL(k_tensor_mac, grid_for(total), dim3(256), 0, st, d.n, W, total, fa, fb, acc,
+                     first, tb);
   return hipGetLastError();
 }
 
