@@ -234,13 +234,15 @@ int nshe_in_mask(nshe_ctx* ctx, const int64_t* x_dev, const int64_t* set_dev, in
  *   products, exact mod Q); g = G_0 + sum_{j>=1} G_j * W_j;
  *   LT = c_(p-1) levels[K] + z * g,
  * every product a multiplication followed by relinearization (as
- * nshe_mul_relin / nshe_square_relin).  op 0 gives LT(x, y); op 1 gives
+ * nshe_mul_relin / nshe_square_relin), except that the m - 1 products
+ * G_j * W_j have their exact tensors added and their sum scaled, rounded
+ * and relinearized once.  op 0 gives LT(x, y); op 1 gives
  * LE(x, y) = (Delta, 0) - LT(y, x).  nshe_between gives
  * LE(lo, x) * LE(x, hi) (one more multiplication).  y (or lo and hi) may be
  * one ciphertext broadcast over the column.  Workspace:
  * nshe_compare_workspace_bytes(ctx, n_ct) (about K + k + m + 27 ciphertext
- * arrays, one operand's transform and the multiply workspace; 0 if the
- * context has no comparison polynomial). */
+ * arrays, one operand's transform, one summed tensor and the multiply
+ * workspace; 0 if the context has no comparison polynomial). */
 #define NSHE_CMP_LT 0
 #define NSHE_CMP_LE 1
 size_t nshe_compare_workspace_bytes(const nshe_ctx* ctx, int n_ct);
