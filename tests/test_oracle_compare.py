@@ -87,6 +87,26 @@ def test_lt_every_pair_in_range_t17(t17):
         assert list(bfv.decrypt_slots(pr, sk, out)) == [int(a < b) for a, b in chunk]
 
 
+def test_mul_sum_relin_decrypts_to_the_sum_of_products(t17):
+    """One scale-and-round and relinearization of summed tensors decrypts to
+    the slot-wise sum of the products (mod t), within the noise budget, and
+    for a single pair it is the textbook product exactly."""
+    pr, sk, rk = t17
+    rng = np.random.default_rng(12)
+    xs = [rng.integers(0, 17, 8) for _ in range(5)]
+    ys = [rng.integers(0, 17, 8) for _ in range(5)]
+    pairs = [(_enc(pr, sk, x, 500 + i), _enc(pr, sk, y, 600 + i))
+             for i, (x, y) in enumerate(zip(xs, ys))]
+    out = bfv.mul_sum_relin(pr, rk, pairs)
+    want = sum(x * y for x, y in zip(xs, ys)) % 17
+    assert list(bfv.decrypt_slots(pr, sk, out)) == list(want)
+    assert bfv.noise_bits(pr, sk, out, encoding.encode(want, pr.t)) > 0
+    one = bfv.mul_sum_relin(pr, rk, pairs[:1])
+    ref = bfv.mul_relin(pr, rk, *pairs[0])
+    for u, v in zip(one, ref):
+        assert np.array_equal(u, v)
+
+
 def test_lt_wraps_outside_the_range(t17):
     """|x - y| > (p-1)/2 wraps: the result is membership of (x - y) mod p in
     the negative half, not x < y (the domain limit of the method)."""
