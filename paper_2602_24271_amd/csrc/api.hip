@@ -992,15 +992,23 @@ static double* fx_second(const nshe_ctx* c, const Ws& w, int n_ct) {
   return w.dig + (size_t)n_ct * 2 * W_of(c) * c->n;
 }
 
+// int64 ciphertexts -> lifted into ext ([n_ct][2][W][N]) -> transformed
+// into fx: the conversion and the lift in one kernel.
+static int prepare_i64(nshe_ctx* c, const int64_t* in, double* ext, double* fx, int n_ct,
+                       hipStream_t st) {
+  Dims d = dims(c, n_ct);
+  {
+    Prof pf(c, K_LIFT, st, 2.0 * n_ct * c->n);
+    HIPCHK(run_i64_lift(d, in, ext, c->tb, st));
+  }
+  return ntt_job_ext(c, ext, fx, n_ct * 2, 0, st);
+}
+
 static int load_two(nshe_ctx* c, const Ws& w, const int64_t* a, const int64_t* b, int n_ct,
                     hipStream_t st) {
-  Dims d = dims(c, n_ct);
-  const size_t W = W_of(c), N = c->n;
-  HIPCHK(run_i64_to_polys(d, a, 2, w.ext, 2 * W * N, W * N, 2, c->tb, st));
-  HIPCHK(run_i64_to_polys(d, b, 2, w.dig, 2 * W * N, W * N, 2, c->tb, st));
-  int rc = prepare_operand(c, w.ext, w.fx, n_ct, st);
+  int rc = prepare_i64(c, a, w.ext, w.fx, n_ct, st);
   if (rc) return rc;
-  return prepare_operand(c, w.dig, fx_second(c, w, n_ct), n_ct, st);
+  return prepare_i64(c, b, w.dig, fx_second(c, w, n_ct), n_ct, st);
 }
 
 int nshe_mul_relin(nshe_ctx* c, const int64_t* a, const int64_t* b, int64_t* out, int n_ct,
@@ -1610,13 +1618,11 @@ static int mul_shared(nshe_ctx* c, const CmpArea& a, const int64_t** held, const
   Dims d = dims(c, n_ct);
   const size_t W = W_of(c), N = c->n;
   if (*held != x) {
-    HIPCHK(run_i64_to_polys(d, x, 2, w.ext, 2 * W * N, W * N, 2, c->tb, st));
-    int rc = prepare_operand(c, w.ext, a.fx, n_ct, st);
+    int rc = prepare_i64(c, x, w.ext, a.fx, n_ct, st);
     if (rc) return rc;
     *held = x;
   }
-  HIPCHK(run_i64_to_polys(d, y, 2, w.dig, 2 * W * N, W * N, 2, c->tb, st));
-  int rc = prepare_operand(c, w.dig, fx_second(c, w, n_ct), n_ct, st);
+  int rc = prepare_i64(c, y, w.dig, fx_second(c, w, n_ct), n_ct, st);
   if (rc) return rc;
   rc = tensor_scale(c, w, fx_second(c, w, n_ct), n_ct, st, a.fx);
   if (rc) return rc;

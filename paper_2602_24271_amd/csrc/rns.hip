@@ -628,6 +628,34 @@ __global__ void __launch_bounds__(256) k_sub_lift(int n, size_t n_poly,
   lift_tail<L>(o, y, S, rs, vo, ls, tb);
 }
 
+// Canonical int64 residues of n_poly polynomials ([n_poly][L][N]) into ext
+// limbs 0..L-1 (balanced) and their lift into limbs L..2L: the conversion
+// (k_i64_to_polys) and k_lift in one pass, the same arithmetic.
+template <int L>
+__global__ void __launch_bounds__(256) k_i64_lift(int n, size_t n_poly,
+                                                  const int64_t* __restrict__ in,
+                                                  double* __restrict__ ext, Tables tb) {
+  constexpr int W = 2 * L + 1;
+  const PolyBlock pb = poly_block(n, n_poly);
+  if (!pb.ok) return;
+  const int64_t* ip = in + pb.pc * (size_t)L * n + pb.c;
+  const auto rs = make_rsrc(ext + pb.pc * (size_t)W * n, (unsigned)(W * n * 8));
+  const unsigned vo = (unsigned)pb.c * 8, ls = (unsigned)n * 8;
+  double o[L], y[L];
+  double S = 0.0;
+#pragma unroll
+  for (int i = 0; i < L; ++i) {
+    const int iq = opaque_idx(i);
+    const double q = cld(tb.p, iq), qinv = cld(tb.pinv, iq);
+    o[i] = from_u64(ip[(size_t)i * n], q);
+    y[i] = mul_bal(o[i], cld(tb.q_hat_inv, iq), q, qinv);
+    S += y[i] * cld(tb.recip, iq);
+  }
+#pragma unroll
+  for (int i = 0; i < L; ++i) buf_store(o[i], rs, vo, i * ls);
+  lift_tail<L>(o, y, S, rs, vo, ls, tb);
+}
+
 // ------------------------------------------------------ plaintext products ---
 
 // The basis plaintext of one slot: m_i = N^-1 zeta^-i mod t, zinv = zeta^-1
@@ -1054,6 +1082,22 @@ hipError_t run_moddown_finish(const Dims& d, const double* acc, const double* dt
   case L_:                                                                                     \
     hipLaunchKernelGGL(k_moddown_finish<L_>, grid_for(total, d.block), dim3(d.block), 0, st,   \
                        d.n, d.n_ct, acc, dt, out, tb);                                         \
+    break;
+    NSHE_L_CASES(C_)
+#undef C_
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t run_i64_lift(const Dims& d, const int64_t* in, double* ext, const Tables& tb,
+                        hipStream_t st) {
+  const size_t np = (size_t)d.n_ct * 2;
+  switch (d.L) {
+#define C_(L_)                                                                            \
+  case L_:                                                                                \
+    hipLaunchKernelGGL(k_i64_lift<L_>, poly_grid(np, d.n, d.block), dim3(d.block), 0, st, \
+                       d.n, np, in, ext, tb);                                             \
     break;
     NSHE_L_CASES(C_)
 #undef C_
