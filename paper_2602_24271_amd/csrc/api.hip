@@ -397,7 +397,7 @@ static int tensor_scale(nshe_ctx* c, const Ws& w, const double* fx_b, int n_ct, 
 // instead (only with the split inverse).
 static int relin(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st,
                  const double* key = nullptr, double* out = nullptr, bool lift_out = false,
-                 int64_t* finish_out = nullptr) {
+                 int64_t* finish_out = nullptr, int64_t* i64_out = nullptr) {
   if (!key) key = c->evk;
   if (!out) out = w.ext;
   Dims d = dims(c, n_ct);
@@ -425,7 +425,10 @@ static int relin(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st,
   if (rc) return rc;
   if (finish_out && d.fused) {
     Prof pf(c, K_MODDOWN, st, 2.0 * n_ct * c->n);
-    HIPCHK(run_moddown_finish(d, w.acc, w.dt, finish_out, c->tb, st));
+    HIPCHK(run_moddown_finish(d, w.acc, w.dt, finish_out, c->tb, st, 1));
+  } else if (i64_out && d.fused) {
+    Prof pf(c, K_MODDOWN, st, 2.0 * n_ct * c->n);
+    HIPCHK(run_moddown_finish(d, w.acc, w.dt, i64_out, c->tb, st, 0));
   } else if (lift_out && d.fused) {
     Prof pf(c, K_MODDOWN_LIFT, st, 2.0 * n_ct * c->n);
     HIPCHK(run_moddown_lift(d, w.acc, w.dt, out, c->tb, st));
@@ -434,6 +437,31 @@ static int relin(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st,
     HIPCHK(run_moddown(d, w.acc, w.dt, out, c->tb, st));
   }
   return NSHE_OK;
+}
+
+// Relinearize and write the result to the int64 buffer out (canonical): the
+// mod-down writes it directly after the split inverse, else a conversion
+// pass follows.
+static int relin_i64(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st, int64_t* out) {
+  Dims d = dims(c, n_ct);
+  if (d.fused) return relin(c, w, n_ct, st, nullptr, nullptr, false, nullptr, out);
+  int rc = relin(c, w, n_ct, st);
+  if (rc) return rc;
+  const size_t W = W_of(c), N = c->n;
+  HIPCHK(run_polys_to_i64(d, w.ext, 2, 2 * W * N, W * N, out, 0, c->tb, st));
+  return NSHE_OK;
+}
+
+// int64 ciphertexts -> lifted into ext ([n_ct][2][W][N]) -> transformed
+// into fx: the conversion and the lift in one kernel.
+static int prepare_i64(nshe_ctx* c, const int64_t* in, double* ext, double* fx, int n_ct,
+                       hipStream_t st) {
+  Dims d = dims(c, n_ct);
+  {
+    Prof pf(c, K_LIFT, st, 2.0 * n_ct * c->n);
+    HIPCHK(run_i64_lift(d, in, ext, c->tb, st));
+  }
+  return ntt_job_ext(c, ext, fx, n_ct * 2, 0, st);
 }
 
 // One squaring level on the ciphertexts in ext.  In a chain of squarings
@@ -978,30 +1006,16 @@ int nshe_square_relin(nshe_ctx* c, const int64_t* in, int64_t* out, int n_ct, vo
   if (!in || !out) return fail(NSHE_EINVAL, "null buffer");
   hipStream_t st = static_cast<hipStream_t>(stream);
   Ws w = carve(c, ws, n_ct);
-  Dims d = dims(c, n_ct);
-  const size_t W = W_of(c), N = c->n;
-  HIPCHK(run_i64_to_polys(d, in, 2, w.ext, 2 * W * N, W * N, 2, c->tb, st));
-  rc = square_level(c, w, n_ct, st);
+  rc = prepare_i64(c, in, w.ext, w.fx, n_ct, st);
   if (rc) return rc;
-  HIPCHK(run_polys_to_i64(d, w.ext, 2, 2 * W * N, W * N, out, 0, c->tb, st));
-  return NSHE_OK;
+  rc = tensor_scale(c, w, nullptr, n_ct, st);
+  if (rc) return rc;
+  return relin_i64(c, w, n_ct, st, out);
 }
 
 // The second operand's transform sits in the digit region after its lift.
 static double* fx_second(const nshe_ctx* c, const Ws& w, int n_ct) {
   return w.dig + (size_t)n_ct * 2 * W_of(c) * c->n;
-}
-
-// int64 ciphertexts -> lifted into ext ([n_ct][2][W][N]) -> transformed
-// into fx: the conversion and the lift in one kernel.
-static int prepare_i64(nshe_ctx* c, const int64_t* in, double* ext, double* fx, int n_ct,
-                       hipStream_t st) {
-  Dims d = dims(c, n_ct);
-  {
-    Prof pf(c, K_LIFT, st, 2.0 * n_ct * c->n);
-    HIPCHK(run_i64_lift(d, in, ext, c->tb, st));
-  }
-  return ntt_job_ext(c, ext, fx, n_ct * 2, 0, st);
 }
 
 static int load_two(nshe_ctx* c, const Ws& w, const int64_t* a, const int64_t* b, int n_ct,
@@ -1019,16 +1033,11 @@ int nshe_mul_relin(nshe_ctx* c, const int64_t* a, const int64_t* b, int64_t* out
   if (!a || !b || !out) return fail(NSHE_EINVAL, "null buffer");
   hipStream_t st = static_cast<hipStream_t>(stream);
   Ws w = carve(c, ws, n_ct);
-  Dims d = dims(c, n_ct);
-  const size_t W = W_of(c), N = c->n;
   rc = load_two(c, w, a, b, n_ct, st);
   if (rc) return rc;
   rc = tensor_scale(c, w, fx_second(c, w, n_ct), n_ct, st);
   if (rc) return rc;
-  rc = relin(c, w, n_ct, st);
-  if (rc) return rc;
-  HIPCHK(run_polys_to_i64(d, w.ext, 2, 2 * W * N, W * N, out, 0, c->tb, st));
-  return NSHE_OK;
+  return relin_i64(c, w, n_ct, st, out);
 }
 
 int nshe_multiply(nshe_ctx* c, const int64_t* a, const int64_t* b, int64_t* out3, int n_ct,
@@ -1615,8 +1624,6 @@ struct CmpArea {
 static int mul_shared(nshe_ctx* c, const CmpArea& a, const int64_t** held, const int64_t* x,
                       const int64_t* y, int64_t* out, int n_ct, hipStream_t st) {
   Ws w = carve(c, a.mws, n_ct);
-  Dims d = dims(c, n_ct);
-  const size_t W = W_of(c), N = c->n;
   if (*held != x) {
     int rc = prepare_i64(c, x, w.ext, a.fx, n_ct, st);
     if (rc) return rc;
@@ -1626,10 +1633,7 @@ static int mul_shared(nshe_ctx* c, const CmpArea& a, const int64_t** held, const
   if (rc) return rc;
   rc = tensor_scale(c, w, fx_second(c, w, n_ct), n_ct, st, a.fx);
   if (rc) return rc;
-  rc = relin(c, w, n_ct, st);
-  if (rc) return rc;
-  HIPCHK(run_polys_to_i64(d, w.ext, 2, 2 * W * N, W * N, out, 0, c->tb, st));
-  return NSHE_OK;
+  return relin_i64(c, w, n_ct, st, out);
 }
 
 // LT of the differences z (int64, n_ct ciphertexts, not in the area) into
@@ -1719,10 +1723,8 @@ static int lt_core(nshe_ctx* c, const int64_t* z, int64_t* out, int n_ct, const 
       Prof pf(c, K_SCALE, st, 3.0 * n_ct * c->n);
       HIPCHK(run_scale(d, w.dt, c->tb, st));
     }
-    int rc = relin(c, w, n_ct, st);
+    int rc = relin_i64(c, w, n_ct, st, a.slot(s_T));
     if (rc) return rc;
-    const size_t W = W_of(c), N = c->n;
-    HIPCHK(run_polys_to_i64(d, w.ext, 2, 2 * W * N, W * N, a.slot(s_T), 0, c->tb, st));
     HIPCHK(run_sum_i64(d, g, a.slot(s_T), 0, 1, g, c->tb, st));
   }
   // out = c_(p-1) z^(p-1) + z g

@@ -133,10 +133,12 @@ hipError_t run_moddown(const Dims& d, const double* acc, const double* dt, doubl
 // the last level's mod-down written to int64 with the mask's finish,
 // (Delta, 0) - z; needs d.fused
 hipError_t run_moddown_finish(const Dims& d, const double* acc, const double* dt, int64_t* out,
-                              const Tables& tb, hipStream_t st);
-// subtraction into ext followed by its lift (the first squaring's operand)
+                              const Tables& tb, hipStream_t st,
+                              int finish = 1);
+// int64 ciphertexts into ext followed by their lift (a product's operands)
 hipError_t run_i64_lift(const Dims& d, const int64_t* in, double* ext, const Tables& tb,
                         hipStream_t st);
+// subtraction into ext followed by its lift (the first squaring's operand)
 hipError_t run_sub_lift(const Dims& d, const int64_t* x, const int64_t* y, int y_bcast,
                         double* ext, const Tables& tb, hipStream_t st);
 // mod-down of the split inverse's output followed by the lift of the result

@@ -459,15 +459,16 @@ __global__ void __launch_bounds__(256) k_moddown(int n, int n_ct, const double* 
   }
 }
 
-// The last level's mod-down (split inverse, pairs as in k_moddown FUSED)
-// written straight to the caller's int64 output with the mask's finish: out
-// = (Delta, 0) - z, i.e. every residue negated and [Delta]_{q_i} added to
-// the constant coefficient of c0; canonical residues in [0, q_i).
+// A mod-down (split inverse, pairs as in k_moddown FUSED) written straight
+// to the caller's int64 output, canonical residues in [0, q_i): with finish,
+// the mask's finish out = (Delta, 0) - z (every residue negated and
+// [Delta]_{q_i} added to the constant coefficient of c0); without, z.
 template <int L>
 __global__ void __launch_bounds__(256) k_moddown_finish(int n, int n_ct,
                                                         const double* __restrict__ acc,
                                                         const double* __restrict__ dt,
-                                                        int64_t* __restrict__ out, Tables tb) {
+                                                        int64_t* __restrict__ out, int finish,
+                                                        Tables tb) {
   constexpr int K = L + 1;
   constexpr int W = 2 * L + 1;
   const int per = n >> 1;
@@ -498,10 +499,12 @@ __global__ void __launch_bounds__(256) k_moddown_finish(int n, int n_ct,
     const double npq = cld(tb.NP_inv_q, i), pq = cld(tb.P_inv_q, i);
     const double r_lo = mul_lazy(lo, npq, q, qinv) - mul_lazy(aP_lo, pq, q, qinv);
     const double r_hi = mul_lazy(hi, npq, q, qinv) - mul_lazy(aP_hi, pq, q, qinv);
-    // -(e + r), plus Delta at coefficient 0 of c0
-    double z_lo = -(e[(size_t)i * n] + r_lo);
-    if (b == 0 && c == 0) z_lo += cld(tb.delta_q, i);
-    const double z_hi = -(e[(size_t)i * n + hn] + r_hi);
+    // finish: -(e + r), plus Delta at coefficient 0 of c0 (sg = -1 exactly
+    // negates); else e + r
+    const double sg = finish ? -1.0 : 1.0;
+    double z_lo = sg * (e[(size_t)i * n] + r_lo);
+    if (finish && b == 0 && c == 0) z_lo += cld(tb.delta_q, i);
+    const double z_hi = sg * (e[(size_t)i * n + hn] + r_hi);
     o[(size_t)i * n] = to_i64(reduce_bal(z_lo, q, qinv), q);
     o[(size_t)i * n + hn] = to_i64(reduce_bal(z_hi, q, qinv), q);
   }
@@ -1074,14 +1077,14 @@ hipError_t run_lift(const Dims& d, double* ext, const Tables& tb, hipStream_t st
 }
 
 hipError_t run_moddown_finish(const Dims& d, const double* acc, const double* dt, int64_t* out,
-                              const Tables& tb, hipStream_t st) {
+                              const Tables& tb, hipStream_t st, int finish) {
   if (!d.fused) return hipErrorInvalidValue;
   const size_t total = (size_t)d.n_ct * 2 * (d.n / 2);
   switch (d.L) {
 #define C_(L_)                                                                                 \
   case L_:                                                                                     \
     hipLaunchKernelGGL(k_moddown_finish<L_>, grid_for(total, d.block), dim3(d.block), 0, st,   \
-                       d.n, d.n_ct, acc, dt, out, tb);                                         \
+                       d.n, d.n_ct, acc, dt, out, finish, tb);                         \
     break;
     NSHE_L_CASES(C_)
 #undef C_
