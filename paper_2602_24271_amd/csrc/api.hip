@@ -394,10 +394,12 @@ static int tensor_scale(nshe_ctx* c, const Ws& w, const double* fx_b, int n_ct, 
 // lift_out: also lift the result (limbs L..2L of out), for a squaring that
 // follows at once (only with the split inverse).
 // finish_out: write the result to this int64 buffer with the mask's finish
-// instead (only with the split inverse).
+// instead (only with the split inverse); i64_out: write it there as it is.
+// accumulate: add the result into out (limbs 0..L-1) instead of storing it.
 static int relin(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st,
                  const double* key = nullptr, double* out = nullptr, bool lift_out = false,
-                 int64_t* finish_out = nullptr, int64_t* i64_out = nullptr) {
+                 int64_t* finish_out = nullptr, int64_t* i64_out = nullptr,
+                 bool accumulate = false) {
   if (!key) key = c->evk;
   if (!out) out = w.ext;
   Dims d = dims(c, n_ct);
@@ -434,7 +436,7 @@ static int relin(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st,
     HIPCHK(run_moddown_lift(d, w.acc, w.dt, out, c->tb, st));
   } else {
     Prof pf(c, K_MODDOWN, st, 2.0 * n_ct * c->n);
-    HIPCHK(run_moddown(d, w.acc, w.dt, out, c->tb, st));
+    HIPCHK(run_moddown(d, w.acc, w.dt, out, c->tb, st, accumulate ? 1 : 0));
   }
   return NSHE_OK;
 }
@@ -1319,24 +1321,23 @@ static unsigned inv_mod_2n(const nshe_ctx* c, uint32_t g) {
 // One rotation of the ciphertexts in w.ext by Galois element g into `out`
 // ([ct][2][W][N] limbs 0..L-1).
 static int rotate_ext(nshe_ctx* c, const Ws& w, int n_ct, uint32_t g, const double* key,
-                      double* out, hipStream_t st) {
+                      double* out, hipStream_t st, bool accumulate = false) {
   Dims d = dims(c, n_ct);
   {
     Prof pf(c, K_AUTOMORPH, st, 2.0 * n_ct * c->L * c->n);
     HIPCHK(run_automorph(d, inv_mod_2n(c, g), w.ext, w.dt, c->tb, st));
   }
-  return relin(c, w, n_ct, st, key, out);
+  return relin(c, w, n_ct, st, key, out, false, nullptr, nullptr, accumulate);
 }
 
 // ct <- ct + rot_g(ct) over the sum elements, on the ciphertexts in w.ext
 static int sum_slots_ext(nshe_ctx* c, const Ws& w, int n_ct, const std::vector<uint32_t>& els,
                          const std::vector<const double*>& keys, hipStream_t st) {
-  Dims d = dims(c, n_ct);
+  // the rotation's mod-down adds its result into the running sum in ext
+  // (the automorphism has read ext before)
   for (size_t k = 0; k < els.size(); ++k) {
-    int rc = rotate_ext(c, w, n_ct, els[k], keys[k], w.fx, st);
+    int rc = rotate_ext(c, w, n_ct, els[k], keys[k], w.ext, st, true);
     if (rc) return rc;
-    Prof pf(c, K_ADD, st, 2.0 * n_ct * c->L * c->n);
-    HIPCHK(run_add_bal(d, w.ext, w.fx, c->tb, st));
   }
   return NSHE_OK;
 }

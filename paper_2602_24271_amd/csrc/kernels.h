@@ -129,7 +129,8 @@ hipError_t run_scale(const Dims& d, double* dt, const Tables& tb, hipStream_t st
 hipError_t run_ks_mac(const Dims& d, const double* dig, const double* evk, double* acc,
                       const Tables& tb, hipStream_t st);
 hipError_t run_moddown(const Dims& d, const double* acc, const double* dt, double* ext,
-                       const Tables& tb, hipStream_t st);
+                       const Tables& tb, hipStream_t st,
+                       int accumulate = 0);
 // the last level's mod-down written to int64 with the mask's finish,
 // (Delta, 0) - z; needs d.fused
 hipError_t run_moddown_finish(const Dims& d, const double* acc, const double* dt, int64_t* out,

@@ -409,7 +409,8 @@ __global__ void __launch_bounds__(256) k_ks_mac(int n, int n_ct, const double* d
 template <int L, bool FUSED>
 __global__ void __launch_bounds__(256) k_moddown(int n, int n_ct, const double* __restrict__ acc,
                                                  const double* __restrict__ dt,
-                                                 double* __restrict__ ext, Tables tb) {
+                                                 double* __restrict__ ext, int accumulate,
+                                                 Tables tb) {
   constexpr int K = L + 1;
   constexpr int W = 2 * L + 1;
   const int per = FUSED ? n >> 1 : n;      // threads per (ct, component)
@@ -433,7 +434,8 @@ __global__ void __launch_bounds__(256) k_moddown(int n, int n_ct, const double* 
       const double q = cld(tb.p, i), qinv = cld(tb.pinv, i);
       const double r = mul_lazy(a[(size_t)i * n], cld(tb.NP_inv_q, i), q, qinv) -
                        mul_lazy(aP, cld(tb.P_inv_q, i), q, qinv);
-      o[(size_t)i * n] = reduce_bal(e[(size_t)i * n] + r, q, qinv);
+      const double z = reduce_bal(e[(size_t)i * n] + r, q, qinv);
+      o[(size_t)i * n] = accumulate ? reduce_bal(o[(size_t)i * n] + z, q, qinv) : z;
     }
   } else {
     const int ht = n >> 6;                 // 512: a half transform's threads
@@ -453,8 +455,10 @@ __global__ void __launch_bounds__(256) k_moddown(int n, int n_ct, const double* 
       const double npq = cld(tb.NP_inv_q, i), pq = cld(tb.P_inv_q, i);
       const double r_lo = mul_lazy(lo, npq, q, qinv) - mul_lazy(aP_lo, pq, q, qinv);
       const double r_hi = mul_lazy(hi, npq, q, qinv) - mul_lazy(aP_hi, pq, q, qinv);
-      o[(size_t)i * n] = reduce_bal(e[(size_t)i * n] + r_lo, q, qinv);
-      o[(size_t)i * n + hn] = reduce_bal(e[(size_t)i * n + hn] + r_hi, q, qinv);
+      const double z_lo = reduce_bal(e[(size_t)i * n] + r_lo, q, qinv);
+      const double z_hi = reduce_bal(e[(size_t)i * n + hn] + r_hi, q, qinv);
+      o[(size_t)i * n] = accumulate ? reduce_bal(o[(size_t)i * n] + z_lo, q, qinv) : z_lo;
+      o[(size_t)i * n + hn] = accumulate ? reduce_bal(o[(size_t)i * n + hn] + z_hi, q, qinv) : z_hi;
     }
   }
 }
@@ -1189,17 +1193,17 @@ hipError_t run_ks_mac(const Dims& d, const double* dig, const double* evk, doubl
 }
 
 hipError_t run_moddown(const Dims& d, const double* acc, const double* dt, double* ext,
-                       const Tables& tb, hipStream_t st) {
+                       const Tables& tb, hipStream_t st, int accumulate) {
   const size_t total = (size_t)d.n_ct * 2 * (d.fused ? d.n / 2 : d.n);
   switch (d.L) {
 #define C_(L_)                                                                              \
   case L_:                                                                                  \
     if (d.fused)                                                                            \
       hipLaunchKernelGGL((k_moddown<L_, true>), grid_for(total, d.block), dim3(d.block), 0, \
-                         st, d.n, d.n_ct, acc, dt, ext, tb);                                \
+                         st, d.n, d.n_ct, acc, dt, ext, accumulate, tb);                    \
     else                                                                                    \
       hipLaunchKernelGGL((k_moddown<L_, false>), grid_for(total, d.block), dim3(d.block), 0, \
-                         st, d.n, d.n_ct, acc, dt, ext, tb);                                \
+                         st, d.n, d.n_ct, acc, dt, ext, accumulate, tb);                    \
     break;
     NSHE_L_CASES(C_)
 #undef C_
