@@ -3,13 +3,13 @@
  * hot path: word-level BFV ciphertext arithmetic on batch-encoded columns.
  *
  * What the calls compute (NSHEDB, arXiv 2602.24271):
- *   - BFV subtraction of two ciphertexts (Sec. 2.1.5, BFV operations);
- *   - one ciphertext multiplication followed by relinearization (Sec. 2.1.5;
- *     Sec. 2.1.3 notes relinearization after each multiplication, and that a
+ *   - BFV subtraction of two ciphertexts (Sec. 2.1.6, BFV operations);
+ *   - one ciphertext multiplication followed by relinearization (Sec. 2.1.6;
+ *     Sec. 2.1.2 notes relinearization after each multiplication, and that a
  *     product's depth is max(depth(A), depth(B)) + 1);
  *   - the equality mask EQ(x, y) = 1 - (x - y)^(p-1) (Eq. eq:equality),
  *     evaluated by exponentiation by squaring with ceil(log2(p-1))
- *     multiplications (Sec. 4.3, equality checks; Table table:noise_levels).
+ *     multiplications (Sec. 4.3.1, equality checks; Table table:noise_levels).
  *     For the paper's p = t = 65537 (Sec. 5.1) this is 16 squarings.
  *
  * Every result is an exact integer function of the inputs (the textbook
@@ -49,8 +49,9 @@
  * Errors: every int-returning call returns NSHE_OK (0) or a negative code;
  * nshe_last_error() gives a message for the calling thread.  Arguments are
  * validated on the host before any work is enqueued (null pointers, sizes,
- * alignment, parameter ranges); a rejected call enqueues nothing.  Residues
- * are NOT range-checked on the device (residues outside [0, q_i) give
+ * alignment, parameter ranges, the depth budget); a rejected call enqueues
+ * nothing.  Residues are range-checked on the device only under the debug
+ * switch NSHE_DEBUG_CHECK_INPUTS (otherwise residues outside [0, q_i) give
  * undefined - but memory-safe - results).  Asynchronous device faults are
  * reported by the next synchronising HIP call.  No C++ exception crosses
  * the ABI.  Calls on one context from several host threads must not
@@ -71,8 +72,12 @@ extern "C" {
 #define NSHE_ESHAPE -2   /* sizes inconsistent with the context */
 #define NSHE_ENOMEM -3   /* workspace too small, or context allocation failed */
 #define NSHE_EDEVICE -4  /* a HIP runtime call failed */
-#define NSHE_EDEPTH -5   /* t - 1 is not a power of two (EQ chain needs it) */
-#define NSHE_ENOKEY -6   /* relinearization key not set */
+#define NSHE_EDEPTH -5   /* the operation's multiplicative depth exceeds the
+                            context's depth budget (see nshe_budget) */
+#define NSHE_ENOKEY -6   /* relinearization (or Galois) key not set */
+#define NSHE_EUNSUPPORTED -7 /* not defined for these parameters: EQ needs
+                            t - 1 = 2^k, comparisons a prime t = 2^K + 1,
+                            slot operations t = 1 (mod 2N) */
 
 #define NSHE_MAX_L 24        /* data primes */
 #define NSHE_MAX_LOG2N 15    /* ring degree up to 32768 */
@@ -107,7 +112,65 @@ typedef struct {
   uint64_t ext_primes[32];
   size_t ct_words;       /* int64 words of one ciphertext: 2 * L * N */
   size_t relin_key_words;/* int64 words of the relin key: L * 2 * (L+1) * N */
+  int32_t depth_budget;  /* multiplications a fresh ciphertext takes (nshe_budget) */
+  int32_t lt_depth;      /* depth of the comparison program, -1 without one */
+  double fresh_bits;     /* noise budget of a fresh encryption, bits */
+  double level_bits;     /* bits one multiplication costs (the model's) */
 } nshe_info;
+
+/* Noise budget and multiplicative depth (Sec. 2.1.2: every multiplication
+ * adds and amplifies noise, and depth(A x B) = max(depth(A), depth(B)) + 1;
+ * Table table:noise_levels gives each operator's depth).  A ciphertext
+ * decrypts correctly while log2(Q / (2 |t (c0 + c1 s) - Q m|)) > 0.  The
+ * library's model (an average-case estimate, not a worst-case bound):
+ *   fresh_bits = log2 Q - log2(2 t (19 + t))   (client errors |e| <= 19:
+ *                a rounded Gaussian of sigma 3.2 clipped at 6 sigma, and a
+ *                ternary secret);
+ *   level_bits = log2 t + log2 N + 2           per multiplication with
+ *                relinearization (one bit above the canonical-embedding
+ *                growth t N sqrt(8/3));
+ *   depth_budget = floor((fresh_bits - 8) / level_bits), >= 0.
+ * It stays below the exact noise the test oracle measures at every level
+ * of the EQ chain.  At the paper's parameters (Sec. 5.1) it gives 799.1,
+ * 33 and 23.  nshe_budget_of needs no device (host arithmetic only). */
+typedef struct {
+  int32_t depth_budget;
+  int32_t lt_depth;      /* depth of the comparison program, -1 without one */
+  double fresh_bits;
+  double level_bits;
+} nshe_budget;
+int nshe_budget_of(const nshe_params* params, nshe_budget* out_host);
+
+/* Depth an operation adds to its inputs (for fresh inputs, the whole
+ * result's depth):
+ *   NSHE_OP_ADD        sub, add, sum, rotate, sum_slots: 0 (rotations'
+ *                      key switching adds noise, not depth);
+ *   NSHE_OP_MUL        multiply, square_relin, mul_relin (SELECT): 1;
+ *   NSHE_OP_MUL_PLAIN  mul_plain, extract (a plaintext product with
+ *                      coefficients up to t/2): 1;
+ *   NSHE_OP_EQ         eq_mask, eq_mask_batched (GROUP BY): k, t - 1 = 2^k;
+ *   NSHE_OP_IN         in_mask with arg = k members: EQ + 1 if k > 1 (the
+ *                      k-way sum, the paper's ceil(log(k)/p));
+ *   NSHE_OP_LT         compare (LT, LE): the program's depth (lt_depth,
+ *                      18 at p = 65537) + 1 for its scalar combination;
+ *   NSHE_OP_BETWEEN    between: LT + 1;
+ *   NSHE_OP_JOIN       join_sum: EQ + 1 (Table table:noise_levels) + 1 for
+ *                      the plaintext product inside Broadcast.
+ * Every call with a fixed depth (all but the additions) returns
+ * NSHE_EDEPTH, enqueuing nothing, when that depth on fresh inputs exceeds
+ * the budget.  The library cannot see an input's history: a caller that
+ * chains calls keeps a depth per ciphertext and asks nshe_depth_after,
+ * which returns NSHE_EDEPTH (and still sets *out_depth) when
+ * in_depth + the operation's depth exceeds the budget.  NSHE_EUNSUPPORTED
+ * names an operation these parameters do not have. */
+#define NSHE_OP_ADD 0
+#define NSHE_OP_MUL 1
+#define NSHE_OP_MUL_PLAIN 2
+#define NSHE_OP_EQ 3
+#define NSHE_OP_IN 4
+#define NSHE_OP_LT 5
+#define NSHE_OP_BETWEEN 6
+#define NSHE_OP_JOIN 7
 
 /* Create a context on HIP device `hip_device`: validates the parameters,
  * selects the extension basis and uploads its tables (this call allocates
@@ -115,28 +178,31 @@ typedef struct {
 int nshe_ctx_create(const nshe_params* params, int hip_device, nshe_ctx** out);
 int nshe_ctx_destroy(nshe_ctx* ctx);
 int nshe_ctx_info(const nshe_ctx* ctx, nshe_info* out);
+int nshe_op_depth(const nshe_ctx* ctx, int op, int arg, int* depth_host);
+int nshe_depth_after(const nshe_ctx* ctx, int op, int arg, int in_depth, int* out_depth_host);
 
-/* Install the relinearization key (Sec. 2.1.3).  Copies and transforms
- * `evk_dev` (layout above) into context-owned memory on `stream` and waits
- * for it; `evk_dev` may be freed on return.  Allocates the context-owned
- * key store on first use and a temporary of the same size during the call
- * (set-up, not the evaluation path). */
-int nshe_set_relin_key(nshe_ctx* ctx, const int64_t* evk_dev, void* stream);
+/* Install the relinearization key (Sec. 2.1.2).  Copies and transforms
+ * `evk_dev` (layout above; n_words must be L * 2 * (L+1) * N, else
+ * NSHE_ESHAPE) into context-owned memory on `stream` and waits for it;
+ * `evk_dev` may be freed on return.  Allocates the context-owned key store
+ * on first use and a temporary of the same size during the call (set-up,
+ * not the evaluation path). */
+int nshe_set_relin_key(nshe_ctx* ctx, const int64_t* evk_dev, size_t n_words, void* stream);
 
 /* Device scratch needed by the evaluation calls for n_ct ciphertexts. */
 size_t nshe_workspace_bytes(const nshe_ctx* ctx, int n_ct);
 
-/* out = [x - y]_Q, component-wise, for n_ct ciphertext pairs (Sec. 2.1.5).
+/* out = [x - y]_Q, component-wise, for n_ct ciphertext pairs (Sec. 2.1.6).
  * out may alias x or y. */
 int nshe_sub(nshe_ctx* ctx, const int64_t* x_dev, const int64_t* y_dev,
              int64_t* out_dev, int n_ct, void* stream);
 
-/* out = relin(in * in): one squaring level of the EQ chain (Sec. 4.3).
+/* out = relin(in * in): one squaring level of the EQ chain (Sec. 4.3.1).
  * out may alias in. */
 int nshe_square_relin(nshe_ctx* ctx, const int64_t* in_dev, int64_t* out_dev,
                       int n_ct, void* ws_dev, size_t ws_bytes, void* stream);
 
-/* out = relin(a * b) (Sec. 2.1.5 multiplication; SELECT and AND, Eq.
+/* out = relin(a * b) (Sec. 2.1.6 multiplication; SELECT and AND, Eq.
  * eq:select and Table tab:operator-support, are this call). */
 int nshe_mul_relin(nshe_ctx* ctx, const int64_t* a_dev, const int64_t* b_dev,
                    int64_t* out_dev, int n_ct, void* ws_dev, size_t ws_bytes,
@@ -190,7 +256,7 @@ int nshe_eq_mask_batched(nshe_ctx* ctx, const nshe_item* items_host,
                          int n_items, int wave_ct, int use_graph, void* ws_dev,
                          size_t ws_bytes, void* stream);
 
-/* BFV addition (Sec. 2.1.5): out = [a + b]_Q per residue, int64
+/* BFV addition (Sec. 2.1.6): out = [a + b]_Q per residue, int64
  * [n_ct][2][L][N] canonical residues.  No workspace. */
 int nshe_add(nshe_ctx* ctx, const int64_t* a_dev, const int64_t* b_dev,
              int64_t* out_dev, int n_ct, void* stream);
@@ -203,14 +269,14 @@ int nshe_sum(nshe_ctx* ctx, const int64_t* in_dev, int k, int64_t* out_dev,
              int n_ct, void* stream);
 
 /* Set membership, IN(x, S) = sum over y in S of EQ(x, y) (Eq. eq:in,
- * Sec. 4.3 range and set queries): x_dev is one column of n_ct
+ * Sec. 4.2.2, range and set queries): x_dev is one column of n_ct
  * ciphertexts, set_dev holds the k members as k single ciphertexts
  * (int64 [k][2][L][N], each broadcast over the column).  With distinct
  * members out_dev decrypts to the indicator [x in S]; a member given twice
  * counts twice.  The k equality masks run as one batched call (waves of
  * wave_ct ciphertexts, 0 = the tuned wave else 32; use_graph as for
  * nshe_eq_mask_batched) into the workspace, then are summed.  GROUP BY
- * (one mask per group value, Sec. 4.3) is nshe_eq_mask_batched with items
+ * (one mask per group value, Sec. 4.2.2) is nshe_eq_mask_batched with items
  * (x, value_j, out_j, n_ct, y_broadcast = 1).  ws_bytes must cover
  * nshe_in_workspace_bytes(ctx, n_ct, k, wave_ct). */
 size_t nshe_in_workspace_bytes(const nshe_ctx* ctx, int n_ct, int k, int wave_ct);
@@ -218,7 +284,7 @@ int nshe_in_mask(nshe_ctx* ctx, const int64_t* x_dev, const int64_t* set_dev, in
                  int64_t* out_dev, int n_ct, int wave_ct, int use_graph,
                  void* ws_dev, size_t ws_bytes, void* stream);
 
-/* Range comparisons (Eq. eq:inequality; BETWEEN, Sec. 4.3).  LT(x, y) is
+/* Range comparisons (Eq. eq:inequality; BETWEEN, Sec. 4.2.2).  LT(x, y) is
  * the sum over a in A = {-(p-1)/2, ..., -1} of 1 - (x - y - a)^(p-1), i.e.
  * the encrypted indicator of x - y in the negative half of Z_p: [x < y] when
  * |x - y| <= (p-1)/2 (larger differences wrap around).  It is evaluated as
@@ -254,7 +320,7 @@ int nshe_between(nshe_ctx* ctx, const int64_t* x_dev, const int64_t* lo_dev,
                  void* ws_dev, size_t ws_bytes, void* stream);
 
 /* Plaintext products, Extract and Broadcast (the derived operations of
- * Sec. 2.1.5) and the fused equi-join aggregation (Sec. 4.3, JOIN).
+ * Sec. 2.1.6) and the fused equi-join aggregation (Sec. 4.2.2, JOIN).
  *   nshe_mul_plain  out = ([c0 m]_Q, [c1 m]_Q) for the plaintext polynomial
  *                   m (int64 [N], coefficients in [0, t), taken as centred
  *                   representatives), exact in Z[X]/(X^N + 1);
@@ -283,7 +349,7 @@ int nshe_join_sum(nshe_ctx* ctx, const int64_t* a_key_dev, const int64_t* b_key_
                   int64_t* out_dev, int n_ct, void* ws_dev, size_t ws_bytes, void* stream);
 
 /* Slot rotations and the rotate-and-add aggregation (COUNT and SUM,
- * Sec. 4.3 aggregation).  Slots follow the 2 x N/2 layout: slot s < N/2 is
+ * Sec. 4.2.2, aggregation).  Slots follow the 2 x N/2 layout: slot s < N/2 is
  * the plaintext's value at psi^(3^s), slot N/2 + s at psi^(-3^s) (psi a
  * primitive 2N-th root of unity mod t), so the automorphism X -> X^g with
  * g = 3^r mod 2N rotates each half left by r and g = 2N - 1 swaps the
@@ -291,8 +357,9 @@ int nshe_join_sum(nshe_ctx* ctx, const int64_t* a_key_dev, const int64_t* b_key_
  * second from sigma_g(s) back to s with the Galois key of g:
  *   key_g  int64 [L][2][L+1][N], digit j = ([-a_j s + e_j + P g_j
  *          sigma_g(s)]_{PQ}, a_j) (the relin key's format with sigma_g(s)
- *          in place of s^2); copied and transformed into context memory
- *          (waits for `stream`; allocates on the first key for g);
+ *          in place of s^2, n_words as for the relin key); copied and
+ *          transformed into context memory (waits for `stream`; allocates
+ *          on the first key for g);
  *   out    = ([sigma_g(c0) + round(sum_j D_j b_j / P)]_Q,
  *             [round(sum_j D_j a_j / P)]_Q), D_j = [sigma_g(c1)]_{q_j}.
  * nshe_sum_slots replaces each ciphertext by ct + rot(ct) for the Galois
@@ -301,7 +368,8 @@ int nshe_join_sum(nshe_ctx* ctx, const int64_t* a_key_dev, const int64_t* b_key_
  * nshe_sum_slots of a 0/1 mask, SUM nshe_sum_slots of a column times the
  * mask (nshe_mul_relin).  Workspace: nshe_workspace_bytes(ctx, n_ct).
  * NSHE_ENOKEY names a missing Galois key. */
-int nshe_set_galois_key(nshe_ctx* ctx, uint32_t g, const int64_t* key_dev, void* stream);
+int nshe_set_galois_key(nshe_ctx* ctx, uint32_t g, const int64_t* key_dev, size_t n_words,
+                        void* stream);
 int nshe_galois_elements(const nshe_ctx* ctx, uint32_t* out_host, int max_out, int* n_out_host);
 int nshe_rotate(nshe_ctx* ctx, const int64_t* in_dev, uint32_t g, int64_t* out_dev,
                 int n_ct, void* ws_dev, size_t ws_bytes, void* stream);
@@ -365,6 +433,33 @@ int nshe_ntt(nshe_ctx* ctx, const int64_t* in_dev, int64_t* out_dev,
  * Results are exact either way.  (Synchronises `stream` to read.) */
 int nshe_margin_events(nshe_ctx* ctx, uint64_t* count_host, void* stream);
 int nshe_reset_margin_events(nshe_ctx* ctx, void* stream);
+
+/* The same events per call site of the lift (counts_host[i] for site i,
+ * min(max_counts, NSHE_MARGIN_SITES) entries, *n_counts_host set):
+ *   0  a product operand's lift (k_lift: batched waves' first level)
+ *   1  the scale-and-round's lift of [t d]_Q
+ *   2  the same after the split inverse (N = 2^15)
+ *   3  the mod-down fused with the next squaring's lift
+ *   4  the subtraction fused with the first squaring's lift
+ *   5  the lift of a product's int64 operands
+ * (Synchronises `stream`.) */
+#define NSHE_MARGIN_SITES 6
+int nshe_margin_sites(nshe_ctx* ctx, uint64_t* counts_host, int max_counts, int* n_counts_host,
+                      void* stream);
+
+/* Test and debugging switches (off in a new context; not for production):
+ *   NSHE_DEBUG_WIDE_LIFT_WINDOW  the lift takes its exact decision whenever
+ *     its estimate S lies within 1/4 of a half-integer instead of 2^-40:
+ *     floor(S) is still exact there, so results do not change, and about
+ *     half of all coefficients go through the exact path (and are counted);
+ *   NSHE_DEBUG_CHECK_INPUTS  every call that reads int64 ciphertexts first
+ *     checks on the device that each residue lies in [0, q_i) and returns
+ *     NSHE_EINVAL, enqueuing nothing more, if one does not (synchronises
+ *     the stream; keys and plaintexts are not checked).
+ * Setting the switches drops the batched call's captured graphs. */
+#define NSHE_DEBUG_WIDE_LIFT_WINDOW 1u
+#define NSHE_DEBUG_CHECK_INPUTS 2u
+int nshe_set_debug(nshe_ctx* ctx, uint32_t flags);
 
 /* Kernel timing.  nshe_profile(ctx, 1) starts recording a pair of HIP
  * events on the call's stream around every kernel launch of subsequent

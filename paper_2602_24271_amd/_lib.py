@@ -22,7 +22,23 @@ class NsheParams(ctypes.Structure):
 class NsheInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_uint32), ("L", ctypes.c_int32), ("L_ext", ctypes.c_int32),
                 ("squarings", ctypes.c_int32), ("ext_primes", ctypes.c_uint64 * 32),
-                ("ct_words", ctypes.c_size_t), ("relin_key_words", ctypes.c_size_t)]
+                ("ct_words", ctypes.c_size_t), ("relin_key_words", ctypes.c_size_t),
+                ("depth_budget", ctypes.c_int32), ("lt_depth", ctypes.c_int32),
+                ("fresh_bits", ctypes.c_double), ("level_bits", ctypes.c_double)]
+
+
+class NsheBudget(ctypes.Structure):
+    _fields_ = [("depth_budget", ctypes.c_int32), ("lt_depth", ctypes.c_int32),
+                ("fresh_bits", ctypes.c_double), ("level_bits", ctypes.c_double)]
+
+
+# error codes and constants of include/nshe.h
+NSHE_EINVAL, NSHE_ESHAPE, NSHE_ENOMEM, NSHE_EDEVICE = -1, -2, -3, -4
+NSHE_EDEPTH, NSHE_ENOKEY, NSHE_EUNSUPPORTED = -5, -6, -7
+OPS = {"add": 0, "mul": 1, "mul_plain": 2, "eq": 3, "in": 4, "lt": 5, "between": 6, "join": 7}
+NSHE_MARGIN_SITES = 6
+NSHE_DEBUG_WIDE_LIFT_WINDOW = 1
+NSHE_DEBUG_CHECK_INPUTS = 2
 
 
 class NsheItem(ctypes.Structure):
@@ -49,7 +65,12 @@ SIGNATURES = {
     "nshe_ctx_create": (_I, [ctypes.POINTER(NsheParams), _I, ctypes.POINTER(_P)]),
     "nshe_ctx_destroy": (_I, [_P]),
     "nshe_ctx_info": (_I, [_P, ctypes.POINTER(NsheInfo)]),
-    "nshe_set_relin_key": (_I, [_P, _P, _P]),
+    "nshe_set_relin_key": (_I, [_P, _P, _SZ, _P]),
+    "nshe_budget_of": (_I, [ctypes.POINTER(NsheParams), ctypes.POINTER(NsheBudget)]),
+    "nshe_op_depth": (_I, [_P, _I, _I, ctypes.POINTER(_I)]),
+    "nshe_depth_after": (_I, [_P, _I, _I, _I, ctypes.POINTER(_I)]),
+    "nshe_set_debug": (_I, [_P, ctypes.c_uint32]),
+    "nshe_margin_sites": (_I, [_P, ctypes.POINTER(ctypes.c_uint64), _I, ctypes.POINTER(_I), _P]),
     "nshe_workspace_bytes": (_SZ, [_P, _I]),
     "nshe_sub": (_I, [_P, _P, _P, _P, _I, _P]),
     "nshe_square_relin": (_I, [_P, _P, _P, _I, _P, _SZ, _P]),
@@ -71,7 +92,7 @@ SIGNATURES = {
     "nshe_join_workspace_bytes": (_SZ, [_P, _I]),
     "nshe_join_sum": (_I, [_P, _P, _P, _P, ctypes.POINTER(ctypes.c_int32), _I, _P, _I, _P, _SZ,
                            _P]),
-    "nshe_set_galois_key": (_I, [_P, ctypes.c_uint32, _P, _P]),
+    "nshe_set_galois_key": (_I, [_P, ctypes.c_uint32, _P, _SZ, _P]),
     "nshe_galois_elements": (_I, [_P, ctypes.POINTER(ctypes.c_uint32), _I, ctypes.POINTER(_I)]),
     "nshe_rotate": (_I, [_P, _P, ctypes.c_uint32, _P, _I, _P, _SZ, _P]),
     "nshe_sum_slots": (_I, [_P, _P, _P, _I, _P, _SZ, _P]),

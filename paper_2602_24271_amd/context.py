@@ -7,6 +7,7 @@ memory (ciphertexts, keys, workspace) comes from PyTorch's allocator.
 from __future__ import annotations
 
 import ctypes
+import weakref
 
 import torch
 
@@ -40,6 +41,14 @@ class Context:
         self.L_ext = info.L_ext
         self.squarings = info.squarings
         self.ext_primes = [info.ext_primes[i] for i in range(info.L_ext)]
+        self.depth_budget = info.depth_budget
+        self.lt_depth = info.lt_depth
+        self.fresh_bits = info.fresh_bits
+        self.level_bits = info.level_bits
+        # per-ciphertext-array level counter (Sec. 2.1.2): the depth of every
+        # output this context produced; arrays it did not produce count as
+        # fresh (depth 0) unless set_depth says otherwise
+        self._depths = weakref.WeakKeyDictionary()
         self.q = list(q)
         self.P = P
         self.t = t
@@ -86,13 +95,52 @@ class Context:
             raise ValueError(f"expected shape [n_ct, {comps}, {self.L}, {self.n}], got {tuple(x.shape)}")
         return x.shape[0]
 
+    # ------------------------------------------------------------ depth
+    def depth(self, x: torch.Tensor) -> int:
+        """Multiplicative depth of a ciphertext array (0 if unknown)."""
+        return self._depths.get(x, 0)
+
+    def set_depth(self, x: torch.Tensor, depth: int) -> None:
+        self._depths[x] = int(depth)
+
+    def op_depth(self, op: str, arg: int = 0) -> int:
+        d = ctypes.c_int()
+        _lib.check(self._lib.nshe_op_depth(self._h, _lib.OPS[op], arg, ctypes.byref(d)))
+        return d.value
+
+    def _depth_after(self, op: str, *inputs, arg: int = 0) -> int:
+        """Depth of an operation's result from its inputs' (raises NsheError
+        NSHE_EDEPTH beyond the budget, before anything is enqueued)."""
+        d = ctypes.c_int()
+        din = max([self.depth(x) for x in inputs] + [0])
+        _lib.check(self._lib.nshe_depth_after(self._h, _lib.OPS[op], arg, din, ctypes.byref(d)))
+        return d.value
+
+    def _tag(self, out: torch.Tensor, depth: int) -> torch.Tensor:
+        self._depths[out] = depth
+        return out
+
+    # ------------------------------------------------------------ debug
+    def set_debug(self, wide_lift_window: bool = False, check_inputs: bool = False) -> None:
+        flags = (_lib.NSHE_DEBUG_WIDE_LIFT_WINDOW if wide_lift_window else 0) | \
+                (_lib.NSHE_DEBUG_CHECK_INPUTS if check_inputs else 0)
+        _lib.check(self._lib.nshe_set_debug(self._h, flags))
+
+    def margin_sites(self) -> list:
+        """Exact-lift fallbacks taken per call site (see nshe_margin_sites)."""
+        buf = (ctypes.c_uint64 * _lib.NSHE_MARGIN_SITES)()
+        n = ctypes.c_int()
+        _lib.check(self._lib.nshe_margin_sites(self._h, buf, _lib.NSHE_MARGIN_SITES,
+                                               ctypes.byref(n), _stream()))
+        return [int(buf[i]) for i in range(n.value)]
+
     # ---------------------------------------------------------------- API
     def set_relin_key(self, evk: torch.Tensor) -> None:
         want = (self.L, 2, self.L + 1, self.n)
         if evk.dtype != torch.int64 or tuple(evk.shape) != want or evk.device != self.device:
             raise ValueError(f"relin key must be int64 {want} on the context device")
         evk = evk.contiguous()
-        _lib.check(self._lib.nshe_set_relin_key(self._h, _ptr(evk), _stream()))
+        _lib.check(self._lib.nshe_set_relin_key(self._h, _ptr(evk), evk.numel(), _stream()))
         self._key = evk  # keep alive until the stream has consumed it
         torch.cuda.current_stream().synchronize()
         self._key = None
@@ -101,17 +149,19 @@ class Context:
         n = self._check_ct(x)
         if self._check_ct(y) != n:
             raise ValueError("x and y must hold the same number of ciphertexts")
+        d = self._depth_after("add", x, y)
         out = torch.empty_like(x)
         _lib.check(self._lib.nshe_sub(self._h, _ptr(x), _ptr(y), _ptr(out), n, _stream()))
-        return out
+        return self._tag(out, d)
 
     def add(self, a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
         n = self._check_ct(a)
         if self._check_ct(b) != n:
             raise ValueError("a and b must hold the same number of ciphertexts")
+        d = self._depth_after("add", a, b)
         out = torch.empty_like(a)
         _lib.check(self._lib.nshe_add(self._h, _ptr(a), _ptr(b), _ptr(out), n, _stream()))
-        return out
+        return self._tag(out, d)
 
     def sum(self, cts: torch.Tensor) -> torch.Tensor:
         """cts: int64 [k][n_ct][2][L][N] -> their sum [n_ct][2][L][N]."""
@@ -119,22 +169,24 @@ class Context:
             raise ValueError("expected a contiguous int64 [k][n_ct][2][L][N] tensor")
         k = int(cts.shape[0])
         n = int(cts.shape[1])
+        d = self._depth_after("add", cts)
         out = torch.empty(self.ct_shape(n), dtype=torch.int64, device=cts.device)
         _lib.check(self._lib.nshe_sum(self._h, _ptr(cts), k, _ptr(out), n, _stream()))
-        return out
+        return self._tag(out, d)
 
     def in_mask(self, x: torch.Tensor, members: torch.Tensor, wave_ct: int = 0,
                 use_graph: bool = True) -> torch.Tensor:
         """IN(x, S) (Eq. eq:in); members: k single ciphertexts [k][2][L][N]."""
         n = self._check_ct(x)
         k = self._check_ct(members)
+        d = self._depth_after("in", x, members, arg=k)
         out = torch.empty_like(x)
         need = int(self._lib.nshe_in_workspace_bytes(self._h, n, k, wave_ct))
         ws = self._workspace_bytes(need)
         _lib.check(self._lib.nshe_in_mask(self._h, _ptr(x), _ptr(members), k, _ptr(out), n,
                                           wave_ct, 1 if use_graph else 0, _ptr(ws), ws.numel(),
                                           _stream()))
-        return out
+        return self._tag(out, d)
 
     def group_masks(self, x: torch.Tensor, values: torch.Tensor, wave_ct: int = 0,
                     use_graph: bool = True) -> list:
@@ -162,11 +214,12 @@ class Context:
         if ny not in (n, 1):
             raise ValueError("y must hold n_ct ciphertexts or one")
         code = {"lt": 0, "le": 1}[op]
+        d = self._depth_after("lt", x, y)
         out = torch.empty_like(x)
         ws = self._cmp_ws(n)
         _lib.check(self._lib.nshe_compare(self._h, _ptr(x), _ptr(y), int(ny == 1 and n != 1),
                                           code, _ptr(out), n, _ptr(ws), ws.numel(), _stream()))
-        return out
+        return self._tag(out, d)
 
     def between(self, x: torch.Tensor, lo: torch.Tensor, hi: torch.Tensor) -> torch.Tensor:
         """[lo <= x <= hi] = LE(lo, x) * LE(x, hi); lo, hi: as many ciphertexts
@@ -175,32 +228,35 @@ class Context:
         nl, nh = self._check_ct(lo), self._check_ct(hi)
         if nl != nh or nl not in (n, 1):
             raise ValueError("lo and hi must both hold n_ct ciphertexts or one")
+        d = self._depth_after("between", x, lo, hi)
         out = torch.empty_like(x)
         ws = self._cmp_ws(n)
         _lib.check(self._lib.nshe_between(self._h, _ptr(x), _ptr(lo), _ptr(hi),
                                           int(nl == 1 and n != 1), _ptr(out), n, _ptr(ws),
                                           ws.numel(), _stream()))
-        return out
+        return self._tag(out, d)
 
     def mul_plain(self, x: torch.Tensor, pt: torch.Tensor) -> torch.Tensor:
         """x times the plaintext polynomial pt (int64 [N], values in [0, t))."""
         n = self._check_ct(x)
         if pt.dtype != torch.int64 or pt.device != self.device or tuple(pt.shape) != (self.n,):
             raise ValueError("pt must be an int64 [N] tensor on the context device")
+        d = self._depth_after("mul_plain", x)
         out = torch.empty_like(x)
         ws = self.workspace(n)
         _lib.check(self._lib.nshe_mul_plain(self._h, _ptr(x), _ptr(pt.contiguous()), _ptr(out), n,
                                             _ptr(ws), ws.numel(), _stream()))
-        return out
+        return self._tag(out, d)
 
     def extract(self, x: torch.Tensor, slot: int, broadcast: bool = False) -> torch.Tensor:
         """Extract one slot (others zero), or Broadcast it to every slot."""
         n = self._check_ct(x)
+        d = self._depth_after("mul_plain", x)
         out = torch.empty_like(x)
         ws = self.workspace(n)
         _lib.check(self._lib.nshe_extract(self._h, _ptr(x), slot, int(bool(broadcast)), _ptr(out),
                                           n, _ptr(ws), ws.numel(), _stream()))
-        return out
+        return self._tag(out, d)
 
     def join_sum(self, a_key: torch.Tensor, b_key: torch.Tensor, b_attr: torch.Tensor,
                  rows) -> torch.Tensor:
@@ -209,13 +265,14 @@ class Context:
         if self._check_ct(b_key) != 1 or self._check_ct(b_attr) != 1:
             raise ValueError("b_key and b_attr must be one ciphertext each")
         rows = list(rows)
+        d = self._depth_after("join", a_key, b_key, b_attr)
         arr = (ctypes.c_int32 * max(1, len(rows)))(*rows)
         out = torch.empty_like(a_key)
         ws = self._workspace_bytes(int(self._lib.nshe_join_workspace_bytes(self._h, n)))
         _lib.check(self._lib.nshe_join_sum(self._h, _ptr(a_key), _ptr(b_key), _ptr(b_attr), arr,
                                            len(rows), _ptr(out), n, _ptr(ws), ws.numel(),
                                            _stream()))
-        return out
+        return self._tag(out, d)
 
     def galois_elements(self) -> list:
         """Galois elements whose keys nshe_sum_slots needs, in order of use."""
@@ -229,61 +286,67 @@ class Context:
             raise ValueError("key must be a contiguous int64 tensor on the context device")
         if tuple(key.shape) != (self.L, 2, self.L + 1, self.n):
             raise ValueError("key must have shape [L, 2, L+1, N]")
-        _lib.check(self._lib.nshe_set_galois_key(self._h, g, _ptr(key), _stream()))
+        _lib.check(self._lib.nshe_set_galois_key(self._h, g, _ptr(key), key.numel(), _stream()))
 
     def rotate(self, x: torch.Tensor, g: int) -> torch.Tensor:
         n = self._check_ct(x)
+        d = self._depth_after("add", x)
         out = torch.empty_like(x)
         ws = self.workspace(n)
         _lib.check(self._lib.nshe_rotate(self._h, _ptr(x), g, _ptr(out), n, _ptr(ws), ws.numel(),
                                          _stream()))
-        return out
+        return self._tag(out, d)
 
     def sum_slots(self, x: torch.Tensor) -> torch.Tensor:
         """COUNT / SUM aggregation: every slot of the result holds the sum of
         all slots of its ciphertext."""
         n = self._check_ct(x)
+        d = self._depth_after("add", x)
         out = torch.empty_like(x)
         ws = self.workspace(n)
         _lib.check(self._lib.nshe_sum_slots(self._h, _ptr(x), _ptr(out), n, _ptr(ws), ws.numel(),
                                             _stream()))
-        return out
+        return self._tag(out, d)
 
     def square_relin(self, x: torch.Tensor) -> torch.Tensor:
         n = self._check_ct(x)
+        d = self._depth_after("mul", x)
         out = torch.empty_like(x)
         ws = self.workspace(n)
         _lib.check(self._lib.nshe_square_relin(self._h, _ptr(x), _ptr(out), n, _ptr(ws),
                                                ws.numel(), _stream()))
-        return out
+        return self._tag(out, d)
 
     def mul_relin(self, a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
         n = self._check_ct(a)
         if self._check_ct(b) != n:
             raise ValueError("a and b must hold the same number of ciphertexts")
+        d = self._depth_after("mul", a, b)
         out = torch.empty_like(a)
         ws = self.workspace(n)
         _lib.check(self._lib.nshe_mul_relin(self._h, _ptr(a), _ptr(b), _ptr(out), n, _ptr(ws),
                                             ws.numel(), _stream()))
-        return out
+        return self._tag(out, d)
 
     def multiply(self, a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
         n = self._check_ct(a)
         if self._check_ct(b) != n:
             raise ValueError("a and b must hold the same number of ciphertexts")
+        d = self._depth_after("mul", a, b)
         out = torch.empty((n, 3, self.L, self.n), dtype=torch.int64, device=self.device)
         ws = self.workspace(n)
         _lib.check(self._lib.nshe_multiply(self._h, _ptr(a), _ptr(b), _ptr(out), n, _ptr(ws),
                                            ws.numel(), _stream()))
-        return out
+        return self._tag(out, d)
 
     def relinearize(self, c3: torch.Tensor) -> torch.Tensor:
         n = self._check_ct(c3, comps=3)
+        d = self._depth_after("add", c3)
         out = torch.empty((n, 2, self.L, self.n), dtype=torch.int64, device=self.device)
         ws = self.workspace(n)
         _lib.check(self._lib.nshe_relinearize(self._h, _ptr(c3), _ptr(out), n, _ptr(ws),
                                               ws.numel(), _stream()))
-        return out
+        return self._tag(out, d)
 
     def eq_mask(self, x: torch.Tensor, y: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         """EQ(x, y) = 1 - (x - y)^(t-1) (Eq. eq:equality).  y holds as many
@@ -293,24 +356,27 @@ class Context:
         if ny not in (n, 1):
             raise ValueError("y must hold n_ct ciphertexts or one")
         bcast = 1 if (ny == 1 and n != 1) else 0
+        d = self._depth_after("eq", x, y)
         if out is None:
             out = torch.empty_like(x)
         ws = self.workspace(n)
         _lib.check(self._lib.nshe_eq_mask(self._h, _ptr(x), _ptr(y), _ptr(out), n, bcast, _ptr(ws),
                                           ws.numel(), _stream()))
-        return out
+        return self._tag(out, d)
 
     def eq_mask_batched(self, items, wave_ct: int = 0, use_graph: bool = True, outs=None):
         """items: list of (x, y) with y one ciphertext (broadcast) or as many
         as x.  Returns the list of outputs."""
         arr = (_lib.NsheItem * len(items))()
         res = []
+        depths = [self._depth_after("eq", x, y) for x, y in items]
         for i, (x, y) in enumerate(items):
             n = self._check_ct(x)
             ny = self._check_ct(y)
             if ny not in (n, 1):
                 raise ValueError("y must hold n_ct ciphertexts or one")
             out = outs[i] if outs is not None else torch.empty_like(x)
+            self._tag(out, depths[i])
             res.append(out)
             arr[i] = _lib.NsheItem(_ptr(x), _ptr(y), _ptr(out), n, 1 if (ny == 1 and n != 1) else 0)
         total = sum(int(x.shape[0]) for x, _ in items)

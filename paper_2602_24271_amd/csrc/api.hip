@@ -192,10 +192,19 @@ struct nshe_ctx {
   // comparison polynomial (t = 2^K + 1 prime; lt_K = 0 otherwise): k babies,
   // m giants, coefficient matrix [m][k] (centred ints) on the device
   int lt_K = 0, lt_k = 0, lt_m = 0, lt_top = 0;
+  int lt_depth = 0;  // multiplicative depth of the comparison program
   const int* lt_coef = nullptr;
+  // noise budget (see budget_of): multiplications a fresh ciphertext takes
+  int depth_budget = 0;
+  double fresh_bits = 0.0, level_bits = 0.0;
+  uint32_t debug = 0;  // NSHE_DEBUG_* switches
 };
 
 namespace nshe {
+
+// the exact-lift window: the default, and the debug switch's 1/4
+constexpr double kLiftEdge = 0.5 - 0x1p-40;
+constexpr double kLiftEdgeWide = 0.25;
 
 #define HIPCHK(expr)                                                            \
   do {                                                                          \
@@ -498,16 +507,12 @@ static int set_device(const nshe_ctx* c) {
 
 }  // namespace nshe
 
-// =================================================================== ABI
+// ---------------------------------------------------------- parameters
 
-extern "C" {
-
-const char* nshe_last_error(void) { return g_err.c_str(); }
-
-int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
-  g_err.clear();
-  if (!pr || !out) return fail(NSHE_EINVAL, "null argument");
-  *out = nullptr;
+// The checks every parameter set must pass (shared by nshe_ctx_create and
+// nshe_budget_of); fills q (the data primes).
+static int check_params(const nshe_params* pr, std::vector<u64>* q_out) {
+  if (!pr) return fail(NSHE_EINVAL, "null argument");
   if (pr->log2_n < NSHE_MIN_LOG2N || pr->log2_n > NSHE_MAX_LOG2N)
     return fail(NSHE_EINVAL, "log2_n out of range");
   if (pr->L < 1 || pr->L > NSHE_MAX_L) return fail(NSHE_EINVAL, "L out of range");
@@ -535,6 +540,147 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
     for (size_t k = 0; k < i; ++k)
       if (qp[k] == x) return fail(NSHE_EINVAL, "primes must be distinct");
   }
+  *q_out = q;
+  return NSHE_OK;
+}
+
+// Multiplicative depth of the comparison program (fresh z): levels[a] =
+// z^(2^a) has depth a; babies and giants are products of earlier ones
+// (as the program builds them); G_j = sum_i c_i B_i keeps the largest baby
+// depth, g = G_0 + sum_j G_j W_j one product more, LT = max(K, depth(g) + 1).
+static int lt_program_depth(int K, int k, int m) {
+  auto split = [](int i) {
+    int h = 1;
+    while (h * 2 <= i) h *= 2;
+    return h;
+  };
+  auto lg = [](int x) {
+    int r = 0;
+    while ((1 << r) < x) ++r;
+    return r;
+  };
+  std::vector<int> bd(k, 0), gd(m, 0);
+  if (k > 1) bd[1] = 1;
+  for (int i = 2; i < k; ++i) {
+    const int h = split(i), r = i - h;
+    bd[i] = r == 0 ? lg(h) + 1 : std::max(bd[h], bd[r]) + 1;
+  }
+  if (m > 1) gd[1] = lg(k) + 1;
+  for (int j = 2; j < m; ++j) {
+    const int h = split(j), r = j - h;
+    gd[j] = r == 0 ? lg(k) + lg(h) + 1 : std::max(gd[h], gd[r]) + 1;
+  }
+  const int dG = *std::max_element(bd.begin(), bd.end());
+  int dg = dG;
+  for (int j = 1; j < m; ++j) dg = std::max(dg, std::max(dG, gd[j]) + 1);
+  return std::max(K, dg + 1);
+}
+
+// Noise budget of a parameter set, in bits of the invariant noise (the
+// decryption error is below 1/2 while log2(Q / (2 |t c(s) - Q m|)) > 0;
+// Sec. 2.1.2: every multiplication adds and amplifies noise).
+//   fresh: a fresh encryption's error t e - [Q]_t m has |.| <= t (B + t),
+//     B = 19 the error bound of the client's sampler (rounded Gaussian,
+//     sigma 3.2, clipped at 6 sigma), so fresh = log2 Q - log2(2 t (B + t));
+//   per multiplication with relinearization: the average-case (canonical
+//     embedding) growth of a BFV product with a ternary secret is a factor
+//     of about t N sqrt(8/3) on the larger operand noise; counted here as
+//     log2 t + log2 N + 2 bits, one bit more, so that the model stays below
+//     the exact noise the oracle measures (19-28 bits per squaring for
+//     N = 64 .. 4096 at t = 65537, against 22-30 here);
+//   the depth budget keeps MARGIN_BITS to spare after its last level.
+constexpr double kErrBound = 19.0;
+constexpr double kMarginBits = 8.0;
+
+static nshe_budget budget_of(int log2n, u64 t, const std::vector<u64>& q) {
+  double log2Q = 0.0;
+  for (u64 x : q) log2Q += std::log2((double)x);
+  const double td = (double)t;
+  nshe_budget b{};
+  b.fresh_bits = log2Q - std::log2(2.0 * td * (kErrBound + td));
+  b.level_bits = std::log2(td) + log2n + 2.0;
+  const double d = std::floor((b.fresh_bits - kMarginBits) / b.level_bits);
+  b.depth_budget = d > 0 ? (int32_t)d : 0;
+  b.lt_depth = -1;
+  int K = 0;
+  while ((1ull << K) + 1 < t) ++K;
+  if ((1ull << K) + 1 == t && K >= 2 && is_prime(t)) {
+    const int kb = K / 2;
+    b.lt_depth = lt_program_depth(K, 1 << kb, 1 << (K - 1 - kb));
+  }
+  return b;
+}
+
+// Depth an operation adds to fresh inputs (the per-operator depths of
+// Table table:noise_levels for this library's programs); -1 if the
+// operation does not exist for these parameters.
+//   LT/LE: the program depth plus one level for its scalar combination
+//   (coefficients up to (p-1)/2 summed over k babies); BETWEEN one more;
+//   IN: EQ plus one level for the k-way sum when k > 1 (the paper's
+//   ceil(log(k)/p)); JOIN: EQ and one product, plus one level for the
+//   plaintext product of Extract inside Broadcast.
+static int op_depth(const nshe_ctx* c, int op, int arg) {
+  switch (op) {
+    case NSHE_OP_ADD: return 0;
+    case NSHE_OP_MUL: return 1;
+    case NSHE_OP_MUL_PLAIN: return 1;
+    case NSHE_OP_EQ: return c->squarings;
+    case NSHE_OP_IN: return c->squarings < 0 ? -1 : c->squarings + (arg > 1 ? 1 : 0);
+    case NSHE_OP_LT: return c->lt_K ? c->lt_depth + 1 : -1;
+    case NSHE_OP_BETWEEN: return c->lt_K ? c->lt_depth + 2 : -1;
+    case NSHE_OP_JOIN: return c->squarings < 0 ? -1 : c->squarings + 2;
+    default: return -1;
+  }
+}
+
+// NSHE_EDEPTH when an operation on fresh inputs needs more levels than the
+// context's budget.
+static int depth_check(const nshe_ctx* c, int op, int arg, const char* what) {
+  const int d = op_depth(c, op, arg);
+  if (d > c->depth_budget)
+    return fail(NSHE_EDEPTH, std::string(what) + " needs multiplicative depth " +
+                                 std::to_string(d) + ", the parameters allow " +
+                                 std::to_string(c->depth_budget));
+  return NSHE_OK;
+}
+
+// Debug switch NSHE_DEBUG_CHECK_INPUTS: every residue of the listed int64
+// polynomials ([polys][L][N]) must lie in [0, q_i); waits for the stream.
+struct InSpan {
+  const int64_t* p;
+  size_t polys;
+};
+
+static int check_inputs(nshe_ctx* c, hipStream_t st, std::initializer_list<InSpan> ins) {
+  if (!(c->debug & NSHE_DEBUG_CHECK_INPUTS)) return NSHE_OK;
+  HIPCHK(run_fill_u64(c->tb.bad_input, 1, 0, st));
+  for (const InSpan& a : ins)
+    if (a.p) HIPCHK(run_check_residues(c->n, c->L, a.polys, a.p, c->tb, st));
+  int bad = 0;
+  HIPCHK(hipMemcpyAsync(&bad, c->tb.bad_input, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (bad) return fail(NSHE_EINVAL, "an input residue lies outside [0, q_i)");
+  return NSHE_OK;
+}
+
+// =================================================================== ABI
+
+extern "C" {
+
+static void drop_graphs(nshe_ctx* c);
+
+const char* nshe_last_error(void) { return g_err.c_str(); }
+
+int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
+  g_err.clear();
+  if (!pr || !out) return fail(NSHE_EINVAL, "null argument");
+  *out = nullptr;
+  std::vector<u64> q;
+  if (int rc0 = check_params(pr, &q)) return rc0;
+  const int n = 1 << pr->log2_n;
+  const u64 lo = 1ull << 48;
+  std::vector<u64> qp = q;
+  qp.push_back(pr->P);
   // --- extension basis: L + 1 largest primes = 1 mod 2^16 below min(q, P)
   const int L = pr->L, LB = L + 1;
   u64 mn = *std::min_element(qp.begin(), qp.end());
@@ -814,6 +960,13 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
         lt_coef[(size_t)j * c->lt_k + i] = centred_small(cp[2 * ((size_t)j * c->lt_k + i) + 1], c->t);
     c->lt_top = centred_small(cp[c->t - 1], c->t);
     lt_coef.push_back(c->lt_top);  // the z^(p-1) coefficient, after the matrix
+    c->lt_depth = lt_program_depth(c->lt_K, c->lt_k, c->lt_m);
+  }
+  {
+    const nshe_budget bud = budget_of(c->log2n, c->t, q);
+    c->depth_budget = bud.depth_budget;
+    c->fresh_bits = bud.fresh_bits;
+    c->level_bits = bud.level_bits;
   }
   const size_t off_lt = total;
   total += (lt_coef.size() * sizeof(int) + 255) & ~size_t(255);
@@ -839,8 +992,11 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
     c->tb.tw_half0 = nullptr;
     c->tb.tw_half_inv = nullptr;
   }
+  // counters: [MARGIN_COUNT] u64 event counts, the input-check flag at +128
+  static_assert(MARGIN_COUNT * 8 <= 128, "counter area");
   c->tb.margin = reinterpret_cast<unsigned long long*>(base + off_counters);
-  c->tb.fault = c->tb.margin + 1;
+  c->tb.bad_input = reinterpret_cast<int*>(base + off_counters + 128);
+  c->tb.lift_edge = kLiftEdge;
   if (e == hipSuccess) e = hipMemset(base + off_counters, 0, 256);
   std::vector<int> lp;
   for (int i = 0; i < W_of(c); ++i) lp.push_back(i);
@@ -892,6 +1048,51 @@ int nshe_ctx_info(const nshe_ctx* c, nshe_info* out) {
   for (int k = 0; k < c->LB && k < 32; ++k) out->ext_primes[k] = c->primes[c->L + k];
   out->ct_words = (size_t)2 * c->L * c->n;
   out->relin_key_words = (size_t)c->L * 2 * (c->L + 1) * c->n;
+  out->depth_budget = c->depth_budget;
+  out->fresh_bits = c->fresh_bits;
+  out->level_bits = c->level_bits;
+  out->lt_depth = c->lt_K ? c->lt_depth : -1;
+  return NSHE_OK;
+}
+
+int nshe_budget_of(const nshe_params* pr, nshe_budget* out) {
+  g_err.clear();
+  if (!pr || !out) return fail(NSHE_EINVAL, "null argument");
+  std::vector<u64> q;
+  if (int rc = check_params(pr, &q)) return rc;
+  *out = budget_of((int)pr->log2_n, pr->t, q);
+  return NSHE_OK;
+}
+
+int nshe_op_depth(const nshe_ctx* c, int op, int arg, int* depth) {
+  g_err.clear();
+  if (check_ctx(c) || !depth) return fail(NSHE_EINVAL, "null argument");
+  if (op < NSHE_OP_ADD || op > NSHE_OP_JOIN) return fail(NSHE_EINVAL, "unknown operation");
+  const int d = op_depth(c, op, arg);
+  if (d < 0) return fail(NSHE_EUNSUPPORTED, "operation not available for these parameters");
+  *depth = d;
+  return NSHE_OK;
+}
+
+int nshe_depth_after(const nshe_ctx* c, int op, int arg, int in_depth, int* out_depth) {
+  int d = 0;
+  if (int rc = nshe_op_depth(c, op, arg, &d)) return rc;
+  if (in_depth < 0) return fail(NSHE_EINVAL, "in_depth < 0");
+  *out_depth = in_depth + d;
+  if (in_depth + d > c->depth_budget)
+    return fail(NSHE_EDEPTH, "depth " + std::to_string(in_depth + d) + " exceeds the budget " +
+                                 std::to_string(c->depth_budget));
+  return NSHE_OK;
+}
+
+int nshe_set_debug(nshe_ctx* c, uint32_t flags) {
+  g_err.clear();
+  if (check_ctx(c)) return NSHE_EINVAL;
+  if (flags & ~(uint32_t)(NSHE_DEBUG_WIDE_LIFT_WINDOW | NSHE_DEBUG_CHECK_INPUTS))
+    return fail(NSHE_EINVAL, "unknown debug flag");
+  c->debug = flags;
+  c->tb.lift_edge = (flags & NSHE_DEBUG_WIDE_LIFT_WINDOW) ? kLiftEdgeWide : kLiftEdge;
+  drop_graphs(c);  // captured kernels hold the tables by value
   return NSHE_OK;
 }
 
@@ -919,10 +1120,15 @@ static int load_switch_key(nshe_ctx* c, const int64_t* key_dev, double** dst, hi
   return rc;
 }
 
-int nshe_set_relin_key(nshe_ctx* c, const int64_t* evk_dev, void* stream) {
+static size_t key_words(const nshe_ctx* c) {
+  return (size_t)c->L * 2 * (c->L + 1) * c->n;
+}
+
+int nshe_set_relin_key(nshe_ctx* c, const int64_t* evk_dev, size_t n_words, void* stream) {
   g_err.clear();
   if (check_ctx(c)) return NSHE_EINVAL;
   if (!evk_dev) return fail(NSHE_EINVAL, "evk is null");
+  if (n_words != key_words(c)) return fail(NSHE_ESHAPE, "evk must hold L * 2 * (L+1) * N words");
   if (set_device(c)) return NSHE_EDEVICE;
   int rc = load_switch_key(c, evk_dev, &c->evk, static_cast<hipStream_t>(stream));
   if (rc) return rc;
@@ -930,10 +1136,12 @@ int nshe_set_relin_key(nshe_ctx* c, const int64_t* evk_dev, void* stream) {
   return NSHE_OK;
 }
 
-int nshe_set_galois_key(nshe_ctx* c, uint32_t g, const int64_t* key_dev, void* stream) {
+int nshe_set_galois_key(nshe_ctx* c, uint32_t g, const int64_t* key_dev, size_t n_words,
+                        void* stream) {
   g_err.clear();
   if (check_ctx(c)) return NSHE_EINVAL;
   if (!key_dev) return fail(NSHE_EINVAL, "key is null");
+  if (n_words != key_words(c)) return fail(NSHE_ESHAPE, "key must hold L * 2 * (L+1) * N words");
   if (g % 2 == 0 || g >= 2u * (uint32_t)c->n) return fail(NSHE_EINVAL, "g must be odd and below 2N");
   if (set_device(c)) return NSHE_EDEVICE;
   double*& slot = c->galois[g];
@@ -954,6 +1162,8 @@ int nshe_sub(nshe_ctx* c, const int64_t* x, const int64_t* y, int64_t* out, int 
   if (!x || !y || !out) return fail(NSHE_EINVAL, "null buffer");
   if (set_device(c)) return NSHE_EDEVICE;
   Dims d = dims(c, n_ct);
+  const size_t np = (size_t)n_ct * 2;
+  if (int rc = check_inputs(c, static_cast<hipStream_t>(stream), {{x, np}, {y, np}})) return rc;
   HIPCHK(run_sub_i64(d, x, y, out, c->tb, static_cast<hipStream_t>(stream)));
   return NSHE_OK;
 }
@@ -966,6 +1176,8 @@ int nshe_add(nshe_ctx* c, const int64_t* a, const int64_t* b, int64_t* out, int 
   if (n_ct == 0) return NSHE_OK;
   if (!a || !b || !out) return fail(NSHE_EINVAL, "null buffer");
   if (set_device(c)) return NSHE_EDEVICE;
+  const size_t np = (size_t)n_ct * 2;
+  if (int rc = check_inputs(c, static_cast<hipStream_t>(stream), {{a, np}, {b, np}})) return rc;
   HIPCHK(run_sum_i64(dims(c, n_ct), a, b, 0, 1, out, c->tb, static_cast<hipStream_t>(stream)));
   return NSHE_OK;
 }
@@ -978,9 +1190,10 @@ int nshe_sum(nshe_ctx* c, const int64_t* in, int k, int64_t* out, int n_ct, void
   if (!out || (k > 0 && !in)) return fail(NSHE_EINVAL, "null buffer");
   if (set_device(c)) return NSHE_EDEVICE;
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if (int rc = check_inputs(c, st, {{in, (size_t)k * n_ct * 2}})) return rc;
   const size_t words = (size_t)n_ct * 2 * c->L * c->n;
   if (k == 0) {
-    HIPCHK(hipMemsetAsync(out, 0, words * sizeof(int64_t), st));  // the encryption (0, 0)
+    HIPCHK(run_fill_u64(out, words, 0, st));  // the encryption (0, 0)
     return NSHE_OK;
   }
   HIPCHK(run_sum_i64(dims(c, n_ct), in, in + words, words, k - 1, out, c->tb, st));
@@ -1006,7 +1219,9 @@ int nshe_square_relin(nshe_ctx* c, const int64_t* in, int64_t* out, int n_ct, vo
   if (rc) return rc;
   if (n_ct == 0) return NSHE_OK;
   if (!in || !out) return fail(NSHE_EINVAL, "null buffer");
+  if ((rc = depth_check(c, NSHE_OP_MUL, 0, "a multiplication"))) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((rc = check_inputs(c, st, {{in, (size_t)n_ct * 2}}))) return rc;
   Ws w = carve(c, ws, n_ct);
   rc = prepare_i64(c, in, w.ext, w.fx, n_ct, st);
   if (rc) return rc;
@@ -1033,7 +1248,9 @@ int nshe_mul_relin(nshe_ctx* c, const int64_t* a, const int64_t* b, int64_t* out
   if (rc) return rc;
   if (n_ct == 0) return NSHE_OK;
   if (!a || !b || !out) return fail(NSHE_EINVAL, "null buffer");
+  if ((rc = depth_check(c, NSHE_OP_MUL, 0, "a multiplication"))) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((rc = check_inputs(c, st, {{a, (size_t)n_ct * 2}, {b, (size_t)n_ct * 2}}))) return rc;
   Ws w = carve(c, ws, n_ct);
   rc = load_two(c, w, a, b, n_ct, st);
   if (rc) return rc;
@@ -1048,7 +1265,9 @@ int nshe_multiply(nshe_ctx* c, const int64_t* a, const int64_t* b, int64_t* out3
   if (rc) return rc;
   if (n_ct == 0) return NSHE_OK;
   if (!a || !b || !out3) return fail(NSHE_EINVAL, "null buffer");
+  if ((rc = depth_check(c, NSHE_OP_MUL, 0, "a multiplication"))) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((rc = check_inputs(c, st, {{a, (size_t)n_ct * 2}, {b, (size_t)n_ct * 2}}))) return rc;
   Ws w = carve(c, ws, n_ct);
   Dims d = dims(c, n_ct);
   const size_t W = W_of(c), N = c->n;
@@ -1067,6 +1286,7 @@ int nshe_relinearize(nshe_ctx* c, const int64_t* in3, int64_t* out, int n_ct, vo
   if (n_ct == 0) return NSHE_OK;
   if (!in3 || !out) return fail(NSHE_EINVAL, "null buffer");
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((rc = check_inputs(c, st, {{in3, (size_t)n_ct * 3}}))) return rc;
   Ws w = carve(c, ws, n_ct);
   Dims d = dims(c, n_ct);
   const size_t W = W_of(c), N = c->n;
@@ -1094,10 +1314,14 @@ int nshe_eq_mask(nshe_ctx* c, const int64_t* x, const int64_t* y, int64_t* out, 
                  int y_broadcast, void* ws, size_t ws_bytes, void* stream) {
   int rc = common_checks(c, n_ct, ws, ws_bytes, true);
   if (rc) return rc;
-  if (c->squarings < 0) return fail(NSHE_EDEPTH, "t - 1 is not a power of two");
+  if (c->squarings < 0) return fail(NSHE_EUNSUPPORTED, "t - 1 is not a power of two");
+  if ((rc = depth_check(c, NSHE_OP_EQ, 0, "EQ"))) return rc;
   if (n_ct == 0) return NSHE_OK;
   if (!x || !y || !out) return fail(NSHE_EINVAL, "null buffer");
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((rc = check_inputs(c, st, {{x, (size_t)n_ct * 2},
+                                 {y, y_broadcast ? (size_t)2 : (size_t)n_ct * 2}})))
+    return rc;
   Ws w = carve(c, ws, n_ct);
   Dims d = dims(c, n_ct);
   const size_t W = W_of(c), N = c->n;
@@ -1119,8 +1343,6 @@ int nshe_eq_mask(nshe_ctx* c, const int64_t* x, const int64_t* y, int64_t* out, 
   }
   return NSHE_OK;
 }
-
-static void drop_graphs(nshe_ctx* c);
 
 // Batched waves.  The caller's workspace holds, after the ciphertext area
 // of one wave, a wave counter (256 bytes) and a table of per-ciphertext
@@ -1175,7 +1397,8 @@ int nshe_eq_mask_batched(nshe_ctx* c, const nshe_item* items, int n_items, int w
   g_err.clear();
   if (check_ctx(c)) return NSHE_EINVAL;
   if (n_items < 0 || (n_items > 0 && !items)) return fail(NSHE_EINVAL, "bad item list");
-  if (c->squarings < 0) return fail(NSHE_EDEPTH, "t - 1 is not a power of two");
+  if (c->squarings < 0) return fail(NSHE_EUNSUPPORTED, "t - 1 is not a power of two");
+  if (int rc0 = depth_check(c, NSHE_OP_EQ, 0, "EQ")) return rc0;
   if (check_key(c)) return NSHE_ENOKEY;
   if (wave_ct < 0) return fail(NSHE_EINVAL, "wave_ct < 0");
   long long total = 0;
@@ -1372,6 +1595,7 @@ int nshe_rotate(nshe_ctx* c, const int64_t* in, uint32_t g, int64_t* out, int n_
   auto key = c->galois.find(g);
   if (key == c->galois.end()) return fail(NSHE_ENOKEY, "no Galois key for g = " + std::to_string(g));
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((rc = check_inputs(c, st, {{in, (size_t)n_ct * 2}}))) return rc;
   Ws w = carve(c, ws, n_ct);
   Dims d = dims(c, n_ct);
   const size_t W = W_of(c), N = c->n;
@@ -1393,6 +1617,7 @@ int nshe_sum_slots(nshe_ctx* c, const int64_t* in, int64_t* out, int n_ct, void*
   rc = sum_keys(c, &els, &keys);
   if (rc) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((rc = check_inputs(c, st, {{in, (size_t)n_ct * 2}}))) return rc;
   Ws w = carve(c, ws, n_ct);
   Dims d = dims(c, n_ct);
   const size_t W = W_of(c), N = c->n;
@@ -1462,8 +1687,11 @@ int nshe_mul_plain(nshe_ctx* c, const int64_t* in, const int64_t* pt, int64_t* o
   if (rc) return rc;
   if (n_ct == 0) return NSHE_OK;
   if (!in || !pt || !out) return fail(NSHE_EINVAL, "null buffer");
-  if ((c->t - 1) % (2ull * c->n)) return fail(NSHE_EINVAL, "plaintext slots need t = 1 mod 2N");
+  if ((c->t - 1) % (2ull * c->n))
+    return fail(NSHE_EUNSUPPORTED, "plaintext slots need t = 1 mod 2N");
+  if ((rc = depth_check(c, NSHE_OP_MUL_PLAIN, 0, "a plaintext product"))) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((rc = check_inputs(c, st, {{in, (size_t)n_ct * 2}}))) return rc;
   Ws w = carve(c, ws, n_ct);
   Dims d = dims(c, n_ct);
   const size_t W = W_of(c), N = c->n;
@@ -1500,7 +1728,9 @@ int nshe_extract(nshe_ctx* c, const int64_t* in, int slot, int broadcast, int64_
   if (n_ct == 0) return NSHE_OK;
   if (!in || !out) return fail(NSHE_EINVAL, "null buffer");
   if (slot < 0 || slot >= c->n) return fail(NSHE_EINVAL, "slot out of range");
-  if ((c->t - 1) % (2ull * c->n)) return fail(NSHE_EINVAL, "plaintext slots need t = 1 mod 2N");
+  if ((c->t - 1) % (2ull * c->n))
+    return fail(NSHE_EUNSUPPORTED, "plaintext slots need t = 1 mod 2N");
+  if ((rc = depth_check(c, NSHE_OP_MUL_PLAIN, 0, "a plaintext product"))) return rc;
   if (broadcast) {
     std::vector<uint32_t> els;
     std::vector<const double*> keys;
@@ -1508,6 +1738,7 @@ int nshe_extract(nshe_ctx* c, const int64_t* in, int slot, int broadcast, int64_
     if (rc) return rc;
   }
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((rc = check_inputs(c, st, {{in, (size_t)n_ct * 2}}))) return rc;
   Ws w = carve(c, ws, n_ct);
   Dims d = dims(c, n_ct);
   const size_t W = W_of(c), N = c->n;
@@ -1534,8 +1765,10 @@ int nshe_join_sum(nshe_ctx* c, const int64_t* a_key, const int64_t* b_key, const
   if (n_ct == 0) return NSHE_OK;
   if (!a_key || !b_key || !b_attr || !out || (n_rows > 0 && !rows))
     return fail(NSHE_EINVAL, "null buffer");
-  if (c->squarings < 0) return fail(NSHE_EDEPTH, "t - 1 is not a power of two");
-  if ((c->t - 1) % (2ull * c->n)) return fail(NSHE_EINVAL, "plaintext slots need t = 1 mod 2N");
+  if (c->squarings < 0) return fail(NSHE_EUNSUPPORTED, "t - 1 is not a power of two");
+  if ((c->t - 1) % (2ull * c->n))
+    return fail(NSHE_EUNSUPPORTED, "plaintext slots need t = 1 mod 2N");
+  if (int rc0 = depth_check(c, NSHE_OP_JOIN, 0, "JOIN")) return rc0;
   for (int r = 0; r < n_rows; ++r)
     if (rows[r] < 0 || rows[r] >= c->n) return fail(NSHE_EINVAL, "row index out of range");
   if (check_key(c)) return NSHE_ENOKEY;
@@ -1551,6 +1784,8 @@ int nshe_join_sum(nshe_ctx* c, const int64_t* a_key, const int64_t* b_key, const
     return fail(NSHE_ENOMEM, "workspace smaller than nshe_join_workspace_bytes(ctx, n_ct)");
   if (set_device(c)) return NSHE_EDEVICE;
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if (int rc0 = check_inputs(c, st, {{a_key, (size_t)n_ct * 2}, {b_key, 2}, {b_attr, 2}}))
+    return rc0;
   if (n_rows == 0) return nshe_sum(c, nullptr, 0, out, n_ct, stream);
   const size_t cb = ct_bytes(c, n_ct), cb1 = ct_bytes(c, 1);
   char* p = static_cast<char*>(ws);
@@ -1742,10 +1977,11 @@ static int lt_core(nshe_ctx* c, const int64_t* z, int64_t* out, int n_ct, const 
   return NSHE_OK;
 }
 
-static int cmp_checks(nshe_ctx* c, int n_ct, void* ws, size_t ws_bytes, CmpArea* a) {
+static int cmp_checks(nshe_ctx* c, int n_ct, void* ws, size_t ws_bytes, CmpArea* a, int op) {
   g_err.clear();
   if (check_ctx(c)) return NSHE_EINVAL;
-  if (c->lt_K == 0) return fail(NSHE_EDEPTH, "comparisons need t = 2^K + 1 prime");
+  if (c->lt_K == 0) return fail(NSHE_EUNSUPPORTED, "comparisons need t = 2^K + 1 prime");
+  if (int rc0 = depth_check(c, op, 0, op == NSHE_OP_LT ? "LT" : "BETWEEN")) return rc0;
   if (n_ct < 0) return fail(NSHE_ESHAPE, "n_ct < 0");
   if (check_key(c)) return NSHE_ENOKEY;
   if (n_ct == 0) return NSHE_OK;
@@ -1784,10 +2020,13 @@ static int compare_into(nshe_ctx* c, const int64_t* x, const int64_t* y, int y_b
 int nshe_compare(nshe_ctx* c, const int64_t* x, const int64_t* y, int y_broadcast, int op,
                  int64_t* out, int n_ct, void* ws, size_t ws_bytes, void* stream) {
   CmpArea a{};
-  int rc = cmp_checks(c, n_ct, ws, ws_bytes, &a);
+  int rc = cmp_checks(c, n_ct, ws, ws_bytes, &a, NSHE_OP_LT);
   if (rc || n_ct == 0) return rc;
   if (op != 0 && op != 1) return fail(NSHE_EINVAL, "op must be 0 (LT) or 1 (LE)");
   if (!x || !y || !out) return fail(NSHE_EINVAL, "null buffer");
+  if ((rc = check_inputs(c, static_cast<hipStream_t>(stream),
+                         {{x, (size_t)n_ct * 2}, {y, y_broadcast ? (size_t)2 : (size_t)n_ct * 2}})))
+    return rc;
   return compare_into(c, x, y, y_broadcast ? 1 : 0, op, out, n_ct, a,
                       static_cast<hipStream_t>(stream));
 }
@@ -1796,10 +2035,14 @@ int nshe_between(nshe_ctx* c, const int64_t* x, const int64_t* lo, const int64_t
                  int bounds_broadcast, int64_t* out, int n_ct, void* ws, size_t ws_bytes,
                  void* stream) {
   CmpArea a{};
-  int rc = cmp_checks(c, n_ct, ws, ws_bytes, &a);
+  int rc = cmp_checks(c, n_ct, ws, ws_bytes, &a, NSHE_OP_BETWEEN);
   if (rc || n_ct == 0) return rc;
   if (!x || !lo || !hi || !out) return fail(NSHE_EINVAL, "null buffer");
   hipStream_t st = static_cast<hipStream_t>(stream);
+  {
+    const size_t nb = bounds_broadcast ? (size_t)2 : (size_t)n_ct * 2;
+    if ((rc = check_inputs(c, st, {{x, (size_t)n_ct * 2}, {lo, nb}, {hi, nb}}))) return rc;
+  }
   Dims d = dims(c, n_ct);
   const int bc = bounds_broadcast ? 1 : 0;
   int64_t* ge = a.slot(cmp_slots(c) - 3);   // [lo <= x] = 1 - LT(x, lo)
@@ -1844,6 +2087,8 @@ int nshe_in_mask(nshe_ctx* c, const int64_t* x, const int64_t* set, int k, int64
   if (n_ct < 0 || k < 0 || wave_ct < 0) return fail(NSHE_ESHAPE, "n_ct, k or wave_ct < 0");
   if (n_ct == 0) return NSHE_OK;
   if (!x || !out || (k > 0 && !set)) return fail(NSHE_EINVAL, "null buffer");
+  if (c->squarings < 0) return fail(NSHE_EUNSUPPORTED, "t - 1 is not a power of two");
+  if (int rc0 = depth_check(c, NSHE_OP_IN, k, "IN")) return rc0;
   if (k == 0) return nshe_sum(c, nullptr, 0, out, n_ct, stream);
   if (!ws) return fail(NSHE_EINVAL, "workspace pointer is null");
   if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(NSHE_EINVAL, "workspace not 256-byte aligned");
@@ -2134,16 +2379,37 @@ int nshe_profile_read(nshe_ctx* c, nshe_kernel_stat* out, int max_stats, int* n_
   return NSHE_OK;
 }
 
+// Reads the counter area (waits for the stream).
+static int read_counters(nshe_ctx* c, hipStream_t st, unsigned long long (&h)[MARGIN_COUNT]) {
+  HIPCHK(hipMemcpyAsync(h, c->tb.margin, sizeof(h), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (h[MARGIN_FAULT]) return fail(NSHE_EDEVICE, "extension-basis lift left its proven range");
+  return NSHE_OK;
+}
+
 int nshe_margin_events(nshe_ctx* c, uint64_t* count, void* stream) {
   g_err.clear();
   if (check_ctx(c) || !count) return fail(NSHE_EINVAL, "null argument");
   if (set_device(c)) return NSHE_EDEVICE;
-  unsigned long long h[2] = {0, 0};
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  HIPCHK(hipMemcpyAsync(h, c->tb.margin, sizeof(h), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  if (h[1]) return fail(NSHE_EDEVICE, "extension-basis lift left its proven range");
-  *count = h[0];
+  unsigned long long h[MARGIN_COUNT] = {};
+  if (int rc = read_counters(c, static_cast<hipStream_t>(stream), h)) return rc;
+  uint64_t sum = 0;
+  for (int i = 0; i < MARGIN_SITES; ++i) sum += h[i];
+  *count = sum;
+  return NSHE_OK;
+}
+
+int nshe_margin_sites(nshe_ctx* c, uint64_t* counts, int max_counts, int* n_counts,
+                      void* stream) {
+  g_err.clear();
+  if (check_ctx(c) || !counts || !n_counts) return fail(NSHE_EINVAL, "null argument");
+  if (set_device(c)) return NSHE_EDEVICE;
+  unsigned long long h[MARGIN_COUNT] = {};
+  if (int rc = read_counters(c, static_cast<hipStream_t>(stream), h)) return rc;
+  const int k = std::min(max_counts, (int)NSHE_MARGIN_SITES);
+  static_assert(NSHE_MARGIN_SITES == MARGIN_SITES, "site list");
+  for (int i = 0; i < k; ++i) counts[i] = h[i];
+  *n_counts = k < 0 ? 0 : k;
   return NSHE_OK;
 }
 
@@ -2151,8 +2417,7 @@ int nshe_reset_margin_events(nshe_ctx* c, void* stream) {
   g_err.clear();
   if (check_ctx(c)) return NSHE_EINVAL;
   if (set_device(c)) return NSHE_EDEVICE;
-  HIPCHK(hipMemsetAsync(c->tb.margin, 0, 2 * sizeof(unsigned long long),
-                        static_cast<hipStream_t>(stream)));
+  HIPCHK(run_fill_u64(c->tb.margin, MARGIN_COUNT, 0, static_cast<hipStream_t>(stream)));
   return NSHE_OK;
 }
 

@@ -74,8 +74,27 @@ struct Tables {
   // exact fallback of the Q lift: mixed-radix digits
   const double* mrc_inv;     // [L][L]   [q_j^-1]_{q_i}, canonical, row j
   const double* mrc_half;    // [L]      mixed-radix digits of (Q-1)/2
-  unsigned long long* margin;  // event counter (fallbacks taken)
-  unsigned long long* fault;   // B->Q lift outside its proven range (never)
+  // event counters ([MARGIN_COUNT]): exact-lift fallbacks taken, per call
+  // site, and B->Q lifts outside their proven range (never)
+  unsigned long long* margin;
+  // the centred lift's exact fallback is taken when |S - rint(S)| exceeds
+  // this (1/2 - 2^-40; 1/4 under the debug switch)
+  double lift_edge;
+  // residues outside [0, q_i) seen by the input check (debug switch)
+  int* bad_input;
+};
+
+// Call sites of the exact-lift fallback (index into Tables::margin).
+enum MarginSite {
+  MARGIN_LIFT = 0,          // k_lift: a product operand's lift (batched waves' first level)
+  MARGIN_SCALE = 1,         // k_scale: the scale-and-round's lift of [t d]_Q
+  MARGIN_SCALE_SPLIT = 2,   // k_scale after the split inverse (N = 2^15)
+  MARGIN_MODDOWN_LIFT = 3,  // k_moddown_lift: the next squaring's operand
+  MARGIN_SUB_LIFT = 4,      // k_sub_lift: the chain's first operand
+  MARGIN_I64_LIFT = 5,      // k_i64_lift: a product's int64 operands
+  MARGIN_SITES = 6,
+  MARGIN_FAULT = 8,         // B->Q lift outside its range (never)
+  MARGIN_COUNT = 9
 };
 
 enum { NTT_INPLACE = 0, NTT_DIGIT = 1, INV_TENSOR = 2, INV_TENSOR2 = 3, INV_PLAIN = 4 };
@@ -171,12 +190,15 @@ hipError_t run_lincomb(const Dims& d, int k, const BabyPtrs& b, const int* coef,
 hipError_t run_fill_one(const Dims& d, int64_t* out, const Tables& tb, hipStream_t st);
 hipError_t run_diff_i64(const Dims& d, const int64_t* x, const int64_t* y, int y_bcast,
                         int negate, int64_t* out, const Tables& tb, hipStream_t st);
-// rotations: automorphism of ext into dt's key-switching layout, and
-// a += b over the data limbs of [ct][2][W][N] ciphertexts
+// rotations: automorphism of ext into dt's key-switching layout
 hipError_t run_automorph(const Dims& d, unsigned ginv, const double* ext, double* dt,
                          const Tables& tb, hipStream_t st);
-hipError_t run_add_bal(const Dims& d, double* a, const double* b, const Tables& tb,
-                       hipStream_t st);
+// p[0..words) = v, as a kernel (no memset node in a captured graph)
+hipError_t run_fill_u64(void* p, size_t words, uint64_t v, hipStream_t st);
+// debug input check: sets *tb.bad_input if a residue of [n_poly][L][N] is
+// outside [0, q_i)
+hipError_t run_check_residues(int n, int L, size_t n_poly, const int64_t* in, const Tables& tb,
+                              hipStream_t st);
 // out = a + sum_{j < k} b[j * stride] (canonical int64 ciphertexts)
 hipError_t run_sum_i64(const Dims& d, const int64_t* a, const int64_t* b, size_t stride, int k,
                        int64_t* out, const Tables& tb, hipStream_t st);

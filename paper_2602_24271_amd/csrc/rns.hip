@@ -12,7 +12,11 @@
 // magnitude < 1/2); when S lies within 2^-40 of a half-integer the rounding
 // decision is taken exactly instead: floor(S) = k, and X > (Q-1)/2 is
 // decided by comparing mixed-radix digits of X with those of (Q-1)/2
-// (Garner's algorithm).  Each such event is counted.
+// (Garner's algorithm).  Each such event is counted, per call site
+// (MarginSite).  The window is a context setting (tb.lift_edge = 1/2 - 2^-40
+// by default); a debug setting widens it to 1/4, which leaves floor(S)
+// exact (S is then at least 1/4 from an integer) and sends about half of
+// all coefficients through the exact path.
 //
 // Scale and round (BFV multiply): for d in Q u B (|d| < QB/2), the exact
 // r = [t d]_Q (centred) gives y = (t d - r) / Q = round(t d / Q) exactly.
@@ -28,7 +32,6 @@
 
 namespace nshe {
 
-constexpr double LIFT_EPS = 0x1p-40;
 
 // Garner mixed-radix digits of X (canonical residues r, basis q_0..q_{L-1})
 // compared with those of (Q-1)/2: returns X > (Q-1)/2.
@@ -142,12 +145,12 @@ __global__ void __launch_bounds__(256) k_lift(int n, size_t n_poly, double* ext,
     S += y[i] * cld(tb.recip, i);
   }
   double v = __builtin_rint(S);
-  if (__builtin_fabs(S - v) > 0.5 - LIFT_EPS) {
+  if (__builtin_fabs(S - v) > tb.lift_edge) {
     double r[L];
 #pragma unroll
     for (int i = 0; i < L; ++i) r[i] = to_canonical(buf_load(rs, vo, i * ls), cld(tb.p, i));
     v = __builtin_floor(S) + (mrc_greater_than_half<L>(r, tb.p, tb.pinv, tb.mrc_inv, tb.mrc_half) ? 1.0 : 0.0);
-    atomicAdd(tb.margin, 1ull);
+    atomicAdd(tb.margin + MARGIN_LIFT, 1ull);
   }
   // |acc| <= (L / 4 + 7.2 + L/2 + 1) 2^48 < 2^53: reduce_bal is exact there
   // (its result within p/2 + 4)
@@ -247,7 +250,6 @@ template <int L, bool FUSED>
 __global__ void __launch_bounds__(256) k_scale(int n, size_t n_poly, double* dt, Tables tb) {
   constexpr int LB = L + 1;
   const PolyBlock pb = poly_block(n, n_poly);
-  if (!pb.ok) return;
   const auto rs = make_rsrc(dt + pb.pc * (size_t)(L + LB) * n, (unsigned)((L + LB) * n * 8));
   CoefSrc cs{(unsigned)pb.c * 8, 0u, 0u, 1.0, false};
   if constexpr (FUSED) {
@@ -269,6 +271,9 @@ __global__ void __launch_bounds__(256) k_scale(int n, size_t n_poly, double* dt,
     if (t < 2 * LB) kl[2 * L + t] = tb.c1[t];
     __syncthreads();
   }
+  // threads past the last coefficient leave only after the block's barrier
+  // (every thread reaches it whatever the grid)
+  if (!pb.ok) return;
   const unsigned vo = cs.v;
   const unsigned ls = (unsigned)n * 8;   // bytes per limb
   const bool third = pb.pc % 3 == 2;
@@ -283,7 +288,7 @@ __global__ void __launch_bounds__(256) k_scale(int n, size_t n_poly, double* dt,
     S += y[i] * cld(tb.recip, iq);
   }
   double v = __builtin_rint(S);
-  if (__builtin_fabs(S - v) > 0.5 - LIFT_EPS) {
+  if (__builtin_fabs(S - v) > tb.lift_edge) {
     double r[L];
 #pragma unroll
     for (int i = 0; i < L; ++i) {
@@ -293,7 +298,7 @@ __global__ void __launch_bounds__(256) k_scale(int n, size_t n_poly, double* dt,
                           p);
     }
     v = __builtin_floor(S) + (mrc_greater_than_half<L>(r, tb.p, tb.pinv, tb.mrc_inv, tb.mrc_half) ? 1.0 : 0.0);
-    atomicAdd(tb.margin, 1ull);
+    atomicAdd(tb.margin + (FUSED ? MARGIN_SCALE_SPLIT : MARGIN_SCALE), 1ull);
   }
   // Split conversions (conv_row).  The base-B residues w_k wait in LDS (this
   // thread's own slots, [LB][blockDim]) between the two conversions, so
@@ -324,7 +329,7 @@ __global__ void __launch_bounds__(256) k_scale(int n, size_t n_poly, double* dt,
     }
   }
   const double v2 = __builtin_rint(S2);
-  if (__builtin_fabs(S2 - v2) > 0.25) atomicAdd(tb.fault, 1ull);
+  if (__builtin_fabs(S2 - v2) > 0.25) atomicAdd(tb.margin + MARGIN_FAULT, 1ull);
   double wh[LB], wl[LB];
 #pragma unroll
   for (int k = 0; k < LB; ++k) split24(wp[k * bs], wh[k], wl[k]);
@@ -518,18 +523,18 @@ __global__ void __launch_bounds__(256) k_moddown_finish(int n, int n_ct,
 // (Q/q_i)^-1]_{q_i}, S = sum_i y_i / q_i are already in registers: the
 // overflow count v (exact fallback near a half-integer, as k_lift), then
 // limbs L..2L of rs at vo.
-template <int L>
+template <int L, int SITE>
 __device__ __forceinline__ void lift_tail(const double (&o)[L], const double (&y)[L], double S,
                                           __amdgpu_buffer_rsrc_t rs, unsigned vo, unsigned ls,
                                           const Tables& tb) {
   constexpr int LB = L + 1;
   double v = __builtin_rint(S);
-  if (__builtin_fabs(S - v) > 0.5 - LIFT_EPS) {
+  if (__builtin_fabs(S - v) > tb.lift_edge) {
     double r[L];
 #pragma unroll
     for (int i = 0; i < L; ++i) r[i] = to_canonical(o[i], cld(tb.p, i));
     v = __builtin_floor(S) + (mrc_greater_than_half<L>(r, tb.p, tb.pinv, tb.mrc_inv, tb.mrc_half) ? 1.0 : 0.0);
-    atomicAdd(tb.margin, 1ull);
+    atomicAdd(tb.margin + SITE, 1ull);
   }
   double yh[L], yl[L];
 #pragma unroll
@@ -599,7 +604,7 @@ __global__ void __launch_bounds__(256) k_moddown_lift(int n, size_t n_poly,
   }
 #pragma unroll
   for (int i = 0; i < L; ++i) buf_store(o[i], rs, vo, i * ls);
-  lift_tail<L>(o, y, S, rs, vo, ls, tb);
+  lift_tail<L, MARGIN_MODDOWN_LIFT>(o, y, S, rs, vo, ls, tb);
 }
 
 // Subtraction z = [x - y]_Q of two ciphertexts (int64, canonical; y one
@@ -632,7 +637,7 @@ __global__ void __launch_bounds__(256) k_sub_lift(int n, size_t n_poly,
   }
 #pragma unroll
   for (int i = 0; i < L; ++i) buf_store(o[i], rs, vo, i * ls);
-  lift_tail<L>(o, y, S, rs, vo, ls, tb);
+  lift_tail<L, MARGIN_SUB_LIFT>(o, y, S, rs, vo, ls, tb);
 }
 
 // Canonical int64 residues of n_poly polynomials ([n_poly][L][N]) into ext
@@ -660,7 +665,7 @@ __global__ void __launch_bounds__(256) k_i64_lift(int n, size_t n_poly,
   }
 #pragma unroll
   for (int i = 0; i < L; ++i) buf_store(o[i], rs, vo, i * ls);
-  lift_tail<L>(o, y, S, rs, vo, ls, tb);
+  lift_tail<L, MARGIN_I64_LIFT>(o, y, S, rs, vo, ls, tb);
 }
 
 // ------------------------------------------------------ plaintext products ---
@@ -859,20 +864,6 @@ __global__ void __launch_bounds__(256) k_automorph(int n, int L, int n_ct, unsig
   }
 }
 
-// a = [a + b] per residue (balanced), ciphertext layout [ct][2][W][N],
-// limbs 0..L-1.
-__global__ void __launch_bounds__(256) k_add_bal(int n, int L, int n_ct, double* a,
-                                                 const double* b, Tables tb) {
-  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= (size_t)n_ct * 2 * L * n) return;
-  const size_t row = gid / n;
-  const int c = (int)(gid - row * n);
-  const int i = (int)(row % L);
-  const size_t cb = row / L;
-  const size_t off = (cb * (2 * L + 1) + i) * n + c;
-  a[off] = reduce_bal(a[off] + b[off], cld(tb.p, i), cld(tb.pinv, i));
-}
-
 // ------------------------------------------------------------ boundary ---
 
 // ext[ct][b][i] (i < L) = balanced(x - y); y broadcast over ct if y_bcast.
@@ -1053,6 +1044,24 @@ __global__ void __launch_bounds__(256) k_ntt_order(size_t total, int log2n, int 
   const int T = n >> loge;
   const int pos = (i & (E - 1)) * T + (i >> loge);
   out[gid] = to_i64(in[row * (size_t)n + pos], cld(tb.p, prime));
+}
+
+// p[0..words) = v (a fill kernel rather than hipMemsetAsync, so that calls
+// a caller captures into a graph record no memset node).
+__global__ void __launch_bounds__(256) k_fill_u64(uint64_t* p, size_t words, uint64_t v) {
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid < words) p[gid] = v;
+}
+
+// Input check of the debug switch: *bad = 1 if a residue of the int64
+// polynomials [n_poly][L][N] lies outside [0, q_i).
+__global__ void __launch_bounds__(256) k_check_residues(int n, int L, size_t total,
+                                                        const int64_t* in, Tables tb) {
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= total) return;
+  const int i = (int)((gid / (size_t)n) % (size_t)L);
+  const int64_t v = in[gid];
+  if (v < 0 || v >= (int64_t)tb.p[i]) atomicOr(tb.bad_input, 1);
 }
 
 // ---------------------------------------------------------------- host ---
@@ -1289,13 +1298,6 @@ hipError_t run_automorph(const Dims& d, unsigned ginv, const double* ext, double
   return hipGetLastError();
 }
 
-hipError_t run_add_bal(const Dims& d, double* a, const double* b, const Tables& tb,
-                       hipStream_t st) {
-  const size_t total = (size_t)d.n_ct * 2 * d.L * d.n;
-  hipLaunchKernelGGL(k_add_bal, grid_for(total), dim3(256), 0, st, d.n, d.L, d.n_ct, a, b, tb);
-  return hipGetLastError();
-}
-
 hipError_t run_sum_i64(const Dims& d, const int64_t* a, const int64_t* b, size_t stride, int k,
                        int64_t* out, const Tables& tb, hipStream_t st) {
   const size_t total = (size_t)d.n_ct * 2 * d.L * d.n;
@@ -1366,6 +1368,21 @@ hipError_t run_i64_to_dbl_limbs(size_t rows, int n, const int64_t* in, double* o
   const size_t total = rows * n;
   hipLaunchKernelGGL(k_i64_rows, grid_for(total), dim3(256), 0, st, total, n, in, out, row_prime,
                      nprime_rows, tb);
+  return hipGetLastError();
+}
+
+hipError_t run_fill_u64(void* p, size_t words, uint64_t v, hipStream_t st) {
+  if (!words) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u64, grid_for(words), dim3(256), 0, st, static_cast<uint64_t*>(p),
+                     words, v);
+  return hipGetLastError();
+}
+
+hipError_t run_check_residues(int n, int L, size_t n_poly, const int64_t* in, const Tables& tb,
+                              hipStream_t st) {
+  const size_t total = n_poly * L * (size_t)n;
+  if (!total) return hipSuccess;
+  hipLaunchKernelGGL(k_check_residues, grid_for(total), dim3(256), 0, st, n, L, total, in, tb);
   return hipGetLastError();
 }
 

@@ -79,6 +79,23 @@ def enc_randomness(seed: int, n: int, moduli_q) -> EncRandomness:
     return EncRandomness(uniform_residues(g[0], moduli_q, n), gaussian(g[1], n))
 
 
+def uniform_switch_key(seed: int, n: int, moduli_pq, n_digits: int) -> np.ndarray:
+    """int64 [n_digits][2][len(moduli_pq)][n] i.i.d. uniform residues: the
+    exchange format of a key switching key, as a stand-in key whose rows are
+    not derived from any secret (key switching is defined for any key; such
+    a key exercises the arithmetic, not decryption)."""
+    g = _gens(seed, 2 * n_digits)
+    return np.stack([np.stack([uniform_residues(g[2 * j + b], moduli_pq, n) for b in range(2)])
+                     for j in range(n_digits)])
+
+
+def plain_poly(seed: int, n: int, t: int) -> np.ndarray:
+    """A plaintext polynomial with n i.i.d. coefficients uniform in [0, t)
+    (int64), for encrypting coefficient vectors directly when t has no
+    slots at this ring degree."""
+    return _gens(seed, 1)[0].integers(0, t, size=n, dtype=np.int64)
+
+
 # ---------------------------------------------------------------- columns ---
 
 def column_pair_half_match(seed: int, n_rows: int, bits: int = PAPER_BITS):

@@ -11,3 +11,11 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (HIP device)")
     config.addinivalue_line("markers", "slow: long CPU-side oracle work")
+
+
+@pytest.fixture(scope="session")
+def s32k():
+    """The paper's parameters (N = 32768, 17 + 1 primes, t = 65537) with the
+    keys of seed 0, shared by the full-size GPU test modules."""
+    from tests.gpu_common import Setup
+    return Setup(15)

@@ -31,6 +31,9 @@ class Setup:
         return bfv.encrypt_slots(self.pr, self.sk, slots, synth.enc_randomness(seed, self.pr.n,
                                                                                self.pr.q))
 
+    def enc_poly(self, m, seed):
+        return bfv.encrypt(self.pr, self.sk, m, synth.enc_randomness(seed, self.pr.n, self.pr.q))
+
     def to_dev(self, cts):
         """list of oracle ciphertexts -> int64 [n, comps, L, N] on the device."""
         arr = np.stack([np.stack([bfv.to_limbs(c, self.pr.q) for c in ct]) for ct in cts])

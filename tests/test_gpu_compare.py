@@ -79,8 +79,8 @@ def test_lt_t257_edges_broadcast(s257):
 
 def test_compare_rejects_non_fermat_t():
     """t = 97 (t - 1 not a power of two): no comparison polynomial; the
-    workspace query returns 0 and the call NSHE_EDEPTH before touching any
-    buffer."""
+    workspace query returns 0 and the call NSHE_EUNSUPPORTED before touching
+    any buffer."""
     S = Setup(4, t=97, seed=1)
     x = S.to_dev([S.enc(np.zeros(S.pr.n, dtype=np.int64), 1)])
     assert S.ctx._lib.nshe_compare_workspace_bytes(S.ctx._h, 1) == 0
@@ -88,4 +88,4 @@ def test_compare_rejects_non_fermat_t():
         S.ctx.compare(x, x)
     rc = S.ctx._lib.nshe_compare(S.ctx._h, x.data_ptr(), x.data_ptr(), 0, 0, x.data_ptr(), 1,
                                  None, 0, None)
-    assert rc == -5
+    assert rc == -7

@@ -27,11 +27,9 @@ class CustomSetup(Setup):
         self.ctx.set_relin_key(torch.from_numpy(self.rk.limbs(self.pr)).to(self.ctx.device))
 
 
-@pytest.mark.parametrize("L", [24, 2])
-def test_prime_count_extremes_bit_exact(L):
-    """L = 24 (the most primes) through the whole mask; L = 2 (too little
-    budget for a correct mask, but the textbook integers are still defined)
-    for one squaring and the mask."""
+def test_prime_count_extremes_bit_exact():
+    """L = 24 (the most primes): one squaring and the whole mask."""
+    L = 24
     primes = nt.primes_congruent_one_below(1 << 49, 1 << 16, L + 1)
     S = CustomSetup(8, primes[1:], primes[0], seed=L)
     x, y = synth.column_pair_half_match(L, S.pr.n)
@@ -43,8 +41,41 @@ def test_prime_count_extremes_bit_exact(L):
     levels, want = bfv.eq_chain(S.pr, S.rk, cx, cy)
     got = S.ctx.eq_mask(S.to_dev([cx]), S.to_dev([cy]))
     np.testing.assert_array_equal(got[0].cpu().numpy(), S.limbs(want))
-    if L == 24:
-        assert list(bfv.decrypt_slots(S.pr, S.sk, want)) == list((x == y).astype(int))
+    assert list(bfv.decrypt_slots(S.pr, S.sk, want)) == list((x == y).astype(int))
+
+
+def test_two_primes_depth_budget():
+    """L = 2 (Q of 98 bits): the budget allows two multiplications, so the
+    16-level mask is refused with NSHE_EDEPTH before any work (it would not
+    decrypt), while the squarings the budget allows are bit-exact and still
+    decrypt; the binding's per-ciphertext depth counter refuses the third."""
+    from paper_2602_24271_amd._lib import NsheError, NSHE_EDEPTH
+    L = 2
+    primes = nt.primes_congruent_one_below(1 << 49, 1 << 16, L + 1)
+    S = CustomSetup(8, primes[1:], primes[0], seed=L)
+    assert S.ctx.depth_budget == 2
+    x, y = synth.column_pair_half_match(L, S.pr.n)
+    cx, cy = S.enc(x, 1), S.enc(y, 2)
+    dx, dy = S.to_dev([cx]), S.to_dev([cy])
+    with pytest.raises(NsheError) as e:
+        S.ctx.eq_mask(dx, dy)
+    assert e.value.code == NSHE_EDEPTH
+    rc = S.ctx._lib.nshe_eq_mask(S.ctx._h, dx.data_ptr(), dy.data_ptr(), dx.data_ptr(), 1, 0,
+                                 None, 0, None)
+    assert rc == NSHE_EDEPTH
+    z = S.ctx.sub(dx, dy)
+    want = bfv.sub(S.pr, cx, cy)
+    zz = (x - y) % S.pr.t
+    for k in (1, 2):
+        z = S.ctx.square_relin(z)
+        want = bfv.square_relin(S.pr, S.rk, want)
+        np.testing.assert_array_equal(z[0].cpu().numpy(), S.limbs(want))
+        assert S.ctx.depth(z) == k
+        assert list(bfv.decrypt_slots(S.pr, S.sk, want)) == \
+            [pow(int(v), 2 ** k, S.pr.t) for v in zz]
+    with pytest.raises(NsheError) as e:
+        S.ctx.square_relin(z)
+    assert e.value.code == NSHE_EDEPTH
 
 
 @pytest.fixture(scope="module")

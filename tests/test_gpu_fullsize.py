@@ -14,11 +14,6 @@ from tests.gpu_common import Setup
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module")
-def s32k():
-    return Setup(15)
-
-
 def test_full_size_ntt_sampled(s32k):
     S = s32k
     rng = np.random.default_rng(3)
