@@ -46,9 +46,10 @@ class Context:
         self.fresh_bits = info.fresh_bits
         self.level_bits = info.level_bits
         # per-ciphertext-array level counter (Sec. 2.1.2): the depth of every
-        # output this context produced; arrays it did not produce count as
-        # fresh (depth 0) unless set_depth says otherwise
-        self._depths = weakref.WeakKeyDictionary()
+        # output this context produced, by tensor identity (an entry leaves
+        # with its tensor); arrays it did not produce count as fresh
+        # (depth 0) unless set_depth says otherwise
+        self._depths = {}
         self.q = list(q)
         self.P = P
         self.t = t
@@ -98,10 +99,13 @@ class Context:
     # ------------------------------------------------------------ depth
     def depth(self, x: torch.Tensor) -> int:
         """Multiplicative depth of a ciphertext array (0 if unknown)."""
-        return self._depths.get(x, 0)
+        return self._depths.get(id(x), 0)
 
     def set_depth(self, x: torch.Tensor, depth: int) -> None:
-        self._depths[x] = int(depth)
+        k = id(x)
+        if k not in self._depths:
+            weakref.finalize(x, self._depths.pop, k, None)
+        self._depths[k] = int(depth)
 
     def op_depth(self, op: str, arg: int = 0) -> int:
         d = ctypes.c_int()
@@ -117,7 +121,7 @@ class Context:
         return d.value
 
     def _tag(self, out: torch.Tensor, depth: int) -> torch.Tensor:
-        self._depths[out] = depth
+        self.set_depth(out, depth)
         return out
 
     # ------------------------------------------------------------ debug

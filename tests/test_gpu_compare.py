@@ -84,8 +84,10 @@ def test_compare_rejects_non_fermat_t():
     S = Setup(4, t=97, seed=1)
     x = S.to_dev([S.enc(np.zeros(S.pr.n, dtype=np.int64), 1)])
     assert S.ctx._lib.nshe_compare_workspace_bytes(S.ctx._h, 1) == 0
-    with pytest.raises(ValueError):
+    from paper_2602_24271_amd._lib import NsheError, NSHE_EUNSUPPORTED
+    with pytest.raises(NsheError) as e:
         S.ctx.compare(x, x)
+    assert e.value.code == NSHE_EUNSUPPORTED
     rc = S.ctx._lib.nshe_compare(S.ctx._h, x.data_ptr(), x.data_ptr(), 0, 0, x.data_ptr(), 1,
                                  None, 0, None)
     assert rc == -7

@@ -60,8 +60,10 @@ def test_two_primes_depth_budget():
     with pytest.raises(NsheError) as e:
         S.ctx.eq_mask(dx, dy)
     assert e.value.code == NSHE_EDEPTH
-    rc = S.ctx._lib.nshe_eq_mask(S.ctx._h, dx.data_ptr(), dy.data_ptr(), dx.data_ptr(), 1, 0,
-                                 None, 0, None)
+    ws = S.ctx.workspace(1)
+    out = torch.empty_like(dx)
+    rc = S.ctx._lib.nshe_eq_mask(S.ctx._h, dx.data_ptr(), dy.data_ptr(), out.data_ptr(), 1, 0,
+                                 ws.data_ptr(), ws.numel(), None)
     assert rc == NSHE_EDEPTH
     z = S.ctx.sub(dx, dy)
     want = bfv.sub(S.pr, cx, cy)
