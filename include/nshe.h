@@ -226,6 +226,24 @@ int nshe_eq_mask(nshe_ctx* ctx, const int64_t* x_dev, const int64_t* y_dev,
                  int64_t* out_dev, int n_ct, int y_broadcast, void* ws_dev,
                  size_t ws_bytes, void* stream);
 
+/* EQ for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation and results as nshe_eq_mask, with the library's own scratch,
+ * a file-scope device array of NSHE_NOALLOC_SCRATCH_BYTES (160 MiB) that
+ * each GPU the library runs on holds until the process ends.  It holds
+ * n_ct ciphertexts' workspace when n_ct * nshe_workspace_bytes(ctx, 1) fits
+ * in it (one ciphertext at N = 32768 with 17 primes, eight at N = 4096);
+ * larger calls return NSHE_ENOMEM before any work.  The caller passes inputs
+ * and outputs only.  Every call on one GPU, from any context, uses that
+ * GPU's one scratch, so calls that overlap on a GPU race: serialise them
+ * (one stream, or events between streams).  Nothing in the scratch needs to
+ * start at zero (every value is written before it is read); it keeps the
+ * last call's contents.  The call makes no hipMalloc, hipFree or other
+ * allocating call and records no profiling events. */
+#define NSHE_NOALLOC_SCRATCH_BYTES ((size_t)160 << 20)
+int nshe_eq_mask_noalloc(nshe_ctx* ctx, const int64_t* x_dev, const int64_t* y_dev,
+                         int64_t* out_dev, int n_ct, int y_broadcast, void* stream);
+
 /* Batched EQ over instances of uneven size: item i has n_ct ciphertexts.
  * The items' ciphertexts are processed together, in waves of at most
  * `wave_ct` ciphertexts, with one

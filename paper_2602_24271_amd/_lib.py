@@ -78,6 +78,7 @@ SIGNATURES = {
     "nshe_multiply": (_I, [_P, _P, _P, _P, _I, _P, _SZ, _P]),
     "nshe_relinearize": (_I, [_P, _P, _P, _I, _P, _SZ, _P]),
     "nshe_eq_mask": (_I, [_P, _P, _P, _P, _I, _I, _P, _SZ, _P]),
+    "nshe_eq_mask_noalloc": (_I, [_P, _P, _P, _P, _I, _I, _P]),
     "nshe_batched_workspace_bytes": (_SZ, [_P, _I, ctypes.c_longlong]),
     "nshe_eq_mask_batched": (_I, [_P, ctypes.POINTER(NsheItem), _I, _I, _I, _P, _SZ, _P]),
     "nshe_add": (_I, [_P, _P, _P, _P, _I, _P]),

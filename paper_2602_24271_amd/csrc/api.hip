@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -198,6 +199,7 @@ struct nshe_ctx {
   int depth_budget = 0;
   double fresh_bits = 0.0, level_bits = 0.0;
   uint32_t debug = 0;  // NSHE_DEBUG_* switches
+  void* scratch = nullptr;  // this device's copy of the no-allocation scratch
 };
 
 namespace nshe {
@@ -663,6 +665,34 @@ static int check_inputs(nshe_ctx* c, hipStream_t st, std::initializer_list<InSpa
   return NSHE_OK;
 }
 
+// ------------------------------------------------- no-allocation scratch
+
+// The scratch of nshe_eq_mask_noalloc: one ciphertext's workspace at the
+// paper's size (N = 2^15, 17 primes: 153.9 MB) fits.  Each GPU the library
+// runs on holds its own copy until the process ends.  In host code the name
+// stands for the array only as a symbol: kernels get the device address
+// that hipGetSymbolAddress returns for the current device (scratch_address).
+constexpr size_t kScratchBytes = NSHE_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static std::mutex g_scratch_mu;
+static std::map<int, void*> g_scratch_ptr;  // device -> address of its copy
+
+// This device's copy (`device` must be current), looked up once per device.
+static int scratch_address(int device, void** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(device);
+  if (it == g_scratch_ptr.end()) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(NSHE_EDEVICE, std::string("scratch address: ") + hipGetErrorString(e));
+    it = g_scratch_ptr.emplace(device, p).first;
+  }
+  *out = it->second;
+  return NSHE_OK;
+}
+
 // =================================================================== ABI
 
 extern "C" {
@@ -1017,6 +1047,11 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
     delete c;
     return fail(NSHE_EDEVICE, std::string("table upload: ") + hipGetErrorString(e));
   }
+  if ((rc = scratch_address(hip_device, &c->scratch))) {
+    (void)hipFree(c->dev_tables);
+    delete c;
+    return rc;
+  }
   *out = c;
   return rc;
 }
@@ -1310,8 +1345,8 @@ static int eq_levels(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st,
   return NSHE_OK;
 }
 
-int nshe_eq_mask(nshe_ctx* c, const int64_t* x, const int64_t* y, int64_t* out, int n_ct,
-                 int y_broadcast, void* ws, size_t ws_bytes, void* stream) {
+static int eq_mask_impl(nshe_ctx* c, const int64_t* x, const int64_t* y, int64_t* out,
+                        int n_ct, int y_broadcast, void* ws, size_t ws_bytes, void* stream) {
   int rc = common_checks(c, n_ct, ws, ws_bytes, true);
   if (rc) return rc;
   if (c->squarings < 0) return fail(NSHE_EUNSUPPORTED, "t - 1 is not a power of two");
@@ -1342,6 +1377,31 @@ int nshe_eq_mask(nshe_ctx* c, const int64_t* x, const int64_t* y, int64_t* out, 
     HIPCHK(run_polys_to_i64(d, w.ext, 2, 2 * W * N, W * N, out, 1, c->tb, st));
   }
   return NSHE_OK;
+}
+
+int nshe_eq_mask(nshe_ctx* c, const int64_t* x, const int64_t* y, int64_t* out, int n_ct,
+                 int y_broadcast, void* ws, size_t ws_bytes, void* stream) {
+  return eq_mask_impl(c, x, y, out, n_ct, y_broadcast, ws, ws_bytes, stream);
+}
+
+int nshe_eq_mask_noalloc(nshe_ctx* c, const int64_t* x, const int64_t* y, int64_t* out,
+                         int n_ct, int y_broadcast, void* stream) {
+  g_err.clear();
+  if (check_ctx(c)) return NSHE_EINVAL;
+  if (n_ct < 0) return fail(NSHE_ESHAPE, "n_ct < 0");
+  const size_t need = ws_doubles(c, n_ct) * sizeof(double);
+  if (need > kScratchBytes)
+    return fail(NSHE_ENOMEM, std::to_string(n_ct) + " ciphertexts need " + std::to_string(need) +
+                                 " bytes of scratch; nshe_eq_mask_noalloc has " +
+                                 std::to_string(kScratchBytes) +
+                                 " (split the call, or use nshe_eq_mask with a workspace)");
+  if (!c->scratch) return fail(NSHE_EDEVICE, "no scratch on this device");
+  // profiling records would create events: none in this call
+  const bool prof = c->prof;
+  c->prof = false;
+  const int rc = eq_mask_impl(c, x, y, out, n_ct, y_broadcast, c->scratch, kScratchBytes, stream);
+  c->prof = prof;
+  return rc;
 }
 
 // Batched waves.  The caller's workspace holds, after the ciphertext area

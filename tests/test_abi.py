@@ -90,3 +90,28 @@ def test_default_parameters_match_the_oracle():
     q, P = params.modulus_chain()
     oq, oP = nt.default_modulus_chain()
     assert (q, P) == (oq, oP)
+
+
+def test_noalloc_scratch_is_a_global_device_symbol(tmp_path):
+    """The no-allocation entry point's scratch array must be a global symbol
+    of the device code object: the runtime finds registered device variables
+    by name among global symbols when it loads the code (a local one is not
+    found).  Checked on the built library with the ROCm LLVM tools."""
+    import shutil
+    import subprocess
+    objdump = "/opt/rocm/llvm/bin/llvm-objdump"
+    readelf = "/opt/rocm/llvm/bin/llvm-readelf"
+    if not (os.path.exists(objdump) and os.path.exists(readelf)):
+        pytest.skip("ROCm LLVM tools not installed")
+    lib = tmp_path / "libnshe.so"
+    shutil.copy(_lib.LIB_PATH, lib)
+    subprocess.run([objdump, "--offloading", str(lib)], cwd=tmp_path, capture_output=True,
+                   check=True)
+    found = []
+    for f in sorted(tmp_path.glob("libnshe.so.*gfx950")):
+        out = subprocess.run([readelf, "-s", "--wide", str(f)], capture_output=True, text=True,
+                             check=True).stdout
+        found += [line.split() for line in out.splitlines() if line.endswith("_ZL7scratch")]
+    assert found, "no scratch symbol in the device code"
+    # (the static and the dynamic symbol tables may both list it)
+    assert {(int(f[2]), f[3], f[4]) for f in found} == {(160 << 20, "OBJECT", "GLOBAL")}, found
