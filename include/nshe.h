@@ -404,15 +404,19 @@ int nshe_sum_slots(nshe_ctx* ctx, const int64_t* in_dev, int64_t* out_dev, int n
  *   ew_block       threads per workgroup of the per-coefficient kernels
  *                  (base lift, scale-and-round, mod-down): 64, 128 or 256;
  *   wave_ct        ciphertexts per wave of nshe_eq_mask_batched when its
- *                  wave_ct argument is 0 (0: as many as the workspace holds).
- * A new context starts at {32, 1, 128, 0}.  nshe_set_tuning validates the
+ *                  wave_ct argument is 0 (0: as many as the workspace holds);
+ *   ks_fused       1: at N = 32768 with split_forward, the key-switch
+ *                  product runs fused with the digit transforms (one
+ *                  kernel; the digits' transforms are never written),
+ *                  0: digit transforms, then the product (two kernels).
+ * A new context starts at {32, 1, 128, 0, 0}.  nshe_set_tuning validates the
  * values (NSHE_EINVAL otherwise) and drops the batched call's cached graphs.
  *
  * nshe_autotune measures, on the caller's sample ciphertexts (int64
  * [n_sample][2][L][N], repeated cyclically to fill larger trials), squaring
- * levels of the EQ chain with HIP events: first ks_chunk, split_forward and
- * ew_block one at a time (each judged by the event time of the kernels it
- * shapes, on min(32, wave limit) ciphertexts), then the per-ciphertext
+ * levels of the EQ chain with HIP events: first ks_chunk, split_forward,
+ * ks_fused and ew_block one at a time (each judged by the event time of the
+ * kernels it shapes, on min(32, wave limit) ciphertexts), then the per-ciphertext
  * time of a level at 1, 2, 4, ... ciphertexts up to the wave limit
  * (max_wave_ct if > 0, and what ws_bytes holds), keeping the smallest wave
  * within 1% of the best rate.  The result becomes the context's tuning and
@@ -426,6 +430,7 @@ typedef struct {
   int32_t split_forward;
   int32_t ew_block;
   int32_t wave_ct;
+  int32_t ks_fused;
 } nshe_tuning;
 
 int nshe_get_tuning(nshe_ctx* ctx, nshe_tuning* out_host);

@@ -393,7 +393,7 @@ class Context:
                                                   _stream()))
         return res
 
-    TUNING_FIELDS = ("ks_chunk", "split_forward", "ew_block", "wave_ct")
+    TUNING_FIELDS = ("ks_chunk", "split_forward", "ew_block", "wave_ct", "ks_fused")
     DEFAULT_WAVE = 32  # batched wave when neither the call nor the tuning sets one
 
     def tuning(self) -> dict:

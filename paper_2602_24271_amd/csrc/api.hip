@@ -188,7 +188,7 @@ struct nshe_ctx {
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
   hipStream_t cap_stream = nullptr;  // capture-only stream (the null stream cannot capture)
-  nshe_tuning tune{32, 1, 128, 0};   // the autotuner's choice at 32 ciphertexts, N = 2^15
+  nshe_tuning tune{32, 1, 128, 0, 0};  // the autotuner's choice at 32 ciphertexts, N = 2^15
   std::map<uint32_t, double*> galois;  // Galois element -> switching key (NTT domain)
   // comparison polynomial (t = 2^K + 1 prime; lt_K = 0 otherwise): k babies,
   // m giants, coefficient matrix [m][k] (centred ints) on the device
@@ -236,11 +236,11 @@ static Dims dims(const nshe_ctx* c, int n_ct) {
 
 enum Kind { K_SUB, K_LIFT, K_NTT_FWD, K_NTT_INV_TENSOR, K_NTT_INV, K_SCALE, K_NTT_DIGIT,
             K_KS_MAC, K_MODDOWN, K_CONVERT, K_AUTOMORPH, K_ADD, K_LINCOMB, K_MODDOWN_LIFT,
-            K_TENSOR_MAC, K_COUNT };
+            K_TENSOR_MAC, K_KS_FUSED, K_COUNT };
 static const char* kKindName[K_COUNT] = {"sub",   "lift",      "ntt_fwd", "ntt_inv_tensor",
                                          "ntt_inv", "scale", "ntt_digit", "ks_mac",
                                          "moddown", "convert", "automorph", "add", "lincomb",
-                                         "moddown_lift", "tensor_mac"};
+                                         "moddown_lift", "tensor_mac", "ks_fused"};
 
 static hipEvent_t take_event(nshe_ctx* c) {
   if (!c->pool.empty()) {
@@ -399,6 +399,16 @@ static int tensor_scale(nshe_ctx* c, const Ws& w, const double* fx_b, int n_ct, 
   return NSHE_OK;
 }
 
+// 2^15-point limbs with the split transforms: the key-switch product may
+// run fused with the digit transforms (k_ks_fused), a tuning choice.
+static bool ks_fused(const nshe_ctx* c) {
+  return c->log2n == 15 && c->tune.split_forward && c->tune.ks_fused && c->tb.tw_half;
+}
+
+static int digit_products(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st, const double* key);
+static int finish_relin(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st, double* out,
+                        bool lift_out, int64_t* finish_out, int64_t* i64_out, bool accumulate);
+
 // Key-switch the third component in dt (limbs 0..L-1, canonical) with
 // `key` (the relinearization key unless given) and add the result to the
 // first two: (c0 + k0, c1 + k1) into `out` (ext unless given), limbs 0..L-1.
@@ -413,6 +423,27 @@ static int relin(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st,
                  bool accumulate = false) {
   if (!key) key = c->evk;
   if (!out) out = w.ext;
+  if (ks_fused(c)) {
+    NttJob j{};
+    j.npoly = n_ct;
+    j.digits = c->L;
+    j.nlimb = c->L + 1;
+    j.limb_prime = c->lp_ks;
+    j.count = n_ct * c->L * (c->L + 1);
+    j.src = w.dt + (size_t)2 * W_of(c) * c->n;
+    j.src_ct_stride = (size_t)3 * W_of(c) * c->n;
+    Prof pf(c, K_KS_FUSED, st, ntt_work(c, j.count));
+    HIPCHK(run_ks_fused(j, key, w.acc, c->tb, st));
+  } else {
+    int rc0 = digit_products(c, w, n_ct, st, key);
+    if (rc0) return rc0;
+  }
+  return finish_relin(c, w, n_ct, st, out, lift_out, finish_out, i64_out, accumulate);
+}
+
+// The digits' transforms (written to w.dig) and their products with the
+// key, summed into w.acc (two kernels).
+static int digit_products(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st, const double* key) {
   Dims d = dims(c, n_ct);
   NttJob j{};
   j.split = c->tune.split_forward;
@@ -434,6 +465,13 @@ static int relin(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st,
     Prof pf(c, K_KS_MAC, st, (double)n_ct * c->L * 2 * (c->L + 1) * c->n);
     HIPCHK(run_ks_mac(d, w.dig, key, w.acc, c->tb, st));
   }
+  return NSHE_OK;
+}
+
+// The key-switch sums in w.acc -> inverse transform -> mod-down (see relin).
+static int finish_relin(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st, double* out,
+                        bool lift_out, int64_t* finish_out, int64_t* i64_out, bool accumulate) {
+  Dims d = dims(c, n_ct);
   int rc = ntt_job_ks(c, w.acc, nullptr, n_ct * 2, 1, st, true);
   if (rc) return rc;
   if (finish_out && d.fused) {
@@ -2173,7 +2211,8 @@ int nshe_in_mask(nshe_ctx* c, const int64_t* x, const int64_t* set, int k, int64
 static bool tuning_valid(const nshe_tuning& t) {
   const bool ks = t.ks_chunk == 4 || t.ks_chunk == 8 || t.ks_chunk == 16 || t.ks_chunk == 32;
   const bool blk = t.ew_block == 64 || t.ew_block == 128 || t.ew_block == 256;
-  return ks && blk && (t.split_forward == 0 || t.split_forward == 1) && t.wave_ct >= 0;
+  return ks && blk && (t.split_forward == 0 || t.split_forward == 1) && t.wave_ct >= 0 &&
+         (t.ks_fused == 0 || t.ks_fused == 1);
 }
 
 static void drop_graphs(nshe_ctx* c) {
@@ -2330,6 +2369,17 @@ int nshe_autotune(nshe_ctx* c, const int64_t* sample, int n_sample, int max_wave
       const double tt = ms[K_NTT_FWD] + ms[K_NTT_DIGIT];
       if (tt < tbest) { tbest = tt; best.split_forward = v; }
     }
+  }
+  if (c->log2n == 15 && best.split_forward) {
+    double tt[2];
+    for (int v = 0; v < 2; ++v) {
+      nshe_tuning t = best;
+      t.ks_fused = v;
+      rc = time_kinds(c, t, w, n_t, 2, st, ms);
+      if (rc) { c->tune = start; return rc; }
+      tt[v] = v ? ms[K_KS_FUSED] : ms[K_NTT_DIGIT] + ms[K_KS_MAC];
+    }
+    best.ks_fused = tt[1] < tt[0] ? 1 : 0;
   }
   {
     const int cand[] = {64, 128, 256};

@@ -127,6 +127,12 @@ struct NttJob {
 // layout direction 3 writes.
 
 hipError_t run_ntt(int log2n, const NttJob& job, const Tables& tb, int dir, hipStream_t st);
+// key-switch product fused with the digit transforms (N = 2^15 only):
+// job.npoly = ciphertexts, job.digits = L, job.nlimb = L + 1, job.src /
+// src_ct_stride the digits' canonical source limbs, job.limb_prime the
+// key-switching basis; writes acc [n_ct][2][L+1][N] (NTT domain)
+hipError_t run_ks_fused(const NttJob& job, const double* evk, double* acc, const Tables& tb,
+                        hipStream_t st);
 int ntt_rounds(int log2n, int* loge, int* r0);
 
 // Per-coefficient and elementwise kernels (rns.hip).

@@ -921,6 +921,123 @@ k_ntt_fwd_half(NttJob job, Tables tb) {
   for (int e = 0; e < S::E; ++e) buf_store(x[e], rd, so, e * 1024 * 8);
 }
 
+// The key-switch product fused with the digit transforms (N = 2^15): a
+// workgroup of 512 threads takes one ciphertext, one target prime of the
+// key-switching basis (limb i < L + 1) and one output half h, and for each
+// digit D_j = [c2]_{q_j}, j = 0..L-1, runs the half-limb forward transform
+// of k_ntt_fwd_half (NTT_DIGIT) in prime i, then multiplies the result by
+// the key's NTT-domain limbs evk[j][0][i] and evk[j][1][i] (same positions)
+// and adds the products to two sums held in registers across the digits.
+// The digits' transforms are never written; the sums are written once, in
+// the layout of k_ks_mac's output (the split inverse's input).  Bounds: the
+// unreduced digit transforms stay below 5.9 p (k_ntt_fwd_half), so each
+// lazy product with a balanced key is below 1.05 p and eight of them plus
+// a reduced sum below 9 p < 2^53 / p: the sums are reduced every 8 digits.
+// Work items: ciphertexts in groups of CG = min(4, n_ct); within a group,
+// item = (limb, half) pair * CG + ciphertext, groups one after the other,
+// and each XCD takes a contiguous range, so that the workgroups resident on
+// an XCD at one time cover a few ciphertexts times a few (limb, half) pairs
+// and share both the digits' source limbs and the key's limbs through L2.
+// Registers: 32 values plus 2 x 32 sums per thread (two waves per SIMD,
+// one workgroup per CU).
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2)))
+k_ks_fused(NttJob job, const double* __restrict__ evk, double* __restrict__ acc, Tables tb) {
+  using S = NttShape<14>;
+  constexpr int NF = 1 << 15;
+  constexpr int R1 = 1 << S::s_start(1);
+  static_assert(R1 * LDS_ROW == 512, "one table entry per thread");
+  __shared__ uint32_t lds[S::LDS_WORDS];
+  __shared__ double ltw[R1 * LDS_ROW];
+  const int n_ct = job.npoly, L = job.digits, K = job.nlimb;
+  const int cg = n_ct < 4 ? n_ct : 4;
+  const int count = ((n_ct + cg - 1) / cg) * cg * 2 * K;
+  const int item = xcd_item(count);
+  if (item >= count) return;
+  const int pair = (item / cg) % (2 * K);
+  const int ct = (item / (cg * 2 * K)) * cg + item % cg;
+  if (ct >= n_ct) return;
+  const int limb = pair >> 1, h = pair & 1;
+  const int prime = cldi(job.limb_prime, limb);
+  const double p = cld(tb.p, prime), pinv = cld(tb.pinv, prime);
+  const double w0 = h ? -cld(tb.tw_half0, prime) : cld(tb.tw_half0, prime);
+  const TwSrc tw{tb.tw_half + ((size_t)prime * 2 + h) * tb.tw_half_len,
+                 tb.tw_cmp_h + ((size_t)prime * 2 + h) * tb.tw_cmp_h_len,
+                 tb.tw_cst_f + (size_t)prime * 32};
+  // round 1's rows into LDS once (read after the first exchange's barriers)
+  ltw[threadIdx.x] = tb.tw_r1_f[((size_t)prime * 2 + h) * 512 + threadIdx.x];
+  const int tid = threadIdx.x;
+  const unsigned vo = tid * 8;
+  const unsigned so = (h * S::T + tid) * 8;   // this thread's output positions
+  static_assert(fwd_schedule_ok<14>(1), "forward reduction schedule");
+  constexpr int HALF_REDUCE_ROUND = 2;
+  static_assert(S::ROUNDS == 3 && fwd_reduces_after<14>(HALF_REDUCE_ROUND - 1, 1) &&
+                    1 + S::stages(0) + S::stages(1) == FWD_STAGES_PER_REDUCTION,
+                "half reduction placement");
+  double a0[S::E], a1[S::E];
+#pragma unroll
+  for (int e = 0; e < S::E; ++e) a0[e] = a1[e] = 0.0;
+  double x[S::E];
+  // digit j's source: canonical residues in [0, q_j), below 2 p_i; the X
+  // operands of stage 0 of the next digit are loaded into x[e] as soon as
+  // this digit's product has used x[e], so they arrive during the products
+  const double* src = job.src + (size_t)ct * job.src_ct_stride;
+  {
+    const auto rs = make_rsrc(src, NF * 8);
+#pragma unroll
+    for (int e = 0; e < S::E; ++e) x[e] = buf_load(rs, vo, e * S::T * 8);
+  }
+  for (int j = 0; j < L; ++j) {
+    const auto rs = make_rsrc(src + (size_t)j * NF, NF * 8);
+    // stage 0 of this half: X + w0 Y (lazy), X and Y NF/2 apart
+    constexpr int G = 8;
+#pragma unroll
+    for (int g = 0; g < S::E; g += G) {
+      double y[G];
+#pragma unroll
+      for (int i = 0; i < G; ++i) y[i] = buf_load(rs, vo, ((g + i) * S::T + (NF >> 1)) * 8);
+#pragma unroll
+      for (int i = 0; i < G; ++i) x[g + i] += mul_lazy(y[i], w0, p, pinv);
+    }
+#pragma unroll
+    for (int r = 0; r < S::ROUNDS; ++r) {
+      // the first exchange of a later digit waits for every wave's reads of
+      // the previous digit's last exchange
+      if (r > 0) exchange<14>(x, r - 1, r, lds, r > 1 || j > 0);
+      fwd_round<14, true>(x, r,
+                          fwd_reduces_after<14>(r, 1) && r != HALF_REDUCE_ROUND - 1 &&
+                              r != S::ROUNDS - 1,
+                          tw, p, pinv, ltw, r == HALF_REDUCE_ROUND);
+    }
+    const size_t kj = (size_t)j * 2 * K + limb;
+    const auto rk0 = make_rsrc(evk + kj * NF, NF * 8);
+    const auto rk1 = make_rsrc(evk + (kj + K) * NF, NF * 8);
+    // past the last digit the next-digit loads read out of range (zeros)
+    const auto rn = make_rsrc(src + (size_t)(j + 1) * NF, j + 1 < L ? NF * 8 : 0);
+#pragma unroll
+    for (int e = 0; e < S::E; ++e) {
+      const double k0 = buf_load(rk0, so, e * 1024 * 8);
+      const double k1 = buf_load(rk1, so, e * 1024 * 8);
+      a0[e] += mul_lazy(x[e], k0, p, pinv);
+      a1[e] += mul_lazy(x[e], k1, p, pinv);
+      x[e] = buf_load(rn, vo, e * S::T * 8);
+    }
+    if ((j & 7) == 7) {
+#pragma unroll
+      for (int e = 0; e < S::E; ++e) {
+        a0[e] = reduce_bal(a0[e], p, pinv);
+        a1[e] = reduce_bal(a1[e], p, pinv);
+      }
+    }
+  }
+  const auto ro0 = make_rsrc(acc + ((size_t)ct * 2 * K + limb) * NF, NF * 8);
+  const auto ro1 = make_rsrc(acc + ((size_t)(ct * 2 + 1) * K + limb) * NF, NF * 8);
+#pragma unroll
+  for (int e = 0; e < S::E; ++e) {
+    buf_store(reduce_bal(a0[e], p, pinv), ro0, so, e * 1024 * 8);
+    buf_store(reduce_bal(a1[e], p, pinv), ro1, so, e * 1024 * 8);
+  }
+}
+
 // Inverse of a 2^15-point limb by two workgroups of 512 threads that stop
 // before the last Gentleman-Sande stage.  Every stage but the last pairs
 // indices with the same top bit h, so half h (standard indices h 2^14 + i')
@@ -1068,6 +1185,16 @@ static hipError_t launch_ntt(const NttJob& job, const Tables& tb, int dir, hipSt
     hipLaunchKernelGGL((k_ntt_inv<LOGN, INV_TENSOR>), grid, block, 0, st, job, tb);
   else
     hipLaunchKernelGGL((k_ntt_inv<LOGN, INV_TENSOR2>), grid, block, 0, st, job, tb);
+  return hipGetLastError();
+}
+
+hipError_t run_ks_fused(const NttJob& job, const double* evk, double* acc, const Tables& tb,
+                        hipStream_t st) {
+  if (!tb.tw_half || job.npoly <= 0) return hipErrorInvalidValue;
+  const int cg = job.npoly < 4 ? job.npoly : 4;
+  const int count = ((job.npoly + cg - 1) / cg) * cg * 2 * job.nlimb;
+  dim3 grid(((count + 7) >> 3) * 8), block(512);
+  hipLaunchKernelGGL(k_ks_fused, grid, block, 0, st, job, evk, acc, tb);
   return hipGetLastError();
 }
 

@@ -55,6 +55,28 @@ def test_eq_chain_every_level_and_mask(s32k):
     assert list(bfv.decrypt_slots(S.pr, S.sk, got)) == list((x == y).astype(int))
 
 
+@pytest.mark.parametrize("fused", [0, 1])
+def test_key_switch_paths_full_size(s32k, fused):
+    """Both key-switch products at N = 32768 (digit transforms written and
+    then multiplied by the key, or the two fused in one kernel), through a
+    squaring level, the whole mask, a batched wave and a rotate-and-add:
+    bit-exact against the oracle."""
+    S = s32k
+    E = _env(S)
+    g = fc.load_golden("eq_edges")
+    x, y, cx, cy = fc.eq_edges_inputs(E)
+    dx, dy = _dev(S, [cx]), _dev(S, [cy])
+    start = S.ctx.tuning()
+    try:
+        S.ctx.set_tuning(ks_fused=fused, split_forward=1)
+        fc.check(g, "level_01", S.ctx.square_relin(S.ctx.sub(dx, dy))[0].cpu().numpy())
+        fc.check(g, "mask", S.ctx.eq_mask(dx, dy)[0].cpu().numpy())
+        outs = S.ctx.eq_mask_batched([(dx, dy)], wave_ct=1, use_graph=True)
+        fc.check(g, "mask", outs[0][0].cpu().numpy())
+    finally:
+        S.ctx.set_tuning(**start)
+
+
 def test_eq_column_uniform_2p20_rows(s32k):
     """configs[1] seed 0 in the benchmark's launch shape: 32 ciphertexts in
     one nshe_eq_mask call, every mask bit-exact."""
@@ -119,8 +141,14 @@ def test_sum_slots_full_size(s32k, uniform_keys):
     g = fc.load_golden("rotations")
     _, ct = fc.rotate_inputs(E)
     assert S.ctx.galois_elements() == galois.sum_elements(S.pr.n)
-    out = S.ctx.sum_slots(_dev(S, [ct]))
-    fc.check(g, "sum_slots", out[0].cpu().numpy())
+    start = S.ctx.tuning()
+    try:
+        for fused in (0, 1):
+            S.ctx.set_tuning(ks_fused=fused)
+            out = S.ctx.sum_slots(_dev(S, [ct]))
+            fc.check(g, "sum_slots", out[0].cpu().numpy())
+    finally:
+        S.ctx.set_tuning(**start)
 
 
 def test_select_extract_broadcast_full_size(s32k, uniform_keys):
