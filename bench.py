@@ -252,7 +252,7 @@ def timed(fn, reps: int) -> float:
 def next_rows(ctx, x, mask, reps: int) -> dict:
     """The operators built on EQ over the same column (n_ct ciphertexts):
     IN against 4 encrypted members (Eq. eq:in), SELECT (Eq. eq:select), the
-    rotate-and-add SUM/COUNT (Sec. 4.3) with 15 Galois keys, and LT against
+    rotate-and-add SUM/COUNT (Sec. 4.2.2) with 15 Galois keys, and LT against
     one constant (Eq. eq:inequality).  Keys, members and the constant are
     seeded uniform residues (timing is data-oblivious)."""
     import synth

@@ -7,16 +7,16 @@ library: it derives its own primes, its own NTT basis and its own CRT
 constants, and reaches every ciphertext through plain big-integer
 definitions.
 
-What it computes (NSHEDB, Sec. 2.1.5-2.1.6 and Sec. 4.3):
+What it computes (NSHEDB, Sec. 2.1.6-2.1.7, Sec. 4.2.2 and Sec. 4.3.1):
 
 * word-level BFV over R_Q = Z_Q[X]/(X^N + 1) with batch encoding of N slots
-  in Z_t (Sec. 3.1 data storage; BFV operations, Sec. 2.1.5);
+  in Z_t (Sec. 4.1 data storage; BFV operations, Sec. 2.1.6);
 * the equality mask EQ(x, y) = 1 - (x - y)^(p-1) (Eq. eq:equality), which for
   a Fermat prime p = t (p - 1 = 2^k) is exactly k chained squarings, each
-  followed by relinearization (Sec. 4.3, equality checks: exponentiation by
-  squaring with ceil(log2(p-1)) multiplications; Sec. 2.1.3, relinearization
+  followed by relinearization (Sec. 4.3.1, equality checks: exponentiation by
+  squaring with ceil(log2(p-1)) multiplications; Sec. 2.1.2, relinearization
   after every multiplication);
-* an exact noise meter (Sec. 2.1.3 multiplicative depth / noise budget).
+* an exact noise meter (Sec. 2.1.2 multiplicative depth / noise budget).
 
 Modules
   nt        primality, NTT-friendly prime search, roots of unity

@@ -7,7 +7,7 @@ Every ciphertext here is a tuple of polynomials with integer coefficients in
 rounding done on exact Python integers.  The paper fixes the scheme (BFV,
 Sec. 1 and 2.1.5), the parameters (n = 32768, log Q = 881, p = t = 65537,
 Sec. 5.1) and the mask (Eq. eq:equality, evaluated by exponentiation by
-squaring, Sec. 4.3); it leaves the RNS split, distributions, relinearization
+squaring, Sec. 4.3.1); it leaves the RNS split, distributions, relinearization
 method and rounding conventions to the library (SEAL).  The readings taken
 here are:
 
@@ -213,7 +213,7 @@ def noise_bits(params: Params, sk: SecretKey, ct, m_true) -> float:
 # --------------------------------------------------------------- evaluate ---
 
 def sub(params: Params, x, y) -> tuple:
-    """Component-wise [x - y]_Q (BFV subtraction, Sec. 2.1.5)."""
+    """Component-wise [x - y]_Q (BFV subtraction, Sec. 2.1.6)."""
     Q = params.Q
     return tuple((ring.as_object(a) - ring.as_object(b)) % Q for a, b in zip(x, y))
 

@@ -28,7 +28,7 @@ chain's squarings:
   LT = c_(p-1) levels[K] + z * g.
 
 LE(x, y) = 1 - LT(y, x); BETWEEN(x, lo, hi) = LE(lo, x) * LE(x, hi), the
-product of two comparisons (Sec. 4.3, BETWEEN).
+product of two comparisons (Sec. 4.2.2, BETWEEN).
 """
 from __future__ import annotations
 
@@ -211,5 +211,5 @@ def le(params: bfv.Params, rk: bfv.RelinKey, x, y) -> tuple:
 
 
 def between(params: bfv.Params, rk: bfv.RelinKey, x, lo, hi) -> tuple:
-    """Encrypted [lo <= x <= hi] = LE(lo, x) * LE(x, hi) (Sec. 4.3)."""
+    """Encrypted [lo <= x <= hi] = LE(lo, x) * LE(x, hi) (Sec. 4.2.2)."""
     return bfv.mul_relin(params, rk, le(params, rk, lo, x), le(params, rk, x, hi))

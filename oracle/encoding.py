@@ -2,7 +2,7 @@
 
 Test infrastructure only (see the package docstring).
 
-NSHEDB packs S = N values into one ciphertext (Sec. 3.1, data storage and
+NSHEDB packs S = N values into one ciphertext (Sec. 4.1, data storage and
 encoding).  With t prime and t = 1 (mod 2N), X^N + 1 splits into N distinct
 linear factors (X - zeta) over Z_t, so Z_t[X]/(X^N+1) is isomorphic to Z_t^N
 by evaluation at the N primitive 2N-th roots of unity zeta = psi^e, e odd.

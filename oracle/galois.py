@@ -4,7 +4,7 @@ Test infrastructure only (see the package docstring).
 
 NSHEDB aggregates a batch-encoded ciphertext by repeated rotation and
 addition with a doubling pattern, so that after log2 of the slot count steps
-every slot holds the total (Sec. 4.3, aggregation: COUNT, SUM).  A rotation
+every slot holds the total (Sec. 4.2.2, aggregation: COUNT, SUM).  A rotation
 of BFV slots is the ring automorphism sigma_g : a(X) -> a(X^g) (g odd mod
 2N) applied to both ciphertext components, followed by key switching from
 sigma_g(s) back to s (the library-level method, which the paper leaves to

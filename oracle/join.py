@@ -2,10 +2,10 @@
 
 Test infrastructure only (see the package docstring).
 
-The paper derives two operations from BFV's primitives (Sec. 2.1.5): Extract
+The paper derives two operations from BFV's primitives (Sec. 2.1.6): Extract
 multiplies a ciphertext by the plaintext basis vector of one slot, and
 Broadcast replicates that slot's value everywhere by extraction followed by
-rotations and additions.  Its JOIN (Sec. 4.3, JOIN) extracts and broadcasts
+rotations and additions.  Its JOIN (Sec. 4.2.2, JOIN) extracts and broadcasts
 each reference-table key, masks the fact table with the equality of the
 keys, multiplies the mask with the reference table's projected attribute
 (also extracted and broadcast) and adds over the reference rows.  Readings:

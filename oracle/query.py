@@ -3,7 +3,7 @@
 Test infrastructure only (see the package docstring).
 
 NSHEDB turns SQL operators into ciphertext arithmetic around EQ
-(Sec. 4.3, query operators):
+(Sec. 4.2.2, query operators):
 
 * IN (set membership, Eq. eq:in): the sum over the set S of EQ(x, y); with
   distinct members at most one term is 1 per slot, so the sum decrypts to
@@ -11,7 +11,7 @@ NSHEDB turns SQL operators into ciphertext arithmetic around EQ
 * GROUP BY: one equality mask per distinct group value;
 * SELECT (Eq. eq:select): the selected column times the mask (one more
   multiplication followed by relinearization);
-* the sums above are BFV additions (Sec. 2.1.5), exact per coefficient
+* the sums above are BFV additions (Sec. 2.1.6), exact per coefficient
   modulo Q, so their order does not change the result.
 """
 from __future__ import annotations
@@ -21,7 +21,7 @@ from . import ring
 
 
 def add(params: bfv.Params, x, y) -> tuple:
-    """Component-wise [x + y]_Q (BFV addition, Sec. 2.1.5)."""
+    """Component-wise [x + y]_Q (BFV addition, Sec. 2.1.6)."""
     Q = params.Q
     return tuple((ring.as_object(a) + ring.as_object(b)) % Q for a, b in zip(x, y))
 

@@ -58,6 +58,16 @@ class NsheTuning(ctypes.Structure):
                 ("ks_fused", ctypes.c_int32)]
 
 
+class NsheModmulProbe(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double), ("products_per_s", ctypes.c_double),
+                ("fp64_ops_per_s", ctypes.c_double)]
+
+
+class NsheConvProbe(ctypes.Structure):
+    _fields_ = [("coefficients", ctypes.c_uint64), ("ms_fma", ctypes.c_double),
+                ("ms_mfma", ctypes.c_double), ("mismatches", ctypes.c_uint64)]
+
+
 # name -> (restype, argtypes)
 _P = ctypes.c_void_p
 _I = ctypes.c_int
@@ -108,6 +118,12 @@ SIGNATURES = {
     "nshe_profile": (_I, [_P, _I]),
     "nshe_profile_read": (_I, [_P, ctypes.POINTER(NsheKernelStat), _I, ctypes.POINTER(_I)]),
     "nshe_last_error": (ctypes.c_char_p, []),
+    # measurement entry points (include/nshe_probe.h)
+    "nshe_probe_modmul": (_I, [_I, _I, ctypes.POINTER(NsheModmulProbe)]),
+    "nshe_probe_conversion": (_I, [_I, ctypes.POINTER(ctypes.c_uint64), _I,
+                                   ctypes.POINTER(ctypes.c_uint64), _I, _SZ, _I,
+                                   ctypes.POINTER(NsheConvProbe)]),
+    "nshe_probe_last_error": (ctypes.c_char_p, []),
 }
 
 _lib = None

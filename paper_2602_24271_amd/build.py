@@ -15,7 +15,7 @@ import tempfile
 from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["csrc/ntt.hip", "csrc/rns.hip", "csrc/api.hip"]
+SOURCES = ["csrc/ntt.hip", "csrc/rns.hip", "csrc/api.hip", "csrc/probe.hip"]
 LIB = os.path.join(HERE, "libnshe.so")
 
 FLAGS = [

@@ -12,11 +12,11 @@ from paper_2602_24271_amd import _lib, params
 from oracle import nt
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "nshe.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("nshe.h", "nshe_probe.h")]
 
 
 def _declared():
-    text = open(HEADER).read()
+    text = "".join(open(h).read() for h in HEADERS)
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(nshe_[a-z_]+)\s*\(", text)))
 

@@ -1,5 +1,5 @@
 """Device parity of the range comparisons (Eq. eq:inequality; BETWEEN,
-Sec. 4.3): LT, LE and BETWEEN bit-exact against the oracle's program at
+Sec. 4.2.2): LT, LE and BETWEEN bit-exact against the oracle's program at
 t = 17 (every in-range pair) and t = 257 (edge differences), decrypting to
 the plain comparisons."""
 import numpy as np

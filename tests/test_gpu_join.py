@@ -1,5 +1,5 @@
-"""Device parity of plaintext products, Extract / Broadcast (Sec. 2.1.5)
-and the fused equi-join aggregation (Sec. 4.3, JOIN): bit-exact against the
+"""Device parity of plaintext products, Extract / Broadcast (Sec. 2.1.6)
+and the fused equi-join aggregation (Sec. 4.2.2, JOIN): bit-exact against the
 oracle, decrypting to the plain join."""
 import numpy as np
 import pytest

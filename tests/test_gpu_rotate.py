@@ -1,5 +1,5 @@
 """Device parity of slot rotations and the rotate-and-add aggregation
-(COUNT, SUM; Sec. 4.3): bit-exact against the oracle, decrypting to rotated
+(COUNT, SUM; Sec. 4.2.2): bit-exact against the oracle, decrypting to rotated
 slots and to totals."""
 import numpy as np
 import pytest

@@ -98,7 +98,7 @@ def test_rotations_decrypt_to_rotated_slots(n64):
 
 def test_sum_slots_counts_and_sums(n64):
     """COUNT of a 0/1 mask and SUM of a masked column: every slot holds the
-    total mod t (Sec. 4.3 aggregation)."""
+    total mod t (Sec. 4.2.2 aggregation)."""
     pr, sk, rk, keys = n64
     rng = np.random.default_rng(6)
     mask = (rng.random(pr.n) < 0.3).astype(np.int64)
