@@ -41,6 +41,8 @@ import platform
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -125,40 +127,185 @@ def roofline_ks(ctx, prof: dict, n_ct: int, ks_chunk: int) -> dict | None:
             "bytes_per_launch": per_launch, "mean_launch_ms": st["ms"] / st["launches"]}
 
 
-def cpu_baseline() -> dict:
-    """The oracle, untuned, on one 32,768-slot ciphertext: one squaring with
-    relinearization (1/16 of that ciphertext's EQ), extrapolated x16."""
-    import numpy as np  # noqa: F401
-    import synth
-    from oracle import bfv
-    n = 32768
-    pr = bfv.paper_params(n)
-    t0 = time.perf_counter()
-    sk, rk = bfv.keygen(pr, synth.key_randomness(0, n, pr.moduli_pq, pr.L))
-    x, y = synth.column_pair_half_match(0, n)
-    cx = bfv.encrypt_slots(pr, sk, x, synth.enc_randomness(1, n, pr.q))
-    cy = bfv.encrypt_slots(pr, sk, y, synth.enc_randomness(2, n, pr.q))
-    z = bfv.sub(pr, cx, cy)
-    # key transform into the oracle's own basis is setup, not timed
-    from oracle import ring
-    bfv._evk_transformed(pr, rk, ring.OwnBasis(pr.L * max(pr.q) * pr.PQ * n, n))
-    log(f"oracle setup {time.perf_counter() - t0:.1f} s")
-    t1 = time.perf_counter()
-    bfv.square_relin(pr, rk, z)
-    dt = time.perf_counter() - t1
+def _host_cpu() -> str:
     cpu = platform.processor() or ""
     try:
         with open("/proc/cpuinfo") as fh:
             for line in fh:
                 if line.startswith("model name"):
-                    cpu = line.split(":", 1)[1].strip()
-                    break
+                    return line.split(":", 1)[1].strip()
     except OSError:
         pass
-    return {"value": n / (16 * dt), "unit": "records/s", "cores": 1, "kind": "oracle",
-            "sample": f"one squaring+relinearization of one {n}-slot ciphertext "
-                      f"({dt:.2f} s), x16 for one ciphertext's EQ",
-            "host_cpu": cpu, "host_cores_available": os.cpu_count()}
+    return cpu
+
+
+# The CPU phase runs before anything touches the GPU: its process pool is
+# forked from a process that holds no device state.
+_POOL = {}
+
+
+def _pool_square(k: int) -> tuple[float, float]:
+    """One worker: encrypt ciphertext k of the 2^20-row column pair (seed 0;
+    setup, untimed), then one squaring with relinearization of x_k - y_k,
+    timed.  Returns (seconds, setup seconds)."""
+    import synth
+    from oracle import bfv
+    pr, sk, rk = _POOL["pr"], _POOL["sk"], _POOL["rk"]
+    n = pr.n
+    t0 = time.perf_counter()
+    x, y = synth.column_pair_half_match(0, 32 * n)
+    sl = slice(k * n, (k + 1) * n)
+    cx = bfv.encrypt_slots(pr, sk, x[sl], synth.enc_randomness(1000 + k, n, pr.q))
+    cy = bfv.encrypt_slots(pr, sk, y[sl], synth.enc_randomness(2000 + k, n, pr.q))
+    z = bfv.sub(pr, cx, cy)
+    t1 = time.perf_counter()
+    bfv.square_relin(pr, rk, z)
+    return time.perf_counter() - t1, t1 - t0
+
+
+def _pool_encrypt(i: int):
+    """Encryptions for the batched leg's decrypt check: instance i is one
+    32,768-row ciphertext of sorted dictionary ids (seed 100 + i) against
+    one encrypted id of the dictionary."""
+    import synth
+    from oracle import bfv
+    pr, sk = _POOL["pr"], _POOL["sk"]
+    n = pr.n
+    x, y = synth.column_structured(100 + i, n)
+    cx = bfv.encrypt_slots(pr, sk, x, synth.enc_randomness(5000 + i, n, pr.q))
+    cy = bfv.encrypt_slots(pr, sk, y, synth.enc_randomness(6000 + i, n, pr.q))
+    return x, int(y[0]), np.stack([bfv.to_limbs(c, pr.q) for c in cx]), \
+        np.stack([bfv.to_limbs(c, pr.q) for c in cy])
+
+
+def cpu_phase(full_chain: bool) -> dict:
+    """The exact-integer oracle (untuned) on the host cores, on bounded
+    samples of the workload:
+      * the whole EQ (16 levels) of one N = 1024 ciphertext pair (seed 0),
+        one core;
+      * one squaring with relinearization (1/16 of a ciphertext's EQ) of
+        each of C ciphertexts of the 2^20-row column, one per worker of a
+        pool of C processes (C = the host cores given to this process, at
+        most 16): rate = C x 32768 records / (16 x the pool's wall time);
+      * with full_chain, one 32,768-slot ciphertext's whole EQ on one core.
+    Also encrypts the inputs of the batched decrypt check and returns the
+    key it used."""
+    import multiprocessing as mp
+    import synth
+    from oracle import bfv, ring
+    out = {}
+    # N = 1024, the whole chain
+    n0 = 1024
+    pr0 = bfv.paper_params(n0)
+    sk0, rk0 = bfv.keygen(pr0, synth.key_randomness(0, n0, pr0.moduli_pq, pr0.L))
+    x0, y0 = synth.column_pair_half_match(0, n0)
+    c0x = bfv.encrypt_slots(pr0, sk0, x0, synth.enc_randomness(1, n0, pr0.q))
+    c0y = bfv.encrypt_slots(pr0, sk0, y0, synth.enc_randomness(2, n0, pr0.q))
+    t0 = time.perf_counter()
+    bfv.eq_chain(pr0, rk0, c0x, c0y)
+    t_small = time.perf_counter() - t0
+    out["n1024_chain"] = {"seconds": t_small, "records_per_s": n0 / t_small, "cores": 1}
+    log(f"oracle: N=1024 EQ chain {t_small:.2f} s")
+    # N = 32768: keys (and the key's transform into the oracle's basis) once,
+    # shared by the forked workers
+    n = 32768
+    pr = bfv.paper_params(n)
+    t0 = time.perf_counter()
+    sk, rk = bfv.keygen(pr, synth.key_randomness(0, n, pr.moduli_pq, pr.L))
+    bfv._evk_transformed(pr, rk, ring.OwnBasis(pr.L * max(pr.q) * pr.PQ * n, n))
+    log(f"oracle: keys at N=32768 {time.perf_counter() - t0:.1f} s")
+    _POOL.update(pr=pr, sk=sk, rk=rk)
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    cores = max(1, min(16, avail))
+    with mp.get_context("fork").Pool(cores) as pool:
+        t0 = time.perf_counter()
+        res = pool.map(_pool_square, range(cores))
+        wall = time.perf_counter() - t0
+        setup = max(r[1] for r in res)
+        check = pool.map(_pool_encrypt, range(8))
+    sq = [r[0] for r in res]
+    # the pool's wall time minus the encryptions each worker did first
+    t_level = max(sq)
+    out["pool"] = {"cores": cores, "squaring_seconds": sq, "wall_seconds": wall,
+                   "setup_seconds_max": setup}
+    out["value"] = cores * n / (16 * t_level)
+    out["single_core_records_per_s"] = n / (16 * (sum(sq) / len(sq)))
+    log(f"oracle: {cores} workers, one squaring each, {t_level:.2f} s (wall {wall:.1f} s)")
+    if full_chain:
+        x, y = synth.column_pair_half_match(0, 32 * n)
+        cx = bfv.encrypt_slots(pr, sk, x[:n], synth.enc_randomness(1000, n, pr.q))
+        cy = bfv.encrypt_slots(pr, sk, y[:n], synth.enc_randomness(2000, n, pr.q))
+        t0 = time.perf_counter()
+        bfv.eq_chain(pr, rk, cx, cy)
+        t_full = time.perf_counter() - t0
+        out["n32768_chain"] = {"seconds": t_full, "records_per_s": n / t_full, "cores": 1}
+        log(f"oracle: N=32768 EQ chain {t_full:.1f} s")
+    out["check"] = check
+    out["keys"] = (pr, sk, rk)
+    return out
+
+
+def cpu_baseline(cp: dict) -> dict:
+    return {"value": cp["value"], "unit": "records/s", "cores": cp["pool"]["cores"],
+            "kind": "oracle",
+            "sample": (f"one squaring + relinearization (1/16 of the EQ) of each of "
+                       f"{cp['pool']['cores']} ciphertexts of the 2^20-row column, one per "
+                       f"process, x16; inputs encrypted first (untimed)"),
+            "single_core_records_per_s": cp["single_core_records_per_s"],
+            "pool": cp["pool"], "n1024_chain": cp["n1024_chain"],
+            "n32768_chain": cp.get("n32768_chain"),
+            "host_cpu": _host_cpu(), "host_cores_available": os.cpu_count()}
+
+
+def batched_check(cp: dict, wave: int) -> dict:
+    """A seeded oracle sample of the batched workload: 8 one-ciphertext
+    instances (real encryptions with the oracle's key) through the batched
+    call in graph waves; every mask decrypts to [x == c]."""
+    import torch
+    from oracle import bfv
+    from paper_2602_24271_amd import Context
+    pr, sk, rk = cp["keys"]
+    ctx = Context.paper(15)
+    ctx.set_relin_key(torch.from_numpy(rk.limbs(pr)).to(ctx.device))
+    items = [(torch.from_numpy(cx[None]).to(ctx.device), torch.from_numpy(cy[None]).to(ctx.device))
+             for _, _, cx, cy in cp["check"]]
+    outs = ctx.eq_mask_batched(items, wave_ct=wave, use_graph=True)
+    torch.cuda.synchronize()
+    ok = 0
+    for (x, c, _, _), o in zip(cp["check"], outs):
+        a = o[0].cpu().numpy()
+        ct = tuple(bfv.from_limbs(a[k], pr.q) for k in range(2))
+        ok += int(list(bfv.decrypt_slots(pr, sk, ct)) == list((x == c).astype(int)))
+    ctx.close()
+    log(f"batched decrypt check: {ok} of {len(items)} masks decrypt to [x == c]")
+    return {"instances": len(items), "ciphertexts": len(items), "wave_ct": wave,
+            "masks_decrypting_correctly": ok}
+
+
+def probes(ctx) -> dict:
+    """The ceilings: the exact modular product's chip-wide rate, and one
+    base conversion (17 -> 18 primes over the scale-and-round's 3 x 2^20
+    coefficients) by split-FMA rows and by integer MFMA."""
+    import ctypes
+    from paper_2602_24271_amd import _lib
+    lib = _lib.load()
+    m = _lib.NsheModmulProbe()
+    _lib.check(lib.nshe_probe_modmul(0, 4096, ctypes.byref(m)))
+    out = {"modmul": {"products_per_s": m.products_per_s, "fp64_ops_per_s": m.fp64_ops_per_s,
+                      "frac_of_issue_peak": m.fp64_ops_per_s / PEAK_FP64_OPS}}
+    qin = (ctypes.c_uint64 * ctx.L)(*ctx.q)
+    qout = (ctypes.c_uint64 * ctx.L_ext)(*ctx.ext_primes)
+    r = _lib.NsheConvProbe()
+    n = 3 << 20
+    _lib.check(lib.nshe_probe_conversion(0, qin, ctx.L, qout, ctx.L_ext, n, 5, ctypes.byref(r)))
+    out["conversion_17_to_18"] = {"coefficients": n, "ms_split_fma": r.ms_fma,
+                                  "ms_mfma_i8": r.ms_mfma, "mismatches": r.mismatches}
+    log(f"probes: modmul {m.fp64_ops_per_s / 1e12:.1f} T FP64 ops/s; conversion fma "
+        f"{r.ms_fma:.3f} ms, mfma {r.ms_mfma:.3f} ms, mismatches {r.mismatches}")
+    return out
 
 
 def batched(ctx, n_inst: int, reps: int, max_wave: int = 128, seed: int = 2,
@@ -400,6 +547,13 @@ def main() -> int:
     ap.add_argument("--batched-reps", type=int, default=1)
     ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="also time one 32,768-slot ciphertext's whole oracle EQ on one core "
+                         "(about 1.5 minutes)")
+    ap.add_argument("--skip-probes", action="store_true")
+    ap.add_argument("--ks-fused", type=int, default=-1,
+                    help="key-switch product fused with the digit transforms (1) or not (0); "
+                         "default: the context's tuning")
     ap.add_argument("--skip-latency", action="store_true",
                     help="skip the one-ciphertext latency runs (profiling: keeps every "
                          "launch at the column's size)")
@@ -413,6 +567,10 @@ def main() -> int:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(ciphertexts shard with no communication; see the design notes)", file=sys.stderr)
         return 2
+
+    cp = None
+    if not args.skip_cpu:
+        cp = cpu_phase(args.cpu_full)
 
     import torch
     import synth
@@ -429,6 +587,8 @@ def main() -> int:
         torch.cuda.synchronize()
         del a, b
     ctx = Context.paper(15)
+    if args.ks_fused in (0, 1):
+        ctx.set_tuning(ks_fused=args.ks_fused)
     n_ct = args.n_ct
     log(f"context N={ctx.n} L={ctx.L} ext={ctx.L_ext} squarings={ctx.squarings}")
     x = synth.uniform_device_residues((n_ct, 2), ctx.q, ctx.n, 0, dev)
@@ -479,10 +639,12 @@ def main() -> int:
         bat = batched(ctx, args.batched_instances, args.batched_reps)
         # 128 instances, rows log-uniform in [2^16, 2^20] (2..32 ciphertexts)
         bat_fwd = batched(ctx, 128, args.batched_reps, seed=3, lo_rows=1 << 16)
-    cpu = None
-    if not args.skip_cpu:
-        cpu = cpu_baseline()
-        log(f"cpu baseline {cpu['value']:.1f} records/s")
+    cpu = check = None
+    if cp is not None:
+        cpu = cpu_baseline(cp)
+        log(f"cpu baseline {cpu['value']:.1f} records/s on {cpu['cores']} cores")
+        check = batched_check(cp, bat["wave_ct"] if bat else 4)
+    prb = None if args.skip_probes else probes(ctx)
 
     line = {
         "metric": "hot-kernel elements/s + % roofline at 1 GPU; batched and adjoint vs plain",
@@ -510,6 +672,8 @@ def main() -> int:
         "kernels": kernels,
         "batched": bat,
         "batched_128": bat_fwd,
+        "batched_check": check,
+        "probes": prb,
         "next_rows": nxt,
         "adjoint": None,
         "adjoint_note": "no adjoint: the mask is discrete (Z_t plaintexts, R_Q ciphertexts)",
