@@ -34,6 +34,15 @@
 namespace nshe {
 
 
+// Whether the lift takes its exact decision: S within 2^-40 of a
+// half-integer, or within 1/4 under the debug switch (tb.lift_edge < 1/2 -
+// 2^-40, a uniform flag: the default window stays a literal, which keeps the
+// kernels' register counts).
+__device__ __forceinline__ bool lift_near_half(double S, double v, const Tables& tb) {
+  const double d = __builtin_fabs(S - v);
+  return d > 0.5 - 0x1p-40 || (tb.lift_edge < 0.5 - 0x1p-40 && d > tb.lift_edge);
+}
+
 // Garner mixed-radix digits of X (canonical residues r, basis q_0..q_{L-1})
 // compared with those of (Q-1)/2: returns X > (Q-1)/2.
 // (Arguments by value: taking the address of the kernel's Tables argument
@@ -104,7 +113,7 @@ __global__ void __launch_bounds__(256) k_lift(int n, size_t n_poly, double* ext,
     S += y[i] * cld(tb.recip, i);
   }
   double v = __builtin_rint(S);
-  if (__builtin_fabs(S - v) > tb.lift_edge) {
+  if (lift_near_half(S, v, tb)) {
     double r[L];
 #pragma unroll
     for (int i = 0; i < L; ++i) r[i] = to_canonical(buf_load(rs, vo, i * ls), cld(tb.p, i));
@@ -209,6 +218,11 @@ template <int L, bool FUSED>
 __global__ void __launch_bounds__(256) k_scale(int n, size_t n_poly, double* dt, Tables tb) {
   constexpr int LB = L + 1;
   const PolyBlock pb = poly_block(n, n_poly);
+  // FUSED has a block barrier below: its launcher requires N to be a
+  // multiple of the block, so pb.ok is the same for every thread of a block
+  // and a block returns here as a whole or not at all (returning after the
+  // barrier instead costs 8 VGPRs and a wave per SIMD)
+  if (!pb.ok) return;
   const auto rs = make_rsrc(dt + pb.pc * (size_t)(L + LB) * n, (unsigned)((L + LB) * n * 8));
   CoefSrc cs{(unsigned)pb.c * 8, 0u, 0u, 1.0, false};
   if constexpr (FUSED) {
@@ -230,9 +244,6 @@ __global__ void __launch_bounds__(256) k_scale(int n, size_t n_poly, double* dt,
     if (t < 2 * LB) kl[2 * L + t] = tb.c1[t];
     __syncthreads();
   }
-  // threads past the last coefficient leave only after the block's barrier
-  // (every thread reaches it whatever the grid)
-  if (!pb.ok) return;
   const unsigned vo = cs.v;
   const unsigned ls = (unsigned)n * 8;   // bytes per limb
   const bool third = pb.pc % 3 == 2;
@@ -247,7 +258,7 @@ __global__ void __launch_bounds__(256) k_scale(int n, size_t n_poly, double* dt,
     S += y[i] * cld(tb.recip, iq);
   }
   double v = __builtin_rint(S);
-  if (__builtin_fabs(S - v) > tb.lift_edge) {
+  if (lift_near_half(S, v, tb)) {
     double r[L];
 #pragma unroll
     for (int i = 0; i < L; ++i) {
@@ -488,7 +499,7 @@ __device__ __forceinline__ void lift_tail(const double (&o)[L], const double (&y
                                           const Tables& tb) {
   constexpr int LB = L + 1;
   double v = __builtin_rint(S);
-  if (__builtin_fabs(S - v) > tb.lift_edge) {
+  if (lift_near_half(S, v, tb)) {
     double r[L];
 #pragma unroll
     for (int i = 0; i < L; ++i) r[i] = to_canonical(o[i], cld(tb.p, i));
@@ -1117,6 +1128,8 @@ hipError_t run_moddown_lift(const Dims& d, const double* acc, const double* dt, 
 
 hipError_t run_scale(const Dims& d, double* dt, const Tables& tb, hipStream_t st) {
   const size_t np = (size_t)d.n_ct * 3;
+  // the split-inverse variant's barrier needs whole blocks (see k_scale)
+  if (d.fused && d.n % d.block) return hipErrorInvalidValue;
   switch (d.L) {
 #define C_(L_) \
   case L_:                                                                                 \
