@@ -515,10 +515,10 @@ def summarize_profiles(prof_dir: str, out_dir: str) -> None:
                    "calibration": {"copy_mib": mib, "factors": factors}}, fh, indent=1)
     cmd_trace = (f"rocprofv3 --kernel-trace --stats -d {prof_dir}/trace -o eq --output-format csv "
                  "-- python3 bench.py --steps 3 --warmup 1 --skip-batched --skip-cpu --skip-next "
-                 "--skip-latency")
+                 "--skip-latency --skip-probes")
     cmd_pmc = (f"rocprofv3 --pmc {{C}} -d {prof_dir}/{{d}} -o eq --output-format csv -- python3 "
                "bench.py --steps 1 --warmup 0 --skip-batched --skip-cpu --skip-next --skip-latency "
-               "--calibrate-copy-mib 256")
+               "--skip-probes --calibrate-copy-mib 256")
     with open(os.path.join(out_dir, "eq_mask_2p20_rows_kernels.md"), "w") as fh:
         fh.write("# EQ mask, 2^20 rows (32 ciphertexts, N=32768), per-kernel time\n\n")
         fh.write(f"Library hash: {kernel_hash()}\n\nCommand (from the repo root, "

@@ -29,6 +29,13 @@ chain's squarings:
 
 LE(x, y) = 1 - LT(y, x); BETWEEN(x, lo, hi) = LE(lo, x) * LE(x, hi), the
 product of two comparisons (Sec. 4.2.2, BETWEEN).
+
+This program is fixed: the device evaluates exactly these products in this
+order (same k, m, factorizations and summed giant-step tensors), so that its
+ciphertexts equal the oracle's bit for bit at every size, and its
+multiplicative depth (18 at p = 65537, before the scalar combination; one
+more for BETWEEN) is what the library's depth budget charges.  A change to
+the program is a change to both sides and to their stored digests.
 """
 from __future__ import annotations
 
