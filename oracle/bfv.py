@@ -11,16 +11,23 @@ squaring, Sec. 4.3.1); it leaves the RNS split, distributions, relinearization
 method and rounding conventions to the library (SEAL).  The readings taken
 here are:
 
-* Q*P spans at most 881 bits, P a single special prime for key switching;
+* Q*P spans at most 881 bits; P is the special modulus of key switching,
+  one prime (the default) or the product of alpha primes;
 * secret key uniform ternary, errors rounded Gaussian (sigma 3.2), drawn by
   the caller and passed in;
 * secret-key encryption ct = ([Delta*m + e - a*s]_Q, a), Delta = floor(Q/t);
 * multiply: centred lifts to (-Q/2, Q/2), exact products in Z[X]/(X^N+1),
   then c_k = [round(t * d_k / Q)]_Q (no ties: Q odd, gcd(t, Q) = 1);
-* relinearize after every multiply with one digit per data prime:
-  D_j = [c_2]_{q_j} in [0, q_j), key evk_j = ([-a_j s + e_j + P g_j s^2]_{PQ},
-  a_j) with g_j = (Q/q_j) * [(Q/q_j)^-1]_{q_j}, and
-  c_b' = [c_b + round(sum_j D_j evk_j[b] / P)]_Q (no ties: P odd);
+* relinearize after every multiply with digits of alpha data primes each
+  (alpha = the number of special primes; one digit per data prime when
+  alpha = 1): the data primes are taken in order in groups of alpha, group j
+  with product Q_j, D_j = [c_2]_{Q_j} in [0, Q_j), key
+  evk_j = ([-a_j s + e_j + P g_j s^2]_{PQ}, a_j) with
+  g_j = (Q/Q_j) * [(Q/Q_j)^-1]_{Q_j}, and
+  c_b' = [c_b + round(sum_j D_j evk_j[b] / P)]_Q (no ties: P odd).  Several
+  primes per digit is the hybrid key switching of Han and Ki ("Better
+  bootstrapping for approximate homomorphic encryption", CT-RSA 2020): fewer,
+  larger digits, with P at least as large as a digit;
 * the constant 1 of "1 - z^(p-1)" is the trivial encryption (Delta, 0).
 """
 from __future__ import annotations
@@ -42,11 +49,46 @@ class Params:
     n: int                      # ring degree = number of slots
     t: int                      # plaintext modulus p (prime, = 1 mod 2n)
     q: tuple                    # data primes q_0 .. q_{L-1}
-    P: int                      # special prime for relinearization
+    special: object             # special prime(s) of key switching: an int
+                                # (one prime) or a tuple of alpha primes
+
+    def __post_init__(self):
+        sp = self.special
+        object.__setattr__(self, "special", (int(sp),) if isinstance(sp, (int, np.integer))
+                           else tuple(int(x) for x in sp))
 
     @property
     def L(self) -> int:
         return len(self.q)
+
+    @property
+    def alpha(self) -> int:
+        """Data primes per key-switching digit = number of special primes."""
+        return len(self.special)
+
+    @property
+    def dnum(self) -> int:
+        """Number of key-switching digits, ceil(L / alpha)."""
+        return -(-self.L // self.alpha)
+
+    def digit_primes(self, j: int) -> tuple:
+        """The data primes of digit j: q_{j alpha} .. q_{min(L, (j+1) alpha) - 1}."""
+        return tuple(self.q[j * self.alpha:(j + 1) * self.alpha])
+
+    def digit_modulus(self, j: int) -> int:
+        """Q_j, the product of digit j's primes."""
+        out = 1
+        for x in self.digit_primes(j):
+            out *= x
+        return out
+
+    @property
+    def P(self) -> int:
+        """The special modulus: the product of the special primes."""
+        out = 1
+        for x in self.special:
+            out *= x
+        return out
 
     @property
     def Q(self) -> int:
@@ -65,13 +107,15 @@ class Params:
 
     @property
     def moduli_pq(self) -> tuple:
-        """Limb order of a relinearization-key polynomial: q_0..q_{L-1}, P."""
-        return tuple(self.q) + (self.P,)
+        """Limb order of a relinearization-key polynomial: q_0..q_{L-1}, then
+        the special primes."""
+        return tuple(self.q) + self.special
 
     def gadget(self, j: int) -> int:
-        """g_j = (Q/q_j) [(Q/q_j)^-1]_{q_j}: g_j = 1 mod q_j, 0 mod q_i (i != j)."""
-        qh = self.Q // self.q[j]
-        return qh * pow(qh, -1, self.q[j])
+        """g_j = (Q/Q_j) [(Q/Q_j)^-1]_{Q_j}: g_j = 1 mod Q_j, 0 mod Q_i (i != j)."""
+        Qj = self.digit_modulus(j)
+        qh = self.Q // Qj
+        return qh * pow(qh, -1, Qj)
 
     def squarings(self) -> int:
         """Multiplicative depth of EQ: ceil(log2(t - 1)) (Table
@@ -79,8 +123,10 @@ class Params:
         return (self.t - 2).bit_length()
 
 
-def paper_params(n: int = 32768, t: int = 65537) -> Params:
-    q, P = nt.default_modulus_chain()
+def paper_params(n: int = 32768, t: int = 65537, alpha: int = 1) -> Params:
+    """The paper's parameters (Sec. 5.1) with alpha special primes (and
+    18 - alpha data primes)."""
+    q, P = nt.default_modulus_chain(n_special=alpha)
     return Params(n, t, tuple(q), P)
 
 
@@ -134,16 +180,16 @@ class SecretKey:
 
 @dataclass
 class RelinKey:
-    b: list                           # L polys mod PQ
-    a: list                           # L polys mod PQ
+    b: list                           # dnum polys mod PQ
+    a: list                           # dnum polys mod PQ
     _own_cache: dict = field(default_factory=dict, repr=False)
 
     def limbs(self, params: Params) -> np.ndarray:
-        """Exchange format [L][2][L+1][N] int64, limbs in moduli_pq order,
-        coefficient domain."""
+        """Exchange format [dnum][2][L+alpha][N] int64, limbs in moduli_pq
+        order, coefficient domain."""
         m = params.moduli_pq
         return np.stack([np.stack([to_limbs(self.b[j], m), to_limbs(self.a[j], m)])
-                         for j in range(params.L)])
+                         for j in range(params.dnum)])
 
 
 def switching_key(params: Params, s, s_from, a_limbs, errors) -> RelinKey:
@@ -153,7 +199,7 @@ def switching_key(params: Params, s, s_from, a_limbs, errors) -> RelinKey:
     s = ring.as_object(s)
     s_from = ring.as_object(s_from)
     bs, as_ = [], []
-    for j in range(params.L):
+    for j in range(params.dnum):
         a = from_limbs(a_limbs[j], params.moduli_pq)
         e = ring.as_object(errors[j])
         b = (-poly_mul(a, s) + e + params.P * params.gadget(j) * s_from) % PQ
@@ -262,20 +308,21 @@ def _evk_transformed(params: Params, rk: RelinKey, B: ring.OwnBasis):
     if key not in rk._own_cache:
         rk._own_cache.clear()
         rk._own_cache[key] = [(B.forward(B.residues(rk.b[j])), B.forward(B.residues(rk.a[j])))
-                              for j in range(params.L)]
+                              for j in range(params.dnum)]
     return rk._own_cache[key]
 
 
 def key_switch(params: Params, key: RelinKey, c) -> tuple:
     """Key switching of one polynomial c (coefficients mod Q) with a
-    switching key for some s' (b_j + a_j s = e_j + P g_j s' mod PQ): one
-    digit per data prime, D_j = [c]_{q_j} in [0, q_j), and
+    switching key for some s' (b_j + a_j s = e_j + P g_j s' mod PQ): digits
+    D_j = [c]_{Q_j} in [0, Q_j) (one data prime each when alpha = 1), and
     (round(sum_j D_j b_j / P), round(sum_j D_j a_j / P)) mod Q, whose phase
     is c * s' plus a small error."""
     Q, P, n = params.Q, params.P, params.n
     c = ring.as_object(c)
-    digits = [(c % qj).astype(np.int64) for qj in params.q]
-    bound = params.L * max(params.q) * params.PQ * n
+    mods = [params.digit_modulus(j) for j in range(params.dnum)]
+    digits = [(c % Qj).astype(np.int64) if Qj < (1 << 62) else c % Qj for Qj in mods]
+    bound = params.dnum * max(mods) * params.PQ * n
     B = ring.OwnBasis(bound, n)
     evk = _evk_transformed(params, key, B)
     acc0 = np.zeros((len(B.primes), n), dtype=np.int64)
@@ -290,7 +337,7 @@ def key_switch(params: Params, key: RelinKey, c) -> tuple:
 
 
 def relinearize(params: Params, rk: RelinKey, ct3) -> tuple:
-    """Key switching of the s^2 component with one digit per data prime."""
+    """Key switching of the s^2 component (digits of alpha data primes)."""
     Q = params.Q
     c0, c1, c2 = (ring.as_object(c) for c in ct3)
     k0, k1 = key_switch(params, rk, c2)

@@ -98,16 +98,19 @@ def integer_root(x: int, k: int) -> int:
 
 
 def default_modulus_chain(log_qp_bits: int = 881, n_primes: int = 18,
-                          step: int = 1 << 16) -> tuple[list[int], int]:
-    """Default data primes q_0..q_{L-1} and special prime P.
+                          step: int = 1 << 16, n_special: int = 1):
+    """Default data primes q_0..q_{L-1} and special prime(s).
 
     Reading of the paper's parameters (Sec. 5.1: n = 32768, log Q = 881,
     t = 65537): the 881 bits bound the largest modulus used, Q*P.  Split it
     into `n_primes` primes, each at most floor(2^(881/18)) so that
     log2(Q*P) <= 881, each = 1 (mod 2^16) so that a negacyclic NTT of every
-    length N <= 2^15 exists.  The largest is the special prime P; the next
-    n_primes - 1, in descending order, are the data primes.
+    length N <= 2^15 exists.  The largest `n_special` are the special primes
+    (returned as one int when there is one, else as a tuple, descending);
+    the other n_primes - n_special, in descending order, are the data
+    primes.
     """
     bound = integer_root(1 << log_qp_bits, n_primes)
     ps = primes_congruent_one_below(bound + 1, step, n_primes)
-    return ps[1:], ps[0]
+    sp = ps[0] if n_special == 1 else tuple(ps[:n_special])
+    return ps[n_special:], sp

@@ -15,12 +15,12 @@ from oracle import bfv, encoding, ring, nt
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
-def _setup(n, t=65537, q=None, P=None, seed=0):
+def _setup(n, t=65537, q=None, P=None, seed=0, alpha=1):
     if q is None:
-        pr = bfv.paper_params(n, t)
+        pr = bfv.paper_params(n, t, alpha)
     else:
         pr = bfv.Params(n, t, tuple(q), P)
-    sk, rk = bfv.keygen(pr, synth.key_randomness(seed, n, pr.moduli_pq, pr.L))
+    sk, rk = bfv.keygen(pr, synth.key_randomness(seed, n, pr.moduli_pq, pr.dnum))
     return pr, sk, rk
 
 
@@ -67,6 +67,49 @@ def test_gadget_is_crt_basis():
     for j in range(pr.L):
         g = pr.gadget(j)
         assert all(g % pr.q[i] == (1 if i == j else 0) for i in range(pr.L))
+
+
+def test_hybrid_parameters():
+    """Two special primes: the same 18 primes, the two largest special, so
+    Q*P keeps its 881 bits; digits are consecutive pairs of data primes."""
+    one, two = bfv.paper_params(16), bfv.paper_params(16, alpha=2)
+    assert two.alpha == 2 and two.L == 16 and two.dnum == 8
+    assert sorted(one.moduli_pq) == sorted(two.moduli_pq)
+    assert two.special == (one.P, one.q[0])
+    assert two.P * two.Q == one.P * one.Q and (two.P * two.Q).bit_length() <= 881
+    for j in range(two.dnum):
+        assert two.digit_modulus(j) == two.q[2 * j] * two.q[2 * j + 1]
+
+
+def test_hybrid_gadget_is_crt_basis_of_digit_groups():
+    pr = bfv.paper_params(16, alpha=2)
+    for j in range(pr.dnum):
+        g = pr.gadget(j)
+        assert 0 <= g < pr.Q
+        assert all(g % pr.q[i] == (1 if i // 2 == j else 0) for i in range(pr.L))
+
+
+def test_hybrid_digits_recompose():
+    """sum_j [c]_{Q_j} g_j = c (mod Q) for any c (the Chinese remainder
+    theorem over the digit moduli), with each digit in [0, Q_j)."""
+    pr = bfv.paper_params(16, alpha=2)
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        c = int.from_bytes(rng.bytes(110), "little") % pr.Q
+        Qs = [pr.q[2 * j] * pr.q[2 * j + 1] for j in range(pr.dnum)]
+        d = [c % Qj for Qj in Qs]
+        assert all(0 <= dj < Qj for dj, Qj in zip(d, Qs))
+        assert sum(dj * pr.gadget(j) for j, dj in enumerate(d)) % pr.Q == c
+
+
+def test_ragged_last_digit():
+    """L not a multiple of alpha: the last digit holds the remaining prime."""
+    q, P = nt.default_modulus_chain(n_special=2)
+    pr = bfv.Params(16, 257, tuple(q[:5]), P)
+    assert pr.dnum == 3 and pr.digit_primes(2) == (q[4],)
+    for j in range(3):
+        g = pr.gadget(j)
+        assert all(g % q[i] == (1 if i // 2 == j else 0) for i in range(5))
 
 
 def test_depth_matches_paper_table():
@@ -178,6 +221,51 @@ def test_relinearize_identity_and_error_bound(small):
         lhs = (rk.b[j] + ring.negacyclic_product(rk.a[j], sk.s)) % pr.PQ
         rhs = (ring.as_object(kr.e[j]) + pr.P * pr.gadget(j) * s2) % pr.PQ
         assert list(lhs) == list(rhs)
+
+
+def test_hybrid_relinearize_matches_schoolbook_route():
+    """Two-prime digits: D_j = [c2]_{q_2j q_2j+1}, products by schoolbook,
+    rounding by exact fractions of P = P_0 P_1."""
+    pr, sk, rk = _setup(8, alpha=2)
+    rng = np.random.default_rng(13)
+    ct3 = bfv.multiply(pr, _enc(pr, sk, rng.integers(0, pr.t, 8), 1),
+                       _enc(pr, sk, rng.integers(0, pr.t, 8), 2))
+    got = bfv.relinearize(pr, rk, ct3)
+    P = pr.special[0] * pr.special[1]
+    u = [np.zeros(8, dtype=object), np.zeros(8, dtype=object)]
+    for j in range(pr.L // 2):
+        dj = ring.as_object(ct3[2]) % (pr.q[2 * j] * pr.q[2 * j + 1])
+        u[0] = u[0] + ring.negacyclic_schoolbook(dj, rk.b[j])
+        u[1] = u[1] + ring.negacyclic_schoolbook(dj, rk.a[j])
+    for b in range(2):
+        want = [(int(c) + round(Fraction(int(v), P))) % pr.Q for c, v in zip(ct3[b], u[b])]
+        assert list(got[b]) == want
+
+
+def test_hybrid_relinearize_identity_and_error_bound():
+    """As with one-prime digits: the phase changes by sum_j D_j e_j / P plus
+    rounding, now with D_j < Q_j ~ 2^98 and P ~ 2^98."""
+    pr, sk, rk = _setup(64, alpha=2)
+    rng = np.random.default_rng(5)
+    ct3 = bfv.multiply(pr, _enc(pr, sk, rng.integers(0, pr.t, pr.n), 1),
+                       _enc(pr, sk, rng.integers(0, pr.t, pr.n), 2))
+    ct2 = bfv.relinearize(pr, rk, ct3)
+    diff = bfv.centred(bfv.phase(pr, sk, ct2) - bfv.phase(pr, sk, ct3), pr.Q)
+    Qj = max(pr.q[2 * j] * pr.q[2 * j + 1] for j in range(pr.dnum))
+    bound = pr.dnum * pr.n * Qj * 19 / pr.P + 0.5 + pr.n / 2
+    assert max(abs(int(v)) for v in diff) <= bound
+    s2 = ring.negacyclic_product(sk.s, sk.s)
+    kr = synth.key_randomness(0, pr.n, pr.moduli_pq, pr.dnum)
+    for j in (0, pr.dnum - 1):
+        lhs = (rk.b[j] + ring.negacyclic_product(rk.a[j], sk.s)) % pr.PQ
+        rhs = (ring.as_object(kr.e[j]) + pr.P * pr.gadget(j) * s2) % pr.PQ
+        assert list(lhs) == list(rhs)
+
+
+def test_hybrid_eq_chain_decrypts():
+    pr, sk, rk = _setup(64, alpha=2)
+    x, y = synth.column_pair_half_match(4, 64)
+    _check_chain(pr, sk, rk, x, y, 21)
 
 
 def test_mul_relin_decrypts_to_product(small):

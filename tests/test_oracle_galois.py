@@ -54,24 +54,25 @@ def test_rotation_elements_act_on_slots(n, t):
     assert got == list(v[h:]) + list(v[:h])
 
 
-def _setup(n, t, seed=3):
-    pr = bfv.paper_params(n, t)
-    sk, rk = bfv.keygen(pr, synth.key_randomness(seed, n, pr.moduli_pq, pr.L))
-    keys = {g: galois.galois_key(pr, sk, g, synth.switch_randomness(100 + i, n, pr.moduli_pq, pr.L))
+def _setup(n, t, seed=3, alpha=1):
+    pr = bfv.paper_params(n, t, alpha)
+    sk, rk = bfv.keygen(pr, synth.key_randomness(seed, n, pr.moduli_pq, pr.dnum))
+    keys = {g: galois.galois_key(pr, sk, g,
+                                 synth.switch_randomness(100 + i, n, pr.moduli_pq, pr.dnum))
             for i, g in enumerate(galois.sum_elements(n))}
     return pr, sk, rk, keys
 
 
-@pytest.fixture(scope="module")
-def n64():
-    return _setup(64, 65537)
+@pytest.fixture(scope="module", params=[1, 2], ids=["alpha1", "alpha2"])
+def n64(request):
+    return _setup(64, 65537, alpha=request.param)
 
 
 def test_galois_key_identity(n64):
     pr, sk, _, keys = n64
     for g, key in keys.items():
         sg = galois.automorphism(sk.s, g)
-        for j in range(pr.L):
+        for j in range(pr.dnum):
             lhs = (key.b[j] + bfv.poly_mul(key.a[j], sk.s)) % pr.PQ
             rhs = (pr.P * pr.gadget(j) * sg) % pr.PQ
             err = bfv.centred((lhs - rhs) % pr.PQ, pr.PQ)

@@ -45,6 +45,11 @@ class _ShiftedGadget(bfv.Params):
         return super().gadget((j + 1) % self.L)
 
 
+class _FirstPrimeDigits(bfv.Params):
+    def digit_modulus(self, j):                          # a digit's second prime dropped
+        return self.q[j * self.alpha]
+
+
 def _run_expect_failure(fn, *args):
     with pytest.raises(AssertionError):
         fn(*args)
@@ -79,3 +84,21 @@ def test_transposed_gadget_is_caught():
     pr = _ShiftedGadget(base.n, base.t, base.q, base.P)
     sk, rk = bfv.keygen(pr, synth.key_randomness(0, 64, pr.moduli_pq, pr.L))
     _run_expect_failure(pins.test_mul_relin_decrypts_to_product, (pr, sk, rk))
+
+
+def test_dropped_digit_prime_is_caught():
+    base = bfv.paper_params(64, alpha=2)
+    pr = _FirstPrimeDigits(base.n, base.t, base.q, base.special)
+    sk, rk = bfv.keygen(pr, synth.key_randomness(0, 64, pr.moduli_pq, pr.dnum))
+    _run_expect_failure(pins.test_mul_relin_decrypts_to_product, (pr, sk, rk))
+
+
+def test_one_special_prime_division_is_caught(monkeypatch):
+    """Dividing by one special prime instead of their product P."""
+    real = bfv.round_div
+
+    def half_p(x, d):
+        base = bfv.paper_params(8, alpha=2)
+        return real(x, base.special[0] if d == base.P else d)
+    monkeypatch.setattr(bfv, "round_div", half_p)
+    _run_expect_failure(pins.test_hybrid_relinearize_matches_schoolbook_route)
