@@ -74,7 +74,12 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def roofline(prof: dict) -> tuple[dict, str]:
+# A two-prime digit's value in a target prime, v_0 + [q_2j]_p v_1: one exact
+# modular product (6 FP64 operations) and one addition per coefficient
+OPS_PER_MODUP = 7
+
+
+def roofline(prof: dict, ctx=None) -> tuple[dict, str]:
     ntt = {k: v for k, v in prof.items() if k.startswith("ntt")}
     dom = max(prof, key=lambda k: prof[k]["ms"])
     if dom not in ntt:
@@ -84,6 +89,14 @@ def roofline(prof: dict) -> tuple[dict, str]:
         dom_ntt = dom
     st = prof[dom_ntt]
     per_launch_ops = st["work"] / st["launches"] * OPS_PER_BUTTERFLY
+    modup = 0.0
+    if ctx is not None and dom_ntt == "ntt_digit" and getattr(ctx, "alpha", 1) == 2:
+        # digits of two primes: each limb transform first forms the digit's
+        # value in its prime (N coefficients, one product and one add each)
+        n = ctx.n
+        limbs = st["work"] / st["launches"] / (n // 2 * (n.bit_length() - 1))
+        modup = limbs * n * OPS_PER_MODUP
+        per_launch_ops += modup
     avg_s = st["ms"] / st["launches"] / 1e3
     achieved = per_launch_ops / avg_s
     traffic = None
@@ -103,6 +116,7 @@ def roofline(prof: dict) -> tuple[dict, str]:
         "frac": achieved / PEAK_FP64_OPS,
         "traffic": traffic,
         "butterflies_per_launch": st["work"] / st["launches"],
+        "modup_ops_per_launch": modup,
         "mean_launch_ms": st["ms"] / st["launches"],
     }, dom_ntt
 
@@ -112,15 +126,15 @@ PEAK_HBM_BYTES = 8.0e12   # MI355X HBM3E
 
 def roofline_ks(ctx, prof: dict, n_ct: int, ks_chunk: int) -> dict | None:
     """The key-switch product (HBM-bound), against the HBM peak: per launch it
-    reads the n_ct ciphertexts' digits (L digits x (L+1) limbs x N doubles
-    each), the key (L x 2 x (L+1) x N) once per chunk of ks_chunk
-    ciphertexts, and writes 2 x (L+1) x N sums per ciphertext."""
+    reads the n_ct ciphertexts' digits (dnum digits x (L+alpha) limbs x N
+    doubles each), the key (dnum x 2 x (L+alpha) x N) once per chunk of
+    ks_chunk ciphertexts, and writes 2 x (L+alpha) x N sums per ciphertext."""
     st = prof.get("ks_mac")
     if not st or not st["launches"]:
         return None
-    n, L = ctx.n, ctx.L
+    n, D, K = ctx.n, ctx.dnum, ctx.L + ctx.alpha
     chunks = -(-n_ct // ks_chunk)
-    per_launch = 8 * n * (L + 1) * (n_ct * L + chunks * 2 * L + n_ct * 2)
+    per_launch = 8 * n * K * (n_ct * D + chunks * 2 * D + n_ct * 2)
     avg_s = st["ms"] / st["launches"] / 1e3
     return {"bound": "hbm", "kernel": "ks_mac", "achieved": per_launch / avg_s / 1e9,
             "peak": PEAK_HBM_BYTES / 1e9, "unit": "GB/s", "frac": per_launch / avg_s / PEAK_HBM_BYTES,
@@ -178,7 +192,7 @@ def _pool_encrypt(i: int):
         np.stack([bfv.to_limbs(c, pr.q) for c in cy])
 
 
-def cpu_phase(full_chain: bool) -> dict:
+def cpu_phase(full_chain: bool, alpha: int = 1) -> dict:
     """The exact-integer oracle (untuned) on the host cores, on bounded
     samples of the workload:
       * the whole EQ (16 levels) of one N = 1024 ciphertext pair (seed 0),
@@ -192,12 +206,12 @@ def cpu_phase(full_chain: bool) -> dict:
     key it used."""
     import multiprocessing as mp
     import synth
-    from oracle import bfv, ring
+    from oracle import bfv
     out = {}
     # N = 1024, the whole chain
     n0 = 1024
-    pr0 = bfv.paper_params(n0)
-    sk0, rk0 = bfv.keygen(pr0, synth.key_randomness(0, n0, pr0.moduli_pq, pr0.L))
+    pr0 = bfv.paper_params(n0, alpha=alpha)
+    sk0, rk0 = bfv.keygen(pr0, synth.key_randomness(0, n0, pr0.moduli_pq, pr0.dnum))
     x0, y0 = synth.column_pair_half_match(0, n0)
     c0x = bfv.encrypt_slots(pr0, sk0, x0, synth.enc_randomness(1, n0, pr0.q))
     c0y = bfv.encrypt_slots(pr0, sk0, y0, synth.enc_randomness(2, n0, pr0.q))
@@ -209,10 +223,10 @@ def cpu_phase(full_chain: bool) -> dict:
     # N = 32768: keys (and the key's transform into the oracle's basis) once,
     # shared by the forked workers
     n = 32768
-    pr = bfv.paper_params(n)
+    pr = bfv.paper_params(n, alpha=alpha)
     t0 = time.perf_counter()
-    sk, rk = bfv.keygen(pr, synth.key_randomness(0, n, pr.moduli_pq, pr.L))
-    bfv._evk_transformed(pr, rk, ring.OwnBasis(pr.L * max(pr.q) * pr.PQ * n, n))
+    sk, rk = bfv.keygen(pr, synth.key_randomness(0, n, pr.moduli_pq, pr.dnum))
+    bfv.prepare_key(pr, rk)
     log(f"oracle: keys at N=32768 {time.perf_counter() - t0:.1f} s")
     _POOL.update(pr=pr, sk=sk, rk=rk)
     try:
@@ -260,7 +274,7 @@ def cpu_baseline(cp: dict) -> dict:
             "host_cpu": _host_cpu(), "host_cores_available": os.cpu_count()}
 
 
-def batched_check(cp: dict, wave: int) -> dict:
+def batched_check(cp: dict, wave: int, alpha: int = 1) -> dict:
     """A seeded oracle sample of the batched workload: 8 one-ciphertext
     instances (real encryptions with the oracle's key) through the batched
     call in graph waves; every mask decrypts to [x == c]."""
@@ -268,7 +282,7 @@ def batched_check(cp: dict, wave: int) -> dict:
     from oracle import bfv
     from paper_2602_24271_amd import Context
     pr, sk, rk = cp["keys"]
-    ctx = Context.paper(15)
+    ctx = Context.paper(15, alpha=alpha)
     ctx.set_relin_key(torch.from_numpy(rk.limbs(pr)).to(ctx.device))
     items = [(torch.from_numpy(cx[None]).to(ctx.device), torch.from_numpy(cy[None]).to(ctx.device))
              for _, _, cx, cy in cp["check"]]
@@ -296,13 +310,18 @@ def probes(ctx) -> dict:
     _lib.check(lib.nshe_probe_modmul(0, 4096, ctypes.byref(m)))
     out = {"modmul": {"products_per_s": m.products_per_s, "fp64_ops_per_s": m.fp64_ops_per_s,
                       "frac_of_issue_peak": m.fp64_ops_per_s / PEAK_FP64_OPS}}
-    qin = (ctypes.c_uint64 * ctx.L)(*ctx.q)
-    qout = (ctypes.c_uint64 * ctx.L_ext)(*ctx.ext_primes)
+    # the probe is built for 17 -> 18 primes: the one-special-prime basis
+    from paper_2602_24271_amd import Context
+    c17 = ctx if ctx.L == 17 else Context.paper(15)
+    qin = (ctypes.c_uint64 * c17.L)(*c17.q)
+    qout = (ctypes.c_uint64 * c17.L_ext)(*c17.ext_primes)
     r = _lib.NsheConvProbe()
     n = 3 << 20
-    _lib.check(lib.nshe_probe_conversion(0, qin, ctx.L, qout, ctx.L_ext, n, 5, ctypes.byref(r)))
+    _lib.check(lib.nshe_probe_conversion(0, qin, c17.L, qout, c17.L_ext, n, 5, ctypes.byref(r)))
     out["conversion_17_to_18"] = {"coefficients": n, "ms_split_fma": r.ms_fma,
                                   "ms_mfma_i8": r.ms_mfma, "mismatches": r.mismatches}
+    if c17 is not ctx:
+        c17.close()
     log(f"probes: modmul {m.fp64_ops_per_s / 1e12:.1f} T FP64 ops/s; conversion fma "
         f"{r.ms_fma:.3f} ms, mfma {r.ms_mfma:.3f} ms, mismatches {r.mismatches}")
     return out
@@ -368,15 +387,18 @@ def derived_rates(ctx, prof: dict, steps: int, n_ct: int, ms: float) -> dict:
     L data primes, LB = L + 1 extension primes and N coefficients: one per
     butterfly; the squaring's tensor 3 (L + LB) N; the lift 2 (L + LB L) N;
     the scale-and-round 3 (L + LB (L + 1) + L LB) N; the key-switch inner
-    product 2 L (L + 1) N; the mod-down 2 (2 L + 1) N."""
+    product 2 D (L + A) N with D digits of A primes; the mod-down
+    2 ((1 + A) L + A) N; with A = 2 also the digits' mixed radix (L / 2) N
+    and their values in every target prime D (L + A) N."""
     sec = ms / 1e3
-    n, L = ctx.n, ctx.L
+    n, L, A, D = ctx.n, ctx.L, ctx.alpha, ctx.dnum
     LB = L + 1
     log2n = n.bit_length() - 1
     bfly = sum(v["work"] for k, v in prof.items() if k.startswith("ntt")) / steps
     levels = ctx.squarings * n_ct
     per_level = (3 * (L + LB) + 2 * (L + LB * L) + 3 * (L + LB * (L + 1) + L * LB)
-                 + 2 * L * (L + 1) + 2 * (2 * L + 1)) * n
+                 + 2 * D * (L + A) + 2 * ((1 + A) * L + A)
+                 + ((L // 2 + D * (L + A)) if A == 2 else 0)) * n
     return {"squarings_per_s": levels / sec,
             "ntt_residues_per_s": bfly * 2 / log2n / sec,
             "modmul_per_s": (bfly + levels * per_level) / sec,
@@ -417,7 +439,7 @@ def next_rows(ctx, x, mask, reps: int) -> dict:
     t = timed(lambda: ctx.select(x, mask), reps)
     out["select"] = {"rows": rows, "ms": t * 1e3, "records_per_s": rows / t}
     log(f"SELECT {t * 1e3:.2f} ms")
-    key = synth.uniform_device_residues((ctx.L, 2), ctx.q + [ctx.P], ctx.n, 31, dev)
+    key = synth.uniform_device_residues((ctx.dnum, 2), ctx.moduli_pq, ctx.n, 31, dev)
     els = ctx.galois_elements()
     for g in els:
         ctx.set_galois_key(g, key)
@@ -428,7 +450,7 @@ def next_rows(ctx, x, mask, reps: int) -> dict:
     ctx.sum_slots(sel)
     prof = ctx.profile_read()
     ctx.profile(False)
-    roof, _ = roofline(prof)
+    roof, _ = roofline(prof, ctx)
     out["sum_slots"] = {"rotations": len(els), "rows": rows, "ms": t * 1e3,
                         "records_per_s": rows / t, "roofline": roof,
                         "kernels": {kk: {"launches": v["launches"], "ms": v["ms"]}
@@ -451,7 +473,7 @@ def next_rows(ctx, x, mask, reps: int) -> dict:
     ctx.compare(x[:chunk], const, "lt")
     prof = ctx.profile_read()
     ctx.profile(False)
-    roof, _ = roofline(prof)
+    roof, _ = roofline(prof, ctx)
     out["lt"] = {"rows": rows, "chunk_ct": chunk, "ms": t * 1e3, "records_per_s": rows / t,
                  "roofline": roof,
                  "kernels": {kk: {"launches": v["launches"], "ms": v["ms"]}
@@ -560,6 +582,9 @@ def main() -> int:
     ap.add_argument("--skip-next", action="store_true",
                     help="skip IN / SELECT / SUM over the same column")
     ap.add_argument("--next-reps", type=int, default=2)
+    ap.add_argument("--alpha", type=int, default=1, choices=(1, 2),
+                    help="data primes per key-switching digit: 1 (17 data primes and one "
+                         "special prime) or 2 (16 data primes, two special primes)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
@@ -570,7 +595,7 @@ def main() -> int:
 
     cp = None
     if not args.skip_cpu:
-        cp = cpu_phase(args.cpu_full)
+        cp = cpu_phase(args.cpu_full, args.alpha)
 
     import torch
     import synth
@@ -586,14 +611,14 @@ def main() -> int:
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    ctx = Context.paper(15)
+    ctx = Context.paper(15, alpha=args.alpha)
     if args.ks_fused in (0, 1):
         ctx.set_tuning(ks_fused=args.ks_fused)
     n_ct = args.n_ct
     log(f"context N={ctx.n} L={ctx.L} ext={ctx.L_ext} squarings={ctx.squarings}")
     x = synth.uniform_device_residues((n_ct, 2), ctx.q, ctx.n, 0, dev)
     y = synth.uniform_device_residues((n_ct, 2), ctx.q, ctx.n, 1, dev)
-    evk = synth.uniform_device_residues((ctx.L, 2), ctx.q + [ctx.P], ctx.n, 2, dev)
+    evk = synth.uniform_device_residues((ctx.dnum, 2), ctx.moduli_pq, ctx.n, 2, dev)
     ctx.set_relin_key(evk)
     del evk
     out = torch.empty_like(x)
@@ -620,7 +645,7 @@ def main() -> int:
     records = n_ct * ctx.n
     value = records / (ms / 1e3)
     log(f"{ms:.2f} ms/step, {value:.4g} records/s")
-    roof, _ = roofline(prof)
+    roof, _ = roofline(prof, ctx)
     rates = derived_rates(ctx, prof, args.steps, n_ct, ms)
     roof_ks = roofline_ks(ctx, prof, n_ct, ctx.tuning()["ks_chunk"])
     # one ciphertext (32,768 rows, the paper's per-query workload): latency
@@ -643,7 +668,7 @@ def main() -> int:
     if cp is not None:
         cpu = cpu_baseline(cp)
         log(f"cpu baseline {cpu['value']:.1f} records/s on {cpu['cores']} cores")
-        check = batched_check(cp, bat["wave_ct"] if bat else 4)
+        check = batched_check(cp, bat["wave_ct"] if bat else 4, args.alpha)
     prb = None if args.skip_probes else probes(ctx)
 
     line = {
@@ -661,9 +686,12 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": f"EQ mask (16 squarings + relinearization) over a column of "
                                f"{records} rows = {n_ct} BFV ciphertexts, N=32768, "
-                               f"log2(QP)<=881 (17+1 primes), p=65537",
+                               f"log2(QP)<=881 ({ctx.L}+{ctx.alpha} primes, key-switching "
+                               f"digits of {ctx.alpha} prime{'s' if ctx.alpha > 1 else ''}), "
+                               f"p=65537",
                    "rows": records, "ciphertexts": n_ct, "ring_degree": ctx.n,
-                   "data_primes": ctx.L, "plaintext_modulus": ctx.t},
+                   "data_primes": ctx.L, "special_primes": ctx.alpha,
+                   "key_switch_digits": ctx.dnum, "plaintext_modulus": ctx.t},
         "roofline": roof,
         "roofline_ks_mac": roof_ks,
         "cpu_baseline": cpu,

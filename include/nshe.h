@@ -17,8 +17,11 @@
  *   multiply     lift both operands' coefficients to (-Q/2, Q/2), form
  *                d0 = a0 b0, d1 = a0 b1 + a1 b0, d2 = a1 b1 exactly in
  *                Z[X]/(X^N + 1), output c_k = [round(t d_k / Q)]_Q;
- *   relinearize  digits D_j = [c2]_{q_j} in [0, q_j), u_b = sum_j D_j evk_j[b],
- *                output [c_b + round(u_b / P)]_Q;
+ *   relinearize  digits D_j = [c2]_{Q_j} in [0, Q_j), u_b = sum_j D_j evk_j[b],
+ *                output [c_b + round(u_b / P)]_Q, where digit j covers alpha
+ *                consecutive data primes (Q_j their product; Q_j = q_j when
+ *                alpha = 1) and P is the product of the alpha special
+ *                primes (hybrid key switching, Han and Ki, CT-RSA 2020);
  *   EQ           z = [x - y]_Q, z <- relin(z * z) (t - 1 = 2^k times k),
  *                out = ([-z0 + Delta e_0]_Q, [-z1]_Q) with Delta = floor(Q/t)
  *                (the trivial encryption of the constant 1, minus z).
@@ -29,9 +32,11 @@
  * Data layout (the exchange format):
  *   ciphertext  int64 [n_ct][2][L][N]  residues in [0, q_i), coefficient
  *               domain, natural coefficient order, limb i belongs to q_i;
- *   relin key   int64 [L][2][L+1][N]   digit j, component b (b = 0 is
- *               [-a_j s + e_j + P g_j s^2]_{PQ}, b = 1 is a_j), limbs in the
- *               order q_0 .. q_{L-1}, P; coefficient domain.
+ *   relin key   int64 [dnum][2][L+alpha][N]  digit j < dnum = L / alpha,
+ *               component b (b = 0 is [-a_j s + e_j + P g_j s^2]_{PQ},
+ *               g_j = (Q/Q_j) [(Q/Q_j)^-1]_{Q_j}; b = 1 is a_j), limbs in
+ *               the order q_0 .. q_{L-1}, P_0 .. P_{alpha-1}; coefficient
+ *               domain.
  * Pointers named *_dev are device memory of the context's HIP device;
  * pointers named *_host are host memory.  The caller owns every buffer
  * passed in; the library borrows it for the duration of the work enqueued
@@ -92,15 +97,23 @@ typedef struct nshe_ctx nshe_ctx;
  *           counts the base-conversion kernels are built for; the paper's
  *           parameters use 17);
  *   q_host  L distinct primes, each in [2^48, 2^49) and = 1 (mod 2N);
- *   P       the special prime, same constraints, distinct from the q_i.
- * Q = prod q_i.  The library picks its own extension basis (primes of the
- * same form below min(q, P)) large enough for exact products. */
+ *   P       the (first) special prime, same constraints, distinct from the q_i;
+ *   alpha   data primes per key-switching digit = number of special primes:
+ *           1 (0 reads as 1: one digit per data prime, a single special
+ *           prime) or 2 (L one of 2, 4, 8 or 16; the paper's modulus budget
+ *           then splits as 16 data primes and two special primes);
+ *   P1      the second special prime when alpha = 2 (ignored otherwise).
+ * Q = prod q_i, P = P (alpha = 1) or P P1.  The library picks its own
+ * extension basis (primes of the same form below every q_i and special
+ * prime) large enough for exact products. */
 typedef struct {
   uint32_t log2_n;
   uint64_t t;
   int32_t L;
   const uint64_t* q_host;
   uint64_t P;
+  int32_t alpha;
+  uint64_t P1;
 } nshe_params;
 
 /* Read-only description of a context (sizes for the caller's buffers). */
@@ -111,11 +124,14 @@ typedef struct {
   int32_t squarings;     /* k with t - 1 = 2^k, or -1 */
   uint64_t ext_primes[32];
   size_t ct_words;       /* int64 words of one ciphertext: 2 * L * N */
-  size_t relin_key_words;/* int64 words of the relin key: L * 2 * (L+1) * N */
+  size_t relin_key_words;/* int64 words of the relin key (and of a Galois
+                            key): dnum * 2 * (L+alpha) * N */
   int32_t depth_budget;  /* multiplications a fresh ciphertext takes (nshe_budget) */
   int32_t lt_depth;      /* depth of the comparison program, -1 without one */
   double fresh_bits;     /* noise budget of a fresh encryption, bits */
   double level_bits;     /* bits one multiplication costs (the model's) */
+  int32_t alpha;         /* data primes per key-switching digit (special primes) */
+  int32_t dnum;          /* key-switching digits, L / alpha */
 } nshe_info;
 
 /* Noise budget and multiplicative depth (Sec. 2.1.2: every multiplication
@@ -182,7 +198,7 @@ int nshe_op_depth(const nshe_ctx* ctx, int op, int arg, int* depth_host);
 int nshe_depth_after(const nshe_ctx* ctx, int op, int arg, int in_depth, int* out_depth_host);
 
 /* Install the relinearization key (Sec. 2.1.2).  Copies and transforms
- * `evk_dev` (layout above; n_words must be L * 2 * (L+1) * N, else
+ * `evk_dev` (layout above; n_words must be dnum * 2 * (L+alpha) * N, else
  * NSHE_ESHAPE) into context-owned memory on `stream` and waits for it;
  * `evk_dev` may be freed on return.  Allocates the context-owned key store
  * on first use and a temporary of the same size during the call (set-up,
@@ -373,13 +389,13 @@ int nshe_join_sum(nshe_ctx* ctx, const int64_t* a_key_dev, const int64_t* b_key_
  * g = 3^r mod 2N rotates each half left by r and g = 2N - 1 swaps the
  * halves.  A rotation applies X -> X^g to both components and switches the
  * second from sigma_g(s) back to s with the Galois key of g:
- *   key_g  int64 [L][2][L+1][N], digit j = ([-a_j s + e_j + P g_j
+ *   key_g  int64 [dnum][2][L+alpha][N], digit j = ([-a_j s + e_j + P g_j
  *          sigma_g(s)]_{PQ}, a_j) (the relin key's format with sigma_g(s)
  *          in place of s^2, n_words as for the relin key); copied and
  *          transformed into context memory (waits for `stream`; allocates
  *          on the first key for g);
  *   out    = ([sigma_g(c0) + round(sum_j D_j b_j / P)]_Q,
- *             [round(sum_j D_j a_j / P)]_Q), D_j = [sigma_g(c1)]_{q_j}.
+ *             [round(sum_j D_j a_j / P)]_Q), D_j = [sigma_g(c1)]_{Q_j}.
  * nshe_sum_slots replaces each ciphertext by ct + rot(ct) for the Galois
  * elements nshe_galois_elements lists (rotations by N/4, ..., 1, then the
  * swap): every slot of the result holds the sum of all slots.  COUNT is

@@ -312,6 +312,19 @@ def _evk_transformed(params: Params, rk: RelinKey, B: ring.OwnBasis):
     return rk._own_cache[key]
 
 
+def _switch_basis(params: Params) -> ring.OwnBasis:
+    """The own basis of a key switch's exact sums: |sum_j D_j k_j| is below
+    dnum max(Q_j) PQ N."""
+    mods = [params.digit_modulus(j) for j in range(params.dnum)]
+    return ring.OwnBasis(params.dnum * max(mods) * params.PQ * params.n, params.n)
+
+
+def prepare_key(params: Params, key: RelinKey) -> None:
+    """Transform a switching key into the basis key_switch uses (cached on
+    the key; a speed-up only, key_switch does it on first use anyway)."""
+    _evk_transformed(params, key, _switch_basis(params))
+
+
 def key_switch(params: Params, key: RelinKey, c) -> tuple:
     """Key switching of one polynomial c (coefficients mod Q) with a
     switching key for some s' (b_j + a_j s = e_j + P g_j s' mod PQ): digits
@@ -322,8 +335,7 @@ def key_switch(params: Params, key: RelinKey, c) -> tuple:
     c = ring.as_object(c)
     mods = [params.digit_modulus(j) for j in range(params.dnum)]
     digits = [(c % Qj).astype(np.int64) if Qj < (1 << 62) else c % Qj for Qj in mods]
-    bound = params.dnum * max(mods) * params.PQ * n
-    B = ring.OwnBasis(bound, n)
+    B = _switch_basis(params)
     evk = _evk_transformed(params, key, B)
     acc0 = np.zeros((len(B.primes), n), dtype=np.int64)
     acc1 = np.zeros_like(acc0)

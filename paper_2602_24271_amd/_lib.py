@@ -16,7 +16,8 @@ NSHE_MAX_L = 24
 
 class NsheParams(ctypes.Structure):
     _fields_ = [("log2_n", ctypes.c_uint32), ("t", ctypes.c_uint64), ("L", ctypes.c_int32),
-                ("q_host", ctypes.POINTER(ctypes.c_uint64)), ("P", ctypes.c_uint64)]
+                ("q_host", ctypes.POINTER(ctypes.c_uint64)), ("P", ctypes.c_uint64),
+                ("alpha", ctypes.c_int32), ("P1", ctypes.c_uint64)]
 
 
 class NsheInfo(ctypes.Structure):
@@ -24,7 +25,8 @@ class NsheInfo(ctypes.Structure):
                 ("squarings", ctypes.c_int32), ("ext_primes", ctypes.c_uint64 * 32),
                 ("ct_words", ctypes.c_size_t), ("relin_key_words", ctypes.c_size_t),
                 ("depth_budget", ctypes.c_int32), ("lt_depth", ctypes.c_int32),
-                ("fresh_bits", ctypes.c_double), ("level_bits", ctypes.c_double)]
+                ("fresh_bits", ctypes.c_double), ("level_bits", ctypes.c_double),
+                ("alpha", ctypes.c_int32), ("dnum", ctypes.c_int32)]
 
 
 class NsheBudget(ctypes.Structure):

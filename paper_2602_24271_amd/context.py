@@ -25,11 +25,17 @@ def _stream() -> int:
 class Context:
     """BFV context on one HIP device (NSHEDB Sec. 5.1 parameters by default)."""
 
-    def __init__(self, log2_n: int, t: int, q, P: int, device: int = 0):
+    def __init__(self, log2_n: int, t: int, q, P, device: int = 0):
+        """P: the special prime, or a sequence of two special primes (key
+        switching with digits of two data primes)."""
         lib = _lib.load()
         self.device = torch.device("cuda", device)
+        special = [int(P)] if isinstance(P, int) else [int(x) for x in P]
+        if len(special) not in (1, 2):
+            raise ValueError("one or two special primes")
         qa = (ctypes.c_uint64 * len(q))(*q)
-        pr = _lib.NsheParams(log2_n, t, len(q), ctypes.cast(qa, ctypes.POINTER(ctypes.c_uint64)), P)
+        pr = _lib.NsheParams(log2_n, t, len(q), ctypes.cast(qa, ctypes.POINTER(ctypes.c_uint64)),
+                             special[0], len(special), special[1] if len(special) == 2 else 0)
         h = ctypes.c_void_p()
         _lib.check(lib.nshe_ctx_create(ctypes.byref(pr), device, ctypes.byref(h)))
         self._h = h
@@ -45,22 +51,33 @@ class Context:
         self.lt_depth = info.lt_depth
         self.fresh_bits = info.fresh_bits
         self.level_bits = info.level_bits
+        self.alpha = info.alpha
+        self.dnum = info.dnum
         # per-ciphertext-array level counter (Sec. 2.1.2): the depth of every
         # output this context produced, by tensor identity (an entry leaves
         # with its tensor); arrays it did not produce count as fresh
         # (depth 0) unless set_depth says otherwise
         self._depths = {}
         self.q = list(q)
-        self.P = P
+        self.special = special
+        self.P = special[0]
+        self.moduli_pq = self.q + special
         self.t = t
         self._ws = None
         self._key = None
 
     @classmethod
-    def paper(cls, log2_n: int = 15, device: int = 0) -> "Context":
+    def paper(cls, log2_n: int = 15, device: int = 0, alpha: int = 1) -> "Context":
+        """The paper's parameters (Sec. 5.1); alpha = 2 takes the two largest
+        of the 18 primes as special primes and 16 data primes."""
         from .params import paper_params
-        p = paper_params(log2_n)
+        p = paper_params(log2_n, alpha=alpha)
         return cls(p["log2_n"], p["t"], p["q"], p["P"], device)
+
+    @property
+    def key_shape(self):
+        """Shape of a relinearization or Galois key: [dnum, 2, L + alpha, N]."""
+        return (self.dnum, 2, self.L + self.alpha, self.n)
 
     def close(self):
         if self._h:
@@ -140,7 +157,7 @@ class Context:
 
     # ---------------------------------------------------------------- API
     def set_relin_key(self, evk: torch.Tensor) -> None:
-        want = (self.L, 2, self.L + 1, self.n)
+        want = self.key_shape
         if evk.dtype != torch.int64 or tuple(evk.shape) != want or evk.device != self.device:
             raise ValueError(f"relin key must be int64 {want} on the context device")
         evk = evk.contiguous()
@@ -288,8 +305,8 @@ class Context:
     def set_galois_key(self, g: int, key: torch.Tensor) -> None:
         if key.dtype != torch.int64 or not key.is_contiguous() or key.device != self.device:
             raise ValueError("key must be a contiguous int64 tensor on the context device")
-        if tuple(key.shape) != (self.L, 2, self.L + 1, self.n):
-            raise ValueError("key must have shape [L, 2, L+1, N]")
+        if tuple(key.shape) != self.key_shape:
+            raise ValueError("key must have shape [dnum, 2, L+alpha, N]")
         _lib.check(self._lib.nshe_set_galois_key(self._h, g, _ptr(key), key.numel(), _stream()))
 
     def rotate(self, x: torch.Tensor, g: int) -> torch.Tensor:

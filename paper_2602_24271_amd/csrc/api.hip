@@ -164,15 +164,16 @@ using namespace nshe;
 struct nshe_ctx {
   int device = 0;
   int log2n = 0, n = 0, L = 0, LB = 0, K = 0;
+  int alpha = 1, dnum = 0;  // data primes per key-switching digit, digits
   u64 t = 0;
   int squarings = -1;
-  std::vector<u64> primes;  // q_0..q_{L-1}, b_0..b_L, P
+  std::vector<u64> primes;  // q_0..q_{L-1}, b_0..b_L, P_0..P_{alpha-1}
   int loge = 0, r0 = 0, rounds = 0, tw_len = 0;
   void* dev_tables = nullptr;
   int* lp_ext = nullptr;  // identity over 2L+1 limbs
-  int* lp_ks = nullptr;   // 0..L-1, 2L+1
+  int* lp_ks = nullptr;   // 0..L-1, 2L+1..2L+alpha
   Tables tb{};
-  double* evk = nullptr;  // [L][2][L+1][N] NTT domain
+  double* evk = nullptr;  // [dnum][2][L+alpha][N] NTT domain
   bool has_key = false;
   struct GraphEntry {
     hipGraphExec_t exec;
@@ -216,6 +217,8 @@ constexpr double kLiftEdgeWide = 0.25;
   } while (0)
 
 static int W_of(const nshe_ctx* c) { return 2 * c->L + 1; }
+// limbs of the key-switching basis Q u P
+static int KS_of(const nshe_ctx* c) { return c->L + c->alpha; }
 
 // 2^15-point limbs: the inverse transforms feeding the scale-and-round and
 // the mod-down run as two half-limb workgroups each, their last stage
@@ -229,6 +232,7 @@ static Dims dims(const nshe_ctx* c, int n_ct) {
   d.block = c->tune.ew_block;
   d.ks_chunk = c->tune.ks_chunk;
   d.fused = split_inverse(c) ? 1 : 0;
+  d.alpha = c->alpha;
   return d;
 }
 
@@ -283,17 +287,17 @@ struct Ws {
   double* ext;   // [n_ct][2][W][N]  current ciphertext (limbs 0..L-1) and its lift
   double* fx;    // [n_ct][2][W][N]  the operand's transform
   double* dt;    // [n_ct][3][W][N]
-  double* dig;   // [n_ct][L][K][N]  (a second operand's lift and transform first)
-  double* acc;   // [n_ct][2][K][N]
+  double* dig;   // [n_ct][dnum][K][N]  (a second operand's lift and transform first)
+  double* acc;   // [n_ct][2][K][N], K = L + alpha
 };
 
 static size_t dig_limbs(const nshe_ctx* c) {
-  const size_t W = W_of(c), K = c->L + 1, L = c->L;
-  return std::max(L * K, 4 * W);
+  const size_t W = W_of(c), K = KS_of(c), D = c->dnum;
+  return std::max(D * K, 4 * W);
 }
 
 static size_t ws_doubles(const nshe_ctx* c, int n_ct) {
-  const size_t W = W_of(c), K = c->L + 1, N = c->n;
+  const size_t W = W_of(c), K = KS_of(c), N = c->n;
   return (size_t)n_ct * N * (2 * W + 2 * W + 3 * W + dig_limbs(c) + 2 * K);
 }
 
@@ -347,9 +351,9 @@ static int ntt_job_ks(nshe_ctx* c, double* base, double* out, int npoly, int dir
   j.split_inv = for_moddown && split_inverse(c) ? 1 : 0;
   j.base = base;
   j.out = out;
-  j.poly_stride = (size_t)(c->L + 1) * c->n;
+  j.poly_stride = (size_t)KS_of(c) * c->n;
   j.npoly = npoly;
-  j.nlimb = c->L + 1;
+  j.nlimb = KS_of(c);
   j.limb_prime = c->lp_ks;
   j.count = npoly * j.nlimb;
   Prof pf(c, dir ? K_NTT_INV : K_NTT_FWD, st, ntt_work(c, j.count));
@@ -402,14 +406,16 @@ static int tensor_scale(nshe_ctx* c, const Ws& w, const double* fx_b, int n_ct, 
 // 2^15-point limbs with the split transforms: the key-switch product may
 // run fused with the digit transforms (k_ks_fused), a tuning choice.
 static bool ks_fused(const nshe_ctx* c) {
-  return c->log2n == 15 && c->tune.split_forward && c->tune.ks_fused && c->tb.tw_half;
+  return c->log2n == 15 && c->tune.split_forward && c->tune.ks_fused && c->tb.tw_half &&
+         c->alpha == 1;
 }
 
 static int digit_products(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st, const double* key);
 static int finish_relin(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st, double* out,
                         bool lift_out, int64_t* finish_out, int64_t* i64_out, bool accumulate);
 
-// Key-switch the third component in dt (limbs 0..L-1, canonical) with
+// Key-switch the third component in dt (limbs 0..L-1: canonical residues,
+// or with two primes per digit their mixed-radix digit pairs) with
 // `key` (the relinearization key unless given) and add the result to the
 // first two: (c0 + k0, c1 + k1) into `out` (ext unless given), limbs 0..L-1.
 // lift_out: also lift the result (limbs L..2L of out), for a squaring that
@@ -449,20 +455,21 @@ static int digit_products(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st, co
   j.split = c->tune.split_forward;
   j.base = w.dig;
   j.out = w.dig;
-  j.poly_stride = (size_t)(c->L + 1) * c->n;
-  j.npoly = n_ct * c->L;
-  j.nlimb = c->L + 1;
+  j.poly_stride = (size_t)KS_of(c) * c->n;
+  j.npoly = n_ct * c->dnum;
+  j.nlimb = KS_of(c);
   j.limb_prime = c->lp_ks;
   j.count = j.npoly * j.nlimb;
   j.src = w.dt + (size_t)2 * W_of(c) * c->n;
   j.src_ct_stride = (size_t)3 * W_of(c) * c->n;
-  j.digits = c->L;
+  j.digits = c->dnum;
+  j.alpha = c->alpha;
   {
     Prof pf(c, K_NTT_DIGIT, st, ntt_work(c, j.count));
     HIPCHK(run_ntt(c->log2n, j, c->tb, 2, st));
   }
   {
-    Prof pf(c, K_KS_MAC, st, (double)n_ct * c->L * 2 * (c->L + 1) * c->n);
+    Prof pf(c, K_KS_MAC, st, (double)n_ct * c->dnum * 2 * KS_of(c) * c->n);
     HIPCHK(run_ks_mac(d, w.dig, key, w.acc, c->tb, st));
   }
   return NSHE_OK;
@@ -566,11 +573,16 @@ static int check_params(const nshe_params* pr, std::vector<u64>* q_out) {
   if (!pr->q_host) return fail(NSHE_EINVAL, "q_host is null");
   if (pr->t < 3 || (pr->t & 1) == 0 || pr->t >= (1u << 24))
     return fail(NSHE_EINVAL, "t must be odd, 3 <= t < 2^24");
+  const int alpha = pr->alpha == 0 ? 1 : pr->alpha;
+  if (alpha != 1 && alpha != 2) return fail(NSHE_EINVAL, "alpha must be 1 or 2");
+  if (alpha == 2 && pr->L != 2 && pr->L != 4 && pr->L != 8 && pr->L != 16)
+    return fail(NSHE_EINVAL, "with alpha = 2, L must be one of 2, 4, 8, 16");
   const int n = 1 << pr->log2_n;
   const u64 lo = 1ull << 48, hi = 1ull << 49;
   std::vector<u64> q(pr->q_host, pr->q_host + pr->L);
   std::vector<u64> qp = q;
   qp.push_back(pr->P);
+  if (alpha == 2) qp.push_back(pr->P1);
   for (size_t i = 0; i < qp.size(); ++i) {
     const u64 x = qp[i];
     if (x < lo || x >= hi) return fail(NSHE_EINVAL, "every prime must lie in [2^48, 2^49)");
@@ -747,9 +759,12 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
   if (int rc0 = check_params(pr, &q)) return rc0;
   const int n = 1 << pr->log2_n;
   const u64 lo = 1ull << 48;
+  const int alpha = pr->alpha == 0 ? 1 : pr->alpha;
+  std::vector<u64> sp{pr->P};
+  if (alpha == 2) sp.push_back(pr->P1);
   std::vector<u64> qp = q;
-  qp.push_back(pr->P);
-  // --- extension basis: L + 1 largest primes = 1 mod 2^16 below min(q, P)
+  qp.insert(qp.end(), sp.begin(), sp.end());
+  // --- extension basis: L + 1 largest primes = 1 mod 2^16 below every q_i and P_k
   const int L = pr->L, LB = L + 1;
   u64 mn = *std::min_element(qp.begin(), qp.end());
   std::vector<u64> b;
@@ -772,7 +787,9 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
   c->n = n;
   c->L = L;
   c->LB = LB;
-  c->K = 2 * L + 2;
+  c->alpha = alpha;
+  c->dnum = L / alpha;
+  c->K = 2 * L + 1 + alpha;
   c->t = pr->t;
   {
     u64 e = pr->t - 1;
@@ -785,7 +802,7 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
   }
   c->primes = q;
   c->primes.insert(c->primes.end(), b.begin(), b.end());
-  c->primes.push_back(pr->P);
+  c->primes.insert(c->primes.end(), sp.begin(), sp.end());
   c->rounds = ntt_rounds(c->log2n, &c->loge, &c->r0);
   c->tw_len = 1 << c->loge;   // round 0's row
   const int K = c->K;
@@ -928,12 +945,24 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
   }
   // t_qhinv, t_q, c1: a second row times the inverse's last-stage twiddle
   std::vector<double> q_hat_inv(L), Q_b(LB), t_qhinv(2 * L), t_q(2 * L),
-      c1(2 * LB), b_hat_inv(LB), B_q(L), P_inv_q(L), NP_inv_q(2 * L), ninv_P(2),
-      delta_q(L), mrc_inv((size_t)L * L, 0.0), mrc_half(L);
-  {
-    const u64 Pp = pr->P, nP = invmod((u64)n % Pp, Pp);
-    ninv_P[0] = bal(nP, Pp);
-    ninv_P[1] = bal(mulmod(nP, w_last[2 * L + 1], Pp), Pp);
+      c1(2 * LB), b_hat_inv(LB), B_q(L), P_inv_q(L), NP_inv_q(2 * L), ninv_P(2 * alpha),
+      P1_inv_q(L, 0.0), delta_q(L), mrc_inv((size_t)L * L, 0.0), mrc_half(L),
+      dig_q0((size_t)(L / alpha) * (L + alpha), 0.0);
+  for (int k = 0; k < alpha; ++k) {
+    const u64 Pp = sp[k], nP = invmod((u64)n % Pp, Pp);
+    ninv_P[2 * k] = bal(nP, Pp);
+    ninv_P[2 * k + 1] = bal(mulmod(nP, w_last[2 * L + 1 + k], Pp), Pp);
+  }
+  // two primes per digit: [P_0^-1]_{P_1}, and digit j's first prime q_{2j}
+  // modulo every prime of the key-switching basis
+  double p0_inv_p1 = 0.0;
+  if (alpha == 2) {
+    p0_inv_p1 = bal(invmod(sp[0] % sp[1], sp[1]), sp[1]);
+    for (int j = 0; j < L / 2; ++j)
+      for (int i = 0; i < L + 2; ++i) {
+        const u64 m = i < L ? q[i] : sp[i - L];
+        dig_q0[(size_t)j * (L + 2) + i] = bal(q[2 * j] % m, m);
+      }
   }
   u64 Qmodt = 1;
   for (u64 x : qv) Qmodt = mulmod(Qmodt, x % c->t, c->t);
@@ -949,8 +978,12 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
     t_qhinv[L + i] = bal(mulmod(tqh, w_last[i], qi), qi);
     t_q[L + i] = bal(mulmod(tq, w_last[i], qi), qi);
     B_q[i] = bal(prod_mod(bv, -1, qi), qi);
-    P_inv_q[i] = bal(invmod(pr->P % qi, qi), qi);
-    const u64 npq = mulmod(invmod(pr->P % qi, qi), ninv_q, qi);
+    // P^-1 with P the product of the special primes
+    u64 Pq = 1;
+    for (u64 x : sp) Pq = mulmod(Pq, x % qi, qi);
+    P_inv_q[i] = bal(invmod(Pq, qi), qi);
+    if (alpha == 2) P1_inv_q[i] = bal(invmod(sp[1] % qi, qi), qi);
+    const u64 npq = mulmod(invmod(Pq, qi), ninv_q, qi);
     NP_inv_q[i] = bal(npq, qi);
     NP_inv_q[L + i] = bal(mulmod(npq, w_last[i], qi), qi);
     // Delta = (Q - (Q mod t)) / t = -(Q mod t) * t^-1 (mod q_i)
@@ -995,7 +1028,7 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
       {&t_qhinv, &c->tb.t_qhinv}, {&t_q, &c->tb.t_q},         {&c1, &c->tb.c1},
       {&b_hat_inv, &c->tb.b_hat_inv},
       {&B_q, &c->tb.B_q},         {&P_inv_q, &c->tb.P_inv_q}, {&NP_inv_q, &c->tb.NP_inv_q},
-      {&ninv_P, &c->tb.ninv_P},
+      {&ninv_P, &c->tb.ninv_P},   {&P1_inv_q, &c->tb.P1_inv_q}, {&dig_q0, &c->tb.dig_q0},
       {&delta_q, &c->tb.delta_q},
       {&mrc_inv, &c->tb.mrc_inv}, {&mrc_half, &c->tb.mrc_half}, {&tw_h, &c->tb.tw_half},
       {&tw_h0, &c->tb.tw_half0},  {&tw_cf, &c->tb.tw_cmp_f},  {&tw_ci, &c->tb.tw_cmp_i},
@@ -1013,7 +1046,7 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
   const size_t off_counters = total;
   total += 256;
   const size_t off_lp = total;
-  total += ((size_t)(W_of(c) + L + 1) * sizeof(int) + 255) & ~size_t(255);
+  total += ((size_t)(W_of(c) + L + alpha) * sizeof(int) + 255) & ~size_t(255);
   // comparison polynomial for a Fermat prime t
   std::vector<int> lt_coef;
   if (c->squarings >= 2 && is_prime(c->t)) {
@@ -1065,11 +1098,13 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
   c->tb.margin = reinterpret_cast<unsigned long long*>(base + off_counters);
   c->tb.bad_input = reinterpret_cast<int*>(base + off_counters + 128);
   c->tb.lift_edge = kLiftEdge;
+  c->tb.ks_alpha = alpha;
+  c->tb.p0_inv_p1 = p0_inv_p1;
   if (e == hipSuccess) e = hipMemset(base + off_counters, 0, 256);
   std::vector<int> lp;
   for (int i = 0; i < W_of(c); ++i) lp.push_back(i);
   for (int i = 0; i < L; ++i) lp.push_back(i);
-  lp.push_back(2 * L + 1);
+  for (int k = 0; k < alpha; ++k) lp.push_back(2 * L + 1 + k);
   c->lp_ext = reinterpret_cast<int*>(base + off_lp);
   c->lp_ks = c->lp_ext + W_of(c);
   if (e == hipSuccess)
@@ -1120,7 +1155,9 @@ int nshe_ctx_info(const nshe_ctx* c, nshe_info* out) {
   out->squarings = c->squarings;
   for (int k = 0; k < c->LB && k < 32; ++k) out->ext_primes[k] = c->primes[c->L + k];
   out->ct_words = (size_t)2 * c->L * c->n;
-  out->relin_key_words = (size_t)c->L * 2 * (c->L + 1) * c->n;
+  out->relin_key_words = (size_t)c->dnum * 2 * KS_of(c) * c->n;
+  out->alpha = c->alpha;
+  out->dnum = c->dnum;
   out->depth_budget = c->depth_budget;
   out->fresh_bits = c->fresh_bits;
   out->level_bits = c->level_bits;
@@ -1174,17 +1211,18 @@ size_t nshe_workspace_bytes(const nshe_ctx* c, int n_ct) {
   return ws_doubles(c, n_ct) * sizeof(double);
 }
 
-// Convert a switching key (int64 [L][2][L+1][N], coefficient domain) into
-// *dst (NTT domain, allocated on first use); waits for the stream.
+// Convert a switching key (int64 [dnum][2][L+alpha][N], coefficient
+// domain) into *dst (NTT domain, allocated on first use); waits for the
+// stream.
 static int load_switch_key(nshe_ctx* c, const int64_t* key_dev, double** dst, hipStream_t st) {
-  const size_t rows = (size_t)c->L * 2 * (c->L + 1);
+  const size_t rows = (size_t)c->dnum * 2 * KS_of(c);
   if (!*dst) HIPCHK(hipMalloc(dst, rows * c->n * sizeof(double)));
   double* tmp = nullptr;
   HIPCHK(hipMalloc(&tmp, rows * c->n * sizeof(double)));
   int rc = NSHE_OK;
-  hipError_t e = run_i64_to_dbl_limbs(rows, c->n, key_dev, tmp, c->lp_ks, c->L + 1, c->tb, st);
+  hipError_t e = run_i64_to_dbl_limbs(rows, c->n, key_dev, tmp, c->lp_ks, KS_of(c), c->tb, st);
   if (e != hipSuccess) rc = fail(NSHE_EDEVICE, std::string("key conversion: ") + hipGetErrorString(e));
-  if (!rc) rc = ntt_job_ks(c, tmp, *dst, c->L * 2, 0, st);
+  if (!rc) rc = ntt_job_ks(c, tmp, *dst, c->dnum * 2, 0, st);
   if (!rc) {
     e = hipStreamSynchronize(st);
     if (e != hipSuccess) rc = fail(NSHE_EDEVICE, std::string("key transform: ") + hipGetErrorString(e));
@@ -1194,14 +1232,14 @@ static int load_switch_key(nshe_ctx* c, const int64_t* key_dev, double** dst, hi
 }
 
 static size_t key_words(const nshe_ctx* c) {
-  return (size_t)c->L * 2 * (c->L + 1) * c->n;
+  return (size_t)c->dnum * 2 * KS_of(c) * c->n;
 }
 
 int nshe_set_relin_key(nshe_ctx* c, const int64_t* evk_dev, size_t n_words, void* stream) {
   g_err.clear();
   if (check_ctx(c)) return NSHE_EINVAL;
   if (!evk_dev) return fail(NSHE_EINVAL, "evk is null");
-  if (n_words != key_words(c)) return fail(NSHE_ESHAPE, "evk must hold L * 2 * (L+1) * N words");
+  if (n_words != key_words(c)) return fail(NSHE_ESHAPE, "evk must hold dnum * 2 * (L+alpha) * N words");
   if (set_device(c)) return NSHE_EDEVICE;
   int rc = load_switch_key(c, evk_dev, &c->evk, static_cast<hipStream_t>(stream));
   if (rc) return rc;
@@ -1214,7 +1252,7 @@ int nshe_set_galois_key(nshe_ctx* c, uint32_t g, const int64_t* key_dev, size_t 
   g_err.clear();
   if (check_ctx(c)) return NSHE_EINVAL;
   if (!key_dev) return fail(NSHE_EINVAL, "key is null");
-  if (n_words != key_words(c)) return fail(NSHE_ESHAPE, "key must hold L * 2 * (L+1) * N words");
+  if (n_words != key_words(c)) return fail(NSHE_ESHAPE, "key must hold dnum * 2 * (L+alpha) * N words");
   if (g % 2 == 0 || g >= 2u * (uint32_t)c->n) return fail(NSHE_EINVAL, "g must be odd and below 2N");
   if (set_device(c)) return NSHE_EDEVICE;
   double*& slot = c->galois[g];
@@ -1364,6 +1402,7 @@ int nshe_relinearize(nshe_ctx* c, const int64_t* in3, int64_t* out, int n_ct, vo
   Dims d = dims(c, n_ct);
   const size_t W = W_of(c), N = c->n;
   HIPCHK(run_i64_to_polys(d, in3, 3, w.dt, 3 * W * N, W * N, 2, c->tb, st));
+  if (c->alpha == 2) HIPCHK(run_digit_mrc(d, w.dt, c->tb, st));
   rc = relin(c, w, n_ct, st);
   if (rc) return rc;
   HIPCHK(run_polys_to_i64(d, w.ext, 2, 2 * W * N, W * N, out, 0, c->tb, st));
@@ -1647,6 +1686,7 @@ static int rotate_ext(nshe_ctx* c, const Ws& w, int n_ct, uint32_t g, const doub
   {
     Prof pf(c, K_AUTOMORPH, st, 2.0 * n_ct * c->L * c->n);
     HIPCHK(run_automorph(d, inv_mod_2n(c, g), w.ext, w.dt, c->tb, st));
+    if (c->alpha == 2) HIPCHK(run_digit_mrc(d, w.dt, c->tb, st));
   }
   return relin(c, w, n_ct, st, key, out, false, nullptr, nullptr, accumulate);
 }

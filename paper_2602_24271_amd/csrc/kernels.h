@@ -9,11 +9,13 @@
 namespace nshe {
 
 constexpr int MAX_L = 24;            // data primes
-constexpr int MAX_PRIMES = 2 * MAX_L + 2;
+constexpr int MAX_ALPHA = 2;         // special primes (data primes per key-switching digit)
+constexpr int MAX_PRIMES = 2 * MAX_L + 1 + MAX_ALPHA;
 
 // Device constant tables of a context (all pointers are device memory).
 // Prime index convention: data primes q_0..q_{L-1} are 0..L-1, extension
-// primes b_0..b_{L} are L..2L, the special prime P is 2L+1.
+// primes b_0..b_{L} are L..2L, the special primes P_0..P_{alpha-1} are
+// 2L+1..2L+alpha (P = P_0 ... P_{alpha-1}).
 struct Tables {
   const double* p;           // [K]
   const double* pinv;        // [K] fl(1/p)
@@ -65,10 +67,11 @@ struct Tables {
   const double* b_hat_q_sp;  // [L][LB][2]  [B/b_k]_{q_i}
   const double* two24;       // [K]
   const double* two48;       // [K]
-  // key switching
+  // key switching (digits of alpha data primes, alpha special primes; the
+  // two-prime tables are at the end of the struct)
   const double* P_inv_q;     // [L]      [P^-1]_{q_i}
   const double* NP_inv_q;    // [2][L]   [N^-1 P^-1]_{q_i}; second row times w_i
-  const double* ninv_P;      // [2]      [N^-1]_P, times w_P (w: the 2^15-point
+  const double* ninv_P;      // [alpha][2] [N^-1]_{P_k}, times w_{P_k} (w: the 2^15-point
                              //          inverse's last-stage twiddle of the prime)
   const double* delta_q;     // [L]      [floor(Q/t)]_{q_i}
   // exact fallback of the Q lift: mixed-radix digits
@@ -82,6 +85,14 @@ struct Tables {
   double lift_edge;
   // residues outside [0, q_i) seen by the input check (debug switch)
   int* bad_input;
+  int ks_alpha;              // alpha: 1 or 2
+  // alpha = 2: the centred residue mod P = P_0 P_1 in mixed radix,
+  // a_0 + P_0 k with k = [(a_1 - a_0) P_0^-1]_{P_1} (both digits balanced)
+  const double* P1_inv_q;    // [L]      [P_1^-1]_{q_i} (= [P_0 P^-1]_{q_i})
+  double p0_inv_p1;          //          [P_0^-1]_{P_1}, balanced
+  // alpha = 2: a digit's value mod target prime i of the key-switching
+  // basis from its mixed-radix digits (v_0, v_1): v_0 + [q_{2j}]_{p_i} v_1
+  const double* dig_q0;      // [dnum][L + alpha] [q_{2j}]_{p_i}, balanced
 };
 
 // Call sites of the exact-lift fallback (index into Tables::margin).
@@ -97,7 +108,8 @@ enum MarginSite {
   MARGIN_COUNT = 9
 };
 
-enum { NTT_INPLACE = 0, NTT_DIGIT = 1, INV_TENSOR = 2, INV_TENSOR2 = 3, INV_PLAIN = 4 };
+enum { NTT_INPLACE = 0, NTT_DIGIT = 1, INV_TENSOR = 2, INV_TENSOR2 = 3, INV_PLAIN = 4,
+       NTT_DIGIT2 = 5 };
 
 struct NttJob {
   double* base;              // first limb of poly 0 (input of in-place kinds)
@@ -108,12 +120,15 @@ struct NttJob {
   const int* limb_prime;     // [nlimb] prime index of each limb
   int count;                 // npoly * nlimb
   // NTT_DIGIT source: third component's data limbs, canonical residues in
-  // [0, q_j) (the digits themselves); INV_TENSOR: the
+  // [0, q_j) (the digits themselves); with two primes per digit, limbs 2j
+  // and 2j + 1 hold digit j's canonical mixed-radix digits (v_0, v_1),
+  // D_j = v_0 + q_{2j} v_1 in [0, q_{2j} q_{2j+1}); INV_TENSOR: the
   // operands' transforms ([ct][2][W][N], src_b null when squaring)
   const double* src;
   const double* src_b;
   size_t src_ct_stride;      // doubles between ciphertexts in src
-  int digits;                // L (digits per ciphertext)
+  int digits;                // digits per ciphertext (L / alpha)
+  int alpha = 1;             // data primes per digit
   int split = 1;             // 2^15-point forward: two workgroups per limb
   // 2^15-point inverse (directions 1 and 3): two workgroups per limb that
   // stop before the last stage, which the consumer (scale-and-round, or
@@ -147,6 +162,7 @@ struct Dims {
   // scale-and-round / mod-down inputs come from the split inverse (2^15
   // points): the last inverse stage is still to be applied on load
   int fused = 0;
+  int alpha = 1;       // special primes (data primes per key-switching digit)
 };
 
 hipError_t run_lift(const Dims& d, double* ext, const Tables& tb, hipStream_t st);
@@ -199,6 +215,9 @@ hipError_t run_diff_i64(const Dims& d, const int64_t* x, const int64_t* y, int y
 // rotations: automorphism of ext into dt's key-switching layout
 hipError_t run_automorph(const Dims& d, unsigned ginv, const double* ext, double* dt,
                          const Tables& tb, hipStream_t st);
+// two primes per digit: canonical residues of the digit source (dt's third
+// component, limbs 0..L-1) into mixed-radix digit pairs, in place
+hipError_t run_digit_mrc(const Dims& d, double* dt, const Tables& tb, hipStream_t st);
 // p[0..words) = v, as a kernel (no memset node in a captured graph)
 hipError_t run_fill_u64(void* p, size_t words, uint64_t v, hipStream_t st);
 // debug input check: sets *tb.bad_input if a residue of [n_poly][L][N] is

@@ -374,6 +374,22 @@ __device__ __forceinline__ void gs_bfly(double& X, double& Y, double W, double p
 // Largest number of forward stages between two reductions (see ct_bfly).
 constexpr int FWD_STAGES_PER_REDUCTION = 10;
 
+// Bound (in units of p) on the values after `stages` Cooley-Tukey stages
+// from inputs below b p (ct_bfly: b -> 1.103 b + 0.5).  Every value must stay
+// below 2^53 / p > 16.6 p (p < 2^48.95) to be an exact integer.
+constexpr double ct_bound(double b, int stages) {
+  for (int i = 0; i < stages; ++i) b = 1.103 * b + 0.5;
+  return b;
+}
+// Inputs of digit transforms: a one-prime digit is below 2 p; a two-prime
+// digit's value is formed on load as v_0 + [q_{2j}]_p v_1 from canonical
+// mixed-radix digits below 1.93 p (all primes in [2^48, 2^48.95)), so below
+// (1.93 + 0.5 + 0.094 x 1.93) p < 2.61 p.
+constexpr double DIGIT_IN = 2.0, DIGIT2_IN = 2.61;
+static_assert(ct_bound(DIGIT_IN, FWD_STAGES_PER_REDUCTION) < 13.5, "one-prime digit bound");
+static_assert(ct_bound(DIGIT2_IN, FWD_STAGES_PER_REDUCTION) < 15.1, "two-prime digit bound");
+static_assert(15.1 < 16.6, "exact below 2^53");
+
 // Whether the forward transform reduces at the end of round r, given
 // `pre` stages done (unreduced) before round 0: at the last round, and
 // whenever the next round would take the count past the limit.
@@ -597,9 +613,9 @@ k_ntt_fwd(NttJob job, Tables tb) {
   using S = NttShape<LOGN>;
   __shared__ uint32_t lds[S::LDS_WORDS];
   int limb, poly;
-  if (MODE == NTT_DIGIT) {
+  if (MODE == NTT_DIGIT || MODE == NTT_DIGIT2) {
     // The digit transforms read one source limb per (ciphertext, digit) for
-    // all L + 1 target primes.  Split the (source x prime) grid into 8
+    // all L + alpha target primes.  Split the (source x prime) grid into 8
     // blocks, one per XCD: two halves of the primes x four quarters of the
     // sources.  Each XCD then keeps about half the primes' twiddle tables
     // in its L2, reads each of its sources once (the half's transforms of
@@ -643,6 +659,21 @@ k_ntt_fwd(NttJob job, Tables tb) {
       const int e = brv_c(i, S::LOGE);
       x[e] = buf_load(rs, vo, e * S::T * 8);
     }
+  } else if constexpr (MODE == NTT_DIGIT2) {
+    // Two primes per digit: limbs 2j and 2j + 1 of the source hold digit
+    // j's canonical mixed-radix digits (v_0, v_1); its value in the target
+    // prime is v_0 + [q_{2j}]_p v_1, below DIGIT2_IN p.
+    const int ct = poly / job.digits;
+    const int j = poly - ct * job.digits;
+    const double* s0 = job.src + (size_t)ct * job.src_ct_stride + (size_t)(2 * j) * S::N;
+    const auto rs0 = make_rsrc(s0, S::N * 8);
+    const auto rs1 = make_rsrc(s0 + S::N, S::N * 8);
+    const double cq = cld(tb.dig_q0, j * job.nlimb + limb);
+#pragma unroll
+    for (int i = 0; i < S::E; ++i) {
+      const int e = brv_c(i, S::LOGE);
+      x[e] = buf_load(rs0, vo, e * S::T * 8) + mul_lazy(buf_load(rs1, vo, e * S::T * 8), cq, p, pinv);
+    }
   } else {
     // loads in bit-reversed element order: the first stage pairs e with
     // e + E/2, so it can start as soon as the first two loads land
@@ -656,7 +687,8 @@ k_ntt_fwd(NttJob job, Tables tb) {
   for (int r = 0; r < S::ROUNDS; ++r) {
     if (r > 0) exchange<LOGN>(x, r - 1, r, lds, r > 1);
     fwd_round<LOGN>(x, r,
-                    fwd_reduces_after<LOGN>(r, 0) && !(MODE == NTT_DIGIT && r == S::ROUNDS - 1),
+                    fwd_reduces_after<LOGN>(r, 0) &&
+                        !((MODE == NTT_DIGIT || MODE == NTT_DIGIT2) && r == S::ROUNDS - 1),
                     tw, p, pinv);
   }
 #pragma unroll
@@ -819,7 +851,7 @@ k_ntt_fwd_half(NttJob job, Tables tb) {
   __shared__ uint32_t lds[S::LDS_WORDS];
   __shared__ double ltw[R1 * LDS_ROW];
   int limb, poly, h;
-  if (MODE == NTT_DIGIT) {
+  if (MODE == NTT_DIGIT || MODE == NTT_DIGIT2) {
     const int x = blockIdx.x & 7, l2 = blockIdx.x >> 3;
     h = l2 & 1;
     const int l = l2 >> 1;
@@ -862,7 +894,49 @@ k_ntt_fwd_half(NttJob job, Tables tb) {
   static_assert(S::ROUNDS == 3 && fwd_reduces_after<14>(HALF_REDUCE_ROUND - 1, 1) &&
                     1 + S::stages(0) + S::stages(1) == FWD_STAGES_PER_REDUCTION,
                 "half reduction placement");
-  {
+  if constexpr (MODE == NTT_DIGIT2) {
+    // two primes per digit: the value of digit j in this prime is
+    // v_0 + [q_{2j}]_p v_1 (see k_ntt_fwd), formed for both operands of
+    // stage 0 as they load; loads pipelined as below, groups of 4 (four
+    // loads per element)
+    const int ct = poly / job.digits;
+    const int j = poly - ct * job.digits;
+    const double* s0 = job.src + (size_t)ct * job.src_ct_stride + (size_t)(2 * j) * NF;
+    const auto rs0 = make_rsrc(s0, NF * 8);
+    const auto rs1 = make_rsrc(s0 + NF, NF * 8);
+    const double cq = cld(tb.dig_q0, j * job.nlimb + limb);
+    constexpr int G = 4;
+    double ax[2][G], bx[2][G], ay[2][G], by[2][G];
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+      ax[0][i] = buf_load(rs0, vo, i * S::T * 8);
+      bx[0][i] = buf_load(rs1, vo, i * S::T * 8);
+      ay[0][i] = buf_load(rs0, vo, (i * S::T + (NF >> 1)) * 8);
+      by[0][i] = buf_load(rs1, vo, (i * S::T + (NF >> 1)) * 8);
+    }
+#pragma unroll
+    for (int g = 0; g < S::E; g += G) {
+      const int slot = (g / G) & 1;
+      if (g + G < S::E) {
+        unsigned v = vo;
+        if (g) asm volatile("" : "+v"(v) : "v"(x[g - 1]));
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+          const unsigned ox = (g + G + i) * S::T * 8, oy = ((g + G + i) * S::T + (NF >> 1)) * 8;
+          ax[slot ^ 1][i] = buf_load(rs0, v, ox);
+          bx[slot ^ 1][i] = buf_load(rs1, v, ox);
+          ay[slot ^ 1][i] = buf_load(rs0, v, oy);
+          by[slot ^ 1][i] = buf_load(rs1, v, oy);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < G; ++i) {
+        const double X = ax[slot][i] + mul_lazy(bx[slot][i], cq, p, pinv);
+        const double Y = ay[slot][i] + mul_lazy(by[slot][i], cq, p, pinv);
+        x[g + i] = X + mul_lazy(Y, w0, p, pinv);
+      }
+    }
+  } else {
     // digit sources hold canonical digits in [0, q_j), below 2 p_i
     const double* src = job.base + off;
     if constexpr (MODE == NTT_DIGIT) {
@@ -903,17 +977,18 @@ k_ntt_fwd_half(NttJob job, Tables tb) {
 #pragma unroll
   for (int r = 0; r < S::ROUNDS; ++r) {
     if (r > 0) exchange<14>(x, r - 1, r, lds, r > 1);
-    // The ten stages to the end of round 1 leave values below 13.5 p.  Only
+    // The ten stages to the end of round 1 leave values below 13.5 p (15.1 p
+    // from two-prime digits, ct_bound).  Only
     // the X operands of round 2's first stage (elements 0..E/2-1: it pairs
     // e with e + E/2) are reduced, at that round's start: its products
-    // take |Y| < 13.5 p (results below 1.9 p), so it outputs below 2.4 p
-    // and the last four stages below 5.9 p (ct_bfly's bound), half the
+    // take |Y| < 15.1 p (results below 2.1 p), so it outputs below 2.6 p
+    // and the last four stages below 6.1 p (ct_bfly's bound), half the
     // reductions of reducing every value after round 1.
     // digit transforms skip the final reduction (outputs below 5.9 p):
     // their only reader, the key-switch product, reduces its sums itself
     fwd_round<14, true>(x, r,
                         fwd_reduces_after<14>(r, 1) && r != HALF_REDUCE_ROUND - 1 &&
-                            !(MODE == NTT_DIGIT && r == S::ROUNDS - 1),
+                            !((MODE == NTT_DIGIT || MODE == NTT_DIGIT2) && r == S::ROUNDS - 1),
                         tw, p, pinv, ltw, r == HALF_REDUCE_ROUND);
   }
   const unsigned so = (h * S::T + tid) * 8;
@@ -1163,6 +1238,8 @@ static hipError_t launch_ntt(const NttJob& job, const Tables& tb, int dir, hipSt
       dim3 grid(per_xcd(job, dir, 2) * 8), block(512);
       if (dir == 0)
         hipLaunchKernelGGL((k_ntt_fwd_half<NTT_INPLACE>), grid, block, 0, st, job, tb);
+      else if (job.alpha == 2)
+        hipLaunchKernelGGL((k_ntt_fwd_half<NTT_DIGIT2>), grid, block, 0, st, job, tb);
       else
         hipLaunchKernelGGL((k_ntt_fwd_half<NTT_DIGIT>), grid, block, 0, st, job, tb);
       return hipGetLastError();
@@ -1179,6 +1256,8 @@ static hipError_t launch_ntt(const NttJob& job, const Tables& tb, int dir, hipSt
     hipLaunchKernelGGL((k_ntt_fwd<LOGN, NTT_INPLACE>), grid, block, 0, st, job, tb);
   else if (dir == 1)
     hipLaunchKernelGGL((k_ntt_inv<LOGN, NTT_INPLACE>), grid, block, 0, st, job, tb);
+  else if (dir == 2 && job.alpha == 2)
+    hipLaunchKernelGGL((k_ntt_fwd<LOGN, NTT_DIGIT2>), grid, block, 0, st, job, tb);
   else if (dir == 2)
     hipLaunchKernelGGL((k_ntt_fwd<LOGN, NTT_DIGIT>), grid, block, 0, st, job, tb);
   else if (job.src_b == nullptr)

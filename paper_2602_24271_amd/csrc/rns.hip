@@ -213,8 +213,9 @@ __device__ __forceinline__ double coef_const(const CoefSrc& s, const double* tab
 // FUSED: dt holds the split inverse's half outputs (see coef_load); each
 // wave takes 32 coefficient pairs (c, c + N/2), lanes 0-31 the lower
 // coefficients and 32-63 the upper, and writes its outputs in place at the
-// positions it alone reads.
-template <int L, bool FUSED>
+// positions it alone reads.  A: data primes per key-switching digit (the
+// third component's digit format).
+template <int L, bool FUSED, int A>
 __global__ void __launch_bounds__(256) k_scale(int n, size_t n_poly, double* dt, Tables tb) {
   constexpr int LB = L + 1;
   const PolyBlock pb = poly_block(n, n_poly);
@@ -303,6 +304,8 @@ __global__ void __launch_bounds__(256) k_scale(int n, size_t n_poly, double* dt,
   double wh[LB], wl[LB];
 #pragma unroll
   for (int k = 0; k < LB; ++k) split24(wp[k * bs], wh[k], wl[k]);
+  const bool pairs = A == 2 && third;
+  double prev = 0.0;
 #pragma unroll
   for (int i = 0; i < L; ++i) {
     const int iq = opaque_idx(i);
@@ -311,32 +314,41 @@ __global__ void __launch_bounds__(256) k_scale(int n, size_t n_poly, double* dt,
     const double acc = conv_row<LB>(wh, wl, sp, cld(tb.two24, iq), cld(tb.two48, iq), q, qinv) -
                        v2 * cld(tb.B_q, iq);
     const double r = reduce_bal(acc, q, qinv);
-    // the third component is only read as relinearization digits, which
-    // are its canonical residues
-    buf_store(third ? to_canonical(r, q) : r, rs, vo, i * ls);
+    // the third component is only read as relinearization digits: its
+    // canonical residues, or with two primes per digit the digit pairs'
+    // canonical mixed-radix digits (limb 2j + 1 gets
+    // [(d_{2j+1} - d_{2j}) q_{2j}^-1]_{q_{2j+1}}; |d_{2j+1} - d_{2j}| < 2^49)
+    double o = third ? to_canonical(r, q) : r;
+    if constexpr (A == 2) {
+      if (pairs && (i & 1))
+        o = to_canonical(mul_bal(o - prev, cld(tb.mrc_inv, (iq - 1) * L + iq), q, qinv), q);
+      prev = o;
+    }
+    buf_store(o, rs, vo, i * ls);
   }
 }
 
 // ---------------------------------------------------------- key switching ---
 
-// acc[ct][b][i] = sum_j dig[ct][j][i] * evk[j][b][i] (NTT domain), limbs
-// i = 0..L (the last one mod P).  The key is read once per chunk of CH
-// ciphertexts.
-template <int L, int CH>
+// acc[ct][b][i] = sum_j dig[ct][j][i] * evk[j][b][i] (NTT domain) over the
+// L / A digits, limbs i = 0..L+A-1 (the last A mod the special primes).
+// The key is read once per chunk of CH ciphertexts.
+template <int L, int A, int CH>
 __global__ void __launch_bounds__(256) k_ks_mac(int n, int n_ct, const double* dig,
                                                 const double* evk, double* acc, Tables tb) {
-  constexpr int K = L + 1;
+  constexpr int K = L + A;
+  constexpr int DN = L / A;
   const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= (size_t)K * n) return;
   const int i = (int)(gid / n);
   const int c = (int)(gid - (size_t)i * n);
-  const int prime = i < L ? i : 2 * L + 1;
+  const int prime = i < L ? i : L + 1 + i;
   const double p = cld(tb.p, prime), pinv = cld(tb.pinv, prime);
   for (int c0 = 0; c0 < n_ct; c0 += CH) {
     double a0[CH], a1[CH];
 #pragma unroll
     for (int u = 0; u < CH; ++u) a0[u] = a1[u] = 0.0;
-    for (int j = 0; j < L; ++j) {
+    for (int j = 0; j < DN; ++j) {
       const double e0 = evk[((size_t)(j * 2 + 0) * K + i) * n + c];
       const double e1 = evk[((size_t)(j * 2 + 1) * K + i) * n + c];
       // every load of the chunk is issued before the products: past the
@@ -346,17 +358,20 @@ __global__ void __launch_bounds__(256) k_ks_mac(int n, int n_ct, const double* d
 #pragma unroll
       for (int u = 0; u < CH; ++u) {
         const int cu = c0 + u < n_ct ? c0 + u : n_ct - 1;
-        dv[u] = __builtin_nontemporal_load(&dig[((size_t)(cu * L + j) * K + i) * n + c]);
+        dv[u] = __builtin_nontemporal_load(&dig[((size_t)(cu * DN + j) * K + i) * n + c]);
       }
 #pragma unroll
       for (int u = 0; u < CH; ++u) {
         a0[u] += mul_lazy(dv[u], e0, p, pinv);
         a1[u] += mul_lazy(dv[u], e1, p, pinv);
       }
-      // digit transforms are not reduced at their end: |dv| < 13.5 p (at
-      // most ten unreduced stages from inputs below 2p; 5.9 p at N = 2^15),
-      // so each product is below 1.75 p and eight of them plus a reduced
-      // sum stay below 14.5 p < 2^53 / p: reduce the sums every 8 digits
+      // digit transforms are not reduced at their end: |dv| < 15.1 p (at
+      // most ten unreduced stages from inputs below 2.61 p, the bound of a
+      // two-prime digit's value; 13.5 p from one-prime digits below 2 p;
+      // 6.1 p at N = 2^15), so each product with a balanced key is below
+      // (1/2 + 0.094 x 15.1) p = 1.92 p and eight of them plus a reduced sum
+      // stay below 15.9 p < 2^53 / p (> 16.6 p for p < 2^48.95): reduce the
+      // sums every 8 digits
       if ((j & 7) == 7) {
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
@@ -375,18 +390,59 @@ __global__ void __launch_bounds__(256) k_ks_mac(int n, int n_ct, const double* d
   }
 }
 
+// A special limb's residues [N^-1 x]_{P_k} (balanced) at coefficients c and
+// c + N/2 from the split inverse's half outputs U (at a) and V (at a + ht):
+// the inverse's last stage (U + V, (U - V) w) applied here.
+__device__ __forceinline__ void special_pair(const double* a, int ht, int ip, double& lo,
+                                             double& hi, const Tables& tb) {
+  const double pk = cld(tb.p, ip), pkinv = cld(tb.pinv, ip);
+  const double u = a[0], v = a[ht];
+  const double ninvk = cld(tb.ninv, ip);
+  lo = mul_bal(u + v, ninvk, pk, pkinv);
+  hi = mul_bal(mul_lazy(u - v, cld(tb.tw_inv, ip * tb.tw_len + 1), pk, pkinv), ninvk, pk, pkinv);
+}
+
+// The centred residue r = [x]_P of a key-switch sum, P = P_0 ... P_{A-1}, in
+// mixed radix r = a_0 + P_0 k from its (balanced) residues a_0 mod P_0 and,
+// for A = 2, a_1 mod P_1: k = [(a_1 - a_0) P_0^-1]_{P_1} balanced
+// (|a_1 - a_0| < 2 P_1).  With both digits balanced,
+// |r| <= (P_0 - 1)/2 + P_0 (P_1 - 1)/2 = (P - 1)/2: r is exactly the
+// centred residue, with no comparison.  (k = 0 for A = 1.)
+template <int A>
+__device__ __forceinline__ double special_k(double a0, double a1, const Tables& tb, int L) {
+  if constexpr (A == 1) {
+    return 0.0;
+  } else {
+    const int ip1 = 2 * L + 2;
+    return mul_bal(a1 - a0, tb.p0_inv_p1, cld(tb.p, ip1), cld(tb.pinv, ip1));
+  }
+}
+
+// (x - r) P^-1 mod q_i up to the factor N^-1 folded into npq: x times
+// [N^-1 P^-1]_{q_i} minus r's digits times [P^-1]_{q_i} and [P_1^-1]_{q_i}
+// (= [P_0 P^-1]_{q_i}).  Each lazy product is below 0.9 q_i (operands
+// below 2 q_i), so the result is below 2.7 q_i.
+template <int A>
+__device__ __forceinline__ double moddown_term(double x, double npq, double a0, double k, int i,
+                                               double q, double qinv, const Tables& tb) {
+  double r = mul_lazy(x, npq, q, qinv) - mul_lazy(a0, cld(tb.P_inv_q, i), q, qinv);
+  if constexpr (A == 2) r -= mul_lazy(k, cld(tb.P1_inv_q, i), q, qinv);
+  return r;
+}
+
 // new ct (into ext limbs 0..L-1) = e_b + (acc_b - [acc_b]_P) * P^-1, where
-// [acc_b]_P is the balanced (= centred) residue of the P limb.  Since
-// mul_lazy(aP, .) needs |aP| < 2p only, P may exceed q_i (both < 2^49).
+// [acc_b]_P is the centred residue mod P of the special limbs (special_k).
+// Since mul_lazy(a0, .) needs |a0| < 2p only, P_k may exceed q_i (all
+// < 2^49).
 // FUSED: acc holds the split inverse's in-place half outputs of a 2^15-point
 // limb (U of pair c at (c / 512) 1024 + c mod 512, V 512 further; see
 // k_ntt_inv_half) and a thread produces both coefficients c and c + N/2.
-template <int L, bool FUSED>
+template <int L, int A, bool FUSED>
 __global__ void __launch_bounds__(256) k_moddown(int n, int n_ct, const double* __restrict__ acc,
                                                  const double* __restrict__ dt,
                                                  double* __restrict__ ext, int accumulate,
                                                  Tables tb) {
-  constexpr int K = L + 1;
+  constexpr int K = L + A;
   constexpr int W = 2 * L + 1;
   const int per = FUSED ? n >> 1 : n;      // threads per (ct, component)
   const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -401,14 +457,19 @@ __global__ void __launch_bounds__(256) k_moddown(int n, int n_ct, const double* 
   double* o = ext + cb * (size_t)W * n + c;
   if constexpr (!FUSED) {
     const double* a = acc + cb * (size_t)K * n + c;
-    // acc is inverse-transform output (N times the sum): the centred
-    // residue mod P is [N^-1 acc_P]_P
+    // acc is inverse-transform output (N times the sum): the residues mod
+    // the special primes are [N^-1 acc_Pk]_Pk
     const double aP = mul_bal(a[(size_t)L * n], cld(tb.ninv, ip), pP, pPinv);
+    double kP = 0.0;
+    if constexpr (A == 2) {
+      const double a1 = mul_bal(a[(size_t)(L + 1) * n], cld(tb.ninv, ip + 1), cld(tb.p, ip + 1),
+                                cld(tb.pinv, ip + 1));
+      kP = special_k<A>(aP, a1, tb, L);
+    }
 #pragma unroll
     for (int i = 0; i < L; ++i) {
       const double q = cld(tb.p, i), qinv = cld(tb.pinv, i);
-      const double r = mul_lazy(a[(size_t)i * n], cld(tb.NP_inv_q, i), q, qinv) -
-                       mul_lazy(aP, cld(tb.P_inv_q, i), q, qinv);
+      const double r = moddown_term<A>(a[(size_t)i * n], cld(tb.NP_inv_q, i), aP, kP, i, q, qinv, tb);
       const double z = reduce_bal(e[(size_t)i * n] + r, q, qinv);
       o[(size_t)i * n] = accumulate ? reduce_bal(o[(size_t)i * n] + z, q, qinv) : z;
     }
@@ -416,20 +477,23 @@ __global__ void __launch_bounds__(256) k_moddown(int n, int n_ct, const double* 
     const int ht = n >> 6;                 // 512: a half transform's threads
     const double* a = acc + cb * (size_t)K * n + (size_t)(c / ht) * 2 * ht + (c % ht);
     const size_t hn = (size_t)(n >> 1);
-    const double uP = a[(size_t)L * n], vP = a[(size_t)L * n + ht];
-    const double ninvP = cld(tb.ninv, ip);
-    const double aP_lo = mul_bal(uP + vP, ninvP, pP, pPinv);
-    const double aP_hi =
-        mul_bal(mul_lazy(uP - vP, cld(tb.tw_inv, ip * tb.tw_len + 1), pP, pPinv), ninvP, pP, pPinv);
+    double aP_lo, aP_hi, k_lo = 0.0, k_hi = 0.0;
+    special_pair(a + (size_t)L * n, ht, ip, aP_lo, aP_hi, tb);
+    if constexpr (A == 2) {
+      double a1_lo, a1_hi;
+      special_pair(a + (size_t)(L + 1) * n, ht, ip + 1, a1_lo, a1_hi, tb);
+      k_lo = special_k<A>(aP_lo, a1_lo, tb, L);
+      k_hi = special_k<A>(aP_hi, a1_hi, tb, L);
+    }
 #pragma unroll
     for (int i = 0; i < L; ++i) {
       const double q = cld(tb.p, i), qinv = cld(tb.pinv, i);
       const double u = a[(size_t)i * n], v = a[(size_t)i * n + ht];
       const double lo = u + v;
       const double hi = mul_lazy(u - v, cld(tb.tw_inv, i * tb.tw_len + 1), q, qinv);
-      const double npq = cld(tb.NP_inv_q, i), pq = cld(tb.P_inv_q, i);
-      const double r_lo = mul_lazy(lo, npq, q, qinv) - mul_lazy(aP_lo, pq, q, qinv);
-      const double r_hi = mul_lazy(hi, npq, q, qinv) - mul_lazy(aP_hi, pq, q, qinv);
+      const double npq = cld(tb.NP_inv_q, i);
+      const double r_lo = moddown_term<A>(lo, npq, aP_lo, k_lo, i, q, qinv, tb);
+      const double r_hi = moddown_term<A>(hi, npq, aP_hi, k_hi, i, q, qinv, tb);
       const double z_lo = reduce_bal(e[(size_t)i * n] + r_lo, q, qinv);
       const double z_hi = reduce_bal(e[(size_t)i * n + hn] + r_hi, q, qinv);
       o[(size_t)i * n] = accumulate ? reduce_bal(o[(size_t)i * n] + z_lo, q, qinv) : z_lo;
@@ -442,13 +506,13 @@ __global__ void __launch_bounds__(256) k_moddown(int n, int n_ct, const double* 
 // to the caller's int64 output, canonical residues in [0, q_i): with finish,
 // the mask's finish out = (Delta, 0) - z (every residue negated and
 // [Delta]_{q_i} added to the constant coefficient of c0); without, z.
-template <int L>
+template <int L, int A>
 __global__ void __launch_bounds__(256) k_moddown_finish(int n, int n_ct,
                                                         const double* __restrict__ acc,
                                                         const double* __restrict__ dt,
                                                         int64_t* __restrict__ out, int finish,
                                                         Tables tb) {
-  constexpr int K = L + 1;
+  constexpr int K = L + A;
   constexpr int W = 2 * L + 1;
   const int per = n >> 1;
   const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -458,26 +522,28 @@ __global__ void __launch_bounds__(256) k_moddown_finish(int n, int n_ct,
   const size_t ct = cb >> 1;
   const int b = (int)(cb & 1);
   const int ip = 2 * L + 1;
-  const double pP = cld(tb.p, ip), pPinv = cld(tb.pinv, ip);
   const double* e = dt + ((ct * 3 + b) * (size_t)W) * n + c;
   int64_t* o = out + cb * (size_t)L * n + c;
   const int ht = n >> 6;
   const double* a = acc + cb * (size_t)K * n + (size_t)(c / ht) * 2 * ht + (c % ht);
   const size_t hn = (size_t)(n >> 1);
-  const double uP = a[(size_t)L * n], vP = a[(size_t)L * n + ht];
-  const double ninvP = cld(tb.ninv, ip);
-  const double aP_lo = mul_bal(uP + vP, ninvP, pP, pPinv);
-  const double aP_hi =
-      mul_bal(mul_lazy(uP - vP, cld(tb.tw_inv, ip * tb.tw_len + 1), pP, pPinv), ninvP, pP, pPinv);
+  double aP_lo, aP_hi, k_lo = 0.0, k_hi = 0.0;
+  special_pair(a + (size_t)L * n, ht, ip, aP_lo, aP_hi, tb);
+  if constexpr (A == 2) {
+    double a1_lo, a1_hi;
+    special_pair(a + (size_t)(L + 1) * n, ht, ip + 1, a1_lo, a1_hi, tb);
+    k_lo = special_k<A>(aP_lo, a1_lo, tb, L);
+    k_hi = special_k<A>(aP_hi, a1_hi, tb, L);
+  }
 #pragma unroll
   for (int i = 0; i < L; ++i) {
     const double q = cld(tb.p, i), qinv = cld(tb.pinv, i);
     const double u = a[(size_t)i * n], v = a[(size_t)i * n + ht];
     const double lo = u + v;
     const double hi = mul_lazy(u - v, cld(tb.tw_inv, i * tb.tw_len + 1), q, qinv);
-    const double npq = cld(tb.NP_inv_q, i), pq = cld(tb.P_inv_q, i);
-    const double r_lo = mul_lazy(lo, npq, q, qinv) - mul_lazy(aP_lo, pq, q, qinv);
-    const double r_hi = mul_lazy(hi, npq, q, qinv) - mul_lazy(aP_hi, pq, q, qinv);
+    const double npq = cld(tb.NP_inv_q, i);
+    const double r_lo = moddown_term<A>(lo, npq, aP_lo, k_lo, i, q, qinv, tb);
+    const double r_hi = moddown_term<A>(hi, npq, aP_hi, k_hi, i, q, qinv, tb);
     // finish: -(e + r), plus Delta at coefficient 0 of c0 (sg = -1 exactly
     // negates); else e + r
     const double sg = finish ? -1.0 : 1.0;
@@ -528,12 +594,12 @@ __device__ __forceinline__ void lift_tail(const double (&o)[L], const double (&y
 // coefficients of a pair (c, c + N/2) and exchange the key-switch sum's half
 // outputs as the scale-and-round does, with the last inverse stage's
 // twiddle folded into the second rows of NP_inv_q and ninv_P.
-template <int L>
+template <int L, int A>
 __global__ void __launch_bounds__(256) k_moddown_lift(int n, size_t n_poly,
                                                       const double* __restrict__ acc,
                                                       const double* __restrict__ dt,
                                                       double* __restrict__ ext, Tables tb) {
-  constexpr int K = L + 1;
+  constexpr int K = L + A;
   constexpr int W = 2 * L + 1;
   const PolyBlock pb = poly_block(n, n_poly);   // poly = ct * 2 + b
   if (!pb.ok) return;
@@ -551,11 +617,19 @@ __global__ void __launch_bounds__(256) k_moddown_lift(int n, size_t n_poly,
   const auto re = make_rsrc(dt + (ct * 3 + b) * (size_t)W * n, (unsigned)(L * n * 8));
   const auto rs = make_rsrc(ext + cb * (size_t)W * n, (unsigned)(W * n * 8));
   const int row = hi ? 1 : 0;
-  // centred [N^-1 acc_P]_P of this coefficient
+  // [N^-1 acc_Pk]_Pk of this coefficient (balanced), and for A = 2 the
+  // centred residue's second mixed-radix digit
   const int ip = 2 * L + 1;
   const double pP = cld(tb.p, ip), pPinv = cld(tb.pinv, ip);
   const double xP = buf_load(ra, pos, L * ls);
   const double aP = mul_bal(pair_combine(xP, sg), tb.ninv_P[row], pP, pPinv);
+  double kP = 0.0;
+  if constexpr (A == 2) {
+    const double x1 = buf_load(ra, pos, (L + 1) * ls);
+    const double a1 = mul_bal(pair_combine(x1, sg), tb.ninv_P[2 + row], cld(tb.p, ip + 1),
+                              cld(tb.pinv, ip + 1));
+    kP = special_k<A>(aP, a1, tb, L);
+  }
   // the new ciphertext's residues are stored only after every load: buffer
   // stores between them would make each limb's loads wait for the previous
   // limb's (the compiler cannot tell the buffers apart)
@@ -566,8 +640,8 @@ __global__ void __launch_bounds__(256) k_moddown_lift(int n, size_t n_poly,
     const int iq = opaque_idx(i);
     const double q = cld(tb.p, iq), qinv = cld(tb.pinv, iq);
     const double x = buf_load(ra, pos, i * ls);
-    const double r = mul_lazy(pair_combine(x, sg), tb.NP_inv_q[row * L + iq], q, qinv) -
-                     mul_lazy(aP, cld(tb.P_inv_q, iq), q, qinv);
+    const double r =
+        moddown_term<A>(pair_combine(x, sg), tb.NP_inv_q[row * L + iq], aP, kP, iq, q, qinv, tb);
     o[i] = reduce_bal(buf_load(re, vo, i * ls) + r, q, qinv);
     y[i] = mul_bal(o[i], cld(tb.q_hat_inv, iq), q, qinv);
     S += y[i] * cld(tb.recip, iq);
@@ -834,6 +908,26 @@ __global__ void __launch_bounds__(256) k_automorph(int n, int L, int n_ct, unsig
   }
 }
 
+// Two primes per key-switching digit: the digit source (dt's third
+// component, limbs 0..L-1, canonical residues d_i) into mixed-radix digit
+// pairs, in place: limb 2j + 1 becomes [(d_{2j+1} - d_{2j}) q_{2j}^-1]_{q_{2j+1}}
+// (canonical), so that digit j, D_j = d_{2j} + q_{2j} v in [0, q_{2j} q_{2j+1}),
+// is [c]_{q_{2j} q_{2j+1}}.  One thread per (ciphertext, pair, coefficient).
+__global__ void __launch_bounds__(256) k_digit_mrc(int n, int L, int n_ct, double* dt, Tables tb) {
+  const int pairs = L >> 1;
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (size_t)n_ct * pairs * n) return;
+  const size_t row = gid / n;               // ct * pairs + j
+  const int c = (int)(gid - row * n);
+  const int j = (int)(row % pairs);
+  const size_t ct = row / pairs;
+  const size_t W = (size_t)2 * L + 1;
+  double* d = dt + (ct * 3 * W + 2 * W + 2 * j) * n + c;
+  const int ib = 2 * j + 1;
+  const double q = cld(tb.p, ib), qinv = cld(tb.pinv, ib);
+  d[n] = to_canonical(mul_bal(d[n] - d[0], cld(tb.mrc_inv, (ib - 1) * L + ib), q, qinv), q);
+}
+
 // ------------------------------------------------------------ boundary ---
 
 // ext[ct][b][i] (i < L) = balanced(x - y); y broadcast over ct if y_bcast.
@@ -1046,6 +1140,8 @@ static inline dim3 grid_for(size_t total, int block = 256) {
 }
 
 #define NSHE_L_CASES(X) X(2) X(3) X(4) X(8) X(12) X(16) X(17) X(20) X(24)
+// data-prime counts built for two primes per key-switching digit
+#define NSHE_L2_CASES(X) X(2) X(4) X(8) X(16)
 
 hipError_t run_lift(const Dims& d, double* ext, const Tables& tb, hipStream_t st) {
   const size_t np = (size_t)d.n_ct * 2;
@@ -1063,16 +1159,29 @@ hipError_t run_moddown_finish(const Dims& d, const double* acc, const double* dt
                               const Tables& tb, hipStream_t st, int finish) {
   if (!d.fused) return hipErrorInvalidValue;
   const size_t total = (size_t)d.n_ct * 2 * (d.n / 2);
-  switch (d.L) {
-#define C_(L_)                                                                                 \
+#define C_(L_, A_)                                                                             \
   case L_:                                                                                     \
-    hipLaunchKernelGGL(k_moddown_finish<L_>, grid_for(total, d.block), dim3(d.block), 0, st,   \
-                       d.n, d.n_ct, acc, dt, out, finish, tb);                         \
+    hipLaunchKernelGGL((k_moddown_finish<L_, A_>), grid_for(total, d.block), dim3(d.block), 0, \
+                       st, d.n, d.n_ct, acc, dt, out, finish, tb);                             \
     break;
-    NSHE_L_CASES(C_)
-#undef C_
-    default: return hipErrorInvalidValue;
+#define C1_(L_) C_(L_, 1)
+#define C2_(L_) C_(L_, 2)
+  if (d.alpha == 1) {
+    switch (d.L) {
+      NSHE_L_CASES(C1_)
+      default: return hipErrorInvalidValue;
+    }
+  } else if (d.alpha == 2) {
+    switch (d.L) {
+      NSHE_L2_CASES(C2_)
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    return hipErrorInvalidValue;
   }
+#undef C1_
+#undef C2_
+#undef C_
   return hipGetLastError();
 }
 
@@ -1112,16 +1221,29 @@ hipError_t run_moddown_lift(const Dims& d, const double* acc, const double* dt, 
                             const Tables& tb, hipStream_t st) {
   if (!d.fused) return hipErrorInvalidValue;
   const size_t np = (size_t)d.n_ct * 2;
-  switch (d.L) {
-#define C_(L_)                                                                               \
+#define C_(L_, A_)                                                                           \
   case L_:                                                                                   \
-    hipLaunchKernelGGL(k_moddown_lift<L_>, poly_grid(np, d.n, d.block), dim3(d.block), 0, st, \
-                       d.n, np, acc, dt, ext, tb);                                           \
+    hipLaunchKernelGGL((k_moddown_lift<L_, A_>), poly_grid(np, d.n, d.block), dim3(d.block), \
+                       0, st, d.n, np, acc, dt, ext, tb);                                    \
     break;
-    NSHE_L_CASES(C_)
-#undef C_
-    default: return hipErrorInvalidValue;
+#define C1_(L_) C_(L_, 1)
+#define C2_(L_) C_(L_, 2)
+  if (d.alpha == 1) {
+    switch (d.L) {
+      NSHE_L_CASES(C1_)
+      default: return hipErrorInvalidValue;
+    }
+  } else if (d.alpha == 2) {
+    switch (d.L) {
+      NSHE_L2_CASES(C2_)
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    return hipErrorInvalidValue;
   }
+#undef C1_
+#undef C2_
+#undef C_
   return hipGetLastError();
 }
 
@@ -1130,66 +1252,112 @@ hipError_t run_scale(const Dims& d, double* dt, const Tables& tb, hipStream_t st
   const size_t np = (size_t)d.n_ct * 3;
   // the split-inverse variant's barrier needs whole blocks (see k_scale)
   if (d.fused && d.n % d.block) return hipErrorInvalidValue;
-  switch (d.L) {
-#define C_(L_) \
-  case L_:                                                                                 \
-    if (d.fused)                                                                           \
-      hipLaunchKernelGGL((k_scale<L_, true>), poly_grid(np, d.n, d.block), dim3(d.block),  \
-                         (size_t)(L_ + 1) * d.block * 8, st, d.n, np, dt, tb);             \
-    else                                                                                   \
-      hipLaunchKernelGGL((k_scale<L_, false>), poly_grid(np, d.n, d.block), dim3(d.block), \
-                         (size_t)(L_ + 1) * d.block * 8, st, d.n, np, dt, tb);             \
+#define C_(L_, A_) \
+  case L_:                                                                                     \
+    if (d.fused)                                                                               \
+      hipLaunchKernelGGL((k_scale<L_, true, A_>), poly_grid(np, d.n, d.block), dim3(d.block),  \
+                         (size_t)(L_ + 1) * d.block * 8, st, d.n, np, dt, tb);                 \
+    else                                                                                       \
+      hipLaunchKernelGGL((k_scale<L_, false, A_>), poly_grid(np, d.n, d.block), dim3(d.block), \
+                         (size_t)(L_ + 1) * d.block * 8, st, d.n, np, dt, tb);                 \
     break;
-    NSHE_L_CASES(C_)
-#undef C_
-    default: return hipErrorInvalidValue;
+#define C1_(L_) C_(L_, 1)
+#define C2_(L_) C_(L_, 2)
+  if (d.alpha == 1) {
+    switch (d.L) {
+      NSHE_L_CASES(C1_)
+      default: return hipErrorInvalidValue;
+    }
+  } else if (d.alpha == 2) {
+    switch (d.L) {
+      NSHE_L2_CASES(C2_)
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    return hipErrorInvalidValue;
   }
+#undef C1_
+#undef C2_
+#undef C_
   return hipGetLastError();
 }
 
 hipError_t run_ks_mac(const Dims& d, const double* dig, const double* evk, double* acc,
                       const Tables& tb, hipStream_t st) {
-  const size_t total = (size_t)(d.L + 1) * d.n;
+  const size_t total = (size_t)(d.L + d.alpha) * d.n;
   // a chunk wider than the ciphertexts present would only repeat its
   // (clamped) loads and products: halve it down to them
   int ch = d.ks_chunk;
   while (ch > 4 && ch / 2 >= d.n_ct) ch /= 2;
-  switch (d.L) {
-#define C_(L_) \
+#define C_(L_, A_) \
   case L_:                                                                                     \
     if (ch == 4)                                                                               \
-      hipLaunchKernelGGL((k_ks_mac<L_, 4>), grid_for(total), dim3(256), 0, st, d.n, d.n_ct, dig, evk, acc, tb); \
+      hipLaunchKernelGGL((k_ks_mac<L_, A_, 4>), grid_for(total), dim3(256), 0, st, d.n, d.n_ct, dig, evk, acc, tb); \
     else if (ch == 8)                                                                          \
-      hipLaunchKernelGGL((k_ks_mac<L_, 8>), grid_for(total), dim3(256), 0, st, d.n, d.n_ct, dig, evk, acc, tb); \
+      hipLaunchKernelGGL((k_ks_mac<L_, A_, 8>), grid_for(total), dim3(256), 0, st, d.n, d.n_ct, dig, evk, acc, tb); \
     else if (ch == 32)                                                                         \
-      hipLaunchKernelGGL((k_ks_mac<L_, 32>), grid_for(total), dim3(256), 0, st, d.n, d.n_ct, dig, evk, acc, tb); \
+      hipLaunchKernelGGL((k_ks_mac<L_, A_, 32>), grid_for(total), dim3(256), 0, st, d.n, d.n_ct, dig, evk, acc, tb); \
     else                                                                                       \
-      hipLaunchKernelGGL((k_ks_mac<L_, 16>), grid_for(total), dim3(256), 0, st, d.n, d.n_ct, dig, evk, acc, tb); \
+      hipLaunchKernelGGL((k_ks_mac<L_, A_, 16>), grid_for(total), dim3(256), 0, st, d.n, d.n_ct, dig, evk, acc, tb); \
     break;
-    NSHE_L_CASES(C_)
-#undef C_
-    default: return hipErrorInvalidValue;
+#define C1_(L_) C_(L_, 1)
+#define C2_(L_) C_(L_, 2)
+  if (d.alpha == 1) {
+    switch (d.L) {
+      NSHE_L_CASES(C1_)
+      default: return hipErrorInvalidValue;
+    }
+  } else if (d.alpha == 2) {
+    switch (d.L) {
+      NSHE_L2_CASES(C2_)
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    return hipErrorInvalidValue;
   }
+#undef C1_
+#undef C2_
+#undef C_
   return hipGetLastError();
 }
 
 hipError_t run_moddown(const Dims& d, const double* acc, const double* dt, double* ext,
                        const Tables& tb, hipStream_t st, int accumulate) {
   const size_t total = (size_t)d.n_ct * 2 * (d.fused ? d.n / 2 : d.n);
-  switch (d.L) {
-#define C_(L_)                                                                              \
-  case L_:                                                                                  \
-    if (d.fused)                                                                            \
-      hipLaunchKernelGGL((k_moddown<L_, true>), grid_for(total, d.block), dim3(d.block), 0, \
-                         st, d.n, d.n_ct, acc, dt, ext, accumulate, tb);                    \
-    else                                                                                    \
-      hipLaunchKernelGGL((k_moddown<L_, false>), grid_for(total, d.block), dim3(d.block), 0, \
-                         st, d.n, d.n_ct, acc, dt, ext, accumulate, tb);                    \
+#define C_(L_, A_)                                                                              \
+  case L_:                                                                                      \
+    if (d.fused)                                                                                \
+      hipLaunchKernelGGL((k_moddown<L_, A_, true>), grid_for(total, d.block), dim3(d.block), 0, \
+                         st, d.n, d.n_ct, acc, dt, ext, accumulate, tb);                        \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_moddown<L_, A_, false>), grid_for(total, d.block), dim3(d.block),   \
+                         0, st, d.n, d.n_ct, acc, dt, ext, accumulate, tb);                     \
     break;
-    NSHE_L_CASES(C_)
-#undef C_
-    default: return hipErrorInvalidValue;
+#define C1_(L_) C_(L_, 1)
+#define C2_(L_) C_(L_, 2)
+  if (d.alpha == 1) {
+    switch (d.L) {
+      NSHE_L_CASES(C1_)
+      default: return hipErrorInvalidValue;
+    }
+  } else if (d.alpha == 2) {
+    switch (d.L) {
+      NSHE_L2_CASES(C2_)
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    return hipErrorInvalidValue;
   }
+#undef C1_
+#undef C2_
+#undef C_
+  return hipGetLastError();
+}
+
+hipError_t run_digit_mrc(const Dims& d, double* dt, const Tables& tb, hipStream_t st) {
+  if (d.alpha != 2 || d.L % 2) return hipErrorInvalidValue;
+  const size_t total = (size_t)d.n_ct * (d.L / 2) * d.n;
+  hipLaunchKernelGGL(k_digit_mrc, grid_for(total), dim3(256), 0, st, d.n, d.L, d.n_ct, dt, tb);
   return hipGetLastError();
 }
 

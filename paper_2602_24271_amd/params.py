@@ -51,8 +51,9 @@ def _root(x: int, k: int) -> int:
     return lo
 
 
-def modulus_chain(log_qp: int = PAPER_LOG_QP, n_primes: int = N_PRIMES):
-    """(data primes q_0..q_{L-1} descending, special prime P)."""
+def modulus_chain(log_qp: int = PAPER_LOG_QP, n_primes: int = N_PRIMES, n_special: int = 1):
+    """(data primes q_0..q_{L-1} descending, special prime P or, for
+    n_special = 2, the tuple of the two largest primes)."""
     bound = _root(1 << log_qp, n_primes)
     out = []
     k = (bound - 1) // STEP
@@ -61,9 +62,11 @@ def modulus_chain(log_qp: int = PAPER_LOG_QP, n_primes: int = N_PRIMES):
         if c <= bound and _is_prime(c):
             out.append(c)
         k -= 1
-    return out[1:], out[0]
+    return out[n_special:], (out[0] if n_special == 1 else tuple(out[:n_special]))
 
 
-def paper_params(log2_n: int = PAPER_LOG2_N, t: int = PAPER_T) -> dict:
-    q, P = modulus_chain()
+def paper_params(log2_n: int = PAPER_LOG2_N, t: int = PAPER_T, alpha: int = 1) -> dict:
+    """The paper's parameters; alpha special primes (one key-switching digit
+    per alpha data primes)."""
+    q, P = modulus_chain(n_special=alpha)
     return {"log2_n": log2_n, "t": t, "q": q, "P": P}

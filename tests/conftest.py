@@ -19,3 +19,11 @@ def s32k():
     keys of seed 0, shared by the full-size GPU test modules."""
     from tests.gpu_common import Setup
     return Setup(15)
+
+
+@pytest.fixture(scope="session")
+def s32k_a2():
+    """The paper's size with key switching by digits of two data primes (16
+    data primes, two special primes), keys of seed 0."""
+    from tests.gpu_common import Setup
+    return Setup(15, alpha=2)

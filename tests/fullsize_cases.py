@@ -1,6 +1,8 @@
 """Seeded inputs and oracle evaluations of the parity cases at the paper's
 size (N = 32768 slots, the 17 + 1 primes of about 49 bits, p = 65537;
-Sec. 5.1), plus two cases at other (N, t) that reach the same kernels.
+Sec. 5.1), plus two cases at other (N, t) that reach the same kernels, and
+the same cases with key switching by digits of two data primes (16 data
+primes, two special primes: the a2_ cases).
 
 The oracle needs minutes per case at this size, so its results are kept as
 SHA-256 digests of the exchange-format arrays (int64 residues, C order,
@@ -75,13 +77,13 @@ def check(golden: dict, label: str, arr) -> None:
 
 class Env:
     """Oracle parameters, secret key and relinearization key (keys from
-    KEY_SEED, as the GPU tests' Setup draws them)."""
+    KEY_SEED, as the GPU tests' Setup draws them); alpha special primes."""
 
-    def __init__(self, log2_n: int = 15, t: int = 65537):
+    def __init__(self, log2_n: int = 15, t: int = 65537, alpha: int = 1):
         n = 1 << log2_n
-        self.pr = bfv.paper_params(n, t)
+        self.pr = bfv.paper_params(n, t, alpha)
         self.sk, self.rk = bfv.keygen(self.pr, synth.key_randomness(
-            KEY_SEED, n, self.pr.moduli_pq, self.pr.L))
+            KEY_SEED, n, self.pr.moduli_pq, self.pr.dnum))
 
     def enc(self, slots, seed):
         return bfv.encrypt_slots(self.pr, self.sk, slots,
@@ -104,7 +106,7 @@ class Env:
         """The same keys under another plaintext modulus (the keys do not
         depend on t)."""
         e = object.__new__(Env)
-        e.pr = bfv.Params(self.pr.n, t, self.pr.q, self.pr.P)
+        e.pr = bfv.Params(self.pr.n, t, self.pr.q, self.pr.special)
         e.sk, e.rk = self.sk, self.rk
         return e
 
@@ -112,23 +114,24 @@ class Env:
 def uniform_galois_limbs(pr) -> dict:
     """Stand-in switching keys (uniform residues) for every element of the
     rotate-and-add sum, in the exchange format."""
-    return {g: synth.uniform_switch_key(UNIFORM_KEY_SEED + i, pr.n, pr.moduli_pq, pr.L)
+    return {g: synth.uniform_switch_key(UNIFORM_KEY_SEED + i, pr.n, pr.moduli_pq, pr.dnum)
             for i, g in enumerate(galois.sum_elements(pr.n))}
 
 
 def oracle_key(pr, limbs) -> bfv.RelinKey:
     m = pr.moduli_pq
-    return bfv.RelinKey([bfv.from_limbs(limbs[j, 0], m) for j in range(pr.L)],
-                        [bfv.from_limbs(limbs[j, 1], m) for j in range(pr.L)])
+    return bfv.RelinKey([bfv.from_limbs(limbs[j, 0], m) for j in range(pr.dnum)],
+                        [bfv.from_limbs(limbs[j, 1], m) for j in range(pr.dnum)])
 
 
 _UNIFORM_KEYS = {}
 
 
 def uniform_galois_keys(pr) -> dict:
-    if pr.n not in _UNIFORM_KEYS:
-        _UNIFORM_KEYS[pr.n] = {g: oracle_key(pr, k) for g, k in uniform_galois_limbs(pr).items()}
-    return _UNIFORM_KEYS[pr.n]
+    k = (pr.n, pr.alpha)
+    if k not in _UNIFORM_KEYS:
+        _UNIFORM_KEYS[k] = {g: oracle_key(pr, x) for g, x in uniform_galois_limbs(pr).items()}
+    return _UNIFORM_KEYS[k]
 
 
 # ------------------------------------------------------------- inputs ---
@@ -180,7 +183,7 @@ def real_rotation(E: Env):
     """Galois element of a rotation by one slot and its (real) key."""
     g = galois.rotation_element(E.pr.n, 1)
     key = galois.galois_key(E.pr, E.sk, g, synth.switch_randomness(500, E.pr.n,
-                                                                     E.pr.moduli_pq, E.pr.L))
+                                                                     E.pr.moduli_pq, E.pr.dnum))
     return g, key
 
 
@@ -301,7 +304,10 @@ def _lt_n64(E: Env) -> dict:
             "between": E.limbs(compare.between(E.pr, E.rk, cts[0], cts[2], cts[3]))}
 
 
-# case -> (log2 N of its Env, [(unit name, function)])
+A2_COLUMN_CTS = 8             # ciphertexts of each column checked with two-prime digits
+
+# case -> (log2 N of its Env, [(unit name, function)]); CASE_ALPHA gives the
+# special primes of a case's Env (1 if absent)
 CASES = {
     "eq_edges": (15, [("chain", _eq_edges)]),
     "eq_column_uniform": (15, [(f"ct{k:02d}", _column_uniform(k)) for k in range(COLUMN_CTS)]),
@@ -312,4 +318,15 @@ CASES = {
     "join": (15, [("join", _join)]),
     "lt_t17": (15, [("lt", _lt17), ("between", _between17)]),
     "lt_n64": (6, [("lt", _lt_n64)]),
+    "a2_eq_edges": (15, [("chain", _eq_edges)]),
+    "a2_eq_column_uniform": (15, [(f"ct{k:02d}", _column_uniform(k))
+                                  for k in range(A2_COLUMN_CTS)]),
+    "a2_eq_column_structured": (15, [(f"ct{k:02d}", _column_structured(k))
+                                     for k in range(A2_COLUMN_CTS)]),
+    "a2_rotations": (15, [("rotate", _rotate_real), ("sum_slots", _sum_slots)]),
+    "a2_products": (15, [("select", _select), ("extract", _extract), ("broadcast", _broadcast)]),
+    "a2_join": (15, [("join", _join)]),
+    "a2_lt_t17": (15, [("lt", _lt17), ("between", _between17)]),
+    "a2_lt_n64": (6, [("lt", _lt_n64)]),
 }
+CASE_ALPHA = {c: 2 for c in CASES if c.startswith("a2_")}

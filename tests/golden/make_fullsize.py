@@ -28,10 +28,10 @@ from tests import fullsize_cases as fc  # noqa: E402
 _ENVS = {}
 
 
-def _env(log2_n: int) -> fc.Env:
-    if log2_n not in _ENVS:
-        _ENVS[log2_n] = fc.Env(log2_n)
-    return _ENVS[log2_n]
+def _env(log2_n: int, alpha: int = 1) -> fc.Env:
+    if (log2_n, alpha) not in _ENVS:
+        _ENVS[(log2_n, alpha)] = fc.Env(log2_n, alpha=alpha)
+    return _ENVS[(log2_n, alpha)]
 
 
 def _run_unit(task):
@@ -39,7 +39,7 @@ def _run_unit(task):
     log2_n, units = fc.CASES[case]
     fn = dict(units)[unit]
     t0 = time.time()
-    out = fn(_env(log2_n))
+    out = fn(_env(log2_n, fc.CASE_ALPHA.get(case, 1)))
     rec = {label: fc.record(arr) for label, arr in out.items()}
     print(f"{case}/{unit}: {time.time() - t0:.0f} s", flush=True)
     return case, unit, rec

@@ -17,13 +17,13 @@ class Setup:
     """Oracle parameters/keys plus a device context holding the same
     relinearization key."""
 
-    def __init__(self, log2_n: int, t: int = 65537, seed: int = 0):
+    def __init__(self, log2_n: int, t: int = 65537, seed: int = 0, alpha: int = 1):
         require_gpu()
         n = 1 << log2_n
-        self.pr = bfv.paper_params(n, t)
+        self.pr = bfv.paper_params(n, t, alpha)
         self.sk, self.rk = bfv.keygen(self.pr, synth.key_randomness(seed, n, self.pr.moduli_pq,
-                                                                     self.pr.L))
-        self.ctx = Context(log2_n, t, list(self.pr.q), self.pr.P)
+                                                                     self.pr.dnum))
+        self.ctx = Context(log2_n, t, list(self.pr.q), list(self.pr.special))
         evk = torch.from_numpy(self.rk.limbs(self.pr)).to(self.ctx.device)
         self.ctx.set_relin_key(evk)
 
@@ -54,7 +54,7 @@ def galois_keys(S: Setup, seed: int = 500):
     from oracle import galois
     keys = {}
     for i, g in enumerate(galois.sum_elements(S.pr.n)):
-        rnd = synth.switch_randomness(seed + i, S.pr.n, S.pr.moduli_pq, S.pr.L)
+        rnd = synth.switch_randomness(seed + i, S.pr.n, S.pr.moduli_pq, S.pr.dnum)
         keys[g] = galois.galois_key(S.pr, S.sk, g, rnd)
         S.ctx.set_galois_key(g, torch.from_numpy(keys[g].limbs(S.pr)).to(S.ctx.device))
     return keys

@@ -115,3 +115,33 @@ def test_noalloc_scratch_is_a_global_device_symbol(tmp_path):
     assert found, "no scratch symbol in the device code"
     # (the static and the dynamic symbol tables may both list it)
     assert {(int(f[2]), f[3], f[4]) for f in found} == {(160 << 20, "OBJECT", "GLOBAL")}, found
+
+
+def _create2(log2_n=10, L=16, P1=None):
+    lib = _lib.load()
+    q, (P0, P1d) = params.modulus_chain(n_special=2)
+    q = q[:L]
+    qa = (ctypes.c_uint64 * len(q))(*q)
+    pr = _lib.NsheParams(log2_n, 65537, len(q), ctypes.cast(qa, ctypes.POINTER(ctypes.c_uint64)),
+                         P0, 2, P1d if P1 is None else P1)
+    h = ctypes.c_void_p()
+    rc = lib.nshe_ctx_create(ctypes.byref(pr), 0, ctypes.byref(h))
+    return rc, lib.nshe_last_error().decode(), h
+
+
+def test_two_special_primes_parameter_rules():
+    """alpha = 2 needs an even supported L and a valid, distinct second
+    special prime; rejected on the host before any device use."""
+    rc, err, h = _create2(L=12)
+    assert rc == -1 and "alpha = 2" in err and not h.value
+    q, P = params.modulus_chain()
+    rc, err, h = _create2(P1=q[3])
+    assert rc == -1 and "distinct" in err and not h.value
+    rc, err, h = _create2(P1=97)
+    assert rc == -1 and "[2^48, 2^49)" in err and not h.value
+
+
+def test_two_special_primes_match_the_oracle():
+    q, sp = params.modulus_chain(n_special=2)
+    oq, osp = nt.default_modulus_chain(n_special=2)
+    assert (q, sp) == (oq, osp) and len(q) == 16

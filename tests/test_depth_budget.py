@@ -127,3 +127,18 @@ def test_no_comparison_depth_without_a_fermat_prime():
     q, P = params.modulus_chain()
     assert budget(3, t=97, q=q, P=P).lt_depth == -1
     assert budget(3, t=9, q=q, P=P).lt_depth == -1
+
+
+def test_two_special_primes_budget():
+    """16 data primes (two special primes): one prime less of noise budget,
+    still room for BETWEEN (LT's 18 + 1, plus 1)."""
+    lib = _lib.load()
+    q, (P0, P1) = params.modulus_chain(n_special=2)
+    qa = (ctypes.c_uint64 * len(q))(*q)
+    pr = _lib.NsheParams(15, 65537, len(q), ctypes.cast(qa, ctypes.POINTER(ctypes.c_uint64)),
+                         P0, 2, P1)
+    b = _lib.NsheBudget()
+    _lib.check(lib.nshe_budget_of(ctypes.byref(pr), ctypes.byref(b)))
+    log2q = sum(math.log2(x) for x in q)
+    assert abs(b.fresh_bits - (log2q - math.log2(2 * 65537 * (19 + 65537)))) < 1e-9
+    assert b.depth_budget == 22 and b.depth_budget >= b.lt_depth + 2
