@@ -376,9 +376,11 @@ static int prepare_operand(nshe_ctx* c, double* ext, double* fx, int n_ct, hipSt
 
 // fx (NTT domain, operands; the first in fx_a when given, else w.fx; the
 // second in fx_b, or squaring) -> dt limbs 0..L-1 of the 3 components:
-// [round(t d_k / Q)]_Q, coefficient domain.
+// [round(t d_k / Q)]_Q, coefficient domain; the third as the
+// relinearization digit source (digit pairs with alpha = 2) unless
+// `residues` asks for its canonical residues (a three-component output).
 static int tensor_scale(nshe_ctx* c, const Ws& w, const double* fx_b, int n_ct, hipStream_t st,
-                        const double* fx_a = nullptr) {
+                        const double* fx_a = nullptr, bool residues = false) {
   Dims d = dims(c, n_ct);
   {
     // the tensor product is formed while the inverse transform loads
@@ -398,7 +400,7 @@ static int tensor_scale(nshe_ctx* c, const Ws& w, const double* fx_b, int n_ct, 
   }
   {
     Prof pf(c, K_SCALE, st, 3.0 * n_ct * c->n);
-    HIPCHK(run_scale(d, w.dt, c->tb, st));
+    HIPCHK(run_scale(d, w.dt, c->tb, st, !residues && c->alpha == 2));
   }
   return NSHE_OK;
 }
@@ -1384,7 +1386,7 @@ int nshe_multiply(nshe_ctx* c, const int64_t* a, const int64_t* b, int64_t* out3
   const size_t W = W_of(c), N = c->n;
   rc = load_two(c, w, a, b, n_ct, st);
   if (rc) return rc;
-  rc = tensor_scale(c, w, fx_second(c, w, n_ct), n_ct, st);
+  rc = tensor_scale(c, w, fx_second(c, w, n_ct), n_ct, st, nullptr, true);
   if (rc) return rc;
   HIPCHK(run_polys_to_i64(d, w.dt, 3, 3 * W * N, W * N, out3, 0, c->tb, st));
   return NSHE_OK;
@@ -2095,7 +2097,7 @@ static int lt_core(nshe_ctx* c, const int64_t* z, int64_t* out, int n_ct, const 
     }
     {
       Prof pf(c, K_SCALE, st, 3.0 * n_ct * c->n);
-      HIPCHK(run_scale(d, w.dt, c->tb, st));
+      HIPCHK(run_scale(d, w.dt, c->tb, st, c->alpha == 2));
     }
     int rc = relin_i64(c, w, n_ct, st, a.slot(s_T));
     if (rc) return rc;
@@ -2410,7 +2412,8 @@ int nshe_autotune(nshe_ctx* c, const int64_t* sample, int n_sample, int max_wave
       if (tt < tbest) { tbest = tt; best.split_forward = v; }
     }
   }
-  if (c->log2n == 15 && best.split_forward) {
+  // (the fused key switch exists for one-prime digits only)
+  if (c->log2n == 15 && best.split_forward && c->alpha == 1) {
     double tt[2];
     for (int v = 0; v < 2; ++v) {
       nshe_tuning t = best;

@@ -166,7 +166,10 @@ struct Dims {
 };
 
 hipError_t run_lift(const Dims& d, double* ext, const Tables& tb, hipStream_t st);
-hipError_t run_scale(const Dims& d, double* dt, const Tables& tb, hipStream_t st);
+// digit_pairs: write the third component as two-prime digit pairs (the
+// relinearization digit source with alpha = 2) instead of canonical residues
+hipError_t run_scale(const Dims& d, double* dt, const Tables& tb, hipStream_t st,
+                     int digit_pairs = 0);
 hipError_t run_ks_mac(const Dims& d, const double* dig, const double* evk, double* acc,
                       const Tables& tb, hipStream_t st);
 hipError_t run_moddown(const Dims& d, const double* acc, const double* dt, double* ext,

@@ -1248,7 +1248,8 @@ hipError_t run_moddown_lift(const Dims& d, const double* acc, const double* dt, 
 }
 
 
-hipError_t run_scale(const Dims& d, double* dt, const Tables& tb, hipStream_t st) {
+hipError_t run_scale(const Dims& d, double* dt, const Tables& tb, hipStream_t st,
+                     int digit_pairs) {
   const size_t np = (size_t)d.n_ct * 3;
   // the split-inverse variant's barrier needs whole blocks (see k_scale)
   if (d.fused && d.n % d.block) return hipErrorInvalidValue;
@@ -1263,7 +1264,7 @@ hipError_t run_scale(const Dims& d, double* dt, const Tables& tb, hipStream_t st
     break;
 #define C1_(L_) C_(L_, 1)
 #define C2_(L_) C_(L_, 2)
-  if (d.alpha == 1) {
+  if (!digit_pairs) {
     switch (d.L) {
       NSHE_L_CASES(C1_)
       default: return hipErrorInvalidValue;

@@ -55,6 +55,15 @@ def test_context_describes_two_prime_digits(a1k):
                                         device=S.ctx.device))
 
 
+def test_multiply_keeps_residues(a1k):
+    """A three-component product is returned as canonical residues (the
+    digit pairs are only the relinearization's internal format)."""
+    S = a1k
+    a, b = _rand_ct(S, 5, 2), _rand_ct(S, 6, 2)
+    out = S.ctx.multiply(S.to_dev(a), S.to_dev(b))
+    _same(S, out, [bfv.multiply(S.pr, x, y) for x, y in zip(a, b)])
+
+
 def test_relinearize_and_square(a1k):
     S = a1k
     a, b = _rand_ct(S, 7), _rand_ct(S, 8)
@@ -174,6 +183,10 @@ def test_full_size_chain_every_level_and_paths(s32k_a2):
     assert list(bfv.decrypt_slots(S.pr, S.sk, S.from_dev(mask)[0])) == list((x == y).astype(int))
     outs = S.ctx.eq_mask_batched([(dx, dy)], wave_ct=1, use_graph=True)
     fc.check(g, "mask", outs[0][0].cpu().numpy())
+    # a product's three components (canonical residues) relinearized on
+    # their own: the same first level
+    z0 = S.ctx.sub(dx, dy)
+    fc.check(g, "level_01", S.ctx.relinearize(S.ctx.multiply(z0, z0))[0].cpu().numpy())
     start = S.ctx.tuning()
     try:
         # the full-limb transforms and unsplit consumers at 2^15
@@ -254,3 +267,16 @@ def test_full_size_lt_between_t17(s32k_a2):
     fc.check(g, "lt", ctx.compare(dev[0], dev[1], "lt")[0].cpu().numpy())
     fc.check(g, "between", ctx.between(dev[0], dev[2], dev[3])[0].cpu().numpy())
     ctx.close()
+
+
+def test_full_size_autotune_keeps_the_two_kernel_key_switch(s32k_a2):
+    """The fused key switch exists for one-prime digits only: the autotuner
+    must not report it (it would time a path the context never takes)."""
+    S = s32k_a2
+    x = synth.uniform_device_residues((2, 2), S.ctx.q, S.ctx.n, 5, S.ctx.device)
+    start = S.ctx.tuning()
+    try:
+        tuned = S.ctx.autotune(x, max_wave_ct=2)
+        assert tuned["ks_fused"] == 0 and tuned["ms_per_ct"] > 0
+    finally:
+        S.ctx.set_tuning(**start)
