@@ -405,6 +405,52 @@ def derived_rates(ctx, prof: dict, steps: int, n_ct: int, ms: float) -> dict:
             "modmul_per_step": bfly + levels * per_level}
 
 
+def eq_setup(alpha: int, n_ct: int, ks_fused: int, dev):
+    """A paper-parameter context with alpha special primes, a uniform
+    stand-in relinearization key and a seeded uniform column pair of n_ct
+    ciphertexts (seeds 0 and 1; timing is data-oblivious)."""
+    import torch
+    import synth
+    from paper_2602_24271_amd import Context
+    ctx = Context.paper(15, alpha=alpha)
+    if ks_fused in (0, 1):
+        ctx.set_tuning(ks_fused=ks_fused)
+    log(f"context N={ctx.n} L={ctx.L}+{ctx.alpha} ext={ctx.L_ext} squarings={ctx.squarings}")
+    x = synth.uniform_device_residues((n_ct, 2), ctx.q, ctx.n, 0, dev)
+    y = synth.uniform_device_residues((n_ct, 2), ctx.q, ctx.n, 1, dev)
+    evk = synth.uniform_device_residues((ctx.dnum, 2), ctx.moduli_pq, ctx.n, 2, dev)
+    ctx.set_relin_key(evk)
+    del evk
+    out = torch.empty_like(x)
+    ctx.workspace(n_ct)
+    return ctx, x, y, out
+
+
+def eq_steps(ctx, x, y, out, steps: int, warmup: int):
+    """warmup untimed EQ steps, then `steps` timed ones (HIP events on the
+    current stream, every launch profiled): (ms per step, profile, exact-lift
+    fallbacks taken)."""
+    import torch
+    ctx.reset_margin_events()
+    for _ in range(warmup):
+        ctx.eq_mask(x, y, out)
+    torch.cuda.synchronize()
+    log("warmup done")
+    ctx.profile(True)
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(steps):
+        ctx.eq_mask(x, y, out)
+    end.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / steps
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    return ms, prof, ctx.margin_events()
+
+
 def timed(fn, reps: int) -> float:
     """Mean wall time (s) of fn() over reps calls after one untimed call,
     the device synchronised around the timed region."""
@@ -528,19 +574,21 @@ def summarize_profiles(prof_dir: str, out_dir: str) -> None:
             continue
         tl.append(f"| {name[:70]} | {grid} | {d.get('FETCH_SIZE', 0) / 1e6:.1f} | "
                   f"{d.get('WRITE_SIZE', 0) / 1e6:.1f} |")
-    # the digit transform is the NTT launch over n_ct * L * (L + 1) limbs
+    # the digit transform: the forward NTT in its digit modes (one- or
+    # two-prime digits), half-limb or full-limb
+    import re
     for (name, grid), d in per_kind.items():
-        if "ntt_fwd" in name and "1>" in name or ("ntt_fwd" in name and grid == 32 * 17 * 18 * 1024):
+        if re.search(r"k_ntt_fwd_half<[15]>|k_ntt_fwd<\d+, [15]>", name):
             traffic["ntt_digit"] = d.get("FETCH_SIZE", 0) + d.get("WRITE_SIZE", 0)
     with open(os.path.join(out_dir, "traffic.json"), "w") as fh:
         json.dump({"kernel_hash": kernel_hash(), "bytes_per_launch": traffic,
                    "calibration": {"copy_mib": mib, "factors": factors}}, fh, indent=1)
     cmd_trace = (f"rocprofv3 --kernel-trace --stats -d {prof_dir}/trace -o eq --output-format csv "
                  "-- python3 bench.py --steps 3 --warmup 1 --skip-batched --skip-cpu --skip-next "
-                 "--skip-latency --skip-probes")
+                 "--skip-latency --skip-probes --skip-other")
     cmd_pmc = (f"rocprofv3 --pmc {{C}} -d {prof_dir}/{{d}} -o eq --output-format csv -- python3 "
                "bench.py --steps 1 --warmup 0 --skip-batched --skip-cpu --skip-next --skip-latency "
-               "--skip-probes --calibrate-copy-mib 256")
+               "--skip-probes --skip-other --calibrate-copy-mib 256")
     with open(os.path.join(out_dir, "eq_mask_2p20_rows_kernels.md"), "w") as fh:
         fh.write("# EQ mask, 2^20 rows (32 ciphertexts, N=32768), per-kernel time\n\n")
         fh.write(f"Library hash: {kernel_hash()}\n\nCommand (from the repo root, "
@@ -582,9 +630,11 @@ def main() -> int:
     ap.add_argument("--skip-next", action="store_true",
                     help="skip IN / SELECT / SUM over the same column")
     ap.add_argument("--next-reps", type=int, default=2)
-    ap.add_argument("--alpha", type=int, default=1, choices=(1, 2),
-                    help="data primes per key-switching digit: 1 (17 data primes and one "
-                         "special prime) or 2 (16 data primes, two special primes)")
+    ap.add_argument("--alpha", type=int, default=2, choices=(1, 2),
+                    help="data primes per key-switching digit: 2 (16 data primes, two special "
+                         "primes; the default) or 1 (17 data primes and one special prime)")
+    ap.add_argument("--skip-other", action="store_true",
+                    help="skip timing the other key-switching decomposition")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
@@ -611,43 +661,31 @@ def main() -> int:
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    ctx = Context.paper(15, alpha=args.alpha)
-    if args.ks_fused in (0, 1):
-        ctx.set_tuning(ks_fused=args.ks_fused)
     n_ct = args.n_ct
-    log(f"context N={ctx.n} L={ctx.L} ext={ctx.L_ext} squarings={ctx.squarings}")
-    x = synth.uniform_device_residues((n_ct, 2), ctx.q, ctx.n, 0, dev)
-    y = synth.uniform_device_residues((n_ct, 2), ctx.q, ctx.n, 1, dev)
-    evk = synth.uniform_device_residues((ctx.dnum, 2), ctx.moduli_pq, ctx.n, 2, dev)
-    ctx.set_relin_key(evk)
-    del evk
-    out = torch.empty_like(x)
-    ctx.workspace(n_ct)
-    ctx.reset_margin_events()
-    for _ in range(args.warmup):
-        ctx.eq_mask(x, y, out)
-    torch.cuda.synchronize()
-    log("warmup done")
-
-    ctx.profile(True)
-    start = torch.cuda.Event(enable_timing=True)
-    end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record()
-    for _ in range(args.steps):
-        ctx.eq_mask(x, y, out)
-    end.record()
-    torch.cuda.synchronize()
-    ms = start.elapsed_time(end) / args.steps
-    prof = ctx.profile_read()
-    ctx.profile(False)
-    margin = ctx.margin_events()
+    ctx, x, y, out = eq_setup(args.alpha, n_ct, args.ks_fused, dev)
+    ms, prof, margin = eq_steps(ctx, x, y, out, args.steps, args.warmup)
     records = n_ct * ctx.n
     value = records / (ms / 1e3)
     log(f"{ms:.2f} ms/step, {value:.4g} records/s")
     roof, _ = roofline(prof, ctx)
     rates = derived_rates(ctx, prof, args.steps, n_ct, ms)
     roof_ks = roofline_ks(ctx, prof, n_ct, ctx.tuning()["ks_chunk"])
+    # the other key-switching decomposition on the same column, same steps
+    other = None
+    if not args.skip_other:
+        oa = 1 if args.alpha == 2 else 2
+        c2, x2, y2, o2 = eq_setup(oa, n_ct, -1, dev)
+        ms2, prof2, _ = eq_steps(c2, x2, y2, o2, args.steps, args.warmup)
+        other = {"special_primes": oa, "data_primes": c2.L, "key_switch_digits": c2.dnum,
+                 "ms_per_step": ms2, "records_per_s": records / (ms2 / 1e3),
+                 "roofline": roofline(prof2, c2)[0],
+                 "roofline_ks_mac": roofline_ks(c2, prof2, n_ct, c2.tuning()["ks_chunk"]),
+                 "kernels": {k: {"launches": v["launches"] // args.steps,
+                                 "ms_per_step": v["ms"] / args.steps} for k, v in prof2.items()}}
+        log(f"alpha={oa}: {ms2:.2f} ms/step, {records / (ms2 / 1e3):.4g} records/s")
+        c2.close()
+        del c2, x2, y2, o2
+        torch.cuda.empty_cache()
     # one ciphertext (32,768 rows, the paper's per-query workload): latency
     lat_ms = None
     if not args.skip_latency:
@@ -694,6 +732,7 @@ def main() -> int:
                    "key_switch_digits": ctx.dnum, "plaintext_modulus": ctx.t},
         "roofline": roof,
         "roofline_ks_mac": roof_ks,
+        "other_key_switching": other,
         "cpu_baseline": cpu,
         "rates": rates,
         "latency_1ct_ms": lat_ms,
