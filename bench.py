@@ -74,8 +74,9 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-# A two-prime digit's value in a target prime, v_0 + [q_2j]_p v_1: one exact
-# modular product (6 FP64 operations) and one addition per coefficient
+# A digit's value in a target prime from its alpha mixed-radix digits,
+# v_0 + [q_g]_p v_1 (+ [q_g q_g+1]_p v_2): alpha - 1 exact modular products
+# (6 FP64 operations each) and as many additions per coefficient
 OPS_PER_MODUP = 7
 
 
@@ -90,12 +91,12 @@ def roofline(prof: dict, ctx=None) -> tuple[dict, str]:
     st = prof[dom_ntt]
     per_launch_ops = st["work"] / st["launches"] * OPS_PER_BUTTERFLY
     modup = 0.0
-    if ctx is not None and dom_ntt == "ntt_digit" and getattr(ctx, "alpha", 1) == 2:
-        # digits of two primes: each limb transform first forms the digit's
-        # value in its prime (N coefficients, one product and one add each)
+    if ctx is not None and dom_ntt == "ntt_digit" and getattr(ctx, "alpha", 1) > 1:
+        # digits of alpha primes: each limb transform first forms the digit's
+        # value in its prime (N coefficients, alpha - 1 products and adds each)
         n = ctx.n
         limbs = st["work"] / st["launches"] / (n // 2 * (n.bit_length() - 1))
-        modup = limbs * n * OPS_PER_MODUP
+        modup = limbs * n * OPS_PER_MODUP * (ctx.alpha - 1)
         per_launch_ops += modup
     avg_s = st["ms"] / st["launches"] / 1e3
     achieved = per_launch_ops / avg_s
@@ -630,9 +631,10 @@ def main() -> int:
     ap.add_argument("--skip-next", action="store_true",
                     help="skip IN / SELECT / SUM over the same column")
     ap.add_argument("--next-reps", type=int, default=2)
-    ap.add_argument("--alpha", type=int, default=2, choices=(1, 2),
+    ap.add_argument("--alpha", type=int, default=2, choices=(1, 2, 3),
                     help="data primes per key-switching digit: 2 (16 data primes, two special "
-                         "primes; the default) or 1 (17 data primes and one special prime)")
+                         "primes; the default), 1 (17 data primes and one special prime) or 3 "
+                         "(15 data primes, three special primes)")
     ap.add_argument("--skip-other", action="store_true",
                     help="skip timing the other key-switching decomposition")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -670,22 +672,27 @@ def main() -> int:
     roof, _ = roofline(prof, ctx)
     rates = derived_rates(ctx, prof, args.steps, n_ct, ms)
     roof_ks = roofline_ks(ctx, prof, n_ct, ctx.tuning()["ks_chunk"])
-    # the other key-switching decomposition on the same column, same steps
+    # the other key-switching decompositions on the same column, same steps
     other = None
     if not args.skip_other:
-        oa = 1 if args.alpha == 2 else 2
-        c2, x2, y2, o2 = eq_setup(oa, n_ct, -1, dev)
-        ms2, prof2, _ = eq_steps(c2, x2, y2, o2, args.steps, args.warmup)
-        other = {"special_primes": oa, "data_primes": c2.L, "key_switch_digits": c2.dnum,
-                 "ms_per_step": ms2, "records_per_s": records / (ms2 / 1e3),
-                 "roofline": roofline(prof2, c2)[0],
-                 "roofline_ks_mac": roofline_ks(c2, prof2, n_ct, c2.tuning()["ks_chunk"]),
-                 "kernels": {k: {"launches": v["launches"] // args.steps,
-                                 "ms_per_step": v["ms"] / args.steps} for k, v in prof2.items()}}
-        log(f"alpha={oa}: {ms2:.2f} ms/step, {records / (ms2 / 1e3):.4g} records/s")
-        c2.close()
-        del c2, x2, y2, o2
-        torch.cuda.empty_cache()
+        other = []
+        for oa in (1, 2, 3):
+            if oa == args.alpha:
+                continue
+            c2, x2, y2, o2 = eq_setup(oa, n_ct, -1, dev)
+            ms2, prof2, _ = eq_steps(c2, x2, y2, o2, args.steps, args.warmup)
+            other.append({"special_primes": oa, "data_primes": c2.L, "key_switch_digits": c2.dnum,
+                          "depth_budget": c2.depth_budget,
+                          "ms_per_step": ms2, "records_per_s": records / (ms2 / 1e3),
+                          "roofline": roofline(prof2, c2)[0],
+                          "roofline_ks_mac": roofline_ks(c2, prof2, n_ct, c2.tuning()["ks_chunk"]),
+                          "kernels": {k: {"launches": v["launches"] // args.steps,
+                                          "ms_per_step": v["ms"] / args.steps}
+                                      for k, v in prof2.items()}})
+            log(f"alpha={oa}: {ms2:.2f} ms/step, {records / (ms2 / 1e3):.4g} records/s")
+            c2.close()
+            del c2, x2, y2, o2
+            torch.cuda.empty_cache()
     # one ciphertext (32,768 rows, the paper's per-query workload): latency
     lat_ms = None
     if not args.skip_latency:

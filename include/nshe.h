@@ -93,17 +93,18 @@ typedef struct nshe_ctx nshe_ctx;
 /* BFV parameters (Sec. 5.1: n = 32768, log Q = 881, t = 65537).
  *   log2_n  ring degree N = 2^log2_n, NSHE_MIN_LOG2N..NSHE_MAX_LOG2N;
  *   t       plaintext modulus, odd, 2 < t < 2^24, coprime to every prime;
- *   L       number of data primes: 2, 3, 4, 8, 12, 16, 17, 20 or 24 (the
+ *   L       number of data primes: 2, 3, 4, 8, 12, 15, 16, 17, 20 or 24 (the
  *           counts the base-conversion kernels are built for; the paper's
- *           parameters use 17);
+ *           18-prime modulus gives 17, 16 or 15 with 1, 2 or 3 special
+ *           primes);
  *   q_host  L distinct primes, each in [2^48, 2^49) and = 1 (mod 2N);
  *   P       the (first) special prime, same constraints, distinct from the q_i;
  *   alpha   data primes per key-switching digit = number of special primes:
  *           1 (0 reads as 1: one digit per data prime, a single special
- *           prime) or 2 (L one of 2, 4, 8 or 16; the paper's modulus budget
- *           then splits as 16 data primes and two special primes);
- *   P1      the second special prime when alpha = 2 (ignored otherwise).
- * Q = prod q_i, P = P (alpha = 1) or P P1.  The library picks its own
+ *           prime), 2 (L one of 2, 4, 8 or 16) or 3 (L one of 3, 12 or 15);
+ *   P1, P2  the second and third special primes when alpha >= 2, 3
+ *           (ignored otherwise).
+ * Q = prod q_i, P = P P1 P2 (as many as alpha).  The library picks its own
  * extension basis (primes of the same form below every q_i and special
  * prime) large enough for exact products. */
 typedef struct {
@@ -114,6 +115,7 @@ typedef struct {
   uint64_t P;
   int32_t alpha;
   uint64_t P1;
+  uint64_t P2;
 } nshe_params;
 
 /* Read-only description of a context (sizes for the caller's buffers). */

@@ -17,7 +17,7 @@ NSHE_MAX_L = 24
 class NsheParams(ctypes.Structure):
     _fields_ = [("log2_n", ctypes.c_uint32), ("t", ctypes.c_uint64), ("L", ctypes.c_int32),
                 ("q_host", ctypes.POINTER(ctypes.c_uint64)), ("P", ctypes.c_uint64),
-                ("alpha", ctypes.c_int32), ("P1", ctypes.c_uint64)]
+                ("alpha", ctypes.c_int32), ("P1", ctypes.c_uint64), ("P2", ctypes.c_uint64)]
 
 
 class NsheInfo(ctypes.Structure):

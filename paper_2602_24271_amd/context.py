@@ -26,16 +26,17 @@ class Context:
     """BFV context on one HIP device (NSHEDB Sec. 5.1 parameters by default)."""
 
     def __init__(self, log2_n: int, t: int, q, P, device: int = 0):
-        """P: the special prime, or a sequence of two special primes (key
-        switching with digits of two data primes)."""
+        """P: the special prime, or a sequence of alpha special primes (key
+        switching with digits of alpha data primes, alpha = 1, 2 or 3)."""
         lib = _lib.load()
         self.device = torch.device("cuda", device)
         special = [int(P)] if isinstance(P, int) else [int(x) for x in P]
-        if len(special) not in (1, 2):
-            raise ValueError("one or two special primes")
+        if len(special) not in (1, 2, 3):
+            raise ValueError("one, two or three special primes")
+        sp = special + [0] * (3 - len(special))
         qa = (ctypes.c_uint64 * len(q))(*q)
         pr = _lib.NsheParams(log2_n, t, len(q), ctypes.cast(qa, ctypes.POINTER(ctypes.c_uint64)),
-                             special[0], len(special), special[1] if len(special) == 2 else 0)
+                             sp[0], len(special), sp[1], sp[2])
         h = ctypes.c_void_p()
         _lib.check(lib.nshe_ctx_create(ctypes.byref(pr), device, ctypes.byref(h)))
         self._h = h
@@ -68,8 +69,9 @@ class Context:
 
     @classmethod
     def paper(cls, log2_n: int = 15, device: int = 0, alpha: int = 1) -> "Context":
-        """The paper's parameters (Sec. 5.1); alpha = 2 takes the two largest
-        of the 18 primes as special primes and 16 data primes."""
+        """The paper's parameters (Sec. 5.1); alpha = 2 or 3 takes the two or
+        three largest of the 18 primes as special primes (16 or 15 data
+        primes)."""
         from .params import paper_params
         p = paper_params(log2_n, alpha=alpha)
         return cls(p["log2_n"], p["t"], p["q"], p["P"], device)

@@ -400,7 +400,7 @@ static int tensor_scale(nshe_ctx* c, const Ws& w, const double* fx_b, int n_ct, 
   }
   {
     Prof pf(c, K_SCALE, st, 3.0 * n_ct * c->n);
-    HIPCHK(run_scale(d, w.dt, c->tb, st, !residues && c->alpha == 2));
+    HIPCHK(run_scale(d, w.dt, c->tb, st, !residues && c->alpha > 1));
   }
   return NSHE_OK;
 }
@@ -567,24 +567,27 @@ static int check_params(const nshe_params* pr, std::vector<u64>* q_out) {
   if (pr->L < 1 || pr->L > NSHE_MAX_L) return fail(NSHE_EINVAL, "L out of range");
   {
     // the base-conversion kernels are instantiated for these prime counts
-    static const int kSupportedL[] = {2, 3, 4, 8, 12, 16, 17, 20, 24};
+    static const int kSupportedL[] = {2, 3, 4, 8, 12, 15, 16, 17, 20, 24};
     bool ok = false;
     for (int v : kSupportedL) ok = ok || v == pr->L;
-    if (!ok) return fail(NSHE_EINVAL, "L must be one of 2, 3, 4, 8, 12, 16, 17, 20, 24");
+    if (!ok) return fail(NSHE_EINVAL, "L must be one of 2, 3, 4, 8, 12, 15, 16, 17, 20, 24");
   }
   if (!pr->q_host) return fail(NSHE_EINVAL, "q_host is null");
   if (pr->t < 3 || (pr->t & 1) == 0 || pr->t >= (1u << 24))
     return fail(NSHE_EINVAL, "t must be odd, 3 <= t < 2^24");
   const int alpha = pr->alpha == 0 ? 1 : pr->alpha;
-  if (alpha != 1 && alpha != 2) return fail(NSHE_EINVAL, "alpha must be 1 or 2");
+  if (alpha < 1 || alpha > 3) return fail(NSHE_EINVAL, "alpha must be 1, 2 or 3");
   if (alpha == 2 && pr->L != 2 && pr->L != 4 && pr->L != 8 && pr->L != 16)
     return fail(NSHE_EINVAL, "with alpha = 2, L must be one of 2, 4, 8, 16");
+  if (alpha == 3 && pr->L != 3 && pr->L != 12 && pr->L != 15)
+    return fail(NSHE_EINVAL, "with alpha = 3, L must be one of 3, 12, 15");
   const int n = 1 << pr->log2_n;
   const u64 lo = 1ull << 48, hi = 1ull << 49;
   std::vector<u64> q(pr->q_host, pr->q_host + pr->L);
   std::vector<u64> qp = q;
   qp.push_back(pr->P);
-  if (alpha == 2) qp.push_back(pr->P1);
+  if (alpha >= 2) qp.push_back(pr->P1);
+  if (alpha >= 3) qp.push_back(pr->P2);
   for (size_t i = 0; i < qp.size(); ++i) {
     const u64 x = qp[i];
     if (x < lo || x >= hi) return fail(NSHE_EINVAL, "every prime must lie in [2^48, 2^49)");
@@ -763,7 +766,8 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
   const u64 lo = 1ull << 48;
   const int alpha = pr->alpha == 0 ? 1 : pr->alpha;
   std::vector<u64> sp{pr->P};
-  if (alpha == 2) sp.push_back(pr->P1);
+  if (alpha >= 2) sp.push_back(pr->P1);
+  if (alpha >= 3) sp.push_back(pr->P2);
   std::vector<u64> qp = q;
   qp.insert(qp.end(), sp.begin(), sp.end());
   // --- extension basis: L + 1 largest primes = 1 mod 2^16 below every q_i and P_k
@@ -948,22 +952,32 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
   // t_qhinv, t_q, c1: a second row times the inverse's last-stage twiddle
   std::vector<double> q_hat_inv(L), Q_b(LB), t_qhinv(2 * L), t_q(2 * L),
       c1(2 * LB), b_hat_inv(LB), B_q(L), P_inv_q(L), NP_inv_q(2 * L), ninv_P(2 * alpha),
-      P1_inv_q(L, 0.0), delta_q(L), mrc_inv((size_t)L * L, 0.0), mrc_half(L),
-      dig_q0((size_t)(L / alpha) * (L + alpha), 0.0);
+      mr_q((size_t)std::max(alpha - 1, 1) * L, 0.0), delta_q(L), mrc_inv((size_t)L * L, 0.0),
+      mrc_half(L), dig_c((size_t)(L / alpha) * (L + alpha) * std::max(alpha - 1, 1), 0.0);
   for (int k = 0; k < alpha; ++k) {
     const u64 Pp = sp[k], nP = invmod((u64)n % Pp, Pp);
     ninv_P[2 * k] = bal(nP, Pp);
     ninv_P[2 * k + 1] = bal(mulmod(nP, w_last[2 * L + 1 + k], Pp), Pp);
   }
-  // two primes per digit: [P_0^-1]_{P_1}, and digit j's first prime q_{2j}
-  // modulo every prime of the key-switching basis
-  double p0_inv_p1 = 0.0;
-  if (alpha == 2) {
-    p0_inv_p1 = bal(invmod(sp[0] % sp[1], sp[1]), sp[1]);
-    for (int j = 0; j < L / 2; ++j)
-      for (int i = 0; i < L + 2; ++i) {
+  // alpha primes per digit: the special primes' Garner inverses
+  // [P_0^-1]_{P_1}, [P_0^-1]_{P_2}, [P_1^-1]_{P_2}, and the mixed-radix
+  // weights of digit j (first prime g = j alpha) modulo every prime of the
+  // key-switching basis: [q_g]_{p_i}, [q_g q_{g+1}]_{p_i}
+  double p_inv_p[3] = {0.0, 0.0, 0.0};
+  if (alpha >= 2) p_inv_p[0] = bal(invmod(sp[0] % sp[1], sp[1]), sp[1]);
+  if (alpha >= 3) {
+    p_inv_p[1] = bal(invmod(sp[0] % sp[2], sp[2]), sp[2]);
+    p_inv_p[2] = bal(invmod(sp[1] % sp[2], sp[2]), sp[2]);
+  }
+  if (alpha >= 2) {
+    for (int j = 0; j < L / alpha; ++j)
+      for (int i = 0; i < L + alpha; ++i) {
         const u64 m = i < L ? q[i] : sp[i - L];
-        dig_q0[(size_t)j * (L + 2) + i] = bal(q[2 * j] % m, m);
+        u64 w = 1;
+        for (int k = 0; k + 1 < alpha; ++k) {
+          w = mulmod(w, q[j * alpha + k] % m, m);
+          dig_c[((size_t)j * (L + alpha) + i) * (alpha - 1) + k] = bal(w, m);
+        }
       }
   }
   u64 Qmodt = 1;
@@ -984,7 +998,14 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
     u64 Pq = 1;
     for (u64 x : sp) Pq = mulmod(Pq, x % qi, qi);
     P_inv_q[i] = bal(invmod(Pq, qi), qi);
-    if (alpha == 2) P1_inv_q[i] = bal(invmod(sp[1] % qi, qi), qi);
+    // [(P_0 ... P_{k-1}) P^-1]_{q_i} for k = 1..alpha-1
+    {
+      u64 pre = 1;
+      for (int k = 1; k < alpha; ++k) {
+        pre = mulmod(pre, sp[k - 1] % qi, qi);
+        mr_q[(size_t)(k - 1) * L + i] = bal(mulmod(pre, invmod(Pq, qi), qi), qi);
+      }
+    }
     const u64 npq = mulmod(invmod(Pq, qi), ninv_q, qi);
     NP_inv_q[i] = bal(npq, qi);
     NP_inv_q[L + i] = bal(mulmod(npq, w_last[i], qi), qi);
@@ -1030,7 +1051,7 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
       {&t_qhinv, &c->tb.t_qhinv}, {&t_q, &c->tb.t_q},         {&c1, &c->tb.c1},
       {&b_hat_inv, &c->tb.b_hat_inv},
       {&B_q, &c->tb.B_q},         {&P_inv_q, &c->tb.P_inv_q}, {&NP_inv_q, &c->tb.NP_inv_q},
-      {&ninv_P, &c->tb.ninv_P},   {&P1_inv_q, &c->tb.P1_inv_q}, {&dig_q0, &c->tb.dig_q0},
+      {&ninv_P, &c->tb.ninv_P},   {&mr_q, &c->tb.mr_q},       {&dig_c, &c->tb.dig_c},
       {&delta_q, &c->tb.delta_q},
       {&mrc_inv, &c->tb.mrc_inv}, {&mrc_half, &c->tb.mrc_half}, {&tw_h, &c->tb.tw_half},
       {&tw_h0, &c->tb.tw_half0},  {&tw_cf, &c->tb.tw_cmp_f},  {&tw_ci, &c->tb.tw_cmp_i},
@@ -1101,7 +1122,7 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
   c->tb.bad_input = reinterpret_cast<int*>(base + off_counters + 128);
   c->tb.lift_edge = kLiftEdge;
   c->tb.ks_alpha = alpha;
-  c->tb.p0_inv_p1 = p0_inv_p1;
+  for (int k = 0; k < 3; ++k) c->tb.p_inv_p[k] = p_inv_p[k];
   if (e == hipSuccess) e = hipMemset(base + off_counters, 0, 256);
   std::vector<int> lp;
   for (int i = 0; i < W_of(c); ++i) lp.push_back(i);
@@ -1404,7 +1425,7 @@ int nshe_relinearize(nshe_ctx* c, const int64_t* in3, int64_t* out, int n_ct, vo
   Dims d = dims(c, n_ct);
   const size_t W = W_of(c), N = c->n;
   HIPCHK(run_i64_to_polys(d, in3, 3, w.dt, 3 * W * N, W * N, 2, c->tb, st));
-  if (c->alpha == 2) HIPCHK(run_digit_mrc(d, w.dt, c->tb, st));
+  if (c->alpha > 1) HIPCHK(run_digit_mrc(d, w.dt, c->tb, st));
   rc = relin(c, w, n_ct, st);
   if (rc) return rc;
   HIPCHK(run_polys_to_i64(d, w.ext, 2, 2 * W * N, W * N, out, 0, c->tb, st));
@@ -1688,7 +1709,7 @@ static int rotate_ext(nshe_ctx* c, const Ws& w, int n_ct, uint32_t g, const doub
   {
     Prof pf(c, K_AUTOMORPH, st, 2.0 * n_ct * c->L * c->n);
     HIPCHK(run_automorph(d, inv_mod_2n(c, g), w.ext, w.dt, c->tb, st));
-    if (c->alpha == 2) HIPCHK(run_digit_mrc(d, w.dt, c->tb, st));
+    if (c->alpha > 1) HIPCHK(run_digit_mrc(d, w.dt, c->tb, st));
   }
   return relin(c, w, n_ct, st, key, out, false, nullptr, nullptr, accumulate);
 }
@@ -2097,7 +2118,7 @@ static int lt_core(nshe_ctx* c, const int64_t* z, int64_t* out, int n_ct, const 
     }
     {
       Prof pf(c, K_SCALE, st, 3.0 * n_ct * c->n);
-      HIPCHK(run_scale(d, w.dt, c->tb, st, c->alpha == 2));
+      HIPCHK(run_scale(d, w.dt, c->tb, st, c->alpha > 1));
     }
     int rc = relin_i64(c, w, n_ct, st, a.slot(s_T));
     if (rc) return rc;

@@ -9,7 +9,7 @@
 namespace nshe {
 
 constexpr int MAX_L = 24;            // data primes
-constexpr int MAX_ALPHA = 2;         // special primes (data primes per key-switching digit)
+constexpr int MAX_ALPHA = 3;         // special primes (data primes per key-switching digit)
 constexpr int MAX_PRIMES = 2 * MAX_L + 1 + MAX_ALPHA;
 
 // Device constant tables of a context (all pointers are device memory).
@@ -85,14 +85,16 @@ struct Tables {
   double lift_edge;
   // residues outside [0, q_i) seen by the input check (debug switch)
   int* bad_input;
-  int ks_alpha;              // alpha: 1 or 2
-  // alpha = 2: the centred residue mod P = P_0 P_1 in mixed radix,
-  // a_0 + P_0 k with k = [(a_1 - a_0) P_0^-1]_{P_1} (both digits balanced)
-  const double* P1_inv_q;    // [L]      [P_1^-1]_{q_i} (= [P_0 P^-1]_{q_i})
-  double p0_inv_p1;          //          [P_0^-1]_{P_1}, balanced
-  // alpha = 2: a digit's value mod target prime i of the key-switching
-  // basis from its mixed-radix digits (v_0, v_1): v_0 + [q_{2j}]_{p_i} v_1
-  const double* dig_q0;      // [dnum][L + alpha] [q_{2j}]_{p_i}, balanced
+  int ks_alpha;              // alpha: 1, 2 or 3
+  // alpha > 1: the centred residue mod P = P_0 ... P_{alpha-1} in mixed
+  // radix, a_0 + P_0 k_1 + P_0 P_1 k_2 with balanced digits (Garner:
+  // k_1 = [(a_1 - a_0) P_0^-1]_{P_1}, k_2 = [((a_2 - a_0) P_0^-1 - k_1) P_1^-1]_{P_2})
+  const double* mr_q;        // [alpha-1][L] [(P_0 ... P_{k-1}) P^-1]_{q_i}, k = 1..alpha-1
+  double p_inv_p[3];         //          [P_0^-1]_{P_1}, [P_0^-1]_{P_2}, [P_1^-1]_{P_2}, balanced
+  // alpha > 1: a digit's value mod target prime i of the key-switching
+  // basis from its canonical mixed-radix digits (v_0, ..., v_{alpha-1}):
+  // v_0 + [q_{j alpha}]_{p_i} v_1 + [q_{j alpha} q_{j alpha + 1}]_{p_i} v_2
+  const double* dig_c;       // [dnum][L + alpha][alpha - 1], balanced
 };
 
 // Call sites of the exact-lift fallback (index into Tables::margin).
@@ -109,7 +111,7 @@ enum MarginSite {
 };
 
 enum { NTT_INPLACE = 0, NTT_DIGIT = 1, INV_TENSOR = 2, INV_TENSOR2 = 3, INV_PLAIN = 4,
-       NTT_DIGIT2 = 5 };
+       NTT_DIGIT2 = 5, NTT_DIGIT3 = 6 };
 
 struct NttJob {
   double* base;              // first limb of poly 0 (input of in-place kinds)
@@ -120,9 +122,10 @@ struct NttJob {
   const int* limb_prime;     // [nlimb] prime index of each limb
   int count;                 // npoly * nlimb
   // NTT_DIGIT source: third component's data limbs, canonical residues in
-  // [0, q_j) (the digits themselves); with two primes per digit, limbs 2j
-  // and 2j + 1 hold digit j's canonical mixed-radix digits (v_0, v_1),
-  // D_j = v_0 + q_{2j} v_1 in [0, q_{2j} q_{2j+1}); INV_TENSOR: the
+  // [0, q_j) (the digits themselves); with alpha primes per digit, limbs
+  // j alpha .. j alpha + alpha - 1 hold digit j's canonical mixed-radix
+  // digits (v_0, v_1[, v_2]), D_j = v_0 + q_{j alpha} v_1 (+ q_{j alpha}
+  // q_{j alpha + 1} v_2) in [0, Q_j) (NTT_DIGIT2, NTT_DIGIT3); INV_TENSOR: the
   // operands' transforms ([ct][2][W][N], src_b null when squaring)
   const double* src;
   const double* src_b;
@@ -166,8 +169,9 @@ struct Dims {
 };
 
 hipError_t run_lift(const Dims& d, double* ext, const Tables& tb, hipStream_t st);
-// digit_pairs: write the third component as two-prime digit pairs (the
-// relinearization digit source with alpha = 2) instead of canonical residues
+// digit_pairs: write the third component as the digits' mixed-radix digits
+// (the relinearization digit source with alpha > 1) instead of canonical
+// residues
 hipError_t run_scale(const Dims& d, double* dt, const Tables& tb, hipStream_t st,
                      int digit_pairs = 0);
 hipError_t run_ks_mac(const Dims& d, const double* dig, const double* evk, double* acc,
@@ -218,8 +222,9 @@ hipError_t run_diff_i64(const Dims& d, const int64_t* x, const int64_t* y, int y
 // rotations: automorphism of ext into dt's key-switching layout
 hipError_t run_automorph(const Dims& d, unsigned ginv, const double* ext, double* dt,
                          const Tables& tb, hipStream_t st);
-// two primes per digit: canonical residues of the digit source (dt's third
-// component, limbs 0..L-1) into mixed-radix digit pairs, in place
+// alpha primes per digit (alpha > 1): canonical residues of the digit
+// source (dt's third component, limbs 0..L-1) into each digit's canonical
+// mixed-radix digits, in place
 hipError_t run_digit_mrc(const Dims& d, double* dt, const Tables& tb, hipStream_t st);
 // p[0..words) = v, as a kernel (no memset node in a captured graph)
 hipError_t run_fill_u64(void* p, size_t words, uint64_t v, hipStream_t st);

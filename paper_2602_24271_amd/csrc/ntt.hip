@@ -385,6 +385,9 @@ constexpr double ct_bound(double b, int stages) {
 // digit's value is formed on load as v_0 + [q_{2j}]_p v_1 from canonical
 // mixed-radix digits below 1.93 p (all primes in [2^48, 2^48.95)), so below
 // (1.93 + 0.5 + 0.094 x 1.93) p < 2.61 p.
+// A three-prime digit's value v_0 + [q_g]_p v_1 + [q_g q_{g+1}]_p v_2 is below
+// (1.93 + 2 x 0.68) p < 3.3 p, too large for ten stages: it is reduced to
+// balanced form (below p/2) before the transform.
 constexpr double DIGIT_IN = 2.0, DIGIT2_IN = 2.61;
 static_assert(ct_bound(DIGIT_IN, FWD_STAGES_PER_REDUCTION) < 13.5, "one-prime digit bound");
 static_assert(ct_bound(DIGIT2_IN, FWD_STAGES_PER_REDUCTION) < 15.1, "two-prime digit bound");
@@ -613,7 +616,7 @@ k_ntt_fwd(NttJob job, Tables tb) {
   using S = NttShape<LOGN>;
   __shared__ uint32_t lds[S::LDS_WORDS];
   int limb, poly;
-  if (MODE == NTT_DIGIT || MODE == NTT_DIGIT2) {
+  if (MODE == NTT_DIGIT || MODE == NTT_DIGIT2 || MODE == NTT_DIGIT3) {
     // The digit transforms read one source limb per (ciphertext, digit) for
     // all L + alpha target primes.  Split the (source x prime) grid into 8
     // blocks, one per XCD: two halves of the primes x four quarters of the
@@ -668,11 +671,30 @@ k_ntt_fwd(NttJob job, Tables tb) {
     const double* s0 = job.src + (size_t)ct * job.src_ct_stride + (size_t)(2 * j) * S::N;
     const auto rs0 = make_rsrc(s0, S::N * 8);
     const auto rs1 = make_rsrc(s0 + S::N, S::N * 8);
-    const double cq = cld(tb.dig_q0, j * job.nlimb + limb);
+    const double cq = cld(tb.dig_c, j * job.nlimb + limb);
 #pragma unroll
     for (int i = 0; i < S::E; ++i) {
       const int e = brv_c(i, S::LOGE);
       x[e] = buf_load(rs0, vo, e * S::T * 8) + mul_lazy(buf_load(rs1, vo, e * S::T * 8), cq, p, pinv);
+    }
+  } else if constexpr (MODE == NTT_DIGIT3) {
+    // Three primes per digit: limbs 3j .. 3j + 2 hold (v_0, v_1, v_2); the
+    // value in the target prime, reduced to balanced form (DIGIT_IN above).
+    const int ct = poly / job.digits;
+    const int j = poly - ct * job.digits;
+    const double* s0 = job.src + (size_t)ct * job.src_ct_stride + (size_t)(3 * j) * S::N;
+    const auto rs0 = make_rsrc(s0, S::N * 8);
+    const auto rs1 = make_rsrc(s0 + S::N, S::N * 8);
+    const auto rs2 = make_rsrc(s0 + 2 * S::N, S::N * 8);
+    const double c1 = cld(tb.dig_c, (j * job.nlimb + limb) * 2);
+    const double c2 = cld(tb.dig_c, (j * job.nlimb + limb) * 2 + 1);
+#pragma unroll
+    for (int i = 0; i < S::E; ++i) {
+      const int e = brv_c(i, S::LOGE);
+      const unsigned o = e * S::T * 8;
+      x[e] = reduce_bal(buf_load(rs0, vo, o) + mul_lazy(buf_load(rs1, vo, o), c1, p, pinv) +
+                            mul_lazy(buf_load(rs2, vo, o), c2, p, pinv),
+                        p, pinv);
     }
   } else {
     // loads in bit-reversed element order: the first stage pairs e with
@@ -688,7 +710,8 @@ k_ntt_fwd(NttJob job, Tables tb) {
     if (r > 0) exchange<LOGN>(x, r - 1, r, lds, r > 1);
     fwd_round<LOGN>(x, r,
                     fwd_reduces_after<LOGN>(r, 0) &&
-                        !((MODE == NTT_DIGIT || MODE == NTT_DIGIT2) && r == S::ROUNDS - 1),
+                        !((MODE == NTT_DIGIT || MODE == NTT_DIGIT2 || MODE == NTT_DIGIT3) &&
+                          r == S::ROUNDS - 1),
                     tw, p, pinv);
   }
 #pragma unroll
@@ -851,7 +874,7 @@ k_ntt_fwd_half(NttJob job, Tables tb) {
   __shared__ uint32_t lds[S::LDS_WORDS];
   __shared__ double ltw[R1 * LDS_ROW];
   int limb, poly, h;
-  if (MODE == NTT_DIGIT || MODE == NTT_DIGIT2) {
+  if (MODE == NTT_DIGIT || MODE == NTT_DIGIT2 || MODE == NTT_DIGIT3) {
     const int x = blockIdx.x & 7, l2 = blockIdx.x >> 3;
     h = l2 & 1;
     const int l = l2 >> 1;
@@ -904,7 +927,7 @@ k_ntt_fwd_half(NttJob job, Tables tb) {
     const double* s0 = job.src + (size_t)ct * job.src_ct_stride + (size_t)(2 * j) * NF;
     const auto rs0 = make_rsrc(s0, NF * 8);
     const auto rs1 = make_rsrc(s0 + NF, NF * 8);
-    const double cq = cld(tb.dig_q0, j * job.nlimb + limb);
+    const double cq = cld(tb.dig_c, j * job.nlimb + limb);
     constexpr int G = 4;
     double ax[2][G], bx[2][G], ay[2][G], by[2][G];
 #pragma unroll
@@ -934,6 +957,57 @@ k_ntt_fwd_half(NttJob job, Tables tb) {
         const double X = ax[slot][i] + mul_lazy(bx[slot][i], cq, p, pinv);
         const double Y = ay[slot][i] + mul_lazy(by[slot][i], cq, p, pinv);
         x[g + i] = X + mul_lazy(Y, w0, p, pinv);
+      }
+    }
+  } else if constexpr (MODE == NTT_DIGIT3) {
+    // three primes per digit: both stage-0 operands' values formed as they
+    // load (k_ntt_fwd), then the stage-0 output reduced to balanced form
+    // (the operands are below 3.3 p, the output below 4.2 p); loads in
+    // groups of 2, pipelined as below (six loads per element)
+    const int ct = poly / job.digits;
+    const int j = poly - ct * job.digits;
+    const double* s0 = job.src + (size_t)ct * job.src_ct_stride + (size_t)(3 * j) * NF;
+    const auto rs0 = make_rsrc(s0, NF * 8);
+    const auto rs1 = make_rsrc(s0 + NF, NF * 8);
+    const auto rs2 = make_rsrc(s0 + 2 * NF, NF * 8);
+    const double c1 = cld(tb.dig_c, (j * job.nlimb + limb) * 2);
+    const double c2 = cld(tb.dig_c, (j * job.nlimb + limb) * 2 + 1);
+    constexpr int G = 2;
+    double ax[2][G], bx[2][G], cx[2][G], ay[2][G], by[2][G], cy[2][G];
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+      const unsigned ox = i * S::T * 8, oy = (i * S::T + (NF >> 1)) * 8;
+      ax[0][i] = buf_load(rs0, vo, ox);
+      bx[0][i] = buf_load(rs1, vo, ox);
+      cx[0][i] = buf_load(rs2, vo, ox);
+      ay[0][i] = buf_load(rs0, vo, oy);
+      by[0][i] = buf_load(rs1, vo, oy);
+      cy[0][i] = buf_load(rs2, vo, oy);
+    }
+#pragma unroll
+    for (int g = 0; g < S::E; g += G) {
+      const int slot = (g / G) & 1;
+      if (g + G < S::E) {
+        unsigned v = vo;
+        if (g) asm volatile("" : "+v"(v) : "v"(x[g - 1]));
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+          const unsigned ox = (g + G + i) * S::T * 8, oy = ((g + G + i) * S::T + (NF >> 1)) * 8;
+          ax[slot ^ 1][i] = buf_load(rs0, v, ox);
+          bx[slot ^ 1][i] = buf_load(rs1, v, ox);
+          cx[slot ^ 1][i] = buf_load(rs2, v, ox);
+          ay[slot ^ 1][i] = buf_load(rs0, v, oy);
+          by[slot ^ 1][i] = buf_load(rs1, v, oy);
+          cy[slot ^ 1][i] = buf_load(rs2, v, oy);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < G; ++i) {
+        const double X = ax[slot][i] + mul_lazy(bx[slot][i], c1, p, pinv) +
+                         mul_lazy(cx[slot][i], c2, p, pinv);
+        const double Y = ay[slot][i] + mul_lazy(by[slot][i], c1, p, pinv) +
+                         mul_lazy(cy[slot][i], c2, p, pinv);
+        x[g + i] = reduce_bal(X + mul_lazy(Y, w0, p, pinv), p, pinv);
       }
     }
   } else {
@@ -988,7 +1062,8 @@ k_ntt_fwd_half(NttJob job, Tables tb) {
     // their only reader, the key-switch product, reduces its sums itself
     fwd_round<14, true>(x, r,
                         fwd_reduces_after<14>(r, 1) && r != HALF_REDUCE_ROUND - 1 &&
-                            !((MODE == NTT_DIGIT || MODE == NTT_DIGIT2) && r == S::ROUNDS - 1),
+                            !((MODE == NTT_DIGIT || MODE == NTT_DIGIT2 || MODE == NTT_DIGIT3) &&
+                              r == S::ROUNDS - 1),
                         tw, p, pinv, ltw, r == HALF_REDUCE_ROUND);
   }
   const unsigned so = (h * S::T + tid) * 8;
@@ -1240,6 +1315,8 @@ static hipError_t launch_ntt(const NttJob& job, const Tables& tb, int dir, hipSt
         hipLaunchKernelGGL((k_ntt_fwd_half<NTT_INPLACE>), grid, block, 0, st, job, tb);
       else if (job.alpha == 2)
         hipLaunchKernelGGL((k_ntt_fwd_half<NTT_DIGIT2>), grid, block, 0, st, job, tb);
+      else if (job.alpha == 3)
+        hipLaunchKernelGGL((k_ntt_fwd_half<NTT_DIGIT3>), grid, block, 0, st, job, tb);
       else
         hipLaunchKernelGGL((k_ntt_fwd_half<NTT_DIGIT>), grid, block, 0, st, job, tb);
       return hipGetLastError();
@@ -1258,6 +1335,8 @@ static hipError_t launch_ntt(const NttJob& job, const Tables& tb, int dir, hipSt
     hipLaunchKernelGGL((k_ntt_inv<LOGN, NTT_INPLACE>), grid, block, 0, st, job, tb);
   else if (dir == 2 && job.alpha == 2)
     hipLaunchKernelGGL((k_ntt_fwd<LOGN, NTT_DIGIT2>), grid, block, 0, st, job, tb);
+  else if (dir == 2 && job.alpha == 3)
+    hipLaunchKernelGGL((k_ntt_fwd<LOGN, NTT_DIGIT3>), grid, block, 0, st, job, tb);
   else if (dir == 2)
     hipLaunchKernelGGL((k_ntt_fwd<LOGN, NTT_DIGIT>), grid, block, 0, st, job, tb);
   else if (job.src_b == nullptr)

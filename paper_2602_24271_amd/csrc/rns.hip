@@ -304,8 +304,10 @@ __global__ void __launch_bounds__(256) k_scale(int n, size_t n_poly, double* dt,
   double wh[LB], wl[LB];
 #pragma unroll
   for (int k = 0; k < LB; ++k) split24(wp[k * bs], wh[k], wl[k]);
-  const bool pairs = A == 2 && third;
-  double prev = 0.0;
+  const bool pairs = A > 1 && third;
+  double grp[A];   // the current digit group's canonical mixed-radix digits
+#pragma unroll
+  for (int k = 0; k < A; ++k) grp[k] = 0.0;
 #pragma unroll
   for (int i = 0; i < L; ++i) {
     const int iq = opaque_idx(i);
@@ -315,14 +317,21 @@ __global__ void __launch_bounds__(256) k_scale(int n, size_t n_poly, double* dt,
                        v2 * cld(tb.B_q, iq);
     const double r = reduce_bal(acc, q, qinv);
     // the third component is only read as relinearization digits: its
-    // canonical residues, or with two primes per digit the digit pairs'
-    // canonical mixed-radix digits (limb 2j + 1 gets
-    // [(d_{2j+1} - d_{2j}) q_{2j}^-1]_{q_{2j+1}}; |d_{2j+1} - d_{2j}| < 2^49)
+    // canonical residues, or with A primes per digit each digit's canonical
+    // mixed-radix digits (Garner: limb g + m of the group starting at g gets
+    // v_m = t_m, t_0 = d_{g+m}, t_{k+1} = [(t_k - v_k) q_{g+k}^-1]_{q_{g+m}};
+    // every difference is below 2^49 < 2 q)
     double o = third ? to_canonical(r, q) : r;
-    if constexpr (A == 2) {
-      if (pairs && (i & 1))
-        o = to_canonical(mul_bal(o - prev, cld(tb.mrc_inv, (iq - 1) * L + iq), q, qinv), q);
-      prev = o;
+    if constexpr (A > 1) {
+      const int m = i % A;
+      if (pairs && m > 0) {
+        double tt = o;
+#pragma unroll
+        for (int k = 0; k < m; ++k)
+          tt = mul_bal(tt - grp[k], cld(tb.mrc_inv, (iq - m + k) * L + iq), q, qinv);
+        o = to_canonical(tt, q);
+      }
+      grp[m] = o;
     }
     buf_store(o, rs, vo, i * ls);
   }
@@ -402,31 +411,39 @@ __device__ __forceinline__ void special_pair(const double* a, int ht, int ip, do
   hi = mul_bal(mul_lazy(u - v, cld(tb.tw_inv, ip * tb.tw_len + 1), pk, pkinv), ninvk, pk, pkinv);
 }
 
-// The centred residue r = [x]_P of a key-switch sum, P = P_0 ... P_{A-1}, in
-// mixed radix r = a_0 + P_0 k from its (balanced) residues a_0 mod P_0 and,
-// for A = 2, a_1 mod P_1: k = [(a_1 - a_0) P_0^-1]_{P_1} balanced
-// (|a_1 - a_0| < 2 P_1).  With both digits balanced,
-// |r| <= (P_0 - 1)/2 + P_0 (P_1 - 1)/2 = (P - 1)/2: r is exactly the
-// centred residue, with no comparison.  (k = 0 for A = 1.)
+// The centred residue r = [x]_P of a key-switch sum, P = P_0 ... P_{A-1},
+// in mixed radix r = k_0 + P_0 k_1 + P_0 P_1 k_2 from its balanced residues
+// a_m mod P_m (Garner, every digit balanced): k_0 = a_0,
+// k_1 = [(a_1 - a_0) P_0^-1]_{P_1}, k_2 = [((a_2 - a_0) P_0^-1 - k_1) P_1^-1]_{P_2}
+// (each difference below 2 P_m: all primes lie in [2^48, 2^49)).  With
+// balanced digits |r| <= sum_m (P_m - 1)/2 prod_{l<m} P_l = (P - 1)/2: r is
+// exactly the centred residue, with no comparison.
 template <int A>
-__device__ __forceinline__ double special_k(double a0, double a1, const Tables& tb, int L) {
-  if constexpr (A == 1) {
-    return 0.0;
-  } else {
+__device__ __forceinline__ void special_digits(const double (&a)[A], double (&k)[A],
+                                               const Tables& tb, int L) {
+  k[0] = a[0];
+  if constexpr (A >= 2) {
     const int ip1 = 2 * L + 2;
-    return mul_bal(a1 - a0, tb.p0_inv_p1, cld(tb.p, ip1), cld(tb.pinv, ip1));
+    k[1] = mul_bal(a[1] - a[0], tb.p_inv_p[0], cld(tb.p, ip1), cld(tb.pinv, ip1));
+  }
+  if constexpr (A >= 3) {
+    const int ip2 = 2 * L + 3;
+    const double p2 = cld(tb.p, ip2), p2inv = cld(tb.pinv, ip2);
+    const double t = mul_bal(a[2] - a[0], tb.p_inv_p[1], p2, p2inv);
+    k[2] = mul_bal(t - k[1], tb.p_inv_p[2], p2, p2inv);
   }
 }
 
 // (x - r) P^-1 mod q_i up to the factor N^-1 folded into npq: x times
-// [N^-1 P^-1]_{q_i} minus r's digits times [P^-1]_{q_i} and [P_1^-1]_{q_i}
-// (= [P_0 P^-1]_{q_i}).  Each lazy product is below 0.9 q_i (operands
-// below 2 q_i), so the result is below 2.7 q_i.
-template <int A>
-__device__ __forceinline__ double moddown_term(double x, double npq, double a0, double k, int i,
+// [N^-1 P^-1]_{q_i} minus r's mixed-radix digits k_m times
+// [(P_0 ... P_{m-1}) P^-1]_{q_i}.  Each lazy product is below 0.9 q_i
+// (operands below 2 q_i), so the result is below 3.6 q_i.
+template <int L, int A>
+__device__ __forceinline__ double moddown_term(double x, double npq, const double (&k)[A], int i,
                                                double q, double qinv, const Tables& tb) {
-  double r = mul_lazy(x, npq, q, qinv) - mul_lazy(a0, cld(tb.P_inv_q, i), q, qinv);
-  if constexpr (A == 2) r -= mul_lazy(k, cld(tb.P1_inv_q, i), q, qinv);
+  double r = mul_lazy(x, npq, q, qinv) - mul_lazy(k[0], cld(tb.P_inv_q, i), q, qinv);
+#pragma unroll
+  for (int m = 1; m < A; ++m) r -= mul_lazy(k[m], cld(tb.mr_q, (m - 1) * L + i), q, qinv);
   return r;
 }
 
@@ -452,24 +469,22 @@ __global__ void __launch_bounds__(256) k_moddown(int n, int n_ct, const double* 
   const size_t ct = cb >> 1;
   const int b = (int)(cb & 1);
   const int ip = 2 * L + 1;
-  const double pP = cld(tb.p, ip), pPinv = cld(tb.pinv, ip);
   const double* e = dt + ((ct * 3 + b) * (size_t)W) * n + c;
   double* o = ext + cb * (size_t)W * n + c;
   if constexpr (!FUSED) {
     const double* a = acc + cb * (size_t)K * n + c;
     // acc is inverse-transform output (N times the sum): the residues mod
     // the special primes are [N^-1 acc_Pk]_Pk
-    const double aP = mul_bal(a[(size_t)L * n], cld(tb.ninv, ip), pP, pPinv);
-    double kP = 0.0;
-    if constexpr (A == 2) {
-      const double a1 = mul_bal(a[(size_t)(L + 1) * n], cld(tb.ninv, ip + 1), cld(tb.p, ip + 1),
-                                cld(tb.pinv, ip + 1));
-      kP = special_k<A>(aP, a1, tb, L);
-    }
+    double as[A], kP[A];
+#pragma unroll
+    for (int m = 0; m < A; ++m)
+      as[m] = mul_bal(a[(size_t)(L + m) * n], cld(tb.ninv, ip + m), cld(tb.p, ip + m),
+                      cld(tb.pinv, ip + m));
+    special_digits<A>(as, kP, tb, L);
 #pragma unroll
     for (int i = 0; i < L; ++i) {
       const double q = cld(tb.p, i), qinv = cld(tb.pinv, i);
-      const double r = moddown_term<A>(a[(size_t)i * n], cld(tb.NP_inv_q, i), aP, kP, i, q, qinv, tb);
+      const double r = moddown_term<L, A>(a[(size_t)i * n], cld(tb.NP_inv_q, i), kP, i, q, qinv, tb);
       const double z = reduce_bal(e[(size_t)i * n] + r, q, qinv);
       o[(size_t)i * n] = accumulate ? reduce_bal(o[(size_t)i * n] + z, q, qinv) : z;
     }
@@ -477,14 +492,12 @@ __global__ void __launch_bounds__(256) k_moddown(int n, int n_ct, const double* 
     const int ht = n >> 6;                 // 512: a half transform's threads
     const double* a = acc + cb * (size_t)K * n + (size_t)(c / ht) * 2 * ht + (c % ht);
     const size_t hn = (size_t)(n >> 1);
-    double aP_lo, aP_hi, k_lo = 0.0, k_hi = 0.0;
-    special_pair(a + (size_t)L * n, ht, ip, aP_lo, aP_hi, tb);
-    if constexpr (A == 2) {
-      double a1_lo, a1_hi;
-      special_pair(a + (size_t)(L + 1) * n, ht, ip + 1, a1_lo, a1_hi, tb);
-      k_lo = special_k<A>(aP_lo, a1_lo, tb, L);
-      k_hi = special_k<A>(aP_hi, a1_hi, tb, L);
-    }
+    double s_lo[A], s_hi[A], k_lo[A], k_hi[A];
+#pragma unroll
+    for (int m = 0; m < A; ++m)
+      special_pair(a + (size_t)(L + m) * n, ht, ip + m, s_lo[m], s_hi[m], tb);
+    special_digits<A>(s_lo, k_lo, tb, L);
+    special_digits<A>(s_hi, k_hi, tb, L);
 #pragma unroll
     for (int i = 0; i < L; ++i) {
       const double q = cld(tb.p, i), qinv = cld(tb.pinv, i);
@@ -492,8 +505,8 @@ __global__ void __launch_bounds__(256) k_moddown(int n, int n_ct, const double* 
       const double lo = u + v;
       const double hi = mul_lazy(u - v, cld(tb.tw_inv, i * tb.tw_len + 1), q, qinv);
       const double npq = cld(tb.NP_inv_q, i);
-      const double r_lo = moddown_term<A>(lo, npq, aP_lo, k_lo, i, q, qinv, tb);
-      const double r_hi = moddown_term<A>(hi, npq, aP_hi, k_hi, i, q, qinv, tb);
+      const double r_lo = moddown_term<L, A>(lo, npq, k_lo, i, q, qinv, tb);
+      const double r_hi = moddown_term<L, A>(hi, npq, k_hi, i, q, qinv, tb);
       const double z_lo = reduce_bal(e[(size_t)i * n] + r_lo, q, qinv);
       const double z_hi = reduce_bal(e[(size_t)i * n + hn] + r_hi, q, qinv);
       o[(size_t)i * n] = accumulate ? reduce_bal(o[(size_t)i * n] + z_lo, q, qinv) : z_lo;
@@ -527,14 +540,12 @@ __global__ void __launch_bounds__(256) k_moddown_finish(int n, int n_ct,
   const int ht = n >> 6;
   const double* a = acc + cb * (size_t)K * n + (size_t)(c / ht) * 2 * ht + (c % ht);
   const size_t hn = (size_t)(n >> 1);
-  double aP_lo, aP_hi, k_lo = 0.0, k_hi = 0.0;
-  special_pair(a + (size_t)L * n, ht, ip, aP_lo, aP_hi, tb);
-  if constexpr (A == 2) {
-    double a1_lo, a1_hi;
-    special_pair(a + (size_t)(L + 1) * n, ht, ip + 1, a1_lo, a1_hi, tb);
-    k_lo = special_k<A>(aP_lo, a1_lo, tb, L);
-    k_hi = special_k<A>(aP_hi, a1_hi, tb, L);
-  }
+  double s_lo[A], s_hi[A], k_lo[A], k_hi[A];
+#pragma unroll
+  for (int m = 0; m < A; ++m)
+    special_pair(a + (size_t)(L + m) * n, ht, ip + m, s_lo[m], s_hi[m], tb);
+  special_digits<A>(s_lo, k_lo, tb, L);
+  special_digits<A>(s_hi, k_hi, tb, L);
 #pragma unroll
   for (int i = 0; i < L; ++i) {
     const double q = cld(tb.p, i), qinv = cld(tb.pinv, i);
@@ -542,8 +553,8 @@ __global__ void __launch_bounds__(256) k_moddown_finish(int n, int n_ct,
     const double lo = u + v;
     const double hi = mul_lazy(u - v, cld(tb.tw_inv, i * tb.tw_len + 1), q, qinv);
     const double npq = cld(tb.NP_inv_q, i);
-    const double r_lo = moddown_term<A>(lo, npq, aP_lo, k_lo, i, q, qinv, tb);
-    const double r_hi = moddown_term<A>(hi, npq, aP_hi, k_hi, i, q, qinv, tb);
+    const double r_lo = moddown_term<L, A>(lo, npq, k_lo, i, q, qinv, tb);
+    const double r_hi = moddown_term<L, A>(hi, npq, k_hi, i, q, qinv, tb);
     // finish: -(e + r), plus Delta at coefficient 0 of c0 (sg = -1 exactly
     // negates); else e + r
     const double sg = finish ? -1.0 : 1.0;
@@ -617,19 +628,17 @@ __global__ void __launch_bounds__(256) k_moddown_lift(int n, size_t n_poly,
   const auto re = make_rsrc(dt + (ct * 3 + b) * (size_t)W * n, (unsigned)(L * n * 8));
   const auto rs = make_rsrc(ext + cb * (size_t)W * n, (unsigned)(W * n * 8));
   const int row = hi ? 1 : 0;
-  // [N^-1 acc_Pk]_Pk of this coefficient (balanced), and for A = 2 the
-  // centred residue's second mixed-radix digit
+  // [N^-1 acc_Pk]_Pk of this coefficient (balanced), then the centred
+  // residue's mixed-radix digits
   const int ip = 2 * L + 1;
-  const double pP = cld(tb.p, ip), pPinv = cld(tb.pinv, ip);
-  const double xP = buf_load(ra, pos, L * ls);
-  const double aP = mul_bal(pair_combine(xP, sg), tb.ninv_P[row], pP, pPinv);
-  double kP = 0.0;
-  if constexpr (A == 2) {
-    const double x1 = buf_load(ra, pos, (L + 1) * ls);
-    const double a1 = mul_bal(pair_combine(x1, sg), tb.ninv_P[2 + row], cld(tb.p, ip + 1),
-                              cld(tb.pinv, ip + 1));
-    kP = special_k<A>(aP, a1, tb, L);
+  double as[A], kP[A];
+#pragma unroll
+  for (int m = 0; m < A; ++m) {
+    const double xP = buf_load(ra, pos, (L + m) * ls);
+    as[m] = mul_bal(pair_combine(xP, sg), tb.ninv_P[2 * m + row], cld(tb.p, ip + m),
+                    cld(tb.pinv, ip + m));
   }
+  special_digits<A>(as, kP, tb, L);
   // the new ciphertext's residues are stored only after every load: buffer
   // stores between them would make each limb's loads wait for the previous
   // limb's (the compiler cannot tell the buffers apart)
@@ -641,7 +650,7 @@ __global__ void __launch_bounds__(256) k_moddown_lift(int n, size_t n_poly,
     const double q = cld(tb.p, iq), qinv = cld(tb.pinv, iq);
     const double x = buf_load(ra, pos, i * ls);
     const double r =
-        moddown_term<A>(pair_combine(x, sg), tb.NP_inv_q[row * L + iq], aP, kP, iq, q, qinv, tb);
+        moddown_term<L, A>(pair_combine(x, sg), tb.NP_inv_q[row * L + iq], kP, iq, q, qinv, tb);
     o[i] = reduce_bal(buf_load(re, vo, i * ls) + r, q, qinv);
     y[i] = mul_bal(o[i], cld(tb.q_hat_inv, iq), q, qinv);
     S += y[i] * cld(tb.recip, iq);
@@ -908,24 +917,37 @@ __global__ void __launch_bounds__(256) k_automorph(int n, int L, int n_ct, unsig
   }
 }
 
-// Two primes per key-switching digit: the digit source (dt's third
-// component, limbs 0..L-1, canonical residues d_i) into mixed-radix digit
-// pairs, in place: limb 2j + 1 becomes [(d_{2j+1} - d_{2j}) q_{2j}^-1]_{q_{2j+1}}
-// (canonical), so that digit j, D_j = d_{2j} + q_{2j} v in [0, q_{2j} q_{2j+1}),
-// is [c]_{q_{2j} q_{2j+1}}.  One thread per (ciphertext, pair, coefficient).
+// A primes per key-switching digit (A = 2, 3): the digit source (dt's
+// third component, limbs 0..L-1, canonical residues d_i) into each digit's
+// canonical mixed-radix digits, in place (as k_scale writes them): limb
+// g + m of the group starting at g = j A gets v_m = t_m, t_0 = d_{g+m},
+// t_{k+1} = [(t_k - v_k) q_{g+k}^-1]_{q_{g+m}}, so that digit j,
+// D_j = v_0 + q_g v_1 + q_g q_{g+1} v_2 in [0, Q_j), is [c]_{Q_j}.  One
+// thread per (ciphertext, digit, coefficient).
+template <int A>
 __global__ void __launch_bounds__(256) k_digit_mrc(int n, int L, int n_ct, double* dt, Tables tb) {
-  const int pairs = L >> 1;
+  const int groups = L / A;
   const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= (size_t)n_ct * pairs * n) return;
-  const size_t row = gid / n;               // ct * pairs + j
+  if (gid >= (size_t)n_ct * groups * n) return;
+  const size_t row = gid / n;               // ct * groups + j
   const int c = (int)(gid - row * n);
-  const int j = (int)(row % pairs);
-  const size_t ct = row / pairs;
+  const int j = (int)(row % groups);
+  const size_t ct = row / groups;
   const size_t W = (size_t)2 * L + 1;
-  double* d = dt + (ct * 3 * W + 2 * W + 2 * j) * n + c;
-  const int ib = 2 * j + 1;
-  const double q = cld(tb.p, ib), qinv = cld(tb.pinv, ib);
-  d[n] = to_canonical(mul_bal(d[n] - d[0], cld(tb.mrc_inv, (ib - 1) * L + ib), q, qinv), q);
+  const int g = j * A;
+  double* d = dt + (ct * 3 * W + 2 * W + g) * n + c;
+  double v[A];
+  v[0] = d[0];
+#pragma unroll
+  for (int m = 1; m < A; ++m) {
+    const int ib = g + m;
+    const double q = cld(tb.p, ib), qinv = cld(tb.pinv, ib);
+    double t = d[(size_t)m * n];
+#pragma unroll
+    for (int k = 0; k < m; ++k) t = mul_bal(t - v[k], cld(tb.mrc_inv, (g + k) * L + ib), q, qinv);
+    v[m] = to_canonical(t, q);
+    d[(size_t)m * n] = v[m];
+  }
 }
 
 // ------------------------------------------------------------ boundary ---
@@ -1139,9 +1161,10 @@ static inline dim3 grid_for(size_t total, int block = 256) {
   return dim3((unsigned)((total + block - 1) / block));
 }
 
-#define NSHE_L_CASES(X) X(2) X(3) X(4) X(8) X(12) X(16) X(17) X(20) X(24)
-// data-prime counts built for two primes per key-switching digit
+#define NSHE_L_CASES(X) X(2) X(3) X(4) X(8) X(12) X(15) X(16) X(17) X(20) X(24)
+// data-prime counts built for two and three primes per key-switching digit
 #define NSHE_L2_CASES(X) X(2) X(4) X(8) X(16)
+#define NSHE_L3_CASES(X) X(3) X(12) X(15)
 
 hipError_t run_lift(const Dims& d, double* ext, const Tables& tb, hipStream_t st) {
   const size_t np = (size_t)d.n_ct * 2;
@@ -1166,6 +1189,7 @@ hipError_t run_moddown_finish(const Dims& d, const double* acc, const double* dt
     break;
 #define C1_(L_) C_(L_, 1)
 #define C2_(L_) C_(L_, 2)
+#define C3_(L_) C_(L_, 3)
   if (d.alpha == 1) {
     switch (d.L) {
       NSHE_L_CASES(C1_)
@@ -1176,11 +1200,17 @@ hipError_t run_moddown_finish(const Dims& d, const double* acc, const double* dt
       NSHE_L2_CASES(C2_)
       default: return hipErrorInvalidValue;
     }
+  } else if (d.alpha == 3) {
+    switch (d.L) {
+      NSHE_L3_CASES(C3_)
+      default: return hipErrorInvalidValue;
+    }
   } else {
     return hipErrorInvalidValue;
   }
 #undef C1_
 #undef C2_
+#undef C3_
 #undef C_
   return hipGetLastError();
 }
@@ -1228,6 +1258,7 @@ hipError_t run_moddown_lift(const Dims& d, const double* acc, const double* dt, 
     break;
 #define C1_(L_) C_(L_, 1)
 #define C2_(L_) C_(L_, 2)
+#define C3_(L_) C_(L_, 3)
   if (d.alpha == 1) {
     switch (d.L) {
       NSHE_L_CASES(C1_)
@@ -1238,11 +1269,17 @@ hipError_t run_moddown_lift(const Dims& d, const double* acc, const double* dt, 
       NSHE_L2_CASES(C2_)
       default: return hipErrorInvalidValue;
     }
+  } else if (d.alpha == 3) {
+    switch (d.L) {
+      NSHE_L3_CASES(C3_)
+      default: return hipErrorInvalidValue;
+    }
   } else {
     return hipErrorInvalidValue;
   }
 #undef C1_
 #undef C2_
+#undef C3_
 #undef C_
   return hipGetLastError();
 }
@@ -1264,6 +1301,7 @@ hipError_t run_scale(const Dims& d, double* dt, const Tables& tb, hipStream_t st
     break;
 #define C1_(L_) C_(L_, 1)
 #define C2_(L_) C_(L_, 2)
+#define C3_(L_) C_(L_, 3)
   if (!digit_pairs) {
     switch (d.L) {
       NSHE_L_CASES(C1_)
@@ -1274,11 +1312,17 @@ hipError_t run_scale(const Dims& d, double* dt, const Tables& tb, hipStream_t st
       NSHE_L2_CASES(C2_)
       default: return hipErrorInvalidValue;
     }
+  } else if (d.alpha == 3) {
+    switch (d.L) {
+      NSHE_L3_CASES(C3_)
+      default: return hipErrorInvalidValue;
+    }
   } else {
     return hipErrorInvalidValue;
   }
 #undef C1_
 #undef C2_
+#undef C3_
 #undef C_
   return hipGetLastError();
 }
@@ -1303,6 +1347,7 @@ hipError_t run_ks_mac(const Dims& d, const double* dig, const double* evk, doubl
     break;
 #define C1_(L_) C_(L_, 1)
 #define C2_(L_) C_(L_, 2)
+#define C3_(L_) C_(L_, 3)
   if (d.alpha == 1) {
     switch (d.L) {
       NSHE_L_CASES(C1_)
@@ -1313,11 +1358,17 @@ hipError_t run_ks_mac(const Dims& d, const double* dig, const double* evk, doubl
       NSHE_L2_CASES(C2_)
       default: return hipErrorInvalidValue;
     }
+  } else if (d.alpha == 3) {
+    switch (d.L) {
+      NSHE_L3_CASES(C3_)
+      default: return hipErrorInvalidValue;
+    }
   } else {
     return hipErrorInvalidValue;
   }
 #undef C1_
 #undef C2_
+#undef C3_
 #undef C_
   return hipGetLastError();
 }
@@ -1336,6 +1387,7 @@ hipError_t run_moddown(const Dims& d, const double* acc, const double* dt, doubl
     break;
 #define C1_(L_) C_(L_, 1)
 #define C2_(L_) C_(L_, 2)
+#define C3_(L_) C_(L_, 3)
   if (d.alpha == 1) {
     switch (d.L) {
       NSHE_L_CASES(C1_)
@@ -1346,19 +1398,28 @@ hipError_t run_moddown(const Dims& d, const double* acc, const double* dt, doubl
       NSHE_L2_CASES(C2_)
       default: return hipErrorInvalidValue;
     }
+  } else if (d.alpha == 3) {
+    switch (d.L) {
+      NSHE_L3_CASES(C3_)
+      default: return hipErrorInvalidValue;
+    }
   } else {
     return hipErrorInvalidValue;
   }
 #undef C1_
 #undef C2_
+#undef C3_
 #undef C_
   return hipGetLastError();
 }
 
 hipError_t run_digit_mrc(const Dims& d, double* dt, const Tables& tb, hipStream_t st) {
-  if (d.alpha != 2 || d.L % 2) return hipErrorInvalidValue;
-  const size_t total = (size_t)d.n_ct * (d.L / 2) * d.n;
-  hipLaunchKernelGGL(k_digit_mrc, grid_for(total), dim3(256), 0, st, d.n, d.L, d.n_ct, dt, tb);
+  if (d.alpha < 2 || d.alpha > 3 || d.L % d.alpha) return hipErrorInvalidValue;
+  const size_t total = (size_t)d.n_ct * (d.L / d.alpha) * d.n;
+  if (d.alpha == 2)
+    hipLaunchKernelGGL(k_digit_mrc<2>, grid_for(total), dim3(256), 0, st, d.n, d.L, d.n_ct, dt, tb);
+  else
+    hipLaunchKernelGGL(k_digit_mrc<3>, grid_for(total), dim3(256), 0, st, d.n, d.L, d.n_ct, dt, tb);
   return hipGetLastError();
 }
 

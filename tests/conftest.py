@@ -27,3 +27,11 @@ def s32k_a2():
     data primes, two special primes), keys of seed 0."""
     from tests.gpu_common import Setup
     return Setup(15, alpha=2)
+
+
+@pytest.fixture(scope="session")
+def s32k_a3():
+    """The paper's size with key switching by digits of three data primes (15
+    data primes, three special primes), keys of seed 0."""
+    from tests.gpu_common import Setup
+    return Setup(15, alpha=3)

@@ -2,7 +2,8 @@
 size (N = 32768 slots, the 17 + 1 primes of about 49 bits, p = 65537;
 Sec. 5.1), plus two cases at other (N, t) that reach the same kernels, and
 the same cases with key switching by digits of two data primes (16 data
-primes, two special primes: the a2_ cases).
+primes, two special primes: the a2_ cases) and of three (15 data primes,
+three special primes: the a3_ cases).
 
 The oracle needs minutes per case at this size, so its results are kept as
 SHA-256 digests of the exchange-format arrays (int64 residues, C order,
@@ -305,6 +306,7 @@ def _lt_n64(E: Env) -> dict:
 
 
 A2_COLUMN_CTS = 8             # ciphertexts of each column checked with two-prime digits
+A3_COLUMN_CTS = 4             # ... and with three-prime digits
 
 # case -> (log2 N of its Env, [(unit name, function)]); CASE_ALPHA gives the
 # special primes of a case's Env (1 if absent)
@@ -328,5 +330,15 @@ CASES = {
     "a2_join": (15, [("join", _join)]),
     "a2_lt_t17": (15, [("lt", _lt17), ("between", _between17)]),
     "a2_lt_n64": (6, [("lt", _lt_n64)]),
+    "a3_eq_edges": (15, [("chain", _eq_edges)]),
+    "a3_eq_column_uniform": (15, [(f"ct{k:02d}", _column_uniform(k))
+                                  for k in range(A3_COLUMN_CTS)]),
+    "a3_eq_column_structured": (15, [(f"ct{k:02d}", _column_structured(k))
+                                     for k in range(A3_COLUMN_CTS)]),
+    "a3_rotations": (15, [("rotate", _rotate_real), ("sum_slots", _sum_slots)]),
+    "a3_products": (15, [("select", _select), ("extract", _extract), ("broadcast", _broadcast)]),
+    "a3_join": (15, [("join", _join)]),
+    "a3_lt_t17": (15, [("lt", _lt17), ("between", _between17)]),
+    "a3_lt_n64": (6, [("lt", _lt_n64)]),
 }
-CASE_ALPHA = {c: 2 for c in CASES if c.startswith("a2_")}
+CASE_ALPHA = {c: int(c[1]) for c in CASES if c[:3] in ("a2_", "a3_")}

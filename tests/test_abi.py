@@ -145,3 +145,20 @@ def test_two_special_primes_match_the_oracle():
     q, sp = params.modulus_chain(n_special=2)
     oq, osp = nt.default_modulus_chain(n_special=2)
     assert (q, sp) == (oq, osp) and len(q) == 16
+
+
+def test_three_special_primes_parameter_rules():
+    lib = _lib.load()
+    q, sp = params.modulus_chain(n_special=3)
+    assert len(q) == 15 and len(sp) == 3
+    for L, ok in ((15, True), (16, False)):
+        qq = (q + list(params.modulus_chain()[0]))[:L] if L > 15 else q[:L]
+        qa = (ctypes.c_uint64 * len(qq))(*qq)
+        pr = _lib.NsheParams(15, 65537, len(qq), ctypes.cast(qa, ctypes.POINTER(ctypes.c_uint64)),
+                             sp[0], 3, sp[1], sp[2])
+        b = _lib.NsheBudget()
+        rc = lib.nshe_budget_of(ctypes.byref(pr), ctypes.byref(b))
+        if ok:
+            assert rc == 0 and b.depth_budget == 21
+        else:
+            assert rc == -1 and "alpha = 3" in lib.nshe_last_error().decode()

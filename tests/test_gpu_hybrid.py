@@ -1,6 +1,8 @@
-"""Device parity with key switching by digits of two data primes (alpha = 2:
-the paper's 18 primes as 16 data primes and two special primes, digits
-D_j = [c2]_{q_2j q_2j+1}, P = P_0 P_1), bit-exact against the oracle:
+"""Device parity with key switching by digits of several data primes
+(hybrid: alpha = 2, the paper's 18 primes as 16 data primes and two special
+primes, digits D_j = [c2]_{q_2j q_2j+1}, P = P_0 P_1; alpha = 3, 15 data
+primes and three special primes, digits of three primes), bit-exact against
+the oracle, for each alpha:
 
 * N = 1024 against the oracle computed here: relinearization, squarings,
   products, every level of the EQ chain (Eq. eq:equality) and its mask, a
@@ -8,11 +10,11 @@ D_j = [c2]_{q_2j q_2j+1}, P = P_0 P_1), bit-exact against the oracle:
   rotate-and-add with real Galois keys, both key-switch ciphertext chunks;
 * N = 64 at p = 65537: LT, LE and BETWEEN (Eq. eq:inequality), the paper's
   comparison program shape;
-* N = 32768 against the stored oracle digests (tests/golden/fullsize_a2_*):
-  the split digit transforms, the fused chain (k_sub_lift, k_moddown_lift,
-  k_moddown_finish with the two-prime mod-down), 8 ciphertexts of each
-  2^20-row column, rotations, SELECT, Extract, Broadcast, JOIN and the
-  comparisons at t = 17.
+* N = 32768 against the stored oracle digests (tests/golden/fullsize_a2_*,
+  fullsize_a3_*): the split digit transforms, the fused chain (k_sub_lift,
+  k_moddown_lift, k_moddown_finish with the several-prime mod-down), 8 (4)
+  ciphertexts of each 2^20-row column, rotations, SELECT, Extract,
+  Broadcast, JOIN and the comparisons at t = 17.
 """
 import numpy as np
 import pytest
@@ -27,9 +29,19 @@ from tests.gpu_common import Setup, galois_keys
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module")
-def a1k():
-    return Setup(10, alpha=2)
+ALPHAS = [2, 3]
+
+
+@pytest.fixture(scope="module", params=ALPHAS, ids=[f"alpha{a}" for a in ALPHAS])
+def a1k(request):
+    return Setup(10, alpha=request.param)
+
+
+def _full(request, alpha):
+    return request.getfixturevalue(f"s32k_a{alpha}")
+
+
+COLUMN_CTS = {2: fc.A2_COLUMN_CTS, 3: fc.A3_COLUMN_CTS}
 
 
 def _rand_ct(S, seed, n_ct=1):
@@ -45,13 +57,14 @@ def _same(S, dev, want_cts):
 
 # ------------------------------------------------------------ N = 1024 ---
 
-def test_context_describes_two_prime_digits(a1k):
+def test_context_describes_its_digits(a1k):
     S = a1k
-    assert (S.ctx.alpha, S.ctx.dnum, S.ctx.L) == (2, 8, 16)
-    assert S.ctx.key_shape == (8, 2, 18, S.pr.n)
+    a = S.pr.alpha
+    assert (S.ctx.alpha, S.ctx.dnum, S.ctx.L) == (a, 18 // a - 1, 18 - a)
+    assert S.ctx.key_shape == (S.ctx.dnum, 2, 18, S.pr.n)
     assert S.ctx.special == list(S.pr.special)
     with pytest.raises(ValueError):
-        S.ctx.set_relin_key(torch.zeros((16, 2, 17, S.pr.n), dtype=torch.int64,
+        S.ctx.set_relin_key(torch.zeros((S.ctx.L, 2, S.ctx.L + 1, S.pr.n), dtype=torch.int64,
                                         device=S.ctx.device))
 
 
@@ -147,10 +160,11 @@ def test_rotations_and_sum_slots(a1k):
 
 # -------------------------------------------------------------- N = 64 ---
 
-def test_lt_le_between_paper_prime_n64():
-    S = Setup(6, alpha=2)
+@pytest.mark.parametrize("alpha", ALPHAS)
+def test_lt_le_between_paper_prime_n64(alpha):
+    S = Setup(6, alpha=alpha)
     E = fc.Env.from_keys(S.pr, S.sk, S.rk)
-    g = fc.load_golden("a2_lt_n64")
+    g = fc.load_golden(f"a{alpha}_lt_n64")
     (x, y, lo, hi), cts = fc.lt_n64_inputs(E)
     dev = [S.to_dev([c]) for c in cts]
     lt = S.ctx.compare(dev[0], dev[1], "lt")
@@ -167,10 +181,11 @@ def _env(S):
     return fc.Env.from_keys(S.pr, S.sk, S.rk)
 
 
-def test_full_size_chain_every_level_and_paths(s32k_a2):
-    S = s32k_a2
+@pytest.mark.parametrize("alpha", ALPHAS)
+def test_full_size_chain_every_level_and_paths(request, alpha):
+    S = _full(request, alpha)
     E = _env(S)
-    g = fc.load_golden("a2_eq_edges")
+    g = fc.load_golden(f"a{alpha}_eq_edges")
     x, y, cx, cy = fc.eq_edges_inputs(E)
     dx, dy = S.to_dev([cx]), S.to_dev([cy])
     z = S.ctx.sub(dx, dy)
@@ -197,35 +212,40 @@ def test_full_size_chain_every_level_and_paths(s32k_a2):
         S.ctx.set_tuning(**start)
 
 
-def test_full_size_columns(s32k_a2):
-    S = s32k_a2
+@pytest.mark.parametrize("alpha", ALPHAS)
+def test_full_size_columns(request, alpha):
+    S = _full(request, alpha)
     E = _env(S)
-    gu = fc.load_golden("a2_eq_column_uniform")
-    pairs = [fc.column_uniform_cts(E, k) for k in range(fc.A2_COLUMN_CTS)]
+    n_ct = COLUMN_CTS[alpha]
+    gu = fc.load_golden(f"a{alpha}_eq_column_uniform")
+    pairs = [fc.column_uniform_cts(E, k) for k in range(n_ct)]
     out = S.ctx.eq_mask(S.to_dev([p[0] for p in pairs]), S.to_dev([p[1] for p in pairs]))
     got = out.cpu().numpy()
-    for k in range(fc.A2_COLUMN_CTS):
+    for k in range(n_ct):
         fc.check(gu, f"mask_{k:02d}", got[k])
-    gs = fc.load_golden("a2_eq_column_structured")
-    xs = S.to_dev([fc.column_structured_ct(E, k) for k in range(fc.A2_COLUMN_CTS)])
+    gs = fc.load_golden(f"a{alpha}_eq_column_structured")
+    xs = S.to_dev([fc.column_structured_ct(E, k) for k in range(n_ct)])
     out = S.ctx.eq_mask(xs, S.to_dev([fc.column_structured_constant(E)]))
     got = out.cpu().numpy()
-    for k in range(fc.A2_COLUMN_CTS):
+    for k in range(n_ct):
         fc.check(gs, f"mask_{k:02d}", got[k])
 
 
-@pytest.fixture(scope="module")
-def a2_uniform_keys(s32k_a2):
-    S = s32k_a2
-    for gel, limbs in fc.uniform_galois_limbs(S.pr).items():
-        S.ctx.set_galois_key(gel, torch.from_numpy(limbs).to(S.ctx.device))
-    return True
+def _uniform_keys(S):
+    """Stand-in (uniform) Galois keys for every element of the sum, loaded
+    once per context."""
+    if not getattr(S, "uniform_keys_loaded", False):
+        for gel, limbs in fc.uniform_galois_limbs(S.pr).items():
+            S.ctx.set_galois_key(gel, torch.from_numpy(limbs).to(S.ctx.device))
+        S.uniform_keys_loaded = True
 
 
-def test_full_size_rotations(s32k_a2, a2_uniform_keys):
-    S = s32k_a2
+@pytest.mark.parametrize("alpha", ALPHAS)
+def test_full_size_rotations(request, alpha):
+    S = _full(request, alpha)
+    _uniform_keys(S)
     E = _env(S)
-    g = fc.load_golden("a2_rotations")
+    g = fc.load_golden(f"a{alpha}_rotations")
     v, ct = fc.rotate_inputs(E)
     gel, key = fc.real_rotation(E)
     S.ctx.set_galois_key(gel, torch.from_numpy(key.limbs(S.pr)).to(S.ctx.device))
@@ -239,10 +259,12 @@ def test_full_size_rotations(s32k_a2, a2_uniform_keys):
     fc.check(g, "sum_slots", S.ctx.sum_slots(S.to_dev([ct]))[0].cpu().numpy())
 
 
-def test_full_size_products_and_join(s32k_a2, a2_uniform_keys):
-    S = s32k_a2
+@pytest.mark.parametrize("alpha", ALPHAS)
+def test_full_size_products_and_join(request, alpha):
+    S = _full(request, alpha)
+    _uniform_keys(S)
     E = _env(S)
-    g = fc.load_golden("a2_products")
+    g = fc.load_golden(f"a{alpha}_products")
     price, mask, cp, cm = fc.select_inputs(E)
     sel = S.ctx.select(S.to_dev([cp]), S.to_dev([cm]))
     fc.check(g, "select", sel[0].cpu().numpy())
@@ -250,16 +272,17 @@ def test_full_size_products_and_join(s32k_a2, a2_uniform_keys):
     fc.check(g, "extract", S.ctx.extract(S.to_dev([ct]), fc.EXTRACT_SLOT)[0].cpu().numpy())
     fc.check(g, "broadcast",
              S.ctx.extract(S.to_dev([ct]), fc.EXTRACT_SLOT, broadcast=True)[0].cpu().numpy())
-    gj = fc.load_golden("a2_join")
+    gj = fc.load_golden(f"a{alpha}_join")
     *_, ca, cbk, cba = fc.join_inputs(E)
     out = S.ctx.join_sum(S.to_dev([ca]), S.to_dev([cbk]), S.to_dev([cba]), [fc.JOIN_SLOT])
     fc.check(gj, "join", out[0].cpu().numpy())
 
 
-def test_full_size_lt_between_t17(s32k_a2):
-    S = s32k_a2
+@pytest.mark.parametrize("alpha", ALPHAS)
+def test_full_size_lt_between_t17(request, alpha):
+    S = _full(request, alpha)
     E17 = _env(S).with_t(17)
-    g = fc.load_golden("a2_lt_t17")
+    g = fc.load_golden(f"a{alpha}_lt_t17")
     ctx = Context(15, 17, list(S.pr.q), list(S.pr.special))
     ctx.set_relin_key(torch.from_numpy(S.rk.limbs(S.pr)).to(ctx.device))
     _, cts = fc.lt17_inputs(E17)
@@ -269,10 +292,11 @@ def test_full_size_lt_between_t17(s32k_a2):
     ctx.close()
 
 
-def test_full_size_autotune_keeps_the_two_kernel_key_switch(s32k_a2):
+@pytest.mark.parametrize("alpha", ALPHAS)
+def test_full_size_autotune_keeps_the_two_kernel_key_switch(request, alpha):
     """The fused key switch exists for one-prime digits only: the autotuner
     must not report it (it would time a path the context never takes)."""
-    S = s32k_a2
+    S = _full(request, alpha)
     x = synth.uniform_device_residues((2, 2), S.ctx.q, S.ctx.n, 5, S.ctx.device)
     start = S.ctx.tuning()
     try:

@@ -382,3 +382,41 @@ def test_noise_meter_flags_budget_exhaustion():
         assert ok == (b > 0), f"level {k}: budget {b}"
         verdicts.append(ok)
     assert verdicts[0] and not verdicts[-1]
+
+
+# --------------------------------------------------- three-prime digits ---
+
+def test_three_prime_digits_parameters_and_gadget():
+    """alpha = 3: the three largest of the 18 primes special, 15 data primes
+    in 5 digits of three; the gadget is the CRT basis of the digit groups."""
+    one, three = bfv.paper_params(16), bfv.paper_params(16, alpha=3)
+    assert (three.L, three.alpha, three.dnum) == (15, 3, 5)
+    assert sorted(one.moduli_pq) == sorted(three.moduli_pq)
+    assert three.P * three.Q == one.P * one.Q
+    for j in range(three.dnum):
+        g = three.gadget(j)
+        assert all(g % three.q[i] == (1 if i // 3 == j else 0) for i in range(three.L))
+        assert three.digit_modulus(j) == three.q[3 * j] * three.q[3 * j + 1] * three.q[3 * j + 2]
+
+
+def test_three_prime_relinearize_matches_schoolbook_route():
+    pr, sk, rk = _setup(8, alpha=3)
+    rng = np.random.default_rng(14)
+    ct3 = bfv.multiply(pr, _enc(pr, sk, rng.integers(0, pr.t, 8), 1),
+                       _enc(pr, sk, rng.integers(0, pr.t, 8), 2))
+    got = bfv.relinearize(pr, rk, ct3)
+    P = pr.special[0] * pr.special[1] * pr.special[2]
+    u = [np.zeros(8, dtype=object), np.zeros(8, dtype=object)]
+    for j in range(5):
+        dj = ring.as_object(ct3[2]) % (pr.q[3 * j] * pr.q[3 * j + 1] * pr.q[3 * j + 2])
+        u[0] = u[0] + ring.negacyclic_schoolbook(dj, rk.b[j])
+        u[1] = u[1] + ring.negacyclic_schoolbook(dj, rk.a[j])
+    for b in range(2):
+        want = [(int(c) + round(Fraction(int(v), P))) % pr.Q for c, v in zip(ct3[b], u[b])]
+        assert list(got[b]) == want
+
+
+def test_three_prime_eq_chain_decrypts():
+    pr, sk, rk = _setup(64, alpha=3)
+    x, y = synth.column_pair_half_match(5, 64)
+    _check_chain(pr, sk, rk, x, y, 31)
