@@ -579,7 +579,7 @@ def summarize_profiles(prof_dir: str, out_dir: str) -> None:
     # two-prime digits), half-limb or full-limb
     import re
     for (name, grid), d in per_kind.items():
-        if re.search(r"k_ntt_fwd_half<[15]>|k_ntt_fwd<\d+, [15]>", name):
+        if re.search(r"k_ntt_fwd_half<[156]>|k_ntt_fwd<\d+, [156]>", name):
             traffic["ntt_digit"] = d.get("FETCH_SIZE", 0) + d.get("WRITE_SIZE", 0)
     with open(os.path.join(out_dir, "traffic.json"), "w") as fh:
         json.dump({"kernel_hash": kernel_hash(), "bytes_per_launch": traffic,
@@ -631,12 +631,13 @@ def main() -> int:
     ap.add_argument("--skip-next", action="store_true",
                     help="skip IN / SELECT / SUM over the same column")
     ap.add_argument("--next-reps", type=int, default=2)
-    ap.add_argument("--alpha", type=int, default=2, choices=(1, 2, 3),
-                    help="data primes per key-switching digit: 2 (16 data primes, two special "
-                         "primes; the default), 1 (17 data primes and one special prime) or 3 "
-                         "(15 data primes, three special primes)")
+    ap.add_argument("--alpha", type=int, default=3, choices=(1, 2, 3),
+                    help="data primes per key-switching digit: 3 (15 data primes, three special "
+                         "primes; the default: the fastest whose noise budget covers every "
+                         "operator), 2 (16 data primes, two special primes) or 1 (17 data "
+                         "primes and one special prime)")
     ap.add_argument("--skip-other", action="store_true",
-                    help="skip timing the other key-switching decomposition")
+                    help="skip timing the other key-switching decompositions")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run one device copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
