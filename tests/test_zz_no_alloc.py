@@ -65,13 +65,14 @@ def test_noalloc_two_calls_match_the_workspace_entry():
     assert e.value.code == _lib.NSHE_ENOMEM
 
 
-def test_noalloc_full_size_one_ciphertext():
+@pytest.mark.parametrize("alpha", [1, 3])
+def test_noalloc_full_size_one_ciphertext(alpha):
     """N = 32768 with a stand-in (uniform) key and uniform residues (the
-    arithmetic is the same for any key): one ciphertext, then an empty call;
-    two ciphertexts are refused."""
-    ctx = Context.paper(15)
-    mpq = list(ctx.q) + [ctx.P]
-    key = synth.uniform_device_residues((ctx.L, 2), mpq, ctx.n, 31, ctx.device)
+    arithmetic is the same for any key), one- and three-prime key-switching
+    digits: one ciphertext, then an empty call; two ciphertexts are
+    refused."""
+    ctx = Context.paper(15, alpha=alpha)
+    key = synth.uniform_device_residues((ctx.dnum, 2), ctx.moduli_pq, ctx.n, 31, ctx.device)
     ctx.set_relin_key(key)
     x = synth.uniform_device_residues((1, 2), ctx.q, ctx.n, 32, ctx.device)
     y = synth.uniform_device_residues((1, 2), ctx.q, ctx.n, 33, ctx.device)
