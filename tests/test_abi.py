@@ -162,3 +162,51 @@ def test_three_special_primes_parameter_rules():
             assert rc == 0 and b.depth_budget == 21
         else:
             assert rc == -1 and "alpha = 3" in lib.nshe_last_error().decode()
+
+
+# C struct name -> (ctypes class, field names): the binding's structs must have the header's
+# size and field offsets (checked by compiling a C program against the header with gcc)
+_STRUCTS = {
+    "nshe_params": ("NsheParams", ["log2_n", "t", "L", "q_host", "P", "alpha", "P1", "P2"]),
+    "nshe_info": ("NsheInfo", ["n", "L", "L_ext", "squarings", "ext_primes", "ct_words",
+                               "relin_key_words", "depth_budget", "lt_depth", "fresh_bits",
+                               "level_bits", "alpha", "dnum"]),
+    "nshe_budget": ("NsheBudget", ["depth_budget", "lt_depth", "fresh_bits", "level_bits"]),
+    "nshe_item": ("NsheItem", ["x_dev", "y_dev", "out_dev", "n_ct", "y_broadcast"]),
+    "nshe_tuning": ("NsheTuning", ["ks_chunk", "split_forward", "ew_block", "wave_ct",
+                                   "ks_fused"]),
+    "nshe_kernel_stat": ("NsheKernelStat", ["name", "launches", "total_ms", "work"]),
+    "nshe_modmul_probe": ("NsheModmulProbe", ["ms", "products_per_s", "fp64_ops_per_s"]),
+    "nshe_conv_probe": ("NsheConvProbe", ["coefficients", "ms_fma", "ms_mfma", "mismatches"]),
+}
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "nshe.h"',
+             '#include "nshe_probe.h"', 'int main(void) {']
+    for cname, (_, fields) in _STRUCTS.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f in fields:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(root, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                               text=True).stdout.splitlines():
+        c, f, v = line.split()
+        got[(c, f)] = int(v)
+    for cname, (pyname, fields) in _STRUCTS.items():
+        cls = getattr(_lib, pyname)
+        assert ctypes.sizeof(cls) == got[(cname, "size")], cname
+        assert [f[0] for f in cls._fields_] == fields, cname
+        for f in fields:
+            assert getattr(cls, f).offset == got[(cname, f)], (cname, f)
