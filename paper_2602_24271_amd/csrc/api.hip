@@ -377,7 +377,8 @@ static int prepare_operand(nshe_ctx* c, double* ext, double* fx, int n_ct, hipSt
 // fx (NTT domain, operands; the first in fx_a when given, else w.fx; the
 // second in fx_b, or squaring) -> dt limbs 0..L-1 of the 3 components:
 // [round(t d_k / Q)]_Q, coefficient domain; the third as the
-// relinearization digit source (digit pairs with alpha = 2) unless
+// relinearization digit source (each digit's mixed-radix digits when
+// alpha > 1) unless
 // `residues` asks for its canonical residues (a three-component output).
 static int tensor_scale(nshe_ctx* c, const Ws& w, const double* fx_b, int n_ct, hipStream_t st,
                         const double* fx_a = nullptr, bool residues = false) {
@@ -417,7 +418,7 @@ static int finish_relin(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st, doub
                         bool lift_out, int64_t* finish_out, int64_t* i64_out, bool accumulate);
 
 // Key-switch the third component in dt (limbs 0..L-1: canonical residues,
-// or with two primes per digit their mixed-radix digit pairs) with
+// or with several primes per digit each digit's mixed-radix digits) with
 // `key` (the relinearization key unless given) and add the result to the
 // first two: (c0 + k0, c1 + k1) into `out` (ext unless given), limbs 0..L-1.
 // lift_out: also lift the result (limbs L..2L of out), for a squaring that

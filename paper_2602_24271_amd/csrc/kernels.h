@@ -68,7 +68,7 @@ struct Tables {
   const double* two24;       // [K]
   const double* two48;       // [K]
   // key switching (digits of alpha data primes, alpha special primes; the
-  // two-prime tables are at the end of the struct)
+  // tables for several primes per digit are at the end of the struct)
   const double* P_inv_q;     // [L]      [P^-1]_{q_i}
   const double* NP_inv_q;    // [2][L]   [N^-1 P^-1]_{q_i}; second row times w_i
   const double* ninv_P;      // [alpha][2] [N^-1]_{P_k}, times w_{P_k} (w: the 2^15-point

@@ -1052,7 +1052,7 @@ k_ntt_fwd_half(NttJob job, Tables tb) {
   for (int r = 0; r < S::ROUNDS; ++r) {
     if (r > 0) exchange<14>(x, r - 1, r, lds, r > 1);
     // The ten stages to the end of round 1 leave values below 13.5 p (15.1 p
-    // from two-prime digits, ct_bound).  Only
+    // from two-prime digits, ct_bound; three-prime digits start reduced).  Only
     // the X operands of round 2's first stage (elements 0..E/2-1: it pairs
     // e with e + E/2) are reduced, at that round's start: its products
     // take |Y| < 15.1 p (results below 2.1 p), so it outputs below 2.6 p

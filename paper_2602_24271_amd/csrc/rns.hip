@@ -376,7 +376,8 @@ __global__ void __launch_bounds__(256) k_ks_mac(int n, int n_ct, const double* d
       }
       // digit transforms are not reduced at their end: |dv| < 15.1 p (at
       // most ten unreduced stages from inputs below 2.61 p, the bound of a
-      // two-prime digit's value; 13.5 p from one-prime digits below 2 p;
+      // two-prime digit's value; 13.5 p from one-prime digits below 2 p and
+      // from three-prime digits, reduced to balanced form first;
       // 6.1 p at N = 2^15), so each product with a balanced key is below
       // (1/2 + 0.094 x 15.1) p = 1.92 p and eight of them plus a reduced sum
       // stay below 15.9 p < 2^53 / p (> 16.6 p for p < 2^48.95): reduce the
