@@ -64,7 +64,8 @@ def log(msg: str) -> None:
 def kernel_hash() -> str:
     """Hash of the built library (its machine code): HBM counters taken on
     one build are reported only while the library is bit-identical (the
-    build is deterministic, so edits to comments keep it)."""
+    build compiles in a fixed directory, so the same sources rebuild to the
+    same bytes)."""
     lib = os.path.join(ROOT, "paper_2602_24271_amd", "libnshe.so")
     if not os.path.exists(lib):
         return "none"

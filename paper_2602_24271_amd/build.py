@@ -11,7 +11,6 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
-import tempfile
 from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -39,14 +38,17 @@ def _run(cmd) -> None:
 
 
 def build(verbose: bool = False) -> str:
-    with tempfile.TemporaryDirectory(prefix="nshe_build_") as tmp:
-        objs = [os.path.join(tmp, os.path.basename(s) + ".o") for s in SOURCES]
-        cmds = [[hipcc(), *FLAGS, "-c", "-o", o, os.path.join(HERE, s)]
-                for s, o in zip(SOURCES, objs)]
-        with ThreadPoolExecutor(len(cmds)) as ex:
-            for f in [ex.submit(_run, c) for c in cmds]:
-                f.result()
-        _run([hipcc(), "--offload-arch=gfx950", "-shared", "-o", LIB + ".tmp", *objs])
+    # objects in a fixed directory (paths end up in the library, so a fixed
+    # one keeps the build reproducible: the same sources give the same bytes)
+    tmp = os.path.join(HERE, "_build")
+    os.makedirs(tmp, exist_ok=True)
+    objs = [os.path.join(tmp, os.path.basename(s) + ".o") for s in SOURCES]
+    cmds = [[hipcc(), *FLAGS, "-c", "-o", o, os.path.join(HERE, s)]
+            for s, o in zip(SOURCES, objs)]
+    with ThreadPoolExecutor(len(cmds)) as ex:
+        for f in [ex.submit(_run, c) for c in cmds]:
+            f.result()
+    _run([hipcc(), "--offload-arch=gfx950", "-shared", "-o", LIB + ".tmp", *objs])
     os.replace(LIB + ".tmp", LIB)
     if verbose:
         sys.stderr.write(f"built {LIB}\n")
