@@ -92,11 +92,18 @@ def roofline(prof: dict, ctx=None) -> tuple[dict, str]:
     st = prof[dom_ntt]
     per_launch_ops = st["work"] / st["launches"] * OPS_PER_BUTTERFLY
     modup = 0.0
-    if ctx is not None and dom_ntt == "ntt_digit" and getattr(ctx, "alpha", 1) > 1:
+    stages = None
+    if ctx is not None and dom_ntt == "ntt_digit":
+        n = ctx.n
+        stages = n.bit_length() - 1
+        if n == 1 << 15 and ctx.tuning()["split_forward"]:
+            # by coefficient parity: two 2^14-point transforms per limb, the
+            # last stage left to the key-switch product
+            stages -= 1
+    if stages and getattr(ctx, "alpha", 1) > 1:
         # digits of alpha primes: each limb transform first forms the digit's
         # value in its prime (N coefficients, alpha - 1 products and adds each)
-        n = ctx.n
-        limbs = st["work"] / st["launches"] / (n // 2 * (n.bit_length() - 1))
+        limbs = st["work"] / st["launches"] / (n // 2 * stages)
         modup = limbs * n * OPS_PER_MODUP * (ctx.alpha - 1)
         per_launch_ops += modup
     avg_s = st["ms"] / st["launches"] / 1e3
@@ -118,6 +125,7 @@ def roofline(prof: dict, ctx=None) -> tuple[dict, str]:
         "frac": achieved / PEAK_FP64_OPS,
         "traffic": traffic,
         "butterflies_per_launch": st["work"] / st["launches"],
+        "stages_per_limb": stages,
         "modup_ops_per_launch": modup,
         "mean_launch_ms": st["ms"] / st["launches"],
     }, dom_ntt
@@ -135,6 +143,12 @@ def roofline_ks(ctx, prof: dict, n_ct: int, ks_chunk: int) -> dict | None:
     if not st or not st["launches"]:
         return None
     n, D, K = ctx.n, ctx.dnum, ctx.L + ctx.alpha
+    # the launcher's chunk: halved down to the ciphertexts present, and at
+    # most 16 with digit transforms by parity (four sums per ciphertext)
+    while ks_chunk > 4 and ks_chunk // 2 >= n_ct:
+        ks_chunk //= 2
+    if n == 1 << 15 and ctx.tuning()["split_forward"]:
+        ks_chunk = min(ks_chunk, 16)
     chunks = -(-n_ct // ks_chunk)
     per_launch = 8 * n * K * (n_ct * D + chunks * 2 * D + n_ct * 2)
     avg_s = st["ms"] / st["launches"] / 1e3
@@ -576,11 +590,11 @@ def summarize_profiles(prof_dir: str, out_dir: str) -> None:
             continue
         tl.append(f"| {name[:70]} | {grid} | {d.get('FETCH_SIZE', 0) / 1e6:.1f} | "
                   f"{d.get('WRITE_SIZE', 0) / 1e6:.1f} |")
-    # the digit transform: the forward NTT in its digit modes (one- or
-    # two-prime digits), half-limb or full-limb
+    # the digit transform: the forward NTT in its digit modes (digits of one,
+    # two or three primes), by coefficient parity or full-limb
     import re
     for (name, grid), d in per_kind.items():
-        if re.search(r"k_ntt_fwd_half<[156]>|k_ntt_fwd<\d+, [156]>", name):
+        if re.search(r"k_ntt_fwd_par<[156]>|k_ntt_fwd_half<[156]>|k_ntt_fwd<\d+, [156]>", name):
             traffic["ntt_digit"] = d.get("FETCH_SIZE", 0) + d.get("WRITE_SIZE", 0)
     with open(os.path.join(out_dir, "traffic.json"), "w") as fh:
         json.dump({"kernel_hash": kernel_hash(), "bytes_per_launch": traffic,

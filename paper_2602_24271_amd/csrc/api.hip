@@ -414,6 +414,9 @@ static bool ks_fused(const nshe_ctx* c) {
 }
 
 static int digit_products(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st, const double* key);
+static bool parity_digits(const nshe_ctx* c) {
+  return c->log2n == 15 && c->tune.split_forward && c->tb.tw_cmp_par && c->tb.tw_last;
+}
 static int finish_relin(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st, double* out,
                         bool lift_out, int64_t* finish_out, int64_t* i64_out, bool accumulate);
 
@@ -456,6 +459,9 @@ static int digit_products(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st, co
   Dims d = dims(c, n_ct);
   NttJob j{};
   j.split = c->tune.split_forward;
+  // 2^15-point limbs with the split transforms: digit transforms by
+  // coefficient parity, their last stage applied by the key-switch product
+  j.parity = d.parity = parity_digits(c) ? 1 : 0;
   j.base = w.dig;
   j.out = w.dig;
   j.poly_stride = (size_t)KS_of(c) * c->n;
@@ -468,7 +474,10 @@ static int digit_products(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st, co
   j.digits = c->dnum;
   j.alpha = c->alpha;
   {
-    Prof pf(c, K_NTT_DIGIT, st, ntt_work(c, j.count));
+    // butterflies done: by parity, 14 of the 15 stages (the key-switch
+    // product applies the last)
+    const double work = j.parity ? (double)j.count * (c->n / 2) * (c->log2n - 1) : ntt_work(c, j.count);
+    Prof pf(c, K_NTT_DIGIT, st, work);
     HIPCHK(run_ntt(c->log2n, j, c->tb, 2, st));
   }
   {
@@ -849,6 +858,11 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
       tw_ch((size_t)K * 2 * std::max(cmp_h_len, 1), 0.0),
       tw_chi((size_t)K * 2 * std::max(cmp_h_len, 1), 0.0), tw_kf((size_t)K * 32, 0.0),
       tw_ki((size_t)K * 32, 0.0);
+  // N = 2^15: the parity sub-transforms' compact rows and round-1 rows, and
+  // the last-stage twiddles of the key-switching basis (see Tables)
+  const int KSn = L + alpha;
+  std::vector<double> tw_cp((size_t)K * std::max(cmp_h_len, 1), 0.0),
+      tw_r1p((size_t)K * 512, 0.0), tw_last(h_rounds ? (size_t)KSn * (n / 2) : 1, 0.0);
   // the inverse's last-stage twiddle of each prime (slot 1 of its round-0 row)
   std::vector<u64> w_last(K, 1);
   {
@@ -931,6 +945,29 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
             off += (size_t)8 << ss;
           }
         }
+        // parity sub-transforms: sub-stage s is the full transform's stage s
+        // (slot 2^s + m), for either parity
+        for (int u = 0; u < (1 << h_r0) && (1 << h_r0) * 32 == 512; ++u)
+          for (int kk = 0; kk < h_loge; ++kk)
+            for (int j = 0; j < (1 << kk); ++j)
+              tw_r1p[(size_t)k * 512 + (size_t)u * 32 + (1 << kk) + j] =
+                  bal(pbr[(1 << (h_r0 + kk)) + (u << kk) + j], p);
+        size_t off = (size_t)k * cmp_h_len;
+        for (int r = 1; r < h_rounds; ++r) {
+          const int ss = h_r0 + (r - 1) * h_loge;
+          for (int u = 0; u < (1 << ss); ++u)
+            for (int kk = 0; kk < h_loge; ++kk)
+              tw_cp[off + ((size_t)kk << ss) + u] = bal(pbr[(1 << (ss + kk)) + (u << kk)], p);
+          off += (size_t)8 << ss;
+        }
+        // last stage, pairing standard indices 2k and 2k + 1: psi^brv(2^14 + k)
+        // for k = 16 m + u at u 1024 + m
+        const int ks = k < L ? k : (k > 2 * L ? L + (k - 2 * L - 1) : -1);
+        if (ks >= 0 && n == (1 << 15))
+          for (int u = 0; u < 16; ++u)
+            for (int m = 0; m < 1024; ++m)
+              tw_last[(size_t)ks * (n / 2) + (size_t)u * 1024 + m] =
+                  bal(pbr[(n / 2) + 16 * m + u], p);
       }
     }
   }
@@ -1060,7 +1097,8 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
       {&q_hat_b_sp, &c->tb.q_hat_b_sp}, {&c2_sp, &c->tb.c2_sp}, {&b_hat_q_sp, &c->tb.b_hat_q_sp},
       {&two24, &c->tb.two24},     {&two48, &c->tb.two48},
       {&tw_hi, &c->tb.tw_half_inv}, {&tw_chi, &c->tb.tw_cmp_hi},
-      {&tw_r1f, &c->tb.tw_r1_f},  {&tw_r1i, &c->tb.tw_r1_i}};
+      {&tw_r1f, &c->tb.tw_r1_f},  {&tw_r1i, &c->tb.tw_r1_i},
+      {&tw_cp, &c->tb.tw_cmp_par}, {&tw_r1p, &c->tb.tw_r1_par}, {&tw_last, &c->tb.tw_last}};
   size_t total = 0;
   std::vector<size_t> offs;
   for (auto& pp : parts) {
@@ -1116,6 +1154,9 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
     c->tb.tw_half = nullptr;
     c->tb.tw_half0 = nullptr;
     c->tb.tw_half_inv = nullptr;
+    c->tb.tw_cmp_par = nullptr;
+    c->tb.tw_r1_par = nullptr;
+    c->tb.tw_last = nullptr;
   }
   // counters: [MARGIN_COUNT] u64 event counts, the input-check flag at +128
   static_assert(MARGIN_COUNT * 8 <= 128, "counter area");
@@ -2430,7 +2471,8 @@ int nshe_autotune(nshe_ctx* c, const int64_t* sample, int n_sample, int max_wave
       t.split_forward = v;
       rc = time_kinds(c, t, w, n_t, 2, st, ms);
       if (rc) { c->tune = start; return rc; }
-      const double tt = ms[K_NTT_FWD] + ms[K_NTT_DIGIT];
+      // the split changes the key-switch product too (parity digits)
+      const double tt = ms[K_NTT_FWD] + ms[K_NTT_DIGIT] + ms[K_KS_MAC];
       if (tt < tbest) { tbest = tt; best.split_forward = v; }
     }
   }

@@ -95,6 +95,17 @@ struct Tables {
   // basis from its canonical mixed-radix digits (v_0, ..., v_{alpha-1}):
   // v_0 + [q_{j alpha}]_{p_i} v_1 + [q_{j alpha} q_{j alpha + 1}]_{p_i} v_2
   const double* dig_c;       // [dnum][L + alpha][alpha - 1], balanced
+  // N = 2^15, digit transforms by coefficient parity (k_ntt_fwd_par): the
+  // 2^14-point transforms of the even and of the odd coefficients (root
+  // psi^2) use the full transform's twiddles of stages 0..13, slot 2^s + m
+  // of stage s (round 0's row is tw_fwd's); their compact rows of rounds 1
+  // and 2, and round 1 in full for the LDS copy (16 rows x 32 slots)
+  const double* tw_cmp_par;  // [K][tw_cmp_h_len]
+  const double* tw_r1_par;   // [K][512]
+  // the full transform's last-stage twiddles psi^brv(2^14 + k) of the
+  // key-switching basis, in the order of k_ks_mac_par's threads: entry
+  // u 1024 + m holds k = 16 m + u
+  const double* tw_last;     // [L + alpha][2^14]
 };
 
 // Call sites of the exact-lift fallback (index into Tables::margin).
@@ -137,6 +148,10 @@ struct NttJob {
   // stop before the last stage, which the consumer (scale-and-round, or
   // mod-down) applies as it loads; see k_ntt_inv_half for the layouts
   int split_inv = 0;
+  // 2^15-point digit transforms (direction 2) by coefficient parity, two
+  // 2^14-point transforms per limb; the key-switch product applies the last
+  // stage (k_ntt_fwd_par, k_ks_mac_par)
+  int parity = 0;
 };
 
 // run_ntt directions: 0 forward in place, 1 inverse in place, 2 forward of
@@ -166,6 +181,9 @@ struct Dims {
   // points): the last inverse stage is still to be applied on load
   int fused = 0;
   int alpha = 1;       // special primes (data primes per key-switching digit)
+  // the digit transforms are by coefficient parity (N = 2^15): the key-switch
+  // product applies their last stage (k_ks_mac_par)
+  int parity = 0;
 };
 
 hipError_t run_lift(const Dims& d, double* ext, const Tables& tb, hipStream_t st);

@@ -867,33 +867,19 @@ k_ntt_inv(NttJob job, Tables tb) {
 template <int MODE>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
 k_ntt_fwd_half(NttJob job, Tables tb) {
+  static_assert(MODE == NTT_INPLACE, "digit transforms run by coefficient parity (k_ntt_fwd_par)");
   using S = NttShape<14>;
   constexpr int NF = 1 << 15;
   constexpr int R1 = 1 << S::s_start(1);   // round 1's index rows
   static_assert(R1 * LDS_ROW == 512, "one table entry per thread");
   __shared__ uint32_t lds[S::LDS_WORDS];
   __shared__ double ltw[R1 * LDS_ROW];
-  int limb, poly, h;
-  if (MODE == NTT_DIGIT || MODE == NTT_DIGIT2 || MODE == NTT_DIGIT3) {
-    const int x = blockIdx.x & 7, l2 = blockIdx.x >> 3;
-    h = l2 & 1;
-    const int l = l2 >> 1;
-    const int ph = (job.nlimb + 1) >> 1;
-    const int g = x & 1;
-    const int np = g ? job.nlimb - ph : ph;
-    const int sq = (job.npoly + 3) >> 2;
-    const int src = (x >> 1) * sq + l / np;
-    if (l / np >= sq || src >= job.npoly) return;
-    poly = src;
-    limb = g * ph + l % np;
-  } else {
-    const int item2 = xcd_item(job.count * 2);
-    if (item2 >= job.count * 2) return;
-    h = item2 & 1;
-    const int item = item2 >> 1;
-    limb = item / job.npoly;
-    poly = item - limb * job.npoly;
-  }
+  const int item2 = xcd_item(job.count * 2);
+  if (item2 >= job.count * 2) return;
+  const int h = item2 & 1;
+  const int item = item2 >> 1;
+  const int limb = item / job.npoly;
+  const int poly = item - limb * job.npoly;
   const int prime = cldi(job.limb_prime, limb);
   const double p = cld(tb.p, prime), pinv = cld(tb.pinv, prime);
   // half 1 takes X - W Y = X + (-W) Y: one uniform sign flip of the twiddle
@@ -917,108 +903,8 @@ k_ntt_fwd_half(NttJob job, Tables tb) {
   static_assert(S::ROUNDS == 3 && fwd_reduces_after<14>(HALF_REDUCE_ROUND - 1, 1) &&
                     1 + S::stages(0) + S::stages(1) == FWD_STAGES_PER_REDUCTION,
                 "half reduction placement");
-  if constexpr (MODE == NTT_DIGIT2) {
-    // two primes per digit: the value of digit j in this prime is
-    // v_0 + [q_{2j}]_p v_1 (see k_ntt_fwd), formed for both operands of
-    // stage 0 as they load; loads pipelined as below, groups of 4 (four
-    // loads per element)
-    const int ct = poly / job.digits;
-    const int j = poly - ct * job.digits;
-    const double* s0 = job.src + (size_t)ct * job.src_ct_stride + (size_t)(2 * j) * NF;
-    const auto rs0 = make_rsrc(s0, NF * 8);
-    const auto rs1 = make_rsrc(s0 + NF, NF * 8);
-    const double cq = cld(tb.dig_c, j * job.nlimb + limb);
-    constexpr int G = 4;
-    double ax[2][G], bx[2][G], ay[2][G], by[2][G];
-#pragma unroll
-    for (int i = 0; i < G; ++i) {
-      ax[0][i] = buf_load(rs0, vo, i * S::T * 8);
-      bx[0][i] = buf_load(rs1, vo, i * S::T * 8);
-      ay[0][i] = buf_load(rs0, vo, (i * S::T + (NF >> 1)) * 8);
-      by[0][i] = buf_load(rs1, vo, (i * S::T + (NF >> 1)) * 8);
-    }
-#pragma unroll
-    for (int g = 0; g < S::E; g += G) {
-      const int slot = (g / G) & 1;
-      if (g + G < S::E) {
-        unsigned v = vo;
-        if (g) asm volatile("" : "+v"(v) : "v"(x[g - 1]));
-#pragma unroll
-        for (int i = 0; i < G; ++i) {
-          const unsigned ox = (g + G + i) * S::T * 8, oy = ((g + G + i) * S::T + (NF >> 1)) * 8;
-          ax[slot ^ 1][i] = buf_load(rs0, v, ox);
-          bx[slot ^ 1][i] = buf_load(rs1, v, ox);
-          ay[slot ^ 1][i] = buf_load(rs0, v, oy);
-          by[slot ^ 1][i] = buf_load(rs1, v, oy);
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < G; ++i) {
-        const double X = ax[slot][i] + mul_lazy(bx[slot][i], cq, p, pinv);
-        const double Y = ay[slot][i] + mul_lazy(by[slot][i], cq, p, pinv);
-        x[g + i] = X + mul_lazy(Y, w0, p, pinv);
-      }
-    }
-  } else if constexpr (MODE == NTT_DIGIT3) {
-    // three primes per digit: both stage-0 operands' values formed as they
-    // load (k_ntt_fwd), then the stage-0 output reduced to balanced form
-    // (the operands are below 3.3 p, the output below 4.2 p); loads in
-    // groups of 2, pipelined as below (six loads per element)
-    const int ct = poly / job.digits;
-    const int j = poly - ct * job.digits;
-    const double* s0 = job.src + (size_t)ct * job.src_ct_stride + (size_t)(3 * j) * NF;
-    const auto rs0 = make_rsrc(s0, NF * 8);
-    const auto rs1 = make_rsrc(s0 + NF, NF * 8);
-    const auto rs2 = make_rsrc(s0 + 2 * NF, NF * 8);
-    const double c1 = cld(tb.dig_c, (j * job.nlimb + limb) * 2);
-    const double c2 = cld(tb.dig_c, (j * job.nlimb + limb) * 2 + 1);
-    constexpr int G = 2;
-    double ax[2][G], bx[2][G], cx[2][G], ay[2][G], by[2][G], cy[2][G];
-#pragma unroll
-    for (int i = 0; i < G; ++i) {
-      const unsigned ox = i * S::T * 8, oy = (i * S::T + (NF >> 1)) * 8;
-      ax[0][i] = buf_load(rs0, vo, ox);
-      bx[0][i] = buf_load(rs1, vo, ox);
-      cx[0][i] = buf_load(rs2, vo, ox);
-      ay[0][i] = buf_load(rs0, vo, oy);
-      by[0][i] = buf_load(rs1, vo, oy);
-      cy[0][i] = buf_load(rs2, vo, oy);
-    }
-#pragma unroll
-    for (int g = 0; g < S::E; g += G) {
-      const int slot = (g / G) & 1;
-      if (g + G < S::E) {
-        unsigned v = vo;
-        if (g) asm volatile("" : "+v"(v) : "v"(x[g - 1]));
-#pragma unroll
-        for (int i = 0; i < G; ++i) {
-          const unsigned ox = (g + G + i) * S::T * 8, oy = ((g + G + i) * S::T + (NF >> 1)) * 8;
-          ax[slot ^ 1][i] = buf_load(rs0, v, ox);
-          bx[slot ^ 1][i] = buf_load(rs1, v, ox);
-          cx[slot ^ 1][i] = buf_load(rs2, v, ox);
-          ay[slot ^ 1][i] = buf_load(rs0, v, oy);
-          by[slot ^ 1][i] = buf_load(rs1, v, oy);
-          cy[slot ^ 1][i] = buf_load(rs2, v, oy);
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < G; ++i) {
-        const double X = ax[slot][i] + mul_lazy(bx[slot][i], c1, p, pinv) +
-                         mul_lazy(cx[slot][i], c2, p, pinv);
-        const double Y = ay[slot][i] + mul_lazy(by[slot][i], c1, p, pinv) +
-                         mul_lazy(cy[slot][i], c2, p, pinv);
-        x[g + i] = reduce_bal(X + mul_lazy(Y, w0, p, pinv), p, pinv);
-      }
-    }
-  } else {
-    // digit sources hold canonical digits in [0, q_j), below 2 p_i
-    const double* src = job.base + off;
-    if constexpr (MODE == NTT_DIGIT) {
-      const int ct = poly / job.digits;
-      const int j = poly - ct * job.digits;
-      src = job.src + (size_t)ct * job.src_ct_stride + (size_t)j * NF;
-    }
-    const auto rs = make_rsrc(src, NF * 8);
+  {
+    const auto rs = make_rsrc(job.base + off, NF * 8);
     // Loads in groups of G elements, software-pipelined one group ahead:
     // group g + 1 is issued (fenced on group g - 1's results) before group g
     // is processed, so at most two groups of loads are in flight.
@@ -1051,36 +937,187 @@ k_ntt_fwd_half(NttJob job, Tables tb) {
 #pragma unroll
   for (int r = 0; r < S::ROUNDS; ++r) {
     if (r > 0) exchange<14>(x, r - 1, r, lds, r > 1);
-    // The ten stages to the end of round 1 leave values below 13.5 p (15.1 p
-    // from two-prime digits, ct_bound; three-prime digits start reduced).  Only
-    // the X operands of round 2's first stage (elements 0..E/2-1: it pairs
-    // e with e + E/2) are reduced, at that round's start: its products
-    // take |Y| < 15.1 p (results below 2.1 p), so it outputs below 2.6 p
-    // and the last four stages below 6.1 p (ct_bfly's bound), half the
-    // reductions of reducing every value after round 1.
-    // digit transforms skip the final reduction (outputs below 5.9 p):
-    // their only reader, the key-switch product, reduces its sums itself
-    fwd_round<14, true>(x, r,
-                        fwd_reduces_after<14>(r, 1) && r != HALF_REDUCE_ROUND - 1 &&
-                            !((MODE == NTT_DIGIT || MODE == NTT_DIGIT2 || MODE == NTT_DIGIT3) &&
-                              r == S::ROUNDS - 1),
-                        tw, p, pinv, ltw, r == HALF_REDUCE_ROUND);
+    // Inputs are residues of the limb's prime (below p in absolute value):
+    // the ten stages to the end of round 1 leave values below 13.5 p
+    // (ct_bound, as from inputs below 2 p).  Only the X operands of round
+    // 2's first stage (elements 0..E/2-1: it pairs e with e + E/2) are
+    // reduced, at that round's start: its products take |Y| < 13.5 p
+    // (results below 1.9 p), so it outputs below 2.4 p and the last four
+    // stages below 6 p (ct_bfly's bound), half the reductions of reducing
+    // every value after round 1; the last round reduces every value.
+    fwd_round<14, true>(x, r, fwd_reduces_after<14>(r, 1) && r != HALF_REDUCE_ROUND - 1, tw, p,
+                        pinv, ltw, r == HALF_REDUCE_ROUND);
   }
   const unsigned so = (h * S::T + tid) * 8;
 #pragma unroll
   for (int e = 0; e < S::E; ++e) buf_store(x[e], rd, so, e * 1024 * 8);
 }
 
+// Digit transforms of 2^15-point limbs by coefficient parity.  With x_e
+// and x_o a digit's even and odd coefficients, x(z) = x_e(z^2) + z x_o(z^2);
+// the full transform's standard positions 2k and 2k + 1 are the points z
+// and -z, z = psi^(2 brv_14(k) + 1), so its outputs there are
+// E_k + z O_k and E_k - z O_k, E and O the 2^14-point negacyclic transforms
+// of x_e and x_o for the root psi^2.  Since psi^(2 brv_14(i)) =
+// psi^(brv_15(i)) for i < 2^14, those transforms use the full transform's
+// twiddles of stages 0..13 (slot 2^s + m).  One workgroup of 512 threads
+// takes one parity h of one (digit, target prime): it loads every second
+// coefficient of the digit's sources (the other parity's workgroup, on the
+// same XCD, reads the other half of the same cache lines), forms each
+// value in the target prime once, and stores the unreduced result to half
+// h of the limb in the 2^14 transform's order (standard index k at
+// (k mod 32) 512 + k / 32).  The last stage, E_k +- z O_k, is left to the
+// key-switch product (k_ks_mac_par): unlike a split by the top index bit
+// (k_ntt_fwd_half), no source is loaded, and no digit value formed, twice.
+//
+// Bounds: nine stages (rounds 0 and 1) from a one-prime digit below 2 p or a
+// two-prime one below 2.61 p stay below 13.2 p (three-prime digits start
+// reduced); round 2 reduces the X operands of its first stage only, so that
+// stage ends below (1/2 + 1/2 + 0.103 x 13.2) p and the last four below
+// PAR_OUT p; the key-switch product's E + z O then stays below 7 p.
+constexpr double PAR_MID = ct_bound(DIGIT2_IN, 9);
+constexpr double PAR_OUT = ct_bound(1.0 + 0.103 * PAR_MID, 4);
+static_assert(PAR_MID < 15.1 && PAR_OUT < 5.9 && 1.103 * PAR_OUT + 0.5 < 7.0,
+              "parity digit transform bounds");
+static_assert(ct_bound(DIGIT_IN, 9) < PAR_MID, "one-prime digits are the smaller");
+
+template <int MODE>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
+k_ntt_fwd_par(NttJob job, Tables tb) {
+  using S = NttShape<14>;
+  constexpr int NF = 1 << 15;
+  constexpr int R1 = 1 << S::s_start(1);   // round 1's index rows
+  static_assert(R1 * LDS_ROW == 512, "one table entry per thread");
+  static_assert(MODE == NTT_DIGIT || MODE == NTT_DIGIT2 || MODE == NTT_DIGIT3, "digit modes");
+  __shared__ uint32_t lds[S::LDS_WORDS];
+  __shared__ double ltw[R1 * LDS_ROW];
+  // the digit transforms' XCD split (k_ntt_fwd), the two parities of a
+  // (source, prime) pair in consecutive workgroups of one XCD
+  const int xc = blockIdx.x & 7, l2 = blockIdx.x >> 3;
+  const int h = l2 & 1;
+  const int l = l2 >> 1;
+  const int ph = (job.nlimb + 1) >> 1;
+  const int g = xc & 1;
+  const int np = g ? job.nlimb - ph : ph;
+  const int sq = (job.npoly + 3) >> 2;
+  const int src = (xc >> 1) * sq + l / np;
+  if (l / np >= sq || src >= job.npoly) return;
+  const int poly = src;
+  const int limb = g * ph + l % np;
+  const int prime = cldi(job.limb_prime, limb);
+  const double p = cld(tb.p, prime), pinv = cld(tb.pinv, prime);
+  const TwSrc tw{tb.tw_fwd + (size_t)prime * tb.tw_len,
+                 tb.tw_cmp_par + (size_t)prime * tb.tw_cmp_h_len,
+                 tb.tw_cst_f + (size_t)prime * 32};
+  // round 1's rows into LDS (read after the first exchange's barriers)
+  ltw[threadIdx.x] = tb.tw_r1_par[(size_t)prime * 512 + threadIdx.x];
+  const int ct = poly / job.digits;
+  const int j = poly - ct * job.digits;
+  const double* s0 = job.src + (size_t)ct * job.src_ct_stride + (size_t)(MODE == NTT_DIGIT3 ? 3 * j : MODE == NTT_DIGIT2 ? 2 * j : j) * NF;
+  // element e of thread tid in round 0 is sub-index e 512 + tid, source
+  // coefficient 2 (e 512 + tid) + h
+  const int tid = threadIdx.x;
+  const unsigned vo = (2 * tid + h) * 8;
+  constexpr unsigned ES = 2 * S::T * 8;
+  double x[S::E];
+  if constexpr (MODE == NTT_DIGIT) {
+    // canonical digits in [0, q_j), below 2 p
+    const auto rs = make_rsrc(s0, NF * 8);
+#pragma unroll
+    for (int e = 0; e < S::E; ++e) x[e] = buf_load(rs, vo, e * ES);
+  } else if constexpr (MODE == NTT_DIGIT2) {
+    // v_0 + [q_{2j}]_p v_1, below DIGIT2_IN p; loads one group of G ahead,
+    // each group's addresses fenced on the previous group's results
+    const auto rs0 = make_rsrc(s0, NF * 8);
+    const auto rs1 = make_rsrc(s0 + NF, NF * 8);
+    const double cq = cld(tb.dig_c, j * job.nlimb + limb);
+    constexpr int G = 8;
+    double ax[2][G], bx[2][G];
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+      ax[0][i] = buf_load(rs0, vo, i * ES);
+      bx[0][i] = buf_load(rs1, vo, i * ES);
+    }
+#pragma unroll
+    for (int g0 = 0; g0 < S::E; g0 += G) {
+      const int slot = (g0 / G) & 1;
+      if (g0 + G < S::E) {
+        unsigned v = vo;
+        if (g0) asm volatile("" : "+v"(v) : "v"(x[g0 - 1]));
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+          ax[slot ^ 1][i] = buf_load(rs0, v, (g0 + G + i) * ES);
+          bx[slot ^ 1][i] = buf_load(rs1, v, (g0 + G + i) * ES);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < G; ++i) x[g0 + i] = ax[slot][i] + mul_lazy(bx[slot][i], cq, p, pinv);
+    }
+  } else {
+    // v_0 + [q_g]_p v_1 + [q_g q_{g+1}]_p v_2 reduced to balanced form
+    // (k_ntt_fwd); loads as above
+    const auto rs0 = make_rsrc(s0, NF * 8);
+    const auto rs1 = make_rsrc(s0 + NF, NF * 8);
+    const auto rs2 = make_rsrc(s0 + 2 * NF, NF * 8);
+    const double c1 = cld(tb.dig_c, (j * job.nlimb + limb) * 2);
+    const double c2 = cld(tb.dig_c, (j * job.nlimb + limb) * 2 + 1);
+    constexpr int G = 4;
+    double ax[2][G], bx[2][G], cx[2][G];
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+      ax[0][i] = buf_load(rs0, vo, i * ES);
+      bx[0][i] = buf_load(rs1, vo, i * ES);
+      cx[0][i] = buf_load(rs2, vo, i * ES);
+    }
+#pragma unroll
+    for (int g0 = 0; g0 < S::E; g0 += G) {
+      const int slot = (g0 / G) & 1;
+      if (g0 + G < S::E) {
+        unsigned v = vo;
+        if (g0) asm volatile("" : "+v"(v) : "v"(x[g0 - 1]));
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+          ax[slot ^ 1][i] = buf_load(rs0, v, (g0 + G + i) * ES);
+          bx[slot ^ 1][i] = buf_load(rs1, v, (g0 + G + i) * ES);
+          cx[slot ^ 1][i] = buf_load(rs2, v, (g0 + G + i) * ES);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < G; ++i)
+        x[g0 + i] = reduce_bal(ax[slot][i] + mul_lazy(bx[slot][i], c1, p, pinv) +
+                                   mul_lazy(cx[slot][i], c2, p, pinv),
+                               p, pinv);
+    }
+  }
+  // the forward schedule would reduce after round 1 (nine stages) and at
+  // the end: the first is replaced by the reduction of round 2's first-stage
+  // X operands, the second left to the key-switch product (bounds above)
+  static_assert(S::ROUNDS == 3 && S::stages(0) + S::stages(1) == 9 &&
+                    !fwd_reduces_after<14>(0, 0) && fwd_reduces_after<14>(1, 0),
+                "parity reduction placement");
+#pragma unroll
+  for (int r = 0; r < S::ROUNDS; ++r) {
+    if (r > 0) exchange<14>(x, r - 1, r, lds, r > 1);
+    fwd_round<14, true>(x, r, false, tw, p, pinv, ltw, r == 2);
+  }
+  const auto rd = make_rsrc(job.out + (size_t)poly * job.poly_stride + (size_t)limb * NF +
+                                (size_t)h * (NF / 2),
+                            NF / 2 * 8);
+#pragma unroll
+  for (int e = 0; e < S::E; ++e) buf_store(x[e], rd, tid * 8, e * S::T * 8);
+}
+
 // The key-switch product fused with the digit transforms (N = 2^15): a
 // workgroup of 512 threads takes one ciphertext, one target prime of the
 // key-switching basis (limb i < L + 1) and one output half h, and for each
 // digit D_j = [c2]_{q_j}, j = 0..L-1, runs the half-limb forward transform
-// of k_ntt_fwd_half (NTT_DIGIT) in prime i, then multiplies the result by
+// (the split by the top index bit of k_ntt_fwd_half) in prime i, then multiplies the result by
 // the key's NTT-domain limbs evk[j][0][i] and evk[j][1][i] (same positions)
 // and adds the products to two sums held in registers across the digits.
 // The digits' transforms are never written; the sums are written once, in
 // the layout of k_ks_mac's output (the split inverse's input).  Bounds: the
-// unreduced digit transforms stay below 5.9 p (k_ntt_fwd_half), so each
+// unreduced digit transforms stay below 6 p (k_ntt_fwd_half's schedule
+// from inputs below 2 p), so each
 // lazy product with a balanced key is below 1.05 p and eight of them plus
 // a reduced sum below 9 p < 2^53 / p: the sums are reduced every 8 digits.
 // Work items: ciphertexts in groups of CG = min(4, n_ct); within a group,
@@ -1309,16 +1346,19 @@ static hipError_t launch_ntt(const NttJob& job, const Tables& tb, int dir, hipSt
         hipLaunchKernelGGL((k_ntt_inv_half<INV_TENSOR2>), grid, block, 0, st, job, tb);
       return hipGetLastError();
     }
-    if (((dir == 0 && job.out && job.out != job.base) || dir == 2) && tb.tw_half && job.split) {
+    if (dir == 2 && job.parity && job.split && tb.tw_cmp_par) {
       dim3 grid(per_xcd(job, dir, 2) * 8), block(512);
-      if (dir == 0)
-        hipLaunchKernelGGL((k_ntt_fwd_half<NTT_INPLACE>), grid, block, 0, st, job, tb);
-      else if (job.alpha == 2)
-        hipLaunchKernelGGL((k_ntt_fwd_half<NTT_DIGIT2>), grid, block, 0, st, job, tb);
+      if (job.alpha == 2)
+        hipLaunchKernelGGL((k_ntt_fwd_par<NTT_DIGIT2>), grid, block, 0, st, job, tb);
       else if (job.alpha == 3)
-        hipLaunchKernelGGL((k_ntt_fwd_half<NTT_DIGIT3>), grid, block, 0, st, job, tb);
+        hipLaunchKernelGGL((k_ntt_fwd_par<NTT_DIGIT3>), grid, block, 0, st, job, tb);
       else
-        hipLaunchKernelGGL((k_ntt_fwd_half<NTT_DIGIT>), grid, block, 0, st, job, tb);
+        hipLaunchKernelGGL((k_ntt_fwd_par<NTT_DIGIT>), grid, block, 0, st, job, tb);
+      return hipGetLastError();
+    }
+    if (dir == 0 && job.out && job.out != job.base && tb.tw_half && job.split) {
+      dim3 grid(per_xcd(job, dir, 2) * 8), block(512);
+      hipLaunchKernelGGL((k_ntt_fwd_half<NTT_INPLACE>), grid, block, 0, st, job, tb);
       return hipGetLastError();
     }
   }

@@ -400,6 +400,86 @@ __global__ void __launch_bounds__(256) k_ks_mac(int n, int n_ct, const double* d
   }
 }
 
+// k_ks_mac for digit transforms by coefficient parity (k_ntt_fwd_par,
+// N = 2^15): half 0 of a digit's limb holds E, half 1 holds O, both in the
+// 2^14 transform's order (standard index k at (k mod 32) 512 + k / 32).
+// Thread (u, m), u < 16, m < 1024, takes k = 16 m + u, whose values in the
+// full transform are X_0 = E_k + z O_k and X_1 = E_k - z O_k (z =
+// psi^brv(2^14 + k), tw_last), at its standard positions 2k and 2k + 1:
+// stored, as the key and the sums are, at 2u 1024 + m and (2u + 1) 1024 + m
+// (consecutive threads, consecutive addresses); E_k and O_k sit at
+// (16 (m mod 2) + u) 512 + m / 2.  The sums are those of k_ks_mac.
+// Bounds: |E|, |O| < 5.9 p, so |X| < 7 p and each product with a balanced
+// key is below 1.16 p: eight of them plus a reduced sum stay below 15.9 p.
+template <int L, int A, int CH>
+__global__ void __launch_bounds__(256) k_ks_mac_par(int n_ct, const double* dig,
+                                                    const double* evk, double* acc, Tables tb) {
+  constexpr int K = L + A;
+  constexpr int DN = L / A;
+  constexpr int NF = 1 << 15, NH = NF / 2;
+  const int gid = blockIdx.x * 256 + threadIdx.x;
+  if (gid >= K * NH) return;
+  const int i = gid >> 14;
+  const int t = gid & (NH - 1);
+  const int u = t >> 10, m = t & 1023;
+  const int prime = i < L ? i : L + 1 + i;
+  const double p = cld(tb.p, prime), pinv = cld(tb.pinv, prime);
+  const double z = tb.tw_last[(size_t)i * NH + t];
+  const size_t pe = (size_t)(((m & 1) << 4) + u) * 512 + (m >> 1);
+  const size_t p0 = (size_t)(2 * u) * 1024 + m;
+  for (int c0 = 0; c0 < n_ct; c0 += CH) {
+    // [key component][position] per ciphertext of the chunk
+    double a00[CH], a01[CH], a10[CH], a11[CH];
+#pragma unroll
+    for (int v = 0; v < CH; ++v) a00[v] = a01[v] = a10[v] = a11[v] = 0.0;
+    for (int j = 0; j < DN; ++j) {
+      const double* kj = evk + ((size_t)(j * 2) * K + i) * NF + p0;
+      const double e00 = kj[0], e01 = kj[1024];
+      const double e10 = kj[(size_t)K * NF], e11 = kj[(size_t)K * NF + 1024];
+      // every load of the chunk is issued before the products: past the
+      // last ciphertext the index is clamped (a valid address) and the
+      // result is never stored
+      double ev[CH], od[CH];
+#pragma unroll
+      for (int v = 0; v < CH; ++v) {
+        const int cv = c0 + v < n_ct ? c0 + v : n_ct - 1;
+        const double* dp = dig + ((size_t)(cv * DN + j) * K + i) * NF + pe;
+        ev[v] = __builtin_nontemporal_load(dp);
+        od[v] = __builtin_nontemporal_load(dp + NH);
+      }
+#pragma unroll
+      for (int v = 0; v < CH; ++v) {
+        const double w = mul_lazy(od[v], z, p, pinv);
+        const double x0 = ev[v] + w, x1 = ev[v] - w;
+        a00[v] += mul_lazy(x0, e00, p, pinv);
+        a01[v] += mul_lazy(x1, e01, p, pinv);
+        a10[v] += mul_lazy(x0, e10, p, pinv);
+        a11[v] += mul_lazy(x1, e11, p, pinv);
+      }
+      if ((j & 7) == 7) {
+#pragma unroll
+        for (int v = 0; v < CH; ++v) {
+          a00[v] = reduce_bal(a00[v], p, pinv);
+          a01[v] = reduce_bal(a01[v], p, pinv);
+          a10[v] = reduce_bal(a10[v], p, pinv);
+          a11[v] = reduce_bal(a11[v], p, pinv);
+        }
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < CH; ++v) {
+      if (c0 + v < n_ct) {
+        double* o0 = acc + ((size_t)((c0 + v) * 2 + 0) * K + i) * NF + p0;
+        double* o1 = acc + ((size_t)((c0 + v) * 2 + 1) * K + i) * NF + p0;
+        o0[0] = reduce_bal(a00[v], p, pinv);
+        o0[1024] = reduce_bal(a01[v], p, pinv);
+        o1[0] = reduce_bal(a10[v], p, pinv);
+        o1[1024] = reduce_bal(a11[v], p, pinv);
+      }
+    }
+  }
+}
+
 // A special limb's residues [N^-1 x]_{P_k} (balanced) at coefficients c and
 // c + N/2 from the split inverse's half outputs U (at a) and V (at a + ht):
 // the inverse's last stage (U + V, (U - V) w) applied here.
@@ -1335,6 +1415,47 @@ hipError_t run_ks_mac(const Dims& d, const double* dig, const double* evk, doubl
   // (clamped) loads and products: halve it down to them
   int ch = d.ks_chunk;
   while (ch > 4 && ch / 2 >= d.n_ct) ch /= 2;
+  if (d.parity) {
+    // four sums per ciphertext of a chunk: at most 16 ciphertexts
+    if (d.n != (1 << 15)) return hipErrorInvalidValue;
+    const size_t tp = (size_t)(d.L + d.alpha) * (d.n / 2);
+    if (ch > 16) ch = 16;
+#define P_(L_, A_) \
+  case L_:                                                                                     \
+    if (ch == 4)                                                                               \
+      hipLaunchKernelGGL((k_ks_mac_par<L_, A_, 4>), grid_for(tp), dim3(256), 0, st, d.n_ct, dig, evk, acc, tb); \
+    else if (ch == 8)                                                                          \
+      hipLaunchKernelGGL((k_ks_mac_par<L_, A_, 8>), grid_for(tp), dim3(256), 0, st, d.n_ct, dig, evk, acc, tb); \
+    else                                                                                       \
+      hipLaunchKernelGGL((k_ks_mac_par<L_, A_, 16>), grid_for(tp), dim3(256), 0, st, d.n_ct, dig, evk, acc, tb); \
+    break;
+#define P1_(L_) P_(L_, 1)
+#define P2_(L_) P_(L_, 2)
+#define P3_(L_) P_(L_, 3)
+    if (d.alpha == 1) {
+      switch (d.L) {
+        NSHE_L_CASES(P1_)
+        default: return hipErrorInvalidValue;
+      }
+    } else if (d.alpha == 2) {
+      switch (d.L) {
+        NSHE_L2_CASES(P2_)
+        default: return hipErrorInvalidValue;
+      }
+    } else if (d.alpha == 3) {
+      switch (d.L) {
+        NSHE_L3_CASES(P3_)
+        default: return hipErrorInvalidValue;
+      }
+    } else {
+      return hipErrorInvalidValue;
+    }
+#undef P1_
+#undef P2_
+#undef P3_
+#undef P_
+    return hipGetLastError();
+  }
 #define C_(L_, A_) \
   case L_:                                                                                     \
     if (ch == 4)                                                                               \
