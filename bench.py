@@ -316,9 +316,10 @@ def batched_check(cp: dict, wave: int, alpha: int = 1) -> dict:
 
 
 def probes(ctx) -> dict:
-    """The ceilings: the exact modular product's chip-wide rate, and one
-    base conversion (17 -> 18 primes over the scale-and-round's 3 x 2^20
-    coefficients) by split-FMA rows and by integer MFMA."""
+    """The ceilings: the exact modular product's chip-wide rate, whether FP64
+    MFMA adds FP64 throughput to the VALU, and one base conversion (17 -> 18
+    primes over the scale-and-round's 3 x 2^20 coefficients) by split-FMA
+    rows and by integer MFMA."""
     import ctypes
     from paper_2602_24271_amd import _lib
     lib = _lib.load()
@@ -326,6 +327,11 @@ def probes(ctx) -> dict:
     _lib.check(lib.nshe_probe_modmul(0, 4096, ctypes.byref(m)))
     out = {"modmul": {"products_per_s": m.products_per_s, "fp64_ops_per_s": m.fp64_ops_per_s,
                       "frac_of_issue_peak": m.fp64_ops_per_s / PEAK_FP64_OPS}}
+    ov = _lib.NsheOverlapProbe()
+    _lib.check(lib.nshe_probe_fp64_overlap(0, 2000, ctypes.byref(ov)))
+    out["fp64_mfma_overlap"] = {"ms_valu": ov.ms_valu, "ms_mfma": ov.ms_mfma, "ms_both": ov.ms_both,
+                                "fma_per_s_valu": ov.fma_per_s_valu,
+                                "fma_per_s_mfma": ov.fma_per_s_mfma}
     # the probe is built for 17 -> 18 primes: the one-special-prime basis
     from paper_2602_24271_amd import Context
     c17 = ctx if ctx.L == 17 else Context.paper(15)
@@ -338,6 +344,7 @@ def probes(ctx) -> dict:
                                   "ms_mfma_i8": r.ms_mfma, "mismatches": r.mismatches}
     if c17 is not ctx:
         c17.close()
+    log(f"probes: FP64 VALU {ov.ms_valu:.2f} ms, MFMA {ov.ms_mfma:.2f} ms, both {ov.ms_both:.2f} ms")
     log(f"probes: modmul {m.fp64_ops_per_s / 1e12:.1f} T FP64 ops/s; conversion fma "
         f"{r.ms_fma:.3f} ms, mfma {r.ms_mfma:.3f} ms, mismatches {r.mismatches}")
     return out

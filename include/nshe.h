@@ -415,10 +415,14 @@ int nshe_sum_slots(nshe_ctx* ctx, const int64_t* in_dev, int64_t* out_dev, int n
 /* Launch shapes and the autotuner.  Results never depend on the tuning
  * (every kernel computes the same exact integers); only the speed does.
  *   ks_chunk       ciphertexts accumulated per pass over the relinearization
- *                  key in the key-switch inner product: 4, 8, 16 or 32;
+ *                  key in the key-switch inner product: 4, 8, 16 or 32
+ *                  (at most 16 are used with digit transforms by parity);
  *   split_forward  1: each 2^15-point forward transform runs as two
- *                  workgroups (one per output half), 0: one workgroup per
- *                  limb (ignored for smaller N);
+ *                  workgroups: one per output half, and for the key-switch
+ *                  digits one per coefficient parity (two 2^14-point
+ *                  transforms whose last radix-2 stage the key-switch
+ *                  product applies); 0: one workgroup per limb (ignored
+ *                  for smaller N);
  *   ew_block       threads per workgroup of the per-coefficient kernels
  *                  (base lift, scale-and-round, mod-down): 64, 128 or 256;
  *   wave_ct        ciphertexts per wave of nshe_eq_mask_batched when its

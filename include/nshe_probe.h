@@ -17,7 +17,16 @@
  *   over `reps` launches after one warm-up pass, and `mismatches` counts
  *   outputs where the two differ mod m_k (must be 0).
  *
- * Both allocate and free their own device buffers on `hip_device` and
+ * nshe_probe_fp64_overlap  whether FP64 matrix instructions add FP64
+ *   throughput to the vector ALU: the same grid (256 x 16 workgroups of 256
+ *   threads, `iters` iterations) runs 64 FP64 FMAs per lane and iteration on
+ *   the VALU (eight independent chains), or four independent
+ *   v_mfma_f64_16x16x4f64 per wave and iteration (the same FMA count), or
+ *   both interleaved in every wave; the second of two timed launches of each
+ *   is reported.  Independent units would give ms_both near the larger of
+ *   ms_valu and ms_mfma; one shared pipeline gives their sum.
+ *
+ * All allocate and free their own device buffers on `hip_device` and
  * synchronise it.  They return 0, or a negative code with a message from
  * nshe_probe_last_error().
  */
@@ -44,7 +53,16 @@ typedef struct {
   uint64_t mismatches;    /* outputs that differ (mod m_k) */
 } nshe_conv_probe;
 
+typedef struct {
+  double ms_valu;         /* VALU FMAs only, one launch */
+  double ms_mfma;         /* FP64 MFMA only */
+  double ms_both;         /* both in every wave */
+  double fma_per_s_valu;  /* lane-level FMAs per second, chip-wide */
+  double fma_per_s_mfma;
+} nshe_overlap_probe;
+
 int nshe_probe_modmul(int hip_device, int iters, nshe_modmul_probe* out_host);
+int nshe_probe_fp64_overlap(int hip_device, int iters, nshe_overlap_probe* out_host);
 int nshe_probe_conversion(int hip_device, const uint64_t* in_primes_host, int n_in,
                           const uint64_t* out_primes_host, int n_out, size_t n_coef, int reps,
                           nshe_conv_probe* out_host);

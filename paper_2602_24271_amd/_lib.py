@@ -65,6 +65,12 @@ class NsheModmulProbe(ctypes.Structure):
                 ("fp64_ops_per_s", ctypes.c_double)]
 
 
+class NsheOverlapProbe(ctypes.Structure):
+    _fields_ = [("ms_valu", ctypes.c_double), ("ms_mfma", ctypes.c_double),
+                ("ms_both", ctypes.c_double), ("fma_per_s_valu", ctypes.c_double),
+                ("fma_per_s_mfma", ctypes.c_double)]
+
+
 class NsheConvProbe(ctypes.Structure):
     _fields_ = [("coefficients", ctypes.c_uint64), ("ms_fma", ctypes.c_double),
                 ("ms_mfma", ctypes.c_double), ("mismatches", ctypes.c_uint64)]
@@ -122,6 +128,7 @@ SIGNATURES = {
     "nshe_last_error": (ctypes.c_char_p, []),
     # measurement entry points (include/nshe_probe.h)
     "nshe_probe_modmul": (_I, [_I, _I, ctypes.POINTER(NsheModmulProbe)]),
+    "nshe_probe_fp64_overlap": (_I, [_I, _I, ctypes.POINTER(NsheOverlapProbe)]),
     "nshe_probe_conversion": (_I, [_I, ctypes.POINTER(ctypes.c_uint64), _I,
                                    ctypes.POINTER(ctypes.c_uint64), _I, _SZ, _I,
                                    ctypes.POINTER(NsheConvProbe)]),

@@ -55,6 +55,43 @@ __global__ void __launch_bounds__(256) k_probe_modmul(double* out, int iters, do
   out[gid] = s;
 }
 
+// -------------------------------------------------- FP64 MFMA overlap ---
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// MODE 0: 64 FP64 FMAs per lane and iteration (eight chains); 1: four
+// independent 16x16x4 FP64 MFMAs per wave and iteration (4096 FMAs per
+// wave, 64 per lane); 2: both.
+template <int MODE>
+__global__ void __launch_bounds__(256) k_probe_overlap(double* out, int iters, double seed) {
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double a = seed + (double)threadIdx.x, b = 1.0 + 1e-9 * (double)threadIdx.x;
+  double v[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) v[c] = a + c;
+  v4d acc[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) acc[c] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int it = 0; it < iters; ++it) {
+    if constexpr (MODE != 0) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
+    }
+    if constexpr (MODE != 1) {
+#pragma unroll
+      for (int r = 0; r < 8; ++r)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) v[c] = __builtin_fma(v[c], b, 1e-300);
+    }
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) s += v[c];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) s += acc[c][0] + acc[c][1] + acc[c][2] + acc[c][3];
+  out[gid] = s;
+}
+
 // ------------------------------------------------------- conversion ---
 
 // Balanced pseudo-random residues: v[r][c] for row r (prime m[r]).
@@ -366,6 +403,43 @@ int nshe_probe_modmul(int hip_device, int iters, nshe_modmul_probe* out) {
   out->ms = ms;
   out->products_per_s = products / (ms * 1e-3);
   out->fp64_ops_per_s = out->products_per_s * 6.0;
+  return 0;
+}
+
+int nshe_probe_fp64_overlap(int hip_device, int iters, nshe_overlap_probe* out) {
+  if (!out || iters < 1) return probe_fail("bad argument");
+  PCHK(hipSetDevice(hip_device));
+  const int blocks = 256 * 16, threads = 256;
+  DevBuf buf;
+  PCHK(hipMalloc(&buf.p, (size_t)blocks * threads * 8));
+  double* o = static_cast<double*>(buf.p);
+  hipEvent_t e0, e1;
+  PCHK(hipEventCreate(&e0));
+  PCHK(hipEventCreate(&e1));
+  float ms[3] = {0.f, 0.f, 0.f};
+  for (int mode = 0; mode < 3; ++mode) {
+    for (int pass = 0; pass < 2; ++pass) {
+      PCHK(hipEventRecord(e0, 0));
+      if (mode == 0)
+        hipLaunchKernelGGL(k_probe_overlap<0>, dim3(blocks), dim3(threads), 0, 0, o, iters, 1.0);
+      else if (mode == 1)
+        hipLaunchKernelGGL(k_probe_overlap<1>, dim3(blocks), dim3(threads), 0, 0, o, iters, 1.0);
+      else
+        hipLaunchKernelGGL(k_probe_overlap<2>, dim3(blocks), dim3(threads), 0, 0, o, iters, 1.0);
+      PCHK(hipGetLastError());
+      PCHK(hipEventRecord(e1, 0));
+      PCHK(hipEventSynchronize(e1));
+      PCHK(hipEventElapsedTime(&ms[mode], e0, e1));
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  const double fmas = (double)blocks * threads * 64 * iters;
+  out->ms_valu = ms[0];
+  out->ms_mfma = ms[1];
+  out->ms_both = ms[2];
+  out->fma_per_s_valu = fmas / (ms[0] * 1e-3);
+  out->fma_per_s_mfma = fmas / (ms[1] * 1e-3);
   return 0;
 }
 

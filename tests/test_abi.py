@@ -18,7 +18,7 @@ HEADERS = [os.path.join(ROOT, "include", h) for h in ("nshe.h", "nshe_probe.h")]
 def _declared():
     text = "".join(open(h).read() for h in HEADERS)
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(nshe_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(nshe_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_declares_the_expected_calls():
@@ -178,6 +178,8 @@ _STRUCTS = {
     "nshe_kernel_stat": ("NsheKernelStat", ["name", "launches", "total_ms", "work"]),
     "nshe_modmul_probe": ("NsheModmulProbe", ["ms", "products_per_s", "fp64_ops_per_s"]),
     "nshe_conv_probe": ("NsheConvProbe", ["coefficients", "ms_fma", "ms_mfma", "mismatches"]),
+    "nshe_overlap_probe": ("NsheOverlapProbe", ["ms_valu", "ms_mfma", "ms_both", "fma_per_s_valu",
+                                                "fma_per_s_mfma"]),
 }
 
 
