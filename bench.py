@@ -81,6 +81,56 @@ def kernel_hash() -> str:
 OPS_PER_MODUP = 7
 
 
+# One term y M of a base-conversion row, computed exactly as four FMAs on
+# 24-bit halves (y = y_h 2^24 + y_l, M = c1 2^24 + c0).
+OPS_PER_CONV_TERM = 4
+
+
+def _traffic(kind: str):
+    """HBM bytes per launch of a kernel kind from profiles/traffic.json, while
+    the built library is the profiled one."""
+    tf = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(tf):
+        return None
+    with open(tf) as fh:
+        t = json.load(fh)
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    return t.get("bytes_per_launch", {}).get(kind)
+
+
+def roofline_scale(prof: dict, ctx) -> dict | None:
+    """The scale-and-round (FP64 VALU): per coefficient of the tensor product
+    (three per ciphertext coefficient) two exact base conversions, L -> L + 1
+    and L + 1 -> L primes, L (L + 1) terms each at OPS_PER_CONV_TERM FP64
+    operations; its reductions, modular products and the digits' mixed-radix
+    digits are overhead."""
+    st = prof.get("scale")
+    if not st or not st["launches"] or ctx is None:
+        return None
+    coeffs = st["work"] / st["launches"]
+    ops = coeffs * 2 * ctx.L * ctx.L_ext * OPS_PER_CONV_TERM
+    avg_s = st["ms"] / st["launches"] / 1e3
+    return {"bound": "alu", "kernel": "scale", "achieved": ops / avg_s / 1e12,
+            "peak": PEAK_FP64_OPS / 1e12, "unit": "TOP/s (FP64 VALU ops)",
+            "frac": ops / avg_s / PEAK_FP64_OPS, "traffic": _traffic("scale"),
+            "coefficients_per_launch": coeffs, "ops_per_launch": ops,
+            "mean_launch_ms": st["ms"] / st["launches"]}
+
+
+def roofline_dominant(prof: dict, ctx) -> tuple[dict, dict]:
+    """The roofline of the kernel kind with the most time (the scale-and-round
+    or a transform), and the heaviest transform's."""
+    ntt, _ = roofline(prof, ctx)
+    dom = max(prof, key=lambda k: prof[k]["ms"])
+    if dom == "scale":
+        sc = roofline_scale(prof, ctx)
+        if sc is not None:
+            sc["dominant_kind"] = dom
+            return sc, ntt
+    return ntt, ntt
+
+
 def roofline(prof: dict, ctx=None) -> tuple[dict, str]:
     ntt = {k: v for k, v in prof.items() if k.startswith("ntt")}
     dom = max(prof, key=lambda k: prof[k]["ms"])
@@ -108,13 +158,7 @@ def roofline(prof: dict, ctx=None) -> tuple[dict, str]:
         per_launch_ops += modup
     avg_s = st["ms"] / st["launches"] / 1e3
     achieved = per_launch_ops / avg_s
-    traffic = None
-    tf = os.path.join(ROOT, "profiles", "traffic.json")
-    if os.path.exists(tf):
-        with open(tf) as fh:
-            t = json.load(fh)
-        if t.get("kernel_hash") == kernel_hash() and dom_ntt in t.get("bytes_per_launch", {}):
-            traffic = t["bytes_per_launch"][dom_ntt]
+    traffic = _traffic(dom_ntt)
     return {
         "bound": "alu",
         "kernel": dom_ntt,
@@ -603,6 +647,8 @@ def summarize_profiles(prof_dir: str, out_dir: str) -> None:
     for (name, grid), d in per_kind.items():
         if re.search(r"k_ntt_fwd_par<[156]>|k_ntt_fwd_half<[156]>|k_ntt_fwd<\d+, [156]>", name):
             traffic["ntt_digit"] = d.get("FETCH_SIZE", 0) + d.get("WRITE_SIZE", 0)
+        if re.search(r"k_scale<", name):
+            traffic["scale"] = d.get("FETCH_SIZE", 0) + d.get("WRITE_SIZE", 0)
     with open(os.path.join(out_dir, "traffic.json"), "w") as fh:
         json.dump({"kernel_hash": kernel_hash(), "bytes_per_launch": traffic,
                    "calibration": {"copy_mib": mib, "factors": factors}}, fh, indent=1)
@@ -692,7 +738,7 @@ def main() -> int:
     records = n_ct * ctx.n
     value = records / (ms / 1e3)
     log(f"{ms:.2f} ms/step, {value:.4g} records/s")
-    roof, _ = roofline(prof, ctx)
+    roof, roof_ntt = roofline_dominant(prof, ctx)
     rates = derived_rates(ctx, prof, args.steps, n_ct, ms)
     roof_ks = roofline_ks(ctx, prof, n_ct, ctx.tuning()["ks_chunk"])
     # the other key-switching decompositions on the same column, same steps
@@ -707,7 +753,7 @@ def main() -> int:
             other.append({"special_primes": oa, "data_primes": c2.L, "key_switch_digits": c2.dnum,
                           "depth_budget": c2.depth_budget,
                           "ms_per_step": ms2, "records_per_s": records / (ms2 / 1e3),
-                          "roofline": roofline(prof2, c2)[0],
+                          "roofline": roofline_dominant(prof2, c2)[0],
                           "roofline_ks_mac": roofline_ks(c2, prof2, n_ct, c2.tuning()["ks_chunk"]),
                           "kernels": {k: {"launches": v["launches"] // args.steps,
                                           "ms_per_step": v["ms"] / args.steps}
@@ -761,6 +807,7 @@ def main() -> int:
                    "data_primes": ctx.L, "special_primes": ctx.alpha,
                    "key_switch_digits": ctx.dnum, "plaintext_modulus": ctx.t},
         "roofline": roof,
+        "roofline_ntt_digit": roof_ntt if roof_ntt is not roof else None,
         "roofline_ks_mac": roof_ks,
         "other_key_switching": other,
         "cpu_baseline": cpu,
