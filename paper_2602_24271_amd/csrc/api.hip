@@ -380,6 +380,43 @@ static int prepare_operand(nshe_ctx* c, double* ext, double* fx, int n_ct, hipSt
 // relinearization digit source (each digit's mixed-radix digits when
 // alpha > 1) unless
 // `residues` asks for its canonical residues (a three-component output).
+// 2^15-point limbs with the split transforms: the key-switch product may
+// run fused with the digit transforms (k_ks_fused), a tuning choice.
+static bool ks_fused(const nshe_ctx* c) {
+  return c->log2n == 15 && c->tune.split_forward && c->tune.ks_fused && c->tb.tw_half &&
+         c->alpha == 1;
+}
+
+// 2^15-point limbs with the split transforms: the key-switch digits are
+// transformed by coefficient parity (k_ntt_fwd_par) and the key-switch
+// product applies the last stage (k_ks_mac_par), unless the product runs
+// fused.
+static bool parity_digits(const nshe_ctx* c) {
+  return c->log2n == 15 && c->tune.split_forward && c->tb.tw_cmp_par && c->tb.tw_last &&
+         !ks_fused(c);
+}
+
+// Where the relinearization digit source (the third component's limbs
+// 0..L-1: canonical residues, or each digit's mixed-radix digits) is
+// written and read: in place in dt, or, for the digit transforms by parity
+// with three-prime digits, in the key-switch sum buffer (idle until the
+// key-switch product) by coefficient parity, c at (c mod 2) N/2 + c/2, so
+// that each parity's transform reads its half contiguously.  In place, that
+// order would overwrite values the scale-and-round's other waves have still
+// to read; with 16 or 17 data primes the scale-and-round's extra destination
+// spills its scalar registers (measured slower), so one- and two-prime
+// digits stay in place and the transform reads every second value.
+struct DigitSrc {
+  double* p;       // ciphertext 0's limb 0
+  size_t stride;   // doubles between ciphertexts
+  int split;       // parity order
+};
+static DigitSrc digit_src(const nshe_ctx* c, const Ws& w) {
+  // (the scale-and-round takes this stride from its template constants)
+  if (parity_digits(c) && c->alpha == 3) return {w.acc, (size_t)2 * KS_of(c) * c->n, 1};
+  return {w.dt + (size_t)2 * W_of(c) * c->n, (size_t)3 * W_of(c) * c->n, 0};
+}
+
 static int tensor_scale(nshe_ctx* c, const Ws& w, const double* fx_b, int n_ct, hipStream_t st,
                         const double* fx_a = nullptr, bool residues = false) {
   Dims d = dims(c, n_ct);
@@ -400,23 +437,16 @@ static int tensor_scale(nshe_ctx* c, const Ws& w, const double* fx_b, int n_ct, 
     HIPCHK(run_ntt(c->log2n, j, c->tb, 3, st));
   }
   {
+    // a product kept as three components (residues) stays in dt
+    const DigitSrc ds = digit_src(c, w);
+    const bool own = !residues && ds.split;
     Prof pf(c, K_SCALE, st, 3.0 * n_ct * c->n);
-    HIPCHK(run_scale(d, w.dt, c->tb, st, !residues && c->alpha > 1));
+    HIPCHK(run_scale(d, w.dt, c->tb, st, !residues && c->alpha > 1, own ? ds.p : nullptr));
   }
   return NSHE_OK;
 }
 
-// 2^15-point limbs with the split transforms: the key-switch product may
-// run fused with the digit transforms (k_ks_fused), a tuning choice.
-static bool ks_fused(const nshe_ctx* c) {
-  return c->log2n == 15 && c->tune.split_forward && c->tune.ks_fused && c->tb.tw_half &&
-         c->alpha == 1;
-}
-
 static int digit_products(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st, const double* key);
-static bool parity_digits(const nshe_ctx* c) {
-  return c->log2n == 15 && c->tune.split_forward && c->tb.tw_cmp_par && c->tb.tw_last;
-}
 static int finish_relin(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st, double* out,
                         bool lift_out, int64_t* finish_out, int64_t* i64_out, bool accumulate);
 
@@ -457,11 +487,13 @@ static int relin(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st,
 // key, summed into w.acc (two kernels).
 static int digit_products(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st, const double* key) {
   Dims d = dims(c, n_ct);
+  const DigitSrc ds = digit_src(c, w);
   NttJob j{};
   j.split = c->tune.split_forward;
   // 2^15-point limbs with the split transforms: digit transforms by
   // coefficient parity, their last stage applied by the key-switch product
   j.parity = d.parity = parity_digits(c) ? 1 : 0;
+  j.src_split = ds.split;
   j.base = w.dig;
   j.out = w.dig;
   j.poly_stride = (size_t)KS_of(c) * c->n;
@@ -469,8 +501,8 @@ static int digit_products(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st, co
   j.nlimb = KS_of(c);
   j.limb_prime = c->lp_ks;
   j.count = j.npoly * j.nlimb;
-  j.src = w.dt + (size_t)2 * W_of(c) * c->n;
-  j.src_ct_stride = (size_t)3 * W_of(c) * c->n;
+  j.src = ds.p;
+  j.src_ct_stride = ds.stride;
   j.digits = c->dnum;
   j.alpha = c->alpha;
   {
@@ -1467,7 +1499,9 @@ int nshe_relinearize(nshe_ctx* c, const int64_t* in3, int64_t* out, int n_ct, vo
   Dims d = dims(c, n_ct);
   const size_t W = W_of(c), N = c->n;
   HIPCHK(run_i64_to_polys(d, in3, 3, w.dt, 3 * W * N, W * N, 2, c->tb, st));
-  if (c->alpha > 1) HIPCHK(run_digit_mrc(d, w.dt, c->tb, st));
+  const DigitSrc ds = digit_src(c, w);
+  if (ds.split) HIPCHK(run_digit_split(d, w.dt, ds.p, ds.stride, st));
+  if (c->alpha > 1) HIPCHK(run_digit_mrc(d, ds.p, ds.stride, c->tb, st));
   rc = relin(c, w, n_ct, st);
   if (rc) return rc;
   HIPCHK(run_polys_to_i64(d, w.ext, 2, 2 * W * N, W * N, out, 0, c->tb, st));
@@ -1750,8 +1784,10 @@ static int rotate_ext(nshe_ctx* c, const Ws& w, int n_ct, uint32_t g, const doub
   Dims d = dims(c, n_ct);
   {
     Prof pf(c, K_AUTOMORPH, st, 2.0 * n_ct * c->L * c->n);
-    HIPCHK(run_automorph(d, inv_mod_2n(c, g), w.ext, w.dt, c->tb, st));
-    if (c->alpha > 1) HIPCHK(run_digit_mrc(d, w.dt, c->tb, st));
+    const DigitSrc ds = digit_src(c, w);
+    HIPCHK(run_automorph(d, inv_mod_2n(c, g), w.ext, w.dt, c->tb, st, ds.split ? ds.p : nullptr,
+                         ds.stride, ds.split));
+    if (c->alpha > 1) HIPCHK(run_digit_mrc(d, ds.p, ds.stride, c->tb, st));
   }
   return relin(c, w, n_ct, st, key, out, false, nullptr, nullptr, accumulate);
 }
@@ -2159,8 +2195,9 @@ static int lt_core(nshe_ctx* c, const int64_t* z, int64_t* out, int n_ct, const 
       HIPCHK(run_ntt(c->log2n, j, c->tb, 4, st));
     }
     {
+      const DigitSrc ds = digit_src(c, w);
       Prof pf(c, K_SCALE, st, 3.0 * n_ct * c->n);
-      HIPCHK(run_scale(d, w.dt, c->tb, st, c->alpha > 1));
+      HIPCHK(run_scale(d, w.dt, c->tb, st, c->alpha > 1, ds.split ? ds.p : nullptr));
     }
     int rc = relin_i64(c, w, n_ct, st, a.slot(s_T));
     if (rc) return rc;

@@ -106,6 +106,9 @@ struct Tables {
   // key-switching basis, in the order of k_ks_mac_par's threads: entry
   // u 1024 + m holds k = 16 m + u
   const double* tw_last;     // [L + alpha][2^14]
+  // set per launch of the scale-and-round: where the relinearization digit
+  // source goes (null: in place; see k_scale)
+  double* dig_src;
 };
 
 // Call sites of the exact-lift fallback (index into Tables::margin).
@@ -136,7 +139,8 @@ struct NttJob {
   // [0, q_j) (the digits themselves); with alpha primes per digit, limbs
   // j alpha .. j alpha + alpha - 1 hold digit j's canonical mixed-radix
   // digits (v_0, v_1[, v_2]), D_j = v_0 + q_{j alpha} v_1 (+ q_{j alpha}
-  // q_{j alpha + 1} v_2) in [0, Q_j) (NTT_DIGIT2, NTT_DIGIT3); INV_TENSOR: the
+  // q_{j alpha + 1} v_2) in [0, Q_j) (NTT_DIGIT2, NTT_DIGIT3), in natural
+  // order or (src_split) by coefficient parity, c at (c mod 2) N/2 + c/2; INV_TENSOR: the
   // operands' transforms ([ct][2][W][N], src_b null when squaring)
   const double* src;
   const double* src_b;
@@ -152,6 +156,9 @@ struct NttJob {
   // 2^14-point transforms per limb; the key-switch product applies the last
   // stage (k_ntt_fwd_par, k_ks_mac_par)
   int parity = 0;
+  // with parity and three-prime digits: the digit source is stored by
+  // coefficient parity (see src)
+  int src_split = 0;
 };
 
 // run_ntt directions: 0 forward in place, 1 inverse in place, 2 forward of
@@ -189,9 +196,12 @@ struct Dims {
 hipError_t run_lift(const Dims& d, double* ext, const Tables& tb, hipStream_t st);
 // digit_pairs: write the third component as the digits' mixed-radix digits
 // (the relinearization digit source with alpha > 1) instead of canonical
-// residues
+// residues.  src (not null): write the third component (the digit source)
+// there instead of in place, ciphertext ct at src + ct 2 (L + alpha) N (limbs
+// 0..L-1, N apart), coefficient c at (c mod 2) N/2 + c/2, the layout the
+// digit transforms by parity read.
 hipError_t run_scale(const Dims& d, double* dt, const Tables& tb, hipStream_t st,
-                     int digit_pairs = 0);
+                     int digit_pairs = 0, double* src = nullptr);
 hipError_t run_ks_mac(const Dims& d, const double* dig, const double* evk, double* acc,
                       const Tables& tb, hipStream_t st);
 hipError_t run_moddown(const Dims& d, const double* acc, const double* dt, double* ext,
@@ -237,13 +247,20 @@ hipError_t run_lincomb(const Dims& d, int k, const BabyPtrs& b, const int* coef,
 hipError_t run_fill_one(const Dims& d, int64_t* out, const Tables& tb, hipStream_t st);
 hipError_t run_diff_i64(const Dims& d, const int64_t* x, const int64_t* y, int y_bcast,
                         int negate, int64_t* out, const Tables& tb, hipStream_t st);
-// rotations: automorphism of ext into dt's key-switching layout
+// rotations: automorphism of ext into dt's key-switching layout (the third
+// component to src, as in run_scale, when src is not null)
 hipError_t run_automorph(const Dims& d, unsigned ginv, const double* ext, double* dt,
-                         const Tables& tb, hipStream_t st);
+                         const Tables& tb, hipStream_t st, double* src = nullptr,
+                         size_t src_stride = 0, int src_split = 0);
 // alpha primes per digit (alpha > 1): canonical residues of the digit
-// source (dt's third component, limbs 0..L-1) into each digit's canonical
-// mixed-radix digits, in place
-hipError_t run_digit_mrc(const Dims& d, double* dt, const Tables& tb, hipStream_t st);
+// source (limbs 0..L-1 of ciphertext ct at src + ct src_stride, any
+// coefficient order) into each digit's canonical mixed-radix digits, in place
+hipError_t run_digit_mrc(const Dims& d, double* src, size_t src_stride, const Tables& tb,
+                         hipStream_t st);
+// dt's third component (natural order) into src by coefficient parity (as
+// run_scale's src_split)
+hipError_t run_digit_split(const Dims& d, const double* dt, double* src, size_t src_stride,
+                           hipStream_t st);
 // p[0..words) = v, as a kernel (no memset node in a captured graph)
 hipError_t run_fill_u64(void* p, size_t words, uint64_t v, hipStream_t st);
 // debug input check: sets *tb.bad_input if a residue of [n_poly][L][N] is

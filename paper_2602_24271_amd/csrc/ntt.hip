@@ -962,9 +962,11 @@ k_ntt_fwd_half(NttJob job, Tables tb) {
 // psi^(brv_15(i)) for i < 2^14, those transforms use the full transform's
 // twiddles of stages 0..13 (slot 2^s + m).  One workgroup of 512 threads
 // takes one parity h of one (digit, target prime): it loads every second
-// coefficient of the digit's sources (the other parity's workgroup, on the
-// same XCD, reads the other half of the same cache lines), forms each
-// value in the target prime once, and stores the unreduced result to half
+// coefficient of the digit's sources (SPLIT: half h of sources that their
+// producers store by coefficient parity, c at (c mod 2) 2^14 + c/2, read
+// contiguously; otherwise natural order, where the other parity's workgroup,
+// on the same XCD, reads the other half of the same cache lines), forms
+// each value in the target prime once, and stores the unreduced result to half
 // h of the limb in the 2^14 transform's order (standard index k at
 // (k mod 32) 512 + k / 32).  The last stage, E_k +- z O_k, is left to the
 // key-switch product (k_ks_mac_par): unlike a split by the top index bit
@@ -981,7 +983,7 @@ static_assert(PAR_MID < 15.1 && PAR_OUT < 5.9 && 1.103 * PAR_OUT + 0.5 < 7.0,
               "parity digit transform bounds");
 static_assert(ct_bound(DIGIT_IN, 9) < PAR_MID, "one-prime digits are the smaller");
 
-template <int MODE>
+template <int MODE, bool SPLIT>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
 k_ntt_fwd_par(NttJob job, Tables tb) {
   using S = NttShape<14>;
@@ -1015,10 +1017,11 @@ k_ntt_fwd_par(NttJob job, Tables tb) {
   const int j = poly - ct * job.digits;
   const double* s0 = job.src + (size_t)ct * job.src_ct_stride + (size_t)(MODE == NTT_DIGIT3 ? 3 * j : MODE == NTT_DIGIT2 ? 2 * j : j) * NF;
   // element e of thread tid in round 0 is sub-index e 512 + tid, source
-  // coefficient 2 (e 512 + tid) + h
+  // coefficient 2 (e 512 + tid) + h, stored there or (SPLIT) at
+  // h 2^14 + e 512 + tid
   const int tid = threadIdx.x;
-  const unsigned vo = (2 * tid + h) * 8;
-  constexpr unsigned ES = 2 * S::T * 8;
+  const unsigned vo = SPLIT ? (h * (NF / 2) + tid) * 8 : (2 * tid + h) * 8;
+  constexpr unsigned ES = SPLIT ? S::T * 8 : 2 * S::T * 8;
   double x[S::E];
   if constexpr (MODE == NTT_DIGIT) {
     // canonical digits in [0, q_j), below 2 p
@@ -1348,12 +1351,15 @@ static hipError_t launch_ntt(const NttJob& job, const Tables& tb, int dir, hipSt
     }
     if (dir == 2 && job.parity && job.split && tb.tw_cmp_par) {
       dim3 grid(per_xcd(job, dir, 2) * 8), block(512);
+      // (sources stored by parity: three-prime digits, see the scale-and-round)
       if (job.alpha == 2)
-        hipLaunchKernelGGL((k_ntt_fwd_par<NTT_DIGIT2>), grid, block, 0, st, job, tb);
+        hipLaunchKernelGGL((k_ntt_fwd_par<NTT_DIGIT2, false>), grid, block, 0, st, job, tb);
+      else if (job.alpha == 3 && job.src_split)
+        hipLaunchKernelGGL((k_ntt_fwd_par<NTT_DIGIT3, true>), grid, block, 0, st, job, tb);
       else if (job.alpha == 3)
-        hipLaunchKernelGGL((k_ntt_fwd_par<NTT_DIGIT3>), grid, block, 0, st, job, tb);
+        hipLaunchKernelGGL((k_ntt_fwd_par<NTT_DIGIT3, false>), grid, block, 0, st, job, tb);
       else
-        hipLaunchKernelGGL((k_ntt_fwd_par<NTT_DIGIT>), grid, block, 0, st, job, tb);
+        hipLaunchKernelGGL((k_ntt_fwd_par<NTT_DIGIT, false>), grid, block, 0, st, job, tb);
       return hipGetLastError();
     }
     if (dir == 0 && job.out && job.out != job.base && tb.tw_half && job.split) {

@@ -214,7 +214,14 @@ __device__ __forceinline__ double coef_const(const CoefSrc& s, const double* tab
 // wave takes 32 coefficient pairs (c, c + N/2), lanes 0-31 the lower
 // coefficients and 32-63 the upper, and writes its outputs in place at the
 // positions it alone reads.  A: data primes per key-switching digit (the
-// third component's digit format).
+// third component's digit format).  tb.dig_src (not null, A = 3 only): the
+// third component (the relinearization digit source) goes there instead,
+// ciphertext ct at dig_src + ct 2 (L + A) N (the key-switch sums' stride),
+// limb i at + i N, and coefficient c at position (c mod 2) N/2 + c/2
+// (k_ntt_fwd_par's layout; in place, those positions are read by other
+// waves).  (A table field, read where it is used: a kernel argument stays
+// in scalar registers through the kernel and spills the 17-prime
+// instance's.)
 template <int L, bool FUSED, int A>
 __global__ void __launch_bounds__(256) k_scale(int n, size_t n_poly, double* dt, Tables tb) {
   constexpr int LB = L + 1;
@@ -308,6 +315,16 @@ __global__ void __launch_bounds__(256) k_scale(int n, size_t n_poly, double* dt,
   double grp[A];   // the current digit group's canonical mixed-radix digits
 #pragma unroll
   for (int k = 0; k < A; ++k) grp[k] = 0.0;
+  // where the outputs go: in place, or the digit source's own buffer and
+  // position (see src above).  Every input has been read by now; formed
+  // here, the destination's scalars are live only in this loop.
+  // (three-prime digits only: with 16 or 17 primes the destination's
+  // scalars spill the conversions' constants, measured slower)
+  const bool own = A == 3 && third && tb.dig_src;
+  const auto rw = make_rsrc(own ? tb.dig_src + (pb.pc / 3) * (size_t)(2 * (L + A)) * n
+                                : dt + pb.pc * (size_t)(L + LB) * n,
+                            (unsigned)((own ? L : L + LB) * n * 8));
+  const unsigned wo = own ? (((vo >> 3) & 1u) * (unsigned)(n >> 1) + (vo >> 4)) * 8u : vo;
 #pragma unroll
   for (int i = 0; i < L; ++i) {
     const int iq = opaque_idx(i);
@@ -333,7 +350,7 @@ __global__ void __launch_bounds__(256) k_scale(int n, size_t n_poly, double* dt,
       }
       grp[m] = o;
     }
-    buf_store(o, rs, vo, i * ls);
+    buf_store(o, rw, wo, i * ls);
   }
 }
 
@@ -976,7 +993,9 @@ __global__ void __launch_bounds__(256) k_diff_i64(int n, int L, size_t total, co
 // canonical residues of sigma(c1).  Output coefficient j of sigma(a) is
 // a_i for i = j g^-1 mod 2N when i < N, else -a_{i-N} (since X^N = -1).
 __global__ void __launch_bounds__(256) k_automorph(int n, int L, int n_ct, unsigned ginv,
-                                                   const double* ext, double* dt, Tables tb) {
+                                                   const double* ext, double* dt, Tables tb,
+                                                   double* dsrc, size_t dsrc_stride,
+                                                   int dsrc_split) {
   const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= (size_t)n_ct * 2 * L * n) return;
   const size_t row = gid / n;               // (ct * 2 + b) * L + i
@@ -993,20 +1012,42 @@ __global__ void __launch_bounds__(256) k_automorph(int n, int L, int n_ct, unsig
   if (b == 0) {
     d[0] = v;
     d[W * n] = 0.0;
+  } else if (dsrc) {
+    // the digit source's own buffer (see k_scale)
+    const int jp = dsrc_split ? (j & 1) * (n >> 1) + (j >> 1) : j;
+    dsrc[ct * dsrc_stride + (size_t)i * n + jp] = to_canonical(v, cld(tb.p, i));
   } else {
     d[2 * W * n] = to_canonical(v, cld(tb.p, i));
   }
 }
 
-// A primes per key-switching digit (A = 2, 3): the digit source (dt's
-// third component, limbs 0..L-1, canonical residues d_i) into each digit's
+// The third component of dt (limbs 0..L-1) into the digit source's own
+// buffer: ciphertext ct at src + ct src_stride, coefficient c at position
+// (c mod 2) N/2 + c/2 (see k_scale).
+__global__ void __launch_bounds__(256) k_digit_split(int n, int L, int n_ct, const double* dt,
+                                                     double* src, size_t src_stride) {
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (size_t)n_ct * L * n) return;
+  const size_t row = gid / n;               // ct * L + i
+  const int c = (int)(gid - row * n);
+  const size_t ct = row / L;
+  const int i = (int)(row - ct * L);
+  const size_t W = (size_t)2 * L + 1;
+  src[ct * src_stride + (size_t)i * n + (c & 1) * (n >> 1) + (c >> 1)] =
+      dt[(ct * 3 * W + 2 * W + i) * n + c];
+}
+
+// A primes per key-switching digit (A = 2, 3): the digit source (limbs
+// 0..L-1 of ciphertext ct at src + ct src_stride, canonical residues d_i, in
+// any coefficient order) into each digit's
 // canonical mixed-radix digits, in place (as k_scale writes them): limb
 // g + m of the group starting at g = j A gets v_m = t_m, t_0 = d_{g+m},
 // t_{k+1} = [(t_k - v_k) q_{g+k}^-1]_{q_{g+m}}, so that digit j,
 // D_j = v_0 + q_g v_1 + q_g q_{g+1} v_2 in [0, Q_j), is [c]_{Q_j}.  One
 // thread per (ciphertext, digit, coefficient).
 template <int A>
-__global__ void __launch_bounds__(256) k_digit_mrc(int n, int L, int n_ct, double* dt, Tables tb) {
+__global__ void __launch_bounds__(256) k_digit_mrc(int n, int L, int n_ct, double* src,
+                                                   size_t src_stride, Tables tb) {
   const int groups = L / A;
   const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= (size_t)n_ct * groups * n) return;
@@ -1014,9 +1055,8 @@ __global__ void __launch_bounds__(256) k_digit_mrc(int n, int L, int n_ct, doubl
   const int c = (int)(gid - row * n);
   const int j = (int)(row % groups);
   const size_t ct = row / groups;
-  const size_t W = (size_t)2 * L + 1;
   const int g = j * A;
-  double* d = dt + (ct * 3 * W + 2 * W + g) * n + c;
+  double* d = src + ct * src_stride + (size_t)g * n + c;
   double v[A];
   v[0] = d[0];
 #pragma unroll
@@ -1367,18 +1407,20 @@ hipError_t run_moddown_lift(const Dims& d, const double* acc, const double* dt, 
 
 
 hipError_t run_scale(const Dims& d, double* dt, const Tables& tb, hipStream_t st,
-                     int digit_pairs) {
+                     int digit_pairs, double* src) {
   const size_t np = (size_t)d.n_ct * 3;
+  Tables t = tb;
+  t.dig_src = src;
   // the split-inverse variant's barrier needs whole blocks (see k_scale)
   if (d.fused && d.n % d.block) return hipErrorInvalidValue;
 #define C_(L_, A_) \
   case L_:                                                                                     \
     if (d.fused)                                                                               \
       hipLaunchKernelGGL((k_scale<L_, true, A_>), poly_grid(np, d.n, d.block), dim3(d.block),  \
-                         (size_t)(L_ + 1) * d.block * 8, st, d.n, np, dt, tb);                 \
+                         (size_t)(L_ + 1) * d.block * 8, st, d.n, np, dt, t);          \
     else                                                                                       \
       hipLaunchKernelGGL((k_scale<L_, false, A_>), poly_grid(np, d.n, d.block), dim3(d.block), \
-                         (size_t)(L_ + 1) * d.block * 8, st, d.n, np, dt, tb);                 \
+                         (size_t)(L_ + 1) * d.block * 8, st, d.n, np, dt, t);          \
     break;
 #define C1_(L_) C_(L_, 1)
 #define C2_(L_) C_(L_, 2)
@@ -1535,13 +1577,24 @@ hipError_t run_moddown(const Dims& d, const double* acc, const double* dt, doubl
   return hipGetLastError();
 }
 
-hipError_t run_digit_mrc(const Dims& d, double* dt, const Tables& tb, hipStream_t st) {
+hipError_t run_digit_mrc(const Dims& d, double* src, size_t src_stride, const Tables& tb,
+                         hipStream_t st) {
   if (d.alpha < 2 || d.alpha > 3 || d.L % d.alpha) return hipErrorInvalidValue;
   const size_t total = (size_t)d.n_ct * (d.L / d.alpha) * d.n;
   if (d.alpha == 2)
-    hipLaunchKernelGGL(k_digit_mrc<2>, grid_for(total), dim3(256), 0, st, d.n, d.L, d.n_ct, dt, tb);
+    hipLaunchKernelGGL(k_digit_mrc<2>, grid_for(total), dim3(256), 0, st, d.n, d.L, d.n_ct, src,
+                       src_stride, tb);
   else
-    hipLaunchKernelGGL(k_digit_mrc<3>, grid_for(total), dim3(256), 0, st, d.n, d.L, d.n_ct, dt, tb);
+    hipLaunchKernelGGL(k_digit_mrc<3>, grid_for(total), dim3(256), 0, st, d.n, d.L, d.n_ct, src,
+                       src_stride, tb);
+  return hipGetLastError();
+}
+
+hipError_t run_digit_split(const Dims& d, const double* dt, double* src, size_t src_stride,
+                           hipStream_t st) {
+  const size_t total = (size_t)d.n_ct * d.L * d.n;
+  hipLaunchKernelGGL(k_digit_split, grid_for(total), dim3(256), 0, st, d.n, d.L, d.n_ct, dt, src,
+                     src_stride);
   return hipGetLastError();
 }
 
@@ -1615,10 +1668,12 @@ hipError_t run_diff_i64(const Dims& d, const int64_t* x, const int64_t* y, int y
 }
 
 hipError_t run_automorph(const Dims& d, unsigned ginv, const double* ext, double* dt,
-                         const Tables& tb, hipStream_t st) {
+                         const Tables& tb, hipStream_t st, double* src, size_t src_stride,
+                         int src_split) {
+  if (src_split && !src) return hipErrorInvalidValue;
   const size_t total = (size_t)d.n_ct * 2 * d.L * d.n;
   hipLaunchKernelGGL(k_automorph, grid_for(total), dim3(256), 0, st, d.n, d.L, d.n_ct, ginv, ext,
-                     dt, tb);
+                     dt, tb, src, src_stride, src_split);
   return hipGetLastError();
 }
 
