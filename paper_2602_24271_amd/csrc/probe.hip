@@ -112,8 +112,7 @@ __global__ void __launch_bounds__(256) k_probe_fill(double* v, size_t n, int row
 template <int NT, int NO>
 __global__ void __launch_bounds__(256) k_conv_fma(size_t n, const double* __restrict__ y,
                                                   double* __restrict__ out,
-                                                  const double* sp, const double* two24,
-                                                  const double* two48, const double* m,
+                                                  const double* sp, const double* m,
                                                   const double* minv) {
   const size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n) return;
@@ -125,7 +124,7 @@ __global__ void __launch_bounds__(256) k_conv_fma(size_t n, const double* __rest
     const int kq = opaque_idx(k);
     const double mk = cld(m, kq), mi = cld(minv, kq);
     const double* row = opaque_row(sp, kq * NT * 2);
-    const double a = conv_row<NT>(yh, yl, row, cld(two24, kq), cld(two48, kq), mk, mi);
+    const double a = conv_row<NT>(yh, yl, row, mk, mi);
     out[(size_t)k * n + c] = reduce_bal(a, mk, mi);
   }
 }
@@ -270,14 +269,11 @@ int run_conversion(const uint64_t* qin, const uint64_t* qout, size_t n, int reps
       const uint64_t mk = qout[k];
       M[(size_t)i * NO + k] = (int64_t)bal((z >> 11) % mk, mk);
     }
-  std::vector<double> sp((size_t)NO * NT * 2), t24(NO), t48(NO), mo(NO), mi(NO), c32(NO), mq(NT);
+  std::vector<double> sp((size_t)NO * NT * 2), mo(NO), mi(NO), c32(NO), mq(NT);
   for (int k = 0; k < NO; ++k) {
     const uint64_t mk = qout[k];
     mo[k] = (double)mk;
     mi[k] = 1.0 / (double)mk;
-    const uint64_t a24 = (1ull << 24) % mk;
-    t24[k] = bal(a24, mk);
-    t48[k] = bal(mulmod(a24, a24, mk), mk);
     c32[k] = bal((1ull << 32) % mk, mk);
     for (int i = 0; i < NT; ++i) {
       const double cb = (double)M[(size_t)i * NO + k];
@@ -310,20 +306,18 @@ int run_conversion(const uint64_t* qin, const uint64_t* qout, size_t n, int reps
           w = (int32_t)((uint32_t)w | ((uint32_t)(uint8_t)(int8_t)d << (8 * (t % 4))));
         }
   DevBuf dy, dof, dom, dtab, dbad;
-  const size_t tab_doubles = sp.size() + 5 * (size_t)NO + NT;
+  const size_t tab_doubles = sp.size() + 3 * (size_t)NO + NT;
   PCHK(hipMalloc(&dy.p, (size_t)NT * n * 8));
   PCHK(hipMalloc(&dof.p, (size_t)NO * n * 8));
   PCHK(hipMalloc(&dom.p, (size_t)NO * n * 8));
   PCHK(hipMalloc(&dtab.p, tab_doubles * 8 + at.size() * 4 + 256));
   PCHK(hipMalloc(&dbad.p, 8));
   double* tb = static_cast<double*>(dtab.p);
-  double *d_sp = tb, *d_t24 = d_sp + sp.size(), *d_t48 = d_t24 + NO, *d_m = d_t48 + NO,
-         *d_mi = d_m + NO, *d_c32 = d_mi + NO, *d_mq = d_c32 + NO;
+  double *d_sp = tb, *d_m = d_sp + sp.size(), *d_mi = d_m + NO, *d_c32 = d_mi + NO,
+         *d_mq = d_c32 + NO;
   v4i* d_at = reinterpret_cast<v4i*>(reinterpret_cast<char*>(dtab.p) +
                                      ((tab_doubles * 8 + 255) & ~(size_t)255));
   PCHK(hipMemcpy(d_sp, sp.data(), sp.size() * 8, hipMemcpyHostToDevice));
-  PCHK(hipMemcpy(d_t24, t24.data(), NO * 8, hipMemcpyHostToDevice));
-  PCHK(hipMemcpy(d_t48, t48.data(), NO * 8, hipMemcpyHostToDevice));
   PCHK(hipMemcpy(d_m, mo.data(), NO * 8, hipMemcpyHostToDevice));
   PCHK(hipMemcpy(d_mi, mi.data(), NO * 8, hipMemcpyHostToDevice));
   PCHK(hipMemcpy(d_c32, c32.data(), NO * 8, hipMemcpyHostToDevice));
@@ -345,8 +339,7 @@ int run_conversion(const uint64_t* qin, const uint64_t* qout, size_t n, int reps
   for (int pass = 0; pass < 2; ++pass) {   // pass 0 warms up
     PCHK(hipEventRecord(e0, 0));
     for (int r = 0; r < reps; ++r)
-      hipLaunchKernelGGL((k_conv_fma<NT, NO>), gf, blk, 0, 0, n, y, of, d_sp, d_t24, d_t48, d_m,
-                         d_mi);
+      hipLaunchKernelGGL((k_conv_fma<NT, NO>), gf, blk, 0, 0, n, y, of, d_sp, d_m, d_mi);
     PCHK(hipEventRecord(e1, 0));
     PCHK(hipEventSynchronize(e1));
     PCHK(hipEventElapsedTime(&ms_f, e0, e1));

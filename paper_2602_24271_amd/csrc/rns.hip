@@ -129,7 +129,7 @@ __global__ void __launch_bounds__(256) k_lift(int n, size_t n_poly, double* ext,
   for (int k = 0; k < LB; ++k) {
     const double b = cld(tb.p, L + k), binv = cld(tb.pinv, L + k);
     const double* sp = opaque_row(tb.q_hat_b_sp, k * L * 2);
-    const double acc = conv_row<L>(yh, yl, sp, cld(tb.two24, L + k), cld(tb.two48, L + k), b, binv) -
+    const double acc = conv_row<L>(yh, yl, sp, b, binv) -
                        v * cld(tb.Q_b, k);
     buf_store(reduce_bal(acc, b, binv), rs, vo, (L + k) * ls);
   }
@@ -300,7 +300,7 @@ __global__ void __launch_bounds__(256) k_scale(int n, size_t n_poly, double* dt,
       const double acc = mul_lazy(coef_load<FUSED>(rs, cs, (L + k) * ls),
                                   coef_const<FUSED>(cs, FUSED ? kl + 2 * L : tb.c1, kq, LB), b, binv) +
                          v * cld(tb.b_hat_inv, kq) -
-                         conv_row<L>(yh, yl, sp, cld(tb.two24, pk), cld(tb.two48, pk), b, binv);
+                         conv_row<L>(yh, yl, sp, b, binv);
       const double w = reduce_bal(acc, b, binv);
       wp[k * bs] = w;
       S2 += w * cld(tb.recip, pk);
@@ -330,7 +330,7 @@ __global__ void __launch_bounds__(256) k_scale(int n, size_t n_poly, double* dt,
     const int iq = opaque_idx(i);
     const double q = cld(tb.p, iq), qinv = cld(tb.pinv, iq);
     const double* sp = opaque_row(tb.b_hat_q_sp, i * LB * 2);
-    const double acc = conv_row<LB>(wh, wl, sp, cld(tb.two24, iq), cld(tb.two48, iq), q, qinv) -
+    const double acc = conv_row<LB>(wh, wl, sp, q, qinv) -
                        v2 * cld(tb.B_q, iq);
     const double r = reduce_bal(acc, q, qinv);
     // the third component is only read as relinearization digits: its
@@ -689,7 +689,7 @@ __device__ __forceinline__ void lift_tail(const double (&o)[L], const double (&y
     const int kq = opaque_idx(k), pk = L + kq;
     const double bb = cld(tb.p, pk), binv = cld(tb.pinv, pk);
     const double* sp = opaque_row(tb.q_hat_b_sp, k * L * 2);
-    const double a = conv_row<L>(yh, yl, sp, cld(tb.two24, pk), cld(tb.two48, pk), bb, binv) -
+    const double a = conv_row<L>(yh, yl, sp, bb, binv) -
                      v * cld(tb.Q_b, kq);
     buf_store(reduce_bal(a, bb, binv), rs, vo, (L + k) * ls);
   }
