@@ -645,7 +645,7 @@ def summarize_profiles(prof_dir: str, out_dir: str) -> None:
     # two or three primes), by coefficient parity or full-limb
     import re
     for (name, grid), d in per_kind.items():
-        if re.search(r"k_ntt_fwd_par<[156]>|k_ntt_fwd_half<[156]>|k_ntt_fwd<\d+, [156]>", name):
+        if re.search(r"k_ntt_fwd_par<[156],|k_ntt_fwd_half<[156]>|k_ntt_fwd<\d+, [156]>", name):
             traffic["ntt_digit"] = d.get("FETCH_SIZE", 0) + d.get("WRITE_SIZE", 0)
         if re.search(r"k_scale<", name):
             traffic["scale"] = d.get("FETCH_SIZE", 0) + d.get("WRITE_SIZE", 0)
