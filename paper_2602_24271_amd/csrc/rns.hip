@@ -146,12 +146,15 @@ __global__ void __launch_bounds__(256) k_lift(int n, size_t n_poly, double* ext,
 // only ever multiplied by a constant, so w is folded into that constant
 // (the "hi" tables) and the load returns U + V or U - V (|.| <= p + 8, as
 // |U|, |V| <= p/2 + 4).  Lanes l and l + 32 of a wave hold the two
-// coefficients of a pair, each loading its own position (U's or V's) and
-// taking the other value from its partner lane, so every value is read once.
+// coefficients of a pair and each loads both U and V (coef_load_both): the
+// second load hits the cache lines of the first, and in the scale-and-round
+// it measured faster than taking the partner lane's value with two lane
+// swaps per value (pair_combine, which the mod-down + lift keeps: there the
+// two loads measured slower).
 struct CoefSrc {
-  unsigned v;      // this lane's position (bytes)
-  unsigned vu;     // the pair's U and V positions, for loads in divergent
-  unsigned vv;     // code (coef_load_both)
+  unsigned v;      // this lane's position (bytes): where it writes
+  unsigned vu;     // the pair's U and V positions
+  unsigned vv;
   double sg;       // -1 upper, +1 lower
   bool hi;
 };
@@ -172,18 +175,7 @@ __device__ __forceinline__ double pair_combine(double x, double sg) {
   return __builtin_fma(sg, v, u);
 }
 
-template <bool FUSED>
-__device__ __forceinline__ double coef_load(__amdgpu_buffer_rsrc_t rs, const CoefSrc& s,
-                                            unsigned soff) {
-  const double x = buf_load(rs, s.v, soff);
-  if constexpr (!FUSED) {
-    return x;
-  } else {
-    return pair_combine(x, s.sg);   // lower U + V, upper U - V
-  }
-}
-
-// The same value without the partner lane (any lane may be inactive).
+// Coefficient c's value (see CoefSrc; any lane may be inactive).
 template <bool FUSED>
 __device__ __forceinline__ double coef_load_both(__amdgpu_buffer_rsrc_t rs, const CoefSrc& s,
                                                  unsigned soff) {
@@ -210,7 +202,7 @@ __device__ __forceinline__ double coef_const(const CoefSrc& s, const double* tab
 
 // dt: [n_poly][L+LB][N] coefficient domain (balanced).  Writes
 // [round(t d / Q)]_Q into limbs 0..L-1 of the same poly.
-// FUSED: dt holds the split inverse's half outputs (see coef_load); each
+// FUSED: dt holds the split inverse's half outputs (see CoefSrc); each
 // wave takes 32 coefficient pairs (c, c + N/2), lanes 0-31 the lower
 // coefficients and 32-63 the upper, and writes its outputs in place at the
 // positions it alone reads.  A: data primes per key-switching digit (the
@@ -261,7 +253,7 @@ __global__ void __launch_bounds__(256) k_scale(int n, size_t n_poly, double* dt,
   for (int i = 0; i < L; ++i) {
     const int iq = opaque_idx(i);
     const double p = cld(tb.p, iq), pinv = cld(tb.pinv, iq);
-    y[i] = mul_bal(coef_load<FUSED>(rs, cs, i * ls),
+    y[i] = mul_bal(coef_load_both<FUSED>(rs, cs, i * ls),
                    coef_const<FUSED>(cs, FUSED ? kl : tb.t_qhinv, iq, L), p, pinv);
     S += y[i] * cld(tb.recip, iq);
   }
@@ -297,7 +289,7 @@ __global__ void __launch_bounds__(256) k_scale(int n, size_t n_poly, double* dt,
       const int kq = opaque_idx(k), pk = L + kq;
       const double b = cld(tb.p, pk), binv = cld(tb.pinv, pk);
       const double* sp = opaque_row(tb.c2_sp, k * L * 2);
-      const double acc = mul_lazy(coef_load<FUSED>(rs, cs, (L + k) * ls),
+      const double acc = mul_lazy(coef_load_both<FUSED>(rs, cs, (L + k) * ls),
                                   coef_const<FUSED>(cs, FUSED ? kl + 2 * L : tb.c1, kq, LB), b, binv) +
                          v * cld(tb.b_hat_inv, kq) -
                          conv_row<L>(yh, yl, sp, b, binv);
