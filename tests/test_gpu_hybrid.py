@@ -213,6 +213,34 @@ def test_full_size_chain_every_level_and_paths(request, alpha):
 
 
 @pytest.mark.parametrize("alpha", ALPHAS)
+def test_full_size_key_switch_chunks(request, alpha):
+    """The benchmark's shape of the key-switch product: 33 ciphertexts (16
+    per pass with the digit transforms by parity, a ragged last chunk of
+    one), squared once at every chunk width (4, 8, 16, 32): all equal, and
+    the first and last ciphertexts (the golden input) bit-exact against the
+    oracle's level."""
+    S = _full(request, alpha)
+    E = _env(S)
+    g = fc.load_golden(f"a{alpha}_eq_edges")
+    x, y, cx, cy = fc.eq_edges_inputs(E)
+    z1 = S.ctx.sub(S.to_dev([cx]), S.to_dev([cy]))
+    others = synth.uniform_device_residues((31, 2), S.ctx.q, S.ctx.n, 77, S.ctx.device)
+    z = torch.cat([z1, others, z1]).contiguous()
+    start = S.ctx.tuning()
+    outs = []
+    try:
+        for ch in (4, 8, 16, 32):
+            S.ctx.set_tuning(ks_chunk=ch)
+            outs.append(S.ctx.square_relin(z))
+    finally:
+        S.ctx.set_tuning(**start)
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+    fc.check(g, "level_01", outs[0][0].cpu().numpy())
+    fc.check(g, "level_01", outs[0][32].cpu().numpy())
+
+
+@pytest.mark.parametrize("alpha", ALPHAS)
 def test_full_size_columns(request, alpha):
     S = _full(request, alpha)
     E = _env(S)
