@@ -19,7 +19,9 @@ constexpr int MAX_PRIMES = 2 * MAX_L + 1 + MAX_ALPHA;
 struct Tables {
   const double* p;           // [K]
   const double* pinv;        // [K] fl(1/p)
-  const double* recip;       // [K] fl(1/p) (kept separate: the CRT estimate)
+  const double* recip;       // [K] fl(1/p), the same values as pinv: no kernel reads it
+                             // any more (pinv serves the CRT estimates); kept so that
+                             // the struct's layout, and the kernels' registers, stay put
   const double* ninv;        // [K] balanced N^-1
   const double* tw_fwd;      // [K][tw_len] round-0 twiddles (slot 2^k + j)
   const double* tw_inv;      // [K][tw_len]

@@ -109,8 +109,9 @@ __global__ void __launch_bounds__(256) k_lift(int n, size_t n_poly, double* ext,
   double S = 0.0;
 #pragma unroll
   for (int i = 0; i < L; ++i) {
-    y[i] = mul_bal(buf_load(rs, vo, i * ls), cld(tb.q_hat_inv, i), cld(tb.p, i), cld(tb.pinv, i));
-    S += y[i] * cld(tb.recip, i);
+    const double pinv = cld(tb.pinv, i);
+    y[i] = mul_bal(buf_load(rs, vo, i * ls), cld(tb.q_hat_inv, i), cld(tb.p, i), pinv);
+    S += y[i] * pinv;
   }
   double v = __builtin_rint(S);
   if (lift_near_half(S, v, tb)) {
@@ -255,7 +256,7 @@ __global__ void __launch_bounds__(256) k_scale(int n, size_t n_poly, double* dt,
     const double p = cld(tb.p, iq), pinv = cld(tb.pinv, iq);
     y[i] = mul_bal(coef_load_both<FUSED>(rs, cs, i * ls),
                    coef_const<FUSED>(cs, FUSED ? kl : tb.t_qhinv, iq, L), p, pinv);
-    S += y[i] * cld(tb.recip, iq);
+    S += y[i] * pinv;
   }
   double v = __builtin_rint(S);
   if (lift_near_half(S, v, tb)) {
@@ -295,7 +296,7 @@ __global__ void __launch_bounds__(256) k_scale(int n, size_t n_poly, double* dt,
                          conv_row<L>(yh, yl, sp, b, binv);
       const double w = reduce_bal(acc, b, binv);
       wp[k * bs] = w;
-      S2 += w * cld(tb.recip, pk);
+      S2 += w * binv;
     }
   }
   const double v2 = __builtin_rint(S2);
@@ -696,7 +697,8 @@ __device__ __forceinline__ void lift_tail(const double (&o)[L], const double (&y
 // outputs as the scale-and-round does, with the last inverse stage's
 // twiddle folded into the second rows of NP_inv_q and ninv_P.
 template <int L, int A>
-__global__ void __launch_bounds__(256) k_moddown_lift(int n, size_t n_poly,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+k_moddown_lift(int n, size_t n_poly,
                                                       const double* __restrict__ acc,
                                                       const double* __restrict__ dt,
                                                       double* __restrict__ ext, Tables tb) {
@@ -743,7 +745,7 @@ __global__ void __launch_bounds__(256) k_moddown_lift(int n, size_t n_poly,
         moddown_term<L, A>(pair_combine(x, sg), tb.NP_inv_q[row * L + iq], kP, iq, q, qinv, tb);
     o[i] = reduce_bal(buf_load(re, vo, i * ls) + r, q, qinv);
     y[i] = mul_bal(o[i], cld(tb.q_hat_inv, iq), q, qinv);
-    S += y[i] * cld(tb.recip, iq);
+    S += y[i] * qinv;
   }
 #pragma unroll
   for (int i = 0; i < L; ++i) buf_store(o[i], rs, vo, i * ls);
@@ -776,7 +778,7 @@ __global__ void __launch_bounds__(256) k_sub_lift(int n, size_t n_poly,
     const double q = cld(tb.p, iq), qinv = cld(tb.pinv, iq);
     o[i] = reduce_bal((double)xp[(size_t)i * n] - (double)yp[(size_t)i * n], q, qinv);
     y[i] = mul_bal(o[i], cld(tb.q_hat_inv, iq), q, qinv);
-    S += y[i] * cld(tb.recip, iq);
+    S += y[i] * qinv;
   }
 #pragma unroll
   for (int i = 0; i < L; ++i) buf_store(o[i], rs, vo, i * ls);
@@ -804,7 +806,7 @@ __global__ void __launch_bounds__(256) k_i64_lift(int n, size_t n_poly,
     const double q = cld(tb.p, iq), qinv = cld(tb.pinv, iq);
     o[i] = from_u64(ip[(size_t)i * n], q);
     y[i] = mul_bal(o[i], cld(tb.q_hat_inv, iq), q, qinv);
-    S += y[i] * cld(tb.recip, iq);
+    S += y[i] * qinv;
   }
 #pragma unroll
   for (int i = 0; i < L; ++i) buf_store(o[i], rs, vo, i * ls);
