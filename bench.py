@@ -472,7 +472,7 @@ def derived_rates(ctx, prof: dict, steps: int, n_ct: int, ms: float) -> dict:
             "modmul_per_step": bfly + levels * per_level}
 
 
-def eq_setup(alpha: int, n_ct: int, ks_fused: int, dev):
+def eq_setup(alpha: int, n_ct: int, ks_fused: int, dev, streams: int = 0):
     """A paper-parameter context with alpha special primes, a uniform
     stand-in relinearization key and a seeded uniform column pair of n_ct
     ciphertexts (seeds 0 and 1; timing is data-oblivious)."""
@@ -482,6 +482,8 @@ def eq_setup(alpha: int, n_ct: int, ks_fused: int, dev):
     ctx = Context.paper(15, alpha=alpha)
     if ks_fused in (0, 1):
         ctx.set_tuning(ks_fused=ks_fused)
+    if streams in (1, 2):
+        ctx.set_tuning(streams=streams)
     log(f"context N={ctx.n} L={ctx.L}+{ctx.alpha} ext={ctx.L_ext} squarings={ctx.squarings}")
     x = synth.uniform_device_residues((n_ct, 2), ctx.q, ctx.n, 0, dev)
     y = synth.uniform_device_residues((n_ct, 2), ctx.q, ctx.n, 1, dev)
@@ -493,17 +495,10 @@ def eq_setup(alpha: int, n_ct: int, ks_fused: int, dev):
     return ctx, x, y, out
 
 
-def eq_steps(ctx, x, y, out, steps: int, warmup: int):
-    """warmup untimed EQ steps, then `steps` timed ones (HIP events on the
-    current stream, every launch profiled): (ms per step, profile, exact-lift
-    fallbacks taken)."""
+def step_ms(ctx, x, y, out, steps: int) -> float:
+    """Mean time of `steps` EQ calls (HIP events on the current stream,
+    which every call joins back to)."""
     import torch
-    ctx.reset_margin_events()
-    for _ in range(warmup):
-        ctx.eq_mask(x, y, out)
-    torch.cuda.synchronize()
-    log("warmup done")
-    ctx.profile(True)
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -512,10 +507,36 @@ def eq_steps(ctx, x, y, out, steps: int, warmup: int):
         ctx.eq_mask(x, y, out)
     end.record()
     torch.cuda.synchronize()
-    ms = start.elapsed_time(end) / steps
+    return start.elapsed_time(end) / steps
+
+
+def eq_steps(ctx, x, y, out, steps: int, warmup: int):
+    """warmup untimed EQ steps, then `steps` timed ones in the context's
+    schedule (with the tuning's two streams: the column's halves on two
+    streams), then `steps` more with every launch timed (profiling runs each
+    call on one stream, so a launch's time is its own, on the whole GPU):
+    (ms per step, profile, exact-lift fallbacks taken, ms per step on one
+    stream or None when the schedule is one stream)."""
+    import torch
+    ctx.reset_margin_events()
+    for _ in range(warmup):
+        ctx.eq_mask(x, y, out)
+    torch.cuda.synchronize()
+    log("warmup done")
+    ms = step_ms(ctx, x, y, out, steps)
+    ms_one = None
+    if ctx.tuning()["streams"] == 2 and x.shape[0] >= 32:
+        ctx.set_tuning(streams=1)
+        ctx.eq_mask(x, y, out)
+        ms_one = step_ms(ctx, x, y, out, steps)
+        ctx.set_tuning(streams=2)
+    ctx.profile(True)
+    for _ in range(steps):
+        ctx.eq_mask(x, y, out)
+    torch.cuda.synchronize()
     prof = ctx.profile_read()
     ctx.profile(False)
-    return ms, prof, ctx.margin_events()
+    return ms, prof, ctx.margin_events(), ms_one
 
 
 def timed(fn, reps: int) -> float:
@@ -654,10 +675,10 @@ def summarize_profiles(prof_dir: str, out_dir: str) -> None:
                    "calibration": {"copy_mib": mib, "factors": factors}}, fh, indent=1)
     cmd_trace = (f"rocprofv3 --kernel-trace --stats -d {prof_dir}/trace -o eq --output-format csv "
                  "-- python3 bench.py --steps 3 --warmup 1 --skip-batched --skip-cpu --skip-next "
-                 "--skip-latency --skip-probes --skip-other")
+                 "--skip-latency --skip-probes --skip-other --streams 1")
     cmd_pmc = (f"rocprofv3 --pmc {{C}} -d {prof_dir}/{{d}} -o eq --output-format csv -- python3 "
                "bench.py --steps 1 --warmup 0 --skip-batched --skip-cpu --skip-next --skip-latency "
-               "--skip-probes --skip-other --calibrate-copy-mib 256")
+               "--skip-probes --skip-other --streams 1 --calibrate-copy-mib 256")
     with open(os.path.join(out_dir, "eq_mask_2p20_rows_kernels.md"), "w") as fh:
         fh.write("# EQ mask, 2^20 rows (32 ciphertexts, N=32768), per-kernel time\n\n")
         fh.write(f"Library hash: {kernel_hash()}\n\nCommand (from the repo root, "
@@ -704,6 +725,10 @@ def main() -> int:
                          "primes; the default: the fastest whose noise budget covers every "
                          "operator), 2 (16 data primes, two special primes) or 1 (17 data "
                          "primes and one special prime)")
+    ap.add_argument("--streams", type=int, default=0, choices=(0, 1, 2),
+                    help="EQ calls on one stream (1) or the column's halves on two (2); "
+                         "default: the context's tuning (two).  The rocprofv3 runs use 1, so "
+                         "that every launch covers the whole column alone on the GPU")
     ap.add_argument("--skip-other", action="store_true",
                     help="skip timing the other key-switching decompositions")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -733,8 +758,8 @@ def main() -> int:
         torch.cuda.synchronize()
         del a, b
     n_ct = args.n_ct
-    ctx, x, y, out = eq_setup(args.alpha, n_ct, args.ks_fused, dev)
-    ms, prof, margin = eq_steps(ctx, x, y, out, args.steps, args.warmup)
+    ctx, x, y, out = eq_setup(args.alpha, n_ct, args.ks_fused, dev, args.streams)
+    ms, prof, margin, ms_one = eq_steps(ctx, x, y, out, args.steps, args.warmup)
     records = n_ct * ctx.n
     value = records / (ms / 1e3)
     log(f"{ms:.2f} ms/step, {value:.4g} records/s")
@@ -748,11 +773,12 @@ def main() -> int:
         for oa in (1, 2, 3):
             if oa == args.alpha:
                 continue
-            c2, x2, y2, o2 = eq_setup(oa, n_ct, -1, dev)
-            ms2, prof2, _ = eq_steps(c2, x2, y2, o2, args.steps, args.warmup)
+            c2, x2, y2, o2 = eq_setup(oa, n_ct, -1, dev, args.streams)
+            ms2, prof2, _, ms2_one = eq_steps(c2, x2, y2, o2, args.steps, args.warmup)
             other.append({"special_primes": oa, "data_primes": c2.L, "key_switch_digits": c2.dnum,
                           "depth_budget": c2.depth_budget,
                           "ms_per_step": ms2, "records_per_s": records / (ms2 / 1e3),
+                          "ms_per_step_one_stream": ms2_one,
                           "roofline": roofline_dominant(prof2, c2)[0],
                           "roofline_ks_mac": roofline_ks(c2, prof2, n_ct, c2.tuning()["ks_chunk"]),
                           "kernels": {k: {"launches": v["launches"] // args.steps,
@@ -793,6 +819,11 @@ def main() -> int:
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms,
+        "ms_per_step_one_stream": ms_one,
+        "schedule": {"timed": ("the column's two halves on two streams" if ms_one is not None
+                               else "one stream"),
+                     "kernels_and_roofline": "one stream: every launch timed alone on the GPU, "
+                                             "covering the whole column"},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

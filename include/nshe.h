@@ -239,7 +239,9 @@ int nshe_relinearize(nshe_ctx* ctx, const int64_t* in3_dev, int64_t* out_dev,
 /* EQ(x, y) = 1 - (x - y)^(t-1) (Eq. eq:equality) for n_ct ciphertexts:
  * x is [n_ct][2][L][N]; y is the same shape, or one ciphertext broadcast to
  * every x when y_broadcast != 0 (an encrypted predicate constant).  Requires
- * t - 1 = 2^k (k squarings).  out may alias x (not y when broadcast). */
+ * t - 1 = 2^k (k squarings).  out may alias x (not y when broadcast).
+ * From 32 ciphertexts on, the call runs its two halves on two streams
+ * (tuning streams, see nshe_tuning); it stays ordered on `stream`. */
 int nshe_eq_mask(nshe_ctx* ctx, const int64_t* x_dev, const int64_t* y_dev,
                  int64_t* out_dev, int n_ct, int y_broadcast, void* ws_dev,
                  size_t ws_bytes, void* stream);
@@ -430,8 +432,18 @@ int nshe_sum_slots(nshe_ctx* ctx, const int64_t* in_dev, int64_t* out_dev, int n
  *   ks_fused       1: at N = 32768 with split_forward, the key-switch
  *                  product runs fused with the digit transforms (one
  *                  kernel; the digits' transforms are never written),
- *                  0: digit transforms, then the product (two kernels).
- * A new context starts at {32, 1, 128, 0, 0}.  nshe_set_tuning validates the
+ *                  0: digit transforms, then the product (two kernels);
+ *   streams        2: nshe_eq_mask with at least 32 ciphertexts runs the
+ *                  first half of them on `stream` and the second half on a
+ *                  second stream the context owns (non-blocking, default
+ *                  priority), each in its own half of the workspace, so
+ *                  that one half's kernels fill the GPU while the other's
+ *                  drain; the second stream starts after the work already
+ *                  on `stream` and `stream` waits for it at the end
+ *                  (events), so the call stays ordered on `stream`.  Not
+ *                  while profiling, while `stream` is being captured into
+ *                  a graph, or in nshe_eq_mask_noalloc.  1: one stream.
+ * A new context starts at {32, 1, 128, 0, 0, 2}.  nshe_set_tuning validates the
  * values (NSHE_EINVAL otherwise) and drops the batched call's cached graphs.
  *
  * nshe_autotune measures, on the caller's sample ciphertexts (int64
@@ -453,6 +465,7 @@ typedef struct {
   int32_t ew_block;
   int32_t wave_ct;
   int32_t ks_fused;
+  int32_t streams;
 } nshe_tuning;
 
 int nshe_get_tuning(nshe_ctx* ctx, nshe_tuning* out_host);

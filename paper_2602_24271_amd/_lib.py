@@ -57,7 +57,7 @@ class NsheKernelStat(ctypes.Structure):
 class NsheTuning(ctypes.Structure):
     _fields_ = [("ks_chunk", ctypes.c_int32), ("split_forward", ctypes.c_int32),
                 ("ew_block", ctypes.c_int32), ("wave_ct", ctypes.c_int32),
-                ("ks_fused", ctypes.c_int32)]
+                ("ks_fused", ctypes.c_int32), ("streams", ctypes.c_int32)]
 
 
 class NsheModmulProbe(ctypes.Structure):

@@ -412,7 +412,7 @@ class Context:
                                                   _stream()))
         return res
 
-    TUNING_FIELDS = ("ks_chunk", "split_forward", "ew_block", "wave_ct", "ks_fused")
+    TUNING_FIELDS = tuple(f for f, _ in _lib.NsheTuning._fields_)
     DEFAULT_WAVE = 32  # batched wave when neither the call nor the tuning sets one
 
     def tuning(self) -> dict:

@@ -189,7 +189,11 @@ struct nshe_ctx {
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
   hipStream_t cap_stream = nullptr;  // capture-only stream (the null stream cannot capture)
-  nshe_tuning tune{32, 1, 128, 0, 0};  // the autotuner's choice at 32 ciphertexts, N = 2^15
+  // the EQ call's second half (tuning streams = 2): its stream and the
+  // events that fork it from, and join it back to, the caller's stream
+  hipStream_t half_stream = nullptr;
+  hipEvent_t half_fork = nullptr, half_join = nullptr;
+  nshe_tuning tune{32, 1, 128, 0, 0, 2};  // the autotuner's choice at 32 ciphertexts, N = 2^15
   std::map<uint32_t, double*> galois;  // Galois element -> switching key (NTT domain)
   // comparison polynomial (t = 2^K + 1 prime; lt_K = 0 otherwise): k babies,
   // m giants, coefficient matrix [m][k] (centred ints) on the device
@@ -1236,6 +1240,9 @@ int nshe_ctx_destroy(nshe_ctx* c) {
   }
   for (auto& e : c->pool) (void)hipEventDestroy(e);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  if (c->half_stream) (void)hipStreamDestroy(c->half_stream);
+  if (c->half_fork) (void)hipEventDestroy(c->half_fork);
+  if (c->half_join) (void)hipEventDestroy(c->half_join);
   if (c->evk) (void)hipFree(c->evk);
   for (auto& kv : c->galois) (void)hipFree(kv.second);
   if (c->dev_tables) (void)hipFree(c->dev_tables);
@@ -1521,6 +1528,22 @@ static int eq_levels(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st,
   return NSHE_OK;
 }
 
+static int eq_run(nshe_ctx* c, const int64_t* x, const int64_t* y, int64_t* out, int n_ct,
+                  int y_broadcast, void* ws, hipStream_t st);
+
+// Whether an EQ call runs as two halves on two streams (tuning streams = 2):
+// at least 32 ciphertexts (16 per half keep the key-switch product's key
+// reads at one per 16 ciphertexts), not profiling (each launch's own time),
+// not the no-allocation scratch, not while st is being captured, and only
+// where the second half's share of the workspace starts 256-byte aligned.
+static bool two_halves(nshe_ctx* c, int n_ct, const void* ws, hipStream_t st) {
+  if (c->tune.streams != 2 || n_ct < 32 || c->prof || ws == c->scratch) return false;
+  if (ws_doubles(c, n_ct / 2) * sizeof(double) % 256) return false;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess) return false;
+  return cs == hipStreamCaptureStatusNone;
+}
+
 static int eq_mask_impl(nshe_ctx* c, const int64_t* x, const int64_t* y, int64_t* out,
                         int n_ct, int y_broadcast, void* ws, size_t ws_bytes, void* stream) {
   int rc = common_checks(c, n_ct, ws, ws_bytes, true);
@@ -1533,6 +1556,33 @@ static int eq_mask_impl(nshe_ctx* c, const int64_t* x, const int64_t* y, int64_t
   if ((rc = check_inputs(c, st, {{x, (size_t)n_ct * 2},
                                  {y, y_broadcast ? (size_t)2 : (size_t)n_ct * 2}})))
     return rc;
+  if (two_halves(c, n_ct, ws, st)) {
+    // the second half: its ciphertexts, its own share of the workspace
+    // (the workspace is linear in n_ct, so the two shares fill it), on the
+    // context's second stream, which starts after the work already on st;
+    // st then waits for it
+    const int h = n_ct / 2;
+    const size_t ctw = (size_t)2 * c->L * c->n;
+    if (!c->half_stream) HIPCHK(hipStreamCreateWithFlags(&c->half_stream, hipStreamNonBlocking));
+    if (!c->half_fork) HIPCHK(hipEventCreateWithFlags(&c->half_fork, hipEventDisableTiming));
+    if (!c->half_join) HIPCHK(hipEventCreateWithFlags(&c->half_join, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(c->half_fork, st));
+    HIPCHK(hipStreamWaitEvent(c->half_stream, c->half_fork, 0));
+    rc = eq_run(c, x, y, out, h, y_broadcast, ws, st);
+    if (!rc)
+      rc = eq_run(c, x + h * ctw, y_broadcast ? y : y + h * ctw, out + h * ctw, n_ct - h,
+                  y_broadcast, static_cast<double*>(ws) + ws_doubles(c, h), c->half_stream);
+    HIPCHK(hipEventRecord(c->half_join, c->half_stream));
+    HIPCHK(hipStreamWaitEvent(st, c->half_join, 0));
+    return rc;
+  }
+  return eq_run(c, x, y, out, n_ct, y_broadcast, ws, st);
+}
+
+// The EQ chain itself on n_ct ciphertexts (checked by the caller), on st.
+static int eq_run(nshe_ctx* c, const int64_t* x, const int64_t* y, int64_t* out, int n_ct,
+                  int y_broadcast, void* ws, hipStream_t st) {
+  int rc = NSHE_OK;
   Ws w = carve(c, ws, n_ct);
   Dims d = dims(c, n_ct);
   const size_t W = W_of(c), N = c->n;
@@ -2354,7 +2404,7 @@ static bool tuning_valid(const nshe_tuning& t) {
   const bool ks = t.ks_chunk == 4 || t.ks_chunk == 8 || t.ks_chunk == 16 || t.ks_chunk == 32;
   const bool blk = t.ew_block == 64 || t.ew_block == 128 || t.ew_block == 256;
   return ks && blk && (t.split_forward == 0 || t.split_forward == 1) && t.wave_ct >= 0 &&
-         (t.ks_fused == 0 || t.ks_fused == 1);
+         (t.ks_fused == 0 || t.ks_fused == 1) && (t.streams == 1 || t.streams == 2);
 }
 
 static void drop_graphs(nshe_ctx* c) {

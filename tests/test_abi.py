@@ -174,7 +174,7 @@ _STRUCTS = {
     "nshe_budget": ("NsheBudget", ["depth_budget", "lt_depth", "fresh_bits", "level_bits"]),
     "nshe_item": ("NsheItem", ["x_dev", "y_dev", "out_dev", "n_ct", "y_broadcast"]),
     "nshe_tuning": ("NsheTuning", ["ks_chunk", "split_forward", "ew_block", "wave_ct",
-                                   "ks_fused"]),
+                                   "ks_fused", "streams"]),
     "nshe_kernel_stat": ("NsheKernelStat", ["name", "launches", "total_ms", "work"]),
     "nshe_modmul_probe": ("NsheModmulProbe", ["ms", "products_per_s", "fp64_ops_per_s"]),
     "nshe_conv_probe": ("NsheConvProbe", ["coefficients", "ms_fma", "ms_mfma", "mismatches"]),

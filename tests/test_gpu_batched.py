@@ -60,7 +60,7 @@ def test_tunings_do_not_change_results(s256):
 def test_set_tuning_rejects_bad_values(s256):
     from paper_2602_24271_amd._lib import NsheError
     for bad in [dict(ks_chunk=5), dict(ew_block=32), dict(split_forward=2), dict(wave_ct=-1),
-                dict(ks_fused=2)]:
+                dict(ks_fused=2), dict(streams=0), dict(streams=3)]:
         with pytest.raises(NsheError):
             s256.ctx.set_tuning(**bad)
 

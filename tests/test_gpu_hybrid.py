@@ -131,6 +131,42 @@ def test_eq_mask_broadcast_and_batched(a1k):
     _same(S, outs[1], want[2:])
 
 
+def _eq_both_schedules(S, dx, dy):
+    """EQ of dx against dy with one stream and with the call's two halves on
+    two streams (tuning streams); also out aliasing x.  Returns the one-stream
+    mask after checking that the others equal it."""
+    start = S.ctx.tuning()
+    try:
+        S.ctx.set_tuning(streams=1)
+        one = S.ctx.eq_mask(dx, dy)
+        S.ctx.set_tuning(streams=2)
+        two = S.ctx.eq_mask(dx, dy)
+        xa = dx.clone()
+        S.ctx.eq_mask(xa, dy, out=xa)
+    finally:
+        S.ctx.set_tuning(**start)
+    assert torch.equal(two, one)
+    assert torch.equal(xa, one)
+    return one
+
+
+def test_eq_mask_two_streams(a1k):
+    """33 ciphertexts (halves of 16 and 17 on two streams): the same masks as
+    on one stream, the first and last (the same pair) the oracle's, with y per
+    ciphertext and broadcast."""
+    S = a1k
+    x, y = synth.column_pair_half_match(5, S.pr.n)
+    cx, cy = S.enc(x, 51), S.enc(y, 52)
+    want = bfv.eq_chain(S.pr, S.rk, cx, cy)[1]
+    dx, dy = S.to_dev([cx]), S.to_dev([cy])
+    ox = synth.uniform_device_residues((31, 2), S.ctx.q, S.ctx.n, 53, S.ctx.device)
+    oy = synth.uniform_device_residues((31, 2), S.ctx.q, S.ctx.n, 54, S.ctx.device)
+    X = torch.cat([dx, ox, dx]).contiguous()
+    for Y in (torch.cat([dy, oy, dy]).contiguous(), dy):
+        got = _eq_both_schedules(S, X, Y)
+        _same(S, got[[0, 32]], [want, want])
+
+
 def test_wide_lift_window(a1k):
     S = a1k
     x, y = synth.column_pair_half_match(3, S.pr.n)
@@ -238,6 +274,25 @@ def test_full_size_key_switch_chunks(request, alpha):
         assert torch.equal(o, outs[0])
     fc.check(g, "level_01", outs[0][0].cpu().numpy())
     fc.check(g, "level_01", outs[0][32].cpu().numpy())
+
+
+@pytest.mark.parametrize("alpha", ALPHAS)
+def test_full_size_eq_mask_two_streams(request, alpha):
+    """The benchmark's schedule at the paper's size: 33 ciphertexts, the
+    call's halves on two streams, equal to one stream; the first and last
+    ciphertexts (the golden pair) bit-exact against the oracle's mask."""
+    S = _full(request, alpha)
+    E = _env(S)
+    g = fc.load_golden(f"a{alpha}_eq_edges")
+    x, y, cx, cy = fc.eq_edges_inputs(E)
+    dx, dy = S.to_dev([cx]), S.to_dev([cy])
+    ox = synth.uniform_device_residues((31, 2), S.ctx.q, S.ctx.n, 78, S.ctx.device)
+    oy = synth.uniform_device_residues((31, 2), S.ctx.q, S.ctx.n, 79, S.ctx.device)
+    X = torch.cat([dx, ox, dx]).contiguous()
+    for Y in (torch.cat([dy, oy, dy]).contiguous(), dy):
+        got = _eq_both_schedules(S, X, Y)
+        fc.check(g, "mask", got[0].cpu().numpy())
+        fc.check(g, "mask", got[32].cpu().numpy())
 
 
 @pytest.mark.parametrize("alpha", ALPHAS)
