@@ -273,7 +273,9 @@ int nshe_eq_mask_noalloc(nshe_ctx* ctx, const int64_t* x_dev, const int64_t* y_d
  * in the workspace (filled by small kernels at the start of the call), so
  * one graph per wave size serves every wave and every later call with the
  * same workspace and wave size.  Capture runs on a context-owned stream and
- * the graph is launched on `stream`.  ws_bytes must cover
+ * the graph is launched on `stream` (with tuning streams = 2 and waves of at
+ * least 32: half-waves, on `stream` and the context's second stream in
+ * turn, one graph per stream and half-wave size).  ws_bytes must cover
  * nshe_batched_workspace_bytes(ctx, wave size, total ciphertexts); with
  * wave_ct = 0 the wave is the tuned one, capped by what ws_bytes holds. */
 typedef struct {
@@ -438,11 +440,14 @@ int nshe_sum_slots(nshe_ctx* ctx, const int64_t* in_dev, int64_t* out_dev, int n
  *                  second stream the context owns (non-blocking, default
  *                  priority), each in its own half of the workspace, so
  *                  that one half's kernels fill the GPU while the other's
- *                  drain; the second stream starts after the work already
- *                  on `stream` and `stream` waits for it at the end
- *                  (events), so the call stays ordered on `stream`.  Not
- *                  while profiling, while `stream` is being captured into
- *                  a graph, or in nshe_eq_mask_noalloc.  1: one stream.
+ *                  drain; nshe_eq_mask_batched with waves of at least 32
+ *                  runs half-waves, taking turns between the two streams
+ *                  (each with its own half of the wave's workspace).  The
+ *                  second stream starts after the work already on `stream`
+ *                  and `stream` waits for it at the end (events), so the
+ *                  call stays ordered on `stream`.  Not while profiling,
+ *                  while `stream` is being captured into a graph, or in
+ *                  nshe_eq_mask_noalloc.  1: one stream.
  * A new context starts at {32, 1, 128, 0, 0, 2}.  nshe_set_tuning validates the
  * values (NSHE_EINVAL otherwise) and drops the batched call's cached graphs.
  *
@@ -453,7 +458,8 @@ int nshe_sum_slots(nshe_ctx* ctx, const int64_t* in_dev, int64_t* out_dev, int n
  * kernels it shapes, on min(32, wave limit) ciphertexts), then the per-ciphertext
  * time of a level at 1, 2, 4, ... ciphertexts up to the wave limit
  * (max_wave_ct if > 0, and what ws_bytes holds), keeping the smallest wave
- * within 1% of the best rate.  The result becomes the context's tuning and
+ * within 1% of the best rate (with streams = 2, at least 32 where that many
+ * fit: the batched call's half-waves).  The result becomes the context's tuning and
  * is copied to *out_host (if not NULL); *ms_per_ct_host (if not NULL)
  * receives the best per-ciphertext level time in ms.  Needs the relin key.
  * The workspace contents are overwritten; the sample is only read.  The

@@ -1536,12 +1536,24 @@ static int eq_run(nshe_ctx* c, const int64_t* x, const int64_t* y, int64_t* out,
 // reads at one per 16 ciphertexts), not profiling (each launch's own time),
 // not the no-allocation scratch, not while st is being captured, and only
 // where the second half's share of the workspace starts 256-byte aligned.
-static bool two_halves(nshe_ctx* c, int n_ct, const void* ws, hipStream_t st) {
-  if (c->tune.streams != 2 || n_ct < 32 || c->prof || ws == c->scratch) return false;
-  if (ws_doubles(c, n_ct / 2) * sizeof(double) % 256) return false;
+static bool stream_idle_capture(hipStream_t st) {
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(st, &cs) != hipSuccess) return false;
   return cs == hipStreamCaptureStatusNone;
+}
+
+static bool two_halves(nshe_ctx* c, int n_ct, const void* ws, hipStream_t st) {
+  if (c->tune.streams != 2 || n_ct < 32 || c->prof || ws == c->scratch) return false;
+  if (ws_doubles(c, n_ct / 2) * sizeof(double) % 256) return false;
+  return stream_idle_capture(st);
+}
+
+// The context's second stream and its fork and join events, made on first use.
+static int half_stream_ready(nshe_ctx* c) {
+  if (!c->half_stream) HIPCHK(hipStreamCreateWithFlags(&c->half_stream, hipStreamNonBlocking));
+  if (!c->half_fork) HIPCHK(hipEventCreateWithFlags(&c->half_fork, hipEventDisableTiming));
+  if (!c->half_join) HIPCHK(hipEventCreateWithFlags(&c->half_join, hipEventDisableTiming));
+  return NSHE_OK;
 }
 
 static int eq_mask_impl(nshe_ctx* c, const int64_t* x, const int64_t* y, int64_t* out,
@@ -1563,9 +1575,7 @@ static int eq_mask_impl(nshe_ctx* c, const int64_t* x, const int64_t* y, int64_t
     // st then waits for it
     const int h = n_ct / 2;
     const size_t ctw = (size_t)2 * c->L * c->n;
-    if (!c->half_stream) HIPCHK(hipStreamCreateWithFlags(&c->half_stream, hipStreamNonBlocking));
-    if (!c->half_fork) HIPCHK(hipEventCreateWithFlags(&c->half_fork, hipEventDisableTiming));
-    if (!c->half_join) HIPCHK(hipEventCreateWithFlags(&c->half_join, hipEventDisableTiming));
+    if ((rc = half_stream_ready(c))) return rc;
     HIPCHK(hipEventRecord(c->half_fork, st));
     HIPCHK(hipStreamWaitEvent(c->half_stream, c->half_fork, 0));
     rc = eq_run(c, x, y, out, h, y_broadcast, ws, st);
@@ -1655,9 +1665,10 @@ static BatchArea batch_area(const nshe_ctx* c, void* ws, int wave_ct, long long 
 }
 
 // One wave of cnt ciphertexts: gather x - y, the 16 levels, scatter the
-// mask, advance the wave counter.
-static int enqueue_wave(nshe_ctx* c, int cnt, int stride, const BatchArea& a, const Ws& w,
-                        hipStream_t st) {
+// mask, advance the wave counter by `step` (the number of streams taking
+// turns over the table's waves).
+static int enqueue_wave(nshe_ctx* c, int cnt, int stride, int step, const BatchArea& a,
+                        const Ws& w, hipStream_t st) {
   Dims d = dims(c, cnt);
   {
     Prof pf(c, K_SUB, st, 2.0 * cnt * c->L * c->n);
@@ -1669,7 +1680,7 @@ static int enqueue_wave(nshe_ctx* c, int cnt, int stride, const BatchArea& a, co
     Prof pf(c, K_CONVERT, st, 2.0 * cnt * c->L * c->n);
     HIPCHK(run_scatter_mask(d, stride, a.table, a.counter, w.ext, c->tb, st));
   }
-  HIPCHK(run_bump_counter(a.counter, st));
+  HIPCHK(run_bump_counter(a.counter, step, st));
   return NSHE_OK;
 }
 
@@ -1717,12 +1728,29 @@ int nshe_eq_mask_batched(nshe_ctx* c, const nshe_item* items, int n_items, int w
   const BatchArea area = batch_area(c, ws, wave_ct, total);
   const size_t ctw = (size_t)2 * c->L * c->n;
 
-  // per-ciphertext pointers, wave by wave (wave k at entries k * wave_ct)
-  HIPCHK(run_set_counter(area.counter, 0, st));
+  // Two streams (tuning streams = 2): half-waves of wave_ct / 2 ciphertexts
+  // alternate between st and the context's second stream.  Each stream has
+  // its own share of the wave's ciphertext area (the two shares fill it)
+  // and its own wave counter (128 bytes apart), which starts at the
+  // stream's first wave and steps by two, so that one stream's kernels and
+  // graphs never touch the other's.  (Units: the waves the table is laid out
+  // in, half-waves with two streams.)
+  const int hw = wave_ct / 2;
+  const bool two = c->tune.streams == 2 && hw >= 16 && total > hw && !c->prof &&
+                   ws_doubles(c, hw) * sizeof(double) % 256 == 0 && stream_idle_capture(st);
+  const int unit = two ? hw : wave_ct;
+  const int n_seq = two ? 2 : 1;
+  const long long n_units = (total + unit - 1) / unit;
+  const BatchArea seq[2] = {area, BatchArea{area.table, area.counter + 32}};
+  char* const share[2] = {static_cast<char*>(ws),
+                          static_cast<char*>(ws) + ws_doubles(c, hw) * sizeof(double)};
+
+  // per-ciphertext pointers, unit by unit (unit u at entries u * unit; at
+  // most total + wave_ct entries)
+  for (int q = 0; q < n_seq; ++q) HIPCHK(run_set_counter(seq[q].counter, q, st));
   TableChunk ch{};
   ch.first = 0;
   ch.n = 0;
-  long long k = 0;  // running ciphertext index = wave * wave_ct + position
   auto flush = [&]() -> int {
     if (ch.n == 0) return NSHE_OK;
     HIPCHK(run_fill_table(ch, area.table, st));
@@ -1732,7 +1760,7 @@ int nshe_eq_mask_batched(nshe_ctx* c, const nshe_item* items, int n_items, int w
   };
   for (int i = 0; i < n_items; ++i) {
     const nshe_item& it = items[i];
-    for (int j = 0; j < it.n_ct; ++j, ++k) {
+    for (int j = 0; j < it.n_ct; ++j) {
       CtPtrs e;
       e.x = it.x_dev + (size_t)j * ctw;
       e.y = it.y_broadcast ? it.y_dev : it.y_dev + (size_t)j * ctw;
@@ -1747,17 +1775,23 @@ int nshe_eq_mask_batched(nshe_ctx* c, const nshe_item* items, int n_items, int w
   int rc = flush();
   if (rc) return rc;
 
-  const long long n_waves = (total + wave_ct - 1) / wave_ct;
-  for (long long wv = 0; wv < n_waves; ++wv) {
-    const int cnt = (int)std::min<long long>(wave_ct, total - wv * wave_ct);
-    Ws w = carve(c, ws, cnt);
+  if (two) {
+    if ((rc = half_stream_ready(c))) return rc;
+    HIPCHK(hipEventRecord(c->half_fork, st));
+    HIPCHK(hipStreamWaitEvent(c->half_stream, c->half_fork, 0));
+  }
+  for (long long u = 0; u < n_units && !rc; ++u) {
+    const int q = (int)(u % n_seq);
+    hipStream_t su = q ? c->half_stream : st;
+    const int cnt = (int)std::min<long long>(unit, total - u * unit);
+    Ws w = carve(c, share[q], cnt);
     if (!use_graph) {
-      rc = enqueue_wave(c, cnt, wave_ct, area, w, st);
-      if (rc) return rc;
+      rc = enqueue_wave(c, cnt, unit, n_seq, seq[q], w, su);
       continue;
     }
-    const std::vector<uintptr_t> key = {reinterpret_cast<uintptr_t>(ws), (uintptr_t)cnt,
-                                        (uintptr_t)wave_ct};
+    const std::vector<uintptr_t> key = {reinterpret_cast<uintptr_t>(share[q]), (uintptr_t)cnt,
+                                        (uintptr_t)unit, (uintptr_t)n_seq,
+                                        reinterpret_cast<uintptr_t>(seq[q].counter)};
     const bool prof_saved = c->prof;
     c->prof = false;  // no event records inside a captured graph
     struct Restore {
@@ -1768,27 +1802,49 @@ int nshe_eq_mask_batched(nshe_ctx* c, const nshe_item* items, int n_items, int w
     auto found = c->graphs.find(key);
     if (found == c->graphs.end()) {
       // Capture on a context-owned stream (nothing executes during capture);
-      // the instantiated graph is then launched on the caller's stream.
-      if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+      // the instantiated graph is then launched on the unit's stream.
+      if (!c->cap_stream) {
+        hipError_t e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+          rc = fail(NSHE_EDEVICE, std::string("stream: ") + hipGetErrorString(e));
+          break;
+        }
+      }
       hipGraph_t g = nullptr;
-      HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-      rc = enqueue_wave(c, cnt, wave_ct, area, w, c->cap_stream);
-      hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+      hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) {
+        rc = fail(NSHE_EDEVICE, std::string("capture: ") + hipGetErrorString(e));
+        break;
+      }
+      rc = enqueue_wave(c, cnt, unit, n_seq, seq[q], w, c->cap_stream);
+      e = hipStreamEndCapture(c->cap_stream, &g);
       if (rc) {
         if (g) (void)hipGraphDestroy(g);
-        return rc;
+        break;
       }
-      if (e != hipSuccess) return fail(NSHE_EDEVICE, std::string("capture: ") + hipGetErrorString(e));
+      if (e != hipSuccess) {
+        rc = fail(NSHE_EDEVICE, std::string("capture: ") + hipGetErrorString(e));
+        break;
+      }
       hipGraphExec_t ex = nullptr;
       e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
       (void)hipGraphDestroy(g);
-      if (e != hipSuccess) return fail(NSHE_EDEVICE, std::string("instantiate: ") + hipGetErrorString(e));
+      if (e != hipSuccess) {
+        rc = fail(NSHE_EDEVICE, std::string("instantiate: ") + hipGetErrorString(e));
+        break;
+      }
       if (c->graphs.size() >= 16) drop_graphs(c);
       found = c->graphs.emplace(key, nshe_ctx::GraphEntry{ex}).first;
     }
-    HIPCHK(hipGraphLaunch(found->second.exec, st));
+    hipError_t e = hipGraphLaunch(found->second.exec, su);
+    if (e != hipSuccess) rc = fail(NSHE_EDEVICE, std::string("launch: ") + hipGetErrorString(e));
   }
-  return NSHE_OK;
+  if (two) {
+    // st waits for the second stream's units whatever happened above
+    HIPCHK(hipEventRecord(c->half_join, c->half_stream));
+    HIPCHK(hipStreamWaitEvent(st, c->half_join, 0));
+  }
+  return rc;
 }
 
 // bytes of an int64 ciphertext array, rounded up to 256
@@ -2607,6 +2663,9 @@ int nshe_autotune(nshe_ctx* c, const int64_t* sample, int n_sample, int max_wave
   for (auto& r : rates) rbest = std::min(rbest, r.second);
   for (auto& r : rates)
     if (r.second <= 1.01 * rbest) { best.wave_ct = r.first; break; }
+  // two streams: waves of at least 32 where the workspace holds them, so
+  // that the batched call's half-waves (16 or more) take turns on them
+  if (best.streams == 2 && fit >= 32) best.wave_ct = std::max(best.wave_ct, 32);
   drop_graphs(c);
   c->tune = best;
   if (out) *out = best;

@@ -292,7 +292,7 @@ struct TableChunk {
 };
 hipError_t run_fill_table(const TableChunk& ch, CtPtrs* table, hipStream_t st);
 hipError_t run_set_counter(int* counter, int v, hipStream_t st);
-hipError_t run_bump_counter(int* counter, hipStream_t st);
+hipError_t run_bump_counter(int* counter, int step, hipStream_t st);
 hipError_t run_sub_i64(const Dims& d, const int64_t* x, const int64_t* y, int64_t* out,
                        const Tables& tb, hipStream_t st);
 // int64 [0, q) -> balanced doubles; polys with index >= canon_from keep the

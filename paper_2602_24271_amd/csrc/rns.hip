@@ -1155,8 +1155,8 @@ __global__ void k_set_counter(int* counter, int v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) counter[0] = v;
 }
 
-__global__ void k_bump_counter(int* counter) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) counter[0] += 1;
+__global__ void k_bump_counter(int* counter, int step) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) counter[0] += step;
 }
 
 __global__ void __launch_bounds__(256) k_sub_i64(int n, int L, size_t total, const int64_t* x,
@@ -1705,8 +1705,8 @@ hipError_t run_set_counter(int* counter, int v, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t run_bump_counter(int* counter, hipStream_t st) {
-  hipLaunchKernelGGL(k_bump_counter, dim3(1), dim3(64), 0, st, counter);
+hipError_t run_bump_counter(int* counter, int step, hipStream_t st) {
+  hipLaunchKernelGGL(k_bump_counter, dim3(1), dim3(64), 0, st, counter, step);
   return hipGetLastError();
 }
 

@@ -40,6 +40,43 @@ def test_batched_matches_oracle(s256, wave_ct, use_graph):
                 np.testing.assert_array_equal(o[i].cpu().numpy(), S.limbs(ct))
 
 
+def test_batched_two_streams(s256):
+    """75 ciphertexts in uneven instances, waves of 32: with two streams the
+    half-waves of 16 (the last of 11) alternate between the caller's stream
+    and the context's second one.  Every mask equals the plain call's on one
+    stream (graphs or not, the graphs replayed), and an encrypted pair's
+    equals the oracle's."""
+    S = s256
+    rng = np.random.default_rng(31)
+    x, y = rng.integers(0, S.pr.t, S.pr.n), rng.integers(0, S.pr.t, S.pr.n)
+    x[::2] = y[::2]
+    cx, cy = S.enc(x, 310), S.enc(y, 311)
+    want = bfv.eq_chain(S.pr, S.rk, cx, cy)[1]
+    items = []
+    for k, m in enumerate([20, 1, 33, 21]):
+        xs = synth.uniform_device_residues((m, 2), S.ctx.q, S.ctx.n, 200 + k, S.ctx.device)
+        ys = synth.uniform_device_residues((1 if k % 2 else m, 2), S.ctx.q, S.ctx.n, 300 + k,
+                                           S.ctx.device)
+        if k == 2:
+            xs[5] = S.to_dev([cx])[0]
+            ys[5] = S.to_dev([cy])[0]
+        items.append((xs, ys))
+    start = S.ctx.tuning()
+    try:
+        S.ctx.set_tuning(streams=1)
+        ref = [S.ctx.eq_mask(xs, ys) for xs, ys in items]
+        S.ctx.set_tuning(streams=2)
+        for use_graph in (True, False):
+            for rep in range(2):
+                outs = S.ctx.eq_mask_batched(items, wave_ct=32, use_graph=use_graph)
+                torch.cuda.synchronize()
+                for o, r in zip(outs, ref):
+                    assert torch.equal(o, r)
+    finally:
+        S.ctx.set_tuning(**start)
+    np.testing.assert_array_equal(ref[2][5].cpu().numpy(), S.limbs(want))
+
+
 def test_tunings_do_not_change_results(s256):
     """Every launch shape gives the same integers (and the oracle's)."""
     S = s256

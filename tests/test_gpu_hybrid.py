@@ -296,6 +296,37 @@ def test_full_size_eq_mask_two_streams(request, alpha):
 
 
 @pytest.mark.parametrize("alpha", ALPHAS)
+def test_full_size_batched_two_streams(request, alpha):
+    """Batched EQ at the paper's size with waves of 32: 40 ciphertexts (the
+    golden pair first) in instances of 25 and 15, half-waves of 16, 16 and 8
+    on two streams: equal to the plain call on one stream, the golden pair's
+    mask the oracle's."""
+    S = _full(request, alpha)
+    E = _env(S)
+    g = fc.load_golden(f"a{alpha}_eq_edges")
+    x, y, cx, cy = fc.eq_edges_inputs(E)
+    dx, dy = S.to_dev([cx]), S.to_dev([cy])
+    ox = synth.uniform_device_residues((39, 2), S.ctx.q, S.ctx.n, 80, S.ctx.device)
+    oy = synth.uniform_device_residues((39, 2), S.ctx.q, S.ctx.n, 81, S.ctx.device)
+    X = torch.cat([dx, ox]).contiguous()
+    Y = torch.cat([dy, oy]).contiguous()
+    items = [(X[:25], Y[:25]), (X[25:], Y[25:])]
+    start = S.ctx.tuning()
+    try:
+        S.ctx.set_tuning(streams=1)
+        ref = [S.ctx.eq_mask(a, b) for a, b in items]
+        S.ctx.set_tuning(streams=2)
+        for rep in range(2):
+            outs = S.ctx.eq_mask_batched(items, wave_ct=32, use_graph=True)
+            torch.cuda.synchronize()
+            for o, r in zip(outs, ref):
+                assert torch.equal(o, r)
+    finally:
+        S.ctx.set_tuning(**start)
+    fc.check(g, "mask", ref[0][0].cpu().numpy())
+
+
+@pytest.mark.parametrize("alpha", ALPHAS)
 def test_full_size_columns(request, alpha):
     S = _full(request, alpha)
     E = _env(S)
