@@ -592,10 +592,11 @@ def next_rows(ctx, x, mask, reps: int) -> dict:
                         "paper_ms_per_record": 0.04,
                         "paper_source": "Table tab:primitive-times, SUM and COUNT rows"}
     log(f"SUM/COUNT ({len(els)} rotations) {t * 1e3:.1f} ms")
-    # LT against a broadcast constant, in chunks of 8 ciphertexts (the
-    # comparison workspace holds about 420 ciphertext arrays per chunk)
+    # LT against a broadcast constant, in chunks of 16 ciphertexts (the
+    # comparison workspace holds about 420 ciphertext arrays per chunk: 56 GB
+    # for 16 at N = 32768; chunks of 8 took 8% longer, of 32 3% less, with 111 GB)
     const = synth.uniform_device_residues((1, 2), ctx.q, ctx.n, 32, dev)
-    chunk = min(8, n_ct)
+    chunk = min(16, n_ct)
 
     def lt_column():
         for c0 in range(0, n_ct, chunk):
