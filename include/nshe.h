@@ -500,7 +500,8 @@ int nshe_reset_margin_events(nshe_ctx* ctx, void* stream);
 
 /* The same events per call site of the lift (counts_host[i] for site i,
  * min(max_counts, NSHE_MARGIN_SITES) entries, *n_counts_host set):
- *   0  a product operand's lift (k_lift: batched waves' first level)
+ *   0  a squaring's operand lift not fused into the kernel before it
+ *      (k_lift: the levels without the split transforms)
  *   1  the scale-and-round's lift of [t d]_Q
  *   2  the same after the split inverse (N = 2^15)
  *   3  the mod-down fused with the next squaring's lift

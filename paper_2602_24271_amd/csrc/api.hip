@@ -452,7 +452,8 @@ static int tensor_scale(nshe_ctx* c, const Ws& w, const double* fx_b, int n_ct, 
 
 static int digit_products(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st, const double* key);
 static int finish_relin(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st, double* out,
-                        bool lift_out, int64_t* finish_out, int64_t* i64_out, bool accumulate);
+                        bool lift_out, int64_t* finish_out, int64_t* i64_out, bool accumulate,
+                        const WaveTab* finish_tab);
 
 // Key-switch the third component in dt (limbs 0..L-1: canonical residues,
 // or with several primes per digit each digit's mixed-radix digits) with
@@ -463,10 +464,11 @@ static int finish_relin(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st, doub
 // finish_out: write the result to this int64 buffer with the mask's finish
 // instead (only with the split inverse); i64_out: write it there as it is.
 // accumulate: add the result into out (limbs 0..L-1) instead of storing it.
+// finish_tab: as finish_out, into a batched wave's ciphertexts (its table).
 static int relin(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st,
                  const double* key = nullptr, double* out = nullptr, bool lift_out = false,
                  int64_t* finish_out = nullptr, int64_t* i64_out = nullptr,
-                 bool accumulate = false) {
+                 bool accumulate = false, const WaveTab* finish_tab = nullptr) {
   if (!key) key = c->evk;
   if (!out) out = w.ext;
   if (ks_fused(c)) {
@@ -484,7 +486,8 @@ static int relin(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st,
     int rc0 = digit_products(c, w, n_ct, st, key);
     if (rc0) return rc0;
   }
-  return finish_relin(c, w, n_ct, st, out, lift_out, finish_out, i64_out, accumulate);
+  return finish_relin(c, w, n_ct, st, out, lift_out, finish_out, i64_out, accumulate,
+                      finish_tab);
 }
 
 // The digits' transforms (written to w.dig) and their products with the
@@ -525,11 +528,13 @@ static int digit_products(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st, co
 
 // The key-switch sums in w.acc -> inverse transform -> mod-down (see relin).
 static int finish_relin(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st, double* out,
-                        bool lift_out, int64_t* finish_out, int64_t* i64_out, bool accumulate) {
+                        bool lift_out, int64_t* finish_out, int64_t* i64_out, bool accumulate,
+                        const WaveTab* finish_tab) {
   Dims d = dims(c, n_ct);
   int rc = ntt_job_ks(c, w.acc, nullptr, n_ct * 2, 1, st, true);
   if (rc) return rc;
-  if (finish_out && d.fused) {
+  if ((finish_out || finish_tab) && d.fused) {
+    if (finish_tab) d.tab = *finish_tab;
     Prof pf(c, K_MODDOWN, st, 2.0 * n_ct * c->n);
     HIPCHK(run_moddown_finish(d, w.acc, w.dt, finish_out, c->tb, st, 1));
   } else if (i64_out && d.fused) {
@@ -575,14 +580,14 @@ static int prepare_i64(nshe_ctx* c, const int64_t* in, double* ext, double* fx, 
 // for the next (lift_out), which then skips its own lift (lifted).
 static int square_level(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st,
                         bool lifted = false, bool lift_out = false,
-                        int64_t* finish_out = nullptr) {
+                        int64_t* finish_out = nullptr, const WaveTab* finish_tab = nullptr) {
   const bool chain = split_inverse(c);
   int rc = prepare_operand(c, w.ext, w.fx, n_ct, st, lifted && chain);
   if (rc) return rc;
   rc = tensor_scale(c, w, nullptr, n_ct, st);
   if (rc) return rc;
   return relin(c, w, n_ct, st, nullptr, nullptr, lift_out && chain,
-               chain ? finish_out : nullptr);
+               chain ? finish_out : nullptr, nullptr, false, chain ? finish_tab : nullptr);
 }
 
 static int check_ctx(const nshe_ctx* c) {
@@ -1516,13 +1521,15 @@ int nshe_relinearize(nshe_ctx* c, const int64_t* in3, int64_t* out, int n_ct, vo
 }
 
 // The EQ chain on ciphertexts already differenced into w.ext.
-// finish_out (with the split inverse): the last level writes the mask to it.
+// finish_out (with the split inverse): the last level writes the mask to it;
+// finish_tab: to a batched wave's ciphertexts, through its table.
 static int eq_levels(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st,
-                     bool first_lifted = false, int64_t* finish_out = nullptr) {
+                     bool first_lifted = false, int64_t* finish_out = nullptr,
+                     const WaveTab* finish_tab = nullptr) {
   for (int k = 0; k < c->squarings; ++k) {
     const bool last = k + 1 == c->squarings;
     int rc = square_level(c, w, n_ct, st, k > 0 || first_lifted, !last,
-                          last ? finish_out : nullptr);
+                          last ? finish_out : nullptr, last ? finish_tab : nullptr);
     if (rc) return rc;
   }
   return NSHE_OK;
@@ -1664,21 +1671,35 @@ static BatchArea batch_area(const nshe_ctx* c, void* ws, int wave_ct, long long 
   return BatchArea{reinterpret_cast<CtPtrs*>(p + cts + 256), reinterpret_cast<int*>(p + cts)};
 }
 
-// One wave of cnt ciphertexts: gather x - y, the 16 levels, scatter the
-// mask, advance the wave counter by `step` (the number of streams taking
-// turns over the table's waves).
+// One wave of cnt ciphertexts: x - y, the 16 levels and the mask's finish,
+// the wave's ciphertexts read and written through its table; then advance
+// the wave counter by `step` (the number of streams taking turns over the
+// table's waves).  With the split inverse the ends are the plain chain's
+// fused kernels (subtraction + first lift, last mod-down + finish), else a
+// gather, the levels and a scatter.
 static int enqueue_wave(nshe_ctx* c, int cnt, int stride, int step, const BatchArea& a,
                         const Ws& w, hipStream_t st) {
   Dims d = dims(c, cnt);
-  {
-    Prof pf(c, K_SUB, st, 2.0 * cnt * c->L * c->n);
-    HIPCHK(run_gather_sub(d, stride, a.table, a.counter, w.ext, c->tb, st));
-  }
-  int rc = eq_levels(c, w, cnt, st);
-  if (rc) return rc;
-  {
-    Prof pf(c, K_CONVERT, st, 2.0 * cnt * c->L * c->n);
-    HIPCHK(run_scatter_mask(d, stride, a.table, a.counter, w.ext, c->tb, st));
+  const WaveTab wt{a.table, a.counter, stride};
+  if (split_inverse(c)) {
+    d.tab = wt;
+    {
+      Prof pf(c, K_SUB, st, 2.0 * cnt * c->L * c->n);
+      HIPCHK(run_sub_lift(d, nullptr, nullptr, 0, w.ext, c->tb, st));
+    }
+    int rc = eq_levels(c, w, cnt, st, true, nullptr, &wt);
+    if (rc) return rc;
+  } else {
+    {
+      Prof pf(c, K_SUB, st, 2.0 * cnt * c->L * c->n);
+      HIPCHK(run_gather_sub(d, stride, a.table, a.counter, w.ext, c->tb, st));
+    }
+    int rc = eq_levels(c, w, cnt, st);
+    if (rc) return rc;
+    {
+      Prof pf(c, K_CONVERT, st, 2.0 * cnt * c->L * c->n);
+      HIPCHK(run_scatter_mask(d, stride, a.table, a.counter, w.ext, c->tb, st));
+    }
   }
   HIPCHK(run_bump_counter(a.counter, step, st));
   return NSHE_OK;

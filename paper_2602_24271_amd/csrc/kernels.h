@@ -115,7 +115,7 @@ struct Tables {
 
 // Call sites of the exact-lift fallback (index into Tables::margin).
 enum MarginSite {
-  MARGIN_LIFT = 0,          // k_lift: a product operand's lift (batched waves' first level)
+  MARGIN_LIFT = 0,          // k_lift: a squaring's operand lift, not fused (no split transforms)
   MARGIN_SCALE = 1,         // k_scale: the scale-and-round's lift of [t d]_Q
   MARGIN_SCALE_SPLIT = 2,   // k_scale after the split inverse (N = 2^15)
   MARGIN_MODDOWN_LIFT = 3,  // k_moddown_lift: the next squaring's operand
@@ -178,6 +178,16 @@ hipError_t run_ks_fused(const NttJob& job, const double* evk, double* acc, const
 int ntt_rounds(int log2n, int* loge, int* r0);
 
 // Per-coefficient and elementwise kernels (rns.hip).
+struct CtPtrs;
+
+// A batched wave's ciphertexts: a device table of per-ciphertext pointers
+// ([wave][stride] entries) and the wave, a device counter (table null: none)
+struct WaveTab {
+  const CtPtrs* table = nullptr;
+  const int* wave = nullptr;
+  int stride = 0;
+};
+
 struct Dims {
   int n;        // N
   int L;        // data primes
@@ -193,6 +203,9 @@ struct Dims {
   // the digit transforms are by coefficient parity (N = 2^15): the key-switch
   // product applies their last stage (k_ks_mac_par)
   int parity = 0;
+  // a batched wave's table: run_sub_lift reads x and y, run_moddown_finish
+  // writes out, through it (their pointer arguments are then unused)
+  WaveTab tab;
 };
 
 hipError_t run_lift(const Dims& d, double* ext, const Tables& tb, hipStream_t st);

@@ -610,12 +610,14 @@ __global__ void __launch_bounds__(256) k_moddown(int n, int n_ct, const double* 
 // to the caller's int64 output, canonical residues in [0, q_i): with finish,
 // the mask's finish out = (Delta, 0) - z (every residue negated and
 // [Delta]_{q_i} added to the constant coefficient of c0); without, z.
+// wt (table not null): a batched wave's ciphertexts, written through the
+// table's out pointers.
 template <int L, int A>
 __global__ void __launch_bounds__(256) k_moddown_finish(int n, int n_ct,
                                                         const double* __restrict__ acc,
                                                         const double* __restrict__ dt,
                                                         int64_t* __restrict__ out, int finish,
-                                                        Tables tb) {
+                                                        Tables tb, WaveTab wt) {
   constexpr int K = L + A;
   constexpr int W = 2 * L + 1;
   const int per = n >> 1;
@@ -627,7 +629,8 @@ __global__ void __launch_bounds__(256) k_moddown_finish(int n, int n_ct,
   const int b = (int)(cb & 1);
   const int ip = 2 * L + 1;
   const double* e = dt + ((ct * 3 + b) * (size_t)W) * n + c;
-  int64_t* o = out + cb * (size_t)L * n + c;
+  int64_t* o = wt.table ? wt.table[(size_t)(*wt.wave) * wt.stride + ct].out + (size_t)b * L * n + c
+                        : out + cb * (size_t)L * n + c;
   const int ht = n >> 6;
   const double* a = acc + cb * (size_t)K * n + (size_t)(c / ht) * 2 * ht + (c % ht);
   const size_t hn = (size_t)(n >> 1);
@@ -756,18 +759,28 @@ k_moddown_lift(int n, size_t n_poly,
 // ciphertext broadcast when y_bcast) into ext limbs 0..L-1, followed by the
 // lift of z (limbs L..2L): the first level of the chain, one kernel.  One
 // thread per coefficient of each (ct, b) polynomial, blocks as in k_lift.
+// wt (table not null): a batched wave's ciphertexts, x and y read through
+// the table (a broadcast y is every entry's y).
 template <int L>
 __global__ void __launch_bounds__(256) k_sub_lift(int n, size_t n_poly,
                                                   const int64_t* __restrict__ xs,
                                                   const int64_t* __restrict__ ys, int y_bcast,
-                                                  double* __restrict__ ext, Tables tb) {
+                                                  double* __restrict__ ext, Tables tb, WaveTab wt) {
   constexpr int W = 2 * L + 1;
   const PolyBlock pb = poly_block(n, n_poly);   // poly = ct * 2 + b
   if (!pb.ok) return;
   const size_t cb = pb.pc;
   const int b = (int)(cb & 1);
-  const int64_t* xp = xs + cb * (size_t)L * n + pb.c;
-  const int64_t* yp = (y_bcast ? ys + (size_t)b * L * n : ys + cb * (size_t)L * n) + pb.c;
+  const int64_t* xp;
+  const int64_t* yp;
+  if (wt.table) {
+    const CtPtrs e = wt.table[(size_t)(*wt.wave) * wt.stride + (cb >> 1)];
+    xp = e.x + (size_t)b * L * n + pb.c;
+    yp = e.y + (size_t)b * L * n + pb.c;
+  } else {
+    xp = xs + cb * (size_t)L * n + pb.c;
+    yp = (y_bcast ? ys + (size_t)b * L * n : ys + cb * (size_t)L * n) + pb.c;
+  }
   const auto rs = make_rsrc(ext + cb * (size_t)W * n, (unsigned)(W * n * 8));
   const unsigned vo = (unsigned)pb.c * 8, ls = (unsigned)n * 8;
   double o[L], y[L];
@@ -1300,7 +1313,7 @@ hipError_t run_moddown_finish(const Dims& d, const double* acc, const double* dt
 #define C_(L_, A_)                                                                             \
   case L_:                                                                                     \
     hipLaunchKernelGGL((k_moddown_finish<L_, A_>), grid_for(total, d.block), dim3(d.block), 0, \
-                       st, d.n, d.n_ct, acc, dt, out, finish, tb);                             \
+                       st, d.n, d.n_ct, acc, dt, out, finish, tb, d.tab);                      \
     break;
 #define C1_(L_) C_(L_, 1)
 #define C2_(L_) C_(L_, 2)
@@ -1353,7 +1366,7 @@ hipError_t run_sub_lift(const Dims& d, const int64_t* x, const int64_t* y, int y
 #define C_(L_)                                                                            \
   case L_:                                                                                \
     hipLaunchKernelGGL(k_sub_lift<L_>, poly_grid(np, d.n, d.block), dim3(d.block), 0, st, \
-                       d.n, np, x, y, y_bcast, ext, tb);                                  \
+                       d.n, np, x, y, y_bcast, ext, tb, d.tab);                           \
     break;
     NSHE_L_CASES(C_)
 #undef C_

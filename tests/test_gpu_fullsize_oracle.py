@@ -249,8 +249,9 @@ def test_wide_lift_window_every_site():
 
 def test_wide_lift_window_every_site_full_size(s32k):
     """N = 32768 (split transforms: the fused chain's k_sub_lift,
-    k_moddown_lift and the split k_scale; k_i64_lift; k_lift in a batched
-    wave's first level): bit-exact against the stored oracle digests."""
+    k_moddown_lift and the split k_scale, in the plain call and in a batched
+    wave; k_i64_lift; without the split transforms, k_lift and k_scale in a
+    batched wave): bit-exact against the stored oracle digests."""
     S = s32k
     E = _env(S)
     g = fc.load_golden("eq_edges")
@@ -265,17 +266,26 @@ def test_wide_lift_window_every_site_full_size(s32k):
         fc.check(g, "level_01", lvl1[0].cpu().numpy())
         outs = S.ctx.eq_mask_batched([(dx, dy)], wave_ct=1, use_graph=False)
         fc.check(g, "mask", outs[0][0].cpu().numpy())
+        start = S.ctx.tuning()
+        try:
+            # unsplit transforms: every level lifts with k_lift, scales with
+            # the unsplit k_scale
+            S.ctx.set_tuning(split_forward=0)
+            outs = S.ctx.eq_mask_batched([(dx, dy)], wave_ct=1, use_graph=False)
+            fc.check(g, "mask", outs[0][0].cpu().numpy())
+        finally:
+            S.ctx.set_tuning(**start)
         sites = S.ctx.margin_sites()
     finally:
         S.ctx.set_debug()
     n = S.pr.n
     print("margin sites at N=32768:", sites)
-    # (site 1, the scale-and-round without the split inverse, runs below 2^15)
-    assert all(sites[i] > 0 for i in (0, 2, 3, 4, 5)), sites
-    assert _frac(sites[0], 2 * n) > 0.3               # the batched wave's first lift
+    assert all(sites[i] > 0 for i in range(6)), sites
+    assert _frac(sites[0], 2 * 16 * n) > 0.3          # the unsplit wave's lifts
+    assert _frac(sites[1], 16 * 3 * n) > 0.3          # the unsplit wave's scale
     assert _frac(sites[2], 2 * 16 * 3 * n) > 0.3      # two chains' split scale
     assert _frac(sites[3], 2 * 15 * 2 * n) > 0.3      # two chains' fused mod-down + lift
-    assert _frac(sites[4], 2 * n) > 0.3               # the eq_mask chain's first lift
+    assert _frac(sites[4], 2 * 2 * n) > 0.3           # two fused chains' first lift
     assert _frac(sites[5], 2 * n) > 0.3               # square_relin's operand lift
 
 
