@@ -199,7 +199,7 @@ struct nshe_ctx {
   // m giants, coefficient matrix [m][k] (centred ints) on the device
   int lt_K = 0, lt_k = 0, lt_m = 0, lt_top = 0;
   int lt_depth = 0;  // multiplicative depth of the comparison program
-  const int* lt_coef = nullptr;
+  const double* lt_coef = nullptr;  // (exact small integers)
   // noise budget (see budget_of): multiplications a fresh ciphertext takes
   int depth_budget = 0;
   double fresh_bits = 0.0, level_bits = 0.0;
@@ -1151,7 +1151,7 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
   const size_t off_lp = total;
   total += ((size_t)(W_of(c) + L + alpha) * sizeof(int) + 255) & ~size_t(255);
   // comparison polynomial for a Fermat prime t
-  std::vector<int> lt_coef;
+  std::vector<double> lt_coef;
   if (c->squarings >= 2 && is_prime(c->t)) {
     const int K = c->squarings, kb = K / 2;
     c->lt_K = K;
@@ -1173,7 +1173,7 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
     c->level_bits = bud.level_bits;
   }
   const size_t off_lt = total;
-  total += (lt_coef.size() * sizeof(int) + 255) & ~size_t(255);
+  total += (lt_coef.size() * sizeof(double) + 255) & ~size_t(255);
   int rc = NSHE_OK;
   hipError_t e = hipSetDevice(hip_device);
   if (e == hipSuccess) e = hipMalloc(&c->dev_tables, total);
@@ -1216,9 +1216,9 @@ int nshe_ctx_create(const nshe_params* pr, int hip_device, nshe_ctx** out) {
   if (e == hipSuccess)
     e = hipMemcpy(c->lp_ext, lp.data(), lp.size() * sizeof(int), hipMemcpyHostToDevice);
   if (!lt_coef.empty()) {
-    c->lt_coef = reinterpret_cast<const int*>(base + off_lt);
+    c->lt_coef = reinterpret_cast<const double*>(base + off_lt);
     if (e == hipSuccess)
-      e = hipMemcpy(base + off_lt, lt_coef.data(), lt_coef.size() * sizeof(int),
+      e = hipMemcpy(base + off_lt, lt_coef.data(), lt_coef.size() * sizeof(double),
                     hipMemcpyHostToDevice);
   }
   if (e != hipSuccess) {

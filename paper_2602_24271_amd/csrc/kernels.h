@@ -257,7 +257,7 @@ struct BabyPtrs {
 };
 hipError_t run_tensor_mac(const Dims& d, const double* fa, const double* fb, double* acc,
                           int first, const Tables& tb, hipStream_t st);
-hipError_t run_lincomb(const Dims& d, int k, const BabyPtrs& b, const int* coef, int J,
+hipError_t run_lincomb(const Dims& d, int k, const BabyPtrs& b, const double* coef, int J,
                        int64_t* out, size_t out_stride, const Tables& tb, hipStream_t st);
 hipError_t run_fill_one(const Dims& d, int64_t* out, const Tables& tb, hipStream_t st);
 hipError_t run_diff_i64(const Dims& d, const int64_t* x, const int64_t* y, int y_bcast,

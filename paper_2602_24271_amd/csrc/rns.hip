@@ -908,15 +908,16 @@ __global__ void __launch_bounds__(256) k_tensor_mac(int n, int W, size_t total,
 // out[jj * out_stride + r] = [sum_t coef[jj * k + t] * b.p[t][r]]_q per
 // residue r < per, jj < J <= 16 (int64 canonical in and out).
 // Coefficients are small centred integers (|c| <= 2^15: the comparison
-// polynomial's coefficients mod a Fermat prime t <= 65537) and uniform
-// across the grid (scalar loads).  Each input v (balanced, |v| <= 2^48) is
+// polynomial's coefficients mod a Fermat prime t <= 65537), stored as
+// doubles (exact) and uniform across the grid: scalar loads that the FMAs
+// take as they are, with no conversion per use.  Each input v (balanced, |v| <= 2^48) is
 // split once as v = vh 2^24 + vl (split24), so that every product is an
 // exact FMA (|vh c| <= 2^39): two exact sums per output over k <= 256
 // terms (below 2^47), combined once as Wh [2^24]_q + Wl.  JT: J fixed at
 // compile time (16 or 1), or 0 for any J (a branch per output and term).
 template <int JT>
 __global__ void __launch_bounds__(256) k_lincomb(int n, int L, size_t per, int k, BabyPtrs b,
-                                                 const int* coef, int Jr, int64_t* out,
+                                                 const double* coef, int Jr, int64_t* out,
                                                  size_t out_stride, Tables tb) {
   const int J = JT ? JT : Jr;
   const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -939,7 +940,7 @@ __global__ void __launch_bounds__(256) k_lincomb(int n, int L, size_t per, int k
       if (jj < J) {
 #pragma unroll
         for (int u = 0; u < G; ++u) {
-          const double c = (double)cldi(coef, jj * k + t + u);
+          const double c = cld(coef, jj * k + t + u);
           ah[jj] = __builtin_fma(vh[u], c, ah[jj]);
           al[jj] = __builtin_fma(vl[u], c, al[jj]);
         }
@@ -952,7 +953,7 @@ __global__ void __launch_bounds__(256) k_lincomb(int n, int L, size_t per, int k
 #pragma unroll
     for (int jj = 0; jj < 16; ++jj) {
       if (jj < J) {
-        const double c = (double)cldi(coef, jj * k + t);
+        const double c = cld(coef, jj * k + t);
         ah[jj] = __builtin_fma(vh, c, ah[jj]);
         al[jj] = __builtin_fma(vl, c, al[jj]);
       }
@@ -1643,7 +1644,7 @@ hipError_t run_tensor_mac(const Dims& d, const double* fa, const double* fb, dou
   return hipGetLastError();
 }
 
-hipError_t run_lincomb(const Dims& d, int k, const BabyPtrs& b, const int* coef, int J,
+hipError_t run_lincomb(const Dims& d, int k, const BabyPtrs& b, const double* coef, int J,
                        int64_t* out, size_t out_stride, const Tables& tb, hipStream_t st) {
   const size_t per = (size_t)d.n_ct * 2 * d.L * d.n;
   if (k < 1 || k > BabyPtrs::CAP || J < 1 || J > 16 || (J > 1 && out_stride < per))
