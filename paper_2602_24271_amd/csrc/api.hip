@@ -1538,17 +1538,19 @@ static int eq_levels(nshe_ctx* c, const Ws& w, int n_ct, hipStream_t st,
 static int eq_run(nshe_ctx* c, const int64_t* x, const int64_t* y, int64_t* out, int n_ct,
                   int y_broadcast, void* ws, hipStream_t st);
 
-// Whether an EQ call runs as two halves on two streams (tuning streams = 2):
-// at least 32 ciphertexts (16 per half keep the key-switch product's key
-// reads at one per 16 ciphertexts), not profiling (each launch's own time),
-// not the no-allocation scratch, not while st is being captured, and only
-// where the second half's share of the workspace starts 256-byte aligned.
+// Whether st is known not to be capturing into a graph (a second stream
+// joins only then).
 static bool stream_idle_capture(hipStream_t st) {
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(st, &cs) != hipSuccess) return false;
   return cs == hipStreamCaptureStatusNone;
 }
 
+// Whether an EQ call runs as two halves on two streams (tuning streams = 2):
+// at least 32 ciphertexts (16 per half keep the key-switch product's key
+// reads at one per 16 ciphertexts), not profiling (each launch's own time),
+// not the no-allocation scratch, not while st is being captured, and only
+// where the second half's share of the workspace starts 256-byte aligned.
 static bool two_halves(nshe_ctx* c, int n_ct, const void* ws, hipStream_t st) {
   if (c->tune.streams != 2 || n_ct < 32 || c->prof || ws == c->scratch) return false;
   if (ws_doubles(c, n_ct / 2) * sizeof(double) % 256) return false;
