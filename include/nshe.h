@@ -407,7 +407,8 @@ int nshe_join_sum(nshe_ctx* ctx, const int64_t* a_key_dev, const int64_t* b_key_
  * swap): every slot of the result holds the sum of all slots.  COUNT is
  * nshe_sum_slots of a 0/1 mask, SUM nshe_sum_slots of a column times the
  * mask (nshe_mul_relin).  Workspace: nshe_workspace_bytes(ctx, n_ct).
- * NSHE_ENOKEY names a missing Galois key. */
+ * NSHE_ENOKEY names a missing Galois key.  nshe_sum_slots runs the two
+ * halves of 32 or more ciphertexts on two streams (tuning streams). */
 int nshe_set_galois_key(nshe_ctx* ctx, uint32_t g, const int64_t* key_dev, size_t n_words,
                         void* stream);
 int nshe_galois_elements(const nshe_ctx* ctx, uint32_t* out_host, int max_out, int* n_out_host);
@@ -435,10 +436,11 @@ int nshe_sum_slots(nshe_ctx* ctx, const int64_t* in_dev, int64_t* out_dev, int n
  *                  product runs fused with the digit transforms (one
  *                  kernel; the digits' transforms are never written),
  *                  0: digit transforms, then the product (two kernels);
- *   streams        2: nshe_eq_mask with at least 32 ciphertexts runs the
- *                  first half of them on `stream` and the second half on a
- *                  second stream the context owns (non-blocking, default
- *                  priority), each in its own half of the workspace, so
+ *   streams        2: nshe_eq_mask and nshe_sum_slots with at least 32
+ *                  ciphertexts run the first half of them on `stream` and
+ *                  the second half on a second stream the context owns
+ *                  (non-blocking, default priority), each in its own half
+ *                  of the workspace, so
  *                  that one half's kernels fill the GPU while the other's
  *                  drain; nshe_eq_mask_batched with waves of at least 32
  *                  runs half-waves, taking turns between the two streams

@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <string>
@@ -1546,7 +1547,8 @@ static bool stream_idle_capture(hipStream_t st) {
   return cs == hipStreamCaptureStatusNone;
 }
 
-// Whether an EQ call runs as two halves on two streams (tuning streams = 2):
+// Whether an EQ or rotate-and-add call runs as two halves on two streams
+// (tuning streams = 2):
 // at least 32 ciphertexts (16 per half keep the key-switch product's key
 // reads at one per 16 ciphertexts), not profiling (each launch's own time),
 // not the no-allocation scratch, not while st is being captured, and only
@@ -1565,6 +1567,25 @@ static int half_stream_ready(nshe_ctx* c) {
   return NSHE_OK;
 }
 
+// run(first ciphertext, count, workspace share, stream) for the two halves
+// of n_ct ciphertexts: the first half on st, the second on the context's
+// second stream, each in its own share of the workspace (the workspace is
+// linear in n_ct, so the two shares fill it).  The second stream starts
+// after the work already on st, and st waits for it at the end.
+static int run_two_halves(nshe_ctx* c, int n_ct, void* ws, hipStream_t st,
+                          const std::function<int(int, int, void*, hipStream_t)>& run) {
+  const int h = n_ct / 2;
+  int rc = half_stream_ready(c);
+  if (rc) return rc;
+  HIPCHK(hipEventRecord(c->half_fork, st));
+  HIPCHK(hipStreamWaitEvent(c->half_stream, c->half_fork, 0));
+  rc = run(0, h, ws, st);
+  if (!rc) rc = run(h, n_ct - h, static_cast<double*>(ws) + ws_doubles(c, h), c->half_stream);
+  HIPCHK(hipEventRecord(c->half_join, c->half_stream));
+  HIPCHK(hipStreamWaitEvent(st, c->half_join, 0));
+  return rc;
+}
+
 static int eq_mask_impl(nshe_ctx* c, const int64_t* x, const int64_t* y, int64_t* out,
                         int n_ct, int y_broadcast, void* ws, size_t ws_bytes, void* stream) {
   int rc = common_checks(c, n_ct, ws, ws_bytes, true);
@@ -1578,22 +1599,11 @@ static int eq_mask_impl(nshe_ctx* c, const int64_t* x, const int64_t* y, int64_t
                                  {y, y_broadcast ? (size_t)2 : (size_t)n_ct * 2}})))
     return rc;
   if (two_halves(c, n_ct, ws, st)) {
-    // the second half: its ciphertexts, its own share of the workspace
-    // (the workspace is linear in n_ct, so the two shares fill it), on the
-    // context's second stream, which starts after the work already on st;
-    // st then waits for it
-    const int h = n_ct / 2;
     const size_t ctw = (size_t)2 * c->L * c->n;
-    if ((rc = half_stream_ready(c))) return rc;
-    HIPCHK(hipEventRecord(c->half_fork, st));
-    HIPCHK(hipStreamWaitEvent(c->half_stream, c->half_fork, 0));
-    rc = eq_run(c, x, y, out, h, y_broadcast, ws, st);
-    if (!rc)
-      rc = eq_run(c, x + h * ctw, y_broadcast ? y : y + h * ctw, out + h * ctw, n_ct - h,
-                  y_broadcast, static_cast<double*>(ws) + ws_doubles(c, h), c->half_stream);
-    HIPCHK(hipEventRecord(c->half_join, c->half_stream));
-    HIPCHK(hipStreamWaitEvent(st, c->half_join, 0));
-    return rc;
+    return run_two_halves(c, n_ct, ws, st, [&](int c0, int cnt, void* wsh, hipStream_t s) {
+      return eq_run(c, x + c0 * ctw, y_broadcast ? y : y + c0 * ctw, out + c0 * ctw, cnt,
+                    y_broadcast, wsh, s);
+    });
   }
   return eq_run(c, x, y, out, n_ct, y_broadcast, ws, st);
 }
@@ -1986,14 +1996,22 @@ int nshe_sum_slots(nshe_ctx* c, const int64_t* in, int64_t* out, int n_ct, void*
   if (rc) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
   if ((rc = check_inputs(c, st, {{in, (size_t)n_ct * 2}}))) return rc;
-  Ws w = carve(c, ws, n_ct);
-  Dims d = dims(c, n_ct);
-  const size_t W = W_of(c), N = c->n;
-  HIPCHK(run_i64_to_polys(d, in, 2, w.ext, 2 * W * N, W * N, 2, c->tb, st));
-  rc = sum_slots_ext(c, w, n_ct, els, keys, st);
-  if (rc) return rc;
-  HIPCHK(run_polys_to_i64(d, w.ext, 2, 2 * W * N, W * N, out, 0, c->tb, st));
-  return NSHE_OK;
+  // the rotate-and-add of cnt ciphertexts from ciphertext c0, on s
+  auto run = [&](int c0, int cnt, void* wsh, hipStream_t s) -> int {
+    const size_t ctw = (size_t)2 * c->L * c->n;
+    Ws w = carve(c, wsh, cnt);
+    Dims d = dims(c, cnt);
+    const size_t W = W_of(c), N = c->n;
+    HIPCHK(run_i64_to_polys(d, in + c0 * ctw, 2, w.ext, 2 * W * N, W * N, 2, c->tb, s));
+    int rc1 = sum_slots_ext(c, w, cnt, els, keys, s);
+    if (rc1) return rc1;
+    HIPCHK(run_polys_to_i64(d, w.ext, 2, 2 * W * N, W * N, out + c0 * ctw, 0, c->tb, s));
+    return NSHE_OK;
+  };
+  // (with the tuning's two streams: the two halves of the ciphertexts on two
+  // streams, as the EQ call)
+  if (two_halves(c, n_ct, ws, st)) return run_two_halves(c, n_ct, ws, st, run);
+  return run(0, n_ct, ws, st);
 }
 
 // ------------------------------------------------------ plaintext products

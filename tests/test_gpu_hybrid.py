@@ -374,6 +374,32 @@ def test_full_size_rotations(request, alpha):
 
 
 @pytest.mark.parametrize("alpha", ALPHAS)
+def test_full_size_sum_slots_two_streams(request, alpha):
+    """The rotate-and-add over 33 ciphertexts (the golden one first and last)
+    on one stream and with its halves on two: equal, and the golden
+    ciphertexts' sums the oracle's."""
+    S = _full(request, alpha)
+    _uniform_keys(S)
+    E = _env(S)
+    g = fc.load_golden(f"a{alpha}_rotations")
+    v, ct = fc.rotate_inputs(E)
+    d = S.to_dev([ct])
+    others = synth.uniform_device_residues((31, 2), S.ctx.q, S.ctx.n, 82, S.ctx.device)
+    X = torch.cat([d, others, d]).contiguous()
+    start = S.ctx.tuning()
+    try:
+        S.ctx.set_tuning(streams=1)
+        one = S.ctx.sum_slots(X)
+        S.ctx.set_tuning(streams=2)
+        two = S.ctx.sum_slots(X)
+    finally:
+        S.ctx.set_tuning(**start)
+    assert torch.equal(two, one)
+    fc.check(g, "sum_slots", one[0].cpu().numpy())
+    fc.check(g, "sum_slots", one[32].cpu().numpy())
+
+
+@pytest.mark.parametrize("alpha", ALPHAS)
 def test_full_size_products_and_join(request, alpha):
     S = _full(request, alpha)
     _uniform_keys(S)
